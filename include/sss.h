@@ -1,0 +1,272 @@
+/*
+ * sss.h -- C-ABI of the MI355X (gfx950) hot path of 3D Student Splatting and
+ * Scooping (arXiv 2503.10148): a differentiable 16x16-tile rasterizer for
+ * signed Student's t mixture components, followed by an SGHMC step.
+ *
+ * The five calls of one training step, in order:
+ *   sss_project     per (view, component): 3D t -> 2D t (Sec. 3.2 eq. t_2D)
+ *   sss_bin_sort    tile binning + depth order (the rasterizer's list build)
+ *   sss_render_fwd  signed front-to-back compositing (Sec. 3.4 eq. SSS_color)
+ *   sss_render_bwd  closed-form gradients (SM "Backward Pass")
+ *   sss_sghmc_step  SGHMC on the means (Sec. 3.4 eq. sigmoidUpdate)
+ *
+ * General rules for every call:
+ *  - Pointers named "device" point to device memory of the current HIP
+ *    device; the caller allocates and owns them.  Structs passed by pointer
+ *    (sss_scene_t, sss_camera_t, ...) live in host memory and are read during
+ *    the call only.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *    is enqueued on it.  sss_bin_sort additionally waits for the stream once
+ *    (it reads two counts back to size its launches); every other call
+ *    returns without waiting.
+ *  - Return value: SSS_OK or a negative SSS_ERR_* code.  On error nothing
+ *    has been enqueued unless stated otherwise, and sss_last_error() returns
+ *    a message for the calling thread.
+ *  - All arithmetic of the raster kernels is FP32; the per-component
+ *    projection (forward and backward) computes in FP64 and stores FP32.
+ *  - Cameras of one call may have different sizes.  Images of all views are
+ *    concatenated: view v occupies pixels [P_v, P_v + W_v H_v) with
+ *    P_v = sum_{u<v} W_u H_u, row-major, 3 channels (HWC) where noted.
+ *    Tiles likewise: view v owns global tile ids [T_v, T_v + tx_v ty_v),
+ *    tx = ceil(W/16), ty = ceil(H/16), row-major inside the view.
+ */
+#ifndef SSS_H
+#define SSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSS_VERSION 100
+#define SSS_TILE 16           /* tile edge in pixels                            */
+#define SSS_MAX_VIEWS 16      /* views per call                                 */
+#define SSS_RECORD_BYTES 64   /* size of one projected record                  */
+
+enum {
+  SSS_OK = 0,
+  SSS_ERR_INVALID = -1,      /* bad argument (null pointer, size, degree ...)   */
+  SSS_ERR_CAPACITY = -2,     /* pair buffer too small; see sss_bins_t.n_pairs  */
+  SSS_ERR_HIP = -3,          /* a HIP runtime call failed                       */
+  SSS_ERR_UNSUPPORTED = -4,  /* valid request outside what this build supports */
+};
+
+/* Components (Sec. 3.2): mean mu, covariance Sigma = R S S^T R^T, degrees of
+ * freedom nu, signed opacity o (Sec. 3.3) and SH colour.  Activated values:
+ *   means   [n][3]                 device, FP32
+ *   scales  [n][3]   S diagonal, > 0
+ *   quats   [n][4]   R as a quaternion (w, x, y, z), any non-zero norm
+ *                    (normalised inside; gradients flow through it)
+ *   nu      [n]      clamped to [nu_min, nu_max] inside
+ *   opacity [n]      o in [-1, 1] (the caller applies tanh)
+ *   sh      [n][(d+1)^2][3]  real SH coefficients, degree d in 0..3, basis
+ *                    ordered k = l*l + l + m with the Condon-Shortley phase;
+ *                    colour = max(0, sum_k Y_k(dir) sh[k] + 1/2) with dir the
+ *                    unit vector from the camera centre to the mean. */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree;
+  int32_t reserved;
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* nu;
+  const float* opacity;
+  const float* sh;
+} sss_scene_t;
+
+/* Gradients with the same layout as sss_scene_t (device, FP32).  Calls ADD
+ * into them (+=); the caller zeroes them.  A NULL array is skipped. */
+typedef struct {
+  float* means;
+  float* scales;
+  float* quats;
+  float* nu;
+  float* opacity;
+  float* sh;
+} sss_grads_t;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  viewmat is the
+ * 3x4 row-major world->camera transform [R | t]; pixel (x, y) is sampled at
+ * (x + 1/2, y + 1/2). */
+typedef struct {
+  float viewmat[12];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} sss_camera_t;
+
+/* Rendering conventions.  Defaults from sss_default_render_opts():
+ *   alpha_min 1/255  a component is skipped at a pixel where |o T2D| < alpha_min
+ *   alpha_max 0.99   |alpha| is clamped to alpha_max (no gradient when clamped)
+ *   t_min     1e-4   a pixel stops before the component that would bring its
+ *                    transmittance below t_min (that component is not added)
+ *   z_near    0.2    components with depth <= z_near are culled
+ *   nu_min, nu_max   1, 1e4 (SM "Implementation Details")
+ *   lowpass   0      added to the diagonal of the 2D covariance (the paper's
+ *                    final model uses none; 0.3 in its ablation setting 1)
+ *   bg        0,0,0  background colour, weighted by the final transmittance */
+typedef struct {
+  float alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass;
+  float bg[3];
+} sss_render_opts_t;
+
+void sss_default_render_opts(sss_render_opts_t* opts);
+
+/* ------------------------------------------------------------------------
+ * sss_project -- Sec. 3.2 eq. (t_2D) and SM "Forward Pass".
+ * For every view v and component i (entry e = v*n + i): camera-space
+ * position, 2D mean, 2D covariance J W Sigma W^T J^T (local affine
+ * approximation; x/z and y/z clamped to 1.3 half-fov for J), its inverse
+ * (the conic), colour from SH, clamped nu, and the truncation rectangle: the
+ * tiles touched by the axis-aligned box of the ellipse h <= h* with
+ * h* = nu ((|o|/alpha_min)^(2/(nu+2)) - 1), outside of which |o T2D| < alpha_min.
+ * Depth key = bits of the FP32 depth fmaf(W20, x, fmaf(W21, y, fmaf(W22, z, t2))).
+ * Culled (tiles_touched = 0): depth key <= z_near, |o| < alpha_min, degenerate
+ * 2D covariance, or a rectangle entirely off screen.
+ * Outputs (device, caller-allocated, n_views*n entries each):
+ *   records        64-byte projected records (opaque to the caller)
+ *   depth_key      uint32
+ *   rect           uint16 x0, y0, x1, y1 per entry (inclusive tile range)
+ *   tiles_touched  uint32, (x1-x0+1)(y1-y0+1), 0 = culled
+ * Errors: INVALID for n <= 0, sh_degree outside 0..3, n_views outside
+ * 1..SSS_MAX_VIEWS, a NULL array, a camera with width/height <= 0 or
+ * non-positive focal lengths. */
+typedef struct {
+  void* records;
+  uint32_t* depth_key;
+  uint16_t* rect;
+  uint32_t* tiles_touched;
+} sss_proj_t;
+
+int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
+                const sss_render_opts_t* opts, const sss_proj_t* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sss_bin_sort -- per-tile component lists in ascending (depth key,
+ * component index) order (the list build of the tile rasterizer the paper
+ * modifies, SM "Implementation Details").
+ * Visible entries are sorted once by depth key (stable radix sort, ties by
+ * entry index), giving each a rank; every (tile, rank) pair of a visible
+ * entry's rectangle is emitted and stably radix-sorted by tile.
+ * Inputs: proj (from sss_project), the same cameras, n_entries = n_views*n.
+ * Outputs (device, caller-allocated):
+ *   order          [n_entries]   rank -> entry; the first n_visible are valid
+ *   sorted_records [n_entries] x 64 B, record of rank r at position r
+ *   tile_start     [n_tiles + 1] pairs of global tile t are
+ *                  pair_rank[tile_start[t] .. tile_start[t+1])
+ *   pair_rank      [pair_capacity] ranks, ascending within each tile
+ * Host outputs: n_visible, n_pairs (always written when the call returns
+ * SSS_OK or SSS_ERR_CAPACITY).
+ * Workspace: ws of ws_bytes >= sss_bin_sort_workspace(n_entries, pair_capacity).
+ * Errors: CAPACITY when n_pairs > pair_capacity (nothing after the count is
+ * enqueued; re-allocate pair_rank and the workspace for n_pairs and call
+ * again); INVALID for NULL pointers or a short workspace. */
+typedef struct {
+  uint32_t* order;
+  void* sorted_records;
+  uint32_t* tile_start;
+  uint32_t* pair_rank;
+  int64_t pair_capacity;
+  int64_t n_visible;   /* out */
+  int64_t n_pairs;     /* out */
+} sss_bins_t;
+
+size_t sss_bin_sort_workspace(int64_t n_entries, int64_t pair_capacity);
+int64_t sss_total_tiles(const sss_camera_t* cams, int n_views);
+int64_t sss_total_pixels(const sss_camera_t* cams, int n_views);
+
+int sss_bin_sort(const sss_proj_t* proj, const sss_camera_t* cams, int n_views, int64_t n,
+                 sss_bins_t* bins, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sss_render_fwd -- Sec. 3.4 eq. (SSS_color): per pixel, over its tile's
+ * list front to back: h = d^T Q d (d = pixel - mean2d), T2D = (1 + h/nu)^(-(nu+2)/2),
+ * alpha = o T2D (skip if |alpha| < alpha_min, clamp |alpha| <= alpha_max),
+ * stop before T(1 - alpha) < t_min, C += colour alpha T, T *= 1 - alpha.
+ * Outputs (device, P = sss_total_pixels):
+ *   image     [P][3]  C + T bg
+ *   t_final   [P]     final transmittance T
+ *   n_contrib [P]     list position after the last added component
+ * Errors: INVALID for NULL pointers / bad views. */
+int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views,
+                   const sss_render_opts_t* opts, float* image, float* t_final,
+                   uint32_t* n_contrib, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sss_render_bwd -- SM "Backward Pass": gradients of a loss L(image) with
+ * respect to means, scales, quats, nu, opacity and sh, through alpha, T2D,
+ * h, the 2D mean and conic, the projection and the SH colour.  dT2D/dnu is
+ * the complete derivative T/2 [(nu+2) h/(nu (nu+h)) - log(1 + h/nu)].
+ *   mode SSS_BWD_STORED     uses image and n_contrib from sss_render_fwd
+ *   mode SSS_BWD_RECOMPUTE  recomputes the forward pass per tile (image,
+ *                           t_final, n_contrib ignored; image_out, if not
+ *                           NULL, receives the forward image)
+ *   loss SSS_LOSS_GRAD      dl_or_target = dL/dimage [P][3]
+ *   loss SSS_LOSS_L1        dl_or_target = target [P][3]; L = mean |image - target|
+ *                           over all 3P values; loss_out (device float,
+ *                           nullable) receives += L
+ * grads: += (see sss_grads_t).  Workspace: ws_bytes >=
+ * sss_render_bwd_workspace(n_views*n) (per-entry screen-space gradients).
+ * Errors: INVALID for NULL pointers, a short workspace, unknown mode/loss. */
+enum { SSS_BWD_STORED = 0, SSS_BWD_RECOMPUTE = 1 };
+enum { SSS_LOSS_GRAD = 0, SSS_LOSS_L1 = 1 };
+
+size_t sss_render_bwd_workspace(int64_t n_entries);
+
+int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
+                   const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts,
+                   int mode, int loss, const float* dl_or_target, const float* image,
+                   const uint32_t* n_contrib, float* image_out, float* loss_out,
+                   const sss_grads_t* grads, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sss_sghmc_step -- Sec. 3.4 eq. (sigmoidUpdate) / SM eq. (SGHMC), per mean
+ * element, eps = lr, C = friction, switch s = sigmoid(k ((1 - |o|) - t)) (on
+ * for |o| below 1 - t), n ~ N(0, 2 eps C) per axis:
+ *   F  = s eps (1 - eps C) r        (F = 0 when burn_in)
+ *   mu <- mu - eps^2 G + F + s eps n  (burn_in: s eps Sigma n, Sigma = R S S^T R^T)
+ *   r  <- (1 - eps C) r - eps G + n
+ * G = grad_means.  Noise: Philox4x32-10 with key (seed lo, seed hi) and
+ * counter (i lo, step lo, step hi, i hi); uniforms ((x >> 9) + 1/2) 2^-23;
+ * Box-Muller on words (0, 1) for x, y and (2, 3) for z.  noise = 0 turns it off.
+ * adam (nullable): Adam (beta1, beta2, eps, step t >= 1) on up to 6 further
+ * arrays (the paper's non-mean parameters), each clamped to [lo, hi].
+ * Arrays: device FP32; means, momentum, grad_means [n][3]; opacity [n];
+ * scales [n][3] and quats [n][4] (read only for burn_in).
+ * Errors: INVALID for n <= 0, NULL arrays, lr < 0, adam->t < 1. */
+typedef struct {
+  float lr, friction, k, t;
+  int32_t burn_in, noise;
+  uint64_t seed, step;
+} sss_sghmc_opts_t;
+
+typedef struct {
+  float* param;
+  const float* grad;
+  float* m;
+  float* v;
+  int64_t count;
+  float lr, lo, hi;
+} sss_adam_array_t;
+
+typedef struct {
+  float beta1, beta2, eps;
+  int32_t n_arrays;
+  int64_t t;
+  sss_adam_array_t arrays[6];
+} sss_adam_t;
+
+int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const float* opacity,
+                   const float* scales, const float* quats, int64_t n,
+                   const sss_sghmc_opts_t* opts, const sss_adam_t* adam, void* stream);
+
+/* ------------------------------------------------------------------------ */
+const char* sss_last_error(void);   /* message of the last failed call on this thread */
+int sss_version(void);              /* SSS_VERSION */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSS_H */

@@ -1,0 +1,260 @@
+// C-ABI entry points (include/sss.h): argument validation, camera and option
+// marshalling, workspace carving and kernel launches.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "common.hpp"
+
+namespace sss {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+bool hip_ok(hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return false;
+}
+
+int make_cam_batch(const sss_camera_t* cams, int n_views, CamBatch* out) {
+  if (!cams || n_views < 1 || n_views > SSS_MAX_VIEWS) {
+    set_error("n_views must be in 1..%d and cams non-null", SSS_MAX_VIEWS);
+    return SSS_ERR_INVALID;
+  }
+  memset(out, 0, sizeof(*out));
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const sss_camera_t& c = cams[v];
+    if (c.width <= 0 || c.height <= 0 || c.width > 65535 * kTile || c.height > 65535 * kTile ||
+        !(c.fx > 0.0f) || !(c.fy > 0.0f)) {
+      set_error("camera %d: width/height must be positive and focal lengths > 0", v);
+      return SSS_ERR_INVALID;
+    }
+    CamDev& d = out->v[v];
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) d.R[3 * r + k] = c.viewmat[4 * r + k];
+      d.t[r] = c.viewmat[4 * r + 3];
+    }
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    d.W = c.width; d.H = c.height;
+    d.tiles_x = (c.width + kTile - 1) / kTile;
+    d.tiles_y = (c.height + kTile - 1) / kTile;
+    d.tile_offset = (int32_t)tiles;
+    d.pix_offset = pix;
+    tiles += (int64_t)d.tiles_x * d.tiles_y;
+    pix += (int64_t)c.width * c.height;
+  }
+  if (tiles > (int64_t)0x7FFFFFFF) {
+    set_error("too many tiles");
+    return SSS_ERR_UNSUPPORTED;
+  }
+  out->n_views = n_views;
+  out->total_tiles = (int32_t)tiles;
+  return SSS_OK;
+}
+
+OptsDev make_opts(const sss_render_opts_t* o) {
+  sss_render_opts_t d;
+  if (!o) {
+    sss_default_render_opts(&d);
+    o = &d;
+  }
+  OptsDev r;
+  r.alpha_min = o->alpha_min; r.alpha_max = o->alpha_max; r.t_min = o->t_min; r.z_near = o->z_near;
+  r.nu_min = o->nu_min; r.nu_max = o->nu_max; r.lowpass = o->lowpass;
+  r.bg[0] = o->bg[0]; r.bg[1] = o->bg[1]; r.bg[2] = o->bg[2];
+  return r;
+}
+
+static int check_scene(const sss_scene_t* s, const char* fn) {
+  if (!s || s->n <= 0 || s->n > (int64_t)0xFFFFFFFF / SSS_MAX_VIEWS || s->sh_degree < 0 || s->sh_degree > 3 ||
+      !s->means || !s->scales || !s->quats || !s->nu || !s->opacity || !s->sh) {
+    set_error("%s: scene needs n in 1..%lld, sh_degree in 0..3 and six non-null arrays", fn,
+              (long long)(0xFFFFFFFFll / SSS_MAX_VIEWS));
+    return SSS_ERR_INVALID;
+  }
+  return SSS_OK;
+}
+
+static int check_opts(const sss_render_opts_t* o, const char* fn) {
+  if (!o) return SSS_OK;
+  if (!(o->alpha_min >= 0.0f) || !(o->alpha_max > 0.0f) || !(o->t_min >= 0.0f) || !(o->nu_min >= 1.0f) ||
+      !(o->nu_max >= o->nu_min) || !(o->lowpass >= 0.0f)) {
+    set_error("%s: options out of range (alpha_min >= 0, alpha_max > 0, t_min >= 0, 1 <= nu_min <= nu_max, "
+              "lowpass >= 0)", fn);
+    return SSS_ERR_INVALID;
+  }
+  return SSS_OK;
+}
+
+static int64_t total_pixels(const CamBatch& cb) {
+  int64_t p = 0;
+  for (int v = 0; v < cb.n_views; ++v) p += (int64_t)cb.v[v].W * cb.v[v].H;
+  return p;
+}
+
+}  // namespace sss
+
+using namespace sss;
+
+extern "C" {
+
+void sss_default_render_opts(sss_render_opts_t* o) {
+  if (!o) return;
+  o->alpha_min = 1.0f / 255.0f;
+  o->alpha_max = 0.99f;
+  o->t_min = 1e-4f;
+  o->z_near = 0.2f;
+  o->nu_min = 1.0f;
+  o->nu_max = 1e4f;
+  o->lowpass = 0.0f;
+  o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+}
+
+const char* sss_last_error(void) { return g_err; }
+int sss_version(void) { return SSS_VERSION; }
+
+int64_t sss_total_tiles(const sss_camera_t* cams, int n_views) {
+  CamBatch cb;
+  if (make_cam_batch(cams, n_views, &cb) != SSS_OK) return -1;
+  return cb.total_tiles;
+}
+
+int64_t sss_total_pixels(const sss_camera_t* cams, int n_views) {
+  CamBatch cb;
+  if (make_cam_batch(cams, n_views, &cb) != SSS_OK) return -1;
+  return total_pixels(cb);
+}
+
+size_t sss_bin_sort_workspace(int64_t n_entries, int64_t pair_capacity) {
+  if (n_entries < 0 || pair_capacity < 0) return 0;
+  return bin_sort_workspace(n_entries, pair_capacity);
+}
+
+size_t sss_render_bwd_workspace(int64_t n_entries) {
+  if (n_entries < 0) return 0;
+  return (size_t)n_entries * kG2 * sizeof(float);
+}
+
+int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts,
+                const sss_proj_t* out, void* stream) {
+  int rc = check_scene(scene, "sss_project");
+  if (rc) return rc;
+  if ((rc = check_opts(opts, "sss_project"))) return rc;
+  CamBatch cb;
+  if ((rc = make_cam_batch(cams, n_views, &cb))) return rc;
+  if (!out || !out->records || !out->depth_key || !out->rect || !out->tiles_touched) {
+    set_error("sss_project: output arrays must be non-null");
+    return SSS_ERR_INVALID;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  launch_project(cb, make_opts(opts), *scene, *out, st);
+  return hip_ok(hipGetLastError(), "sss_project launch") ? SSS_OK : SSS_ERR_HIP;
+}
+
+int sss_bin_sort(const sss_proj_t* proj, const sss_camera_t* cams, int n_views, int64_t n, sss_bins_t* bins,
+                 void* ws, size_t ws_bytes, void* stream) {
+  CamBatch cb;
+  int rc = make_cam_batch(cams, n_views, &cb);
+  if (rc) return rc;
+  if (!proj || !proj->records || !proj->depth_key || !proj->rect || !proj->tiles_touched || !bins ||
+      !bins->order || !bins->sorted_records || !bins->tile_start || !bins->pair_rank || !ws || n <= 0 ||
+      bins->pair_capacity < 0 || n > (int64_t)0xFFFFFFFF / SSS_MAX_VIEWS) {
+    set_error("sss_bin_sort: null pointer, n <= 0 or negative pair capacity");
+    return SSS_ERR_INVALID;
+  }
+  return run_bin_sort(cb, *proj, n, bins, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts,
+                   float* image, float* t_final, uint32_t* n_contrib, void* stream) {
+  CamBatch cb;
+  int rc = make_cam_batch(cams, n_views, &cb);
+  if (rc) return rc;
+  if ((rc = check_opts(opts, "sss_render_fwd"))) return rc;
+  if (!bins || !bins->sorted_records || !bins->tile_start || !bins->pair_rank || !image) {
+    set_error("sss_render_fwd: bins arrays and image must be non-null");
+    return SSS_ERR_INVALID;
+  }
+  launch_render_fwd(cb, make_opts(opts), *bins, image, t_final, n_contrib, (hipStream_t)stream);
+  return hip_ok(hipGetLastError(), "sss_render_fwd launch") ? SSS_OK : SSS_ERR_HIP;
+}
+
+int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
+                   const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts, int mode, int loss,
+                   const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
+                   float* loss_out, const sss_grads_t* grads, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_scene(scene, "sss_render_bwd");
+  if (rc) return rc;
+  if ((rc = check_opts(opts, "sss_render_bwd"))) return rc;
+  CamBatch cb;
+  if ((rc = make_cam_batch(cams, n_views, &cb))) return rc;
+  if (mode != SSS_BWD_STORED && mode != SSS_BWD_RECOMPUTE) {
+    set_error("sss_render_bwd: unknown mode %d", mode);
+    return SSS_ERR_INVALID;
+  }
+  if (loss != SSS_LOSS_GRAD && loss != SSS_LOSS_L1) {
+    set_error("sss_render_bwd: unknown loss %d", loss);
+    return SSS_ERR_INVALID;
+  }
+  if (!proj || !proj->tiles_touched || !bins || !bins->sorted_records || !bins->tile_start || !bins->pair_rank ||
+      !dl_or_target || !grads || !ws) {
+    set_error("sss_render_bwd: null pointer");
+    return SSS_ERR_INVALID;
+  }
+  if (mode == SSS_BWD_STORED && (!image || !n_contrib)) {
+    set_error("sss_render_bwd: STORED mode needs image and n_contrib");
+    return SSS_ERR_INVALID;
+  }
+  const int64_t n_entries = scene->n * n_views;
+  if (ws_bytes < sss_render_bwd_workspace(n_entries)) {
+    set_error("sss_render_bwd: workspace of %zu bytes, %zu needed", ws_bytes, sss_render_bwd_workspace(n_entries));
+    return SSS_ERR_INVALID;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const OptsDev op = make_opts(opts);
+  float* g2 = (float*)ws;
+  launch_zero(g2, n_entries * kG2, st);
+  launch_render_bwd(cb, op, *bins, mode, loss, dl_or_target, image, n_contrib, image_out, loss_out, g2,
+                    total_pixels(cb), st);
+  launch_project_bwd(cb, op, *scene, proj->tiles_touched, g2, *grads, st);
+  return hip_ok(hipGetLastError(), "sss_render_bwd launch") ? SSS_OK : SSS_ERR_HIP;
+}
+
+int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const float* opacity,
+                   const float* scales, const float* quats, int64_t n, const sss_sghmc_opts_t* opts,
+                   const sss_adam_t* adam, void* stream) {
+  if (!means || !momentum || !grad_means || !opacity || !opts || n <= 0 || !(opts->lr >= 0.0f) ||
+      (opts->burn_in && (!scales || !quats))) {
+    set_error("sss_sghmc_step: null array, n <= 0 or lr < 0 (burn-in needs scales and quats)");
+    return SSS_ERR_INVALID;
+  }
+  if (adam) {
+    if (adam->t < 1 || adam->n_arrays < 0 || adam->n_arrays > 6) {
+      set_error("sss_sghmc_step: adam needs t >= 1 and 0..6 arrays");
+      return SSS_ERR_INVALID;
+    }
+    for (int k = 0; k < adam->n_arrays; ++k) {
+      const sss_adam_array_t& a = adam->arrays[k];
+      if (!a.param || !a.grad || !a.m || !a.v || a.count < 0) {
+        set_error("sss_sghmc_step: adam array %d has a null pointer or negative count", k);
+        return SSS_ERR_INVALID;
+      }
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  launch_sghmc(means, momentum, grad_means, opacity, scales, quats, n, *opts, st);
+  if (adam)
+    for (int k = 0; k < adam->n_arrays; ++k)
+      if (adam->arrays[k].count > 0) launch_adam(adam->arrays[k], adam->beta1, adam->beta2, adam->eps, adam->t, st);
+  return hip_ok(hipGetLastError(), "sss_sghmc_step launch") ? SSS_OK : SSS_ERR_HIP;
+}
+
+}  // extern "C"

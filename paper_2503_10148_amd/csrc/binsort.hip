@@ -1,0 +1,415 @@
+// Tile binning and depth ordering.
+//
+//  1. visible entries (tiles_touched > 0) are compacted in entry order and
+//     the total pair count is reduced; both counts are read back once;
+//  2. a stable LSD radix sort by the 32-bit depth key gives each visible
+//     entry its rank (ties keep entry order, i.e. component index);
+//  3. every (tile, rank) pair of a visible entry's rectangle is written in
+//     rank order (exclusive scan of tiles_touched over ranks), the projected
+//     records are gathered into rank order alongside;
+//  4. a stable radix sort of the pairs by global tile id leaves each tile's
+//     ranks ascending, i.e. in (depth key, component index) order;
+//  5. tile_start[] marks where each tile's run begins.
+//
+// All passes stream through HBM with coalesced 16-byte accesses where the
+// data allows; the radix scatter ranks keys inside a wave with ballots
+// (64-wide match) so the sort is stable without per-thread digit counters.
+#include "common.hpp"
+
+namespace sss {
+namespace {
+
+constexpr int kItems = 16;                 // items per thread in scans / radix passes
+constexpr int kPerBlock = kBlock * kItems; // 4096
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
+  // Hillis-Steele over 256 values in LDS; returns the exclusive prefix.
+  const int t = threadIdx.x;
+  lds[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const uint32_t add = t >= off ? lds[t - off] : 0u;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  const uint32_t incl = lds[t];
+  if (total) *total = lds[kBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                             uint32_t* __restrict__ sums) {
+  __shared__ uint32_t red[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kPerBlock;
+  uint32_t s = 0;
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
+    if (j < n) s += in[j];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+// Exclusive scan of one 4096-item block plus the block's prefix.
+__global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t* in, int64_t n,
+                                                            const uint32_t* __restrict__ prefix,
+                                                            uint32_t* out) {
+  __shared__ uint32_t lds[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
+  uint32_t v[kItems];
+  uint32_t s = 0;
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t j = base + k;
+    v[k] = j < n ? in[j] : 0u;
+    s += v[k];
+  }
+  uint32_t run = block_excl_scan(s, lds, nullptr) + (prefix ? prefix[blockIdx.x] : 0u);
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t j = base + k;
+    if (j < n) out[j] = run;
+    run += v[k];
+  }
+}
+
+// Exclusive scan of n uint32 values, any n; ws must hold scan_ws_words(n).
+int64_t scan_ws_words(int64_t n) {
+  int64_t w = 0;
+  while (n > kPerBlock) {
+    n = (n + kPerBlock - 1) / kPerBlock;
+    w += 2 * n;
+  }
+  return w + 16;
+}
+
+void scan_excl(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* ws, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
+  if (nb == 1) {
+    hipLaunchKernelGGL(scan_apply_kernel, dim3(1), dim3(kBlock), 0, st, in, n, (const uint32_t*)nullptr, out);
+    return;
+  }
+  uint32_t* sums = ws;
+  uint32_t* sums_scan = ws + nb;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, sums);
+  scan_excl(sums, sums_scan, nb, ws + 2 * nb, st);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n,
+                     (const uint32_t*)sums_scan, out);
+}
+
+// ---------------------------------------------------------------------------
+// 1. visibility
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void visible_kernel(const uint32_t* __restrict__ touched, int64_t n,
+                                                         uint32_t* __restrict__ flags,
+                                                         unsigned long long* __restrict__ counters) {
+  __shared__ unsigned long long red[kBlock];
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t t = j < n ? touched[j] : 0u;
+  if (j < n) flags[j] = t > 0 ? 1u : 0u;
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0]) atomicAdd(counters + 1, red[0]);
+}
+
+__global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* __restrict__ flags,
+                                                         const uint32_t* __restrict__ pos,
+                                                         const uint32_t* __restrict__ keys, int64_t n,
+                                                         uint32_t* __restrict__ out_keys,
+                                                         uint32_t* __restrict__ out_vals,
+                                                         unsigned long long* __restrict__ counters) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t p = pos[j];
+  if (flags[j]) {
+    out_keys[p] = keys[j];
+    out_vals[p] = (uint32_t)j;
+  }
+  if (j == n - 1) counters[0] = (unsigned long long)p + flags[j];
+}
+
+// ---------------------------------------------------------------------------
+// 2./4. stable LSD radix sort, 8-bit digits
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
+                                                            int shift, uint32_t mask, int64_t nblocks,
+                                                            uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kPerBlock;
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
+    if (j < n) atomicAdd(&h[(keys[j] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Block b owns items [b*4096, (b+1)*4096); wave w owns the w-th quarter and
+// walks it in 16 rounds of 64 consecutive items, so (wave, round, lane) is
+// item order and ranks computed in that order are stable.
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift, int bits,
+    int64_t nblocks, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ okeys,
+    uint32_t* __restrict__ ovals) {
+  __shared__ uint32_t cnt[4][256];
+  __shared__ uint32_t gbase[256];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
+  const uint32_t mask = (1u << bits) - 1u;
+  for (int k = 0; k < 4; ++k) cnt[k][tid] = 0;
+  gbase[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)w * (kPerBlock / 4);
+  uint32_t key[kItems], val[kItems], loc[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t j = base + (int64_t)r * 64 + lane;
+    const bool ok = j < n;
+    key[r] = ok ? keys[j] : 0u;
+    val[r] = ok ? vals[j] : 0u;
+    const uint32_t d = (key[r] >> shift) & mask;
+    uint64_t peers = __ballot(ok);
+    for (int b = 0; b < bits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t on = __ballot(bit);
+      peers &= bit ? on : ~on;
+    }
+    const uint32_t before = (uint32_t)__popcll(peers & lt);
+    const uint32_t cur = cnt[w][d];
+    loc[r] = cur + before;
+    const int leader = __ffsll((unsigned long long)peers) - 1;
+    __builtin_amdgcn_wave_barrier();
+    if (ok && lane == leader) cnt[w][d] = cur + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // exclusive prefix over waves for each digit
+  {
+    const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid];
+    __syncthreads();
+    cnt[0][tid] = 0;
+    cnt[1][tid] = c0;
+    cnt[2][tid] = c0 + c1;
+    cnt[3][tid] = c0 + c1 + c2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t j = base + (int64_t)r * 64 + lane;
+    if (j < n) {
+      const uint32_t d = (key[r] >> shift) & mask;
+      const uint32_t p = gbase[d] + cnt[w][d] + loc[r];
+      okeys[p] = key[r];
+      ovals[p] = val[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. emission
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void touched_by_rank_kernel(const uint32_t* __restrict__ order,
+                                                                 const uint32_t* __restrict__ touched,
+                                                                 int64_t n_vis, uint32_t* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r < n_vis) out[r] = touched[order[r]];
+}
+
+__device__ __forceinline__ uint32_t off_next(const uint32_t* __restrict__ off, int64_t r, int64_t n_vis,
+                                              uint32_t total) {
+  return (r + 1 < n_vis ? off[r + 1] : total) - off[r];
+}
+
+__device__ __forceinline__ int tiles_y_of(const CamBatch& cb, int v) {
+  int ty = 1;
+  for (int k = 0; k < cb.n_views; ++k)
+    if (k == v) ty = cb.v[k].tiles_y;
+  return ty;
+}
+
+__global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, const uint32_t* __restrict__ order,
+                                                      const ushort4* __restrict__ rects,
+                                                      const uint32_t* __restrict__ off, int64_t n_vis, uint32_t total,
+                                                      const uint4* __restrict__ rec_in, uint4* __restrict__ rec_out,
+                                                      uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= n_vis) return;
+  const uint32_t e = order[r];
+  // gather the record into rank order
+  const uint4* src = rec_in + (size_t)e * 4;
+  uint4* dst = rec_out + (size_t)r * 4;
+  const uint4 a = src[0], b = src[1], c = src[2], d = src[3];
+  dst[0] = a; dst[1] = b; dst[2] = c; dst[3] = d;
+  const int v = (int)(e / (uint64_t)n);
+  int tile_off = 0, tiles_x = 1;
+  for (int k = 0; k < cb.n_views; ++k)
+    if (k == v) { tile_off = cb.v[k].tile_offset; tiles_x = cb.v[k].tiles_x; }
+  const ushort4 rc = rects[e];
+  // Exactly tiles_touched[e] pairs are written (the scan reserved that many);
+  // a tile outside the view's grid, or a slot the rectangle does not fill,
+  // gets the sentinel key n_tiles, which sorts after every real tile.
+  const uint32_t cnt = off_next(off, r, n_vis, total);
+  uint32_t p = off[r], k = 0;
+  const int tiles_y = tiles_y_of(cb, v);
+  for (int ty = rc.y; ty <= rc.w && k < cnt; ++ty) {
+    for (int tx = rc.x; tx <= rc.z && k < cnt; ++tx, ++k) {
+      const bool in = tx < tiles_x && ty < tiles_y;
+      tkeys[p + k] = in ? (uint32_t)(tile_off + ty * tiles_x + tx) : (uint32_t)cb.total_tiles;
+      tvals[p + k] = (uint32_t)r;
+    }
+  }
+  for (; k < cnt; ++k) {
+    tkeys[p + k] = (uint32_t)cb.total_tiles;
+    tvals[p + k] = (uint32_t)r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 5. tile ranges
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void tile_start_kernel(const uint32_t* __restrict__ tkeys, int64_t m,
+                                                            int64_t n_tiles, uint32_t* __restrict__ start) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i > m) return;
+  int64_t prev = i == 0 ? -1 : (int64_t)tkeys[i - 1];
+  if (prev > n_tiles) prev = n_tiles;
+  int64_t cur = i == m ? n_tiles : (int64_t)tkeys[i];
+  if (cur > n_tiles) cur = n_tiles;
+  for (int64_t t = prev + 1; t <= cur; ++t) start[t] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+struct Ws {
+  uint32_t *flags, *pos, *ka, *va, *kb, *vb, *hist, *scan;
+  unsigned long long* counters;
+  size_t bytes;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+Ws carve(void* base, int64_t n_entries, int64_t pair_cap) {
+  const int64_t big = n_entries > pair_cap ? n_entries : pair_cap;
+  const int64_t nb = (big + kPerBlock - 1) / kPerBlock;
+  Ws w;
+  char* p = (char*)base;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { char* q = p ? p + off : nullptr; off += align256(bytes); return q; };
+  w.counters = (unsigned long long*)take(4 * sizeof(unsigned long long));
+  w.flags = (uint32_t*)take(sizeof(uint32_t) * (size_t)n_entries);
+  w.pos = (uint32_t*)take(sizeof(uint32_t) * (size_t)n_entries);
+  w.ka = (uint32_t*)take(sizeof(uint32_t) * (size_t)big);
+  w.va = (uint32_t*)take(sizeof(uint32_t) * (size_t)big);
+  w.kb = (uint32_t*)take(sizeof(uint32_t) * (size_t)big);
+  w.vb = (uint32_t*)take(sizeof(uint32_t) * (size_t)big);
+  w.hist = (uint32_t*)take(sizeof(uint32_t) * 256 * (size_t)nb);
+  w.scan = (uint32_t*)take(sizeof(uint32_t) * (size_t)scan_ws_words(256 * nb > big ? 256 * nb : big));
+  w.bytes = off;
+  return w;
+}
+
+// Stable sort of (keys, vals)[0, n) by bits [0, nbits).  The data starts in
+// (ka, va); keys ping-pong between ka and kb, values between va and vb, and
+// the last pass writes the values to out_v.  Returns the buffer holding the
+// sorted keys (never the last pass's input).
+uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int nbits,
+                     uint32_t* out_v, Ws& w, hipStream_t st) {
+  const int passes = (nbits + 7) / 8;
+  uint32_t* final_keys = ((passes - 1) % 2 == 0) ? kb : ka;
+  if (n <= 0) return final_keys;
+  const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    const int bits = (nbits - shift) < 8 ? (nbits - shift) : 8;
+    uint32_t* ik = (p % 2 == 0) ? ka : kb;
+    uint32_t* iv = (p % 2 == 0) ? va : vb;
+    uint32_t* okk = (p % 2 == 0) ? kb : ka;
+    uint32_t* ovv = (p == passes - 1) ? out_v : ((p % 2 == 0) ? vb : va);
+    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, n, shift,
+                       (uint32_t)((1u << bits) - 1u), nb, w.hist);
+    scan_excl(w.hist, w.hist, 256 * nb, w.scan, st);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, iv, n, shift, bits,
+                       nb, (const uint32_t*)w.hist, okk, ovv);
+  }
+  return final_keys;
+}
+
+int bits_for(int64_t v) {
+  int b = 1;
+  while (b < 32 && (int64_t(1) << b) < v) ++b;
+  return b;
+}
+
+}  // namespace
+
+size_t bin_sort_workspace(int64_t n_entries, int64_t pair_capacity) {
+  return carve(nullptr, n_entries, pair_capacity).bytes;
+}
+
+int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins_t* bins, void* ws,
+                 size_t ws_bytes, hipStream_t st) {
+  const int64_t n_entries = n * cb.n_views;
+  Ws w = carve(ws, n_entries, bins->pair_capacity);
+  if (ws_bytes < w.bytes) {
+    set_error("sss_bin_sort: workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
+    return SSS_ERR_INVALID;
+  }
+  const unsigned g1 = (unsigned)((n_entries + kBlock - 1) / kBlock);
+  if (!hip_ok(hipMemsetAsync(w.counters, 0, 4 * sizeof(unsigned long long), st), "memset")) return SSS_ERR_HIP;
+  hipLaunchKernelGGL(visible_kernel, dim3(g1), dim3(kBlock), 0, st, proj.tiles_touched, n_entries, w.flags,
+                     w.counters);
+  scan_excl(w.flags, w.pos, n_entries, w.scan, st);
+  hipLaunchKernelGGL(compact_kernel, dim3(g1), dim3(kBlock), 0, st, w.flags, w.pos, proj.depth_key, n_entries,
+                     w.ka, w.va, w.counters);
+  unsigned long long counts[2];
+  if (!hip_ok(hipMemcpyAsync(counts, w.counters, sizeof(counts), hipMemcpyDeviceToHost, st), "count readback"))
+    return SSS_ERR_HIP;
+  if (!hip_ok(hipStreamSynchronize(st), "count sync")) return SSS_ERR_HIP;
+  const int64_t n_vis = (int64_t)counts[0], m = (int64_t)counts[1];
+  bins->n_visible = n_vis;
+  bins->n_pairs = m;
+  if (m > bins->pair_capacity) {
+    set_error("sss_bin_sort: %lld pairs exceed the capacity %lld", (long long)m, (long long)bins->pair_capacity);
+    return SSS_ERR_CAPACITY;
+  }
+  if (m > (int64_t)0xFFFFFFFFll) {
+    set_error("sss_bin_sort: %lld pairs exceed 2^32", (long long)m);
+    return SSS_ERR_UNSUPPORTED;
+  }
+  // 2. depth order of the visible entries
+  radix_sort(w.ka, w.va, w.kb, w.vb, n_vis, 32, bins->order, w, st);
+  // 3. pair offsets in rank order, emission, record gather
+  if (n_vis > 0) {
+    const unsigned gv = (unsigned)((n_vis + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(touched_by_rank_kernel, dim3(gv), dim3(kBlock), 0, st, bins->order, proj.tiles_touched,
+                       n_vis, w.flags);
+    scan_excl(w.flags, w.pos, n_vis, w.scan, st);
+    hipLaunchKernelGGL(emit_kernel, dim3(gv), dim3(kBlock), 0, st, cb, n, bins->order,
+                       (const ushort4*)proj.rect, w.pos, n_vis, (uint32_t)m, (const uint4*)proj.records,
+                       (uint4*)bins->sorted_records, w.ka, w.va);
+  }
+  // 4. stable sort of the pairs by tile
+  const uint32_t* tkeys = radix_sort(w.ka, w.va, w.kb, w.vb, m, bits_for((int64_t)cb.total_tiles + 1), bins->pair_rank, w, st);
+  // 5. tile ranges
+  const unsigned gt = (unsigned)((m + 1 + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(tile_start_kernel, dim3(gt), dim3(kBlock), 0, st, tkeys, m,
+                     (int64_t)cb.total_tiles, bins->tile_start);
+  if (!hip_ok(hipGetLastError(), "bin_sort launch")) return SSS_ERR_HIP;
+  return SSS_OK;
+}
+
+}  // namespace sss

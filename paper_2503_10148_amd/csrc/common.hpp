@@ -1,0 +1,81 @@
+// Internal definitions shared by the HIP translation units of libsss.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sss.h"
+
+namespace sss {
+
+constexpr int kTile = SSS_TILE;
+constexpr int kBlock = 256;               // threads per workgroup (4 waves of 64)
+
+// Per-view camera constants, passed by value in the kernel argument segment.
+struct CamDev {
+  float R[9];          // world->camera rotation, row-major
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t W, H, tiles_x, tiles_y;
+  int32_t tile_offset;  // first global tile id of the view
+  int32_t pad;
+  int64_t pix_offset;   // first pixel of the view
+};
+
+struct CamBatch {
+  CamDev v[SSS_MAX_VIEWS];
+  int32_t n_views;
+  int32_t total_tiles;
+};
+
+struct OptsDev {
+  float alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass;
+  float bg[3];
+};
+
+// Projected record of one (view, component) entry, 64 bytes.
+// The 2D mean is kept in FP64 so that pixel offsets are exact to well below
+// 1e-6 px at 1080p; everything a pixel evaluation needs follows.
+struct __align__(16) Rec {
+  double mx, my;       // 2D mean (pixels)
+  float qa, qb, qc;    // conic: h = qa dx^2 + 2 qb dx dy + qc dy^2
+  float cr, cg, cb;    // colour
+  float o;             // signed opacity
+  float inv_nu;        // 1 / nu
+  float nb;            // -(nu + 2) / 2
+  float hs;            // truncation level h*
+  uint32_t entry;      // v * n + i
+  float nu;            // clamped nu
+};
+static_assert(sizeof(Rec) == SSS_RECORD_BYTES, "record size");
+
+// Number of float slots per entry in the screen-space gradient buffer:
+// d/d(mx, my), d/d(qa, qb, qc), d/d(cr, cg, cb), d/do, d/dnu (+2 pad).
+constexpr int kG2 = 12;
+
+void set_error(const char* fmt, ...);
+bool hip_ok(hipError_t e, const char* what);
+int make_cam_batch(const sss_camera_t* cams, int n_views, CamBatch* out);
+OptsDev make_opts(const sss_render_opts_t* o);
+
+// launchers (stream is hipStream_t)
+void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
+                    const sss_proj_t& out, hipStream_t st);
+void launch_project_bwd(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
+                        const uint32_t* touched, const float* g2, const sss_grads_t& g,
+                        hipStream_t st);
+int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins_t* bins,
+                 void* ws, size_t ws_bytes, hipStream_t st);
+size_t bin_sort_workspace(int64_t n_entries, int64_t pair_capacity);
+void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b,
+                       float* image, float* t_final, uint32_t* n_contrib, hipStream_t st);
+void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, int mode,
+                       int loss, const float* dl_or_target, const float* image,
+                       const uint32_t* n_contrib, float* image_out, float* loss_out, float* g2,
+                       int64_t total_pixels, hipStream_t st);
+void launch_zero(float* p, int64_t count, hipStream_t st);
+void launch_sghmc(float* means, float* mom, const float* g, const float* opac, const float* scales,
+                  const float* quats, int64_t n, const sss_sghmc_opts_t& o, hipStream_t st);
+void launch_adam(const sss_adam_array_t& a, float b1, float b2, float eps, int64_t t, hipStream_t st);
+
+}  // namespace sss

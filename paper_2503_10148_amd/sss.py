@@ -1,0 +1,322 @@
+"""ctypes binding of libsss.so (include/sss.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of libsss.so.  Tensors must be CUDA (ROCm) tensors on the current
+device; work is enqueued on torch's current stream unless a stream is given.
+Importing this module loads the library and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsss.so")
+
+TILE = 16
+MAX_VIEWS = 16
+RECORD_BYTES = 64
+G2_SLOTS = 12
+OK, ERR_INVALID, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+BWD_STORED, BWD_RECOMPUTE = 0, 1
+LOSS_GRAD, LOSS_L1 = 0, 1
+
+c_f32p = ctypes.c_void_p
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("nu", ctypes.c_void_p), ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("nu", ctypes.c_void_p), ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("viewmat", ctypes.c_float * 12), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32)]
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
+                ("z_near", ctypes.c_float), ("nu_min", ctypes.c_float), ("nu_max", ctypes.c_float),
+                ("lowpass", ctypes.c_float), ("bg", ctypes.c_float * 3)]
+
+
+class Proj(ctypes.Structure):
+    _fields_ = [("records", ctypes.c_void_p), ("depth_key", ctypes.c_void_p), ("rect", ctypes.c_void_p),
+                ("tiles_touched", ctypes.c_void_p)]
+
+
+class Bins(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_void_p), ("sorted_records", ctypes.c_void_p), ("tile_start", ctypes.c_void_p),
+                ("pair_rank", ctypes.c_void_p), ("pair_capacity", ctypes.c_int64), ("n_visible", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64)]
+
+
+class SghmcOpts(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("friction", ctypes.c_float), ("k", ctypes.c_float), ("t", ctypes.c_float),
+                ("burn_in", ctypes.c_int32), ("noise", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("step", ctypes.c_uint64)]
+
+
+class AdamArray(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("m", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("count", ctypes.c_int64), ("lr", ctypes.c_float), ("lo", ctypes.c_float),
+                ("hi", ctypes.c_float)]
+
+
+class Adam(ctypes.Structure):
+    _fields_ = [("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("n_arrays", ctypes.c_int32), ("t", ctypes.c_int64), ("arrays", AdamArray * 6)]
+
+
+EXPORTS = ["sss_default_render_opts", "sss_project", "sss_bin_sort", "sss_bin_sort_workspace", "sss_total_tiles",
+           "sss_total_pixels", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_workspace", "sss_sghmc_step",
+           "sss_last_error", "sss_version"]
+
+_lib = None
+
+
+def lib():
+    """Load libsss.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_10148_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.sss_last_error.restype = ctypes.c_char_p
+        L.sss_version.restype = i32
+        L.sss_bin_sort_workspace.restype = ctypes.c_size_t
+        L.sss_bin_sort_workspace.argtypes = [i64, i64]
+        L.sss_render_bwd_workspace.restype = ctypes.c_size_t
+        L.sss_render_bwd_workspace.argtypes = [i64]
+        L.sss_total_tiles.restype = i64
+        L.sss_total_tiles.argtypes = [vp, i32]
+        L.sss_total_pixels.restype = i64
+        L.sss_total_pixels.argtypes = [vp, i32]
+        L.sss_project.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.sss_bin_sort.argtypes = [vp, vp, i32, i64, vp, vp, ctypes.c_size_t, vp]
+        L.sss_render_fwd.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+        L.sss_render_bwd.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp,
+                                     ctypes.c_size_t, vp]
+        L.sss_sghmc_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+        for name in ("sss_project", "sss_bin_sort", "sss_render_fwd", "sss_render_bwd", "sss_sghmc_step"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+class SSSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise SSSError(rc, f"{what}: {lib().sss_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+
+
+# ---------------------------------------------------------------------------
+# argument structs
+# ---------------------------------------------------------------------------
+def camera_array(cams):
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        vm = [float(x) for x in list(torch.as_tensor(c["viewmat"], dtype=torch.float32).reshape(12))]
+        arr[i].viewmat[:] = vm
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = c["fx"], c["fy"], c["cx"], c["cy"]
+        arr[i].width, arr[i].height = int(c["width"]), int(c["height"])
+    return arr
+
+
+def render_opts(opts=None):
+    o = RenderOpts()
+    lib().sss_default_render_opts(ctypes.byref(o))
+    for k, v in (opts or {}).items():
+        if k == "bg":
+            o.bg[:] = [float(x) for x in v]
+        else:
+            setattr(o, k, float(v))
+    return o
+
+
+def scene_struct(scene):
+    """scene: dict of CUDA float32 tensors means [n,3], scales [n,3], quats [n,4],
+    nu [n], opacity [n], sh [n,K,3] and an int sh_degree."""
+    n = scene["means"].shape[0]
+    for k in ("means", "scales", "quats", "nu", "opacity", "sh"):
+        _need(scene[k], torch.float32, k)
+    return Scene(n, int(scene["sh_degree"]), 0, *(scene[k].data_ptr() for k in
+                                                   ("means", "scales", "quats", "nu", "opacity", "sh")))
+
+
+def total_tiles(cams):
+    return int(lib().sss_total_tiles(camera_array(cams), len(cams)))
+
+
+def total_pixels(cams):
+    return int(lib().sss_total_pixels(camera_array(cams), len(cams)))
+
+
+# ---------------------------------------------------------------------------
+# calls
+# ---------------------------------------------------------------------------
+@dataclass
+class Projected:
+    records: torch.Tensor      # uint8 [E, 64]
+    depth_key: torch.Tensor    # int32 [E] (uint32 bits)
+    rect: torch.Tensor         # int16 [E, 4]
+    touched: torch.Tensor      # int32 [E]
+
+    def struct(self):
+        return Proj(self.records.data_ptr(), self.depth_key.data_ptr(), self.rect.data_ptr(), self.touched.data_ptr())
+
+
+def project(scene, cams, opts=None, stream=None, out: Projected | None = None) -> Projected:
+    n = scene["means"].shape[0]
+    E = n * len(cams)
+    dev = scene["means"].device
+    if out is None:
+        out = Projected(torch.empty((E, RECORD_BYTES), dtype=torch.uint8, device=dev),
+                        torch.empty(E, dtype=torch.int32, device=dev),
+                        torch.empty((E, 4), dtype=torch.int16, device=dev),
+                        torch.empty(E, dtype=torch.int32, device=dev))
+    s = scene_struct(scene)
+    p = out.struct()
+    _check(lib().sss_project(ctypes.byref(s), camera_array(cams), len(cams), ctypes.byref(render_opts(opts)),
+                             ctypes.byref(p), _stream(stream)), "sss_project")
+    return out
+
+
+@dataclass
+class Binned:
+    order: torch.Tensor          # int32 [E]
+    sorted_records: torch.Tensor # uint8 [E, 64]
+    tile_start: torch.Tensor     # int32 [tiles + 1]
+    pair_rank: torch.Tensor      # int32 [capacity]
+    n_visible: int = 0
+    n_pairs: int = 0
+
+    def struct(self):
+        return Bins(self.order.data_ptr(), self.sorted_records.data_ptr(), self.tile_start.data_ptr(),
+                    self.pair_rank.data_ptr(), self.pair_rank.numel(), self.n_visible, self.n_pairs)
+
+
+class BinSorter:
+    """Holds the pair and workspace buffers of sss_bin_sort and grows them
+    (with 25% headroom) when a call reports SSS_ERR_CAPACITY."""
+
+    def __init__(self, pair_capacity: int = 0):
+        self.cap = int(pair_capacity)
+        self.ws = None
+        self.pair_rank = None
+
+    def __call__(self, proj: Projected, cams, n: int, stream=None, out: Binned | None = None) -> Binned:
+        E = n * len(cams)
+        dev = proj.records.device
+        T = total_tiles(cams)
+        if out is None:
+            out = Binned(torch.empty(E, dtype=torch.int32, device=dev),
+                         torch.empty((E, RECORD_BYTES), dtype=torch.uint8, device=dev),
+                         torch.empty(T + 1, dtype=torch.int32, device=dev), None)
+        camarr = camera_array(cams)
+        p = proj.struct()
+        for _ in range(3):
+            if self.pair_rank is None or self.pair_rank.numel() < max(self.cap, 1):
+                self.pair_rank = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
+            need = int(lib().sss_bin_sort_workspace(E, self.pair_rank.numel()))
+            if self.ws is None or self.ws.numel() < need:
+                self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            out.pair_rank = self.pair_rank
+            b = out.struct()
+            rc = lib().sss_bin_sort(ctypes.byref(p), camarr, len(cams), n, ctypes.byref(b), _ptr(self.ws),
+                                    self.ws.numel(), _stream(stream))
+            out.n_visible, out.n_pairs = int(b.n_visible), int(b.n_pairs)
+            if rc == ERR_CAPACITY:
+                self.cap = int(b.n_pairs * 1.25) + 1024
+                continue
+            _check(rc, "sss_bin_sort")
+            return out
+        raise SSSError(ERR_CAPACITY, "sss_bin_sort: capacity retry did not converge")
+
+
+def render_fwd(bins: Binned, cams, opts=None, stream=None, image=None, t_final=None, n_contrib=None):
+    P = total_pixels(cams)
+    dev = bins.order.device
+    image = torch.empty((P, 3), dtype=torch.float32, device=dev) if image is None else image
+    t_final = torch.empty(P, dtype=torch.float32, device=dev) if t_final is None else t_final
+    n_contrib = torch.empty(P, dtype=torch.int32, device=dev) if n_contrib is None else n_contrib
+    b = bins.struct()
+    _check(lib().sss_render_fwd(ctypes.byref(b), camera_array(cams), len(cams), ctypes.byref(render_opts(opts)),
+                                _ptr(image), _ptr(t_final), _ptr(n_contrib), _stream(stream)), "sss_render_fwd")
+    return image, t_final, n_contrib
+
+
+def zero_grads_like(scene):
+    return {k: torch.zeros_like(scene[k]) for k in ("means", "scales", "quats", "nu", "opacity", "sh")}
+
+
+def render_bwd(scene, proj: Projected, bins: Binned, cams, dl_or_target, opts=None, mode=BWD_STORED,
+               loss=LOSS_GRAD, image=None, n_contrib=None, image_out=None, loss_out=None, grads=None,
+               ws=None, stream=None):
+    """Gradients (+= into `grads`, created zeroed if None).  Returns grads."""
+    n = scene["means"].shape[0]
+    E = n * len(cams)
+    if grads is None:
+        grads = zero_grads_like(scene)
+    need = int(lib().sss_render_bwd_workspace(E))
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need // 4, dtype=torch.float32, device=scene["means"].device)
+    s = scene_struct(scene)
+    g = Grads(*(grads[k].data_ptr() for k in ("means", "scales", "quats", "nu", "opacity", "sh")))
+    p = proj.struct()
+    b = bins.struct()
+    _check(lib().sss_render_bwd(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), camera_array(cams), len(cams),
+                                ctypes.byref(render_opts(opts)), mode, loss, _ptr(dl_or_target), _ptr(image),
+                                _ptr(n_contrib), _ptr(image_out), _ptr(loss_out), ctypes.byref(g), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)), "sss_render_bwd")
+    return grads
+
+
+def sghmc_step(means, momentum, grad_means, opacity, lr, friction=0.1, k=100.0, t=0.995, burn_in=False,
+               noise=True, seed=0, step=0, scales=None, quats=None, adam=None, stream=None):
+    """In-place SGHMC step on `means`/`momentum`.  adam: optional dict with
+    beta1, beta2, eps, t and a list 'arrays' of dicts (param, grad, m, v, lr, lo, hi)."""
+    o = SghmcOpts(lr, friction, k, t, int(burn_in), int(noise), seed, step)
+    ad = None
+    if adam is not None:
+        ad = Adam()
+        ad.beta1, ad.beta2, ad.eps = adam.get("beta1", 0.9), adam.get("beta2", 0.999), adam.get("eps", 1e-15)
+        ad.t = int(adam["t"])
+        ad.n_arrays = len(adam["arrays"])
+        for i, a in enumerate(adam["arrays"]):
+            ad.arrays[i] = AdamArray(a["param"].data_ptr(), a["grad"].data_ptr(), a["m"].data_ptr(),
+                                     a["v"].data_ptr(), a["param"].numel(), a["lr"], a.get("lo", -3.0e38),
+                                     a.get("hi", 3.0e38))
+    _check(lib().sss_sghmc_step(_ptr(means), _ptr(momentum), _ptr(grad_means), _ptr(opacity), _ptr(scales),
+                                _ptr(quats), means.shape[0], ctypes.byref(o),
+                                ctypes.byref(ad) if ad is not None else None, _stream(stream)), "sss_sghmc_step")

@@ -1,0 +1,154 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments before touching the GPU.  CPU only (no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_10148_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sss():
+    from paper_2503_10148_amd import build, sss as binding
+    if not os.path.exists(binding.LIB_PATH):
+        build.build()
+    return binding
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sss.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sss_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_five_calls():
+    names = declared_functions()
+    for fn in ("sss_project", "sss_bin_sort", "sss_render_fwd", "sss_render_bwd", "sss_sghmc_step"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol(sss):
+    lib = ctypes.CDLL(sss.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sss.lib().sss_version() == 100
+
+
+def test_default_options(sss):
+    o = sss.render_opts()
+    assert o.alpha_min == pytest.approx(1 / 255)
+    assert o.alpha_max == pytest.approx(0.99)
+    assert o.t_min == pytest.approx(1e-4)
+    assert (o.nu_min, o.nu_max, o.lowpass) == (1.0, 1e4, 0.0)
+
+
+def test_tiles_and_pixels_of_ragged_views(sss):
+    cams = [scenes.ring_camera(1297, 840), scenes.ring_camera(17, 16), scenes.ring_camera(1, 1)]
+    assert sss.total_tiles(cams) == 82 * 53 + 2 * 1 + 1
+    assert sss.total_pixels(cams) == 1297 * 840 + 17 * 16 + 1
+
+
+def test_workspace_sizes_grow(sss):
+    L = sss.lib()
+    a = L.sss_bin_sort_workspace(1000, 1000)
+    b = L.sss_bin_sort_workspace(1000, 10 ** 6)
+    assert 0 < a < b
+    assert L.sss_render_bwd_workspace(1000) == 1000 * 12 * 4
+
+
+def _scene_struct(sss, n=10, deg=0, null=None):
+    ptrs = [ctypes.c_void_p(0x1000 + 64 * i) for i in range(6)]
+    if null is not None:
+        ptrs[null] = ctypes.c_void_p(0)
+    return sss.Scene(n, deg, 0, *ptrs)
+
+
+def _proj_struct(sss):
+    return sss.Proj(0x2000, 0x3000, 0x4000, 0x5000)
+
+
+@pytest.mark.parametrize("kind", ["null_scene", "bad_degree", "zero_n", "null_array", "no_views", "too_many_views",
+                                  "zero_width", "bad_focal", "bad_opts"])
+def test_project_rejects_bad_arguments(sss, kind):
+    L = sss.lib()
+    cam = scenes.ring_camera(64, 48)
+    cams = sss.camera_array([cam] * 17)
+    opts = sss.render_opts()
+    scene = _scene_struct(sss)
+    nviews = 1
+    if kind == "bad_degree":
+        scene = _scene_struct(sss, deg=4)
+    elif kind == "zero_n":
+        scene = _scene_struct(sss, n=0)
+    elif kind == "null_array":
+        scene = _scene_struct(sss, null=5)
+    elif kind == "no_views":
+        nviews = 0
+    elif kind == "too_many_views":
+        nviews = 17
+    elif kind == "zero_width":
+        cams[0].width = 0
+    elif kind == "bad_focal":
+        cams[0].fx = 0.0
+    elif kind == "bad_opts":
+        opts.nu_min = 0.5
+    p = _proj_struct(sss)
+    sp = None if kind == "null_scene" else ctypes.byref(scene)
+    rc = L.sss_project(sp, cams, nviews, ctypes.byref(opts), ctypes.byref(p), None)
+    assert rc == sss.ERR_INVALID
+    assert len(L.sss_last_error()) > 0
+
+
+def test_bin_sort_rejects_short_workspace_and_nulls(sss):
+    L = sss.lib()
+    cams = sss.camera_array([scenes.ring_camera(64, 48)])
+    p = _proj_struct(sss)
+    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, 100, 0, 0)
+    assert L.sss_bin_sort(ctypes.byref(p), cams, 1, 10, ctypes.byref(b), None, 0, None) == sss.ERR_INVALID
+    b0 = sss.Bins(0, 0x2000, 0x3000, 0x4000, 100, 0, 0)
+    assert L.sss_bin_sort(ctypes.byref(p), cams, 1, 10, ctypes.byref(b0), ctypes.c_void_p(0x9000), 10 ** 9,
+                          None) == sss.ERR_INVALID
+
+
+def test_render_bwd_rejects_unknown_mode_and_short_workspace(sss):
+    L = sss.lib()
+    cams = sss.camera_array([scenes.ring_camera(64, 48)])
+    opts = sss.render_opts()
+    scene = _scene_struct(sss)
+    p = _proj_struct(sss)
+    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, 100, 0, 0)
+    g = sss.Grads(0, 0, 0, 0, 0, 0)
+    args = lambda mode, loss, wsb: (ctypes.byref(scene), ctypes.byref(p), ctypes.byref(b), cams, 1,
+                                    ctypes.byref(opts), mode, loss, ctypes.c_void_p(0x6000), ctypes.c_void_p(0x7000),
+                                    ctypes.c_void_p(0x8000), None, None, ctypes.byref(g), ctypes.c_void_p(0x9000),
+                                    wsb, None)
+    assert L.sss_render_bwd(*args(7, 0, 10 ** 6)) == sss.ERR_INVALID
+    assert L.sss_render_bwd(*args(0, 9, 10 ** 6)) == sss.ERR_INVALID
+    assert L.sss_render_bwd(*args(0, 0, 10)) == sss.ERR_INVALID
+    assert b"workspace" in L.sss_last_error()
+
+
+def test_sghmc_rejects_bad_arguments(sss):
+    L = sss.lib()
+    o = sss.SghmcOpts(0.01, 0.1, 100.0, 0.995, 0, 1, 0, 0)
+    v = ctypes.c_void_p(0x1000)
+    assert L.sss_sghmc_step(None, v, v, v, None, None, 10, ctypes.byref(o), None, None) == sss.ERR_INVALID
+    assert L.sss_sghmc_step(v, v, v, v, None, None, 0, ctypes.byref(o), None, None) == sss.ERR_INVALID
+    ob = sss.SghmcOpts(0.01, 0.1, 100.0, 0.995, 1, 1, 0, 0)
+    assert L.sss_sghmc_step(v, v, v, v, None, None, 10, ctypes.byref(ob), None, None) == sss.ERR_INVALID
+    bad = sss.SghmcOpts(-1.0, 0.1, 100.0, 0.995, 0, 1, 0, 0)
+    assert L.sss_sghmc_step(v, v, v, v, None, None, 10, ctypes.byref(bad), None, None) == sss.ERR_INVALID
+    ad = sss.Adam()
+    ad.t = 0
+    assert L.sss_sghmc_step(v, v, v, v, None, None, 10, ctypes.byref(o), ctypes.byref(ad), None) == sss.ERR_INVALID
+
+
+def test_records_layout_matches_decoder():
+    from tests._util import REC_DTYPE
+    assert REC_DTYPE.itemsize == 64
+    assert REC_DTYPE.names[-2:] == ("entry", "nu")

@@ -1,0 +1,412 @@
+"""GPU parity: every call of the HIP path, through the C-ABI, against the FP64
+oracle on the same seeded inputs.
+
+Tolerances (from the method's stated targets, made precise):
+  * depth keys, culling, rectangles, tile lists, sort order: bit-exact,
+    except components the oracle flags as within 1e-9 of a discrete
+    threshold;
+  * images: |delta| <= 1e-4 per channel at every pixel the oracle does not
+    flag as "explained" (an alpha within 1e-5 of the cut-off or clamp, a
+    transmittance within 1e-3 of t_min, or a flagged component);
+  * gradients: |delta| <= 1e-3 max(|g_ref|, rms(g_ref of the array)), with
+    the loss weight zeroed at explained pixels.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_10148_amd import scenes
+from tests._util import PARAMS, decode_records, grad_close, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_10148_amd import sss as binding
+    binding.lib()
+    return binding
+
+
+def _case(name):
+    if name == "small":                          # 10k components, 256x256, SH 0
+        return scenes.workload("small")
+    if name == "sh3_ragged":                     # SH 3, image not a multiple of 16
+        s = scenes.make_scene(3000, 3, seed=7, neg_frac=0.3)
+        s["scales"] *= np.float32(2.0)
+        return s, [scenes.ring_camera(250, 190, angle=1.1)]
+    if name == "clusters":                       # clustered, nu log-uniform [1, 150]
+        s = scenes.make_scene(6000, 3, seed=8, layout="clusters", neg_frac=0.3, nu_mode="loguniform")
+        return s, [scenes.ring_camera(203, 141, angle=2.2)]
+    if name == "bigcomp":                        # few large fat-tailed components
+        s = scenes.make_scene(300, 1, seed=9, neg_frac=0.3, scale_range=(0.05, 0.3))
+        return s, [scenes.ring_camera(170, 120, angle=0.2)]
+    raise KeyError(name)
+
+
+CASES = ["small", "sh3_ragged", "clusters", "bigcomp"]
+
+
+def gpu_forward(sss, scene, cams, opts=None):
+    dev = to_device(scene)
+    n = scene["means"].shape[0]
+    proj = sss.project(dev, cams, opts)
+    bins = sss.BinSorter(1024)(proj, cams, n)
+    img, tfin, ncon = sss.render_fwd(bins, cams, opts)
+    torch.cuda.synchronize()
+    return dev, proj, bins, img, tfin, ncon
+
+
+# ---------------------------------------------------------------------------
+# projection
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", CASES)
+def test_project_matches_oracle(sss, name):
+    scene, cams = _case(name)
+    cam = cams[0]
+    o = oracle.project(scene, cam)
+    proj = sss.project(to_device(scene), cams)
+    torch.cuda.synchronize()
+    rec = decode_records(proj.records.cpu().numpy())
+    touched = proj.touched.cpu().numpy()
+    keys = proj.depth_key.cpu().numpy().view(np.uint32)
+    rect = proj.rect.cpu().numpy().astype(np.int32)
+    assert np.array_equal(keys, o["key"])
+    flagged = o["pflags"] != 0
+    vis = touched > 0
+    assert np.array_equal(vis[~flagged], o["valid"][~flagged] == 1)
+    m = vis & (o["valid"] == 1)
+    assert m.sum() > 0.5 * len(m) or name == "bigcomp"
+    assert np.array_equal(touched[m & ~flagged], o["touched"][m & ~flagged])
+    assert np.array_equal(rect[m & ~flagged], o["rect"][m & ~flagged])
+    np.testing.assert_allclose(rec["mx"][m], o["mean2d"][m, 0], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(rec["my"][m], o["mean2d"][m, 1], rtol=1e-12, atol=1e-9)
+    cs = np.abs(o["conic"][m]).sum(1)
+    for j, f in enumerate(("qa", "qb", "qc")):
+        assert np.all(np.abs(rec[f][m] - o["conic"][m, j]) <= 2e-7 * cs)
+    for j, f in enumerate(("cr", "cg", "cb")):
+        np.testing.assert_allclose(rec[f][m], o["rgb"][m, j], rtol=2e-7, atol=1e-7)
+    np.testing.assert_allclose(rec["nu"][m], o["nu_c"][m], rtol=1e-7)
+    np.testing.assert_allclose(rec["hs"][m], o["hstar"][m], rtol=2e-7)
+    assert np.array_equal(rec["entry"][m], np.nonzero(m)[0])
+
+
+# ---------------------------------------------------------------------------
+# binning / sorting
+# ---------------------------------------------------------------------------
+def test_bin_sort_bit_exact_on_synthetic_inputs(sss):
+    """Given identical rectangles and keys (many ties), the GPU lists equal the
+    oracle's (tile, key, index) order exactly; records are gathered verbatim."""
+    rng = np.random.default_rng(101)
+    cams = [scenes.ring_camera(100, 90, angle=0.0), scenes.ring_camera(61, 37, angle=1.0),
+            scenes.ring_camera(300, 20, angle=2.0)]
+    n = 4000
+    V = len(cams)
+    E = n * V
+    touched = np.zeros(E, np.int32)
+    rect = np.zeros((E, 4), np.int16)
+    keys = (0x3F800000 + rng.integers(0, 40, E)).astype(np.uint32)   # many equal depths
+    for v, c in enumerate(cams):
+        tx, ty = oracle.tiles(c)
+        for i in range(n):
+            e = v * n + i
+            if rng.uniform() < 0.25:
+                continue
+            x0 = rng.integers(0, tx)
+            y0 = rng.integers(0, ty)
+            x1 = min(tx - 1, x0 + rng.integers(0, 4))
+            y1 = min(ty - 1, y0 + rng.integers(0, 3))
+            rect[e] = (x0, y0, x1, y1)
+            touched[e] = (x1 - x0 + 1) * (y1 - y0 + 1)
+    records = rng.integers(0, 256, (E, 64), dtype=np.uint8)
+    proj = sss.Projected(torch.as_tensor(records, device="cuda"), torch.as_tensor(keys.view(np.int32), device="cuda"),
+                         torch.as_tensor(rect, device="cuda"), torch.as_tensor(touched, device="cuda"))
+    bins = sss.BinSorter(16)(proj, cams, n)
+    torch.cuda.synchronize()
+    vis = np.nonzero(touched > 0)[0]
+    assert bins.n_visible == len(vis) and bins.n_pairs == int(touched.sum())
+    order = bins.order.cpu().numpy()[: bins.n_visible].view(np.uint32).astype(np.int64)
+    want = vis[np.lexsort((vis, keys[vis]))]
+    assert np.array_equal(order, want)
+    srec = bins.sorted_records.cpu().numpy()[: bins.n_visible]
+    assert np.array_equal(srec, records[order])
+    start = bins.tile_start.cpu().numpy().astype(np.int64)
+    pr = bins.pair_rank.cpu().numpy()[: bins.n_pairs].astype(np.int64)
+    toff = 0
+    for v, c in enumerate(cams):
+        tx, ty = oracle.tiles(c)
+        ost, olst = oracle.bin_tiles(touched[v * n:(v + 1) * n], rect[v * n:(v + 1) * n].astype(np.int32),
+                                     keys[v * n:(v + 1) * n], tx, ty)
+        for t in range(tx * ty):
+            g = order[pr[start[toff + t]:start[toff + t + 1]]] - v * n
+            assert np.array_equal(g, olst[ost[t]:ost[t + 1]]), (v, t)
+        toff += tx * ty
+    assert start[toff] == bins.n_pairs
+
+
+def test_bin_sort_reports_capacity_and_recovers(sss):
+    scene, cams = _case("small")
+    n = scene["means"].shape[0]
+    proj = sss.project(to_device(scene), cams)
+    binner = sss.BinSorter(10)              # far too small: first call returns CAPACITY
+    bins = binner(proj, cams, n)
+    torch.cuda.synchronize()
+    o = oracle.project(scene, cams[0])
+    assert bins.n_pairs == int(o["touched"].sum())
+    assert binner.cap >= bins.n_pairs
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_tile_lists_end_to_end(sss, name):
+    scene, cams = _case(name)
+    cam = cams[0]
+    n = scene["means"].shape[0]
+    o = oracle.project(scene, cam)
+    tx, ty = oracle.tiles(cam)
+    ost, olst = oracle.bin_tiles(o["touched"], o["rect"], o["key"], tx, ty)
+    proj = sss.project(to_device(scene), cams)
+    bins = sss.BinSorter(1024)(proj, cams, n)
+    torch.cuda.synchronize()
+    order = bins.order.cpu().numpy().view(np.uint32).astype(np.int64)
+    start = bins.tile_start.cpu().numpy().astype(np.int64)
+    pr = bins.pair_rank.cpu().numpy()[: bins.n_pairs].astype(np.int64)
+    flagged = set(np.nonzero(o["pflags"] & oracle.PF_RECT_EDGE)[0].tolist())
+    for t in range(tx * ty):
+        g = [int(i) for i in order[pr[start[t]:start[t + 1]]] if int(i) not in flagged]
+        r = [int(i) for i in olst[ost[t]:ost[t + 1]] if int(i) not in flagged]
+        assert g == r, t
+
+
+# ---------------------------------------------------------------------------
+# forward
+# ---------------------------------------------------------------------------
+def _image_check(img_gpu, ref, xflags, tol=1e-4):
+    H, W = xflags.shape
+    img = img_gpu.reshape(H, W, 3)
+    diff = np.abs(img - ref["image"]).max(axis=2)
+    explained = xflags != 0
+    bad = (diff > tol) & ~explained
+    return bad, diff, explained
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_render_fwd_matches_oracle(sss, name):
+    scene, cams = _case(name)
+    ref = oracle.render(scene, cams[0])
+    _, _, _, img, tfin, ncon = gpu_forward(sss, scene, cams)
+    bad, diff, explained = _image_check(img.cpu().numpy(), ref, ref["xflags"])
+    assert not bad.any(), f"{bad.sum()} unexplained pixels, max {diff[~explained].max()}"
+    assert explained.mean() < 0.01
+    H, W = ref["xflags"].shape
+    nc = ncon.cpu().numpy().reshape(H, W)
+    assert np.array_equal(nc[~explained], ref["ncontrib"][~explained])
+    tf = tfin.cpu().numpy().reshape(H, W)
+    assert np.all(np.abs(tf - ref["tfinal"])[~explained] <= 1e-4 * np.maximum(1.0, ref["tfinal"][~explained]))
+
+
+def test_render_fwd_matches_brute_force(sss):
+    s = scenes.make_scene(250, 2, seed=12, neg_frac=0.4)
+    s["scales"] *= np.float32(3.0)
+    cams = [scenes.ring_camera(77, 53, angle=0.9)]
+    ref = oracle.render(s, cams[0], brute=True)
+    _, _, _, img, _, _ = gpu_forward(sss, s, cams)
+    bad, diff, explained = _image_check(img.cpu().numpy(), ref, ref["xflags"])
+    assert not bad.any()
+
+
+def test_render_fwd_with_background_and_lowpass(sss):
+    scene, cams = _case("sh3_ragged")
+    opts = dict(bg=(0.25, 0.5, 0.75), lowpass=0.3)
+    ref = oracle.render(scene, cams[0], opts)
+    _, _, _, img, _, _ = gpu_forward(sss, scene, cams, opts)
+    bad, _, _ = _image_check(img.cpu().numpy(), ref, ref["xflags"])
+    assert not bad.any()
+
+
+def test_render_fwd_is_deterministic(sss):
+    scene, cams = _case("clusters")
+    a = gpu_forward(sss, scene, cams)[3].cpu().numpy()
+    b = gpu_forward(sss, scene, cams)[3].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_multiview_matches_single_views(sss):
+    s = scenes.make_scene(4000, 3, seed=13, neg_frac=0.25)
+    cams = [scenes.ring_camera(128, 96, angle=0.3), scenes.ring_camera(61, 45, angle=2.0),
+            scenes.ring_camera(200, 33, angle=4.0)]
+    _, _, _, img, _, _ = gpu_forward(sss, s, cams)
+    img = img.cpu().numpy()
+    off = 0
+    for c in cams:
+        P = c["width"] * c["height"]
+        ref = oracle.render(s, c)
+        bad, _, _ = _image_check(img[off:off + P], ref, ref["xflags"])
+        assert not bad.any()
+        single = gpu_forward(sss, s, [c])[3].cpu().numpy()
+        assert np.array_equal(single, img[off:off + P])       # alone == in the batch, bit for bit
+        off += P
+
+
+def test_alpha_min_zero_renders_everything(sss):
+    s = scenes.make_scene(60, 0, seed=14, neg_frac=0.3)
+    cams = [scenes.ring_camera(48, 40, angle=0.5)]
+    opts = dict(alpha_min=0.0)
+    ref = oracle.render(s, cams[0], opts)
+    _, _, _, img, _, _ = gpu_forward(sss, s, cams, opts)
+    bad, _, _ = _image_check(img.cpu().numpy(), ref, ref["xflags"])
+    assert not bad.any()
+
+
+# ---------------------------------------------------------------------------
+# backward
+# ---------------------------------------------------------------------------
+def _explained_components(ref, n, cam):
+    """Components listed in a tile that holds an explained pixel."""
+    start, lst = ref["bins"]
+    tx, _ = oracle.tiles(cam)
+    ys, xs = np.nonzero(ref["xflags"])
+    comps = set()
+    for y, x in zip(ys, xs):
+        t = (y // 16) * tx + x // 16
+        comps.update(lst[start[t]:start[t + 1]].tolist())
+    m = np.zeros(n, bool)
+    m[list(comps)] = True
+    return m
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_render_bwd_matches_oracle(sss, name, mode):
+    scene, cams = _case(name)
+    cam = cams[0]
+    n = scene["means"].shape[0]
+    ref = oracle.render(scene, cam)
+    rng = np.random.default_rng(77)
+    w = rng.standard_normal(ref["image"].shape)
+    w[ref["xflags"] != 0] = 0.0
+    gref = oracle.render_backward(scene, cam, w, fwd=ref)
+    dev, proj, bins, img, tfin, ncon = gpu_forward(sss, scene, cams)
+    dl = torch.as_tensor(w.reshape(-1, 3), dtype=torch.float32, device="cuda")
+    m = sss.BWD_STORED if mode == "stored" else sss.BWD_RECOMPUTE
+    g = sss.render_bwd(dev, proj, bins, cams, dl, mode=m, image=img, n_contrib=ncon)
+    torch.cuda.synchronize()
+    keep = ref["proj"]["pflags"] == 0
+    for k in PARAMS:
+        ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=keep)
+        assert ok, (k, worst)
+
+
+def test_render_bwd_l1_fused_matches_oracle(sss):
+    scene, cams = _case("small")
+    cam = cams[0]
+    n = scene["means"].shape[0]
+    target = scenes.smooth_target(cam["width"], cam["height"])
+    ref = oracle.render(scene, cam)
+    gl = oracle.l1_grad(ref["image"], target)
+    gref = oracle.render_backward(scene, cam, gl, fwd=ref)
+    near = np.abs(ref["image"] - target).min(axis=2) < 1e-4
+    xf = ref["xflags"].copy()
+    xf[near] |= 16
+    skip = _explained_components(dict(ref, xflags=xf), n, cam) | (ref["proj"]["pflags"] != 0)
+    dev = to_device(scene)
+    proj = sss.project(dev, cams)
+    bins = sss.BinSorter(1024)(proj, cams, n)
+    tgt = torch.as_tensor(target.reshape(-1, 3), device="cuda")
+    img_out = torch.empty((cam["width"] * cam["height"], 3), device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    g = sss.render_bwd(dev, proj, bins, cams, tgt, mode=sss.BWD_RECOMPUTE, loss=sss.LOSS_L1, image_out=img_out,
+                       loss_out=loss)
+    torch.cuda.synchronize()
+    lref = np.abs(ref["image"] - target).mean()
+    assert loss.item() == pytest.approx(lref, rel=1e-5)
+    bad, _, _ = _image_check(img_out.cpu().numpy(), ref, ref["xflags"])
+    assert not bad.any()
+    for k in PARAMS:
+        ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=~skip)
+        assert ok, (k, worst)
+
+
+def test_render_bwd_multiview_sums_views(sss):
+    s = scenes.make_scene(2000, 2, seed=15, neg_frac=0.3)
+    cams = [scenes.ring_camera(96, 64, angle=0.1), scenes.ring_camera(80, 80, angle=1.3)]
+    rng = np.random.default_rng(5)
+    gref = None
+    ws = []
+    for c in cams:
+        ref = oracle.render(s, c)
+        w = rng.standard_normal(ref["image"].shape)
+        w[ref["xflags"] != 0] = 0.0
+        ws.append(w.reshape(-1, 3))
+        gr = oracle.render_backward(s, c, w, fwd=ref)
+        gref = gr if gref is None else {k: gref[k] + gr[k] for k in PARAMS}
+    dev, proj, bins, img, _, ncon = gpu_forward(sss, s, cams)
+    dl = torch.as_tensor(np.concatenate(ws), dtype=torch.float32, device="cuda")
+    g = sss.render_bwd(dev, proj, bins, cams, dl, image=img, n_contrib=ncon)
+    torch.cuda.synchronize()
+    for k in PARAMS:
+        ok, worst = grad_close(g[k].cpu().numpy(), gref[k])
+        assert ok, (k, worst)
+
+
+# ---------------------------------------------------------------------------
+# SGHMC / Adam
+# ---------------------------------------------------------------------------
+def _sg(n, seed):
+    rng = np.random.default_rng(seed)
+    f = lambda a: a.astype(np.float32)
+    return (f(rng.standard_normal((n, 3))), f(rng.standard_normal((n, 3))), f(rng.standard_normal((n, 3))),
+            f(rng.uniform(-1, 1, n)), f(np.exp(rng.uniform(-4, -2, (n, 3)))), f(rng.standard_normal((n, 4))))
+
+
+@pytest.mark.parametrize("burn_in,noise,t", [(False, True, 0.995), (True, True, 0.995), (False, False, -1.0),
+                                             (False, True, -1.0)])
+def test_sghmc_matches_oracle(sss, burn_in, noise, t):
+    n = 20000
+    mu, r, g, o, sc, q = _sg(n, 31)
+    lr = 0.01
+    ref_mu, ref_r = oracle.sghmc_step(mu, r, g, o, sc, q, lr, 0.1, 100.0, t, burn_in, noise, seed=77, step=12)
+    T = lambda a: torch.as_tensor(a, device="cuda")
+    dmu, dr = T(mu.copy()), T(r.copy())
+    sss.sghmc_step(dmu, dr, T(g), T(o), lr, 0.1, 100.0, t, burn_in, noise, seed=77, step=12, scales=T(sc), quats=T(q))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(dmu.cpu().numpy(), ref_mu, rtol=1e-5, atol=2e-6)
+    np.testing.assert_allclose(dr.cpu().numpy(), ref_r, rtol=1e-5, atol=2e-6)
+
+
+def test_sghmc_noise_is_the_oracles_philox_stream(sss):
+    """From rest with G = 0 the momentum is exactly the noise n = sqrt(2 eps C) z;
+    z must match the oracle's Philox/Box-Muller normals draw for draw."""
+    n = 50000
+    z0 = np.zeros((n, 3), np.float32)
+    T = lambda a: torch.as_tensor(a, device="cuda")
+    mu, r = T(z0.copy()), T(z0.copy())
+    lr, C = 0.02, 0.1
+    sss.sghmc_step(mu, r, T(z0), T(np.ones(n, np.float32)), lr, C, seed=2 ** 40 + 17, step=2 ** 33 + 5)
+    torch.cuda.synchronize()
+    z = r.cpu().numpy() / math.sqrt(2 * lr * C)
+    for i in list(range(0, n, 997)) + [n - 1]:
+        np.testing.assert_allclose(z[i], oracle.normals3(i, 2 ** 40 + 17, 2 ** 33 + 5), rtol=2e-5, atol=2e-5)
+
+
+def test_adam_matches_oracle(sss):
+    rng = np.random.default_rng(3)
+    p, g = rng.standard_normal(5000).astype(np.float32), rng.standard_normal(5000).astype(np.float32)
+    m, v = (rng.standard_normal(5000) * 0.1).astype(np.float32), rng.uniform(0, 0.1, 5000).astype(np.float32)
+    f32 = lambda x: float(np.float32(x))          # the library receives FP32 hyper-parameters
+    ref = oracle.adam_step(p, g, m, v, lr=f32(0.01), b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8), t=7, lo=-1.0, hi=1.0)
+    T = lambda a: torch.as_tensor(a.copy(), device="cuda")
+    dp, dg, dm, dv = T(p), T(g), T(m), T(v)
+    z = torch.zeros((1, 3), device="cuda")
+    sss.sghmc_step(z.clone(), z.clone(), z.clone(), torch.ones(1, device="cuda"), 0.0, noise=False,
+                   adam=dict(beta1=0.9, beta2=0.999, eps=1e-8, t=7,
+                             arrays=[dict(param=dp, grad=dg, m=dm, v=dv, lr=0.01, lo=-1.0, hi=1.0)]))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(dp.cpu().numpy(), ref[0], rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(dm.cpu().numpy(), ref[1], rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(dv.cpu().numpy(), ref[2], rtol=1e-5, atol=1e-8)
