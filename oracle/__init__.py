@@ -66,14 +66,30 @@ def _f64(a):
 
 
 def cam_array(cam) -> np.ndarray:
-    """cam dict (viewmat 3x4, fx, fy, cx, cy, width, height) -> 18 doubles.
+    """cam dict (viewmat 3x4, fx, fy, cx, cy, width, height) -> 20 doubles.
 
     Every value is first rounded to FP32, because the library receives
-    FP32 cameras."""
+    FP32 cameras.  A window cut out of a larger image (see `window_camera`)
+    carries that image's size in 'clamp_size' for the EWA frustum clamp."""
     v = np.asarray(cam["viewmat"], dtype=np.float32).reshape(12)
     rest = np.array([cam["fx"], cam["fy"], cam["cx"], cam["cy"]], dtype=np.float32)
+    cw, ch = cam.get("clamp_size", (cam["width"], cam["height"]))
     return np.concatenate([v.astype(np.float64), rest.astype(np.float64),
-                           np.array([cam["width"], cam["height"]], dtype=np.float64)])
+                           np.array([cam["width"], cam["height"], cw, ch], dtype=np.float64)])
+
+
+def window_camera(cam, x0, y0, w, h):
+    """The camera that renders pixels [x0, x0+w) x [y0, y0+h) of `cam`.
+
+    The principal point moves by the window origin (exact in FP32 for
+    integer offsets) and the frustum clamp keeps the full image's size, so
+    every pixel of the window gets the same value as in the full render."""
+    c = dict(cam)
+    c["cx"] = float(np.float32(cam["cx"]) - np.float32(x0))
+    c["cy"] = float(np.float32(cam["cy"]) - np.float32(y0))
+    c["width"], c["height"] = int(w), int(h)
+    c["clamp_size"] = cam.get("clamp_size", (cam["width"], cam["height"]))
+    return c
 
 
 DEFAULT_OPTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, z_near=0.2, nu_min=1.0,

@@ -37,7 +37,10 @@
  * readings stated in the design notes.
  *
  * Layouts (all doubles unless noted, row-major):
- *   cam[18]  = viewmat (3x4 world->camera) [12], fx, fy, cx, cy, width, height
+ *   cam[20]  = viewmat (3x4 world->camera) [12], fx, fy, cx, cy, width, height,
+ *              clamp_width, clamp_height (the image size whose half field of
+ *              view bounds the EWA Jacobian; equal to width, height except
+ *              for a window cut out of a larger image)
  *   opts[10] = alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass,
  *              bg_r, bg_g, bg_b
  */
@@ -237,7 +240,7 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
   const int tx_n = orc_tiles_x(cam), ty_n = orc_tiles_y(cam);
   const double alpha_min = opts[0], z_near = opts[3], nu_min = opts[4], nu_max = opts[5];
   const double lowpass = opts[6];
-  const double limx = 1.3 * (W / (2.0 * fx)), limy = 1.3 * (H / (2.0 * fy));
+  const double limx = 1.3 * (cam[18] / (2.0 * fx)), limy = 1.3 * (cam[19] / (2.0 * fy));
   /* camera centre: -R^T t */
   double campos[3];
   for (int a = 0; a < 3; ++a)
@@ -576,9 +579,8 @@ void orc_project_backward(int n, int sh_degree, const double* means, const doubl
   const int K = (sh_degree + 1) * (sh_degree + 1);
   const double* Wm = cam;
   const double fx = cam[12], fy = cam[13];
-  const int W = (int)cam[16], H = (int)cam[17];
   const double nu_min = opts[4], nu_max = opts[5], lowpass = opts[6];
-  const double limx = 1.3 * (W / (2.0 * fx)), limy = 1.3 * (H / (2.0 * fy));
+  const double limx = 1.3 * (cam[18] / (2.0 * fx)), limy = 1.3 * (cam[19] / (2.0 * fy));
   double campos[3];
   for (int a = 0; a < 3; ++a)
     campos[a] = -(Wm[0 * 4 + a] * Wm[3] + Wm[1 * 4 + a] * Wm[7] + Wm[2 * 4 + a] * Wm[11]);

@@ -472,3 +472,13 @@ def test_adam_first_step_moves_by_lr_times_sign(oracle_lib):
     np.testing.assert_allclose(p1, p - 0.01 * np.sign(g), atol=1e-12)
     np.testing.assert_allclose(m, 0.1 * g)
     np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_window_render_equals_crop_of_full_render(oracle_lib):
+    """A window camera reproduces the crop of the full image (same clamp)."""
+    s = scenes.make_scene(600, 2, seed=71, neg_frac=0.3)
+    s["scales"] *= np.float32(2.0)
+    cam = scenes.ring_camera(160, 120, angle=0.8)
+    full = oracle_lib.render(s, cam)
+    win = oracle_lib.render(s, oracle_lib.window_camera(cam, 37, 21, 70, 50))
+    np.testing.assert_allclose(win["image"], full["image"][21:71, 37:107], rtol=0, atol=1e-12)
