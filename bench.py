@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of one training step of the Student's t rasterizer hot path.
+
+A step = sss_project -> sss_bin_sort -> sss_render_fwd -> sss_render_bwd
+(L1 loss against a target image, gradient fused into the backward) ->
+sss_sghmc_step (SGHMC on the means, Adam on the other parameters), over one
+batch of seeded synthetic input resident in HBM.
+
+Default workload (the throughput metric's configuration): 1M components, SH
+degree 3, one 1920x1080 camera on a ring of radius 4.
+
+    python bench.py [--steps K] [--warmup W] [--mode stored|recompute]
+                    [--workload m1|train|small|large] [--no-cpu-baseline]
+
+Prints ONE JSON line.  Only one GPU is used: --gpus N with N > 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpix/s & HBM GB/s @1M comps 1080p; serving p50/p99 ms vs plain"
+
+# VALU issue slots per (pixel, component) evaluation that the definition
+# needs (FP32 ops counted 1, transcendentals 4): forward 28, backward 70.
+SLOTS_FWD, SLOTS_BWD = 28, 70
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz FP32 lane-ops per second
+# (no packed FP32), and 8 TB/s HBM3E.
+PEAK_VALU = 256 * 4 * 16 * 2.4e9
+PEAK_HBM = 8.0e12
+
+WORKLOADS = {
+    "m1": "1M components, SH degree 3, one 1920x1080 camera, fwd+bwd+SGHMC",
+    "train": "300k components, SH degree 3, one 1297x840 camera, fwd+bwd+SGHMC",
+    "small": "10k components, SH degree 0, one 256x256 camera, fwd+bwd+SGHMC",
+    "large": "3M clustered components, nu 1..150, 30% negative, one 1920x1080 camera, fwd+bwd+SGHMC",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(workload):
+    from paper_2503_10148_amd import scenes
+    scene, cams = scenes.workload(workload)
+    target = scenes.smooth_target(cams[0]["width"], cams[0]["height"])
+    return scene, cams, target
+
+
+def cpu_baseline(scene, cam, budget_px=128 * 128):
+    """The FP64 oracle on a bounded sample: full projection (+ its backward)
+    of every component and the raster fwd+bwd of a central window; the raster
+    time is scaled to the full frame."""
+    import oracle
+    from paper_2503_10148_amd import scenes
+    W, H = cam["width"], cam["height"]
+    side = int(math.sqrt(budget_px))
+    x0, y0 = (W - side) // 2 // 16 * 16, (H - side) // 2 // 16 * 16
+    win = oracle.window_camera(cam, x0, y0, side, side)
+    target = scenes.smooth_target(W, H)[y0:y0 + side, x0:x0 + side]
+    t0 = time.perf_counter()
+    proj = oracle.project(scene, win)
+    t1 = time.perf_counter()
+    fwd = oracle.render(scene, win, proj=proj)
+    t2 = time.perf_counter()
+    g = oracle.l1_grad(fwd["image"], target)
+    oracle.render_backward(scene, win, g, fwd=fwd)
+    t3 = time.perf_counter()
+    # the backward call includes the per-component projection backward;
+    # count it with the projection, estimated as the forward projection time
+    t_proj = (t1 - t0) * 2.0
+    t_raster = (t2 - t1) + (t3 - t2) - (t1 - t0)
+    t_frame = t_proj + max(t_raster, 0.0) * (W * H) / float(side * side)
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return {"value": round(W * H / t_frame / 1e6, 6), "unit": "Mpix/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"FP64 oracle: projection of all {scene['means'].shape[0]} components, raster fwd+bwd of a "
+                       f"{side}x{side} window at ({x0},{y0}) scaled to {W}x{H}; measured {t3 - t0:.1f} s, "
+                       f"projection/compositing loops on {threads} OpenMP threads, raster backward single-threaded")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="m1", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="stored", choices=["stored", "recompute"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-window", type=int, default=128 * 128)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (one GPU per box in this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_10148_amd import sss
+    PARAMS = ("means", "scales", "quats", "nu", "opacity", "sh")
+
+    torch.cuda.set_device(0)
+    scene_np, cams, target_np = make_inputs(args.workload)
+    n = scene_np["means"].shape[0]
+    P = sss.total_pixels(cams)
+    log(f"workload {args.workload}: n={n} pixels={P}")
+    scene = sss.scene_to_device(scene_np)
+    target = torch.as_tensor(target_np.reshape(-1, 3), device="cuda")
+    mom = torch.zeros_like(scene["means"])
+    grads = {k: torch.zeros_like(scene[k]) for k in PARAMS}
+    adam_state = {k: (torch.zeros_like(scene[k]), torch.zeros_like(scene[k])) for k in PARAMS if k != "means"}
+    bounds = dict(scales=(1e-4, 3.0e38), quats=(-3.0e38, 3.0e38), nu=(1.0, 1e4), opacity=(-1.0, 1.0),
+                  sh=(-3.0e38, 3.0e38))
+    lrs = dict(scales=1e-4, quats=1e-3, nu=1e-2, opacity=1e-3, sh=2.5e-4)
+    binner = sss.BinSorter(0)
+    image = torch.empty((P, 3), device="cuda")
+    t_final = torch.empty(P, device="cuda")
+    n_contrib = torch.empty(P, dtype=torch.int32, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    bwd_ws = torch.empty(int(sss.lib().sss_render_bwd_workspace(n * len(cams))) // 4, device="cuda")
+    mode = sss.BWD_STORED if args.mode == "stored" else sss.BWD_RECOMPUTE
+    state = {"proj": None, "bins": None}
+
+    def step(it):
+        proj = sss.project(scene, cams, out=state["proj"])
+        state["proj"] = proj
+        bins = binner(proj, cams, n, out=state["bins"])
+        state["bins"] = bins
+        if mode == sss.BWD_STORED:
+            sss.render_fwd(bins, cams, image=image, t_final=t_final, n_contrib=n_contrib)
+            sss.render_bwd(scene, proj, bins, cams, target, mode=mode, loss=sss.LOSS_L1, image=image,
+                           n_contrib=n_contrib, loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True)
+        else:
+            sss.render_bwd(scene, proj, bins, cams, target, mode=mode, loss=sss.LOSS_L1, image_out=image,
+                           loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True)
+        adam = dict(beta1=0.9, beta2=0.999, eps=1e-15, t=it + 1,
+                    arrays=[dict(param=scene[k], grad=grads[k], m=adam_state[k][0], v=adam_state[k][1], lr=lrs[k],
+                                 lo=bounds[k][0], hi=bounds[k][1]) for k in adam_state])
+        sss.sghmc_step(scene["means"], mom, grads["means"], scene["opacity"], lr=1e-3, friction=0.1, seed=4,
+                       step=it, scales=scene["scales"], quats=scene["quats"], adam=adam)
+
+    for it in range(args.warmup):
+        step(it)
+    torch.cuda.synchronize()
+    log(f"warmup done: pairs={state['bins'].n_pairs} visible={state['bins'].n_visible}")
+
+    sss.timing_enable(True)
+    sss.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.warmup, args.warmup + args.steps):
+        step(it)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = sss.timing_read()
+    sss.timing_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = P * args.steps / (t1 - t0) / 1e6
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.1f} Mpix/s")
+
+    # algorithmic work of the last step
+    if mode == sss.BWD_RECOMPUTE:
+        sss.render_fwd(state["bins"], cams, image=image, t_final=t_final, n_contrib=n_contrib)
+    torch.cuda.synchronize()
+    evals = float(n_contrib.to(torch.float64).sum().item())
+    bins = state["bins"]
+    avg = {k: v[1] / v[0] for k, v in kt.items()}          # ms per launch
+    per_step = {k: v[1] / args.steps for k, v in kt.items()}
+    bwd_ms = avg.get("render_bwd", float("nan"))
+    achieved = SLOTS_BWD * evals / (bwd_ms * 1e-3)
+    # compulsory HBM bytes of the HBM-bound kernels (per launch)
+    K = (scene_np["sh_degree"] + 1) ** 2
+    par_b = 4 * (3 + 3 + 4 + 1 + 1 + 3 * K)
+    bytes_ = {
+        "project": n * len(cams) * (par_b + 64 + 16),
+        "project_bwd": n * (par_b + 48 + 4 + par_b),
+        "sghmc": n * 64,
+        "adam": n * (3 + 4 + 1 + 1 + 3 * K) * 28 / 5,           # per launch, 5 arrays
+    }
+    stages = {k: {"ms_per_step": round(per_step[k], 4), "launches_per_step": kt[k][0] / args.steps}
+              for k in sorted(kt)}
+    for k, b in bytes_.items():
+        if k in avg:
+            stages[k]["alg_gbps"] = round(b / (avg[k] * 1e-3) / 1e9, 1)
+            stages[k]["hbm_frac"] = round(b / (avg[k] * 1e-3) / PEAK_HBM, 4)
+    if "render_fwd" in avg:
+        stages["render_fwd"]["valu_frac"] = round(SLOTS_FWD * evals / (avg["render_fwd"] * 1e-3) / PEAK_VALU, 4)
+    step_bytes = (bytes_["project"] + bytes_["project_bwd"] + bytes_["sghmc"] + 5 * bytes_["adam"]
+                  + 16 * n + 136 * bins.n_visible + 8 * bins.n_pairs + P * (12 + 12 + 4 + 12))
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "components": n,
+                   "pixels_per_step": P, "bwd_mode": args.mode, "loss": "L1", "pairs": bins.n_pairs,
+                   "visible": bins.n_visible, "evaluations": evals},
+        "hbm_gbps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "roofline": {"bound": "alu", "kernel": "render_bwd", "achieved": round(achieved / 1e12, 3),
+                     "peak": round(PEAK_VALU / 1e12, 3), "unit": "Tops/s",
+                     "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
+                     "avg_ms": round(bwd_ms, 4), "units": evals, "ops_per_unit": SLOTS_BWD},
+        "stages": stages,
+        "loss": float(loss.item()) / (args.warmup + args.steps),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(scene_np, cams[0], args.cpu_window)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

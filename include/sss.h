@@ -77,8 +77,10 @@ typedef struct {
   const float* sh;
 } sss_scene_t;
 
-/* Gradients with the same layout as sss_scene_t (device, FP32).  Calls ADD
- * into them (+=); the caller zeroes them.  A NULL array is skipped. */
+/* Gradients with the same layout as sss_scene_t (device, FP32).  With
+ * overwrite = 0 calls ADD into them (+=; the caller zeroes them first); with
+ * overwrite = 1 every element is written, components that no view sees get 0.
+ * A NULL array is skipped. */
 typedef struct {
   float* means;
   float* scales;
@@ -86,6 +88,8 @@ typedef struct {
   float* nu;
   float* opacity;
   float* sh;
+  int32_t overwrite;
+  int32_t reserved;
 } sss_grads_t;
 
 /* Pinhole camera, OpenCV axes (x right, y down, z forward).  viewmat is the
@@ -207,7 +211,7 @@ int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views
  *   loss SSS_LOSS_L1        dl_or_target = target [P][3]; L = mean |image - target|
  *                           over all 3P values; loss_out (device float,
  *                           nullable) receives += L
- * grads: += (see sss_grads_t).  Workspace: ws_bytes >=
+ * grads: += or = (see sss_grads_t).  Workspace: ws_bytes >=
  * sss_render_bwd_workspace(n_views*n) (per-entry screen-space gradients).
  * Errors: INVALID for NULL pointers, a short workspace, unknown mode/loss. */
 enum { SSS_BWD_STORED = 0, SSS_BWD_RECOMPUTE = 1 };
@@ -261,6 +265,24 @@ typedef struct {
 int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const float* opacity,
                    const float* scales, const float* quats, int64_t n,
                    const sss_sghmc_opts_t* opts, const sss_adam_t* adam, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (tracing).  When enabled, every kernel the library launches
+ * is bracketed by two HIP events on its own stream; sss_timing_read waits
+ * for the recorded events and returns, per kernel name, the number of
+ * launches and their summed duration in milliseconds since the last reset.
+ * Off by default; the events cost a few microseconds per launch.
+ * sss_timing_read returns the number of entries written (<= max_entries) or
+ * a negative error code. */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} sss_kernel_time_t;
+
+int sss_timing_enable(int on);
+void sss_timing_reset(void);
+int sss_timing_read(sss_kernel_time_t* out, int max_entries);
 
 /* ------------------------------------------------------------------------ */
 const char* sss_last_error(void);   /* message of the last failed call on this thread */

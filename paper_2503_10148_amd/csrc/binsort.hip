@@ -92,14 +92,14 @@ void scan_excl(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* ws, hipSt
   if (n <= 0) return;
   const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
   if (nb == 1) {
-    hipLaunchKernelGGL(scan_apply_kernel, dim3(1), dim3(kBlock), 0, st, in, n, (const uint32_t*)nullptr, out);
+    SSS_LAUNCH("scan_apply", scan_apply_kernel, dim3(1), dim3(kBlock), 0, st, in, n, (const uint32_t*)nullptr, out);
     return;
   }
   uint32_t* sums = ws;
   uint32_t* sums_scan = ws + nb;
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, sums);
+  SSS_LAUNCH("scan_reduce", scan_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, sums);
   scan_excl(sums, sums_scan, nb, ws + 2 * nb, st);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n,
+  SSS_LAUNCH("scan_apply", scan_apply_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n,
                      (const uint32_t*)sums_scan, out);
 }
 
@@ -339,10 +339,10 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
     uint32_t* iv = (p % 2 == 0) ? va : vb;
     uint32_t* okk = (p % 2 == 0) ? kb : ka;
     uint32_t* ovv = (p == passes - 1) ? out_v : ((p % 2 == 0) ? vb : va);
-    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, n, shift,
+    SSS_LAUNCH("radix_hist", radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, n, shift,
                        (uint32_t)((1u << bits) - 1u), nb, w.hist);
     scan_excl(w.hist, w.hist, 256 * nb, w.scan, st);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, iv, n, shift, bits,
+    SSS_LAUNCH("radix_scatter", radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, iv, n, shift, bits,
                        nb, (const uint32_t*)w.hist, okk, ovv);
   }
   return final_keys;
@@ -370,10 +370,10 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
   }
   const unsigned g1 = (unsigned)((n_entries + kBlock - 1) / kBlock);
   if (!hip_ok(hipMemsetAsync(w.counters, 0, 4 * sizeof(unsigned long long), st), "memset")) return SSS_ERR_HIP;
-  hipLaunchKernelGGL(visible_kernel, dim3(g1), dim3(kBlock), 0, st, proj.tiles_touched, n_entries, w.flags,
+  SSS_LAUNCH("visible", visible_kernel, dim3(g1), dim3(kBlock), 0, st, proj.tiles_touched, n_entries, w.flags,
                      w.counters);
   scan_excl(w.flags, w.pos, n_entries, w.scan, st);
-  hipLaunchKernelGGL(compact_kernel, dim3(g1), dim3(kBlock), 0, st, w.flags, w.pos, proj.depth_key, n_entries,
+  SSS_LAUNCH("compact", compact_kernel, dim3(g1), dim3(kBlock), 0, st, w.flags, w.pos, proj.depth_key, n_entries,
                      w.ka, w.va, w.counters);
   unsigned long long counts[2];
   if (!hip_ok(hipMemcpyAsync(counts, w.counters, sizeof(counts), hipMemcpyDeviceToHost, st), "count readback"))
@@ -395,10 +395,10 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
   // 3. pair offsets in rank order, emission, record gather
   if (n_vis > 0) {
     const unsigned gv = (unsigned)((n_vis + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(touched_by_rank_kernel, dim3(gv), dim3(kBlock), 0, st, bins->order, proj.tiles_touched,
+    SSS_LAUNCH("touched_by_rank", touched_by_rank_kernel, dim3(gv), dim3(kBlock), 0, st, bins->order, proj.tiles_touched,
                        n_vis, w.flags);
     scan_excl(w.flags, w.pos, n_vis, w.scan, st);
-    hipLaunchKernelGGL(emit_kernel, dim3(gv), dim3(kBlock), 0, st, cb, n, bins->order,
+    SSS_LAUNCH("emit", emit_kernel, dim3(gv), dim3(kBlock), 0, st, cb, n, bins->order,
                        (const ushort4*)proj.rect, w.pos, n_vis, (uint32_t)m, (const uint4*)proj.records,
                        (uint4*)bins->sorted_records, w.ka, w.va);
   }
@@ -406,7 +406,7 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
   const uint32_t* tkeys = radix_sort(w.ka, w.va, w.kb, w.vb, m, bits_for((int64_t)cb.total_tiles + 1), bins->pair_rank, w, st);
   // 5. tile ranges
   const unsigned gt = (unsigned)((m + 1 + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(tile_start_kernel, dim3(gt), dim3(kBlock), 0, st, tkeys, m,
+  SSS_LAUNCH("tile_start", tile_start_kernel, dim3(gt), dim3(kBlock), 0, st, tkeys, m,
                      (int64_t)cb.total_tiles, bins->tile_start);
   if (!hip_ok(hipGetLastError(), "bin_sort launch")) return SSS_ERR_HIP;
   return SSS_OK;

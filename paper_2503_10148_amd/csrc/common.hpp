@@ -53,6 +53,25 @@ static_assert(sizeof(Rec) == SSS_RECORD_BYTES, "record size");
 // d/d(mx, my), d/d(qa, qb, qc), d/d(cr, cg, cb), d/do, d/dnu (+2 pad).
 constexpr int kG2 = 12;
 
+// Brackets one kernel launch with HIP events when timing is enabled.
+class KernelTimer {
+ public:
+  KernelTimer(const char* name, hipStream_t st);
+  ~KernelTimer();
+
+ private:
+  const char* name_;
+  hipStream_t st_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+// Launch with optional event timing under the kernel's short name.
+#define SSS_LAUNCH(label, kernel, grid, block, shmem, stream, ...)         \
+  do {                                                                     \
+    ::sss::KernelTimer sss_kt_(label, stream);                             \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);   \
+  } while (0)
+
 void set_error(const char* fmt, ...);
 bool hip_ok(hipError_t e, const char* what);
 int make_cam_batch(const sss_camera_t* cams, int n_views, CamBatch* out);

@@ -254,12 +254,14 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     const float* __restrict__ scales, const float* __restrict__ quats, const float* __restrict__ nu,
     const float* __restrict__ sh, const uint32_t* __restrict__ touched, const float* __restrict__ g2,
     float* __restrict__ d_means, float* __restrict__ d_scales, float* __restrict__ d_quats,
-    float* __restrict__ d_nu, float* __restrict__ d_opac, float* __restrict__ d_sh) {
+    float* __restrict__ d_nu, float* __restrict__ d_opac, float* __restrict__ d_sh, int overwrite) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const float* mu = means + 3 * i;
   const float* s = scales + 3 * i;
   const int K = (deg + 1) * (deg + 1);
+  if (overwrite && d_sh)
+    for (int k = 0; k < 3 * K; ++k) d_sh[(size_t)i * K * 3 + k] = 0.0f;
   double gmu[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
   double gnu = 0.0, gop = 0.0;
   bool any = false;
@@ -383,14 +385,21 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     gmu[1] += (gy - dir[1] * dd) * ivn;
     gmu[2] += (gz - dir[2] * dd) * ivn;
   }
-  if (!any) return;
-  if (d_means) for (int a = 0; a < 3; ++a) d_means[3 * i + a] += (float)gmu[a];
-  if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] += (float)gs[a];
-  if (d_quats) for (int a = 0; a < 4; ++a) d_quats[4 * i + a] += (float)gq[a];
-  if (d_opac) d_opac[i] += (float)gop;
-  if (d_nu) {
-    const float nv = nu[i];
-    if (nv >= op.nu_min && nv <= op.nu_max) d_nu[i] += (float)gnu;
+  if (!any && !overwrite) return;
+  const float nv = nu[i];
+  if (!(nv >= op.nu_min && nv <= op.nu_max)) gnu = 0.0;
+  if (overwrite) {
+    if (d_means) for (int a = 0; a < 3; ++a) d_means[3 * i + a] = (float)gmu[a];
+    if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] = (float)gs[a];
+    if (d_quats) for (int a = 0; a < 4; ++a) d_quats[4 * i + a] = (float)gq[a];
+    if (d_opac) d_opac[i] = (float)gop;
+    if (d_nu) d_nu[i] = (float)gnu;
+  } else {
+    if (d_means) for (int a = 0; a < 3; ++a) d_means[3 * i + a] += (float)gmu[a];
+    if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] += (float)gs[a];
+    if (d_quats) for (int a = 0; a < 4; ++a) d_quats[4 * i + a] += (float)gq[a];
+    if (d_opac) d_opac[i] += (float)gop;
+    if (d_nu) d_nu[i] += (float)gnu;
   }
 }
 
@@ -399,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
 void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s, const sss_proj_t& out,
                     hipStream_t st) {
   dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock), (unsigned)cb.n_views);
-  hipLaunchKernelGGL(project_kernel, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, (int)s.sh_degree,
+  SSS_LAUNCH("project", project_kernel, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, (int)s.sh_degree,
                      s.means, s.scales, s.quats, s.nu, s.opacity, s.sh, (Rec*)out.records, out.depth_key,
                      (ushort4*)out.rect, out.tiles_touched);
 }
@@ -407,9 +416,9 @@ void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
 void launch_project_bwd(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s, const uint32_t* touched,
                         const float* g2, const sss_grads_t& gr, hipStream_t st) {
   dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock));
-  hipLaunchKernelGGL(project_bwd_kernel, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, (int)s.sh_degree,
+  SSS_LAUNCH("project_bwd", project_bwd_kernel, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, (int)s.sh_degree,
                      s.means, s.scales, s.quats, s.nu, s.sh, touched, g2, gr.means, gr.scales, gr.quats,
-                     gr.nu, gr.opacity, gr.sh);
+                     gr.nu, gr.opacity, gr.sh, (int)gr.overwrite);
 }
 
 }  // namespace sss

@@ -349,13 +349,13 @@ void launch_zero(float* p, int64_t count, hipStream_t st) {
   // count is a multiple of 4 for every caller (kG2 = 12 floats per entry)
   const int64_t n4 = count / 4;
   if (n4 <= 0) return;
-  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+  SSS_LAUNCH("zero", zero_kernel, dim3((unsigned)((n4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                      (float4*)p, n4);
 }
 
 void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, float* image, float* t_final,
                        uint32_t* n_contrib, hipStream_t st) {
-  hipLaunchKernelGGL(render_fwd_kernel, dim3((unsigned)cb.total_tiles), dim3(kBlock), 0, st, cb, op,
+  SSS_LAUNCH("render_fwd", render_fwd_kernel, dim3((unsigned)cb.total_tiles), dim3(kBlock), 0, st, cb, op,
                      (const Rec*)b.sorted_records, (const uint32_t*)b.tile_start, (const uint32_t*)b.pair_rank,
                      image, t_final, n_contrib);
 }
@@ -369,7 +369,7 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
   const uint32_t* ts = b.tile_start;
   const uint32_t* pr = b.pair_rank;
 #define SSS_BWD(M, L)                                                                                        \
-  hipLaunchKernelGGL((render_bwd_kernel<M, L>), grid, blk, 0, st, cb, op, sr, ts, pr, dl_or_target, image,  \
+  SSS_LAUNCH("render_bwd", (render_bwd_kernel<M, L>), grid, blk, 0, st, cb, op, sr, ts, pr, dl_or_target, image,  \
                      n_contrib, image_out, loss_out, inv_count, g2)
   if (mode == SSS_BWD_STORED && loss == SSS_LOSS_GRAD) SSS_BWD(SSS_BWD_STORED, SSS_LOSS_GRAD);
   else if (mode == SSS_BWD_STORED) SSS_BWD(SSS_BWD_STORED, SSS_LOSS_L1);

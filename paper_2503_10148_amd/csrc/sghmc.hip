@@ -94,16 +94,16 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(float* __restrict__ p, con
 
 void launch_sghmc(float* means, float* mom, const float* g, const float* opac, const float* scales,
                   const float* quats, int64_t n, const sss_sghmc_opts_t& o, hipStream_t st) {
-  hipLaunchKernelGGL(sghmc_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, means, mom, g,
+  SSS_LAUNCH("sghmc", sghmc_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, means, mom, g,
                      opac, scales, quats, n, o.lr, o.friction, o.k, o.t, (int)o.burn_in, (int)o.noise, o.seed, o.step);
 }
 
 void launch_adam(const sss_adam_array_t& a, float b1, float b2, float eps, int64_t t, hipStream_t st) {
-  // 1 - beta and the bias corrections in FP64: 1 - 0.999f in FP32 would lose 1e-5
+  // 1 - beta and the bias corrections on the host, in FP64
   const float c1 = (float)(1.0 - pow((double)b1, (double)t));
   const float c2 = (float)(1.0 - pow((double)b2, (double)t));
   const float omb1 = (float)(1.0 - (double)b1), omb2 = (float)(1.0 - (double)b2);
-  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((a.count + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a.param,
+  SSS_LAUNCH("adam", adam_kernel, dim3((unsigned)((a.count + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a.param,
                      a.grad, a.m, a.v, a.count, a.lr, b1, b2, omb1, omb2, eps, c1, c2, a.lo, a.hi);
 }
 

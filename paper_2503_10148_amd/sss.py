@@ -35,7 +35,8 @@ class Scene(ctypes.Structure):
 
 class Grads(ctypes.Structure):
     _fields_ = [("means", ctypes.c_void_p), ("scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
-                ("nu", ctypes.c_void_p), ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+                ("nu", ctypes.c_void_p), ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p),
+                ("overwrite", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Camera(ctypes.Structure):
@@ -78,6 +79,10 @@ class Adam(ctypes.Structure):
                 ("n_arrays", ctypes.c_int32), ("t", ctypes.c_int64), ("arrays", AdamArray * 6)]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
 EXPORTS = ["sss_default_render_opts", "sss_project", "sss_bin_sort", "sss_bin_sort_workspace", "sss_total_tiles",
            "sss_total_pixels", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_workspace", "sss_sghmc_step",
            "sss_last_error", "sss_version"]
@@ -109,6 +114,11 @@ def lib():
         L.sss_render_bwd.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                      ctypes.c_size_t, vp]
         L.sss_sghmc_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+        L.sss_timing_enable.argtypes = [i32]
+        L.sss_timing_enable.restype = i32
+        L.sss_timing_reset.restype = None
+        L.sss_timing_read.argtypes = [vp, i32]
+        L.sss_timing_read.restype = i32
         for name in ("sss_project", "sss_bin_sort", "sss_render_fwd", "sss_render_bwd", "sss_sghmc_step"):
             getattr(L, name).restype = i32
         _lib = L
@@ -172,6 +182,15 @@ def scene_struct(scene):
         _need(scene[k], torch.float32, k)
     return Scene(n, int(scene["sh_degree"]), 0, *(scene[k].data_ptr() for k in
                                                    ("means", "scales", "quats", "nu", "opacity", "sh")))
+
+
+def scene_to_device(scene, device="cuda"):
+    """numpy scene dict -> dict of contiguous float32 tensors on `device`."""
+    import numpy as np
+    out = {k: torch.as_tensor(np.ascontiguousarray(scene[k]), dtype=torch.float32, device=device)
+           for k in ("means", "scales", "quats", "nu", "opacity", "sh")}
+    out["sh_degree"] = int(scene["sh_degree"])
+    return out
 
 
 def total_tiles(cams):
@@ -282,17 +301,20 @@ def zero_grads_like(scene):
 
 def render_bwd(scene, proj: Projected, bins: Binned, cams, dl_or_target, opts=None, mode=BWD_STORED,
                loss=LOSS_GRAD, image=None, n_contrib=None, image_out=None, loss_out=None, grads=None,
-               ws=None, stream=None):
-    """Gradients (+= into `grads`, created zeroed if None).  Returns grads."""
+               ws=None, stream=None, overwrite=None):
+    """Gradients into `grads` (+= by default; written when overwrite, which is
+    the default when grads is None and new buffers are allocated)."""
     n = scene["means"].shape[0]
     E = n * len(cams)
     if grads is None:
-        grads = zero_grads_like(scene)
+        grads = {k: torch.empty_like(scene[k]) for k in ("means", "scales", "quats", "nu", "opacity", "sh")}
+        overwrite = True if overwrite is None else overwrite
+    overwrite = bool(overwrite)
     need = int(lib().sss_render_bwd_workspace(E))
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need // 4, dtype=torch.float32, device=scene["means"].device)
     s = scene_struct(scene)
-    g = Grads(*(grads[k].data_ptr() for k in ("means", "scales", "quats", "nu", "opacity", "sh")))
+    g = Grads(*(grads[k].data_ptr() for k in ("means", "scales", "quats", "nu", "opacity", "sh")), int(overwrite), 0)
     p = proj.struct()
     b = bins.struct()
     _check(lib().sss_render_bwd(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), camera_array(cams), len(cams),
@@ -320,3 +342,23 @@ def sghmc_step(means, momentum, grad_means, opacity, lr, friction=0.1, k=100.0, 
     _check(lib().sss_sghmc_step(_ptr(means), _ptr(momentum), _ptr(grad_means), _ptr(opacity), _ptr(scales),
                                 _ptr(quats), means.shape[0], ctypes.byref(o),
                                 ctypes.byref(ad) if ad is not None else None, _stream(stream)), "sss_sghmc_step")
+
+
+# ---------------------------------------------------------------------------
+# kernel timing
+# ---------------------------------------------------------------------------
+def timing_enable(on: bool = True):
+    _check(lib().sss_timing_enable(int(on)), "sss_timing_enable")
+
+
+def timing_reset():
+    lib().sss_timing_reset()
+
+
+def timing_read() -> dict:
+    """{kernel name: (launches, total ms)} since the last reset (waits for the events)."""
+    buf = (KernelTime * 64)()
+    k = lib().sss_timing_read(buf, 64)
+    if k < 0:
+        _check(k, "sss_timing_read")
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(k)}

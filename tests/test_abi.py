@@ -122,7 +122,7 @@ def test_render_bwd_rejects_unknown_mode_and_short_workspace(sss):
     scene = _scene_struct(sss)
     p = _proj_struct(sss)
     b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, 100, 0, 0)
-    g = sss.Grads(0, 0, 0, 0, 0, 0)
+    g = sss.Grads(0, 0, 0, 0, 0, 0, 0, 0)
     args = lambda mode, loss, wsb: (ctypes.byref(scene), ctypes.byref(p), ctypes.byref(b), cams, 1,
                                     ctypes.byref(opts), mode, loss, ctypes.c_void_p(0x6000), ctypes.c_void_p(0x7000),
                                     ctypes.c_void_p(0x8000), None, None, ctypes.byref(g), ctypes.c_void_p(0x9000),
