@@ -88,6 +88,38 @@ def cpu_baseline(scene, cam, budget_px=128 * 128):
                        f"projection/compositing loops on {threads} OpenMP threads, raster backward single-threaded")}
 
 
+def serving(scene_np, rates, seconds):
+    """Batched server vs plain one-request-per-launch on the resident 1M
+    scene (SH 3): Poisson arrivals, cameras on a sphere of radius 3..5,
+    resolution uniform over {640x360, 1280x720, 1920x1080}, batch <= 16."""
+    import torch
+    from paper_2503_10148_amd import scenes, serve, sss
+    scene = sss.scene_to_device(scene_np)
+    rng = np.random.default_rng(scenes.SEED_ARRIVALS)
+    sizes = [(640, 360), (1280, 720), (1920, 1080)]
+    res = {"workload": "resident scene of the bench workload; requests: camera direction uniform on the sphere, "
+                       "radius U[3,5], resolution uniform over 640x360/1280x720/1920x1080; batch <= 16, "
+                       "memory budget 6 GiB", "runs": []}
+    # warm both paths (allocator, code objects)
+    warm = [scenes.sphere_camera(rng, *sizes[i % 3]) for i in range(6)]
+    serve.run_load("plain", scene, warm, [0.0] * 6)
+    serve.run_load("batched", scene, warm, [0.0] * 6)
+    torch.cuda.synchronize()
+    for rate in rates:
+        arr = serve.poisson_arrivals(rate, seconds, rng)
+        cams = [scenes.sphere_camera(rng, *sizes[int(rng.integers(0, 3))]) for _ in arr]
+        px = sum(c["width"] * c["height"] for c in cams)
+        row = {"rate_req_s": rate, "requests": len(arr)}
+        for kind in ("plain", "batched"):
+            lat, wall, stats = serve.run_load(kind, scene, cams, arr)
+            row[kind] = {"p50_ms": round(serve.percentile(lat, 50) * 1e3, 3),
+                         "p99_ms": round(serve.percentile(lat, 99) * 1e3, 3),
+                         "mpix_s": round(px / wall / 1e6, 2), **stats}
+            log(f"serve rate {rate} {kind}: {row[kind]}")
+        res["runs"].append(row)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,7 +128,11 @@ def main():
     ap.add_argument("--workload", default="m1", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="stored", choices=["stored", "recompute"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=int, default=128 * 128)
+    ap.add_argument("--cpu-window", type=int, default=384 * 384)
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="arrival window of each serving run (0 disables the serving measurement)")
+    ap.add_argument("--serve-rates", default="200,1000",
+                    help="Poisson request rates (req/s) for the serving comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (one GPU per box in this build)",
@@ -220,6 +256,8 @@ def main():
         "stages": stages,
         "loss": float(loss.item()) / (args.warmup + args.steps),
     }
+    if args.serve_seconds > 0:
+        out["serving"] = serving(scene_np, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(scene_np, cams[0], args.cpu_window)

@@ -24,135 +24,139 @@ constexpr double kY3c = 0.4570457994644658;   // y(4zz - xx - yy), x(4zz - xx - 
 constexpr double kY3d = 0.3731763325901154;   // z(2zz - 3xx - 3yy)
 constexpr double kY3e = 1.445305721320277;    // z(xx - yy)
 
-__device__ __forceinline__ void sh_basis(int deg, double x, double y, double z, double* Y) {
-  Y[0] = kY0;
+template <typename F>
+__device__ __forceinline__ void sh_basis(int deg, F x, F y, F z, F* Y) {
+  Y[0] = F(kY0);
   if (deg < 1) return;
-  Y[1] = -kY1 * y;
-  Y[2] = kY1 * z;
-  Y[3] = -kY1 * x;
+  Y[1] = -F(kY1) * y;
+  Y[2] = F(kY1) * z;
+  Y[3] = -F(kY1) * x;
   if (deg < 2) return;
-  const double xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = kY2a * x * y;
-  Y[5] = -kY2a * y * z;
-  Y[6] = kY2b * (2.0 * zz - xx - yy);
-  Y[7] = -kY2a * x * z;
-  Y[8] = kY2c * (xx - yy);
+  const F xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = F(kY2a) * x * y;
+  Y[5] = -F(kY2a) * y * z;
+  Y[6] = F(kY2b) * (F(2.0) * zz - xx - yy);
+  Y[7] = -F(kY2a) * x * z;
+  Y[8] = F(kY2c) * (xx - yy);
   if (deg < 3) return;
-  Y[9] = -kY3a * y * (3.0 * xx - yy);
-  Y[10] = kY3b * x * y * z;
-  Y[11] = -kY3c * y * (4.0 * zz - xx - yy);
-  Y[12] = kY3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-  Y[13] = -kY3c * x * (4.0 * zz - xx - yy);
-  Y[14] = kY3e * z * (xx - yy);
-  Y[15] = -kY3a * x * (xx - 3.0 * yy);
+  Y[9] = -F(kY3a) * y * (F(3.0) * xx - yy);
+  Y[10] = F(kY3b) * x * y * z;
+  Y[11] = -F(kY3c) * y * (F(4.0) * zz - xx - yy);
+  Y[12] = F(kY3d) * z * (F(2.0) * zz - F(3.0) * xx - F(3.0) * yy);
+  Y[13] = -F(kY3c) * x * (F(4.0) * zz - xx - yy);
+  Y[14] = F(kY3e) * z * (xx - yy);
+  Y[15] = -F(kY3a) * x * (xx - F(3.0) * yy);
 }
 
 // Gradient of sum_k w[k] Y_k(x, y, z) (polynomial extension) w.r.t. (x, y, z).
-__device__ __forceinline__ void sh_basis_grad(int deg, double x, double y, double z, const double* w,
-                                              double* gx, double* gy, double* gz) {
-  double ax = 0.0, ay = 0.0, az = 0.0;
+template <typename F>
+__device__ __forceinline__ void sh_basis_grad(int deg, F x, F y, F z, const F* w, F* gx, F* gy, F* gz) {
+  F ax = 0, ay = 0, az = 0;
   if (deg >= 1) {
-    ay += -kY1 * w[1];
-    az += kY1 * w[2];
-    ax += -kY1 * w[3];
+    ay += -F(kY1) * w[1];
+    az += F(kY1) * w[2];
+    ax += -F(kY1) * w[3];
   }
   if (deg >= 2) {
-    ax += kY2a * y * w[4];             ay += kY2a * x * w[4];
-    ay += -kY2a * z * w[5];            az += -kY2a * y * w[5];
-    ax += -2.0 * kY2b * x * w[6];      ay += -2.0 * kY2b * y * w[6];  az += 4.0 * kY2b * z * w[6];
-    ax += -kY2a * z * w[7];            az += -kY2a * x * w[7];
-    ax += 2.0 * kY2c * x * w[8];       ay += -2.0 * kY2c * y * w[8];
+    ax += F(kY2a) * y * w[4];             ay += F(kY2a) * x * w[4];
+    ay += -F(kY2a) * z * w[5];            az += -F(kY2a) * y * w[5];
+    ax += -F(2.0) * F(kY2b) * x * w[6];      ay += -F(2.0) * F(kY2b) * y * w[6];  az += F(4.0) * F(kY2b) * z * w[6];
+    ax += -F(kY2a) * z * w[7];            az += -F(kY2a) * x * w[7];
+    ax += F(2.0) * F(kY2c) * x * w[8];       ay += -F(2.0) * F(kY2c) * y * w[8];
   }
   if (deg >= 3) {
-    const double xx = x * x, yy = y * y, zz = z * z;
+    const F xx = x * x, yy = y * y, zz = z * z;
     // Y9 = -a (3 xx y - y^3)
-    ax += -kY3a * 6.0 * x * y * w[9];
-    ay += -kY3a * (3.0 * xx - 3.0 * yy) * w[9];
+    ax += -F(kY3a) * F(6.0) * x * y * w[9];
+    ay += -F(kY3a) * (F(3.0) * xx - F(3.0) * yy) * w[9];
     // Y10 = b x y z
-    ax += kY3b * y * z * w[10];  ay += kY3b * x * z * w[10];  az += kY3b * x * y * w[10];
+    ax += F(kY3b) * y * z * w[10];  ay += F(kY3b) * x * z * w[10];  az += F(kY3b) * x * y * w[10];
     // Y11 = -c (4 y zz - xx y - y^3)
-    ax += kY3c * 2.0 * x * y * w[11];
-    ay += -kY3c * (4.0 * zz - xx - 3.0 * yy) * w[11];
-    az += -kY3c * 8.0 * y * z * w[11];
+    ax += F(kY3c) * F(2.0) * x * y * w[11];
+    ay += -F(kY3c) * (F(4.0) * zz - xx - F(3.0) * yy) * w[11];
+    az += -F(kY3c) * F(8.0) * y * z * w[11];
     // Y12 = d (2 z^3 - 3 xx z - 3 yy z)
-    ax += -kY3d * 6.0 * x * z * w[12];
-    ay += -kY3d * 6.0 * y * z * w[12];
-    az += kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12];
+    ax += -F(kY3d) * F(6.0) * x * z * w[12];
+    ay += -F(kY3d) * F(6.0) * y * z * w[12];
+    az += F(kY3d) * (F(6.0) * zz - F(3.0) * xx - F(3.0) * yy) * w[12];
     // Y13 = -c (4 x zz - x^3 - x yy)
-    ax += -kY3c * (4.0 * zz - 3.0 * xx - yy) * w[13];
-    ay += kY3c * 2.0 * x * y * w[13];
-    az += -kY3c * 8.0 * x * z * w[13];
+    ax += -F(kY3c) * (F(4.0) * zz - F(3.0) * xx - yy) * w[13];
+    ay += F(kY3c) * F(2.0) * x * y * w[13];
+    az += -F(kY3c) * F(8.0) * x * z * w[13];
     // Y14 = e (xx z - yy z)
-    ax += kY3e * 2.0 * x * z * w[14];
-    ay += -kY3e * 2.0 * y * z * w[14];
-    az += kY3e * (xx - yy) * w[14];
+    ax += F(kY3e) * F(2.0) * x * z * w[14];
+    ay += -F(kY3e) * F(2.0) * y * z * w[14];
+    az += F(kY3e) * (xx - yy) * w[14];
     // Y15 = -a (x^3 - 3 x yy)
-    ax += -kY3a * (3.0 * xx - 3.0 * yy) * w[15];
-    ay += kY3a * 6.0 * x * y * w[15];
+    ax += -F(kY3a) * (F(3.0) * xx - F(3.0) * yy) * w[15];
+    ay += F(kY3a) * F(6.0) * x * y * w[15];
   }
   *gx = ax; *gy = ay; *gz = az;
 }
 
 // Rotation of a unit quaternion (w, x, y, z), row-major.
-__device__ __forceinline__ void rotation(const double* q, double* R) {
-  const double w = q[0], x = q[1], y = q[2], z = q[3];
-  R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
-  R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
-  R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+template <typename F>
+__device__ __forceinline__ void rotation(const F* q, F* R) {
+  const F w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = F(1.0) - F(2.0) * (y * y + z * z); R[1] = F(2.0) * (x * y - w * z);       R[2] = F(2.0) * (x * z + w * y);
+  R[3] = F(2.0) * (x * y + w * z);       R[4] = F(1.0) - F(2.0) * (x * x + z * z); R[5] = F(2.0) * (y * z - w * x);
+  R[6] = F(2.0) * (x * z - w * y);       R[7] = F(2.0) * (y * z + w * x);       R[8] = F(1.0) - F(2.0) * (x * x + y * y);
 }
 
 // Forward intermediates of one entry, shared by the forward and backward kernels.
+template <typename F>
 struct Geo {
-  double X, Y, Z;        // camera-space position
-  double qn, q[4];       // quaternion norm and unit quaternion
-  double Rq[9];          // component rotation
-  double S[6];           // Sigma (xx, xy, xz, yy, yz, zz)
-  double xz, yz, txz, tyz;
+  F X, Y, Z;        // camera-space position
+  F qn, q[4];       // quaternion norm and unit quaternion
+  F Rq[9];          // component rotation
+  F S[6];           // Sigma (xx, xy, xz, yy, yz, zz)
+  F xz, yz, txz, tyz;
   bool clx, cly;         // EWA clamp active
-  double M[6];           // J * Rview (2x3)
-  double A, B, D, det;   // 2D covariance (+lowpass) and determinant
+  F M[6];           // J * Rview (2x3)
+  F A, B, D, det;   // 2D covariance (+lowpass) and determinant
 };
 
+template <typename F>
 __device__ __forceinline__ void geometry(const CamDev& c, const OptsDev& op, const float* mu, const float* s,
-                                         const float* qraw, Geo& g) {
-  const double m0 = mu[0], m1 = mu[1], m2 = mu[2];
-  g.X = (double)c.R[0] * m0 + (double)c.R[1] * m1 + (double)c.R[2] * m2 + (double)c.t[0];
-  g.Y = (double)c.R[3] * m0 + (double)c.R[4] * m1 + (double)c.R[5] * m2 + (double)c.t[1];
-  g.Z = (double)c.R[6] * m0 + (double)c.R[7] * m1 + (double)c.R[8] * m2 + (double)c.t[2];
-  const double q0 = qraw[0], q1 = qraw[1], q2 = qraw[2], q3 = qraw[3];
+                                         const float* qraw, Geo<F>& g) {
+  const F m0 = mu[0], m1 = mu[1], m2 = mu[2];
+  g.X = (F)c.R[0] * m0 + (F)c.R[1] * m1 + (F)c.R[2] * m2 + (F)c.t[0];
+  g.Y = (F)c.R[3] * m0 + (F)c.R[4] * m1 + (F)c.R[5] * m2 + (F)c.t[1];
+  g.Z = (F)c.R[6] * m0 + (F)c.R[7] * m1 + (F)c.R[8] * m2 + (F)c.t[2];
+  const F q0 = qraw[0], q1 = qraw[1], q2 = qraw[2], q3 = qraw[3];
   g.qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-  const double iq = 1.0 / g.qn;
+  const F iq = F(1.0) / g.qn;
   g.q[0] = q0 * iq; g.q[1] = q1 * iq; g.q[2] = q2 * iq; g.q[3] = q3 * iq;
   rotation(g.q, g.Rq);
-  const double s0 = (double)s[0] * s[0], s1 = (double)s[1] * s[1], s2 = (double)s[2] * s[2];
-  const double* R = g.Rq;
+  const F s0 = (F)s[0] * s[0], s1 = (F)s[1] * s[1], s2 = (F)s[2] * s[2];
+  const F* R = g.Rq;
   g.S[0] = R[0] * R[0] * s0 + R[1] * R[1] * s1 + R[2] * R[2] * s2;
   g.S[1] = R[0] * R[3] * s0 + R[1] * R[4] * s1 + R[2] * R[5] * s2;
   g.S[2] = R[0] * R[6] * s0 + R[1] * R[7] * s1 + R[2] * R[8] * s2;
   g.S[3] = R[3] * R[3] * s0 + R[4] * R[4] * s1 + R[5] * R[5] * s2;
   g.S[4] = R[3] * R[6] * s0 + R[4] * R[7] * s1 + R[5] * R[8] * s2;
   g.S[5] = R[6] * R[6] * s0 + R[7] * R[7] * s1 + R[8] * R[8] * s2;
-  const double limx = 1.3 * (double)c.W / (2.0 * (double)c.fx);
-  const double limy = 1.3 * (double)c.H / (2.0 * (double)c.fy);
-  const double iz = 1.0 / g.Z;
+  const F limx = F(1.3) * (F)c.W / (F(2.0) * (F)c.fx);
+  const F limy = F(1.3) * (F)c.H / (F(2.0) * (F)c.fy);
+  const F iz = F(1.0) / g.Z;
   g.xz = g.X * iz;
   g.yz = g.Y * iz;
   g.clx = g.xz < -limx || g.xz > limx;
   g.cly = g.yz < -limy || g.yz > limy;
   g.txz = fmin(fmax(g.xz, -limx), limx);
   g.tyz = fmin(fmax(g.yz, -limy), limy);
-  const double j00 = c.fx * iz, j02 = -c.fx * g.txz * iz;
-  const double j11 = c.fy * iz, j12 = -c.fy * g.tyz * iz;
+  const F j00 = c.fx * iz, j02 = -c.fx * g.txz * iz;
+  const F j11 = c.fy * iz, j12 = -c.fy * g.tyz * iz;
   for (int k = 0; k < 3; ++k) {
     g.M[k] = j00 * c.R[k] + j02 * c.R[6 + k];
     g.M[3 + k] = j11 * c.R[3 + k] + j12 * c.R[6 + k];
   }
   // Sigma2 = M S M^T with S symmetric
-  double t0[3], t1[3];
-  const double* S = g.S;
+  F t0[3], t1[3];
+  const F* S = g.S;
   for (int r = 0; r < 2; ++r) {
-    const double* m = g.M + 3 * r;
-    double* t = r ? t1 : t0;
+    const F* m = g.M + 3 * r;
+    F* t = r ? t1 : t0;
     t[0] = m[0] * S[0] + m[1] * S[1] + m[2] * S[2];
     t[1] = m[0] * S[1] + m[1] * S[3] + m[2] * S[4];
     t[2] = m[0] * S[2] + m[1] * S[4] + m[2] * S[5];
@@ -163,14 +167,15 @@ __device__ __forceinline__ void geometry(const CamDev& c, const OptsDev& op, con
   g.det = g.A * g.D - g.B * g.B;
 }
 
-__device__ __forceinline__ void view_dir(const CamDev& c, const float* mu, double* dir, double* vn) {
+template <typename F>
+__device__ __forceinline__ void view_dir(const CamDev& c, const float* mu, F* dir, F* vn) {
   // camera centre = -R^T t
-  const double px = -((double)c.R[0] * c.t[0] + (double)c.R[3] * c.t[1] + (double)c.R[6] * c.t[2]);
-  const double py = -((double)c.R[1] * c.t[0] + (double)c.R[4] * c.t[1] + (double)c.R[7] * c.t[2]);
-  const double pz = -((double)c.R[2] * c.t[0] + (double)c.R[5] * c.t[1] + (double)c.R[8] * c.t[2]);
-  const double vx = mu[0] - px, vy = mu[1] - py, vz = mu[2] - pz;
+  const F px = -((F)c.R[0] * c.t[0] + (F)c.R[3] * c.t[1] + (F)c.R[6] * c.t[2]);
+  const F py = -((F)c.R[1] * c.t[0] + (F)c.R[4] * c.t[1] + (F)c.R[7] * c.t[2]);
+  const F pz = -((F)c.R[2] * c.t[0] + (F)c.R[5] * c.t[1] + (F)c.R[8] * c.t[2]);
+  const F vx = mu[0] - px, vy = mu[1] - py, vz = mu[2] - pz;
   *vn = sqrt(vx * vx + vy * vy + vz * vz);
-  const double inv = 1.0 / *vn;
+  const F inv = F(1.0) / *vn;
   dir[0] = vx * inv; dir[1] = vy * inv; dir[2] = vz * inv;
 }
 
@@ -192,8 +197,8 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   const float o = opac[i];
   if (!(zf > op.z_near) || !(fabsf(o) >= op.alpha_min)) return;
 
-  Geo g;
-  geometry(c, op, mu, scales + 3 * i, quats + 4 * i, g);
+  Geo<double> g;
+  geometry<double>(c, op, mu, scales + 3 * i, quats + 4 * i, g);
   if (!(g.qn > 0.0) || !(g.det > 0.0)) return;
 
   const double mx = c.fx * g.xz + c.cx, my = c.fy * g.yz + c.cy;
@@ -214,9 +219,9 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   }
 
   double dir[3], vn;
-  view_dir(c, mu, dir, &vn);
+  view_dir<double>(c, mu, dir, &vn);
   double Y[16];
-  sh_basis(deg, dir[0], dir[1], dir[2], Y);
+  sh_basis<double>(deg, dir[0], dir[1], dir[2], Y);
   const int K = (deg + 1) * (deg + 1);
   const float* shi = sh + (size_t)i * K * 3;
   double col[3] = {0.5, 0.5, 0.5};
@@ -255,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     const float* __restrict__ sh, const uint32_t* __restrict__ touched, const float* __restrict__ g2,
     float* __restrict__ d_means, float* __restrict__ d_scales, float* __restrict__ d_quats,
     float* __restrict__ d_nu, float* __restrict__ d_opac, float* __restrict__ d_sh, int overwrite) {
+  using F = float;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const float* mu = means + 3 * i;
@@ -262,8 +268,8 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
   const int K = (deg + 1) * (deg + 1);
   if (overwrite && d_sh)
     for (int k = 0; k < 3 * K; ++k) d_sh[(size_t)i * K * 3 + k] = 0.0f;
-  double gmu[3] = {0.0, 0.0, 0.0}, gs[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
-  double gnu = 0.0, gop = 0.0;
+  F gmu[3] = {F(0.0), F(0.0), F(0.0)}, gs[3] = {F(0.0), F(0.0), F(0.0)}, gq[4] = {F(0.0), F(0.0), F(0.0), F(0.0)};
+  F gnu = F(0.0), gop = F(0.0);
   bool any = false;
   for (int v = 0; v < cb.n_views; ++v) {
     const int64_t e = (int64_t)v * n + i;
@@ -273,121 +279,120 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     const float4 ga4 = *reinterpret_cast<const float4*>(g2 + e * kG2);
     const float4 gb4 = *reinterpret_cast<const float4*>(g2 + e * kG2 + 4);
     const float2 gc2 = *reinterpret_cast<const float2*>(g2 + e * kG2 + 8);
-    const double gmx = ga4.x, gmy = ga4.y, gqa = ga4.z, gqb = ga4.w;
-    const double gqc = gb4.x, gcr = gb4.y, gcg = gb4.z, gcb = gb4.w;
+    const F gmx = ga4.x, gmy = ga4.y, gqa = ga4.z, gqb = ga4.w;
+    const F gqc = gb4.x, gcr = gb4.y, gcg = gb4.z, gcb = gb4.w;
     gop += gc2.x;
     gnu += gc2.y;
 
-    Geo g;
-    geometry(c, op, mu, s, quats + 4 * i, g);
-    const double A = g.A, B = g.B, D = g.D, det = g.det;
+    Geo<F> g;
+    geometry<F>(c, op, mu, s, quats + 4 * i, g);
+    const F A = g.A, B = g.B, D = g.D, det = g.det;
     // conic (qa, qb, qc) = (D, -B, A) / det -> gradients w.r.t. (A, B, D)
-    const double id = 1.0 / det, id2 = id * id;
-    const double gA = -gqa * D * D * id2 + gqb * B * D * id2 + gqc * (id - A * D * id2);
-    const double gD = gqa * (id - A * D * id2) + gqb * A * B * id2 - gqc * A * A * id2;
-    const double gB = 2.0 * gqa * B * D * id2 - gqb * (id + 2.0 * B * B * id2) + 2.0 * gqc * A * B * id2;
+    const F id = F(1.0) / det, id2 = id * id;
+    const F gA = -gqa * D * D * id2 + gqb * B * D * id2 + gqc * (id - A * D * id2);
+    const F gD = gqa * (id - A * D * id2) + gqb * A * B * id2 - gqc * A * A * id2;
+    const F gB = F(2.0) * gqa * B * D * id2 - gqb * (id + F(2.0) * B * B * id2) + F(2.0) * gqc * A * B * id2;
     // G (symmetric 2x2, off-diagonal shared by B)
-    const double G00 = gA, G01 = 0.5 * gB, G11 = gD;
+    const F G00 = gA, G01 = F(0.5) * gB, G11 = gD;
     // dSigma = M^T G M (3x3 symmetric, stored xx xy xz yy yz zz)
-    const double* M = g.M;
-    double GM[6];  // G M (2x3)
+    const F* M = g.M;
+    F GM[6];  // G M (2x3)
     for (int k = 0; k < 3; ++k) {
       GM[k] = G00 * M[k] + G01 * M[3 + k];
       GM[3 + k] = G01 * M[k] + G11 * M[3 + k];
     }
-    double dS[9];
+    F dS[9];
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) dS[3 * a + b] = M[a] * GM[b] + M[3 + a] * GM[3 + b];
     // dM = 2 G M Sigma
-    const double* S = g.S;
-    const double Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
-    double dM[6];
+    const F* S = g.S;
+    const F Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+    F dM[6];
     for (int r = 0; r < 2; ++r)
       for (int b = 0; b < 3; ++b)
-        dM[3 * r + b] = 2.0 * (GM[3 * r] * Sf[b] + GM[3 * r + 1] * Sf[3 + b] + GM[3 * r + 2] * Sf[6 + b]);
+        dM[3 * r + b] = F(2.0) * (GM[3 * r] * Sf[b] + GM[3 * r + 1] * Sf[3 + b] + GM[3 * r + 2] * Sf[6 + b]);
     // M = J Rview: dJ = dM Rview^T (only J00, J02, J11, J12 are non-zero)
-    const double dJ00 = dM[0] * c.R[0] + dM[1] * c.R[1] + dM[2] * c.R[2];
-    const double dJ02 = dM[0] * c.R[6] + dM[1] * c.R[7] + dM[2] * c.R[8];
-    const double dJ11 = dM[3] * c.R[3] + dM[4] * c.R[4] + dM[5] * c.R[5];
-    const double dJ12 = dM[3] * c.R[6] + dM[4] * c.R[7] + dM[5] * c.R[8];
-    const double iz = 1.0 / g.Z, iz2 = iz * iz;
-    double dX = gmx * c.fx * iz;
-    double dY = gmy * c.fy * iz;
-    double dZ = -(gmx * c.fx * g.X + gmy * c.fy * g.Y) * iz2;
+    const F dJ00 = dM[0] * c.R[0] + dM[1] * c.R[1] + dM[2] * c.R[2];
+    const F dJ02 = dM[0] * c.R[6] + dM[1] * c.R[7] + dM[2] * c.R[8];
+    const F dJ11 = dM[3] * c.R[3] + dM[4] * c.R[4] + dM[5] * c.R[5];
+    const F dJ12 = dM[3] * c.R[6] + dM[4] * c.R[7] + dM[5] * c.R[8];
+    const F iz = F(1.0) / g.Z, iz2 = iz * iz;
+    F dX = gmx * c.fx * iz;
+    F dY = gmy * c.fy * iz;
+    F dZ = -(gmx * c.fx * g.X + gmy * c.fy * g.Y) * iz2;
     dZ += -dJ00 * c.fx * iz2 - dJ11 * c.fy * iz2;
     if (g.clx) {
       dZ += dJ02 * c.fx * g.txz * iz2;
     } else {
       dX += -dJ02 * c.fx * iz2;
-      dZ += 2.0 * dJ02 * c.fx * g.X * iz2 * iz;
+      dZ += F(2.0) * dJ02 * c.fx * g.X * iz2 * iz;
     }
     if (g.cly) {
       dZ += dJ12 * c.fy * g.tyz * iz2;
     } else {
       dY += -dJ12 * c.fy * iz2;
-      dZ += 2.0 * dJ12 * c.fy * g.Y * iz2 * iz;
+      dZ += F(2.0) * dJ12 * c.fy * g.Y * iz2 * iz;
     }
     for (int a = 0; a < 3; ++a) gmu[a] += c.R[a] * dX + c.R[3 + a] * dY + c.R[6 + a] * dZ;
 
     // Sigma = Rq diag(s^2) Rq^T
-    const double* R = g.Rq;
-    const double sq[3] = {(double)s[0] * s[0], (double)s[1] * s[1], (double)s[2] * s[2]};
-    double dR[9];
+    const F* R = g.Rq;
+    const F sq[3] = {(F)s[0] * s[0], (F)s[1] * s[1], (F)s[2] * s[2]};
+    F dR[9];
     for (int r = 0; r < 3; ++r)
       for (int k = 0; k < 3; ++k) {
-        const double t = dS[3 * r] * R[k] + dS[3 * r + 1] * R[3 + k] + dS[3 * r + 2] * R[6 + k];
-        dR[3 * r + k] = 2.0 * t * sq[k];
-        if (r == 0) (void)0;
+        const F t = dS[3 * r] * R[k] + dS[3 * r + 1] * R[3 + k] + dS[3 * r + 2] * R[6 + k];
+        dR[3 * r + k] = F(2.0) * t * sq[k];
       }
     for (int k = 0; k < 3; ++k) {
       // (R^T dS R)_kk
-      double acc = 0.0;
+      F acc = F(0.0);
       for (int r = 0; r < 3; ++r)
         acc += R[3 * r + k] * (dS[3 * r] * R[k] + dS[3 * r + 1] * R[3 + k] + dS[3 * r + 2] * R[6 + k]);
-      gs[k] += 2.0 * (double)s[k] * acc;
+      gs[k] += F(2.0) * (F)s[k] * acc;
     }
-    const double w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
-    double gu[4];
-    gu[0] = -2.0 * z * dR[1] + 2.0 * y * dR[2] + 2.0 * z * dR[3] - 2.0 * x * dR[5] - 2.0 * y * dR[6] + 2.0 * x * dR[7];
-    gu[1] = 2.0 * y * dR[1] + 2.0 * z * dR[2] + 2.0 * y * dR[3] - 4.0 * x * dR[4] - 2.0 * w * dR[5] + 2.0 * z * dR[6] +
-            2.0 * w * dR[7] - 4.0 * x * dR[8];
-    gu[2] = -4.0 * y * dR[0] + 2.0 * x * dR[1] + 2.0 * w * dR[2] + 2.0 * x * dR[3] + 2.0 * z * dR[5] - 2.0 * w * dR[6] +
-            2.0 * z * dR[7] - 4.0 * y * dR[8];
-    gu[3] = -4.0 * z * dR[0] - 2.0 * w * dR[1] + 2.0 * x * dR[2] + 2.0 * w * dR[3] - 4.0 * z * dR[4] + 2.0 * y * dR[5] +
-            2.0 * x * dR[6] + 2.0 * y * dR[7];
-    const double dq = gu[0] * g.q[0] + gu[1] * g.q[1] + gu[2] * g.q[2] + gu[3] * g.q[3];
+    const F w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
+    F gu[4];
+    gu[0] = -F(2.0) * z * dR[1] + F(2.0) * y * dR[2] + F(2.0) * z * dR[3] - F(2.0) * x * dR[5] - F(2.0) * y * dR[6] + F(2.0) * x * dR[7];
+    gu[1] = F(2.0) * y * dR[1] + F(2.0) * z * dR[2] + F(2.0) * y * dR[3] - F(4.0) * x * dR[4] - F(2.0) * w * dR[5] + F(2.0) * z * dR[6] +
+            F(2.0) * w * dR[7] - F(4.0) * x * dR[8];
+    gu[2] = -F(4.0) * y * dR[0] + F(2.0) * x * dR[1] + F(2.0) * w * dR[2] + F(2.0) * x * dR[3] + F(2.0) * z * dR[5] - F(2.0) * w * dR[6] +
+            F(2.0) * z * dR[7] - F(4.0) * y * dR[8];
+    gu[3] = -F(4.0) * z * dR[0] - F(2.0) * w * dR[1] + F(2.0) * x * dR[2] + F(2.0) * w * dR[3] - F(4.0) * z * dR[4] + F(2.0) * y * dR[5] +
+            F(2.0) * x * dR[6] + F(2.0) * y * dR[7];
+    const F dq = gu[0] * g.q[0] + gu[1] * g.q[1] + gu[2] * g.q[2] + gu[3] * g.q[3];
     for (int a = 0; a < 4; ++a) gq[a] += (gu[a] - g.q[a] * dq) / g.qn;
 
     // colour
-    double dir[3], vn;
-    view_dir(c, mu, dir, &vn);
-    double Yb[16];
-    sh_basis(deg, dir[0], dir[1], dir[2], Yb);
+    F dir[3], vn;
+    view_dir<F>(c, mu, dir, &vn);
+    F Yb[16];
+    sh_basis<F>(deg, dir[0], dir[1], dir[2], Yb);
     const float* shi = sh + (size_t)i * K * 3;
     float* dshi = d_sh + (size_t)i * K * 3;
-    const double gcol[3] = {gcr, gcg, gcb};
-    double wsum[16];
-    for (int k = 0; k < K; ++k) wsum[k] = 0.0;
+    const F gcol[3] = {gcr, gcg, gcb};
+    F wsum[16];
+    for (int k = 0; k < K; ++k) wsum[k] = F(0.0);
     for (int ch = 0; ch < 3; ++ch) {
-      double raw = 0.5;
+      F raw = F(0.5);
       for (int k = 0; k < K; ++k) raw += Yb[k] * shi[3 * k + ch];
-      if (!(raw > 0.0)) continue;
+      if (!(raw > F(0.0))) continue;
       for (int k = 0; k < K; ++k) {
         if (d_sh) dshi[3 * k + ch] += (float)(gcol[ch] * Yb[k]);
         wsum[k] += gcol[ch] * shi[3 * k + ch];
       }
     }
-    double gx, gy, gz;
-    sh_basis_grad(deg, dir[0], dir[1], dir[2], wsum, &gx, &gy, &gz);
-    const double dd = gx * dir[0] + gy * dir[1] + gz * dir[2];
-    const double ivn = 1.0 / vn;
+    F gx, gy, gz;
+    sh_basis_grad<F>(deg, dir[0], dir[1], dir[2], wsum, &gx, &gy, &gz);
+    const F dd = gx * dir[0] + gy * dir[1] + gz * dir[2];
+    const F ivn = F(1.0) / vn;
     gmu[0] += (gx - dir[0] * dd) * ivn;
     gmu[1] += (gy - dir[1] * dd) * ivn;
     gmu[2] += (gz - dir[2] * dd) * ivn;
   }
   if (!any && !overwrite) return;
   const float nv = nu[i];
-  if (!(nv >= op.nu_min && nv <= op.nu_max)) gnu = 0.0;
+  if (!(nv >= op.nu_min && nv <= op.nu_max)) gnu = F(0.0);
   if (overwrite) {
     if (d_means) for (int a = 0; a < 3; ++a) d_means[3 * i + a] = (float)gmu[a];
     if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] = (float)gs[a];

@@ -15,6 +15,8 @@
 // T.  The per-pixel gradients of each record are summed over the wave with
 // DPP row shifts / broadcasts, and lane 63 adds them to the entry's
 // screen-space gradient slot with hardware float atomics.
+#include <stdlib.h>
+
 #include "common.hpp"
 
 namespace sss {
@@ -100,221 +102,290 @@ __device__ __forceinline__ float wave_sum63(float v) {
   return v;
 }
 
+// Pixels of one tile owned by a thread: with PIX pixels per thread the
+// workgroup has 256/PIX threads; thread t owns column t % 16 and the rows
+// t/16 + k*(256/PIX)/16, k < PIX.
+template <int PIX>
 struct TileCtx {
-  int view, tx, ty, x, y;
-  bool inside;
-  float px, py;
-  double ox, oy;
-  int64_t pix;
+  int view;
   uint32_t start, end;
+  double ox, oy;
+  float px;
+  float py[PIX];
+  bool inside[PIX];
+  int64_t pix[PIX];
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const CamBatch& cb, const uint32_t* __restrict__ tile_start) {
-  TileCtx t;
+template <int PIX>
+__device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint32_t* __restrict__ tile_start) {
+  constexpr int kThreads = kBlock / PIX;
+  constexpr int kRowStep = kThreads / kTile;
+  TileCtx<PIX> t;
   const int g = blockIdx.x;
   int v = 0;
   for (int k = 1; k < cb.n_views; ++k)
     if (g >= cb.v[k].tile_offset) v = k;
   const CamDev& c = cb.v[v];
   const int lt = g - c.tile_offset;
+  const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
   t.view = v;
-  t.tx = lt % c.tiles_x;
-  t.ty = lt / c.tiles_x;
-  const int lx = threadIdx.x & (kTile - 1), ly = threadIdx.x / kTile;
-  t.x = t.tx * kTile + lx;
-  t.y = t.ty * kTile + ly;
-  t.inside = t.x < c.W && t.y < c.H;
+  const int lx = threadIdx.x & (kTile - 1), ly0 = threadIdx.x / kTile;
+  const int x = tx * kTile + lx;
   t.px = (float)lx + 0.5f;
-  t.py = (float)ly + 0.5f;
-  t.ox = (double)(t.tx * kTile);
-  t.oy = (double)(t.ty * kTile);
-  t.pix = c.pix_offset + (int64_t)t.y * c.W + t.x;
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    const int ly = ly0 + k * kRowStep;
+    const int y = ty * kTile + ly;
+    t.py[k] = (float)ly + 0.5f;
+    t.inside[k] = x < c.W && y < c.H;
+    t.pix[k] = c.pix_offset + (int64_t)y * c.W + x;
+  }
+  t.ox = (double)(tx * kTile);
+  t.oy = (double)(ty * kTile);
   t.start = tile_start[g];
   t.end = tile_start[g + 1];
   return t;
 }
 
+// A batch is one staged record per thread.
+template <int PIX>
+__device__ __forceinline__ void stage_batch(const TileCtx<PIX>& t, const Rec* __restrict__ srec,
+                                            const uint32_t* __restrict__ pair_rank, uint32_t base, uint32_t stop,
+                                            LRec* lds) {
+  const uint32_t k = base + threadIdx.x;
+  if (k < stop) stage(srec, pair_rank[k], t.ox, t.oy, lds + threadIdx.x);
+}
+
 // Forward traversal of the tile list; identical in render_fwd and in the
 // recompute phase of render_bwd.
-__device__ __forceinline__ void forward_walk(const TileCtx& t, const OptsDev& op, const Rec* __restrict__ srec,
-                                             const uint32_t* __restrict__ pair_rank, LRec* lds, float* C,
+template <int PIX>
+__device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDev& op, const Rec* __restrict__ srec,
+                                             const uint32_t* __restrict__ pair_rank, LRec* lds, float (*C)[3],
                                              float* Tout, uint32_t* last_out) {
-  bool done = !t.inside;
-  float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-  uint32_t last = 0;
-  for (uint32_t base = t.start; base < t.end; base += kBlock) {
-    if (__syncthreads_count(done) == kBlock) break;
-    const uint32_t k = base + threadIdx.x;
-    if (k < t.end) stage(srec, pair_rank[k], t.ox, t.oy, lds + threadIdx.x);
+  bool done[PIX];
+  float T[PIX], c0[PIX], c1[PIX], c2[PIX];
+  uint32_t last[PIX];
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    done[k] = !t.inside[k];
+    T[k] = 1.0f; c0[k] = 0.0f; c1[k] = 0.0f; c2[k] = 0.0f;
+    last[k] = 0;
+  }
+  constexpr uint32_t kBatch = kBlock / PIX;
+  for (uint32_t base = t.start; base < t.end; base += kBatch) {
+    bool alive = false;
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) alive |= !done[k];
+    if (__syncthreads_count(alive) == 0) break;
+    stage_batch<PIX>(t, srec, pair_rank, base, t.end, lds);
     __syncthreads();
-    const int cnt = (int)min((uint32_t)kBlock, t.end - base);
-    if (!done) {
-      for (int j = 0; j < cnt; ++j) {
-        const LRec L = lds[j];
+    const int cnt = (int)min(kBatch, t.end - base);
+    for (int j = 0; j < cnt && alive; ++j) {
+      const LRec L = lds[j];
+      alive = false;
+#pragma unroll
+      for (int k = 0; k < PIX; ++k) {
+        if (done[k]) continue;
         Eval E;
-        evaluate(t.px, t.py, L, op.alpha_min, op.alpha_max, E);
-        if (!E.hit) continue;
-        const float Tn = T * (1.0f - E.alpha);
-        if (Tn < op.t_min) {
-          done = true;
-          break;
+        evaluate(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
+        if (E.hit) {
+          const float Tn = T[k] * (1.0f - E.alpha);
+          if (Tn < op.t_min) {
+            done[k] = true;
+          } else {
+            const float wgt = E.alpha * T[k];
+            c0[k] = __fmaf_rn(L.cr, wgt, c0[k]);
+            c1[k] = __fmaf_rn(L.cg, wgt, c1[k]);
+            c2[k] = __fmaf_rn(L.cb, wgt, c2[k]);
+            T[k] = Tn;
+            last[k] = base - t.start + (uint32_t)j + 1u;
+          }
         }
-        const float wgt = E.alpha * T;
-        c0 = __fmaf_rn(L.cr, wgt, c0);
-        c1 = __fmaf_rn(L.cg, wgt, c1);
-        c2 = __fmaf_rn(L.cb, wgt, c2);
-        T = Tn;
-        last = base - t.start + (uint32_t)j + 1u;
+        alive |= !done[k];
       }
     }
   }
-  C[0] = __fmaf_rn(T, op.bg[0], c0);
-  C[1] = __fmaf_rn(T, op.bg[1], c1);
-  C[2] = __fmaf_rn(T, op.bg[2], c2);
-  *Tout = T;
-  *last_out = last;
-}
-
-__global__ __launch_bounds__(kBlock) void render_fwd_kernel(CamBatch cb, OptsDev op, const Rec* __restrict__ srec,
-                                                            const uint32_t* __restrict__ tile_start,
-                                                            const uint32_t* __restrict__ pair_rank,
-                                                            float* __restrict__ image, float* __restrict__ t_final,
-                                                            uint32_t* __restrict__ n_contrib) {
-  __shared__ LRec lds[kBlock];
-  const TileCtx t = tile_ctx(cb, tile_start);
-  float C[3], T;
-  uint32_t last;
-  forward_walk(t, op, srec, pair_rank, lds, C, &T, &last);
-  if (t.inside) {
-    image[3 * t.pix + 0] = C[0];
-    image[3 * t.pix + 1] = C[1];
-    image[3 * t.pix + 2] = C[2];
-    if (t_final) t_final[t.pix] = T;
-    if (n_contrib) n_contrib[t.pix] = last;
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    C[k][0] = __fmaf_rn(T[k], op.bg[0], c0[k]);
+    C[k][1] = __fmaf_rn(T[k], op.bg[1], c1[k]);
+    C[k][2] = __fmaf_rn(T[k], op.bg[2], c2[k]);
+    Tout[k] = T[k];
+    last_out[k] = last[k];
   }
 }
 
-template <int kMode, int kLoss>
-__global__ __launch_bounds__(kBlock) void render_bwd_kernel(CamBatch cb, OptsDev op, const Rec* __restrict__ srec,
-                                                            const uint32_t* __restrict__ tile_start,
-                                                            const uint32_t* __restrict__ pair_rank,
-                                                            const float* __restrict__ dl_or_target,
-                                                            const float* __restrict__ image,
-                                                            const uint32_t* __restrict__ n_contrib,
-                                                            float* __restrict__ image_out, float* __restrict__ loss_out,
-                                                            float inv_count, float* __restrict__ g2) {
-  __shared__ LRec lds[kBlock];
+template <int PIX>
+__global__ __launch_bounds__(kBlock / PIX) void render_fwd_kernel(CamBatch cb, OptsDev op,
+                                                                  const Rec* __restrict__ srec,
+                                                                  const uint32_t* __restrict__ tile_start,
+                                                                  const uint32_t* __restrict__ pair_rank,
+                                                                  float* __restrict__ image,
+                                                                  float* __restrict__ t_final,
+                                                                  uint32_t* __restrict__ n_contrib) {
+  __shared__ LRec lds[kBlock / PIX];
+  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start);
+  float C[PIX][3], T[PIX];
+  uint32_t last[PIX];
+  forward_walk<PIX>(t, op, srec, pair_rank, lds, C, T, last);
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    if (!t.inside[k]) continue;
+    const int64_t p = t.pix[k];
+    image[3 * p + 0] = C[k][0];
+    image[3 * p + 1] = C[k][1];
+    image[3 * p + 2] = C[k][2];
+    if (t_final) t_final[p] = T[k];
+    if (n_contrib) n_contrib[p] = last[k];
+  }
+}
+
+template <int PIX, int kMode, int kLoss>
+__global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
+    CamBatch cb, OptsDev op, const Rec* __restrict__ srec, const uint32_t* __restrict__ tile_start,
+    const uint32_t* __restrict__ pair_rank, const float* __restrict__ dl_or_target, const float* __restrict__ image,
+    const uint32_t* __restrict__ n_contrib, float* __restrict__ image_out, float* __restrict__ loss_out,
+    float inv_count, float* __restrict__ g2) {
+  constexpr int kWaves = kBlock / PIX / 64;
+  constexpr uint32_t kBatch = kBlock / PIX;
+  __shared__ LRec lds[kBatch];
   __shared__ uint32_t s_max;
-  __shared__ float s_loss[kBlock / 64];
-  const TileCtx t = tile_ctx(cb, tile_start);
+  __shared__ float s_loss[kWaves];
+  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start);
   const int lane = threadIdx.x & 63;
 
   // ---- per-pixel forward output and loss gradient ----
-  float out[3] = {0.0f, 0.0f, 0.0f};
-  uint32_t bound = 0;
+  float out[PIX][3];
+  uint32_t bound[PIX];
   if (kMode == SSS_BWD_RECOMPUTE) {
-    float T;
-    forward_walk(t, op, srec, pair_rank, lds, out, &T, &bound);
-    if (image_out && t.inside) {
-      image_out[3 * t.pix + 0] = out[0];
-      image_out[3 * t.pix + 1] = out[1];
-      image_out[3 * t.pix + 2] = out[2];
-    }
-    if (!t.inside) bound = 0;
-  } else if (t.inside) {
-    out[0] = image[3 * t.pix + 0];
-    out[1] = image[3 * t.pix + 1];
-    out[2] = image[3 * t.pix + 2];
-    bound = n_contrib[t.pix];
-  }
-  float g[3] = {0.0f, 0.0f, 0.0f};
-  float l1 = 0.0f;
-  if (t.inside) {
-    if (kLoss == SSS_LOSS_L1) {
-      for (int ch = 0; ch < 3; ++ch) {
-        const float d = out[ch] - dl_or_target[3 * t.pix + ch];
-        g[ch] = d > 0.0f ? inv_count : (d < 0.0f ? -inv_count : 0.0f);
-        l1 += fabsf(d);
+    float T[PIX];
+    forward_walk<PIX>(t, op, srec, pair_rank, lds, out, T, bound);
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) {
+      if (!t.inside[k]) {
+        bound[k] = 0;
+        continue;
       }
-    } else {
-      g[0] = dl_or_target[3 * t.pix + 0];
-      g[1] = dl_or_target[3 * t.pix + 1];
-      g[2] = dl_or_target[3 * t.pix + 2];
+      if (image_out) {
+        image_out[3 * t.pix[k] + 0] = out[k][0];
+        image_out[3 * t.pix[k] + 1] = out[k][1];
+        image_out[3 * t.pix[k] + 2] = out[k][2];
+      }
     }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) {
+      out[k][0] = out[k][1] = out[k][2] = 0.0f;
+      bound[k] = 0;
+      if (!t.inside[k]) continue;
+      out[k][0] = image[3 * t.pix[k] + 0];
+      out[k][1] = image[3 * t.pix[k] + 1];
+      out[k][2] = image[3 * t.pix[k] + 2];
+      bound[k] = n_contrib[t.pix[k]];
+    }
+  }
+  float g[PIX][3], gout[PIX];
+  float l1 = 0.0f;
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    g[k][0] = g[k][1] = g[k][2] = 0.0f;
+    if (t.inside[k]) {
+      if (kLoss == SSS_LOSS_L1) {
+        for (int ch = 0; ch < 3; ++ch) {
+          const float d = out[k][ch] - dl_or_target[3 * t.pix[k] + ch];
+          g[k][ch] = d > 0.0f ? inv_count : (d < 0.0f ? -inv_count : 0.0f);
+          l1 += fabsf(d);
+        }
+      } else {
+        g[k][0] = dl_or_target[3 * t.pix[k] + 0];
+        g[k][1] = dl_or_target[3 * t.pix[k] + 1];
+        g[k][2] = dl_or_target[3 * t.pix[k] + 2];
+      }
+    }
+    gout[k] = g[k][0] * out[k][0] + g[k][1] * out[k][1] + g[k][2] * out[k][2];
   }
   if (kLoss == SSS_LOSS_L1 && loss_out) {
     // |out - target| summed over the workgroup, one atomic per tile
     l1 = wave_sum63(l1);
     if (lane == 63) s_loss[threadIdx.x >> 6] = l1;
   }
-  const float gout = g[0] * out[0] + g[1] * out[1] + g[2] * out[2];
 
+  uint32_t mb = 0;
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) mb = max(mb, bound[k]);
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
-  atomicMax(&s_max, bound);
+  atomicMax(&s_max, mb);
   __syncthreads();
   const uint32_t stop = min(t.start + s_max, t.end);
-  if (kLoss == SSS_LOSS_L1 && loss_out && threadIdx.x == 0)
-    atomicAdd(loss_out, (s_loss[0] + s_loss[1] + s_loss[2] + s_loss[3]) * inv_count);
+  if (kLoss == SSS_LOSS_L1 && loss_out && threadIdx.x == 0) {
+    float l = 0.0f;
+    for (int w = 0; w < kWaves; ++w) l += s_loss[w];
+    atomicAdd(loss_out, l * inv_count);
+  }
 
   // ---- front-to-back gradient walk ----
-  float T = 1.0f, gA = 0.0f;
-  for (uint32_t base = t.start; base < stop; base += kBlock) {
+  float T[PIX], gA[PIX];
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    T[k] = 1.0f;
+    gA[k] = 0.0f;
+  }
+  for (uint32_t base = t.start; base < stop; base += kBatch) {
     __syncthreads();
-    const uint32_t k = base + threadIdx.x;
-    if (k < stop) stage(srec, pair_rank[k], t.ox, t.oy, lds + threadIdx.x);
+    stage_batch<PIX>(t, srec, pair_rank, base, stop, lds);
     __syncthreads();
-    const int cnt = (int)min((uint32_t)kBlock, stop - base);
+    const int cnt = (int)min(kBatch, stop - base);
     for (int j = 0; j < cnt; ++j) {
       const uint32_t pos = base - t.start + (uint32_t)j;
       const LRec L = lds[j];
       float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f;
       float v5 = 0.0f, v6 = 0.0f, v7 = 0.0f, v8 = 0.0f, v9 = 0.0f;
       bool hit = false;
-      if (pos < bound) {
+#pragma unroll
+      for (int k = 0; k < PIX; ++k) {
+        if (pos >= bound[k]) continue;
         Eval E;
-        evaluate(t.px, t.py, L, op.alpha_min, op.alpha_max, E);
-        if (E.hit) {
-          hit = true;
-          const float a = E.alpha;
-          const float Tn = T * (1.0f - a);
-          const float w = a * T;
-          const float gc = __fmaf_rn(g[2], L.cb, __fmaf_rn(g[1], L.cg, g[0] * L.cr));
-          gA = __fmaf_rn(w, gc, gA);
-          const float gR = gout - gA;
-          const float da = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), T * gc);
-          v5 = g[0] * w;
-          v6 = g[1] * w;
-          v7 = g[2] * w;
-          if (!E.clamped) {
-            v8 = da * E.t2;
-            const float dt2 = da * L.o;
-            const float ru = __builtin_amdgcn_rcpf(E.u);
-            const float dh = dt2 * E.t2 * L.nb * L.inv_nu * ru;
-            v0 = dh * E.ax;
-            v1 = dh * E.ay;
-            const float tq = dh * E.dx;
-            v2 = tq * E.dx;
-            v3 = tq * E.dy;
-            v4 = dh * E.dy * E.dy;
-            // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]
-            const float y = E.y;
-            float q;
-            if (y < 0.1f) {
-              float s = __fmaf_rn(y, 6.0f / 7.0f, -5.0f / 6.0f);
-              s = __fmaf_rn(y, s, 4.0f / 5.0f);
-              s = __fmaf_rn(y, s, -3.0f / 4.0f);
-              s = __fmaf_rn(y, s, 2.0f / 3.0f);
-              s = __fmaf_rn(y, s, -0.5f);
-              q = y * y * s;
-            } else {
-              q = __fmaf_rn(y, ru, -E.l2 * kLn2);
-            }
-            const float dtn = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
-            v9 = dt2 * dtn;
-          }
-          T = Tn;
+        evaluate(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
+        if (!E.hit) continue;
+        hit = true;
+        const float a = E.alpha;
+        const float Tk = T[k];
+        const float w = a * Tk;
+        const float gc = __fmaf_rn(g[k][2], L.cb, __fmaf_rn(g[k][1], L.cg, g[k][0] * L.cr));
+        gA[k] = __fmaf_rn(w, gc, gA[k]);
+        const float gR = gout[k] - gA[k];
+        const float da = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), Tk * gc);
+        v5 = __fmaf_rn(g[k][0], w, v5);
+        v6 = __fmaf_rn(g[k][1], w, v6);
+        v7 = __fmaf_rn(g[k][2], w, v7);
+        T[k] = Tk * (1.0f - a);
+        if (E.clamped) continue;
+        v8 = __fmaf_rn(da, E.t2, v8);
+        const float dt2 = da * L.o;
+        const float ru = __builtin_amdgcn_rcpf(E.u);
+        const float dh = dt2 * E.t2 * L.nb * L.inv_nu * ru;
+        v0 = __fmaf_rn(dh, E.ax, v0);
+        v1 = __fmaf_rn(dh, E.ay, v1);
+        const float tq = dh * E.dx;
+        v2 = __fmaf_rn(tq, E.dx, v2);
+        v3 = __fmaf_rn(tq, E.dy, v3);
+        v4 = __fmaf_rn(dh * E.dy, E.dy, v4);
+        // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]
+        const float y = E.y;
+        float q;
+        if (y < 0.1f) {
+          float s = __fmaf_rn(y, 6.0f / 7.0f, -5.0f / 6.0f);
+          s = __fmaf_rn(y, s, 4.0f / 5.0f);
+          s = __fmaf_rn(y, s, -3.0f / 4.0f);
+          s = __fmaf_rn(y, s, 2.0f / 3.0f);
+          s = __fmaf_rn(y, s, -0.5f);
+          q = y * y * s;
+        } else {
+          q = __fmaf_rn(y, ru, -E.l2 * kLn2);
         }
+        const float dtn = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
+        v9 = __fmaf_rn(dt2, dtn, v9);
       }
       if (__any(hit)) {
         v0 = wave_sum63(v0); v1 = wave_sum63(v1); v2 = wave_sum63(v2); v3 = wave_sum63(v3);
@@ -353,28 +424,47 @@ void launch_zero(float* p, int64_t count, hipStream_t st) {
                      (float4*)p, n4);
 }
 
+int env_pix(const char* name, int dflt) {
+  const char* e = getenv(name);
+  const int v = e ? atoi(e) : dflt;
+  return (v == 1 || v == 2 || v == 4) ? v : dflt;
+}
+
 void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, float* image, float* t_final,
                        uint32_t* n_contrib, hipStream_t st) {
-  SSS_LAUNCH("render_fwd", render_fwd_kernel, dim3((unsigned)cb.total_tiles), dim3(kBlock), 0, st, cb, op,
-                     (const Rec*)b.sorted_records, (const uint32_t*)b.tile_start, (const uint32_t*)b.pair_rank,
-                     image, t_final, n_contrib);
+  static const int pix = env_pix("SSS_PIX_FWD", 2);
+  const dim3 grid((unsigned)cb.total_tiles);
+  const Rec* sr = (const Rec*)b.sorted_records;
+#define SSS_FWD(P)                                                                                          \
+  SSS_LAUNCH("render_fwd", render_fwd_kernel<P>, grid, dim3(kBlock / P), 0, st, cb, op, sr,                \
+             (const uint32_t*)b.tile_start, (const uint32_t*)b.pair_rank, image, t_final, n_contrib)
+  if (pix == 1) SSS_FWD(1);
+  else if (pix == 2) SSS_FWD(2);
+  else SSS_FWD(4);
+#undef SSS_FWD
 }
 
 void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, int mode, int loss,
                        const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
                        float* loss_out, float* g2, int64_t total_pixels, hipStream_t st) {
+  static const int pix = env_pix("SSS_PIX_BWD", 4);
   const float inv_count = 1.0f / (3.0f * (float)total_pixels);
-  const dim3 grid((unsigned)cb.total_tiles), blk(kBlock);
+  const dim3 grid((unsigned)cb.total_tiles);
   const Rec* sr = (const Rec*)b.sorted_records;
   const uint32_t* ts = b.tile_start;
   const uint32_t* pr = b.pair_rank;
-#define SSS_BWD(M, L)                                                                                        \
-  SSS_LAUNCH("render_bwd", (render_bwd_kernel<M, L>), grid, blk, 0, st, cb, op, sr, ts, pr, dl_or_target, image,  \
-                     n_contrib, image_out, loss_out, inv_count, g2)
-  if (mode == SSS_BWD_STORED && loss == SSS_LOSS_GRAD) SSS_BWD(SSS_BWD_STORED, SSS_LOSS_GRAD);
-  else if (mode == SSS_BWD_STORED) SSS_BWD(SSS_BWD_STORED, SSS_LOSS_L1);
-  else if (loss == SSS_LOSS_GRAD) SSS_BWD(SSS_BWD_RECOMPUTE, SSS_LOSS_GRAD);
-  else SSS_BWD(SSS_BWD_RECOMPUTE, SSS_LOSS_L1);
+#define SSS_BWD(P, M, L)                                                                                    \
+  SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L>), grid, dim3(kBlock / P), 0, st, cb, op, sr, ts, pr, \
+             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2)
+#define SSS_BWD_P(M, L)              \
+  if (pix == 1) SSS_BWD(1, M, L);    \
+  else if (pix == 2) SSS_BWD(2, M, L); \
+  else SSS_BWD(4, M, L)
+  if (mode == SSS_BWD_STORED && loss == SSS_LOSS_GRAD) { SSS_BWD_P(SSS_BWD_STORED, SSS_LOSS_GRAD); }
+  else if (mode == SSS_BWD_STORED) { SSS_BWD_P(SSS_BWD_STORED, SSS_LOSS_L1); }
+  else if (loss == SSS_LOSS_GRAD) { SSS_BWD_P(SSS_BWD_RECOMPUTE, SSS_LOSS_GRAD); }
+  else { SSS_BWD_P(SSS_BWD_RECOMPUTE, SSS_LOSS_L1); }
+#undef SSS_BWD_P
 #undef SSS_BWD
 }
 

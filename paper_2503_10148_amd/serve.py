@@ -1,0 +1,256 @@
+"""Continuous-batching render server for a resident scene.
+
+Requests (a camera of any size) arrive at any time.  A scheduler thread
+admits queued requests into a batch while the batch has fewer than
+`max_batch` views and the estimated device memory of everything in flight
+stays within `mem_budget`; it launches the batch as ONE sss_project +
+sss_bin_sort + sss_render_fwd sequence over all its views, on the next of
+`n_streams` streams, and goes on admitting: the next batch's projection and
+sort run on another stream while the previous batch still rasterizes.  A
+completion thread waits for each batch's event, hands every request its
+image (a [H, W, 3] device tensor) and releases the batch's memory, which lets
+the scheduler admit more.
+
+Each view is rendered independently inside a batch (its own tiles, ranks
+ordered by depth within the view), so a request's image is bit-identical
+alone and in any mix.
+
+`PlainRenderer` is the baseline: one request per launch sequence, FIFO, one
+stream, same kernels.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import threading
+import time
+from concurrent.futures import Future
+
+import torch
+
+from . import sss
+
+_REC = sss.RECORD_BYTES
+
+
+class _Req:
+    __slots__ = ("cam", "t_submit", "future", "pixels", "t_done")
+
+    def __init__(self, cam):
+        self.cam = cam
+        self.t_submit = time.perf_counter()
+        self.future = Future()
+        self.future.request = self
+        self.pixels = int(cam["width"]) * int(cam["height"])
+        self.t_done = None
+
+
+class RenderServer:
+    def __init__(self, scene: dict, opts=None, max_batch: int = 16, mem_budget: int = 6 << 30,
+                 n_streams: int = 2, pairs_per_pixel: float = 20.0, device: int = 0):
+        """scene: dict of device tensors (see sss.scene_struct)."""
+        if not 1 <= max_batch <= sss.MAX_VIEWS:
+            raise ValueError(f"max_batch must be in 1..{sss.MAX_VIEWS}")
+        self.scene = scene
+        self.n = scene["means"].shape[0]
+        self.opts = opts
+        self.max_batch = max_batch
+        self.mem_budget = int(mem_budget)
+        self.device = device
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self.pairs_per_pixel = float(pairs_per_pixel)   # running estimate, refined from every batch
+        self._q = collections.deque()
+        self._cv = threading.Condition()
+        self._inflight = collections.deque()           # (event, reqs, bytes, keepalive)
+        self._mem_used = 0
+        self._launching = 0                            # batches popped but not yet in flight
+        self._running = True
+        self.batches = 0
+        self.batch_sizes = []
+        self._sched = threading.Thread(target=self._schedule, name="sss-sched", daemon=True)
+        self._done = threading.Thread(target=self._complete, name="sss-done", daemon=True)
+        self._sched.start()
+        self._done.start()
+
+    # ---------------------------------------------------------------- public
+    def submit(self, cam) -> Future:
+        r = _Req(cam)
+        if self._estimate([r]) > self.mem_budget:
+            r.future.set_exception(MemoryError(f"request of {r.pixels} pixels exceeds the memory budget"))
+            return r.future
+        with self._cv:
+            if not self._running:
+                raise RuntimeError("server closed")
+            self._q.append(r)
+            self._cv.notify_all()
+        return r.future
+
+    def close(self):
+        with self._cv:
+            self._running = False
+            self._cv.notify_all()
+        self._sched.join()
+        self._done.join()
+
+    # ------------------------------------------------------------- internals
+    def _estimate(self, reqs) -> int:
+        """Device bytes of one batch: per-view projection + bins, per-pixel
+        outputs, and the pair list + sort buffers from the pair estimate."""
+        V = len(reqs)
+        P = sum(r.pixels for r in reqs)
+        E = V * self.n
+        M = int(P * self.pairs_per_pixel * 1.25) + 1024
+        per_entry = _REC + 4 + 8 + 4 + 4 + _REC
+        ws = int(sss.lib().sss_bin_sort_workspace(E, M))
+        return E * per_entry + P * (12 + 4 + 4) + 4 * M + ws
+
+    def _schedule(self):
+        torch.cuda.set_device(self.device)
+        k = 0
+        while True:
+            with self._cv:
+                while self._running and not self._q:
+                    self._cv.wait()
+                if not self._running and not self._q:
+                    return
+                batch = []
+                while self._q and len(batch) < self.max_batch:
+                    cand = batch + [self._q[0]]
+                    need = self._estimate(cand)
+                    if self._mem_used + need > self.mem_budget and (batch or self._inflight):
+                        break
+                    batch.append(self._q.popleft())
+                if not batch:                                   # memory full: wait for a completion
+                    self._cv.wait(timeout=0.05)
+                    continue
+                need = self._estimate(batch)
+                self._mem_used += need
+                self._launching += 1
+            stream = self.streams[k % len(self.streams)]
+            k += 1
+            try:
+                keep, ev = self._launch(batch, stream)
+            except Exception as exc:                            # pragma: no cover - surfaced to callers
+                for r in batch:
+                    r.future.set_exception(exc)
+                with self._cv:
+                    self._mem_used -= need
+                    self._launching -= 1
+                    self._cv.notify_all()
+                continue
+            with self._cv:
+                self._inflight.append((ev, batch, need, keep))
+                self._launching -= 1
+                self.batches += 1
+                self.batch_sizes.append(len(batch))
+                self._cv.notify_all()
+
+    def _launch(self, batch, stream):
+        cams = [r.cam for r in batch]
+        with torch.cuda.stream(stream):
+            proj = sss.project(self.scene, cams, self.opts, stream=stream)
+            P = sum(r.pixels for r in batch)
+            binner = sss.BinSorter(int(P * self.pairs_per_pixel * 1.25) + 1024)
+            bins = binner(proj, cams, self.n, stream=stream)
+            image, _, _ = sss.render_fwd(bins, cams, self.opts, stream=stream)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        if P > 0:
+            self.pairs_per_pixel = 0.8 * self.pairs_per_pixel + 0.2 * bins.n_pairs / P
+        return (proj, bins, binner, image), ev
+
+    def _complete(self):
+        torch.cuda.set_device(self.device)
+        while True:
+            with self._cv:
+                while not self._inflight:
+                    if not self._running and not self._q and self._launching == 0:
+                        return
+                    self._cv.wait(timeout=0.05)
+                ev, batch, need, keep = self._inflight[0]
+            ev.synchronize()
+            t = time.perf_counter()
+            image = keep[3]
+            off = 0
+            for r in batch:
+                H, W = int(r.cam["height"]), int(r.cam["width"])
+                r.t_done = t
+                r.future.set_result(image[off:off + r.pixels].view(H, W, 3))
+                off += r.pixels
+            with self._cv:
+                self._inflight.popleft()
+                self._mem_used -= need
+                self._cv.notify_all()
+
+
+class PlainRenderer:
+    """One request per launch sequence, FIFO, one stream."""
+
+    def __init__(self, scene: dict, opts=None):
+        self.scene = scene
+        self.n = scene["means"].shape[0]
+        self.opts = opts
+        self.binner = sss.BinSorter(0)
+
+    def render(self, cam):
+        cams = [cam]
+        proj = sss.project(self.scene, cams, self.opts)
+        bins = self.binner(proj, cams, self.n)
+        image, _, _ = sss.render_fwd(bins, cams, self.opts)
+        torch.cuda.current_stream().synchronize()
+        return image.view(int(cam["height"]), int(cam["width"]), 3)
+
+
+def poisson_arrivals(rate: float, duration: float, rng):
+    """Arrival times of a Poisson process of `rate` per second over `duration` s."""
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            return out
+        out.append(t)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, **server_kw):
+    """Replay `arrivals` (seconds from start) with the request cameras `cams`
+    against the batched server or the plain renderer.  Latency is measured
+    from the scheduled arrival to the moment the image is ready on the
+    device.  Returns (latencies in s, wall time in s, server stats)."""
+    lat = []
+    t0 = time.perf_counter()
+    stats = {}
+    if server_kind == "batched":
+        srv = RenderServer(scene, opts, **server_kw)
+        futs = []
+        for a, cam in zip(arrivals, cams):
+            now = time.perf_counter() - t0
+            if a > now:
+                time.sleep(a - now)
+            futs.append((t0 + a, srv.submit(cam)))
+        for _, f in futs:
+            f.result()
+        t_end = time.perf_counter()
+        lat = [f.request.t_done - ta for ta, f in futs]
+        srv.close()
+        stats = dict(batches=srv.batches, mean_batch=sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)))
+    elif server_kind == "plain":
+        pr = PlainRenderer(scene, opts)
+        for a, cam in zip(arrivals, cams):
+            now = time.perf_counter() - t0
+            if a > now:
+                time.sleep(a - now)
+            pr.render(cam)
+            lat.append(time.perf_counter() - t0 - a)
+        t_end = time.perf_counter()
+    else:
+        raise ValueError(server_kind)
+    return lat, t_end - t0, stats

@@ -1,0 +1,112 @@
+"""Continuous-batching server: results alone == in the mix, memory admission,
+rejection of oversized requests, parity of a served image with the oracle."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_10148_amd import scenes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_10148_amd import serve, sss
+    scene_np = scenes.make_scene(20000, 3, seed=41, neg_frac=0.25)
+    return serve, sss, scene_np, sss.scene_to_device(scene_np)
+
+
+def _cams(k, seed=0):
+    rng = np.random.default_rng(seed)
+    sizes = [(160, 90), (320, 180), (480, 270), (97, 61)]
+    return [scenes.sphere_camera(rng, *sizes[i % len(sizes)]) for i in range(k)]
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix(env):
+    serve, sss, _, scene = env
+    cams = _cams(12)
+    plain = serve.PlainRenderer(scene)
+    alone = [plain.render(c).cpu().numpy() for c in cams]
+    srv = serve.RenderServer(scene, max_batch=5, mem_budget=2 << 30)
+    futs = [srv.submit(c) for c in cams]                 # arrive together -> batched
+    got = [f.result(timeout=60).cpu().numpy() for f in futs]
+    srv.close()
+    assert srv.batches < len(cams)                       # some requests really shared a launch
+    for a, b in zip(alone, got):
+        assert np.array_equal(a, b)
+
+
+def test_requests_arriving_while_others_run_are_admitted(env):
+    serve, sss, _, scene = env
+    cams = _cams(40, seed=1)
+    srv = serve.RenderServer(scene, max_batch=4, mem_budget=2 << 30)
+    futs = []
+
+    def client():
+        for c in cams:
+            futs.append(srv.submit(c))
+            time.sleep(0.002)
+
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    out = [f.result(timeout=60) for f in futs]
+    srv.close()
+    assert len(out) == len(cams)
+    assert max(srv.batch_sizes) <= 4
+
+
+def test_memory_admission_bounds_inflight_bytes(env):
+    serve, sss, _, scene = env
+    cams = [scenes.sphere_camera(np.random.default_rng(i), 480, 270) for i in range(10)]
+    probe = serve.RenderServer(scene, max_batch=16, mem_budget=8 << 30)
+    one = probe._estimate([serve._Req(cams[0])])
+    probe.close()
+    budget = int(2.5 * one)                             # room for two requests at a time
+    srv = serve.RenderServer(scene, max_batch=16, mem_budget=budget)
+    peak = [0]
+    stop = [False]
+
+    def watch():
+        while not stop[0]:
+            peak[0] = max(peak[0], srv._mem_used)
+            time.sleep(0.0005)
+
+    w = threading.Thread(target=watch)
+    w.start()
+    futs = [srv.submit(c) for c in cams]
+    for f in futs:
+        f.result(timeout=60)
+    stop[0] = True
+    w.join()
+    srv.close()
+    assert peak[0] <= budget
+    assert max(srv.batch_sizes) <= 2
+
+
+def test_oversized_request_is_rejected(env):
+    serve, sss, _, scene = env
+    srv = serve.RenderServer(scene, mem_budget=1 << 20)
+    f = srv.submit(scenes.sphere_camera(np.random.default_rng(0), 640, 360))
+    with pytest.raises(MemoryError):
+        f.result(timeout=10)
+    srv.close()
+
+
+def test_served_image_matches_oracle(env):
+    serve, sss, scene_np, scene = env
+    cams = _cams(3, seed=5)
+    srv = serve.RenderServer(scene, max_batch=3)
+    futs = [srv.submit(c) for c in cams]
+    imgs = [f.result(timeout=60).cpu().numpy() for f in futs]
+    srv.close()
+    for c, img in zip(cams, imgs):
+        ref = oracle.render(scene_np, c)
+        diff = np.abs(img - ref["image"]).max(axis=2)
+        assert not ((diff > 1e-4) & (ref["xflags"] == 0)).any()
