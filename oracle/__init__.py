@@ -54,6 +54,8 @@ def _load():
         _lib.orc_bin.restype = ctypes.c_int64
         _lib.orc_tiles_x.restype = ctypes.c_int
         _lib.orc_tiles_y.restype = ctypes.c_int
+        _lib.orc_lnbeta.restype = ctypes.c_double
+        _lib.orc_lnbeta.argtypes = [ctypes.c_double, ctypes.c_double]
     return _lib
 
 
@@ -309,3 +311,20 @@ def adam_step(param, grad, m, v, lr, b1=0.9, b2=0.999, eps=1e-15, t=1, lo=-np.in
                       ctypes.c_double(b1), ctypes.c_double(b2), ctypes.c_double(eps), ctypes.c_int64(t),
                       ctypes.c_double(lo), ctypes.c_double(hi))
     return param, m, v
+
+
+# --------------------------------------------------------------------------
+# recycling
+# --------------------------------------------------------------------------
+def lnbeta(x, y):
+    return float(_load().orc_lnbeta(x, y))
+
+
+def relocate(o_old, nu_old, nu_new, N):
+    """(o_new, Sigma_new / Sigma_old) for N components at one old component."""
+    lib = _load()
+    o = ctypes.c_double()
+    f = ctypes.c_double()
+    lib.orc_relocate(ctypes.c_double(o_old), ctypes.c_double(nu_old), ctypes.c_double(nu_new), ctypes.c_int(N),
+                     ctypes.byref(o), ctypes.byref(f))
+    return o.value, f.value

@@ -821,3 +821,33 @@ void orc_adam_step(int64_t count, double* param, const double* grad, double* m, 
     param[j] = p;
   }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Recycling (Sec. 3.4 eq. relocation, SM "Component Recycling")              */
+/* ------------------------------------------------------------------------ */
+/* ln beta(x, y) through ln Gamma (SM eq. beta4). */
+double orc_lnbeta(double x, double y) { return lgamma(x) + lgamma(y) - lgamma(x + y); }
+
+/* N components placed at one old component's mean reproduce, in the 1D
+ * integral of the composited opacity, the old component: the new opacity
+ * from (1 - o_new)^N = 1 - |o_old| and the covariance scale factor
+ *   Sigma_new / Sigma_old = o_old^2 (nu_old / nu_new) (beta(1/2, (nu_old+2)/2) / K)^2
+ *   K = sum_{i=1..N} sum_{k=0..i-1} C(i-1, k) (-1)^k o_new^(k+1) beta(1/2, ((k+1)(nu_new+3)-1)/2).
+ * The sign of the new opacity is the sign of o_old. */
+void orc_relocate(double o_old, double nu_old, double nu_new, int N, double* o_new, double* factor) {
+  const double a = fabs(o_old);
+  const double on = 1.0 - pow(1.0 - a, 1.0 / (double)N);
+  double K = 0.0;
+  for (int i = 1; i <= N; ++i) {
+    double binom = 1.0;                                /* C(i-1, k) */
+    for (int k = 0; k <= i - 1; ++k) {
+      const double term = binom * ((k % 2) ? -1.0 : 1.0) * pow(on, (double)(k + 1)) *
+                          exp(orc_lnbeta(0.5, ((k + 1) * (nu_new + 3.0) - 1.0) / 2.0));
+      K += term;
+      binom = binom * (double)(i - 1 - k) / (double)(k + 1);
+    }
+  }
+  const double b_old = exp(orc_lnbeta(0.5, (nu_old + 2.0) / 2.0));
+  *o_new = o_old < 0.0 ? -on : on;
+  *factor = a * a * (nu_old / nu_new) * (b_old / K) * (b_old / K);
+}

@@ -158,13 +158,18 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
 
 // Block b owns items [b*4096, (b+1)*4096); wave w owns the w-th quarter and
 // walks it in 16 rounds of 64 consecutive items, so (wave, round, lane) is
-// item order and ranks computed in that order are stable.
+// item order and ranks computed in that order are stable.  The block is then
+// reordered by digit in LDS and written out digit run by digit run, so
+// consecutive threads store to consecutive addresses.
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift, int bits,
     int64_t nblocks, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ okeys,
     uint32_t* __restrict__ ovals) {
   __shared__ uint32_t cnt[4][256];
   __shared__ uint32_t gbase[256];
+  __shared__ uint32_t dofs[256];
+  __shared__ uint32_t sk[kPerBlock];
+  __shared__ uint32_t sv[kPerBlock];
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
   const uint32_t mask = (1u << bits) - 1u;
@@ -172,7 +177,8 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   gbase[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)w * (kPerBlock / 4);
+  const int64_t block0 = (int64_t)blockIdx.x * kPerBlock;
+  const int64_t base = block0 + (int64_t)w * (kPerBlock / 4);
   uint32_t key[kItems], val[kItems], loc[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
@@ -196,25 +202,33 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // exclusive prefix over waves for each digit
-  {
-    const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid];
-    __syncthreads();
-    cnt[0][tid] = 0;
-    cnt[1][tid] = c0;
-    cnt[2][tid] = c0 + c1;
-    cnt[3][tid] = c0 + c1 + c2;
-  }
+  // per digit: exclusive prefix over waves, and the block-level digit offset
+  const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid], c3 = cnt[3][tid];
+  const uint32_t dstart = block_excl_scan(c0 + c1 + c2 + c3, dofs, nullptr);
+  cnt[0][tid] = dstart;
+  cnt[1][tid] = dstart + c0;
+  cnt[2][tid] = dstart + c0 + c1;
+  cnt[3][tid] = dstart + c0 + c1 + c2;
+  dofs[tid] = dstart;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int64_t j = base + (int64_t)r * 64 + lane;
     if (j < n) {
       const uint32_t d = (key[r] >> shift) & mask;
-      const uint32_t p = gbase[d] + cnt[w][d] + loc[r];
-      okeys[p] = key[r];
-      ovals[p] = val[r];
+      const uint32_t bp = cnt[w][d] + loc[r];
+      sk[bp] = key[r];
+      sv[bp] = val[r];
     }
+  }
+  __syncthreads();
+  const int in_block = (int)min((int64_t)kPerBlock, n - block0);
+  for (int i = tid; i < in_block; i += kBlock) {
+    const uint32_t k = sk[i];
+    const uint32_t d = (k >> shift) & mask;
+    const uint32_t p = gbase[d] + ((uint32_t)i - dofs[d]);
+    okeys[p] = k;
+    ovals[p] = sv[i];
   }
 }
 
@@ -233,47 +247,58 @@ __device__ __forceinline__ uint32_t off_next(const uint32_t* __restrict__ off, i
   return (r + 1 < n_vis ? off[r + 1] : total) - off[r];
 }
 
-__device__ __forceinline__ int tiles_y_of(const CamBatch& cb, int v) {
-  int ty = 1;
-  for (int k = 0; k < cb.n_views; ++k)
-    if (k == v) ty = cb.v[k].tiles_y;
-  return ty;
-}
-
+// One lane per rank gathers that rank's record; the pairs are then written
+// wave-cooperatively: for each of the wave's 64 ranks in turn, the 64 lanes
+// store consecutive pairs of its rectangle (row-major over the rectangle).
+// Exactly tiles_touched pairs are written per rank (the scan reserved that
+// many); a tile outside the view's grid or a slot the rectangle does not
+// fill gets the sentinel key n_tiles, which sorts after every real tile.
 __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, const uint32_t* __restrict__ order,
                                                       const ushort4* __restrict__ rects,
                                                       const uint32_t* __restrict__ off, int64_t n_vis, uint32_t total,
                                                       const uint4* __restrict__ rec_in, uint4* __restrict__ rec_out,
                                                       uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (r >= n_vis) return;
-  const uint32_t e = order[r];
-  // gather the record into rank order
-  const uint4* src = rec_in + (size_t)e * 4;
-  uint4* dst = rec_out + (size_t)r * 4;
-  const uint4 a = src[0], b = src[1], c = src[2], d = src[3];
-  dst[0] = a; dst[1] = b; dst[2] = c; dst[3] = d;
-  const int v = (int)(e / (uint64_t)n);
-  int tile_off = 0, tiles_x = 1;
-  for (int k = 0; k < cb.n_views; ++k)
-    if (k == v) { tile_off = cb.v[k].tile_offset; tiles_x = cb.v[k].tiles_x; }
-  const ushort4 rc = rects[e];
-  // Exactly tiles_touched[e] pairs are written (the scan reserved that many);
-  // a tile outside the view's grid, or a slot the rectangle does not fill,
-  // gets the sentinel key n_tiles, which sorts after every real tile.
-  const uint32_t cnt = off_next(off, r, n_vis, total);
-  uint32_t p = off[r], k = 0;
-  const int tiles_y = tiles_y_of(cb, v);
-  for (int ty = rc.y; ty <= rc.w && k < cnt; ++ty) {
-    for (int tx = rc.x; tx <= rc.z && k < cnt; ++tx, ++k) {
-      const bool in = tx < tiles_x && ty < tiles_y;
-      tkeys[p + k] = in ? (uint32_t)(tile_off + ty * tiles_x + tx) : (uint32_t)cb.total_tiles;
-      tvals[p + k] = (uint32_t)r;
-    }
+  const int lane = threadIdx.x & 63;
+  int my_off = 0, my_cnt = 0, my_x0 = 0, my_y0 = 0, my_w = 1, my_h = 1, my_toff = 0, my_tx = 1, my_ty = 1;
+  if (r < n_vis) {
+    const uint32_t e = order[r];
+    const uint4* src = rec_in + (size_t)e * 4;
+    uint4* dst = rec_out + (size_t)r * 4;
+    const uint4 a = src[0], b = src[1], c = src[2], d = src[3];
+    dst[0] = a; dst[1] = b; dst[2] = c; dst[3] = d;
+    const int v = (int)(e / (uint64_t)n);
+    for (int k = 0; k < cb.n_views; ++k)
+      if (k == v) { my_toff = cb.v[k].tile_offset; my_tx = cb.v[k].tiles_x; my_ty = cb.v[k].tiles_y; }
+    const ushort4 rc = rects[e];
+    my_off = (int)off[r];
+    my_cnt = (int)off_next(off, r, n_vis, total);
+    my_x0 = rc.x; my_y0 = rc.y;
+    my_w = max(1, (int)rc.z - (int)rc.x + 1);
+    my_h = max(1, (int)rc.w - (int)rc.y + 1);
   }
-  for (; k < cnt; ++k) {
-    tkeys[p + k] = (uint32_t)cb.total_tiles;
-    tvals[p + k] = (uint32_t)r;
+  const int64_t r0 = r - lane;
+  for (int j = 0; j < 64; ++j) {
+    const int cntj = __builtin_amdgcn_readlane(my_cnt, j);
+    if (cntj == 0) continue;
+    const uint32_t offj = (uint32_t)__builtin_amdgcn_readlane(my_off, j);
+    const int x0 = __builtin_amdgcn_readlane(my_x0, j), y0 = __builtin_amdgcn_readlane(my_y0, j);
+    const int wj = __builtin_amdgcn_readlane(my_w, j), hj = __builtin_amdgcn_readlane(my_h, j);
+    const int toff = __builtin_amdgcn_readlane(my_toff, j);
+    const int tx = __builtin_amdgcn_readlane(my_tx, j), ty = __builtin_amdgcn_readlane(my_ty, j);
+    const uint32_t rank = (uint32_t)(r0 + j);
+    const float inv_w = 1.0f / (float)wj;
+    for (int k = lane; k < cntj; k += 64) {
+      // row q and column c of pair k; the float quotient is off by at most one
+      int q = (int)((float)k * inv_w);
+      int c = k - q * wj;
+      if (c < 0) { --q; c += wj; }
+      if (c >= wj) { ++q; c -= wj; }
+      const int x = x0 + c, y = y0 + q;
+      const bool in = q < hj && x < tx && y < ty;
+      tkeys[offj + k] = in ? (uint32_t)(toff + y * tx + x) : (uint32_t)cb.total_tiles;
+      tvals[offj + k] = rank;
+    }
   }
 }
 

@@ -45,7 +45,7 @@ struct __align__(16) Rec {
   float nb;            // -(nu + 2) / 2
   float hs;            // truncation level h*
   uint32_t entry;      // v * n + i
-  float nu;            // clamped nu
+  float ey;            // half extent in y of the ellipse h <= h*: sqrt(h* Sigma2D_yy)
 };
 static_assert(sizeof(Rec) == SSS_RECORD_BYTES, "record size");
 

@@ -179,13 +179,42 @@ __device__ __forceinline__ void view_dir(const CamDev& c, const float* mu, F* di
   dir[0] = vx * inv; dir[1] = vy * inv; dir[2] = vz * inv;
 }
 
+// Coalesced copy of the SH coefficients of components [i0, i0 + cnt) into LDS
+// with a padded stride (3K + 1 floats), so that each thread afterwards reads
+// its own coefficients without bank conflicts.
+template <int DEG>
+__device__ __forceinline__ void stage_sh(const float* __restrict__ sh, int64_t i0, int cnt, float* lds) {
+  constexpr int KC = 3 * (DEG + 1) * (DEG + 1), STR = KC + 1;
+  const float* src = sh + (size_t)i0 * KC;
+  if (KC % 4 == 0) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+    for (int g = threadIdx.x; g < cnt * KC / 4; g += kBlock) {
+      const float4 q = s4[g];
+      const int f = 4 * g, c = f / KC, j = f - c * KC;
+      float* d = lds + c * STR + j;
+      d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+    }
+  } else {
+    for (int g = threadIdx.x; g < cnt * KC; g += kBlock) {
+      const int c = g / KC, j = g - c * KC;
+      lds[c * STR + j] = src[g];
+    }
+  }
+}
+
+template <int DEG>
 __global__ __launch_bounds__(kBlock) void project_kernel(
-    CamBatch cb, OptsDev op, int64_t n, int deg, const float* __restrict__ means,
-    const float* __restrict__ scales, const float* __restrict__ quats, const float* __restrict__ nu,
-    const float* __restrict__ opac, const float* __restrict__ sh, Rec* __restrict__ rec,
-    uint32_t* __restrict__ keys, ushort4* __restrict__ rects, uint32_t* __restrict__ touched) {
+    CamBatch cb, OptsDev op, int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
+    const float* __restrict__ quats, const float* __restrict__ nu, const float* __restrict__ opac,
+    const float* __restrict__ sh, Rec* __restrict__ rec, uint32_t* __restrict__ keys, ushort4* __restrict__ rects,
+    uint32_t* __restrict__ touched) {
+  constexpr int K = (DEG + 1) * (DEG + 1), STR = 3 * K + 1;
+  __shared__ float shs[kBlock * STR];
   const int v = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+  stage_sh<DEG>(sh, i0, (int)min((int64_t)kBlock, n - i0), shs);
+  __syncthreads();
+  const int64_t i = i0 + threadIdx.x;
   if (i >= n) return;
   const CamDev& c = cb.v[v];
   const int64_t e = (int64_t)v * n + i;
@@ -203,11 +232,12 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
 
   const double mx = c.fx * g.xz + c.cx, my = c.fy * g.yz + c.cy;
   const double nuc = fmin(fmax((double)nu[i], (double)op.nu_min), (double)op.nu_max);
-  double hs;
+  double hs, ey;
   int x0, x1, y0, y1;
   if (op.alpha_min > 0.0f) {
     hs = nuc * expm1(2.0 / (nuc + 2.0) * log(fabs((double)o) / (double)op.alpha_min));
-    const double ex = sqrt(hs * g.A), ey = sqrt(hs * g.D);
+    const double ex = sqrt(hs * g.A);
+    ey = sqrt(hs * g.D);
     const double lx = (mx - ex) * (1.0 / kTile), hx = (mx + ex) * (1.0 / kTile);
     const double ly = (my - ey) * (1.0 / kTile), hy = (my + ey) * (1.0 / kTile);
     if (hx < 0.0 || lx >= c.tiles_x || hy < 0.0 || ly >= c.tiles_y) return;
@@ -215,16 +245,17 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     y0 = (int)fmax(0.0, floor(ly)); y1 = (int)fmin((double)(c.tiles_y - 1), floor(hy));
   } else {
     hs = __builtin_inf();
+    ey = __builtin_inf();
     x0 = 0; x1 = c.tiles_x - 1; y0 = 0; y1 = c.tiles_y - 1;
   }
 
   double dir[3], vn;
   view_dir<double>(c, mu, dir, &vn);
   double Y[16];
-  sh_basis<double>(deg, dir[0], dir[1], dir[2], Y);
-  const int K = (deg + 1) * (deg + 1);
-  const float* shi = sh + (size_t)i * K * 3;
+  sh_basis<double>(DEG, dir[0], dir[1], dir[2], Y);
+  const float* shi = shs + threadIdx.x * STR;
   double col[3] = {0.5, 0.5, 0.5};
+#pragma unroll
   for (int k = 0; k < K; ++k) {
     col[0] += Y[k] * shi[3 * k + 0];
     col[1] += Y[k] * shi[3 * k + 1];
@@ -246,30 +277,28 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   r.nb = (float)(-0.5 * (nuc + 2.0));
   r.hs = (float)hs;
   r.entry = (uint32_t)e;
-  r.nu = (float)nuc;
+  r.ey = (float)ey;
   rec[e] = r;
   rects[e] = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1);
   touched[e] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
 }
 
-// Backward: per component, sum over views of the chain from the screen-space
-// gradients (d mean2d, d conic, d colour, d o, d nu) to the parameters.
+// Backward of the geometry: per component, sum over views of the chain from
+// d mean2d and d conic (and d o, d nu) to means, scales, quats, opacity, nu.
+// FP32; the SH part is sh_bwd_kernel.  d_means is always accumulated (+=):
+// sh_bwd_kernel runs first and initialises it when overwriting.
 __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
-    CamBatch cb, OptsDev op, int64_t n, int deg, const float* __restrict__ means,
-    const float* __restrict__ scales, const float* __restrict__ quats, const float* __restrict__ nu,
-    const float* __restrict__ sh, const uint32_t* __restrict__ touched, const float* __restrict__ g2,
-    float* __restrict__ d_means, float* __restrict__ d_scales, float* __restrict__ d_quats,
-    float* __restrict__ d_nu, float* __restrict__ d_opac, float* __restrict__ d_sh, int overwrite) {
+    CamBatch cb, OptsDev op, int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
+    const float* __restrict__ quats, const float* __restrict__ nu, const uint32_t* __restrict__ touched,
+    const float* __restrict__ g2, float* __restrict__ d_means, float* __restrict__ d_scales,
+    float* __restrict__ d_quats, float* __restrict__ d_nu, float* __restrict__ d_opac, int overwrite) {
   using F = float;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const float* mu = means + 3 * i;
   const float* s = scales + 3 * i;
-  const int K = (deg + 1) * (deg + 1);
-  if (overwrite && d_sh)
-    for (int k = 0; k < 3 * K; ++k) d_sh[(size_t)i * K * 3 + k] = 0.0f;
-  F gmu[3] = {F(0.0), F(0.0), F(0.0)}, gs[3] = {F(0.0), F(0.0), F(0.0)}, gq[4] = {F(0.0), F(0.0), F(0.0), F(0.0)};
-  F gnu = F(0.0), gop = F(0.0);
+  F gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0};
+  F gnu = 0, gop = 0;
   bool any = false;
   for (int v = 0; v < cb.n_views; ++v) {
     const int64_t e = (int64_t)v * n + i;
@@ -279,8 +308,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     const float4 ga4 = *reinterpret_cast<const float4*>(g2 + e * kG2);
     const float4 gb4 = *reinterpret_cast<const float4*>(g2 + e * kG2 + 4);
     const float2 gc2 = *reinterpret_cast<const float2*>(g2 + e * kG2 + 8);
-    const F gmx = ga4.x, gmy = ga4.y, gqa = ga4.z, gqb = ga4.w;
-    const F gqc = gb4.x, gcr = gb4.y, gcg = gb4.z, gcb = gb4.w;
+    const F gmx = ga4.x, gmy = ga4.y, gqa = ga4.z, gqb = ga4.w, gqc = gb4.x;
     gop += gc2.x;
     gnu += gc2.y;
 
@@ -288,13 +316,13 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     geometry<F>(c, op, mu, s, quats + 4 * i, g);
     const F A = g.A, B = g.B, D = g.D, det = g.det;
     // conic (qa, qb, qc) = (D, -B, A) / det -> gradients w.r.t. (A, B, D)
-    const F id = F(1.0) / det, id2 = id * id;
+    const F id = F(1) / det, id2 = id * id;
     const F gA = -gqa * D * D * id2 + gqb * B * D * id2 + gqc * (id - A * D * id2);
     const F gD = gqa * (id - A * D * id2) + gqb * A * B * id2 - gqc * A * A * id2;
-    const F gB = F(2.0) * gqa * B * D * id2 - gqb * (id + F(2.0) * B * B * id2) + F(2.0) * gqc * A * B * id2;
+    const F gB = F(2) * gqa * B * D * id2 - gqb * (id + F(2) * B * B * id2) + F(2) * gqc * A * B * id2;
     // G (symmetric 2x2, off-diagonal shared by B)
     const F G00 = gA, G01 = F(0.5) * gB, G11 = gD;
-    // dSigma = M^T G M (3x3 symmetric, stored xx xy xz yy yz zz)
+    // dSigma = M^T G M
     const F* M = g.M;
     F GM[6];  // G M (2x3)
     for (int k = 0; k < 3; ++k) {
@@ -310,13 +338,13 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     F dM[6];
     for (int r = 0; r < 2; ++r)
       for (int b = 0; b < 3; ++b)
-        dM[3 * r + b] = F(2.0) * (GM[3 * r] * Sf[b] + GM[3 * r + 1] * Sf[3 + b] + GM[3 * r + 2] * Sf[6 + b]);
+        dM[3 * r + b] = F(2) * (GM[3 * r] * Sf[b] + GM[3 * r + 1] * Sf[3 + b] + GM[3 * r + 2] * Sf[6 + b]);
     // M = J Rview: dJ = dM Rview^T (only J00, J02, J11, J12 are non-zero)
     const F dJ00 = dM[0] * c.R[0] + dM[1] * c.R[1] + dM[2] * c.R[2];
     const F dJ02 = dM[0] * c.R[6] + dM[1] * c.R[7] + dM[2] * c.R[8];
     const F dJ11 = dM[3] * c.R[3] + dM[4] * c.R[4] + dM[5] * c.R[5];
     const F dJ12 = dM[3] * c.R[6] + dM[4] * c.R[7] + dM[5] * c.R[8];
-    const F iz = F(1.0) / g.Z, iz2 = iz * iz;
+    const F iz = F(1) / g.Z, iz2 = iz * iz;
     F dX = gmx * c.fx * iz;
     F dY = gmy * c.fy * iz;
     F dZ = -(gmx * c.fx * g.X + gmy * c.fy * g.Y) * iz2;
@@ -325,86 +353,151 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
       dZ += dJ02 * c.fx * g.txz * iz2;
     } else {
       dX += -dJ02 * c.fx * iz2;
-      dZ += F(2.0) * dJ02 * c.fx * g.X * iz2 * iz;
+      dZ += F(2) * dJ02 * c.fx * g.X * iz2 * iz;
     }
     if (g.cly) {
       dZ += dJ12 * c.fy * g.tyz * iz2;
     } else {
       dY += -dJ12 * c.fy * iz2;
-      dZ += F(2.0) * dJ12 * c.fy * g.Y * iz2 * iz;
+      dZ += F(2) * dJ12 * c.fy * g.Y * iz2 * iz;
     }
     for (int a = 0; a < 3; ++a) gmu[a] += c.R[a] * dX + c.R[3 + a] * dY + c.R[6 + a] * dZ;
 
     // Sigma = Rq diag(s^2) Rq^T
     const F* R = g.Rq;
-    const F sq[3] = {(F)s[0] * s[0], (F)s[1] * s[1], (F)s[2] * s[2]};
+    const F sq[3] = {s[0] * s[0], s[1] * s[1], s[2] * s[2]};
     F dR[9];
     for (int r = 0; r < 3; ++r)
       for (int k = 0; k < 3; ++k) {
         const F t = dS[3 * r] * R[k] + dS[3 * r + 1] * R[3 + k] + dS[3 * r + 2] * R[6 + k];
-        dR[3 * r + k] = F(2.0) * t * sq[k];
+        dR[3 * r + k] = F(2) * t * sq[k];
       }
     for (int k = 0; k < 3; ++k) {
       // (R^T dS R)_kk
-      F acc = F(0.0);
+      F acc = 0;
       for (int r = 0; r < 3; ++r)
         acc += R[3 * r + k] * (dS[3 * r] * R[k] + dS[3 * r + 1] * R[3 + k] + dS[3 * r + 2] * R[6 + k]);
-      gs[k] += F(2.0) * (F)s[k] * acc;
+      gs[k] += F(2) * s[k] * acc;
     }
     const F w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
     F gu[4];
-    gu[0] = -F(2.0) * z * dR[1] + F(2.0) * y * dR[2] + F(2.0) * z * dR[3] - F(2.0) * x * dR[5] - F(2.0) * y * dR[6] + F(2.0) * x * dR[7];
-    gu[1] = F(2.0) * y * dR[1] + F(2.0) * z * dR[2] + F(2.0) * y * dR[3] - F(4.0) * x * dR[4] - F(2.0) * w * dR[5] + F(2.0) * z * dR[6] +
-            F(2.0) * w * dR[7] - F(4.0) * x * dR[8];
-    gu[2] = -F(4.0) * y * dR[0] + F(2.0) * x * dR[1] + F(2.0) * w * dR[2] + F(2.0) * x * dR[3] + F(2.0) * z * dR[5] - F(2.0) * w * dR[6] +
-            F(2.0) * z * dR[7] - F(4.0) * y * dR[8];
-    gu[3] = -F(4.0) * z * dR[0] - F(2.0) * w * dR[1] + F(2.0) * x * dR[2] + F(2.0) * w * dR[3] - F(4.0) * z * dR[4] + F(2.0) * y * dR[5] +
-            F(2.0) * x * dR[6] + F(2.0) * y * dR[7];
+    gu[0] = -F(2) * z * dR[1] + F(2) * y * dR[2] + F(2) * z * dR[3] - F(2) * x * dR[5] - F(2) * y * dR[6] +
+            F(2) * x * dR[7];
+    gu[1] = F(2) * y * dR[1] + F(2) * z * dR[2] + F(2) * y * dR[3] - F(4) * x * dR[4] - F(2) * w * dR[5] +
+            F(2) * z * dR[6] + F(2) * w * dR[7] - F(4) * x * dR[8];
+    gu[2] = -F(4) * y * dR[0] + F(2) * x * dR[1] + F(2) * w * dR[2] + F(2) * x * dR[3] + F(2) * z * dR[5] -
+            F(2) * w * dR[6] + F(2) * z * dR[7] - F(4) * y * dR[8];
+    gu[3] = -F(4) * z * dR[0] - F(2) * w * dR[1] + F(2) * x * dR[2] + F(2) * w * dR[3] - F(4) * z * dR[4] +
+            F(2) * y * dR[5] + F(2) * x * dR[6] + F(2) * y * dR[7];
     const F dq = gu[0] * g.q[0] + gu[1] * g.q[1] + gu[2] * g.q[2] + gu[3] * g.q[3];
     for (int a = 0; a < 4; ++a) gq[a] += (gu[a] - g.q[a] * dq) / g.qn;
-
-    // colour
-    F dir[3], vn;
-    view_dir<F>(c, mu, dir, &vn);
-    F Yb[16];
-    sh_basis<F>(deg, dir[0], dir[1], dir[2], Yb);
-    const float* shi = sh + (size_t)i * K * 3;
-    float* dshi = d_sh + (size_t)i * K * 3;
-    const F gcol[3] = {gcr, gcg, gcb};
-    F wsum[16];
-    for (int k = 0; k < K; ++k) wsum[k] = F(0.0);
-    for (int ch = 0; ch < 3; ++ch) {
-      F raw = F(0.5);
-      for (int k = 0; k < K; ++k) raw += Yb[k] * shi[3 * k + ch];
-      if (!(raw > F(0.0))) continue;
-      for (int k = 0; k < K; ++k) {
-        if (d_sh) dshi[3 * k + ch] += (float)(gcol[ch] * Yb[k]);
-        wsum[k] += gcol[ch] * shi[3 * k + ch];
-      }
-    }
-    F gx, gy, gz;
-    sh_basis_grad<F>(deg, dir[0], dir[1], dir[2], wsum, &gx, &gy, &gz);
-    const F dd = gx * dir[0] + gy * dir[1] + gz * dir[2];
-    const F ivn = F(1.0) / vn;
-    gmu[0] += (gx - dir[0] * dd) * ivn;
-    gmu[1] += (gy - dir[1] * dd) * ivn;
-    gmu[2] += (gz - dir[2] * dd) * ivn;
   }
   if (!any && !overwrite) return;
   const float nv = nu[i];
-  if (!(nv >= op.nu_min && nv <= op.nu_max)) gnu = F(0.0);
+  if (!(nv >= op.nu_min && nv <= op.nu_max)) gnu = 0;
+  if (d_means) for (int a = 0; a < 3; ++a) d_means[3 * i + a] += gmu[a];
   if (overwrite) {
-    if (d_means) for (int a = 0; a < 3; ++a) d_means[3 * i + a] = (float)gmu[a];
-    if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] = (float)gs[a];
-    if (d_quats) for (int a = 0; a < 4; ++a) d_quats[4 * i + a] = (float)gq[a];
-    if (d_opac) d_opac[i] = (float)gop;
-    if (d_nu) d_nu[i] = (float)gnu;
+    if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] = gs[a];
+    if (d_quats) for (int a = 0; a < 4; ++a) d_quats[4 * i + a] = gq[a];
+    if (d_opac) d_opac[i] = gop;
+    if (d_nu) d_nu[i] = gnu;
   } else {
-    if (d_means) for (int a = 0; a < 3; ++a) d_means[3 * i + a] += (float)gmu[a];
-    if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] += (float)gs[a];
-    if (d_quats) for (int a = 0; a < 4; ++a) d_quats[4 * i + a] += (float)gq[a];
-    if (d_opac) d_opac[i] += (float)gop;
-    if (d_nu) d_nu[i] += (float)gnu;
+    if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] += gs[a];
+    if (d_quats) for (int a = 0; a < 4; ++a) d_quats[4 * i + a] += gq[a];
+    if (d_opac) d_opac[i] += gop;
+    if (d_nu) d_nu[i] += gnu;
+  }
+}
+
+// Backward of the SH colour: d_sh[k][c] = sum over views of d colour_c Y_k
+// (where the colour is not clamped), and the part of d_means that comes from
+// the viewing direction.  The block's SH are staged in LDS, read for every
+// view's colour and direction gradient, then the same LDS slots accumulate
+// d_sh and are written back coalesced.  d_means is written (overwrite) or
+// accumulated; project_bwd_kernel adds the geometric part afterwards.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, const float* __restrict__ means,
+                                                        const float* __restrict__ sh,
+                                                        const uint32_t* __restrict__ touched,
+                                                        const float* __restrict__ g2, float* __restrict__ d_means,
+                                                        float* __restrict__ d_sh, int overwrite) {
+  using F = float;
+  constexpr int K = (DEG + 1) * (DEG + 1), KC = 3 * K, STR = KC + 1;
+  __shared__ float shs[kBlock * STR];
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+  const int cnt = (int)min((int64_t)kBlock, n - i0);
+  stage_sh<DEG>(sh, i0, cnt, shs);
+  __syncthreads();
+  const int64_t i = i0 + threadIdx.x;
+  float* slot = shs + threadIdx.x * STR;
+  if (i < n) {
+    const float* mu = means + 3 * i;
+    F gmu[3] = {0, 0, 0};
+    uint64_t clamped = 0;                      // bit 3v+c: colour c of view v clamped at 0
+    for (int v = 0; v < cb.n_views; ++v) {
+      const int64_t e = (int64_t)v * n + i;
+      if (touched[e] == 0) continue;
+      const CamDev& c = cb.v[v];
+      const float4 gb4 = *reinterpret_cast<const float4*>(g2 + e * kG2 + 4);
+      const F gcol[3] = {gb4.y, gb4.z, gb4.w};
+      F dir[3], vn;
+      view_dir<F>(c, mu, dir, &vn);
+      F Yb[K];
+      sh_basis<F>(DEG, dir[0], dir[1], dir[2], Yb);
+      F wsum[16];
+#pragma unroll
+      for (int k = 0; k < K; ++k) wsum[k] = 0;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        F raw = F(0.5);
+#pragma unroll
+        for (int k = 0; k < K; ++k) raw += Yb[k] * slot[3 * k + ch];
+        if (!(raw > F(0))) {
+          clamped |= 1ull << (3 * v + ch);
+          continue;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) wsum[k] += gcol[ch] * slot[3 * k + ch];
+      }
+      F gx = 0, gy = 0, gz = 0;
+      if (DEG > 0) sh_basis_grad<F>(DEG, dir[0], dir[1], dir[2], wsum, &gx, &gy, &gz);
+      const F dd = gx * dir[0] + gy * dir[1] + gz * dir[2];
+      const F ivn = F(1) / vn;
+      gmu[0] += (gx - dir[0] * dd) * ivn;
+      gmu[1] += (gy - dir[1] * dd) * ivn;
+      gmu[2] += (gz - dir[2] * dd) * ivn;
+    }
+    if (d_means) {
+      if (overwrite) for (int a = 0; a < 3; ++a) d_means[3 * i + a] = gmu[a];
+      else for (int a = 0; a < 3; ++a) d_means[3 * i + a] += gmu[a];
+    }
+    // the SH values of this slot are no longer needed: accumulate d_sh in it
+    for (int j = 0; j < KC; ++j) slot[j] = 0.0f;
+    for (int v = 0; v < cb.n_views; ++v) {
+      const int64_t e = (int64_t)v * n + i;
+      if (touched[e] == 0) continue;
+      const CamDev& c = cb.v[v];
+      const float4 gb4 = *reinterpret_cast<const float4*>(g2 + e * kG2 + 4);
+      const F gcol[3] = {gb4.y, gb4.z, gb4.w};
+      F dir[3], vn;
+      view_dir<F>(c, mu, dir, &vn);
+      F Yb[K];
+      sh_basis<F>(DEG, dir[0], dir[1], dir[2], Yb);
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        if (clamped & (1ull << (3 * v + ch))) continue;
+#pragma unroll
+        for (int k = 0; k < K; ++k) slot[3 * k + ch] += gcol[ch] * Yb[k];
+      }
+    }
+  }
+  __syncthreads();
+  if (!d_sh) return;
+  float* dst = d_sh + (size_t)i0 * KC;
+  for (int g = threadIdx.x; g < cnt * KC; g += kBlock) {
+    const int c = g / KC, j = g - c * KC;
+    if (overwrite) dst[g] = shs[c * STR + j];
+    else dst[g] += shs[c * STR + j];
   }
 }
 
@@ -413,17 +506,34 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
 void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s, const sss_proj_t& out,
                     hipStream_t st) {
   dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock), (unsigned)cb.n_views);
-  SSS_LAUNCH("project", project_kernel, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, (int)s.sh_degree,
-                     s.means, s.scales, s.quats, s.nu, s.opacity, s.sh, (Rec*)out.records, out.depth_key,
-                     (ushort4*)out.rect, out.tiles_touched);
+#define SSS_PROJ(D)                                                                                          \
+  SSS_LAUNCH("project", project_kernel<D>, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, s.means, s.scales, \
+             s.quats, s.nu, s.opacity, s.sh, (Rec*)out.records, out.depth_key, (ushort4*)out.rect,            \
+             out.tiles_touched)
+  switch (s.sh_degree) {
+    case 0: SSS_PROJ(0); break;
+    case 1: SSS_PROJ(1); break;
+    case 2: SSS_PROJ(2); break;
+    default: SSS_PROJ(3); break;
+  }
+#undef SSS_PROJ
 }
 
 void launch_project_bwd(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s, const uint32_t* touched,
                         const float* g2, const sss_grads_t& gr, hipStream_t st) {
   dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock));
-  SSS_LAUNCH("project_bwd", project_bwd_kernel, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, (int)s.sh_degree,
-                     s.means, s.scales, s.quats, s.nu, s.sh, touched, g2, gr.means, gr.scales, gr.quats,
-                     gr.nu, gr.opacity, gr.sh, (int)gr.overwrite);
+#define SSS_SHB(D)                                                                                         \
+  SSS_LAUNCH("sh_bwd", sh_bwd_kernel<D>, grid, dim3(kBlock), 0, st, cb, (int64_t)s.n, s.means, s.sh, touched, \
+             g2, gr.means, gr.sh, (int)gr.overwrite)
+  switch (s.sh_degree) {
+    case 0: SSS_SHB(0); break;
+    case 1: SSS_SHB(1); break;
+    case 2: SSS_SHB(2); break;
+    default: SSS_SHB(3); break;
+  }
+#undef SSS_SHB
+  SSS_LAUNCH("project_bwd", project_bwd_kernel, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, s.means, s.scales,
+             s.quats, s.nu, touched, g2, gr.means, gr.scales, gr.quats, gr.nu, gr.opacity, (int)gr.overwrite);
 }
 
 }  // namespace sss

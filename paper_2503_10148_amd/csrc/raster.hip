@@ -30,7 +30,7 @@ struct __align__(16) LRec {
   float mx, my, qa, qb;      // mean relative to the tile origin; conic a, b
   float qc, hs, o, inv_nu;   // conic c; truncation test level; opacity; 1/nu
   float nb, cr, cg, cb;      // -(nu+2)/2; colour
-  float nu, pad0;
+  float pad0, ey;            // -; half extent in y of the pre-test ellipse
   uint32_t entry;
   float pad1;
 };
@@ -47,8 +47,9 @@ __device__ __forceinline__ void stage(const Rec* __restrict__ srec, uint32_t ran
   l.inv_nu = r.inv_nu;
   l.nb = r.nb;
   l.cr = r.cr; l.cg = r.cg; l.cb = r.cb;
-  l.nu = r.nu;
   l.pad0 = 0.0f;
+  // sqrt(1.0001) covers the widened pre-test level, the rest FP32 rounding
+  l.ey = r.ey * 1.0001f + 1e-3f;
   l.entry = r.entry;
   l.pad1 = 0.0f;
   *dst = l;
@@ -147,6 +148,15 @@ __device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint3
   return t;
 }
 
+// Whether the ellipse of a staged record can reach the 16x4 pixel strip that
+// this wave covers in its k-th pixel group (rows 4w + k*rowstep .. +3).
+template <int PIX>
+__device__ __forceinline__ bool strip_hit(const LRec& L, int k) {
+  constexpr int kRowStep = kBlock / PIX / kTile;
+  const float y0 = (float)((threadIdx.x >> 6) * 4 + k * kRowStep) + 0.5f;
+  return L.my + L.ey >= y0 && L.my - L.ey <= y0 + 3.0f;
+}
+
 // A batch is one staged record per thread.
 template <int PIX>
 __device__ __forceinline__ void stage_batch(const TileCtx<PIX>& t, const Rec* __restrict__ srec,
@@ -186,6 +196,10 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
         if (done[k]) continue;
+        if (!strip_hit<PIX>(L, k)) {
+          alive |= true;
+          continue;
+        }
         Eval E;
         evaluate(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
         if (E.hit) {
@@ -344,7 +358,7 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
       bool hit = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
-        if (pos >= bound[k]) continue;
+        if (pos >= bound[k] || !strip_hit<PIX>(L, k)) continue;
         Eval E;
         evaluate(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
         if (!E.hit) continue;

@@ -3,7 +3,7 @@ import numpy as np
 
 REC_DTYPE = np.dtype([("mx", "<f8"), ("my", "<f8"), ("qa", "<f4"), ("qb", "<f4"), ("qc", "<f4"), ("cr", "<f4"),
                       ("cg", "<f4"), ("cb", "<f4"), ("o", "<f4"), ("inv_nu", "<f4"), ("nb", "<f4"), ("hs", "<f4"),
-                      ("entry", "<u4"), ("nu", "<f4")])
+                      ("entry", "<u4"), ("ey", "<f4")])
 assert REC_DTYPE.itemsize == 64
 
 PARAMS = ("means", "scales", "quats", "nu", "opacity", "sh")

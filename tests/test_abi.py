@@ -151,4 +151,4 @@ def test_sghmc_rejects_bad_arguments(sss):
 def test_records_layout_matches_decoder():
     from tests._util import REC_DTYPE
     assert REC_DTYPE.itemsize == 64
-    assert REC_DTYPE.names[-2:] == ("entry", "nu")
+    assert REC_DTYPE.names[-2:] == ("entry", "ey")

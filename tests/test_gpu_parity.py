@@ -92,8 +92,11 @@ def test_project_matches_oracle(sss, name):
         assert np.all(np.abs(rec[f][m] - o["conic"][m, j]) <= 2e-7 * cs)
     for j, f in enumerate(("cr", "cg", "cb")):
         np.testing.assert_allclose(rec[f][m], o["rgb"][m, j], rtol=2e-7, atol=1e-7)
-    np.testing.assert_allclose(rec["nu"][m], o["nu_c"][m], rtol=1e-7)
+    np.testing.assert_allclose(1.0 / rec["inv_nu"][m].astype(np.float64), o["nu_c"][m], rtol=2e-7)
+    np.testing.assert_allclose(rec["nb"][m], -0.5 * (o["nu_c"][m] + 2.0), rtol=2e-7)
     np.testing.assert_allclose(rec["hs"][m], o["hstar"][m], rtol=2e-7)
+    # half extent in y of the truncation ellipse: sqrt(h* Sigma2D_yy)
+    np.testing.assert_allclose(rec["ey"][m], np.sqrt(o["hstar"][m] * o["cov2d"][m, 2]), rtol=2e-7)
     assert np.array_equal(rec["entry"][m], np.nonzero(m)[0])
 
 

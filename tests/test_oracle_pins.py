@@ -482,3 +482,40 @@ def test_window_render_equals_crop_of_full_render(oracle_lib):
     full = oracle_lib.render(s, cam)
     win = oracle_lib.render(s, oracle_lib.window_camera(cam, 37, 21, 70, 50))
     np.testing.assert_allclose(win["image"], full["image"][21:71, 37:107], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# recycling (SM "Component Recycling")
+# ---------------------------------------------------------------------------
+def test_lnbeta_matches_scipy_and_the_integral(oracle_lib):
+    from scipy import integrate, special
+    for x, y in [(0.5, 1.5), (0.5, 3.7), (2.0, 7.5), (0.5, 2500.0)]:
+        assert oracle_lib.lnbeta(x, y) == pytest.approx(special.betaln(x, y), rel=1e-12, abs=1e-12)
+    for alpha in (1.0, 2.0, 3.5, 9.0):              # int (1+x^2)^-alpha dx = beta(1/2, alpha - 1/2)
+        val, _ = integrate.quad(lambda x: (1 + x * x) ** -alpha, -np.inf, np.inf, epsabs=1e-13, epsrel=1e-12)
+        assert math.exp(oracle_lib.lnbeta(0.5, alpha - 0.5)) == pytest.approx(val, rel=1e-9)
+
+
+def test_relocation_identity_and_sign(oracle_lib):
+    o, f = oracle_lib.relocate(0.37, 6.0, 6.0, 1)
+    assert o == pytest.approx(0.37, abs=1e-15) and f == pytest.approx(1.0, rel=1e-13)
+    on, fn = oracle_lib.relocate(-0.37, 6.0, 6.0, 4)
+    op, fp = oracle_lib.relocate(0.37, 6.0, 6.0, 4)
+    assert on == -op and fn == fp
+    assert (1 - op) ** 4 == pytest.approx(1 - 0.37, rel=1e-14)
+
+
+@pytest.mark.parametrize("o_old,nu_old,nu_new,N", [(0.8, 3.0, 3.0, 2), (0.55, 12.0, 12.0, 5), (0.95, 1.5, 4.0, 3),
+                                                   (0.3, 40.0, 40.0, 8)])
+def test_relocation_preserves_the_integrated_opacity(oracle_lib, o_old, nu_old, nu_new, N):
+    """N stacked new components composite to 1 - (1 - o_new T_new)^N; its 1D
+    integral must equal that of the old component, o_old T_old (quadrature)."""
+    from scipy import integrate
+    o_new, f = oracle_lib.relocate(o_old, nu_old, nu_new, N)
+    s_old = 0.7
+    s_new = s_old * f
+    T = lambda x, nu, s: (1 + x * x / (nu * s)) ** (-(nu + 3) / 2)
+    old, _ = integrate.quad(lambda x: o_old * T(x, nu_old, s_old), -np.inf, np.inf, epsabs=1e-13, epsrel=1e-11)
+    new, _ = integrate.quad(lambda x: 1 - (1 - o_new * T(x, nu_new, s_new)) ** N, -np.inf, np.inf, epsabs=1e-13,
+                            epsrel=1e-11)
+    assert new == pytest.approx(old, rel=1e-8)
