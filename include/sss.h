@@ -267,6 +267,45 @@ int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const
                    const sss_sghmc_opts_t* opts, const sss_adam_t* adam, void* stream);
 
 /* ------------------------------------------------------------------------
+ * sss_relocate -- recycling of low-opacity components (Sec. 3.4 "Adding and
+ * Recycling Components", eq. relocation; SM "Component Recycling").
+ * Dead components (|o| <= dead_opacity), in index order and at most
+ * floor(n * max_fraction) of them, are moved onto live targets drawn from a
+ * multinomial over |o| (integer weights floor(|o| 2^24); draw j: Philox4x32-10,
+ * key (seed lo, seed hi), counter (j lo, step lo, step hi, 2^31 | j hi),
+ * position floor(((x1 << 32) | x0) W / 2^64) in the weight prefix sum W).
+ * A target drawn m times ends with N = m + 1 components at its mean: the
+ * moved ones copy its mean, rotation, nu and SH; all N get the opacity from
+ * (1 - o_new)^N = 1 - |o| (sign of the target's o) and scales multiplied by
+ * |o| beta(1/2, (nu+2)/2) / K with
+ * K = sum_{i=1..N} sum_{k<i} C(i-1,k) (-1)^k o_new^(k+1) beta(1/2, ((k+1)(nu+3)-1)/2)
+ * (nu unchanged, clamped to [1, 1e4] in the rule), beta through ln Gamma.
+ * Every listed state array (width floats per component: SGHMC momentum, Adam
+ * moments ...) gets the moved components' rows zeroed.  Components to add
+ * are appended by the caller with opacity 0 before the call (they are dead).
+ * The scene's arrays are modified in place (device, caller-owned).
+ * n_moved (host, nullable): when given, the call waits for the stream and
+ * writes the number of components moved.
+ * Errors: INVALID for null arrays, n < 1, max_fraction outside [0, 1],
+ * a short workspace or more than 8 state arrays. */
+typedef struct {
+  float dead_opacity;   /* 0.005 */
+  float max_fraction;   /* 0.05 */
+  uint64_t seed, step;
+} sss_relocate_opts_t;
+
+typedef struct {
+  float* ptr;           /* [n][width] device */
+  int32_t width;
+  int32_t reserved;
+} sss_state_t;
+
+size_t sss_relocate_workspace(int64_t n, float max_fraction);
+int sss_relocate(const sss_scene_t* scene, const sss_state_t* state, int n_state,
+                 const sss_relocate_opts_t* opts, void* ws, size_t ws_bytes, int64_t* n_moved,
+                 void* stream);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (tracing).  When enabled, every kernel the library launches
  * is bracketed by two HIP events on its own stream; sss_timing_read waits
  * for the recorded events and returns, per kernel name, the number of

@@ -56,6 +56,7 @@ def _load():
         _lib.orc_tiles_y.restype = ctypes.c_int
         _lib.orc_lnbeta.restype = ctypes.c_double
         _lib.orc_lnbeta.argtypes = [ctypes.c_double, ctypes.c_double]
+        _lib.orc_relocate_step.restype = ctypes.c_int64
     return _lib
 
 
@@ -328,3 +329,22 @@ def relocate(o_old, nu_old, nu_new, N):
     lib.orc_relocate(ctypes.c_double(o_old), ctypes.c_double(nu_old), ctypes.c_double(nu_new), ctypes.c_int(N),
                      ctypes.byref(o), ctypes.byref(f))
     return o.value, f.value
+
+
+def relocate_step(scene, dead_opacity=0.005, max_fraction=0.05, seed=0, step=0, states=()):
+    """One recycling step on float64 copies; returns (scene, states, dead, targets)."""
+    lib = _load()
+    s = _scene64(scene)
+    n = s["n"]
+    arrs = {k: s[k].copy() for k in ("means", "scales", "quats", "nu", "opacity", "sh")}
+    st = [np.ascontiguousarray(np.asarray(a, np.float64).reshape(n, -1)).copy() for a in states]
+    ptrs = (ctypes.c_void_p * max(1, len(st)))(*[a.ctypes.data for a in st])
+    widths = (ctypes.c_int * max(1, len(st)))(*[a.shape[1] for a in st])
+    dead = np.zeros(n, np.int64)
+    targ = np.zeros(n, np.int64)
+    nd = lib.orc_relocate_step(ctypes.c_int64(n), ctypes.c_int(s["deg"]), _p(arrs["means"]), _p(arrs["scales"]),
+                               _p(arrs["quats"]), _p(arrs["nu"]), _p(arrs["opacity"]), _p(arrs["sh"]),
+                               ctypes.c_double(dead_opacity), ctypes.c_double(max_fraction), ctypes.c_uint64(seed),
+                               ctypes.c_uint64(step), ctypes.c_int(len(st)), ptrs, widths, _p(dead), _p(targ))
+    arrs["sh_degree"] = s["deg"]
+    return arrs, st, dead[:nd], targ[:nd]

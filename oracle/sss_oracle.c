@@ -851,3 +851,81 @@ void orc_relocate(double o_old, double nu_old, double nu_new, int N, double* o_n
   *o_new = o_old < 0.0 ? -on : on;
   *factor = a * a * (nu_old / nu_new) * (b_old / K) * (b_old / K);
 }
+
+/* One recycling step over a whole scene (Sec. 3.4 "Adding and Recycling
+ * Components"; SM "Component Recycling"), the oracle of sss_relocate:
+ *  1. dead = |o| <= dead_opacity, taken in index order, at most
+ *     floor(n * max_fraction) of them;
+ *  2. targets from a multinomial over the live components with integer
+ *     weights w_i = floor(|o_i| 2^24) (exact, so the draw is reproducible
+ *     bit for bit): draw j uses Philox4x32-10 with key (seed lo, seed hi) and
+ *     counter (j lo, step lo, step hi, 2^31 | j hi); r = (x1 << 32) | x0 and the
+ *     drawn weight position is floor(r * W / 2^64), W = sum of weights; the
+ *     target is the component whose weight interval contains it;
+ *  3. a target drawn m times ends with N = m + 1 components at its mean: the
+ *     moved ones copy its mean, rotation, nu and SH, all N get the opacity and
+ *     covariance factor of orc_relocate (nu_new = nu_old, scales multiplied
+ *     by sqrt(factor)), and the moved ones' optimiser state is reset.
+ * Writes target[j] for the moved components (dead[j] -> target[j]); returns
+ * the number moved.  state/state_width: per-component rows zeroed for moved
+ * components (momentum, Adam moments). */
+int64_t orc_relocate_step(int64_t n, int sh_degree, double* means, double* scales, double* quats, double* nu,
+                          double* opac, double* sh, double dead_opacity, double max_fraction, uint64_t seed,
+                          uint64_t step, int n_state, double** state, const int* state_width,
+                          int64_t* dead_out, int64_t* target_out) {
+  const int K3 = 3 * (sh_degree + 1) * (sh_degree + 1);
+  const int64_t cap = (int64_t)floor((double)n * max_fraction);
+  int64_t nd = 0;
+  for (int64_t i = 0; i < n && nd < cap; ++i)
+    if (fabs((float)opac[i]) <= (float)dead_opacity) dead_out[nd++] = i;
+  uint64_t* excl = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n + 1));
+  uint64_t W = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    excl[i] = W;
+    const float a = fabsf((float)opac[i]);
+    if (!(a <= (float)dead_opacity)) W += (uint64_t)floorf(a * 16777216.0f);
+  }
+  excl[n] = W;
+  if (W == 0 || nd == 0) { free(excl); return 0; }
+  int32_t* m = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+  for (int64_t j = 0; j < nd; ++j) {
+    const uint32_t ctr[4] = {(uint32_t)j, (uint32_t)step, (uint32_t)(step >> 32), 0x80000000u | (uint32_t)(j >> 32)};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    const uint64_t r = ((uint64_t)x[1] << 32) | x[0];
+    const uint64_t pos = (uint64_t)(((unsigned __int128)r * W) >> 64);
+    int64_t lo = 0, hi = n;                       /* last t with excl[t] <= pos */
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) / 2;
+      if (excl[mid] <= pos) lo = mid; else hi = mid;
+    }
+    target_out[j] = lo;
+    m[lo] += 1;
+  }
+  /* moved components copy the (old) target, with the new opacity and scale */
+  for (int64_t j = 0; j < nd; ++j) {
+    const int64_t d = dead_out[j], t = target_out[j];
+    const double nut = fmin(fmax(nu[t], 1.0), 1e4);
+    double on, f;
+    orc_relocate(opac[t], nut, nut, m[t] + 1, &on, &f);
+    for (int a = 0; a < 3; ++a) { means[3 * d + a] = means[3 * t + a]; scales[3 * d + a] = scales[3 * t + a] * sqrt(f); }
+    for (int a = 0; a < 4; ++a) quats[4 * d + a] = quats[4 * t + a];
+    nu[d] = nu[t];
+    opac[d] = on;
+    for (int a = 0; a < K3; ++a) sh[(size_t)d * K3 + a] = sh[(size_t)t * K3 + a];
+    for (int s = 0; s < n_state; ++s)
+      for (int a = 0; a < state_width[s]; ++a) state[s][(size_t)d * state_width[s] + a] = 0.0;
+  }
+  for (int64_t t = 0; t < n; ++t) {
+    if (!m[t]) continue;
+    const double nut = fmin(fmax(nu[t], 1.0), 1e4);
+    double on, f;
+    orc_relocate(opac[t], nut, nut, m[t] + 1, &on, &f);
+    opac[t] = on;
+    for (int a = 0; a < 3; ++a) scales[3 * t + a] *= sqrt(f);
+  }
+  free(m);
+  free(excl);
+  return nd;
+}

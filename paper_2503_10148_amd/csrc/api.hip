@@ -257,4 +257,31 @@ int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const
   return hip_ok(hipGetLastError(), "sss_sghmc_step launch") ? SSS_OK : SSS_ERR_HIP;
 }
 
+size_t sss_relocate_workspace(int64_t n, float max_fraction) {
+  if (n < 1 || !(max_fraction >= 0.0f && max_fraction <= 1.0f)) return 0;
+  return relocate_workspace(n, (double)max_fraction);
+}
+
+int sss_relocate(const sss_scene_t* scene, const sss_state_t* state, int n_state, const sss_relocate_opts_t* opts,
+                 void* ws, size_t ws_bytes, int64_t* n_moved, void* stream) {
+  int rc = check_scene(scene, "sss_relocate");
+  if (rc) return rc;
+  if (!opts || !(opts->max_fraction >= 0.0f && opts->max_fraction <= 1.0f) || !ws || n_state < 0 || n_state > 8 ||
+      (n_state > 0 && !state)) {
+    set_error("sss_relocate: options, workspace or state list invalid (max_fraction in [0,1], <= 8 states)");
+    return SSS_ERR_INVALID;
+  }
+  float* ptrs[8];
+  int32_t widths[8];
+  for (int k = 0; k < n_state; ++k) {
+    if (!state[k].ptr || state[k].width < 1) {
+      set_error("sss_relocate: state array %d is null or has width < 1", k);
+      return SSS_ERR_INVALID;
+    }
+    ptrs[k] = state[k].ptr;
+    widths[k] = state[k].width;
+  }
+  return run_relocate(*scene, ptrs, widths, n_state, *opts, ws, ws_bytes, n_moved, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -15,93 +15,11 @@
 // data allows; the radix scatter ranks keys inside a wave with ballots
 // (64-wide match) so the sort is stable without per-thread digit counters.
 #include "common.hpp"
+#include "scan.hpp"
 
 namespace sss {
 namespace {
 
-constexpr int kItems = 16;                 // items per thread in scans / radix passes
-constexpr int kPerBlock = kBlock * kItems; // 4096
-
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
-  // Hillis-Steele over 256 values in LDS; returns the exclusive prefix.
-  const int t = threadIdx.x;
-  lds[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const uint32_t add = t >= off ? lds[t - off] : 0u;
-    __syncthreads();
-    lds[t] += add;
-    __syncthreads();
-  }
-  const uint32_t incl = lds[t];
-  if (total) *total = lds[kBlock - 1];
-  __syncthreads();
-  return incl - v;
-}
-
-__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
-                                                             uint32_t* __restrict__ sums) {
-  __shared__ uint32_t red[kBlock];
-  const int64_t base = (int64_t)blockIdx.x * kPerBlock;
-  uint32_t s = 0;
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-    if (j < n) s += in[j];
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
-}
-
-// Exclusive scan of one 4096-item block plus the block's prefix.
-__global__ __launch_bounds__(kBlock) void scan_apply_kernel(const uint32_t* in, int64_t n,
-                                                            const uint32_t* __restrict__ prefix,
-                                                            uint32_t* out) {
-  __shared__ uint32_t lds[kBlock];
-  const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
-  uint32_t v[kItems];
-  uint32_t s = 0;
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t j = base + k;
-    v[k] = j < n ? in[j] : 0u;
-    s += v[k];
-  }
-  uint32_t run = block_excl_scan(s, lds, nullptr) + (prefix ? prefix[blockIdx.x] : 0u);
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t j = base + k;
-    if (j < n) out[j] = run;
-    run += v[k];
-  }
-}
-
-// Exclusive scan of n uint32 values, any n; ws must hold scan_ws_words(n).
-int64_t scan_ws_words(int64_t n) {
-  int64_t w = 0;
-  while (n > kPerBlock) {
-    n = (n + kPerBlock - 1) / kPerBlock;
-    w += 2 * n;
-  }
-  return w + 16;
-}
-
-void scan_excl(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* ws, hipStream_t st) {
-  if (n <= 0) return;
-  const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
-  if (nb == 1) {
-    SSS_LAUNCH("scan_apply", scan_apply_kernel, dim3(1), dim3(kBlock), 0, st, in, n, (const uint32_t*)nullptr, out);
-    return;
-  }
-  uint32_t* sums = ws;
-  uint32_t* sums_scan = ws + nb;
-  SSS_LAUNCH("scan_reduce", scan_reduce_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, sums);
-  scan_excl(sums, sums_scan, nb, ws + 2 * nb, st);
-  SSS_LAUNCH("scan_apply", scan_apply_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n,
-                     (const uint32_t*)sums_scan, out);
-}
 
 // ---------------------------------------------------------------------------
 // 1. visibility
@@ -204,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   __syncthreads();
   // per digit: exclusive prefix over waves, and the block-level digit offset
   const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid], c3 = cnt[3][tid];
-  const uint32_t dstart = block_excl_scan(c0 + c1 + c2 + c3, dofs, nullptr);
+  const uint32_t dstart = block_excl_scan<uint32_t>(c0 + c1 + c2 + c3, dofs, (uint32_t*)nullptr);
   cnt[0][tid] = dstart;
   cnt[1][tid] = dstart + c0;
   cnt[2][tid] = dstart + c0 + c1;

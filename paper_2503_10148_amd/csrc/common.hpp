@@ -93,6 +93,9 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                        const uint32_t* n_contrib, float* image_out, float* loss_out, float* g2,
                        int64_t total_pixels, hipStream_t st);
 void launch_zero(float* p, int64_t count, hipStream_t st);
+size_t relocate_workspace(int64_t n, double max_fraction);
+int run_relocate(const sss_scene_t& s, float* const* state, const int32_t* widths, int n_state,
+                 const sss_relocate_opts_t& o, void* ws, size_t ws_bytes, int64_t* n_moved, hipStream_t st);
 void launch_sghmc(float* means, float* mom, const float* g, const float* opac, const float* scales,
                   const float* quats, int64_t n, const sss_sghmc_opts_t& o, hipStream_t st);
 void launch_adam(const sss_adam_array_t& a, float b1, float b2, float eps, int64_t t, hipStream_t st);

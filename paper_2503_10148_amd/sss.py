@@ -79,13 +79,23 @@ class Adam(ctypes.Structure):
                 ("n_arrays", ctypes.c_int32), ("t", ctypes.c_int64), ("arrays", AdamArray * 6)]
 
 
+class RelocateOpts(ctypes.Structure):
+    _fields_ = [("dead_opacity", ctypes.c_float), ("max_fraction", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("step", ctypes.c_uint64)]
+
+
+class StateArray(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("width", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
 EXPORTS = ["sss_default_render_opts", "sss_project", "sss_bin_sort", "sss_bin_sort_workspace", "sss_total_tiles",
            "sss_total_pixels", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_workspace", "sss_sghmc_step",
-           "sss_last_error", "sss_version"]
+           "sss_last_error", "sss_version", "sss_relocate", "sss_relocate_workspace", "sss_timing_enable",
+           "sss_timing_reset", "sss_timing_read"]
 
 _lib = None
 
@@ -114,6 +124,10 @@ def lib():
         L.sss_render_bwd.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                      ctypes.c_size_t, vp]
         L.sss_sghmc_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+        L.sss_relocate_workspace.restype = ctypes.c_size_t
+        L.sss_relocate_workspace.argtypes = [i64, ctypes.c_float]
+        L.sss_relocate.argtypes = [vp, vp, i32, vp, vp, ctypes.c_size_t, vp, vp]
+        L.sss_relocate.restype = i32
         L.sss_timing_enable.argtypes = [i32]
         L.sss_timing_enable.restype = i32
         L.sss_timing_reset.restype = None
@@ -362,3 +376,27 @@ def timing_read() -> dict:
     if k < 0:
         _check(k, "sss_timing_read")
     return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(k)}
+
+
+# ---------------------------------------------------------------------------
+# recycling
+# ---------------------------------------------------------------------------
+def relocate(scene, states=(), dead_opacity=0.005, max_fraction=0.05, seed=0, step=0, ws=None, stream=None,
+             want_count=True):
+    """In-place recycling step on the scene tensors; `states` are [n, w]
+    tensors (momentum, Adam moments) whose moved rows are zeroed.  Returns
+    the number of components moved (waits for the stream) or None."""
+    n = scene["means"].shape[0]
+    s = scene_struct(scene)
+    st = (StateArray * max(1, len(states)))()
+    for k, a in enumerate(states):
+        _need(a, torch.float32, "state")
+        st[k] = StateArray(a.data_ptr(), a.numel() // n, 0)
+    need = int(lib().sss_relocate_workspace(n, max_fraction))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=scene["means"].device)
+    o = RelocateOpts(dead_opacity, max_fraction, seed, step)
+    moved = ctypes.c_int64(0)
+    _check(lib().sss_relocate(ctypes.byref(s), st, len(states), ctypes.byref(o), _ptr(ws), ws.numel(),
+                              ctypes.byref(moved) if want_count else None, _stream(stream)), "sss_relocate")
+    return int(moved.value) if want_count else None

@@ -519,3 +519,41 @@ def test_relocation_preserves_the_integrated_opacity(oracle_lib, o_old, nu_old, 
     new, _ = integrate.quad(lambda x: 1 - (1 - o_new * T(x, nu_new, s_new)) ** N, -np.inf, np.inf, epsabs=1e-13,
                             epsrel=1e-11)
     assert new == pytest.approx(old, rel=1e-8)
+
+
+def test_relocate_step_draws_targets_in_proportion_to_opacity(oracle_lib):
+    """The multinomial over live |o| (integer weights): chi-square of the target
+    counts of many draws against the expected frequencies."""
+    n = 400
+    s = scenes.make_scene(n, 0, seed=91)
+    s["opacity"][:] = np.where(np.arange(n) < 200, np.float32(0.001), s["opacity"])     # 200 dead
+    counts = np.zeros(n)
+    for step in range(200):
+        _, _, dead, targ = oracle_lib.relocate_step(s, 0.005, 0.5, seed=3, step=step)
+        assert len(dead) == 200 and np.all(dead == np.arange(200))
+        np.add.at(counts, targ, 1)
+    live = np.arange(200, n)
+    w = np.floor(np.abs(s["opacity"][live].astype(np.float32)) * np.float32(2 ** 24))
+    exp_ = w / w.sum() * counts.sum()
+    assert counts[:200].sum() == 0
+    chi2 = ((counts[live] - exp_) ** 2 / exp_).sum()
+    assert stats.chi2.sf(chi2, len(live) - 1) > 1e-4
+
+
+def test_relocate_step_group_rule(oracle_lib):
+    """Every target group of N = m + 1 components satisfies (1 - |o_new|)^N = 1 - |o_old|
+    and has the scale factor of the pinned single-group rule."""
+    n = 1000
+    s = scenes.make_scene(n, 1, seed=92, neg_frac=0.4)
+    s["opacity"][::10] = np.float32(0.0)
+    out, _, dead, targ = oracle_lib.relocate_step(s, 0.005, 0.05, seed=5, step=1)
+    for t in np.unique(targ):
+        m = int((targ == t).sum())
+        o_old = float(s["opacity"][t])
+        o_new, f = oracle_lib.relocate(o_old, float(s["nu"][t]), float(s["nu"][t]), m + 1)
+        assert out["opacity"][t] == pytest.approx(o_new, rel=1e-12)
+        assert (1 - abs(out["opacity"][t])) ** (m + 1) == pytest.approx(1 - abs(o_old), rel=1e-12)
+        np.testing.assert_allclose(out["scales"][t], s["scales"][t].astype(np.float64) * math.sqrt(f), rtol=1e-12)
+        for d in dead[targ == t]:
+            np.testing.assert_allclose(out["means"][d], s["means"][t])
+            assert np.sign(out["opacity"][d]) == np.sign(o_old)
