@@ -96,7 +96,7 @@ def window_camera(cam, x0, y0, w, h):
 
 
 DEFAULT_OPTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, z_near=0.2, nu_min=1.0,
-                    nu_max=1e4, lowpass=0.0, bg=(0.0, 0.0, 0.0))
+                    nu_max=1e4, lowpass=0.0, bg=(0.0, 0.0, 0.0), family="student_t")
 
 
 def opts_array(opts=None) -> np.ndarray:
@@ -105,7 +105,9 @@ def opts_array(opts=None) -> np.ndarray:
         o.update(opts)
     vals = [o["alpha_min"], o["alpha_max"], o["t_min"], o["z_near"], o["nu_min"], o["nu_max"],
             o["lowpass"], *o["bg"]]
-    return np.asarray(vals, dtype=np.float32).astype(np.float64)
+    fam = {"student_t": 0, "gaussian": 1}.get(o["family"], o["family"]) if isinstance(o["family"], str) \
+        else int(o["family"])
+    return np.concatenate([np.asarray(vals, dtype=np.float32).astype(np.float64), [float(fam)]])
 
 
 def tiles(cam):

@@ -41,8 +41,9 @@
  *              clamp_width, clamp_height (the image size whose half field of
  *              view bounds the EWA Jacobian; equal to width, height except
  *              for a window cut out of a larger image)
- *   opts[10] = alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass,
- *              bg_r, bg_g, bg_b
+ *   opts[11] = alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass,
+ *              bg_r, bg_g, bg_b, family (0 Student's t, 1 Gaussian: the
+ *              nu -> infinity limit exp(-h/2) of Sec. 3.2)
  */
 #include <math.h>
 #include <stdint.h>
@@ -314,7 +315,7 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
     int x0, x1, y0, y1;
     double hs;
     if (alpha_min > 0.0) {
-      hs = nuc * expm1(2.0 / (nuc + 2.0) * log(fabs(o) / alpha_min));
+      hs = opts[10] == 1.0 ? 2.0 * log(fabs(o) / alpha_min) : nuc * expm1(2.0 / (nuc + 2.0) * log(fabs(o) / alpha_min));
       const double ex = sqrt(hs * A), ey = sqrt(hs * D);
       const double lx = (mx - ex) / ORC_TILE, hx = (mx + ex) / ORC_TILE;
       const double ly = (my - ey) / ORC_TILE, hy = (my + ey) / ORC_TILE;
@@ -428,7 +429,7 @@ static int composite_pixel(double px, double py, const int32_t* list, int64_t le
     const double dx = px - mean2d[2 * i], dy = py - mean2d[2 * i + 1];
     const double a = conic[3 * i], b = conic[3 * i + 1], c = conic[3 * i + 2];
     const double h = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy;
-    const double tt = t2d(h, nu_c[i]);
+    const double tt = opts[10] == 1.0 ? exp(-0.5 * h) : t2d(h, nu_c[i]);
     double alpha = opac[i] * tt;
     if (fabs(fabs(alpha) - amin) <= 1e-5 * amin) flags |= XF_ALPHA_MIN;
     if (fabs(alpha) < amin) continue;
@@ -548,10 +549,11 @@ void orc_render_backward(int n, const double* mean2d, const double* conic, const
         g_opac[i] += dalpha * e->t2;
         const double dt2 = dalpha * opac[i];
         const double nu = nu_c[i], h = e->h;
-        /* dT2D/dh = -(nu+2)/(2 nu) (1 + h/nu)^(-(nu+4)/2) */
-        const double dt_dh = -e->t2 * (nu + 2.0) / (2.0 * (nu + h));
-        /* dT2D/dnu, both the base and the exponent depend on nu */
-        const double dt_dnu = e->t2 * 0.5 * ((nu + 2.0) * h / (nu * (nu + h)) - log1p(h / nu));
+        /* dT2D/dh = -(nu+2)/(2 nu) (1 + h/nu)^(-(nu+4)/2); Gaussian: -T/2 */
+        const double dt_dh = opts[10] == 1.0 ? -0.5 * e->t2 : -e->t2 * (nu + 2.0) / (2.0 * (nu + h));
+        /* dT2D/dnu, both the base and the exponent depend on nu; Gaussian: 0 */
+        const double dt_dnu = opts[10] == 1.0 ? 0.0
+                                              : e->t2 * 0.5 * ((nu + 2.0) * h / (nu * (nu + h)) - log1p(h / nu));
         const double dh = dt2 * dt_dh;
         const double a = conic[3 * i], b = conic[3 * i + 1], cc = conic[3 * i + 2];
         g_mean2d[2 * i] += dh * (-2.0) * (a * e->dx + b * e->dy);

@@ -557,3 +557,28 @@ def test_relocate_step_group_rule(oracle_lib):
         for d in dead[targ == t]:
             np.testing.assert_allclose(out["means"][d], s["means"][t])
             assert np.sign(out["opacity"][d]) == np.sign(o_old)
+
+
+def test_gaussian_family_is_the_exact_gaussian(oracle_lib):
+    """family='gaussian' renders exp(-h/2) (the nu -> infinity limit of Sec. 3.2)."""
+    cam = axis_camera(64, 64)
+    s = one_component(scale=(0.04, 0.06, 0.05), nu=3.0, opacity=0.8, quat=(0.9, 0.1, -0.3, 0.2))
+    f = oracle_lib.render(s, cam, dict(family="gaussian", alpha_min=0.0))
+    p = f["proj"]
+    a, b, c = p["conic"][0]
+    ys, xs = np.mgrid[0:64, 0:64]
+    dx, dy = xs + 0.5 - p["mean2d"][0, 0], ys + 0.5 - p["mean2d"][0, 1]
+    h = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+    np.testing.assert_allclose(f["image"][..., 0], np.float64(np.float32(0.8)) * np.exp(-0.5 * h) * p["rgb"][0, 0],
+                               rtol=1e-13, atol=1e-300)
+    # truncation level of the Gaussian: |o| exp(-h*/2) = alpha_min
+    g = oracle_lib.render(s, cam, dict(family="gaussian"))
+    assert g["proj"]["hstar"][0] == pytest.approx(2 * math.log(np.float32(0.8) / np.float64(np.float32(1 / 255))))
+
+
+def test_gaussian_family_backward_matches_fd(oracle_lib):
+    s = scenes.make_scene(30, 2, seed=55, neg_frac=0.3)
+    s["scales"] *= np.float32(3.0)
+    cams = [scenes.ring_camera(44, 36, angle=1.2)]
+    checked = _fd_check(oracle_lib, s, cams, dict(family="gaussian"), 10, 56, 1e-5)
+    assert checked >= 40
