@@ -110,10 +110,17 @@ typedef struct {
  *   nu_min, nu_max   1, 1e4 (SM "Implementation Details")
  *   lowpass   0      added to the diagonal of the 2D covariance (the paper's
  *                    final model uses none; 0.3 in its ablation setting 1)
- *   bg        0,0,0  background colour, weighted by the final transmittance */
+ *   bg        0,0,0  background colour, weighted by the final transmittance
+ *   family    SSS_FAMILY_STUDENT_T; SSS_FAMILY_GAUSSIAN renders every component
+ *                    with the Gaussian kernel exp(-h/2) (the nu -> infinity limit,
+ *                    Sec. 3.2; the paper's SGHMC-with-Gaussians ablation), nu
+ *                    is ignored and gets no gradient */
+enum { SSS_FAMILY_STUDENT_T = 0, SSS_FAMILY_GAUSSIAN = 1 };
+
 typedef struct {
   float alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass;
   float bg[3];
+  int32_t family;
 } sss_render_opts_t;
 
 void sss_default_render_opts(sss_render_opts_t* opts);

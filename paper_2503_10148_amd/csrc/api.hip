@@ -70,6 +70,7 @@ OptsDev make_opts(const sss_render_opts_t* o) {
   r.alpha_min = o->alpha_min; r.alpha_max = o->alpha_max; r.t_min = o->t_min; r.z_near = o->z_near;
   r.nu_min = o->nu_min; r.nu_max = o->nu_max; r.lowpass = o->lowpass;
   r.bg[0] = o->bg[0]; r.bg[1] = o->bg[1]; r.bg[2] = o->bg[2];
+  r.family = o->family;
   return r;
 }
 
@@ -86,9 +87,10 @@ static int check_scene(const sss_scene_t* s, const char* fn) {
 static int check_opts(const sss_render_opts_t* o, const char* fn) {
   if (!o) return SSS_OK;
   if (!(o->alpha_min >= 0.0f) || !(o->alpha_max > 0.0f) || !(o->t_min >= 0.0f) || !(o->nu_min >= 1.0f) ||
-      !(o->nu_max >= o->nu_min) || !(o->lowpass >= 0.0f)) {
+      !(o->nu_max >= o->nu_min) || !(o->lowpass >= 0.0f) ||
+      (o->family != SSS_FAMILY_STUDENT_T && o->family != SSS_FAMILY_GAUSSIAN)) {
     set_error("%s: options out of range (alpha_min >= 0, alpha_max > 0, t_min >= 0, 1 <= nu_min <= nu_max, "
-              "lowpass >= 0)", fn);
+              "lowpass >= 0, known family)", fn);
     return SSS_ERR_INVALID;
   }
   return SSS_OK;
@@ -116,6 +118,7 @@ void sss_default_render_opts(sss_render_opts_t* o) {
   o->nu_max = 1e4f;
   o->lowpass = 0.0f;
   o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+  o->family = SSS_FAMILY_STUDENT_T;
 }
 
 const char* sss_last_error(void) { return g_err; }

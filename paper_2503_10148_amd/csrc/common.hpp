@@ -31,6 +31,7 @@ struct CamBatch {
 struct OptsDev {
   float alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass;
   float bg[3];
+  int32_t family;
 };
 
 // Projected record of one (view, component) entry, 64 bytes.
@@ -41,8 +42,8 @@ struct __align__(16) Rec {
   float qa, qb, qc;    // conic: h = qa dx^2 + 2 qb dx dy + qc dy^2
   float cr, cg, cb;    // colour
   float o;             // signed opacity
-  float inv_nu;        // 1 / nu
-  float nb;            // -(nu + 2) / 2
+  float inv_nu;        // 1 / nu; 0 for the Gaussian family
+  float nb;            // -(nu + 2) / 2; -log2(e) / 2 for the Gaussian family
   float hs;            // truncation level h*
   uint32_t entry;      // v * n + i
   float ey;            // half extent in y of the ellipse h <= h*: sqrt(h* Sigma2D_yy)

@@ -234,8 +234,11 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   const double nuc = fmin(fmax((double)nu[i], (double)op.nu_min), (double)op.nu_max);
   double hs, ey;
   int x0, x1, y0, y1;
+  const bool gauss = op.family == SSS_FAMILY_GAUSSIAN;
   if (op.alpha_min > 0.0f) {
-    hs = nuc * expm1(2.0 / (nuc + 2.0) * log(fabs((double)o) / (double)op.alpha_min));
+    // alpha level set |o| T2D(h*) = alpha_min
+    const double lr = log(fabs((double)o) / (double)op.alpha_min);
+    hs = gauss ? 2.0 * lr : nuc * expm1(2.0 / (nuc + 2.0) * lr);
     const double ex = sqrt(hs * g.A);
     ey = sqrt(hs * g.D);
     const double lx = (mx - ex) * (1.0 / kTile), hx = (mx + ex) * (1.0 / kTile);
@@ -273,8 +276,8 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   r.cg = (float)fmax(col[1], 0.0);
   r.cb = (float)fmax(col[2], 0.0);
   r.o = o;
-  r.inv_nu = (float)(1.0 / nuc);
-  r.nb = (float)(-0.5 * (nuc + 2.0));
+  r.inv_nu = gauss ? 0.0f : (float)(1.0 / nuc);
+  r.nb = gauss ? (float)(-0.5 * 1.4426950408889634) : (float)(-0.5 * (nuc + 2.0));
   r.hs = (float)hs;
   r.entry = (uint32_t)e;
   r.ey = (float)ey;
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
   }
   if (!any && !overwrite) return;
   const float nv = nu[i];
-  if (!(nv >= op.nu_min && nv <= op.nu_max)) gnu = 0;
+  if (!(nv >= op.nu_min && nv <= op.nu_max) || op.family == SSS_FAMILY_GAUSSIAN) gnu = 0;
   if (d_means) for (int a = 0; a < 3; ++a) d_means[3 * i + a] += gmu[a];
   if (overwrite) {
     if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] = gs[a];

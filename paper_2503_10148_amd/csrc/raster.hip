@@ -73,11 +73,18 @@ __device__ __forceinline__ void evaluate(float px, float py, const LRec& L, floa
   if (!(E.h <= L.hs)) return;
   // T2D = (1 + h/nu)^(-(nu+2)/2) = 2^(nb log2(1 + y)), y = h/nu.  log2(1 + y) is
   // corrected by the rounding error of u = 1 + y while u < 2.
-  E.y = E.h * L.inv_nu;
-  E.u = 1.0f + E.y;
-  const float z = E.u - 1.0f;
-  const float corr = E.u < 2.0f ? (E.y - z) : 0.0f;
-  E.l2 = __fmaf_rn(corr, kLog2e, __builtin_amdgcn_logf(E.u));
+  if (L.inv_nu != 0.0f) {
+    E.y = E.h * L.inv_nu;
+    E.u = 1.0f + E.y;
+    const float z = E.u - 1.0f;
+    const float corr = E.u < 2.0f ? (E.y - z) : 0.0f;
+    E.l2 = __fmaf_rn(corr, kLog2e, __builtin_amdgcn_logf(E.u));
+  } else {
+    // Gaussian family: T2D = exp(-h/2) = 2^(nb h), nb = -log2(e)/2
+    E.y = 0.0f;
+    E.u = 1.0f;
+    E.l2 = E.h;
+  }
   E.t2 = __builtin_amdgcn_exp2f(L.nb * E.l2);
   float a = L.o * E.t2;
   if (fabsf(a) < amin) return;
@@ -378,7 +385,9 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
         v8 = __fmaf_rn(da, E.t2, v8);
         const float dt2 = da * L.o;
         const float ru = __builtin_amdgcn_rcpf(E.u);
-        const float dh = dt2 * E.t2 * L.nb * L.inv_nu * ru;
+        // d log2 T / dh = nb / (nu (1 + y)); nb ln 2 for the Gaussian family
+        const float kh = L.inv_nu != 0.0f ? L.inv_nu * ru : kLn2;
+        const float dh = dt2 * E.t2 * L.nb * kh;
         v0 = __fmaf_rn(dh, E.ax, v0);
         v1 = __fmaf_rn(dh, E.ay, v1);
         const float tq = dh * E.dx;

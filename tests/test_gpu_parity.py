@@ -413,3 +413,25 @@ def test_adam_matches_oracle(sss):
     np.testing.assert_allclose(dp.cpu().numpy(), ref[0], rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(dm.cpu().numpy(), ref[1], rtol=1e-5, atol=1e-7)
     np.testing.assert_allclose(dv.cpu().numpy(), ref[2], rtol=1e-5, atol=1e-8)
+
+
+@pytest.mark.parametrize("name", ["sh3_ragged", "bigcomp"])
+def test_gaussian_family_matches_oracle(sss, name):
+    scene, cams = _case(name)
+    cam = cams[0]
+    opts = dict(family="gaussian")
+    ref = oracle.render(scene, cam, opts)
+    dev, proj, bins, img, _, ncon = gpu_forward(sss, scene, cams, opts)
+    bad, _, _ = _image_check(img.cpu().numpy(), ref, ref["xflags"])
+    assert not bad.any()
+    w = np.random.default_rng(8).standard_normal(ref["image"].shape)
+    w[ref["xflags"] != 0] = 0.0
+    gref = oracle.render_backward(scene, cam, w, opts, fwd=ref)
+    g = sss.render_bwd(dev, proj, bins, cams, torch.as_tensor(w.reshape(-1, 3), dtype=torch.float32, device="cuda"),
+                       opts, image=img, n_contrib=ncon)
+    torch.cuda.synchronize()
+    keep = ref["proj"]["pflags"] == 0
+    assert not np.any(g["nu"].cpu().numpy())
+    for k in PARAMS:
+        ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=keep)
+        assert ok, (k, worst)
