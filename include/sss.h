@@ -274,6 +274,22 @@ int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const
                    const sss_sghmc_opts_t* opts, const sss_adam_t* adam, void* stream);
 
 /* ------------------------------------------------------------------------
+ * sss_loss -- the photometric loss of Sec. 3.4,
+ *   L = (1 - lambda) L1 + lambda (1 - SSIM),
+ * and dL/dimage, to feed sss_render_bwd (SSS_LOSS_GRAD).  L1 and SSIM are
+ * means over all 3P values of all views; SSIM uses an 11x11 Gaussian window
+ * (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2 and zero padding, each view filtered
+ * on its own.  (The paper's opacity and scale regularisers are sums over
+ * parameters and do not enter dL/dimage.)
+ *   image, target [P][3]  device; dl_dimage [P][3] written;
+ *   loss_out (device float, nullable) receives += L;
+ *   ws of ws_bytes >= sss_loss_workspace(P) (per-pixel SSIM partials).
+ * Errors: INVALID for null pointers, lambda outside [0, 1], short workspace. */
+size_t sss_loss_workspace(int64_t total_pixels);
+int sss_loss(const float* image, const float* target, const sss_camera_t* cams, int n_views, float lambda_dssim,
+             float* dl_dimage, float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * sss_relocate -- recycling of low-opacity components (Sec. 3.4 "Adding and
  * Recycling Components", eq. relocation; SM "Component Recycling").
  * Dead components (|o| <= dead_opacity), in index order and at most

@@ -260,6 +260,29 @@ int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const
   return hip_ok(hipGetLastError(), "sss_sghmc_step launch") ? SSS_OK : SSS_ERR_HIP;
 }
 
+size_t sss_loss_workspace(int64_t total_pixels) {
+  if (total_pixels < 0) return 0;
+  return loss_workspace(total_pixels);
+}
+
+int sss_loss(const float* image, const float* target, const sss_camera_t* cams, int n_views, float lambda_dssim,
+             float* dl_dimage, float* loss_out, void* ws, size_t ws_bytes, void* stream) {
+  CamBatch cb;
+  int rc = make_cam_batch(cams, n_views, &cb);
+  if (rc) return rc;
+  if (!image || !target || !dl_dimage || !ws || !(lambda_dssim >= 0.0f && lambda_dssim <= 1.0f)) {
+    set_error("sss_loss: null pointer or lambda outside [0, 1]");
+    return SSS_ERR_INVALID;
+  }
+  const int64_t P = total_pixels(cb);
+  if (ws_bytes < loss_workspace(P)) {
+    set_error("sss_loss: workspace of %zu bytes, %zu needed", ws_bytes, loss_workspace(P));
+    return SSS_ERR_INVALID;
+  }
+  launch_loss(cb, image, target, lambda_dssim, dl_dimage, loss_out, (float*)ws, P, (hipStream_t)stream);
+  return hip_ok(hipGetLastError(), "sss_loss launch") ? SSS_OK : SSS_ERR_HIP;
+}
+
 size_t sss_relocate_workspace(int64_t n, float max_fraction) {
   if (n < 1 || !(max_fraction >= 0.0f && max_fraction <= 1.0f)) return 0;
   return relocate_workspace(n, (double)max_fraction);

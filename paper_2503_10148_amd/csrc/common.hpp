@@ -95,6 +95,9 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                        int64_t total_pixels, hipStream_t st);
 void launch_zero(float* p, int64_t count, hipStream_t st);
 size_t relocate_workspace(int64_t n, double max_fraction);
+size_t loss_workspace(int64_t total_pixels);
+void launch_loss(const CamBatch& cb, const float* img, const float* tgt, float lam, float* dl, float* loss_out,
+                 float* partial, int64_t total_pixels, hipStream_t st);
 int run_relocate(const sss_scene_t& s, float* const* state, const int32_t* widths, int n_state,
                  const sss_relocate_opts_t& o, void* ws, size_t ws_bytes, int64_t* n_moved, hipStream_t st);
 void launch_sghmc(float* means, float* mom, const float* g, const float* opac, const float* scales,

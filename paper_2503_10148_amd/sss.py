@@ -94,7 +94,7 @@ class KernelTime(ctypes.Structure):
 
 EXPORTS = ["sss_default_render_opts", "sss_project", "sss_bin_sort", "sss_bin_sort_workspace", "sss_total_tiles",
            "sss_total_pixels", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_workspace", "sss_sghmc_step",
-           "sss_last_error", "sss_version", "sss_relocate", "sss_relocate_workspace", "sss_timing_enable",
+           "sss_last_error", "sss_version", "sss_loss", "sss_loss_workspace", "sss_relocate", "sss_relocate_workspace", "sss_timing_enable",
            "sss_timing_reset", "sss_timing_read"]
 
 _lib = None
@@ -124,6 +124,10 @@ def lib():
         L.sss_render_bwd.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                      ctypes.c_size_t, vp]
         L.sss_sghmc_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+        L.sss_loss_workspace.restype = ctypes.c_size_t
+        L.sss_loss_workspace.argtypes = [i64]
+        L.sss_loss.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, ctypes.c_size_t, vp]
+        L.sss_loss.restype = i32
         L.sss_relocate_workspace.restype = ctypes.c_size_t
         L.sss_relocate_workspace.argtypes = [i64, ctypes.c_float]
         L.sss_relocate.argtypes = [vp, vp, i32, vp, vp, ctypes.c_size_t, vp, vp]
@@ -402,3 +406,21 @@ def relocate(scene, states=(), dead_opacity=0.005, max_fraction=0.05, seed=0, st
     _check(lib().sss_relocate(ctypes.byref(s), st, len(states), ctypes.byref(o), _ptr(ws), ws.numel(),
                               ctypes.byref(moved) if want_count else None, _stream(stream)), "sss_relocate")
     return int(moved.value) if want_count else None
+
+
+# ---------------------------------------------------------------------------
+# loss
+# ---------------------------------------------------------------------------
+def loss(image, target, cams, lambda_dssim=0.2, dl_dimage=None, loss_out=None, ws=None, stream=None):
+    """(1 - lambda) L1 + lambda (1 - SSIM) over all views; returns dL/dimage
+    (and adds L into loss_out when given)."""
+    P = total_pixels(cams)
+    _need(image, torch.float32, "image")
+    _need(target, torch.float32, "target")
+    dl_dimage = torch.empty_like(image) if dl_dimage is None else dl_dimage
+    need = int(lib().sss_loss_workspace(P))
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(max(need // 4, 1), dtype=torch.float32, device=image.device)
+    _check(lib().sss_loss(_ptr(image), _ptr(target), camera_array(cams), len(cams), lambda_dssim, _ptr(dl_dimage),
+                          _ptr(loss_out), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)), "sss_loss")
+    return dl_dimage

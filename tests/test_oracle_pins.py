@@ -582,3 +582,40 @@ def test_gaussian_family_backward_matches_fd(oracle_lib):
     cams = [scenes.ring_camera(44, 36, angle=1.2)]
     checked = _fd_check(oracle_lib, s, cams, dict(family="gaussian"), 10, 56, 1e-5)
     assert checked >= 40
+
+
+# ---------------------------------------------------------------------------
+# loss (L1 + D-SSIM)
+# ---------------------------------------------------------------------------
+def test_ssim_closed_forms():
+    import torch
+    from oracle import loss
+    rng = np.random.default_rng(1)
+    x = torch.tensor(rng.uniform(0, 1, (3, 40, 50)))
+    assert torch.allclose(loss.ssim_map(x, x), torch.ones_like(x), atol=1e-12)
+    # constant images: away from the border sigma = 0 and SSIM = (2ab + C1)/(a^2 + b^2 + C1)
+    a, b = 0.3, 0.7
+    m = loss.ssim_map(torch.full((1, 40, 40), a, dtype=torch.float64), torch.full((1, 40, 40), b, dtype=torch.float64))
+    want = (2 * a * b + loss.C1) / (a * a + b * b + loss.C1)
+    assert torch.allclose(m[0, 5:-5, 5:-5], torch.full((30, 30), want, dtype=torch.float64), atol=1e-12)
+    w = loss.gaussian_window()
+    assert abs(float(w.sum()) - 1) < 1e-14 and w.shape == (11, 11)
+    assert float(w[5, 5] / w[5, 6]) == pytest.approx(math.exp(1 / (2 * 1.5 ** 2)), rel=1e-12)
+
+
+def test_loss_gradient_matches_finite_differences():
+    from oracle import loss
+    rng = np.random.default_rng(2)
+    img = rng.uniform(0, 1, (20, 23, 3))
+    tgt = rng.uniform(0, 1, (20, 23, 3))
+    L, g = loss.loss_and_grad(img, tgt, 0.2)
+    assert L == pytest.approx(0.8 * np.abs(img - tgt).mean() + 0.2 * (1 - float(
+        loss.ssim_map(*(loss.torch.tensor(a).permute(2, 0, 1) for a in (img, tgt))).mean())), rel=1e-12)
+    for _ in range(25):
+        y, x, c = rng.integers(0, 20), rng.integers(0, 23), rng.integers(0, 3)
+        h = 1e-6
+        p, m = img.copy(), img.copy()
+        p[y, x, c] += h
+        m[y, x, c] -= h
+        fd = (loss.loss_and_grad(p, tgt, 0.2)[0] - loss.loss_and_grad(m, tgt, 0.2)[0]) / (2 * h)
+        assert g[y, x, c] == pytest.approx(fd, rel=1e-5, abs=1e-10)
