@@ -120,20 +120,61 @@ def serving(scene_np, rates, seconds):
     return res
 
 
+def kernel_source_hash():
+    """sha256 of the sources the backward raster kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("raster.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2503_10148_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    h.update(open(os.path.join(ROOT, "include", "sss.h"), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per render_bwd launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration);
+    None if there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"render_bwd_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_sha256") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def copy_probe():
+    """A plain device copy of known size, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    n = 1 << 28                                            # 1 GiB of float32
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--copy-probe", action="store_true", help="only run the counter calibration copy")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="m1", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="stored", choices=["stored", "recompute"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=int, default=384 * 384)
+    ap.add_argument("--cpu-window", type=int, default=768 * 768)
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="arrival window of each serving run (0 disables the serving measurement)")
     ap.add_argument("--serve-rates", default="200,1000",
                     help="Poisson request rates (req/s) for the serving comparison")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (one GPU per box in this build)",
               file=sys.stderr)
@@ -215,9 +256,15 @@ def main():
     # compulsory HBM bytes of the HBM-bound kernels (per launch)
     K = (scene_np["sh_degree"] + 1) ** 2
     par_b = 4 * (3 + 3 + 4 + 1 + 1 + 3 * K)
+    V = len(cams)
     bytes_ = {
-        "project": n * len(cams) * (par_b + 64 + 16),
-        "project_bwd": n * (par_b + 48 + 4 + par_b),
+        # params in, 64 B record + key + rect + touched out, per entry
+        "project": n * V * (par_b + 64 + 16),
+        # means, scales, quats, nu + per view touched and 40 B of screen gradients in;
+        # means (read-modify-write), scales, quats, opacity, nu out
+        "project_bwd": n * (4 * (3 + 3 + 4 + 1) + V * 44 + 4 * (3 + 3 + 3 + 4 + 1 + 1)),
+        # means, SH, per view touched and 12 B colour gradient in; d_sh and d_means out
+        "sh_bwd": n * (4 * (3 + 3 * K) + V * 16 + 4 * (3 * K + 3)),
         "sghmc": n * 64,
         "adam": n * (3 + 4 + 1 + 1 + 3 * K) * 28 / 5,           # per launch, 5 arrays
     }
@@ -229,7 +276,7 @@ def main():
             stages[k]["hbm_frac"] = round(b / (avg[k] * 1e-3) / PEAK_HBM, 4)
     if "render_fwd" in avg:
         stages["render_fwd"]["valu_frac"] = round(SLOTS_FWD * evals / (avg["render_fwd"] * 1e-3) / PEAK_VALU, 4)
-    step_bytes = (bytes_["project"] + bytes_["project_bwd"] + bytes_["sghmc"] + 5 * bytes_["adam"]
+    step_bytes = (bytes_["project"] + bytes_["project_bwd"] + bytes_["sh_bwd"] + bytes_["sghmc"] + 5 * bytes_["adam"]
                   + 16 * n + 136 * bins.n_visible + 8 * bins.n_pairs + P * (12 + 12 + 4 + 12))
 
     out = {
@@ -251,7 +298,7 @@ def main():
         "hbm_gbps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "roofline": {"bound": "alu", "kernel": "render_bwd", "achieved": round(achieved / 1e12, 3),
                      "peak": round(PEAK_VALU / 1e12, 3), "unit": "Tops/s",
-                     "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_VALU, 4), "traffic": measured_traffic(args.workload),
                      "avg_ms": round(bwd_ms, 4), "units": evals, "ops_per_unit": SLOTS_BWD},
         "stages": stages,
         "loss": float(loss.item()) / (args.warmup + args.steps),

@@ -44,6 +44,7 @@ def test_autograd_matches_finite_differences_on_training_workload(mods):
     ref = oracle.render(scene, cam)
     proj = ref["proj"]
     w = np.sign(ref["image"] - target) / (3.0 * P)
+    w[ref["xflags"] != 0] = 0.0          # explained pixels take no part in either side
 
     p = _leaf(scene)
     img = ag.render(p["means"], p["scales"], p["quats"], p["nu"], p["opacity"], p["sh"], cams)
@@ -51,14 +52,12 @@ def test_autograd_matches_finite_differences_on_training_workload(mods):
     torch.cuda.synchronize()
     g_gpu = {k: p[k].grad.cpu().numpy() for k in PARAMS}
 
-    # candidate components: visible, unflagged, small rectangle, no explained pixel inside
+    # candidate components: visible, unflagged, small rectangle
     rng = np.random.default_rng(scenes.SEED_FD)
     rect = proj["rect"]
     area = (rect[:, 2] - rect[:, 0] + 1) * (rect[:, 3] - rect[:, 1] + 1)
-    xf = ref["xflags"] != 0
     ok = (proj["valid"] == 1) & (proj["pflags"] == 0) & (area <= 16)
-    cand = [i for i in rng.permutation(np.nonzero(ok)[0])[:4000]
-            if not xf[rect[i, 1] * 16:(rect[i, 3] + 1) * 16, rect[i, 0] * 16:(rect[i, 2] + 1) * 16].any()]
+    cand = list(rng.permutation(np.nonzero(ok)[0])[:4000])
     s64 = {k: np.asarray(scene[k], np.float64).copy() for k in PARAMS}
 
     def window_loss(i, sub, s_sub, wx0, wy0, ww, wh):
@@ -85,7 +84,7 @@ def test_autograd_matches_finite_differences_on_training_workload(mods):
                              (r[:, 3] >= y0))[0]
             s_sub = {kk: s64[kk][sub].copy() for kk in PARAMS}
             li = int(np.nonzero(sub == i)[0][0])
-            flat = s_sub[k][li].reshape(-1)
+            flat = s_sub[k].reshape(len(sub), -1)[li]          # a view, also for 1-D arrays
             j = int(rng.integers(0, flat.size))
             est = []
             for hrel in (1e-6, 5e-7):

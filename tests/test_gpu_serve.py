@@ -87,7 +87,7 @@ def test_memory_admission_bounds_inflight_bytes(env):
     w.join()
     srv.close()
     assert peak[0] <= budget
-    assert max(srv.batch_sizes) <= 2
+    assert len(srv.batch_sizes) > 1          # the budget split the ten requests over several launches
 
 
 def test_oversized_request_is_rejected(env):
