@@ -280,7 +280,7 @@ int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const
  * means over all 3P values of all views; SSIM uses an 11x11 Gaussian window
  * (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2 and zero padding, each view filtered
  * on its own.  (The paper's opacity and scale regularisers are sums over
- * parameters and do not enter dL/dimage.)
+ * parameters and do not enter dL/dimage: see sss_regularise.)
  *   image, target [P][3]  device; dl_dimage [P][3] written;
  *   loss_out (device float, nullable) receives += L;
  *   ws of ws_bytes >= sss_loss_workspace(P) (per-pixel SSIM partials).
@@ -288,6 +288,17 @@ int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const
 size_t sss_loss_workspace(int64_t total_pixels);
 int sss_loss(const float* image, const float* target, const sss_camera_t* cams, int n_views, float lambda_dssim,
              float* dl_dimage, float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sss_regularise -- the two regularisers of the Sec. 3.4 loss,
+ *   eps_opacity sum_i |o_i| + eps_sigma sum_i sum_j sqrt(lambda_ij),
+ * lambda_ij the eigenvalues of Sigma_i = R S S^T R^T, so sqrt(lambda_ij) =
+ * |s_ij|.  Adds the gradient eps sign(x) (0 at x = 0) into d_opacity [n] and
+ * d_scales [n][3] (device, nullable: skipped) and, when loss_out (device
+ * float) is given, adds the value to it.  opacity [n], scales [n][3] device.
+ * Errors: INVALID for null inputs, n <= 0, negative weights. */
+int sss_regularise(const float* opacity, const float* scales, int64_t n, float eps_opacity, float eps_sigma,
+                   float* d_opacity, float* d_scales, float* loss_out, void* stream);
 
 /* ------------------------------------------------------------------------
  * sss_relocate -- recycling of low-opacity components (Sec. 3.4 "Adding and

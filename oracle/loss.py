@@ -8,8 +8,11 @@ Bovik, Sheikh, Simoncelli 2004) with an 11 x 11 Gaussian window of standard
 deviation 1.5, constants C1 = 0.01^2, C2 = 0.03^2, and zero padding at the
 image border (the window/padding convention of the Gaussian rasterizer the
 paper builds on; the paper does not state it).  The opacity and scale
-regularisers of the paper's loss are sums over parameters and are not part of
-the image gradient.
+regularisers of the paper's loss, eps_o sum_i |o_i| + eps_s sum_ij sqrt(lambda_ij)
+with lambda the eigenvalues of Sigma_i, are sums over parameters and are not
+part of the image gradient: `regulariser` computes them from that definition
+(Sigma built from the quaternion and scales, eigenvalues by a symmetric
+eigensolver).
 
 TEST INFRASTRUCTURE ONLY.  Plain float64 PyTorch CPU operations; the
 gradient dL/dimage is reverse-mode autograd of this definition.
@@ -56,3 +59,27 @@ def loss_and_grad(image, target, lam):
     L = (1.0 - lam) * l1 + lam * (1.0 - ssim)
     L.backward()
     return float(L), x.grad.permute(1, 2, 0).numpy().copy()
+
+
+def _sigma(scales, quats):
+    """Sigma = R diag(s^2) R^T per component, R from the normalised quaternion (w, x, y, z)."""
+    q = quats / torch.linalg.norm(quats, dim=1, keepdim=True)
+    w, x, y, z = q.unbind(1)
+    R = torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], 1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], 1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1)], 1)
+    return R @ torch.diag_embed(scales * scales) @ R.transpose(1, 2)
+
+
+def regulariser(opacity, scales, quats, eps_o, eps_s):
+    """Sec. 3.4 regularisers eps_o sum|o| + eps_s sum sqrt(eig Sigma).  Returns
+    (value, d/d opacity [n], d/d scales [n, 3], d/d quats [n, 4]), FP64,
+    gradient by reverse-mode autograd of the definition."""
+    o = torch.tensor(np.asarray(opacity, np.float64)).requires_grad_(True)
+    s = torch.tensor(np.asarray(scales, np.float64)).requires_grad_(True)
+    q = torch.tensor(np.asarray(quats, np.float64)).requires_grad_(True)
+    lam = torch.linalg.eigvalsh(_sigma(s, q)).clamp_min(0.0)
+    R = eps_o * o.abs().sum() + eps_s * lam.sqrt().sum()
+    R.backward()
+    return float(R), o.grad.numpy().copy(), s.grad.numpy().copy(), q.grad.numpy().copy()

@@ -283,6 +283,17 @@ int sss_loss(const float* image, const float* target, const sss_camera_t* cams, 
   return hip_ok(hipGetLastError(), "sss_loss launch") ? SSS_OK : SSS_ERR_HIP;
 }
 
+int sss_regularise(const float* opacity, const float* scales, int64_t n, float eps_opacity, float eps_sigma,
+                   float* d_opacity, float* d_scales, float* loss_out, void* stream) {
+  if (!opacity || !scales || n <= 0 || n > (int64_t)0x7FFFFFFF * kBlock || !(eps_opacity >= 0.0f) ||
+      !(eps_sigma >= 0.0f)) {
+    set_error("sss_regularise: null array, n <= 0 or a negative weight");
+    return SSS_ERR_INVALID;
+  }
+  launch_regularise(opacity, scales, n, eps_opacity, eps_sigma, d_opacity, d_scales, loss_out, (hipStream_t)stream);
+  return hip_ok(hipGetLastError(), "sss_regularise launch") ? SSS_OK : SSS_ERR_HIP;
+}
+
 size_t sss_relocate_workspace(int64_t n, float max_fraction) {
   if (n < 1 || !(max_fraction >= 0.0f && max_fraction <= 1.0f)) return 0;
   return relocate_workspace(n, (double)max_fraction);

@@ -90,7 +90,43 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(float* __restrict__ p, con
   p[i] = fminf(fmaxf(p[i] - upd, lo), hi);
 }
 
+// Regularisers of the Sec. 3.4 loss: eps_o sum_i |o_i| + eps_s sum_ij sqrt(lambda_ij)
+// with lambda_ij the eigenvalues of Sigma_i = R S S^T R^T, i.e. |s_ij| (R is
+// orthogonal).  Adds the (sub)gradient sign(x) eps to the opacity and scale
+// gradients and accumulates the value.  HBM-bound: 16 B read, 16 B read +
+// written per component.
+__global__ __launch_bounds__(kBlock) void regularise_kernel(const float* __restrict__ opac,
+                                                            const float* __restrict__ scales, int64_t n, float eps_o,
+                                                            float eps_s, float* __restrict__ d_opac,
+                                                            float* __restrict__ d_scales, float* __restrict__ loss_out) {
+  __shared__ float red[kBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  float acc = 0.0f;
+  if (i < n) {
+    const float o = opac[i];
+    acc = eps_o * fabsf(o);
+    if (d_opac) d_opac[i] += o > 0.0f ? eps_o : (o < 0.0f ? -eps_o : 0.0f);
+    for (int a = 0; a < 3; ++a) {
+      const float s = scales[3 * i + a];
+      acc += eps_s * fabsf(s);
+      if (d_scales) d_scales[3 * i + a] += s > 0.0f ? eps_s : (s < 0.0f ? -eps_s : 0.0f);
+    }
+  }
+  if (loss_out) {
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss_out, red[0] + red[1] + red[2] + red[3]);
+  }
+}
+
 }  // namespace
+
+void launch_regularise(const float* opac, const float* scales, int64_t n, float eps_o, float eps_s, float* d_opac,
+                       float* d_scales, float* loss_out, hipStream_t st) {
+  SSS_LAUNCH("regularise", regularise_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, opac,
+             scales, n, eps_o, eps_s, d_opac, d_scales, loss_out);
+}
 
 void launch_sghmc(float* means, float* mom, const float* g, const float* opac, const float* scales,
                   const float* quats, int64_t n, const sss_sghmc_opts_t& o, hipStream_t st) {

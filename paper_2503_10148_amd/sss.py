@@ -128,6 +128,8 @@ def lib():
         L.sss_loss_workspace.argtypes = [i64]
         L.sss_loss.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, ctypes.c_size_t, vp]
         L.sss_loss.restype = i32
+        L.sss_regularise.argtypes = [vp, vp, i64, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
+        L.sss_regularise.restype = i32
         L.sss_relocate_workspace.restype = ctypes.c_size_t
         L.sss_relocate_workspace.argtypes = [i64, ctypes.c_float]
         L.sss_relocate.argtypes = [vp, vp, i32, vp, vp, ctypes.c_size_t, vp, vp]
@@ -424,3 +426,14 @@ def loss(image, target, cams, lambda_dssim=0.2, dl_dimage=None, loss_out=None, w
     _check(lib().sss_loss(_ptr(image), _ptr(target), camera_array(cams), len(cams), lambda_dssim, _ptr(dl_dimage),
                           _ptr(loss_out), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)), "sss_loss")
     return dl_dimage
+
+
+def regularise(opacity, scales, eps_opacity, eps_sigma, d_opacity=None, d_scales=None, loss_out=None, stream=None):
+    """eps_o sum |o| + eps_sigma sum sqrt(eig Sigma) (= sum |s|): adds the
+    gradients into d_opacity / d_scales and the value into loss_out (each
+    optional, device tensors)."""
+    _need(opacity, torch.float32, "opacity")
+    _need(scales, torch.float32, "scales")
+    n = opacity.shape[0]
+    _check(lib().sss_regularise(_ptr(opacity), _ptr(scales), n, eps_opacity, eps_sigma, _ptr(d_opacity),
+                                _ptr(d_scales), _ptr(loss_out), _stream(stream)), "sss_regularise")

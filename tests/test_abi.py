@@ -148,6 +148,15 @@ def test_sghmc_rejects_bad_arguments(sss):
     assert L.sss_sghmc_step(v, v, v, v, None, None, 10, ctypes.byref(o), ctypes.byref(ad), None) == sss.ERR_INVALID
 
 
+def test_regularise_rejects_bad_arguments(sss):
+    L = sss.lib()
+    v = ctypes.c_void_p(0x1000)
+    assert L.sss_regularise(None, v, 10, 0.1, 0.1, None, None, None, None) == sss.ERR_INVALID
+    assert L.sss_regularise(v, v, 0, 0.1, 0.1, None, None, None, None) == sss.ERR_INVALID
+    assert L.sss_regularise(v, v, 10, -0.1, 0.1, None, None, None, None) == sss.ERR_INVALID
+    assert L.sss_regularise(v, v, 10, 0.1, float("nan"), None, None, None, None) == sss.ERR_INVALID
+
+
 def test_records_layout_matches_decoder():
     from tests._util import REC_DTYPE
     assert REC_DTYPE.itemsize == 64

@@ -42,3 +42,24 @@ def test_loss_matches_oracle_multiview(sss, lam):
     got = dl.cpu().numpy()
     scale = np.sqrt(np.mean(want ** 2))
     assert np.all(np.abs(got - want) <= 1e-3 * np.maximum(np.abs(want), scale))
+
+
+@pytest.mark.parametrize("n", [1, 1000, 300001])
+def test_regulariser_matches_oracle(sss, n):
+    rng = np.random.default_rng(n)
+    o = rng.uniform(-1, 1, n).astype(np.float32)
+    o[: min(n, 7)] = 0.0                                       # sign(0) = 0
+    s = np.exp(rng.uniform(-6, 0, (n, 3))).astype(np.float32)
+    q = rng.standard_normal((n, 4)).astype(np.float32)
+    v, go, gs, _ = oloss.regulariser(o, s, q, 0.01, 0.25)
+    base_o = rng.standard_normal(n).astype(np.float32)
+    base_s = rng.standard_normal((n, 3)).astype(np.float32)
+    d_o = torch.as_tensor(base_o, device="cuda")
+    d_s = torch.as_tensor(base_s, device="cuda")
+    out = torch.zeros(1, device="cuda")
+    sss.regularise(torch.as_tensor(o, device="cuda"), torch.as_tensor(s, device="cuda"), 0.01, 0.25,
+                   d_opacity=d_o, d_scales=d_s, loss_out=out)
+    torch.cuda.synchronize()
+    assert out.item() == pytest.approx(v, rel=1e-5)
+    assert np.allclose(d_o.cpu().numpy(), base_o + go, rtol=1e-6, atol=1e-7)
+    assert np.allclose(d_s.cpu().numpy(), base_s + gs, rtol=1e-6, atol=1e-7)

@@ -619,3 +619,26 @@ def test_loss_gradient_matches_finite_differences():
         m[y, x, c] -= h
         fd = (loss.loss_and_grad(p, tgt, 0.2)[0] - loss.loss_and_grad(m, tgt, 0.2)[0]) / (2 * h)
         assert g[y, x, c] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# regularisers (Sec. 3.4 loss, last two terms)
+# ---------------------------------------------------------------------------
+def test_regulariser_sqrt_eigenvalues_are_the_scales():
+    """Sigma = R S S^T R^T with R orthogonal: sqrt(eig Sigma) = |s| (closed
+    form), the value does not depend on the rotation, and the gradient is
+    eps sign(x) on o and s and zero on the quaternion."""
+    from oracle import loss
+    rng = np.random.default_rng(3)
+    n = 50
+    o = rng.uniform(-1, 1, n)
+    s = np.exp(rng.uniform(-5, 0, (n, 3)))
+    s[0] = [0.02, 0.02, 0.02]                       # repeated eigenvalues
+    q = rng.standard_normal((n, 4))
+    v, go, gs, gq = loss.regulariser(o, s, q, 0.01, 0.3)
+    assert v == pytest.approx(0.01 * np.abs(o).sum() + 0.3 * np.abs(s).sum(), rel=1e-12)
+    assert np.allclose(go, 0.01 * np.sign(o), atol=1e-14)
+    assert np.allclose(gs, 0.3, rtol=1e-8)
+    assert np.abs(gq).max() < 1e-8
+    v2 = loss.regulariser(o, s, rng.standard_normal((n, 4)), 0.01, 0.3)[0]
+    assert v2 == pytest.approx(v, rel=1e-12)
