@@ -114,13 +114,25 @@ typedef struct {
  *   family    SSS_FAMILY_STUDENT_T; SSS_FAMILY_GAUSSIAN renders every component
  *                    with the Gaussian kernel exp(-h/2) (the nu -> infinity limit,
  *                    Sec. 3.2; the paper's SGHMC-with-Gaussians ablation), nu
- *                    is ignored and gets no gradient */
+ *                    is ignored and gets no gradient
+ *   trunc_mode SSS_TRUNC_ALPHA: a component's tile rectangle bounds its alpha
+ *                    level set h <= h* (lossless: outside it every pixel
+ *                    fails the alpha test).  SSS_TRUNC_COVERAGE: the paper's
+ *                    truncation by a t critical value (Sec. 3.2, SM
+ *                    "Implementation Details"), read as the ellipse h <= q
+ *                    holding the probability mass of the Gaussian 3-sigma
+ *                    ellipse, 1 - exp(-9/2): P(h <= q) = 1 - (1 + q/nu)^(-nu/2)
+ *                    gives q = nu (exp(9/nu) - 1) (9 for the Gaussian
+ *                    family); the rectangle bounds h <= min(q, h*), so heavy
+ *                    tails (small nu) are unchanged and light ones are cut. */
 enum { SSS_FAMILY_STUDENT_T = 0, SSS_FAMILY_GAUSSIAN = 1 };
+enum { SSS_TRUNC_ALPHA = 0, SSS_TRUNC_COVERAGE = 1 };
 
 typedef struct {
   float alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass;
   float bg[3];
   int32_t family;
+  int32_t trunc_mode;
 } sss_render_opts_t;
 
 void sss_default_render_opts(sss_render_opts_t* opts);
@@ -132,7 +144,8 @@ void sss_default_render_opts(sss_render_opts_t* opts);
  * approximation; x/z and y/z clamped to 1.3 half-fov for J), its inverse
  * (the conic), colour from SH, clamped nu, and the truncation rectangle: the
  * tiles touched by the axis-aligned box of the ellipse h <= h* with
- * h* = nu ((|o|/alpha_min)^(2/(nu+2)) - 1), outside of which |o T2D| < alpha_min.
+ * h* = nu ((|o|/alpha_min)^(2/(nu+2)) - 1), outside of which |o T2D| < alpha_min
+ * (SSS_TRUNC_COVERAGE: the box of h <= min(q, h*), see sss_render_opts_t).
  * Depth key = bits of the FP32 depth fmaf(W20, x, fmaf(W21, y, fmaf(W22, z, t2))).
  * Culled (tiles_touched = 0): depth key <= z_near, |o| < alpha_min, degenerate
  * 2D covariance, or a rectangle entirely off screen.

@@ -96,7 +96,7 @@ def window_camera(cam, x0, y0, w, h):
 
 
 DEFAULT_OPTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, z_near=0.2, nu_min=1.0,
-                    nu_max=1e4, lowpass=0.0, bg=(0.0, 0.0, 0.0), family="student_t")
+                    nu_max=1e4, lowpass=0.0, bg=(0.0, 0.0, 0.0), family="student_t", trunc_mode=0)
 
 
 def opts_array(opts=None) -> np.ndarray:
@@ -107,7 +107,9 @@ def opts_array(opts=None) -> np.ndarray:
             o["lowpass"], *o["bg"]]
     fam = {"student_t": 0, "gaussian": 1}.get(o["family"], o["family"]) if isinstance(o["family"], str) \
         else int(o["family"])
-    return np.concatenate([np.asarray(vals, dtype=np.float32).astype(np.float64), [float(fam)]])
+    tm = {"alpha": 0, "coverage": 1}.get(o["trunc_mode"], o["trunc_mode"]) if isinstance(o["trunc_mode"], str) \
+        else int(o["trunc_mode"])
+    return np.concatenate([np.asarray(vals, dtype=np.float32).astype(np.float64), [float(fam), float(tm)]])
 
 
 def tiles(cam):

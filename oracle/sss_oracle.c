@@ -41,9 +41,12 @@
  *              clamp_width, clamp_height (the image size whose half field of
  *              view bounds the EWA Jacobian; equal to width, height except
  *              for a window cut out of a larger image)
- *   opts[11] = alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass,
+ *   opts[12] = alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass,
  *              bg_r, bg_g, bg_b, family (0 Student's t, 1 Gaussian: the
- *              nu -> infinity limit exp(-h/2) of Sec. 3.2)
+ *              nu -> infinity limit exp(-h/2) of Sec. 3.2), trunc_mode (0: the
+ *              rectangle bounds the alpha level set; 1: it bounds the smaller
+ *              of that set and the ellipse holding the same probability mass
+ *              as the Gaussian 3-sigma ellipse)
  */
 #include <math.h>
 #include <stdint.h>
@@ -316,7 +319,17 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
     double hs;
     if (alpha_min > 0.0) {
       hs = opts[10] == 1.0 ? 2.0 * log(fabs(o) / alpha_min) : nuc * expm1(2.0 / (nuc + 2.0) * log(fabs(o) / alpha_min));
-      const double ex = sqrt(hs * A), ey = sqrt(hs * D);
+      /* coverage rule (Sec. 3.2 truncation by a critical value): h of a 2D t
+         variable has P(h <= q) = 1 - (1 + q/nu)^(-nu/2); the Gaussian 3-sigma
+         ellipse holds 1 - exp(-9/2), reached at q = nu (exp(9/nu) - 1)
+         (q = 9 for the Gaussian).  Beyond h* nothing is drawn anyway, so the
+         rectangle uses the smaller of the two. */
+      double hr = hs;
+      if (opts[11] == 1.0) {
+        const double q = opts[10] == 1.0 ? 9.0 : nuc * expm1(9.0 / nuc);
+        if (q < hr) hr = q;
+      }
+      const double ex = sqrt(hr * A), ey = sqrt(hr * D);
       const double lx = (mx - ex) / ORC_TILE, hx = (mx + ex) / ORC_TILE;
       const double ly = (my - ey) / ORC_TILE, hy = (my + ey) / ORC_TILE;
       if (hx < 0.0 || lx >= tx_n || hy < 0.0 || ly >= ty_n) continue;   /* off-screen */

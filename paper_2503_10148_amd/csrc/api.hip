@@ -71,6 +71,7 @@ OptsDev make_opts(const sss_render_opts_t* o) {
   r.nu_min = o->nu_min; r.nu_max = o->nu_max; r.lowpass = o->lowpass;
   r.bg[0] = o->bg[0]; r.bg[1] = o->bg[1]; r.bg[2] = o->bg[2];
   r.family = o->family;
+  r.trunc_mode = o->trunc_mode;
   return r;
 }
 
@@ -88,9 +89,10 @@ static int check_opts(const sss_render_opts_t* o, const char* fn) {
   if (!o) return SSS_OK;
   if (!(o->alpha_min >= 0.0f) || !(o->alpha_max > 0.0f) || !(o->t_min >= 0.0f) || !(o->nu_min >= 1.0f) ||
       !(o->nu_max >= o->nu_min) || !(o->lowpass >= 0.0f) ||
-      (o->family != SSS_FAMILY_STUDENT_T && o->family != SSS_FAMILY_GAUSSIAN)) {
+      (o->family != SSS_FAMILY_STUDENT_T && o->family != SSS_FAMILY_GAUSSIAN) ||
+      (o->trunc_mode != SSS_TRUNC_ALPHA && o->trunc_mode != SSS_TRUNC_COVERAGE)) {
     set_error("%s: options out of range (alpha_min >= 0, alpha_max > 0, t_min >= 0, 1 <= nu_min <= nu_max, "
-              "lowpass >= 0, known family)", fn);
+              "lowpass >= 0, known family and truncation mode)", fn);
     return SSS_ERR_INVALID;
   }
   return SSS_OK;
@@ -119,6 +121,7 @@ void sss_default_render_opts(sss_render_opts_t* o) {
   o->lowpass = 0.0f;
   o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
   o->family = SSS_FAMILY_STUDENT_T;
+  o->trunc_mode = SSS_TRUNC_ALPHA;
 }
 
 const char* sss_last_error(void) { return g_err; }

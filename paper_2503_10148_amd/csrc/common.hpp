@@ -31,7 +31,7 @@ struct CamBatch {
 struct OptsDev {
   float alpha_min, alpha_max, t_min, z_near, nu_min, nu_max, lowpass;
   float bg[3];
-  int32_t family;
+  int32_t family, trunc_mode;
 };
 
 // Projected record of one (view, component) entry, 64 bytes.

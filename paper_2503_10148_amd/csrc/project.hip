@@ -239,10 +239,13 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     // alpha level set |o| T2D(h*) = alpha_min
     const double lr = log(fabs((double)o) / (double)op.alpha_min);
     hs = gauss ? 2.0 * lr : nuc * expm1(2.0 / (nuc + 2.0) * lr);
-    const double ex = sqrt(hs * g.A);
-    ey = sqrt(hs * g.D);
-    const double lx = (mx - ex) * (1.0 / kTile), hx = (mx + ex) * (1.0 / kTile);
-    const double ly = (my - ey) * (1.0 / kTile), hy = (my + ey) * (1.0 / kTile);
+    ey = sqrt(hs * g.D);   // row extent of the pixels that can pass the alpha test
+    // coverage rule: the ellipse with the Gaussian 3-sigma probability mass,
+    // P(h <= q) = 1 - (1 + q/nu)^(-nu/2) = 1 - exp(-9/2); never beyond h*
+    const double hr = op.trunc_mode == SSS_TRUNC_COVERAGE ? fmin(hs, gauss ? 9.0 : nuc * expm1(9.0 / nuc)) : hs;
+    const double erx = sqrt(hr * g.A), ery = sqrt(hr * g.D);
+    const double lx = (mx - erx) * (1.0 / kTile), hx = (mx + erx) * (1.0 / kTile);
+    const double ly = (my - ery) * (1.0 / kTile), hy = (my + ery) * (1.0 / kTile);
     if (hx < 0.0 || lx >= c.tiles_x || hy < 0.0 || ly >= c.tiles_y) return;
     x0 = (int)fmax(0.0, floor(lx)); x1 = (int)fmin((double)(c.tiles_x - 1), floor(hx));
     y0 = (int)fmax(0.0, floor(ly)); y1 = (int)fmin((double)(c.tiles_y - 1), floor(hy));

@@ -48,7 +48,8 @@ class Camera(ctypes.Structure):
 class RenderOpts(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
                 ("z_near", ctypes.c_float), ("nu_min", ctypes.c_float), ("nu_max", ctypes.c_float),
-                ("lowpass", ctypes.c_float), ("bg", ctypes.c_float * 3), ("family", ctypes.c_int32)]
+                ("lowpass", ctypes.c_float), ("bg", ctypes.c_float * 3), ("family", ctypes.c_int32),
+                ("trunc_mode", ctypes.c_int32)]
 
 
 class Proj(ctypes.Structure):
@@ -191,6 +192,8 @@ def render_opts(opts=None):
             o.bg[:] = [float(x) for x in v]
         elif k == "family":
             o.family = {"student_t": 0, "gaussian": 1}.get(v, v) if isinstance(v, str) else int(v)
+        elif k == "trunc_mode":
+            o.trunc_mode = {"alpha": 0, "coverage": 1}.get(v, v) if isinstance(v, str) else int(v)
         else:
             setattr(o, k, float(v))
     return o

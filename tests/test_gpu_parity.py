@@ -435,3 +435,34 @@ def test_gaussian_family_matches_oracle(sss, name):
     for k in PARAMS:
         ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=keep)
         assert ok, (k, worst)
+
+
+@pytest.mark.parametrize("family", ["student_t", "gaussian"])
+def test_coverage_truncation_matches_oracle(sss, family):
+    """trunc_mode coverage: rectangles and tile lists bit-exact, image and
+    gradients at the usual tolerance, on clustered components with nu up to
+    150 (light tails are cut)."""
+    scene, cams = _case("clusters")
+    scene = dict(scene)
+    scene["scales"] = scene["scales"] * np.float32(2.5)
+    cam = cams[0]
+    opts = dict(trunc_mode="coverage", family=family)
+    ref = oracle.render(scene, cam, opts)
+    full = oracle.project(scene, cam, dict(family=family))
+    assert ref["proj"]["touched"].sum() < full["touched"].sum()      # the rule cut something
+    dev, proj, bins, img, _, ncon = gpu_forward(sss, scene, cams, opts)
+    ok = ref["proj"]["pflags"] == 0
+    vis = ok & (ref["proj"]["touched"] > 0)
+    assert np.array_equal(proj.touched.cpu().numpy()[ok], ref["proj"]["touched"][ok])
+    assert np.array_equal(proj.rect.cpu().numpy().astype(np.int64).reshape(-1, 4)[vis], ref["proj"]["rect"][vis])
+    bad, _, _ = _image_check(img.cpu().numpy(), ref, ref["xflags"])
+    assert not bad.any()
+    w = np.random.default_rng(9).standard_normal(ref["image"].shape)
+    w[ref["xflags"] != 0] = 0.0
+    gref = oracle.render_backward(scene, cam, w, opts, fwd=ref)
+    g = sss.render_bwd(dev, proj, bins, cams, torch.as_tensor(w.reshape(-1, 3), dtype=torch.float32, device="cuda"),
+                       opts, image=img, n_contrib=ncon)
+    torch.cuda.synchronize()
+    for k in PARAMS:
+        good, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=ok)
+        assert good, (k, worst)

@@ -642,3 +642,72 @@ def test_regulariser_sqrt_eigenvalues_are_the_scales():
     assert np.abs(gq).max() < 1e-8
     v2 = loss.regulariser(o, s, rng.standard_normal((n, 4)), 0.01, 0.3)[0]
     assert v2 == pytest.approx(v, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# coverage truncation (trunc_mode 1)
+# ---------------------------------------------------------------------------
+def _coverage_q(nu, gaussian=False):
+    """The h whose ellipse holds 1 - exp(-9/2) of the 2D t (or Gaussian)
+    density, by quadrature of the radial profile and root finding."""
+    from scipy import integrate, optimize
+    prof = (lambda r: math.exp(-r * r / 2)) if gaussian else (lambda r: (1 + r * r / nu) ** (-(nu + 2) / 2))
+    total = integrate.quad(lambda r: prof(r) * r, 0, np.inf, epsabs=0, epsrel=1e-13, limit=500)[0]
+    target = 1 - math.exp(-4.5)
+    f = lambda q: integrate.quad(lambda r: prof(r) * r, 0, math.sqrt(q), epsabs=0, epsrel=1e-13,
+                                 limit=500)[0] / total - target
+    return optimize.brentq(f, 1e-6, 1e7, xtol=1e-12, rtol=1e-14)
+
+
+@pytest.mark.parametrize("nu,family,cut", [(2.0, "student_t", False), (50.0, "student_t", True),
+                                           (400.0, "student_t", True), (5.0, "gaussian", True)])
+def test_coverage_rectangle_bounds_the_3sigma_mass_ellipse(oracle_lib, nu, family, cut):
+    """Isotropic component on the optical axis (Sigma2D = sigma^2 I): the
+    coverage rectangle is the tile box of radius sigma sqrt(min(q, h*)) with q
+    from the probability-mass condition."""
+    W = H = 1024
+    cam = axis_camera(W, H)
+    sc = 0.5
+    s = one_component(scale=(sc, sc, sc), nu=nu, opacity=0.9, quat=(0.6, 0.2, -0.1, 0.3))
+    p_alpha = oracle_lib.project(s, cam, dict(family=family))
+    p_cov = oracle_lib.project(s, cam, dict(family=family, trunc_mode="coverage"))
+    sigma = cam["fx"] * np.float64(np.float32(sc)) / 4.0
+    q = _coverage_q(np.float64(np.float32(nu)), gaussian=(family == "gaussian"))
+    hs = p_alpha["hstar"][0]
+    assert p_cov["hstar"][0] == hs                               # the alpha test is unchanged
+    m = p_cov["mean2d"][0]
+
+    def box(h):
+        e = sigma * math.sqrt(h)
+        lo = [max(0, math.floor((m[k] - e) / 16)) for k in (0, 1)]
+        hi = [min(W // 16 - 1, math.floor((m[k] + e) / 16)) for k in (0, 1)]
+        return [lo[0], lo[1], hi[0], hi[1]]
+
+    assert list(p_cov["rect"][0]) == box(min(q, hs))
+    assert list(p_alpha["rect"][0]) == box(hs)
+    assert (q < hs) == cut
+    assert (p_cov["touched"][0] < p_alpha["touched"][0]) == cut
+
+
+def test_coverage_mode_keeps_heavy_tails_and_cuts_light_ones(oracle_lib):
+    """q(nu) >= h* for every |o| <= 1 when nu <= 8, so the image is unchanged;
+    for light tails the dropped tiles show only the background."""
+    heavy = scenes.make_scene(400, 1, seed=5, neg_frac=0.2)
+    heavy["nu"] = np.random.default_rng(0).uniform(1, 8, 400).astype(np.float32)
+    cam = scenes.ring_camera(200, 150)
+    a = oracle_lib.render(heavy, cam)
+    b = oracle_lib.render(heavy, cam, dict(trunc_mode="coverage"))
+    assert np.array_equal(a["image"], b["image"])
+    assert np.array_equal(a["proj"]["rect"], b["proj"]["rect"])
+    W = H = 256
+    cam = axis_camera(W, H)
+    s = one_component(scale=(0.36, 0.36, 0.36), nu=5e3, opacity=0.95, colour=(1.0, 1.0, 1.0))
+    bg = (0.2, 0.3, 0.4)
+    full = oracle_lib.render(s, cam, dict(bg=bg))
+    cut = oracle_lib.render(s, cam, dict(bg=bg, trunc_mode="coverage"))
+    x0, y0, x1, y1 = cut["proj"]["rect"][0]
+    inside = np.zeros((H, W), bool)
+    inside[16 * y0:16 * (y1 + 1), 16 * x0:16 * (x1 + 1)] = True
+    assert np.array_equal(cut["image"][inside], full["image"][inside])
+    assert np.all(cut["image"][~inside] == np.float64(np.float32(bg)))
+    assert (full["image"][~inside] != np.float64(np.float32(bg))).any()
