@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define SSS_VERSION 100
+#define SSS_VERSION 101
 #define SSS_TILE 16           /* tile edge in pixels                            */
 #define SSS_MAX_VIEWS 16      /* views per call                                 */
 #define SSS_RECORD_BYTES 64   /* size of one projected record                  */
@@ -181,6 +181,10 @@ int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
  *   tile_start     [n_tiles + 1] pairs of global tile t are
  *                  pair_rank[tile_start[t] .. tile_start[t+1])
  *   pair_rank      [pair_capacity] ranks, ascending within each tile
+ *   rank_offset    [n_entries] (nullable) first pair of rank r in emission
+ *                  order: rank r emitted its rectangle's tiles row-major at
+ *                  positions rank_offset[r] + k, k < tiles_touched.  Needed
+ *                  by the deterministic backward pass.
  * Host outputs: n_visible, n_pairs (always written when the call returns
  * SSS_OK or SSS_ERR_CAPACITY).
  * Workspace: ws of ws_bytes >= sss_bin_sort_workspace(n_entries, pair_capacity).
@@ -192,6 +196,7 @@ typedef struct {
   void* sorted_records;
   uint32_t* tile_start;
   uint32_t* pair_rank;
+  uint32_t* rank_offset;
   int64_t pair_capacity;
   int64_t n_visible;   /* out */
   int64_t n_pairs;     /* out */
@@ -227,6 +232,15 @@ int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views
  *   mode SSS_BWD_RECOMPUTE  recomputes the forward pass per tile (image,
  *                           t_final, n_contrib ignored; image_out, if not
  *                           NULL, receives the forward image)
+ *   | SSS_BWD_DETERMINISTIC (flag OR-ed into either mode): no float
+ *                           atomics; each (tile, component) pair's per-tile
+ *                           sums go to their own slot, then every entry sums
+ *                           its slots in emission order, so gradients and
+ *                           loss_out are bit-identical run to run.  Needs
+ *                           bins->order and bins->rank_offset, proj->rect
+ *                           and the larger workspace
+ *                           sss_render_bwd_workspace_det(n_entries,
+ *                           bins->n_pairs, n_tiles).
  *   loss SSS_LOSS_GRAD      dl_or_target = dL/dimage [P][3]
  *   loss SSS_LOSS_L1        dl_or_target = target [P][3]; L = mean |image - target|
  *                           over all 3P values; loss_out (device float,
@@ -234,10 +248,11 @@ int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views
  * grads: += or = (see sss_grads_t).  Workspace: ws_bytes >=
  * sss_render_bwd_workspace(n_views*n) (per-entry screen-space gradients).
  * Errors: INVALID for NULL pointers, a short workspace, unknown mode/loss. */
-enum { SSS_BWD_STORED = 0, SSS_BWD_RECOMPUTE = 1 };
+enum { SSS_BWD_STORED = 0, SSS_BWD_RECOMPUTE = 1, SSS_BWD_DETERMINISTIC = 4 };
 enum { SSS_LOSS_GRAD = 0, SSS_LOSS_L1 = 1 };
 
 size_t sss_render_bwd_workspace(int64_t n_entries);
+size_t sss_render_bwd_workspace_det(int64_t n_entries, int64_t n_pairs, int64_t n_tiles);
 
 int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
                    const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts,

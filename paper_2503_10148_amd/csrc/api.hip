@@ -202,6 +202,8 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
   if ((rc = check_opts(opts, "sss_render_bwd"))) return rc;
   CamBatch cb;
   if ((rc = make_cam_batch(cams, n_views, &cb))) return rc;
+  const bool det = (mode & SSS_BWD_DETERMINISTIC) != 0;
+  mode &= ~SSS_BWD_DETERMINISTIC;
   if (mode != SSS_BWD_STORED && mode != SSS_BWD_RECOMPUTE) {
     set_error("sss_render_bwd: unknown mode %d", mode);
     return SSS_ERR_INVALID;
@@ -220,18 +222,38 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
     return SSS_ERR_INVALID;
   }
   const int64_t n_entries = scene->n * n_views;
-  if (ws_bytes < sss_render_bwd_workspace(n_entries)) {
-    set_error("sss_render_bwd: workspace of %zu bytes, %zu needed", ws_bytes, sss_render_bwd_workspace(n_entries));
+  if (det && (!bins->order || !bins->rank_offset || !proj->rect || bins->n_pairs < 0 ||
+              bins->n_visible < 0 || bins->n_visible > n_entries)) {
+    set_error("sss_render_bwd: the deterministic mode needs bins->order, bins->rank_offset, proj->rect and the "
+              "counts of the sss_bin_sort call");
+    return SSS_ERR_INVALID;
+  }
+  const size_t need = det ? render_bwd_det_workspace(n_entries, bins->n_pairs, cb.total_tiles)
+                          : sss_render_bwd_workspace(n_entries);
+  if (ws_bytes < need) {
+    set_error("sss_render_bwd: workspace of %zu bytes, %zu needed", ws_bytes, need);
     return SSS_ERR_INVALID;
   }
   hipStream_t st = (hipStream_t)stream;
   const OptsDev op = make_opts(opts);
   float* g2 = (float*)ws;
+  DetArgs da{};
+  if (det) {
+    da = carve_det(ws, n_entries, bins->n_pairs, cb.total_tiles, &g2);
+    da.order = bins->order;
+    da.rank_off = bins->rank_offset;
+    da.rects = (const ushort4*)proj->rect;
+  }
   launch_zero(g2, n_entries * kG2, st);
   launch_render_bwd(cb, op, *bins, mode, loss, dl_or_target, image, n_contrib, image_out, loss_out, g2,
-                    total_pixels(cb), st);
+                    total_pixels(cb), det ? &da : nullptr, scene->n, st);
   launch_project_bwd(cb, op, *scene, proj->tiles_touched, g2, *grads, st);
   return hip_ok(hipGetLastError(), "sss_render_bwd launch") ? SSS_OK : SSS_ERR_HIP;
+}
+
+size_t sss_render_bwd_workspace_det(int64_t n_entries, int64_t n_pairs, int64_t n_tiles) {
+  if (n_entries < 0 || n_pairs < 0 || n_tiles < 0) return 0;
+  return render_bwd_det_workspace(n_entries, n_pairs, n_tiles);
 }
 
 int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const float* opacity,

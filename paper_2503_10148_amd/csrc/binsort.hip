@@ -340,9 +340,11 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
     const unsigned gv = (unsigned)((n_vis + kBlock - 1) / kBlock);
     SSS_LAUNCH("touched_by_rank", touched_by_rank_kernel, dim3(gv), dim3(kBlock), 0, st, bins->order, proj.tiles_touched,
                        n_vis, w.flags);
-    scan_excl(w.flags, w.pos, n_vis, w.scan, st);
+    // the caller may keep the offsets (deterministic backward pass)
+    uint32_t* offs = bins->rank_offset ? bins->rank_offset : w.pos;
+    scan_excl(w.flags, offs, n_vis, w.scan, st);
     SSS_LAUNCH("emit", emit_kernel, dim3(gv), dim3(kBlock), 0, st, cb, n, bins->order,
-                       (const ushort4*)proj.rect, w.pos, n_vis, (uint32_t)m, (const uint4*)proj.records,
+                       (const ushort4*)proj.rect, offs, n_vis, (uint32_t)m, (const uint4*)proj.records,
                        (uint4*)bins->sorted_records, w.ka, w.va);
   }
   // 4. stable sort of the pairs by tile

@@ -89,10 +89,21 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
 size_t bin_sort_workspace(int64_t n_entries, int64_t pair_capacity);
 void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b,
                        float* image, float* t_final, uint32_t* n_contrib, hipStream_t st);
+// Buffers of the deterministic backward pass (see raster.hip).
+struct DetArgs {
+  const uint32_t* order;      // rank -> entry
+  const uint32_t* rank_off;   // first emission position of each rank
+  const ushort4* rects;       // per-entry tile rectangles
+  float* part;                // [n_pairs][kG2] per-pair sums
+  uint32_t* lastp1;           // [n_tiles] last visited rank + 1
+  float* loss_part;           // [n_tiles] per-tile loss
+};
+size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_tiles);
+DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, float** g2);
 void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, int mode,
                        int loss, const float* dl_or_target, const float* image,
                        const uint32_t* n_contrib, float* image_out, float* loss_out, float* g2,
-                       int64_t total_pixels, hipStream_t st);
+                       int64_t total_pixels, const DetArgs* det, int64_t n, hipStream_t st);
 void launch_zero(float* p, int64_t count, hipStream_t st);
 size_t relocate_workspace(int64_t n, double max_fraction);
 size_t loss_workspace(int64_t total_pixels);

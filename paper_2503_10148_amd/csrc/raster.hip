@@ -15,6 +15,13 @@
 // T.  The per-pixel gradients of each record are summed over the wave with
 // DPP row shifts / broadcasts, and lane 63 adds them to the entry's
 // screen-space gradient slot with hardware float atomics.
+//
+// Deterministic variant: instead of the atomics, lane 63 stores the sums of
+// each (tile, component) pair in the pair's own slot, addressed by the pair's
+// position in emission order (the component's rank offset plus the tile's
+// row-major index in its rectangle).  A second kernel then adds, for every
+// component, its slots in emission order with a fixed reduction tree, so the
+// result does not depend on scheduling.
 #include <stdlib.h>
 
 #include "common.hpp"
@@ -32,10 +39,11 @@ struct __align__(16) LRec {
   float nb, cr, cg, cb;      // -(nu+2)/2; colour
   float pad0, ey;            // -; half extent in y of the pre-test ellipse
   uint32_t entry;
-  float pad1;
+  uint32_t slot;             // deterministic backward: the pair's emission position
 };
 
-__device__ __forceinline__ void stage(const Rec* __restrict__ srec, uint32_t rank, double ox, double oy, LRec* dst) {
+__device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, double ox, double oy,
+                                          LRec* dst) {
   const Rec r = srec[rank];
   LRec l;
   l.mx = (float)(r.mx - ox);
@@ -51,8 +59,9 @@ __device__ __forceinline__ void stage(const Rec* __restrict__ srec, uint32_t ran
   // sqrt(1.0001) covers the widened pre-test level, the rest FP32 rounding
   l.ey = r.ey * 1.0001f + 1e-3f;
   l.entry = r.entry;
-  l.pad1 = 0.0f;
+  l.slot = 0u;
   *dst = l;
+  return r.entry;
 }
 
 // Evaluation of one record at one pixel, shared bit-for-bit by the forward
@@ -115,7 +124,7 @@ __device__ __forceinline__ float wave_sum63(float v) {
 // t/16 + k*(256/PIX)/16, k < PIX.
 template <int PIX>
 struct TileCtx {
-  int view;
+  int view, tx, ty;
   uint32_t start, end;
   double ox, oy;
   float px;
@@ -137,6 +146,8 @@ __device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint3
   const int lt = g - c.tile_offset;
   const int tx = lt % c.tiles_x, ty = lt / c.tiles_x;
   t.view = v;
+  t.tx = tx;
+  t.ty = ty;
   const int lx = threadIdx.x & (kTile - 1), ly0 = threadIdx.x / kTile;
   const int x = tx * kTile + lx;
   t.px = (float)lx + 0.5f;
@@ -171,6 +182,24 @@ __device__ __forceinline__ void stage_batch(const TileCtx<PIX>& t, const Rec* __
                                             LRec* lds) {
   const uint32_t k = base + threadIdx.x;
   if (k < stop) stage(srec, pair_rank[k], t.ox, t.oy, lds + threadIdx.x);
+}
+
+// The same, also recording each pair's emission position (rank offset plus
+// the tile's row-major index inside the component's rectangle).
+template <int PIX>
+__device__ __forceinline__ void stage_batch_slot(const TileCtx<PIX>& t, const Rec* __restrict__ srec,
+                                                 const uint32_t* __restrict__ pair_rank,
+                                                 const uint32_t* __restrict__ rank_off,
+                                                 const ushort4* __restrict__ rects, uint32_t base, uint32_t stop,
+                                                 LRec* lds) {
+  const uint32_t k = base + threadIdx.x;
+  if (k < stop) {
+    const uint32_t rank = pair_rank[k];
+    const uint32_t e = stage(srec, rank, t.ox, t.oy, lds + threadIdx.x);
+    const ushort4 rc = rects[e];
+    lds[threadIdx.x].slot =
+        rank_off[rank] + (uint32_t)((t.ty - (int)rc.y) * ((int)rc.z - (int)rc.x + 1) + (t.tx - (int)rc.x));
+  }
 }
 
 // Forward traversal of the tile list; identical in render_fwd and in the
@@ -261,12 +290,13 @@ __global__ __launch_bounds__(kBlock / PIX) void render_fwd_kernel(CamBatch cb, O
   }
 }
 
-template <int PIX, int kMode, int kLoss>
+template <int PIX, int kMode, int kLoss, bool kDet>
 __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
     CamBatch cb, OptsDev op, const Rec* __restrict__ srec, const uint32_t* __restrict__ tile_start,
     const uint32_t* __restrict__ pair_rank, const float* __restrict__ dl_or_target, const float* __restrict__ image,
     const uint32_t* __restrict__ n_contrib, float* __restrict__ image_out, float* __restrict__ loss_out,
-    float inv_count, float* __restrict__ g2) {
+    float inv_count, float* __restrict__ g2, DetArgs det) {
+  static_assert(!kDet || PIX == 4, "the deterministic variant runs one wave per tile");
   constexpr int kWaves = kBlock / PIX / 64;
   constexpr uint32_t kBatch = kBlock / PIX;
   __shared__ LRec lds[kBatch];
@@ -342,8 +372,11 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   if (kLoss == SSS_LOSS_L1 && loss_out && threadIdx.x == 0) {
     float l = 0.0f;
     for (int w = 0; w < kWaves; ++w) l += s_loss[w];
-    atomicAdd(loss_out, l * inv_count);
+    if (kDet) det.loss_part[blockIdx.x] = l * inv_count;
+    else atomicAdd(loss_out, l * inv_count);
   }
+  // pairs of this tile up to rank lastp1 - 1 are visited (lists ascend in rank)
+  if (kDet && threadIdx.x == 0) det.lastp1[blockIdx.x] = stop > t.start ? pair_rank[stop - 1] + 1u : 0u;
 
   // ---- front-to-back gradient walk ----
   float T[PIX], gA[PIX];
@@ -354,7 +387,8 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   }
   for (uint32_t base = t.start; base < stop; base += kBatch) {
     __syncthreads();
-    stage_batch<PIX>(t, srec, pair_rank, base, stop, lds);
+    if (kDet) stage_batch_slot<PIX>(t, srec, pair_rank, det.rank_off, det.rects, base, stop, lds);
+    else stage_batch<PIX>(t, srec, pair_rank, base, stop, lds);
     __syncthreads();
     const int cnt = (int)min(kBatch, stop - base);
     for (int j = 0; j < cnt; ++j) {
@@ -410,7 +444,20 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
         const float dtn = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
         v9 = __fmaf_rn(dt2, dtn, v9);
       }
-      if (__any(hit)) {
+      if (kDet) {
+        // every visited pair's slot is written, zeros when no pixel was hit
+        if (__any(hit)) {
+          v0 = wave_sum63(v0); v1 = wave_sum63(v1); v2 = wave_sum63(v2); v3 = wave_sum63(v3);
+          v4 = wave_sum63(v4); v5 = wave_sum63(v5); v6 = wave_sum63(v6); v7 = wave_sum63(v7);
+          v8 = wave_sum63(v8); v9 = wave_sum63(v9);
+        }
+        if (lane == 63) {
+          float4* q = reinterpret_cast<float4*>(det.part + (size_t)L.slot * kG2);
+          q[0] = make_float4(-2.0f * v0, -2.0f * v1, v2, 2.0f * v3);
+          q[1] = make_float4(v4, v5, v6, v7);
+          q[2] = make_float4(v8, v9, 0.0f, 0.0f);
+        }
+      } else if (__any(hit)) {
         v0 = wave_sum63(v0); v1 = wave_sum63(v1); v2 = wave_sum63(v2); v3 = wave_sum63(v3);
         v4 = wave_sum63(v4); v5 = wave_sum63(v5); v6 = wave_sum63(v6); v7 = wave_sum63(v7);
         v8 = wave_sum63(v8); v9 = wave_sum63(v9);
@@ -432,6 +479,62 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   }
 }
 
+// Deterministic sum of the pair slots: one wave per visible rank r.  Lane l
+// adds the slots k = l, l + 64, ... of r's emission range in order (skipping
+// tiles whose walk stopped before r), then a fixed DPP tree sums the lanes and
+// lane 63 writes the entry's screen-space gradient.
+__global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t n, int64_t n_vis, uint32_t m,
+                                                            DetArgs det, float* __restrict__ g2) {
+  const int64_t r = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n_vis) return;   // uniform per wave
+  const uint32_t e = det.order[r];
+  const uint32_t off = det.rank_off[r];
+  const uint32_t cnt = (r + 1 < n_vis ? det.rank_off[r + 1] : m) - off;
+  const ushort4 rc = det.rects[e];
+  const int v = (int)(e / (uint64_t)n);
+  int toff = 0, tiles_x = 1;
+  for (int k = 0; k < cb.n_views; ++k)
+    if (k == v) { toff = cb.v[k].tile_offset; tiles_x = cb.v[k].tiles_x; }
+  const int w = (int)rc.z - (int)rc.x + 1;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, a4 = 0.0f, a5 = 0.0f, a6 = 0.0f, a7 = 0.0f, a8 = 0.0f,
+        a9 = 0.0f;
+  for (uint32_t k = (uint32_t)lane; k < cnt; k += 64) {
+    const int q = (int)k / w, c = (int)k - q * w;
+    const int tile = toff + ((int)rc.y + q) * tiles_x + (int)rc.x + c;
+    if ((uint32_t)r < det.lastp1[tile]) {
+      const float4* p = reinterpret_cast<const float4*>(det.part + (size_t)(off + k) * kG2);
+      const float4 x = p[0], y = p[1], z = p[2];
+      a0 += x.x; a1 += x.y; a2 += x.z; a3 += x.w;
+      a4 += y.x; a5 += y.y; a6 += y.z; a7 += y.w;
+      a8 += z.x; a9 += z.y;
+    }
+  }
+  a0 = wave_sum63(a0); a1 = wave_sum63(a1); a2 = wave_sum63(a2); a3 = wave_sum63(a3); a4 = wave_sum63(a4);
+  a5 = wave_sum63(a5); a6 = wave_sum63(a6); a7 = wave_sum63(a7); a8 = wave_sum63(a8); a9 = wave_sum63(a9);
+  if (lane == 63) {
+    float4* g = reinterpret_cast<float4*>(g2 + (size_t)e * kG2);
+    g[0] = make_float4(a0, a1, a2, a3);
+    g[1] = make_float4(a4, a5, a6, a7);
+    g[2] = make_float4(a8, a9, 0.0f, 0.0f);
+  }
+}
+
+// Fixed-order sum of the per-tile loss values (one workgroup).
+__global__ __launch_bounds__(kBlock) void det_loss_kernel(const float* __restrict__ part, int64_t n,
+                                                          float* __restrict__ loss_out) {
+  __shared__ float red[kBlock];
+  float s = 0.0f;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss_out, red[0]);
+}
+
 __global__ __launch_bounds__(kBlock) void zero_kernel(float4* __restrict__ p, int64_t n4) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n4) p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -445,6 +548,41 @@ void launch_zero(float* p, int64_t count, hipStream_t st) {
   if (n4 <= 0) return;
   SSS_LAUNCH("zero", zero_kernel, dim3((unsigned)((n4 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                      (float4*)p, n4);
+}
+
+// Deterministic-mode workspace: screen-space gradients [E][kG2], per-pair
+// sums [M][kG2], per-tile visit bounds [T] and loss values [T], each
+// 256-byte aligned.
+static size_t det_parts(int64_t n_entries, int64_t n_pairs, int64_t n_tiles, size_t part[4]) {
+  part[0] = sizeof(float) * kG2 * (size_t)n_entries;
+  part[1] = sizeof(float) * kG2 * (size_t)(n_pairs > 0 ? n_pairs : 1);
+  part[2] = sizeof(uint32_t) * (size_t)n_tiles;
+  part[3] = sizeof(float) * (size_t)n_tiles;
+  size_t total = 0;
+  for (int k = 0; k < 4; ++k) total += (part[k] + 255) & ~(size_t)255;
+  return total;
+}
+
+size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_tiles) {
+  size_t part[4];
+  return det_parts(n_entries, n_pairs, n_tiles, part);
+}
+
+DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, float** g2) {
+  size_t part[4];
+  det_parts(n_entries, n_pairs, n_tiles, part);
+  char* q[4];
+  char* p = (char*)ws;
+  for (int k = 0; k < 4; ++k) {
+    q[k] = p;
+    p += (part[k] + 255) & ~(size_t)255;
+  }
+  DetArgs d{};
+  *g2 = (float*)q[0];
+  d.part = (float*)q[1];
+  d.lastp1 = (uint32_t*)q[2];
+  d.loss_part = (float*)q[3];
+  return d;
 }
 
 int env_pix(const char* name, int dflt) {
@@ -469,16 +607,38 @@ void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
 
 void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, int mode, int loss,
                        const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
-                       float* loss_out, float* g2, int64_t total_pixels, hipStream_t st) {
+                       float* loss_out, float* g2, int64_t total_pixels, const DetArgs* det, int64_t n,
+                       hipStream_t st) {
   static const int pix = env_pix("SSS_PIX_BWD", 4);
   const float inv_count = 1.0f / (3.0f * (float)total_pixels);
   const dim3 grid((unsigned)cb.total_tiles);
   const Rec* sr = (const Rec*)b.sorted_records;
   const uint32_t* ts = b.tile_start;
   const uint32_t* pr = b.pair_rank;
+  if (det) {
+    // one wave per tile; then the fixed-order sums
+#define SSS_BWD_DET(M, L)                                                                                       \
+  SSS_LAUNCH("render_bwd", (render_bwd_kernel<4, M, L, true>), grid, dim3(kBlock / 4), 0, st, cb, op, sr, ts, pr, \
+             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, *det)
+    if (mode == SSS_BWD_STORED && loss == SSS_LOSS_GRAD) { SSS_BWD_DET(SSS_BWD_STORED, SSS_LOSS_GRAD); }
+    else if (mode == SSS_BWD_STORED) { SSS_BWD_DET(SSS_BWD_STORED, SSS_LOSS_L1); }
+    else if (loss == SSS_LOSS_GRAD) { SSS_BWD_DET(SSS_BWD_RECOMPUTE, SSS_LOSS_GRAD); }
+    else { SSS_BWD_DET(SSS_BWD_RECOMPUTE, SSS_LOSS_L1); }
+#undef SSS_BWD_DET
+    if (b.n_visible > 0) {
+      const unsigned gr = (unsigned)((b.n_visible + kBlock / 64 - 1) / (kBlock / 64));
+      SSS_LAUNCH("det_reduce", det_reduce_kernel, dim3(gr), dim3(kBlock), 0, st, cb, n, b.n_visible,
+                 (uint32_t)b.n_pairs, *det, g2);
+    }
+    if (loss == SSS_LOSS_L1 && loss_out)
+      SSS_LAUNCH("det_loss", det_loss_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)det->loss_part,
+                 (int64_t)cb.total_tiles, loss_out);
+    return;
+  }
+  const DetArgs nodet{};
 #define SSS_BWD(P, M, L)                                                                                    \
-  SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L>), grid, dim3(kBlock / P), 0, st, cb, op, sr, ts, pr, \
-             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2)
+  SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L, false>), grid, dim3(kBlock / P), 0, st, cb, op, sr, ts, pr, \
+             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, nodet)
 #define SSS_BWD_P(M, L)              \
   if (pix == 1) SSS_BWD(1, M, L);    \
   else if (pix == 2) SSS_BWD(2, M, L); \

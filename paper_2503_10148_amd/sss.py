@@ -21,7 +21,7 @@ MAX_VIEWS = 16
 RECORD_BYTES = 64
 G2_SLOTS = 12
 OK, ERR_INVALID, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
-BWD_STORED, BWD_RECOMPUTE = 0, 1
+BWD_STORED, BWD_RECOMPUTE, BWD_DETERMINISTIC = 0, 1, 4
 LOSS_GRAD, LOSS_L1 = 0, 1
 
 c_f32p = ctypes.c_void_p
@@ -59,8 +59,8 @@ class Proj(ctypes.Structure):
 
 class Bins(ctypes.Structure):
     _fields_ = [("order", ctypes.c_void_p), ("sorted_records", ctypes.c_void_p), ("tile_start", ctypes.c_void_p),
-                ("pair_rank", ctypes.c_void_p), ("pair_capacity", ctypes.c_int64), ("n_visible", ctypes.c_int64),
-                ("n_pairs", ctypes.c_int64)]
+                ("pair_rank", ctypes.c_void_p), ("rank_offset", ctypes.c_void_p), ("pair_capacity", ctypes.c_int64),
+                ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64)]
 
 
 class SghmcOpts(ctypes.Structure):
@@ -115,6 +115,8 @@ def lib():
         L.sss_bin_sort_workspace.argtypes = [i64, i64]
         L.sss_render_bwd_workspace.restype = ctypes.c_size_t
         L.sss_render_bwd_workspace.argtypes = [i64]
+        L.sss_render_bwd_workspace_det.restype = ctypes.c_size_t
+        L.sss_render_bwd_workspace_det.argtypes = [i64, i64, i64]
         L.sss_total_tiles.restype = i64
         L.sss_total_tiles.argtypes = [vp, i32]
         L.sss_total_pixels.restype = i64
@@ -159,6 +161,10 @@ def _check(rc, what):
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _addr(t):
+    return None if t is None else t.data_ptr()
 
 
 def _stream(stream):
@@ -264,20 +270,23 @@ class Binned:
     pair_rank: torch.Tensor      # int32 [capacity]
     n_visible: int = 0
     n_pairs: int = 0
+    rank_offset: torch.Tensor | None = None   # int32 [E], kept for the deterministic backward
 
     def struct(self):
         return Bins(self.order.data_ptr(), self.sorted_records.data_ptr(), self.tile_start.data_ptr(),
-                    self.pair_rank.data_ptr(), self.pair_rank.numel(), self.n_visible, self.n_pairs)
+                    self.pair_rank.data_ptr(), _addr(self.rank_offset), self.pair_rank.numel(), self.n_visible,
+                    self.n_pairs)
 
 
 class BinSorter:
     """Holds the pair and workspace buffers of sss_bin_sort and grows them
     (with 25% headroom) when a call reports SSS_ERR_CAPACITY."""
 
-    def __init__(self, pair_capacity: int = 0):
+    def __init__(self, pair_capacity: int = 0, keep_offsets: bool = False):
         self.cap = int(pair_capacity)
         self.ws = None
         self.pair_rank = None
+        self.keep_offsets = keep_offsets
 
     def __call__(self, proj: Projected, cams, n: int, stream=None, out: Binned | None = None) -> Binned:
         E = n * len(cams)
@@ -287,6 +296,8 @@ class BinSorter:
             out = Binned(torch.empty(E, dtype=torch.int32, device=dev),
                          torch.empty((E, RECORD_BYTES), dtype=torch.uint8, device=dev),
                          torch.empty(T + 1, dtype=torch.int32, device=dev), None)
+        if self.keep_offsets and (out.rank_offset is None or out.rank_offset.numel() < E):
+            out.rank_offset = torch.empty(E, dtype=torch.int32, device=dev)
         camarr = camera_array(cams)
         p = proj.struct()
         for _ in range(3):
@@ -326,16 +337,22 @@ def zero_grads_like(scene):
 
 def render_bwd(scene, proj: Projected, bins: Binned, cams, dl_or_target, opts=None, mode=BWD_STORED,
                loss=LOSS_GRAD, image=None, n_contrib=None, image_out=None, loss_out=None, grads=None,
-               ws=None, stream=None, overwrite=None):
+               ws=None, stream=None, overwrite=None, deterministic=False):
     """Gradients into `grads` (+= by default; written when overwrite, which is
-    the default when grads is None and new buffers are allocated)."""
+    the default when grads is None and new buffers are allocated).
+    deterministic: no float atomics, bit-identical results run to run (needs
+    bins from BinSorter(keep_offsets=True))."""
     n = scene["means"].shape[0]
     E = n * len(cams)
     if grads is None:
         grads = {k: torch.empty_like(scene[k]) for k in ("means", "scales", "quats", "nu", "opacity", "sh")}
         overwrite = True if overwrite is None else overwrite
     overwrite = bool(overwrite)
-    need = int(lib().sss_render_bwd_workspace(E))
+    if deterministic:
+        mode |= BWD_DETERMINISTIC
+        need = int(lib().sss_render_bwd_workspace_det(E, bins.n_pairs, total_tiles(cams)))
+    else:
+        need = int(lib().sss_render_bwd_workspace(E))
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need // 4, dtype=torch.float32, device=scene["means"].device)
     s = scene_struct(scene)

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(sss):
     lib = ctypes.CDLL(sss.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert sss.lib().sss_version() == 100
+    assert sss.lib().sss_version() == 101
 
 
 def test_default_options(sss):
@@ -108,9 +108,9 @@ def test_bin_sort_rejects_short_workspace_and_nulls(sss):
     L = sss.lib()
     cams = sss.camera_array([scenes.ring_camera(64, 48)])
     p = _proj_struct(sss)
-    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, 100, 0, 0)
+    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, None, 100, 0, 0)
     assert L.sss_bin_sort(ctypes.byref(p), cams, 1, 10, ctypes.byref(b), None, 0, None) == sss.ERR_INVALID
-    b0 = sss.Bins(0, 0x2000, 0x3000, 0x4000, 100, 0, 0)
+    b0 = sss.Bins(0, 0x2000, 0x3000, 0x4000, None, 100, 0, 0)
     assert L.sss_bin_sort(ctypes.byref(p), cams, 1, 10, ctypes.byref(b0), ctypes.c_void_p(0x9000), 10 ** 9,
                           None) == sss.ERR_INVALID
 
@@ -121,7 +121,7 @@ def test_render_bwd_rejects_unknown_mode_and_short_workspace(sss):
     opts = sss.render_opts()
     scene = _scene_struct(sss)
     p = _proj_struct(sss)
-    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, 100, 0, 0)
+    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, None, 100, 0, 0)
     g = sss.Grads(0, 0, 0, 0, 0, 0, 0, 0)
     args = lambda mode, loss, wsb: (ctypes.byref(scene), ctypes.byref(p), ctypes.byref(b), cams, 1,
                                     ctypes.byref(opts), mode, loss, ctypes.c_void_p(0x6000), ctypes.c_void_p(0x7000),
@@ -131,6 +131,22 @@ def test_render_bwd_rejects_unknown_mode_and_short_workspace(sss):
     assert L.sss_render_bwd(*args(0, 9, 10 ** 6)) == sss.ERR_INVALID
     assert L.sss_render_bwd(*args(0, 0, 10)) == sss.ERR_INVALID
     assert b"workspace" in L.sss_last_error()
+    assert L.sss_render_bwd(*args(8, 0, 10 ** 6)) == sss.ERR_INVALID          # unknown flag bit
+    # deterministic mode without the rank offsets of the bin sort
+    assert L.sss_render_bwd(*args(sss.BWD_DETERMINISTIC, 0, 10 ** 9)) == sss.ERR_INVALID
+    assert b"rank_offset" in L.sss_last_error()
+    b.rank_offset = 0x5000
+    b.n_pairs, b.n_visible = 100, 10
+    assert L.sss_render_bwd(*args(sss.BWD_DETERMINISTIC | sss.BWD_RECOMPUTE, 0, 100)) == sss.ERR_INVALID
+    assert b"workspace" in L.sss_last_error()
+
+
+def test_deterministic_workspace_covers_pairs_and_tiles(sss):
+    L = sss.lib()
+    base = L.sss_render_bwd_workspace_det(1000, 0, 10)
+    assert base >= 1000 * 48
+    assert L.sss_render_bwd_workspace_det(1000, 10 ** 6, 10) - base >= 10 ** 6 * 48 - 48 - 256
+    assert L.sss_render_bwd_workspace_det(1000, 0, 10 ** 5) - base >= 2 * 4 * (10 ** 5 - 10) - 512
 
 
 def test_sghmc_rejects_bad_arguments(sss):

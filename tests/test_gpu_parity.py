@@ -466,3 +466,77 @@ def test_coverage_truncation_matches_oracle(sss, family):
     for k in PARAMS:
         good, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=ok)
         assert good, (k, worst)
+
+
+# ---------------------------------------------------------------------------
+# deterministic backward (no float atomics)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["sh3_ragged", "clusters", "bigcomp"])
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_deterministic_backward_matches_oracle_and_repeats_bitwise(sss, name, mode):
+    scene, cams = _case(name)
+    cam = cams[0]
+    n = scene["means"].shape[0]
+    ref = oracle.render(scene, cam)
+    w = np.random.default_rng(78).standard_normal(ref["image"].shape)
+    w[ref["xflags"] != 0] = 0.0
+    gref = oracle.render_backward(scene, cam, w, fwd=ref)
+    dev = to_device(scene)
+    proj = sss.project(dev, cams)
+    bins = sss.BinSorter(1024, keep_offsets=True)(proj, cams, n)
+    img, _, ncon = sss.render_fwd(bins, cams)
+    dl = torch.as_tensor(w.reshape(-1, 3), dtype=torch.float32, device="cuda")
+    m = sss.BWD_STORED if mode == "stored" else sss.BWD_RECOMPUTE
+    runs = [sss.render_bwd(dev, proj, bins, cams, dl, mode=m, image=img, n_contrib=ncon, deterministic=True)
+            for _ in range(3)]
+    atom = sss.render_bwd(dev, proj, bins, cams, dl, mode=m, image=img, n_contrib=ncon)
+    torch.cuda.synchronize()
+    keep = ref["proj"]["pflags"] == 0
+    for k in PARAMS:
+        a = runs[0][k].cpu().numpy()
+        for r in runs[1:]:
+            assert np.array_equal(a.view(np.uint32), r[k].cpu().numpy().view(np.uint32)), k
+        ok, worst = grad_close(a, gref[k], mask=keep)
+        assert ok, (k, worst)
+        ok, worst = grad_close(atom[k].cpu().numpy(), a)
+        assert ok, (k, worst)
+
+
+def test_deterministic_backward_multiview_l1_loss(sss):
+    """Several views of different sizes, fused L1 loss: the loss value and the
+    gradients repeat bit for bit and equal the oracle's."""
+    s = scenes.make_scene(4000, 3, seed=16, neg_frac=0.3)
+    cams = [scenes.ring_camera(150, 97, angle=0.3), scenes.ring_camera(64, 64, angle=2.0),
+            scenes.ring_camera(33, 250, angle=4.0)]
+    n = s["means"].shape[0]
+    tg = [scenes.smooth_target(c["width"], c["height"], seed=i) for i, c in enumerate(cams)]
+    P = sum(c["width"] * c["height"] for c in cams)
+    gref, lref, skip = None, 0.0, np.zeros(n, bool)
+    for c, t in zip(cams, tg):
+        ref = oracle.render(s, c)
+        gl = oracle.l1_grad(ref["image"], t) * (c["width"] * c["height"] / P)
+        lref += np.abs(ref["image"] - t).sum() / (3.0 * P)
+        gr = oracle.render_backward(s, c, gl, fwd=ref)
+        gref = gr if gref is None else {k: gref[k] + gr[k] for k in PARAMS}
+        near = np.abs(ref["image"] - t).min(axis=2) < 1e-4
+        xf = ref["xflags"].copy()
+        xf[near] |= 16
+        skip |= _explained_components(dict(ref, xflags=xf), n, c) | (ref["proj"]["pflags"] != 0)
+    dev = to_device(s)
+    proj = sss.project(dev, cams)
+    bins = sss.BinSorter(1024, keep_offsets=True)(proj, cams, n)
+    tgt = torch.as_tensor(np.concatenate([t.reshape(-1, 3) for t in tg]), device="cuda")
+    outs = []
+    for _ in range(2):
+        loss = torch.zeros(1, device="cuda")
+        g = sss.render_bwd(dev, proj, bins, cams, tgt, mode=sss.BWD_RECOMPUTE, loss=sss.LOSS_L1, loss_out=loss,
+                           deterministic=True)
+        outs.append((loss, g))
+    torch.cuda.synchronize()
+    assert outs[0][0].item() == outs[1][0].item()
+    assert outs[0][0].item() == pytest.approx(lref, rel=1e-5)
+    for k in PARAMS:
+        a, b = outs[0][1][k].cpu().numpy(), outs[1][1][k].cpu().numpy()
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), k
+        ok, worst = grad_close(a, gref[k], mask=~skip)
+        assert ok, (k, worst)
