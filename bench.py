@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="m1", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="stored", choices=["stored", "recompute"])
+    ap.add_argument("--deterministic", action="store_true",
+                    help="backward without float atomics (bit-identical gradients run to run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=768 * 768)
     ap.add_argument("--serve-seconds", type=float, default=6.0,
@@ -197,7 +199,7 @@ def main():
     bounds = dict(scales=(1e-4, 3.0e38), quats=(-3.0e38, 3.0e38), nu=(1.0, 1e4), opacity=(-1.0, 1.0),
                   sh=(-3.0e38, 3.0e38))
     lrs = dict(scales=1e-4, quats=1e-3, nu=1e-2, opacity=1e-3, sh=2.5e-4)
-    binner = sss.BinSorter(0)
+    binner = sss.BinSorter(0, keep_offsets=args.deterministic)
     image = torch.empty((P, 3), device="cuda")
     t_final = torch.empty(P, device="cuda")
     n_contrib = torch.empty(P, dtype=torch.int32, device="cuda")
@@ -205,19 +207,26 @@ def main():
     bwd_ws = torch.empty(int(sss.lib().sss_render_bwd_workspace(n * len(cams))) // 4, device="cuda")
     mode = sss.BWD_STORED if args.mode == "stored" else sss.BWD_RECOMPUTE
     state = {"proj": None, "bins": None}
+    T = sss.total_tiles(cams)
 
     def step(it):
+        nonlocal bwd_ws
         proj = sss.project(scene, cams, out=state["proj"])
         state["proj"] = proj
         bins = binner(proj, cams, n, out=state["bins"])
         state["bins"] = bins
+        if args.deterministic:
+            need = int(sss.lib().sss_render_bwd_workspace_det(n * len(cams), bins.n_pairs, T))
+            if bwd_ws.numel() * 4 < need:
+                bwd_ws = torch.empty(int(need * 1.1) // 4 + 64, device="cuda")
         if mode == sss.BWD_STORED:
             sss.render_fwd(bins, cams, image=image, t_final=t_final, n_contrib=n_contrib)
             sss.render_bwd(scene, proj, bins, cams, target, mode=mode, loss=sss.LOSS_L1, image=image,
-                           n_contrib=n_contrib, loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True)
+                           n_contrib=n_contrib, loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True,
+                           deterministic=args.deterministic)
         else:
             sss.render_bwd(scene, proj, bins, cams, target, mode=mode, loss=sss.LOSS_L1, image_out=image,
-                           loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True)
+                           loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True, deterministic=args.deterministic)
         adam = dict(beta1=0.9, beta2=0.999, eps=1e-15, t=it + 1,
                     arrays=[dict(param=scene[k], grad=grads[k], m=adam_state[k][0], v=adam_state[k][1], lr=lrs[k],
                                  lo=bounds[k][0], hi=bounds[k][1]) for k in adam_state])
@@ -229,19 +238,28 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup done: pairs={state['bins'].n_pairs} visible={state['bins'].n_visible}")
 
-    sss.timing_enable(True)
-    sss.timing_reset()
+    # the timed steps run uninstrumented; the per-kernel breakdown comes from
+    # a few further steps with HIP events around every launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(args.warmup, args.warmup + args.steps):
         step(it)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kt = sss.timing_read()
-    sss.timing_enable(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = P * args.steps / (t1 - t0) / 1e6
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.1f} Mpix/s")
+    n_inst = max(1, min(args.steps, 5))
+    sss.timing_enable(True)
+    sss.timing_reset()
+    torch.cuda.synchronize()
+    ti0 = time.perf_counter()
+    for it in range(args.warmup + args.steps, args.warmup + args.steps + n_inst):
+        step(it)
+    torch.cuda.synchronize()
+    ti1 = time.perf_counter()
+    kt = sss.timing_read()
+    sss.timing_enable(False)
 
     # algorithmic work of the last step
     if mode == sss.BWD_RECOMPUTE:
@@ -250,7 +268,7 @@ def main():
     evals = float(n_contrib.to(torch.float64).sum().item())
     bins = state["bins"]
     avg = {k: v[1] / v[0] for k, v in kt.items()}          # ms per launch
-    per_step = {k: v[1] / args.steps for k, v in kt.items()}
+    per_step = {k: v[1] / n_inst for k, v in kt.items()}
     bwd_ms = avg.get("render_bwd", float("nan"))
     achieved = SLOTS_BWD * evals / (bwd_ms * 1e-3)
     # compulsory HBM bytes of the HBM-bound kernels (per launch)
@@ -268,7 +286,7 @@ def main():
         "sghmc": n * 64,
         "adam": n * (3 + 4 + 1 + 1 + 3 * K) * 28 / 5,           # per launch, 5 arrays
     }
-    stages = {k: {"ms_per_step": round(per_step[k], 4), "launches_per_step": kt[k][0] / args.steps}
+    stages = {k: {"ms_per_step": round(per_step[k], 4), "launches_per_step": kt[k][0] / n_inst}
               for k in sorted(kt)}
     for k, b in bytes_.items():
         if k in avg:
@@ -293,7 +311,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "components": n,
-                   "pixels_per_step": P, "bwd_mode": args.mode, "loss": "L1", "pairs": bins.n_pairs,
+                   "pixels_per_step": P, "bwd_mode": args.mode,
+                   "deterministic": args.deterministic, "loss": "L1", "pairs": bins.n_pairs,
                    "visible": bins.n_visible, "evaluations": evals},
         "hbm_gbps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "roofline": {"bound": "alu", "kernel": "render_bwd", "achieved": round(achieved / 1e12, 3),
@@ -301,7 +320,8 @@ def main():
                      "frac": round(achieved / PEAK_VALU, 4), "traffic": measured_traffic(args.workload),
                      "avg_ms": round(bwd_ms, 4), "units": evals, "ops_per_unit": SLOTS_BWD},
         "stages": stages,
-        "loss": float(loss.item()) / (args.warmup + args.steps),
+        "instrumented_ms_per_step": round((ti1 - ti0) * 1e3 / n_inst, 4),
+        "loss": float(loss.item()) / (args.warmup + args.steps + n_inst),
     }
     if args.serve_seconds > 0:
         out["serving"] = serving(scene_np, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds)

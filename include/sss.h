@@ -142,10 +142,13 @@ void sss_default_render_opts(sss_render_opts_t* opts);
  * For every view v and component i (entry e = v*n + i): camera-space
  * position, 2D mean, 2D covariance J W Sigma W^T J^T (local affine
  * approximation; x/z and y/z clamped to 1.3 half-fov for J), its inverse
- * (the conic), colour from SH, clamped nu, and the truncation rectangle: the
- * tiles touched by the axis-aligned box of the ellipse h <= h* with
- * h* = nu ((|o|/alpha_min)^(2/(nu+2)) - 1), outside of which |o T2D| < alpha_min
- * (SSS_TRUNC_COVERAGE: the box of h <= min(q, h*), see sss_render_opts_t).
+ * (the conic), colour from SH, clamped nu, and the truncation ellipse
+ * h <= h* with h* = nu ((|o|/alpha_min)^(2/(nu+2)) - 1), outside of which
+ * |o T2D| < alpha_min (SSS_TRUNC_COVERAGE: h <= min(q, h*), see
+ * sss_render_opts_t).  rect is the range of tiles of its axis-aligned box;
+ * the entry is listed in the tiles of that range whose box of pixel centres
+ * meets the ellipse (row by row: the ellipse's x-extent over the band of
+ * pixel-centre rows), and tiles_touched counts those tiles.
  * Depth key = bits of the FP32 depth fmaf(W20, x, fmaf(W21, y, fmaf(W22, z, t2))).
  * Culled (tiles_touched = 0): depth key <= z_near, |o| < alpha_min, degenerate
  * 2D covariance, or a rectangle entirely off screen.
@@ -153,7 +156,10 @@ void sss_default_render_opts(sss_render_opts_t* opts);
  *   records        64-byte projected records (opaque to the caller)
  *   depth_key      uint32
  *   rect           uint16 x0, y0, x1, y1 per entry (inclusive tile range)
- *   tiles_touched  uint32, (x1-x0+1)(y1-y0+1), 0 = culled
+ *   tiles_touched  uint32, number of listed tiles, 0 = culled
+ *   ellipse        4 doubles per entry: the FP64 2D covariance A, B, D and
+ *                  the ellipse level (valid where tiles_touched > 0; read
+ *                  by sss_bin_sort and the deterministic backward pass)
  * Errors: INVALID for n <= 0, sh_degree outside 0..3, n_views outside
  * 1..SSS_MAX_VIEWS, a NULL array, a camera with width/height <= 0 or
  * non-positive focal lengths. */
@@ -162,6 +168,7 @@ typedef struct {
   uint32_t* depth_key;
   uint16_t* rect;
   uint32_t* tiles_touched;
+  double* ellipse;
 } sss_proj_t;
 
 int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,

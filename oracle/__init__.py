@@ -172,19 +172,21 @@ def project(scene, cam, opts=None):
     o = opts_array(opts)
     out = dict(valid=np.zeros(n, np.int32), mean2d=np.zeros((n, 2)), cov2d=np.zeros((n, 3)),
                conic=np.zeros((n, 3)), rgb=np.zeros((n, 3)), nu_c=np.zeros(n), hstar=np.zeros(n),
-               rect=np.zeros((n, 4), np.int32), key=np.zeros(n, np.uint32),
+               hrect=np.zeros(n), rect=np.zeros((n, 4), np.int32), key=np.zeros(n, np.uint32),
                touched=np.zeros(n, np.int32), pflags=np.zeros(n, np.int32))
     lib.orc_project(ctypes.c_int(n), ctypes.c_int(s["deg"]), _p(s["means"]), _p(s["scales"]),
                     _p(s["quats"]), _p(s["nu"]), _p(s["opacity"]), _p(s["sh"]), _p(c), _p(o),
                     _p(out["valid"]), _p(out["mean2d"]), _p(out["cov2d"]), _p(out["conic"]),
-                    _p(out["rgb"]), _p(out["nu_c"]), _p(out["hstar"]), _p(out["rect"]),
+                    _p(out["rgb"]), _p(out["nu_c"]), _p(out["hstar"]), _p(out["hrect"]), _p(out["rect"]),
                     _p(out["key"]), _p(out["touched"]), _p(out["pflags"]))
     out["opacity"] = s["opacity"]
     return out
 
 
-def bin_tiles(touched, rect, key, tiles_x, tiles_y):
-    """Per-tile component lists in ascending (depth key, index) order."""
+def bin_tiles(touched, rect, key, tiles_x, tiles_y, proj=None):
+    """Per-tile component lists in ascending (depth key, index) order.  With
+    `proj` (a projection result) every rectangle row is cut to the ellipse;
+    without it whole rectangles are listed."""
     lib = _load()
     touched = np.ascontiguousarray(touched, dtype=np.int32)
     rect = np.ascontiguousarray(rect, dtype=np.int32)
@@ -193,8 +195,10 @@ def bin_tiles(touched, rect, key, tiles_x, tiles_y):
     m = int(np.clip(touched, 0, None).astype(np.int64).sum())
     start = np.zeros(tiles_x * tiles_y + 1, np.int32)
     lst = np.zeros(max(m, 1), np.int32)
-    got = lib.orc_bin(ctypes.c_int(n), _p(touched), _p(rect), _p(key), ctypes.c_int(tiles_x),
-                      ctypes.c_int(tiles_y), _p(start), _p(lst), ctypes.c_int64(max(m, 1)))
+    geo = (None, None, None) if proj is None else tuple(
+        np.ascontiguousarray(proj[k], dtype=np.float64) for k in ("mean2d", "cov2d", "hrect"))
+    got = lib.orc_bin(ctypes.c_int(n), _p(touched), _p(rect), _p(key), *(None if g is None else _p(g) for g in geo),
+                      ctypes.c_int(tiles_x), ctypes.c_int(tiles_y), _p(start), _p(lst), ctypes.c_int64(max(m, 1)))
     assert got == m, (got, m)
     return start, lst[:m]
 
@@ -219,7 +223,7 @@ def render(scene, cam, opts=None, brute=False, proj=None):
                              _p(tfin), _p(ncon), _p(xf))
         bins = None
     else:
-        start, lst = bin_tiles(proj["touched"], proj["rect"], proj["key"], tx, ty)
+        start, lst = bin_tiles(proj["touched"], proj["rect"], proj["key"], tx, ty, proj=proj)
         lst_c = np.ascontiguousarray(lst if lst.size else np.zeros(1, np.int32))
         lib.orc_render_tiled(_p(proj["mean2d"]), _p(proj["conic"]), _p(proj["rgb"]), _p(proj["opacity"]),
                              _p(proj["nu_c"]), _p(proj["pflags"]), ctypes.c_int(W), ctypes.c_int(H),

@@ -224,6 +224,52 @@ static uint32_t depth_key32(const double* cam, const double* mu, float* zf_out) 
   return bits;
 }
 
+/* Tile columns of tile row ty met by the ellipse {d : d^T Sigma2D^-1 d <= hr}
+ * around (mx, my), Sigma2D = [[A, B], [B, D]], sampled at pixel centres: the
+ * ellipse's x-extent over the band of pixel-centre rows
+ * [16 ty + 1/2, 16 ty + 31/2] (a convex set, so an interval), mapped to the
+ * tiles whose pixel-centre columns [16 tx + 1/2, 16 tx + 31/2] it reaches and
+ * clipped to [x0, x1].  On the chord at height dy the ellipse spans
+ * dx = (B/D) dy +- sqrt((A - B^2/D)(hr - dy^2/D)) (Schur complement), whose
+ * right end is largest at dy = B sqrt(hr/A) (the ellipse's rightmost point)
+ * and left end smallest at the opposite point; over a band the extremes are
+ * these points clamped into it.  The per-component constants are formed once
+ * (1/D as a reciprocal); the kernels use the same operations in the same
+ * order, so both sides list the same tiles.  Returns the number of tiles;
+ * sets *edge when a tile decision lies within 1e-9 of its threshold. */
+typedef struct { double mx, my, k, S, ds, ey, iD, hr; int inf; } row_geo;
+
+static row_geo make_row_geo(double mx, double my, double A, double B, double D, double hr) {
+  row_geo g;
+  g.mx = mx; g.my = my; g.hr = hr;
+  g.inf = isinf(hr) ? 1 : 0;
+  g.iD = 1.0 / D;
+  g.k = B * g.iD;
+  g.S = A - B * g.k;
+  g.ds = B * sqrt(hr / A);
+  g.ey = sqrt(hr * D);
+  return g;
+}
+
+static int row_run(const row_geo* g, int ty, int x0, int x1, int* t0, int* t1, int* edge) {
+  *t0 = x0; *t1 = x0 - 1;
+  if (g->inf) { *t1 = x1; return x1 - x0 + 1; }
+  const double y0 = 16.0 * ty + 0.5 - g->my, y1 = 16.0 * ty + 15.5 - g->my;
+  const double lo = fmax(y0, -g->ey), hi = fmin(y1, g->ey);
+  if (fabs(lo - hi) <= 1e-9 * fmax(1.0, fabs(lo))) *edge = 1;
+  if (lo > hi) return 0;
+  const double dr = fmin(fmax(g->ds, lo), hi), dl = fmin(fmax(-g->ds, lo), hi);
+  const double wr = g->S * (g->hr - dr * dr * g->iD), wl = g->S * (g->hr - dl * dl * g->iD);
+  const double xr = g->mx + (g->k * dr + (wr > 0.0 ? sqrt(wr) : 0.0));
+  const double xl = g->mx + (g->k * dl - (wl > 0.0 ? sqrt(wl) : 0.0));
+  const double ul = (xl - 15.5) * 0.0625, ur = (xr - 0.5) * 0.0625;
+  if (near_integer(ul) || near_integer(ur)) *edge = 1;
+  const int a = (int)fmin(fmax(ceil(ul), (double)x0), (double)x1 + 1.0);
+  const int b = (int)fmax(fmin(floor(ur), (double)x1), (double)x0 - 1.0);
+  *t0 = a; *t1 = b;
+  return b >= a ? b - a + 1 : 0;
+}
+
 int orc_tiles_x(const double* cam) { return ((int)cam[16] + ORC_TILE - 1) / ORC_TILE; }
 int orc_tiles_y(const double* cam) { return ((int)cam[17] + ORC_TILE - 1) / ORC_TILE; }
 
@@ -234,7 +280,7 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
                  const double* quats, const double* nu, const double* opac,
                  const double* sh, const double* cam, const double* opts,
                  int32_t* valid, double* mean2d, double* cov2d, double* conic,
-                 double* rgb, double* nu_c, double* hstar, int32_t* rect,
+                 double* rgb, double* nu_c, double* hstar, double* hrect, int32_t* rect,
                  uint32_t* key, int32_t* touched, int32_t* pflags) {
   sh_init();
   const int K = (sh_degree + 1) * (sh_degree + 1);
@@ -316,7 +362,7 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
     /* truncation: the alpha level set |o| T2D(h) = alpha_min, i.e.
        h* = nu ((|o|/alpha_min)^(2/(nu+2)) - 1); outside it |alpha| < alpha_min */
     int x0, x1, y0, y1;
-    double hs;
+    double hs, hr;
     if (alpha_min > 0.0) {
       hs = opts[10] == 1.0 ? 2.0 * log(fabs(o) / alpha_min) : nuc * expm1(2.0 / (nuc + 2.0) * log(fabs(o) / alpha_min));
       /* coverage rule (Sec. 3.2 truncation by a critical value): h of a 2D t
@@ -324,7 +370,7 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
          ellipse holds 1 - exp(-9/2), reached at q = nu (exp(9/nu) - 1)
          (q = 9 for the Gaussian).  Beyond h* nothing is drawn anyway, so the
          rectangle uses the smaller of the two. */
-      double hr = hs;
+      hr = hs;
       if (opts[11] == 1.0) {
         const double q = opts[10] == 1.0 ? 9.0 : nuc * expm1(9.0 / nuc);
         if (q < hr) hr = q;
@@ -337,9 +383,18 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
       x0 = (int)fmax(0.0, floor(lx)); x1 = (int)fmin((double)(tx_n - 1), floor(hx));
       y0 = (int)fmax(0.0, floor(ly)); y1 = (int)fmin((double)(ty_n - 1), floor(hy));
     } else {
-      hs = INFINITY;
+      hs = hr = INFINITY;
       x0 = 0; x1 = tx_n - 1; y0 = 0; y1 = ty_n - 1;
     }
+    /* tiles: the rows of the rectangle, each cut to the ellipse's extent */
+    int count = 0, edge = 0;
+    const row_geo rg = make_row_geo(mx, my, A, B, D, hr);
+    for (int ty = y0; ty <= y1; ++ty) {
+      int a, b;
+      count += row_run(&rg, ty, x0, x1, &a, &b, &edge);
+    }
+    if (edge) pflags[i] |= PF_RECT_EDGE;
+    if (count == 0) continue;
 
     /* colour: SH at the viewing direction, offset by 1/2, clamped at 0 */
     double v[3] = {mu[0] - campos[0], mu[1] - campos[1], mu[2] - campos[2]};
@@ -361,8 +416,9 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
     conic[3 * i] = D / det; conic[3 * i + 1] = -B / det; conic[3 * i + 2] = A / det;
     nu_c[i] = nuc;
     hstar[i] = hs;
+    hrect[i] = hr;
     rect[4 * i] = x0; rect[4 * i + 1] = y0; rect[4 * i + 2] = x1; rect[4 * i + 3] = y1;
-    touched[i] = (x1 - x0 + 1) * (y1 - y0 + 1);
+    touched[i] = count;
   }
 }
 
@@ -381,9 +437,12 @@ static int pair_cmp(const void* pa, const void* pb) {
 }
 
 /* rect[4*i] = x0,y0,x1,y1 (inclusive tile range); touched[i] == 0 means not
+ * listed.  With geometry (mean2d, cov2d, hrect non-NULL) each row of the
+ * rectangle is cut to the ellipse (row_run), else the whole rectangle is
  * listed.  Writes tile_start[n_tiles+1] and tile_list[] (component indices).
  * Returns the number of pairs, or -(needed) when it exceeds list_cap. */
 int64_t orc_bin(int n, const int32_t* touched, const int32_t* rect, const uint32_t* key,
+                const double* mean2d, const double* cov2d, const double* hrect,
                 int tiles_x, int tiles_y, int32_t* tile_start, int32_t* tile_list, int64_t list_cap) {
   int64_t m = 0;
   for (int i = 0; i < n; ++i) m += touched[i] > 0 ? touched[i] : 0;
@@ -392,14 +451,23 @@ int64_t orc_bin(int n, const int32_t* touched, const int32_t* rect, const uint32
   int64_t p = 0;
   for (int i = 0; i < n; ++i) {
     if (touched[i] <= 0) continue;
-    for (int ty = rect[4 * i + 1]; ty <= rect[4 * i + 3]; ++ty)
-      for (int tx = rect[4 * i]; tx <= rect[4 * i + 2]; ++tx) {
+    for (int ty = rect[4 * i + 1]; ty <= rect[4 * i + 3]; ++ty) {
+      int a = rect[4 * i], b = rect[4 * i + 2], edge = 0;
+      if (mean2d) {
+        const row_geo rg = make_row_geo(mean2d[2 * i], mean2d[2 * i + 1], cov2d[3 * i], cov2d[3 * i + 1],
+                                        cov2d[3 * i + 2], hrect[i]);
+        row_run(&rg, ty, rect[4 * i], rect[4 * i + 2], &a, &b, &edge);
+      }
+      for (int tx = a; tx <= b; ++tx) {
+        if (p == m) { free(pairs); return -(m + 1); }   /* touched does not match the rows */
         pairs[p].tile = (int64_t)ty * tiles_x + tx;
         pairs[p].key = key[i];
         pairs[p].idx = i;
         ++p;
       }
+    }
   }
+  if (p != m) { free(pairs); return -(m + 1); }
   qsort(pairs, (size_t)m, sizeof(orc_pair), pair_cmp);
   const int64_t nt = (int64_t)tiles_x * tiles_y;
   int64_t cur = 0;

@@ -156,7 +156,7 @@ int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
   if ((rc = check_opts(opts, "sss_project"))) return rc;
   CamBatch cb;
   if ((rc = make_cam_batch(cams, n_views, &cb))) return rc;
-  if (!out || !out->records || !out->depth_key || !out->rect || !out->tiles_touched) {
+  if (!out || !out->records || !out->depth_key || !out->rect || !out->tiles_touched || !out->ellipse) {
     set_error("sss_project: output arrays must be non-null");
     return SSS_ERR_INVALID;
   }
@@ -170,7 +170,7 @@ int sss_bin_sort(const sss_proj_t* proj, const sss_camera_t* cams, int n_views, 
   CamBatch cb;
   int rc = make_cam_batch(cams, n_views, &cb);
   if (rc) return rc;
-  if (!proj || !proj->records || !proj->depth_key || !proj->rect || !proj->tiles_touched || !bins ||
+  if (!proj || !proj->records || !proj->depth_key || !proj->rect || !proj->tiles_touched || !proj->ellipse || !bins ||
       !bins->order || !bins->sorted_records || !bins->tile_start || !bins->pair_rank || !ws || n <= 0 ||
       bins->pair_capacity < 0 || n > (int64_t)0xFFFFFFFF / SSS_MAX_VIEWS) {
     set_error("sss_bin_sort: null pointer, n <= 0 or negative pair capacity");
@@ -222,9 +222,9 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
     return SSS_ERR_INVALID;
   }
   const int64_t n_entries = scene->n * n_views;
-  if (det && (!bins->order || !bins->rank_offset || !proj->rect || bins->n_pairs < 0 ||
+  if (det && (!bins->order || !bins->rank_offset || !proj->rect || !proj->ellipse || bins->n_pairs < 0 ||
               bins->n_visible < 0 || bins->n_visible > n_entries)) {
-    set_error("sss_render_bwd: the deterministic mode needs bins->order, bins->rank_offset, proj->rect and the "
+    set_error("sss_render_bwd: the deterministic mode needs bins->order, bins->rank_offset, proj->rect, proj->ellipse and the "
               "counts of the sss_bin_sort call");
     return SSS_ERR_INVALID;
   }
@@ -243,6 +243,8 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
     da.order = bins->order;
     da.rank_off = bins->rank_offset;
     da.rects = (const ushort4*)proj->rect;
+    da.ell = (const Ellipse*)proj->ellipse;
+    da.n_pairs = (uint32_t)bins->n_pairs;
   }
   launch_zero(g2, n_entries * kG2, st);
   launch_render_bwd(cb, op, *bins, mode, loss, dl_or_target, image, n_contrib, image_out, loss_out, g2,

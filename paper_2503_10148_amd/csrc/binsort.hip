@@ -15,6 +15,7 @@
 // data allows; the radix scatter ranks keys inside a wave with ballots
 // (64-wide match) so the sort is stable without per-thread digit counters.
 #include "common.hpp"
+#include "tiles.hpp"
 #include "scan.hpp"
 
 namespace sss {
@@ -24,20 +25,26 @@ namespace {
 // ---------------------------------------------------------------------------
 // 1. visibility
 // ---------------------------------------------------------------------------
+// The pair total is accumulated into kPairCounters separate counters (block b
+// adds to counter b mod kPairCounters), so the atomics of thousands of blocks
+// do not queue on one address; the host adds them up.
+constexpr int kPairCounters = 32;
+
 __global__ __launch_bounds__(kBlock) void visible_kernel(const uint32_t* __restrict__ touched, int64_t n,
                                                          uint32_t* __restrict__ flags,
                                                          unsigned long long* __restrict__ counters) {
-  __shared__ unsigned long long red[kBlock];
+  __shared__ unsigned long long red[kBlock / 64];
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  uint32_t t = j < n ? touched[j] : 0u;
+  const uint32_t t = j < n ? touched[j] : 0u;
   if (j < n) flags[j] = t > 0 ? 1u : 0u;
-  red[threadIdx.x] = t;
+  unsigned long long v = t;
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long b = red[0] + red[1] + red[2] + red[3];
+    if (b) atomicAdd(counters + 1 + blockIdx.x % kPairCounters, b);
   }
-  if (threadIdx.x == 0 && red[0]) atomicAdd(counters + 1, red[0]);
 }
 
 __global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* __restrict__ flags,
@@ -165,56 +172,72 @@ __device__ __forceinline__ uint32_t off_next(const uint32_t* __restrict__ off, i
   return (r + 1 < n_vis ? off[r + 1] : total) - off[r];
 }
 
-// One lane per rank gathers that rank's record; the pairs are then written
-// wave-cooperatively: for each of the wave's 64 ranks in turn, the 64 lanes
-// store consecutive pairs of its rectangle (row-major over the rectangle).
-// Exactly tiles_touched pairs are written per rank (the scan reserved that
-// many); a tile outside the view's grid or a slot the rectangle does not
-// fill gets the sentinel key n_tiles, which sorts after every real tile.
+// One lane per rank gathers that rank's record and evaluates the rows of its
+// rectangle into the wave's row table (wave_row_table); the pairs are then
+// written wave-cooperatively: for each of the wave's 64 ranks in turn, the
+// lanes store its listed tiles in emission order, so the stores of one rank
+// are contiguous.  Exactly tiles_touched pairs are written per rank (the scan
+// reserved that many, and the projection counted them with the same row_run
+// on the same values); slots left over if the two ever disagreed get the
+// sentinel key n_tiles, which sorts after every real tile, and no store
+// leaves the rank's range.
 __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, const uint32_t* __restrict__ order,
                                                       const ushort4* __restrict__ rects,
+                                                      const Ellipse* __restrict__ ell,
                                                       const uint32_t* __restrict__ off, int64_t n_vis, uint32_t total,
                                                       const uint4* __restrict__ rec_in, uint4* __restrict__ rec_out,
                                                       uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
+  __shared__ RowTable s_rows[kBlock / 64];
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  int my_off = 0, my_cnt = 0, my_x0 = 0, my_y0 = 0, my_w = 1, my_h = 1, my_toff = 0, my_tx = 1, my_ty = 1;
-  if (r < n_vis) {
+  RowTable* table = &s_rows[threadIdx.x >> 6];
+  int my_off = 0, my_cnt = 0, my_x0 = 0, my_y0 = 0, my_x1 = 0, my_y1 = 0, my_toff = 0, my_tx = 1;
+  double my_mx = 0.0, my_my = 0.0;
+  Ellipse my_el{1.0, 0.0, 1.0, 0.0};
+  const bool valid = r < n_vis;
+  if (valid) {
     const uint32_t e = order[r];
     const uint4* src = rec_in + (size_t)e * 4;
     uint4* dst = rec_out + (size_t)r * 4;
     const uint4 a = src[0], b = src[1], c = src[2], d = src[3];
     dst[0] = a; dst[1] = b; dst[2] = c; dst[3] = d;
+    my_mx = __hiloint2double((int)a.y, (int)a.x);   // Rec: 2D mean in FP64 first
+    my_my = __hiloint2double((int)a.w, (int)a.z);
     const int v = (int)(e / (uint64_t)n);
     for (int k = 0; k < cb.n_views; ++k)
-      if (k == v) { my_toff = cb.v[k].tile_offset; my_tx = cb.v[k].tiles_x; my_ty = cb.v[k].tiles_y; }
+      if (k == v) { my_toff = cb.v[k].tile_offset; my_tx = cb.v[k].tiles_x; }
     const ushort4 rc = rects[e];
+    my_el = ell[e];
     my_off = (int)off[r];
     my_cnt = (int)off_next(off, r, n_vis, total);
-    my_x0 = rc.x; my_y0 = rc.y;
-    my_w = max(1, (int)rc.z - (int)rc.x + 1);
-    my_h = max(1, (int)rc.w - (int)rc.y + 1);
+    my_x0 = rc.x; my_y0 = rc.y; my_x1 = rc.z; my_y1 = rc.w;
   }
+  const WaveRows wr = wave_row_table(valid, my_mx, my_my, my_el, my_x0, my_y0, my_x1, my_y1, table);
+  __syncthreads();
   const int64_t r0 = r - lane;
   for (int j = 0; j < 64; ++j) {
-    const int cntj = __builtin_amdgcn_readlane(my_cnt, j);
+    const int cntj = bcast_i(my_cnt, j);
     if (cntj == 0) continue;
-    const uint32_t offj = (uint32_t)__builtin_amdgcn_readlane(my_off, j);
-    const int x0 = __builtin_amdgcn_readlane(my_x0, j), y0 = __builtin_amdgcn_readlane(my_y0, j);
-    const int wj = __builtin_amdgcn_readlane(my_w, j), hj = __builtin_amdgcn_readlane(my_h, j);
-    const int toff = __builtin_amdgcn_readlane(my_toff, j);
-    const int tx = __builtin_amdgcn_readlane(my_tx, j), ty = __builtin_amdgcn_readlane(my_ty, j);
+    const uint32_t offj = (uint32_t)bcast_i(my_off, j);
     const uint32_t rank = (uint32_t)(r0 + j);
-    const float inv_w = 1.0f / (float)wj;
-    for (int k = lane; k < cntj; k += 64) {
-      // row q and column c of pair k; the float quotient is off by at most one
-      int q = (int)((float)k * inv_w);
-      int c = k - q * wj;
-      if (c < 0) { --q; c += wj; }
-      if (c >= wj) { ++q; c -= wj; }
-      const int x = x0 + c, y = y0 + q;
-      const bool in = q < hj && x < tx && y < ty;
-      tkeys[offj + k] = in ? (uint32_t)(toff + y * tx + x) : (uint32_t)cb.total_tiles;
+    const int toff = bcast_i(my_toff, j), tx = bcast_i(my_tx, j);
+    auto put = [&](int k, int x, int y) {
+      if (k < cntj) {
+        tkeys[offj + k] = (uint32_t)(toff + y * tx + x);
+        tvals[offj + k] = rank;
+      }
+    };
+    int written;
+    if (__builtin_amdgcn_readlane((int)wr.fits, j)) {
+      written = bcast_i(wr.total, j);
+      for_each_tile_in_table(table, bcast_i(wr.base, j), bcast_i(wr.h, j), written, bcast_i(my_y0, j), put);
+    } else {
+      const Ellipse el{bcast_d(my_el.A, j), bcast_d(my_el.B, j), bcast_d(my_el.D, j), bcast_d(my_el.hr, j)};
+      written = for_each_listed_tile(bcast_d(my_mx, j), bcast_d(my_my, j), el, bcast_i(my_x0, j), bcast_i(my_y0, j),
+                                     bcast_i(my_x1, j), bcast_i(my_y1, j), put);
+    }
+    for (int k = written + lane; k < cntj; k += 64) {
+      tkeys[offj + k] = (uint32_t)cb.total_tiles;
       tvals[offj + k] = rank;
     }
   }
@@ -252,7 +275,7 @@ Ws carve(void* base, int64_t n_entries, int64_t pair_cap) {
   char* p = (char*)base;
   size_t off = 0;
   auto take = [&](size_t bytes) { char* q = p ? p + off : nullptr; off += align256(bytes); return q; };
-  w.counters = (unsigned long long*)take(4 * sizeof(unsigned long long));
+  w.counters = (unsigned long long*)take((1 + kPairCounters) * sizeof(unsigned long long));
   w.flags = (uint32_t*)take(sizeof(uint32_t) * (size_t)n_entries);
   w.pos = (uint32_t*)take(sizeof(uint32_t) * (size_t)n_entries);
   w.ka = (uint32_t*)take(sizeof(uint32_t) * (size_t)big);
@@ -271,13 +294,17 @@ Ws carve(void* base, int64_t n_entries, int64_t pair_cap) {
 // sorted keys (never the last pass's input).
 uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int nbits,
                      uint32_t* out_v, Ws& w, hipStream_t st) {
+  // as few passes of at most 8 bits as possible, with the bits spread evenly
+  // (e.g. 13 bits as 7 + 6): wider runs per digit and block make the
+  // scatter's stores longer
   const int passes = (nbits + 7) / 8;
+  const int width = (nbits + passes - 1) / passes;
   uint32_t* final_keys = ((passes - 1) % 2 == 0) ? kb : ka;
   if (n <= 0) return final_keys;
   const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
-    const int bits = (nbits - shift) < 8 ? (nbits - shift) : 8;
+    const int shift = width * p;
+    const int bits = (nbits - shift) < width ? (nbits - shift) : width;
     uint32_t* ik = (p % 2 == 0) ? ka : kb;
     uint32_t* iv = (p % 2 == 0) ? va : vb;
     uint32_t* okk = (p % 2 == 0) ? kb : ka;
@@ -312,17 +339,20 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
     return SSS_ERR_INVALID;
   }
   const unsigned g1 = (unsigned)((n_entries + kBlock - 1) / kBlock);
-  if (!hip_ok(hipMemsetAsync(w.counters, 0, 4 * sizeof(unsigned long long), st), "memset")) return SSS_ERR_HIP;
+  if (!hip_ok(hipMemsetAsync(w.counters, 0, (1 + kPairCounters) * sizeof(unsigned long long), st), "memset"))
+    return SSS_ERR_HIP;
   SSS_LAUNCH("visible", visible_kernel, dim3(g1), dim3(kBlock), 0, st, proj.tiles_touched, n_entries, w.flags,
                      w.counters);
   scan_excl(w.flags, w.pos, n_entries, w.scan, st);
   SSS_LAUNCH("compact", compact_kernel, dim3(g1), dim3(kBlock), 0, st, w.flags, w.pos, proj.depth_key, n_entries,
                      w.ka, w.va, w.counters);
-  unsigned long long counts[2];
+  unsigned long long counts[1 + kPairCounters];
   if (!hip_ok(hipMemcpyAsync(counts, w.counters, sizeof(counts), hipMemcpyDeviceToHost, st), "count readback"))
     return SSS_ERR_HIP;
   if (!hip_ok(hipStreamSynchronize(st), "count sync")) return SSS_ERR_HIP;
-  const int64_t n_vis = (int64_t)counts[0], m = (int64_t)counts[1];
+  int64_t m = 0;
+  for (int k = 0; k < kPairCounters; ++k) m += (int64_t)counts[1 + k];
+  const int64_t n_vis = (int64_t)counts[0];
   bins->n_visible = n_vis;
   bins->n_pairs = m;
   if (m > bins->pair_capacity) {
@@ -344,7 +374,8 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
     uint32_t* offs = bins->rank_offset ? bins->rank_offset : w.pos;
     scan_excl(w.flags, offs, n_vis, w.scan, st);
     SSS_LAUNCH("emit", emit_kernel, dim3(gv), dim3(kBlock), 0, st, cb, n, bins->order,
-                       (const ushort4*)proj.rect, offs, n_vis, (uint32_t)m, (const uint4*)proj.records,
+                       (const ushort4*)proj.rect, (const Ellipse*)proj.ellipse, offs, n_vis, (uint32_t)m,
+                       (const uint4*)proj.records,
                        (uint4*)bins->sorted_records, w.ka, w.va);
   }
   // 4. stable sort of the pairs by tile

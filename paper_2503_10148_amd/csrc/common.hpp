@@ -89,14 +89,23 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
 size_t bin_sort_workspace(int64_t n_entries, int64_t pair_capacity);
 void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b,
                        float* image, float* t_final, uint32_t* n_contrib, hipStream_t st);
+// Per-entry FP64 ellipse written by the projection: 2D covariance
+// [[A, B], [B, D]] and the level hr of the listed ellipse
+// {d : d^T Sigma^-1 d <= hr} (see tiles.hpp).
+struct Ellipse {
+  double A, B, D, hr;
+};
+
 // Buffers of the deterministic backward pass (see raster.hip).
 struct DetArgs {
   const uint32_t* order;      // rank -> entry
   const uint32_t* rank_off;   // first emission position of each rank
   const ushort4* rects;       // per-entry tile rectangles
+  const Ellipse* ell;         // per-entry ellipses
   float* part;                // [n_pairs][kG2] per-pair sums
   uint32_t* lastp1;           // [n_tiles] last visited rank + 1
   float* loss_part;           // [n_tiles] per-tile loss
+  uint32_t n_pairs;           // bound of the slots (part has n_pairs rows)
 };
 size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_tiles);
 DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, float** g2);

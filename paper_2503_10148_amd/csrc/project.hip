@@ -8,6 +8,7 @@
 // is exact to far below a pixel's 1e-6; results are stored in FP32 except the
 // mean, which the record keeps in FP64.
 #include "common.hpp"
+#include "tiles.hpp"
 
 namespace sss {
 namespace {
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     CamBatch cb, OptsDev op, int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
     const float* __restrict__ quats, const float* __restrict__ nu, const float* __restrict__ opac,
     const float* __restrict__ sh, Rec* __restrict__ rec, uint32_t* __restrict__ keys, ushort4* __restrict__ rects,
-    uint32_t* __restrict__ touched) {
+    uint32_t* __restrict__ touched, Ellipse* __restrict__ ell) {
   constexpr int K = (DEG + 1) * (DEG + 1), STR = 3 * K + 1;
   __shared__ float shs[kBlock * STR];
   const int v = blockIdx.y;
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
 
   const double mx = c.fx * g.xz + c.cx, my = c.fy * g.yz + c.cy;
   const double nuc = fmin(fmax((double)nu[i], (double)op.nu_min), (double)op.nu_max);
-  double hs, ey;
+  double hs, ey, hr;
   int x0, x1, y0, y1;
   const bool gauss = op.family == SSS_FAMILY_GAUSSIAN;
   if (op.alpha_min > 0.0f) {
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     ey = sqrt(hs * g.D);   // row extent of the pixels that can pass the alpha test
     // coverage rule: the ellipse with the Gaussian 3-sigma probability mass,
     // P(h <= q) = 1 - (1 + q/nu)^(-nu/2) = 1 - exp(-9/2); never beyond h*
-    const double hr = op.trunc_mode == SSS_TRUNC_COVERAGE ? fmin(hs, gauss ? 9.0 : nuc * expm1(9.0 / nuc)) : hs;
+    hr = op.trunc_mode == SSS_TRUNC_COVERAGE ? fmin(hs, gauss ? 9.0 : nuc * expm1(9.0 / nuc)) : hs;
     const double erx = sqrt(hr * g.A), ery = sqrt(hr * g.D);
     const double lx = (mx - erx) * (1.0 / kTile), hx = (mx + erx) * (1.0 / kTile);
     const double ly = (my - ery) * (1.0 / kTile), hy = (my + ery) * (1.0 / kTile);
@@ -250,10 +251,19 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     x0 = (int)fmax(0.0, floor(lx)); x1 = (int)fmin((double)(c.tiles_x - 1), floor(hx));
     y0 = (int)fmax(0.0, floor(ly)); y1 = (int)fmin((double)(c.tiles_y - 1), floor(hy));
   } else {
-    hs = __builtin_inf();
+    hs = hr = __builtin_inf();
     ey = __builtin_inf();
     x0 = 0; x1 = c.tiles_x - 1; y0 = 0; y1 = c.tiles_y - 1;
   }
+  // the rectangle's rows, each cut to the ellipse's extent
+  const Ellipse el{g.A, g.B, g.D, hr};
+  const RowGeo rg = make_row_geo(mx, my, el);
+  int count = 0;
+  for (int ty = y0; ty <= y1; ++ty) {
+    int t0;
+    count += row_run(rg, ty, x0, x1, &t0);
+  }
+  if (count == 0) return;
 
   double dir[3], vn;
   view_dir<double>(c, mu, dir, &vn);
@@ -286,7 +296,8 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   r.ey = (float)ey;
   rec[e] = r;
   rects[e] = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1);
-  touched[e] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+  ell[e] = el;
+  touched[e] = (uint32_t)count;
 }
 
 // Backward of the geometry: per component, sum over views of the chain from
@@ -515,7 +526,7 @@ void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
 #define SSS_PROJ(D)                                                                                          \
   SSS_LAUNCH("project", project_kernel<D>, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, s.means, s.scales, \
              s.quats, s.nu, s.opacity, s.sh, (Rec*)out.records, out.depth_key, (ushort4*)out.rect,            \
-             out.tiles_touched)
+             out.tiles_touched, (Ellipse*)out.ellipse)
   switch (s.sh_degree) {
     case 0: SSS_PROJ(0); break;
     case 1: SSS_PROJ(1); break;

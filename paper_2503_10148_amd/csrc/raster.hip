@@ -25,6 +25,7 @@
 #include <stdlib.h>
 
 #include "common.hpp"
+#include "tiles.hpp"
 
 namespace sss {
 namespace {
@@ -184,21 +185,25 @@ __device__ __forceinline__ void stage_batch(const TileCtx<PIX>& t, const Rec* __
   if (k < stop) stage(srec, pair_rank[k], t.ox, t.oy, lds + threadIdx.x);
 }
 
-// The same, also recording each pair's emission position (rank offset plus
-// the tile's row-major index inside the component's rectangle).
+// The same, also recording each pair's emission position: the rank's offset
+// plus the number of the entry's listed tiles before this one (rows above,
+// then columns to the left in this row), from the same row_run as the
+// emission.
 template <int PIX>
 __device__ __forceinline__ void stage_batch_slot(const TileCtx<PIX>& t, const Rec* __restrict__ srec,
-                                                 const uint32_t* __restrict__ pair_rank,
-                                                 const uint32_t* __restrict__ rank_off,
-                                                 const ushort4* __restrict__ rects, uint32_t base, uint32_t stop,
-                                                 LRec* lds) {
+                                                 const uint32_t* __restrict__ pair_rank, const DetArgs& det,
+                                                 uint32_t base, uint32_t stop, LRec* lds) {
   const uint32_t k = base + threadIdx.x;
   if (k < stop) {
     const uint32_t rank = pair_rank[k];
     const uint32_t e = stage(srec, rank, t.ox, t.oy, lds + threadIdx.x);
-    const ushort4 rc = rects[e];
-    lds[threadIdx.x].slot =
-        rank_off[rank] + (uint32_t)((t.ty - (int)rc.y) * ((int)rc.z - (int)rc.x + 1) + (t.tx - (int)rc.x));
+    const ushort4 rc = det.rects[e];
+    const RowGeo g = make_row_geo(srec[rank].mx, srec[rank].my, det.ell[e]);
+    uint32_t pos = det.rank_off[rank];
+    int t0;
+    for (int ty = rc.y; ty < t.ty; ++ty) pos += (uint32_t)row_run(g, ty, rc.x, rc.z, &t0);
+    row_run(g, t.ty, rc.x, rc.z, &t0);
+    lds[threadIdx.x].slot = pos + (uint32_t)(t.tx - t0);
   }
 }
 
@@ -387,7 +392,7 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   }
   for (uint32_t base = t.start; base < stop; base += kBatch) {
     __syncthreads();
-    if (kDet) stage_batch_slot<PIX>(t, srec, pair_rank, det.rank_off, det.rects, base, stop, lds);
+    if (kDet) stage_batch_slot<PIX>(t, srec, pair_rank, det, base, stop, lds);
     else stage_batch<PIX>(t, srec, pair_rank, base, stop, lds);
     __syncthreads();
     const int cnt = (int)min(kBatch, stop - base);
@@ -451,7 +456,7 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
           v4 = wave_sum63(v4); v5 = wave_sum63(v5); v6 = wave_sum63(v6); v7 = wave_sum63(v7);
           v8 = wave_sum63(v8); v9 = wave_sum63(v9);
         }
-        if (lane == 63) {
+        if (lane == 63 && L.slot < det.n_pairs) {
           float4* q = reinterpret_cast<float4*>(det.part + (size_t)L.slot * kG2);
           q[0] = make_float4(-2.0f * v0, -2.0f * v1, v2, 2.0f * v3);
           q[1] = make_float4(v4, v5, v6, v7);
@@ -479,44 +484,74 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   }
 }
 
-// Deterministic sum of the pair slots: one wave per visible rank r.  Lane l
-// adds the slots k = l, l + 64, ... of r's emission range in order (skipping
-// tiles whose walk stopped before r), then a fixed DPP tree sums the lanes and
-// lane 63 writes the entry's screen-space gradient.
+// Deterministic sum of the pair slots.  A wave takes 64 visible ranks: each
+// lane evaluates its rank's rows into the wave's row table, then for each
+// rank in turn the wave walks its listed tiles in emission order; lane l adds
+// the slots it is handed (positions l, l + 64, ... of each row) in that
+// order, skipping tiles whose walk stopped before the rank; a fixed DPP tree
+// sums the lanes and lane 63 writes the entry's screen-space gradient.
 __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t n, int64_t n_vis, uint32_t m,
-                                                            DetArgs det, float* __restrict__ g2) {
-  const int64_t r = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+                                                            const Rec* __restrict__ srec, DetArgs det,
+                                                            float* __restrict__ g2) {
+  __shared__ RowTable s_rows[kBlock / 64];
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  if (r >= n_vis) return;   // uniform per wave
-  const uint32_t e = det.order[r];
-  const uint32_t off = det.rank_off[r];
-  const uint32_t cnt = (r + 1 < n_vis ? det.rank_off[r + 1] : m) - off;
-  const ushort4 rc = det.rects[e];
-  const int v = (int)(e / (uint64_t)n);
-  int toff = 0, tiles_x = 1;
-  for (int k = 0; k < cb.n_views; ++k)
-    if (k == v) { toff = cb.v[k].tile_offset; tiles_x = cb.v[k].tiles_x; }
-  const int w = (int)rc.z - (int)rc.x + 1;
-  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, a4 = 0.0f, a5 = 0.0f, a6 = 0.0f, a7 = 0.0f, a8 = 0.0f,
-        a9 = 0.0f;
-  for (uint32_t k = (uint32_t)lane; k < cnt; k += 64) {
-    const int q = (int)k / w, c = (int)k - q * w;
-    const int tile = toff + ((int)rc.y + q) * tiles_x + (int)rc.x + c;
-    if ((uint32_t)r < det.lastp1[tile]) {
-      const float4* p = reinterpret_cast<const float4*>(det.part + (size_t)(off + k) * kG2);
-      const float4 x = p[0], y = p[1], z = p[2];
-      a0 += x.x; a1 += x.y; a2 += x.z; a3 += x.w;
-      a4 += y.x; a5 += y.y; a6 += y.z; a7 += y.w;
-      a8 += z.x; a9 += z.y;
-    }
+  RowTable* table = &s_rows[threadIdx.x >> 6];
+  const bool valid = r < n_vis;
+  int my_e = 0, my_off = 0, my_cnt = 0, my_toff = 0, my_tx = 1;
+  ushort4 rc = make_ushort4(0, 0, 0, 0);
+  double mx = 0.0, my = 0.0;
+  Ellipse el{1.0, 0.0, 1.0, 0.0};
+  if (valid) {
+    const uint32_t e = det.order[r];
+    my_e = (int)e;
+    my_off = (int)det.rank_off[r];
+    my_cnt = (int)((r + 1 < n_vis ? det.rank_off[r + 1] : m) - (uint32_t)my_off);
+    rc = det.rects[e];
+    el = det.ell[e];
+    mx = srec[r].mx;
+    my = srec[r].my;
+    const int v = (int)(e / (uint64_t)n);
+    for (int k = 0; k < cb.n_views; ++k)
+      if (k == v) { my_toff = cb.v[k].tile_offset; my_tx = cb.v[k].tiles_x; }
   }
-  a0 = wave_sum63(a0); a1 = wave_sum63(a1); a2 = wave_sum63(a2); a3 = wave_sum63(a3); a4 = wave_sum63(a4);
-  a5 = wave_sum63(a5); a6 = wave_sum63(a6); a7 = wave_sum63(a7); a8 = wave_sum63(a8); a9 = wave_sum63(a9);
-  if (lane == 63) {
-    float4* g = reinterpret_cast<float4*>(g2 + (size_t)e * kG2);
-    g[0] = make_float4(a0, a1, a2, a3);
-    g[1] = make_float4(a4, a5, a6, a7);
-    g[2] = make_float4(a8, a9, 0.0f, 0.0f);
+  const WaveRows wr = wave_row_table(valid, mx, my, el, rc.x, rc.y, rc.z, rc.w, table);
+  __syncthreads();
+  const int64_t r0 = r - lane;
+  for (int j = 0; j < 64; ++j) {
+    if (r0 + j >= n_vis) break;   // uniform
+    const uint32_t rank = (uint32_t)(r0 + j);
+    const int cnt = bcast_i(my_cnt, j);
+    const uint32_t off = (uint32_t)bcast_i(my_off, j);
+    const int toff = bcast_i(my_toff, j), tiles_x = bcast_i(my_tx, j);
+    float a[10];
+#pragma unroll
+    for (int f = 0; f < 10; ++f) a[f] = 0.0f;
+    auto add = [&](int k, int x, int y) {
+      if (k < cnt && rank < det.lastp1[toff + y * tiles_x + x]) {
+        const float4* p = reinterpret_cast<const float4*>(det.part + (size_t)(off + (uint32_t)k) * kG2);
+        const float4 u = p[0], w = p[1], z = p[2];
+        a[0] += u.x; a[1] += u.y; a[2] += u.z; a[3] += u.w;
+        a[4] += w.x; a[5] += w.y; a[6] += w.z; a[7] += w.w;
+        a[8] += z.x; a[9] += z.y;
+      }
+    };
+    const int y0 = bcast_i(rc.y, j);
+    if (__builtin_amdgcn_readlane((int)wr.fits, j)) {
+      for_each_tile_in_table(table, bcast_i(wr.base, j), bcast_i(wr.h, j), bcast_i(wr.total, j), y0, add);
+    } else {
+      const Ellipse ej{bcast_d(el.A, j), bcast_d(el.B, j), bcast_d(el.D, j), bcast_d(el.hr, j)};
+      for_each_listed_tile(bcast_d(mx, j), bcast_d(my, j), ej, bcast_i(rc.x, j), y0, bcast_i(rc.z, j),
+                           bcast_i(rc.w, j), add);
+    }
+#pragma unroll
+    for (int f = 0; f < 10; ++f) a[f] = wave_sum63(a[f]);
+    if (lane == 63) {
+      float4* g = reinterpret_cast<float4*>(g2 + (size_t)bcast_i(my_e, j) * kG2);
+      g[0] = make_float4(a[0], a[1], a[2], a[3]);
+      g[1] = make_float4(a[4], a[5], a[6], a[7]);
+      g[2] = make_float4(a[8], a[9], 0.0f, 0.0f);
+    }
   }
 }
 
@@ -626,9 +661,9 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
     else { SSS_BWD_DET(SSS_BWD_RECOMPUTE, SSS_LOSS_L1); }
 #undef SSS_BWD_DET
     if (b.n_visible > 0) {
-      const unsigned gr = (unsigned)((b.n_visible + kBlock / 64 - 1) / (kBlock / 64));
+      const unsigned gr = (unsigned)((b.n_visible + kBlock - 1) / kBlock);
       SSS_LAUNCH("det_reduce", det_reduce_kernel, dim3(gr), dim3(kBlock), 0, st, cb, n, b.n_visible,
-                 (uint32_t)b.n_pairs, *det, g2);
+                 (uint32_t)b.n_pairs, sr, *det, g2);
     }
     if (loss == SSS_LOSS_L1 && loss_out)
       SSS_LAUNCH("det_loss", det_loss_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)det->loss_part,

@@ -100,7 +100,7 @@ class RenderServer:
         P = sum(r.pixels for r in reqs)
         E = V * self.n
         M = int(P * self.pairs_per_pixel * 1.25) + 1024
-        per_entry = _REC + 4 + 8 + 4 + 4 + _REC
+        per_entry = _REC + 4 + 8 + 4 + 32 + 4 + _REC
         ws = int(sss.lib().sss_bin_sort_workspace(E, M))
         return E * per_entry + P * (12 + 4 + 4) + 4 * M + ws
 

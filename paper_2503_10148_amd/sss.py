@@ -54,7 +54,7 @@ class RenderOpts(ctypes.Structure):
 
 class Proj(ctypes.Structure):
     _fields_ = [("records", ctypes.c_void_p), ("depth_key", ctypes.c_void_p), ("rect", ctypes.c_void_p),
-                ("tiles_touched", ctypes.c_void_p)]
+                ("tiles_touched", ctypes.c_void_p), ("ellipse", ctypes.c_void_p)]
 
 
 class Bins(ctypes.Structure):
@@ -241,9 +241,11 @@ class Projected:
     depth_key: torch.Tensor    # int32 [E] (uint32 bits)
     rect: torch.Tensor         # int16 [E, 4]
     touched: torch.Tensor      # int32 [E]
+    ellipse: torch.Tensor      # float64 [E, 4]
 
     def struct(self):
-        return Proj(self.records.data_ptr(), self.depth_key.data_ptr(), self.rect.data_ptr(), self.touched.data_ptr())
+        return Proj(self.records.data_ptr(), self.depth_key.data_ptr(), self.rect.data_ptr(), self.touched.data_ptr(),
+                    self.ellipse.data_ptr())
 
 
 def project(scene, cams, opts=None, stream=None, out: Projected | None = None) -> Projected:
@@ -254,7 +256,8 @@ def project(scene, cams, opts=None, stream=None, out: Projected | None = None) -
         out = Projected(torch.empty((E, RECORD_BYTES), dtype=torch.uint8, device=dev),
                         torch.empty(E, dtype=torch.int32, device=dev),
                         torch.empty((E, 4), dtype=torch.int16, device=dev),
-                        torch.empty(E, dtype=torch.int32, device=dev))
+                        torch.empty(E, dtype=torch.int32, device=dev),
+                        torch.empty((E, 4), dtype=torch.float64, device=dev))
     s = scene_struct(scene)
     p = out.struct()
     _check(lib().sss_project(ctypes.byref(s), camera_array(cams), len(cams), ctypes.byref(render_opts(opts)),

@@ -69,7 +69,7 @@ def _scene_struct(sss, n=10, deg=0, null=None):
 
 
 def _proj_struct(sss):
-    return sss.Proj(0x2000, 0x3000, 0x4000, 0x5000)
+    return sss.Proj(0x2000, 0x3000, 0x4000, 0x5000, 0x5800)
 
 
 @pytest.mark.parametrize("kind", ["null_scene", "bad_degree", "zero_n", "null_array", "no_views", "too_many_views",

@@ -98,6 +98,9 @@ def test_project_matches_oracle(sss, name):
     # half extent in y of the truncation ellipse: sqrt(h* Sigma2D_yy)
     np.testing.assert_allclose(rec["ey"][m], np.sqrt(o["hstar"][m] * o["cov2d"][m, 2]), rtol=2e-7)
     assert np.array_equal(rec["entry"][m], np.nonzero(m)[0])
+    ell = proj.ellipse.cpu().numpy()
+    np.testing.assert_allclose(ell[m, :3], o["cov2d"][m], rtol=1e-12, atol=1e-12 * np.abs(o["cov2d"][m]).max())
+    np.testing.assert_allclose(ell[m, 3], o["hrect"][m], rtol=1e-12)
 
 
 # ---------------------------------------------------------------------------
@@ -105,7 +108,8 @@ def test_project_matches_oracle(sss, name):
 # ---------------------------------------------------------------------------
 def test_bin_sort_bit_exact_on_synthetic_inputs(sss):
     """Given identical rectangles and keys (many ties), the GPU lists equal the
-    oracle's (tile, key, index) order exactly; records are gathered verbatim."""
+    oracle's (tile, key, index) order exactly; records are gathered verbatim.
+    The ellipses have an infinite level, so whole rectangles are listed."""
     rng = np.random.default_rng(101)
     cams = [scenes.ring_camera(100, 90, angle=0.0), scenes.ring_camera(61, 37, angle=1.0),
             scenes.ring_camera(300, 20, angle=2.0)]
@@ -128,8 +132,10 @@ def test_bin_sort_bit_exact_on_synthetic_inputs(sss):
             rect[e] = (x0, y0, x1, y1)
             touched[e] = (x1 - x0 + 1) * (y1 - y0 + 1)
     records = rng.integers(0, 256, (E, 64), dtype=np.uint8)
+    ell = np.tile(np.array([1.0, 0.0, 1.0, np.inf]), (E, 1))
     proj = sss.Projected(torch.as_tensor(records, device="cuda"), torch.as_tensor(keys.view(np.int32), device="cuda"),
-                         torch.as_tensor(rect, device="cuda"), torch.as_tensor(touched, device="cuda"))
+                         torch.as_tensor(rect, device="cuda"), torch.as_tensor(touched, device="cuda"),
+                         torch.as_tensor(ell, device="cuda"))
     bins = sss.BinSorter(16)(proj, cams, n)
     torch.cuda.synchronize()
     vis = np.nonzero(touched > 0)[0]
@@ -172,7 +178,7 @@ def test_tile_lists_end_to_end(sss, name):
     n = scene["means"].shape[0]
     o = oracle.project(scene, cam)
     tx, ty = oracle.tiles(cam)
-    ost, olst = oracle.bin_tiles(o["touched"], o["rect"], o["key"], tx, ty)
+    ost, olst = oracle.bin_tiles(o["touched"], o["rect"], o["key"], tx, ty, proj=o)
     proj = sss.project(to_device(scene), cams)
     bins = sss.BinSorter(1024)(proj, cams, n)
     torch.cuda.synchronize()

@@ -281,28 +281,73 @@ def test_brute_force_equals_tiled(oracle_lib, seed, n, W, H, deg):
     assert np.array_equal(a["tfinal"], b["tfinal"])
 
 
-def test_tile_lists_are_rect_membership_in_depth_order(oracle_lib):
-    s = scenes.make_scene(800, 0, seed=41)
+def _box_min_h(conic, m, bx0, bx1, by0, by1):
+    """Minimum of d^T Q d over the box [bx0, bx1] x [by0, by1] (d = p - m): the
+    centre if inside, else the smallest of the four edge minima (on an edge the
+    form is a 1D quadratic, minimised at its vertex clamped to the edge)."""
+    a, b, c = conic
+    if bx0 <= m[0] <= bx1 and by0 <= m[1] <= by1:
+        return 0.0
+    best = np.inf
+    for x in (bx0, bx1):                       # vertical edges: minimise over y
+        dx = x - m[0]
+        dy = np.clip(-b * dx / c, by0 - m[1], by1 - m[1])
+        best = min(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+    for y in (by0, by1):                       # horizontal edges: minimise over x
+        dy = y - m[1]
+        dx = np.clip(-b * dy / a, bx0 - m[0], bx1 - m[0])
+        best = min(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+    return best
+
+
+def test_tile_lists_are_ellipse_membership_in_depth_order(oracle_lib):
+    """A component is listed in exactly the tiles of its rectangle whose box of
+    pixel centres meets its ellipse h <= h_rect (minimum of the quadratic form
+    over the box, computed edge by edge), in (depth key, index) order."""
+    s = scenes.make_scene(800, 0, seed=41, neg_frac=0.2)
+    s["scales"] *= np.float32(2.0)
     cam = scenes.ring_camera(200, 130, angle=1.0)
     p = oracle_lib.project(s, cam)
     tx, ty = oracle_lib.tiles(cam)
-    start, lst = oracle_lib.bin_tiles(p["touched"], p["rect"], p["key"], tx, ty)
+    start, lst = oracle_lib.bin_tiles(p["touched"], p["rect"], p["key"], tx, ty, proj=p)
+    member = {t: [] for t in range(tx * ty)}
+    unsure = set()
+    saved = 0
+    for i in np.nonzero(p["touched"] > 0)[0]:
+        x0, y0, x1, y1 = p["rect"][i]
+        for y in range(y0, y1 + 1):
+            for x in range(x0, x1 + 1):
+                hmin = _box_min_h(p["conic"][i], p["mean2d"][i], 16 * x + 0.5, 16 * x + 15.5, 16 * y + 0.5,
+                                  16 * y + 15.5)
+                if abs(hmin - p["hrect"][i]) <= 1e-7 * p["hrect"][i]:
+                    unsure.add(i)
+                if hmin <= p["hrect"][i]:
+                    member[y * tx + x].append(i)
+                else:
+                    saved += 1
+    assert saved > 0                                          # the ellipse test drops rectangle tiles
     key = p["key"].astype(np.int64)
     for t in range(tx * ty):
-        x, y = t % tx, t // tx
-        r = p["rect"]
-        inside = np.nonzero((p["touched"] > 0) & (r[:, 0] <= x) & (x <= r[:, 2]) & (r[:, 1] <= y) & (y <= r[:, 3]))[0]
-        want = inside[np.lexsort((inside, key[inside]))]
-        assert np.array_equal(lst[start[t]:start[t + 1]], want)
+        inside = np.array(member[t], np.int64)
+        want = inside[np.lexsort((inside, key[inside]))] if inside.size else inside
+        got = lst[start[t]:start[t + 1]]
+        assert np.array_equal([g for g in got if g not in unsure], [w for w in want if w not in unsure]), t
+    assert int(p["touched"].sum()) == len(lst)
 
 
 def test_truncation_is_lossless(oracle_lib):
-    """Every pixel where |o T2D| >= alpha_min lies in a tile of the component's rect."""
+    """Every pixel where |o T2D| >= alpha_min lies in a tile that lists the component."""
     s = scenes.make_scene(300, 0, seed=42, neg_frac=0.5)
     s["scales"] *= np.float32(4.0)
     cam = scenes.ring_camera(160, 120, angle=0.3)
     p = oracle_lib.project(s, cam)
+    tx, ty = oracle_lib.tiles(cam)
+    start, lst = oracle_lib.bin_tiles(p["touched"], p["rect"], p["key"], tx, ty, proj=p)
+    listed = np.zeros((p["valid"].shape[0], tx * ty), bool)
+    for t in range(tx * ty):
+        listed[lst[start[t]:start[t + 1]], t] = True
     ys, xs = np.mgrid[0:120, 0:160]
+    tile = (ys // 16) * tx + xs // 16
     amin = np.float64(np.float32(1 / 255))
     for i in np.nonzero(p["valid"])[0]:
         a, b, c = p["conic"][i]
@@ -311,8 +356,7 @@ def test_truncation_is_lossless(oracle_lib):
         nu = p["nu_c"][i]
         alpha = p["opacity"][i] * (1 + h / nu) ** (-(nu + 2) / 2)
         hit = np.abs(alpha) >= amin * (1 + 1e-9)
-        r = p["rect"][i]
-        assert np.all((xs[hit] // 16 >= r[0]) & (xs[hit] // 16 <= r[2]) & (ys[hit] // 16 >= r[1]) & (ys[hit] // 16 <= r[3]))
+        assert np.all(listed[i, tile[hit]])
 
 
 # ---------------------------------------------------------------------------
