@@ -120,6 +120,59 @@ __device__ __forceinline__ float wave_sum63(float v) {
   return v;
 }
 
+template <int kCtrl>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, false));
+}
+
+// One halving step of the transposed reduction: the n values are split into
+// a low half [0, h) and a high half [h, n) (zero-padded to h); a lane whose
+// selector bit is 0 keeps the low half and sends the high one to its partner
+// (which keeps the high half), and adds what the partner sends.
+template <int kCtrl, int N>
+__device__ __forceinline__ void halve(const float (&a)[N], float (&out)[(N + 1) / 2], bool bit) {
+  constexpr int H = (N + 1) / 2;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const float hi = (H + i < N) ? a[H + i] : 0.0f;
+    const float keep = bit ? hi : a[i];
+    const float send = bit ? a[i] : hi;
+    out[i] = keep + dpp_mov<kCtrl>(send);
+  }
+}
+
+// Wave sums of ten per-lane values, transposed: afterwards lane l holds the
+// wave sum of value tr_index(l) (lanes where tr_index is -1 hold 0).  Four
+// halving steps inside each row of 16 lanes, with partners l^8 (row_ror:8),
+// l^7 (row_half_mirror), l^3 and l^1 (quad permutations), whose xor masks
+// span all 16 lanes, then two exchanges across rows.  About 40 instructions
+// instead of ten 6-step reductions, and the ten sums end in ten lanes of one
+// row, so one memory instruction can store or add them all.
+__device__ __forceinline__ float wave_sum10_transposed(const float (&v)[10]) {
+  const int lane = threadIdx.x & 63;
+  float a[5], b[3], c[2], d[1];
+  halve<0x128, 10>(v, a, lane & 8);   // row_ror:8
+  halve<0x141, 5>(a, b, lane & 4);    // row_half_mirror
+  halve<0x1B, 3>(b, c, lane & 2);     // quad_perm [3,2,1,0]
+  halve<0xB1, 2>(c, d, lane & 1);     // quad_perm [1,0,3,2]
+  float x = d[0];
+  x += __shfl_xor(x, 16, 64);
+  x += __shfl_xor(x, 32, 64);
+  return x;
+}
+
+// Which of the ten values lane l holds after wave_sum10_transposed (-1: none).
+__device__ __forceinline__ int tr_index(int lane) {
+  const int b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1, b1 = (lane >> 1) & 1, b0 = lane & 1;
+  if ((b1 & b0) | (b2 & b1)) return -1;
+  return 5 * b3 + 3 * b2 + 2 * b1 + b0;
+}
+
+// Scale of each screen-space gradient component as stored: d/d mean (x, y)
+// and d/d conic b carry the factors of h = a dx^2 + 2 b dx dy + c dy^2 with
+// d = pixel - mean.
+__device__ __forceinline__ float g2_scale(int idx) { return idx < 2 ? -2.0f : (idx == 3 ? 2.0f : 1.0f); }
+
 // Pixels of one tile owned by a thread: with PIX pixels per thread the
 // workgroup has 256/PIX threads; thread t owns column t % 16 and the rows
 // t/16 + k*(256/PIX)/16, k < PIX.
@@ -399,8 +452,9 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
     for (int j = 0; j < cnt; ++j) {
       const uint32_t pos = base - t.start + (uint32_t)j;
       const LRec L = lds[j];
-      float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f;
-      float v5 = 0.0f, v6 = 0.0f, v7 = 0.0f, v8 = 0.0f, v9 = 0.0f;
+      float v[10];
+#pragma unroll
+      for (int f = 0; f < 10; ++f) v[f] = 0.0f;
       bool hit = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
@@ -416,23 +470,23 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
         gA[k] = __fmaf_rn(w, gc, gA[k]);
         const float gR = gout[k] - gA[k];
         const float da = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), Tk * gc);
-        v5 = __fmaf_rn(g[k][0], w, v5);
-        v6 = __fmaf_rn(g[k][1], w, v6);
-        v7 = __fmaf_rn(g[k][2], w, v7);
+        v[5] = __fmaf_rn(g[k][0], w, v[5]);
+        v[6] = __fmaf_rn(g[k][1], w, v[6]);
+        v[7] = __fmaf_rn(g[k][2], w, v[7]);
         T[k] = Tk * (1.0f - a);
         if (E.clamped) continue;
-        v8 = __fmaf_rn(da, E.t2, v8);
+        v[8] = __fmaf_rn(da, E.t2, v[8]);
         const float dt2 = da * L.o;
         const float ru = __builtin_amdgcn_rcpf(E.u);
         // d log2 T / dh = nb / (nu (1 + y)); nb ln 2 for the Gaussian family
         const float kh = L.inv_nu != 0.0f ? L.inv_nu * ru : kLn2;
         const float dh = dt2 * E.t2 * L.nb * kh;
-        v0 = __fmaf_rn(dh, E.ax, v0);
-        v1 = __fmaf_rn(dh, E.ay, v1);
+        v[0] = __fmaf_rn(dh, E.ax, v[0]);
+        v[1] = __fmaf_rn(dh, E.ay, v[1]);
         const float tq = dh * E.dx;
-        v2 = __fmaf_rn(tq, E.dx, v2);
-        v3 = __fmaf_rn(tq, E.dy, v3);
-        v4 = __fmaf_rn(dh * E.dy, E.dy, v4);
+        v[2] = __fmaf_rn(tq, E.dx, v[2]);
+        v[3] = __fmaf_rn(tq, E.dy, v[3]);
+        v[4] = __fmaf_rn(dh * E.dy, E.dy, v[4]);
         // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]
         const float y = E.y;
         float q;
@@ -447,66 +501,72 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
           q = __fmaf_rn(y, ru, -E.l2 * kLn2);
         }
         const float dtn = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
-        v9 = __fmaf_rn(dt2, dtn, v9);
+        v[9] = __fmaf_rn(dt2, dtn, v[9]);
       }
+      // sums over the wave, transposed: lane tr_index(l) of the first row
+      // holds component tr_index(l) of the entry's screen-space gradient
+      const int idx = tr_index(lane);
       if (kDet) {
         // every visited pair's slot is written, zeros when no pixel was hit
-        if (__any(hit)) {
-          v0 = wave_sum63(v0); v1 = wave_sum63(v1); v2 = wave_sum63(v2); v3 = wave_sum63(v3);
-          v4 = wave_sum63(v4); v5 = wave_sum63(v5); v6 = wave_sum63(v6); v7 = wave_sum63(v7);
-          v8 = wave_sum63(v8); v9 = wave_sum63(v9);
-        }
-        if (lane == 63 && L.slot < det.n_pairs) {
-          float4* q = reinterpret_cast<float4*>(det.part + (size_t)L.slot * kG2);
-          q[0] = make_float4(-2.0f * v0, -2.0f * v1, v2, 2.0f * v3);
-          q[1] = make_float4(v4, v5, v6, v7);
-          q[2] = make_float4(v8, v9, 0.0f, 0.0f);
-        }
+        const float x = __any(hit) ? wave_sum10_transposed(v) : 0.0f;
+        if (lane < 16 && idx >= 0 && L.slot < det.n_pairs) det.part[(size_t)L.slot * kG2 + idx] = g2_scale(idx) * x;
       } else if (__any(hit)) {
-        v0 = wave_sum63(v0); v1 = wave_sum63(v1); v2 = wave_sum63(v2); v3 = wave_sum63(v3);
-        v4 = wave_sum63(v4); v5 = wave_sum63(v5); v6 = wave_sum63(v6); v7 = wave_sum63(v7);
-        v8 = wave_sum63(v8); v9 = wave_sum63(v9);
-        if (lane == 63) {
-          float* gp = g2 + (size_t)L.entry * kG2;
-          atomicAdd(gp + 0, -2.0f * v0);
-          atomicAdd(gp + 1, -2.0f * v1);
-          atomicAdd(gp + 2, v2);
-          atomicAdd(gp + 3, 2.0f * v3);
-          atomicAdd(gp + 4, v4);
-          atomicAdd(gp + 5, v5);
-          atomicAdd(gp + 6, v6);
-          atomicAdd(gp + 7, v7);
-          atomicAdd(gp + 8, v8);
-          atomicAdd(gp + 9, v9);
-        }
+        const float x = wave_sum10_transposed(v);
+        if (lane < 16 && idx >= 0) atomicAdd(g2 + (size_t)L.entry * kG2 + idx, g2_scale(idx) * x);
       }
     }
   }
 }
 
-// Deterministic sum of the pair slots.  A wave takes 64 visible ranks: each
-// lane evaluates its rank's rows into the wave's row table, then for each
-// rank in turn the wave walks its listed tiles in emission order; lane l adds
-// the slots it is handed (positions l, l + 64, ... of each row) in that
-// order, skipping tiles whose walk stopped before the rank; a fixed DPP tree
-// sums the lanes and lane 63 writes the entry's screen-space gradient.
+// One step of a segmented inclusive scan over the wave: the value of the
+// lane the DPP control selects is added where that lane has the same key
+// (keys are non-decreasing over lanes and >= 1; lanes outside the row or
+// masked rows read key 0).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void seg_step(int key, float (&v)[10]) {
+  const int kk = __builtin_amdgcn_update_dpp(0, key, kCtrl, kRowMask, 0xf, true);
+  const bool same = kk == key;
+#pragma unroll
+  for (int f = 0; f < 10; ++f) {
+    const float t = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[f]), kCtrl, kRowMask, 0xf, true));
+    v[f] += same ? t : 0.0f;
+  }
+}
+
+// Deterministic sum of the pair slots.  A wave takes 64 consecutive visible
+// ranks, whose slots are one contiguous range in emission order.  Each lane
+// first evaluates its rank's rows into the wave's row table; the wave then
+// streams through the slot range 64 slots at a time (coalesced loads), each
+// lane finding its slot's rank and tile by binary search and zeroing slots
+// whose tile walk stopped before the rank; a segmented scan by rank sums each
+// rank's slots within the chunk and the segment's last lane adds the sum to
+// the rank's accumulator in LDS, chunk after chunk.  Ranks whose rows do not
+// fit the table are summed afterwards with for_each_listed_tile.  The result
+// depends only on the data, never on scheduling.
 __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t n, int64_t n_vis, uint32_t m,
                                                             const Rec* __restrict__ srec, DetArgs det,
                                                             float* __restrict__ g2) {
+  struct WaveMeta {
+    uint32_t off[65];
+    int base[64], h[64], total[64], y0[64], toff[64], tiles_x[64], fits[64];
+    float acc[64][10];
+  };
   __shared__ RowTable s_rows[kBlock / 64];
+  __shared__ WaveMeta s_meta[kBlock / 64];
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
   RowTable* table = &s_rows[threadIdx.x >> 6];
+  WaveMeta& M = s_meta[threadIdx.x >> 6];
   const bool valid = r < n_vis;
-  int my_e = 0, my_off = 0, my_cnt = 0, my_toff = 0, my_tx = 1;
+  int my_e = 0, my_toff = 0, my_tx = 1;
+  uint32_t my_off = m;
   ushort4 rc = make_ushort4(0, 0, 0, 0);
   double mx = 0.0, my = 0.0;
   Ellipse el{1.0, 0.0, 1.0, 0.0};
   if (valid) {
     const uint32_t e = det.order[r];
     my_e = (int)e;
-    my_off = (int)det.rank_off[r];
-    my_cnt = (int)((r + 1 < n_vis ? det.rank_off[r + 1] : m) - (uint32_t)my_off);
+    my_off = det.rank_off[r];
     rc = det.rects[e];
     el = det.ell[e];
     mx = srec[r].mx;
@@ -516,42 +576,104 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
       if (k == v) { my_toff = cb.v[k].tile_offset; my_tx = cb.v[k].tiles_x; }
   }
   const WaveRows wr = wave_row_table(valid, mx, my, el, rc.x, rc.y, rc.z, rc.w, table);
-  __syncthreads();
   const int64_t r0 = r - lane;
+  M.off[lane] = my_off;
+  if (lane == 63) M.off[64] = r0 + 64 < n_vis ? det.rank_off[r0 + 64] : m;
+  M.base[lane] = wr.base;
+  M.h[lane] = wr.h;
+  M.total[lane] = wr.total;
+  M.y0[lane] = rc.y;
+  M.toff[lane] = my_toff;
+  M.tiles_x[lane] = my_tx;
+  M.fits[lane] = valid && wr.fits;
+#pragma unroll
+  for (int f = 0; f < 10; ++f) M.acc[lane][f] = 0.0f;
+  __syncthreads();
+  if (r0 >= n_vis) return;   // uniform per wave; no barrier follows
+  const uint32_t s0 = M.off[0], s1 = M.off[64];
+  for (uint32_t c0 = s0; c0 < s1; c0 += 64) {
+    const uint32_t s = c0 + (uint32_t)lane;
+    const bool in = s < s1;
+    // rank of the slot: last rho with off[rho] <= s
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (M.off[mid] <= s) lo = mid;
+      else hi = mid - 1;
+    }
+    const int rho = lo;
+    float v[10];
+#pragma unroll
+    for (int f = 0; f < 10; ++f) v[f] = 0.0f;
+    if (in && M.fits[rho]) {
+      const int k = (int)(s - M.off[rho]);
+      if (k < M.total[rho]) {
+        const int b = M.base[rho];
+        int qlo = 0, qhi = M.h[rho] - 1;
+        while (qlo < qhi) {
+          const int mid = (qlo + qhi + 1) >> 1;
+          if ((int)table->cum[b + mid] <= k) qlo = mid;
+          else qhi = mid - 1;
+        }
+        const int x = (int)table->t0[b + qlo] + (k - (int)table->cum[b + qlo]);
+        const int y = M.y0[rho] + qlo;
+        if ((uint32_t)(r0 + rho) < det.lastp1[M.toff[rho] + y * M.tiles_x[rho] + x]) {
+          const float4* p = reinterpret_cast<const float4*>(det.part + (size_t)s * kG2);
+          const float4 u = p[0], w = p[1], z = p[2];
+          v[0] = u.x; v[1] = u.y; v[2] = u.z; v[3] = u.w;
+          v[4] = w.x; v[5] = w.y; v[6] = w.z; v[7] = w.w;
+          v[8] = z.x; v[9] = z.y;
+        }
+      }
+    }
+    const int key = in ? rho + 1 : 65;
+    seg_step<0x111, 0xf>(key, v);   // row_shr:1
+    seg_step<0x112, 0xf>(key, v);   // row_shr:2
+    seg_step<0x114, 0xf>(key, v);   // row_shr:4
+    seg_step<0x118, 0xf>(key, v);   // row_shr:8
+    seg_step<0x142, 0xa>(key, v);   // row_bcast:15
+    seg_step<0x143, 0xc>(key, v);   // row_bcast:31
+    const int next = __shfl_down(key, 1, 64);
+    if (in && (lane == 63 || next != key)) {
+#pragma unroll
+      for (int f = 0; f < 10; ++f) M.acc[rho][f] += v[f];
+    }
+  }
+  // ranks whose rows did not fit the table
   for (int j = 0; j < 64; ++j) {
     if (r0 + j >= n_vis) break;   // uniform
+    if (M.fits[j]) continue;
     const uint32_t rank = (uint32_t)(r0 + j);
-    const int cnt = bcast_i(my_cnt, j);
-    const uint32_t off = (uint32_t)bcast_i(my_off, j);
-    const int toff = bcast_i(my_toff, j), tiles_x = bcast_i(my_tx, j);
+    const uint32_t off = M.off[j];
+    const int cnt = (int)(M.off[j + 1] - off);
+    const int toff = M.toff[j], tiles_x = M.tiles_x[j];
     float a[10];
 #pragma unroll
     for (int f = 0; f < 10; ++f) a[f] = 0.0f;
-    auto add = [&](int k, int x, int y) {
-      if (k < cnt && rank < det.lastp1[toff + y * tiles_x + x]) {
-        const float4* p = reinterpret_cast<const float4*>(det.part + (size_t)(off + (uint32_t)k) * kG2);
-        const float4 u = p[0], w = p[1], z = p[2];
-        a[0] += u.x; a[1] += u.y; a[2] += u.z; a[3] += u.w;
-        a[4] += w.x; a[5] += w.y; a[6] += w.z; a[7] += w.w;
-        a[8] += z.x; a[9] += z.y;
-      }
-    };
-    const int y0 = bcast_i(rc.y, j);
-    if (__builtin_amdgcn_readlane((int)wr.fits, j)) {
-      for_each_tile_in_table(table, bcast_i(wr.base, j), bcast_i(wr.h, j), bcast_i(wr.total, j), y0, add);
-    } else {
-      const Ellipse ej{bcast_d(el.A, j), bcast_d(el.B, j), bcast_d(el.D, j), bcast_d(el.hr, j)};
-      for_each_listed_tile(bcast_d(mx, j), bcast_d(my, j), ej, bcast_i(rc.x, j), y0, bcast_i(rc.z, j),
-                           bcast_i(rc.w, j), add);
-    }
+    const Ellipse ej{bcast_d(el.A, j), bcast_d(el.B, j), bcast_d(el.D, j), bcast_d(el.hr, j)};
+    for_each_listed_tile(bcast_d(mx, j), bcast_d(my, j), ej, bcast_i(rc.x, j), bcast_i(rc.y, j), bcast_i(rc.z, j),
+                         bcast_i(rc.w, j), [&](int k, int x, int y) {
+                           if (k < cnt && rank < det.lastp1[toff + y * tiles_x + x]) {
+                             const float4* p =
+                                 reinterpret_cast<const float4*>(det.part + (size_t)(off + (uint32_t)k) * kG2);
+                             const float4 u = p[0], w = p[1], z = p[2];
+                             a[0] += u.x; a[1] += u.y; a[2] += u.z; a[3] += u.w;
+                             a[4] += w.x; a[5] += w.y; a[6] += w.z; a[7] += w.w;
+                             a[8] += z.x; a[9] += z.y;
+                           }
+                         });
 #pragma unroll
     for (int f = 0; f < 10; ++f) a[f] = wave_sum63(a[f]);
     if (lane == 63) {
-      float4* g = reinterpret_cast<float4*>(g2 + (size_t)bcast_i(my_e, j) * kG2);
-      g[0] = make_float4(a[0], a[1], a[2], a[3]);
-      g[1] = make_float4(a[4], a[5], a[6], a[7]);
-      g[2] = make_float4(a[8], a[9], 0.0f, 0.0f);
+#pragma unroll
+      for (int f = 0; f < 10; ++f) M.acc[j][f] = a[f];
     }
+  }
+  if (valid) {
+    float4* g = reinterpret_cast<float4*>(g2 + (size_t)my_e * kG2);
+    g[0] = make_float4(M.acc[lane][0], M.acc[lane][1], M.acc[lane][2], M.acc[lane][3]);
+    g[1] = make_float4(M.acc[lane][4], M.acc[lane][5], M.acc[lane][6], M.acc[lane][7]);
+    g[2] = make_float4(M.acc[lane][8], M.acc[lane][9], 0.0f, 0.0f);
   }
 }
 
