@@ -64,16 +64,21 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* __restr
 }
 
 // ---------------------------------------------------------------------------
-// 2./4. stable LSD radix sort, 8-bit digits
+// 2./4. stable LSD radix sort, digits of up to 8 bits
 // ---------------------------------------------------------------------------
+#ifndef SSS_RADIX_ITEMS
+#define SSS_RADIX_ITEMS 16
+#endif
+constexpr int kRItems = SSS_RADIX_ITEMS;           // items per thread of a radix pass
+constexpr int kRPerBlock = kBlock * kRItems;      // items per workgroup
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
                                                             int shift, uint32_t mask, int64_t nblocks,
                                                             uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kPerBlock;
-  for (int k = 0; k < kItems; ++k) {
+  const int64_t base = (int64_t)blockIdx.x * kRPerBlock;
+  for (int k = 0; k < kRItems; ++k) {
     const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
     if (j < n) atomicAdd(&h[(keys[j] >> shift) & mask], 1u);
   }
@@ -93,8 +98,8 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   __shared__ uint32_t cnt[4][256];
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t dofs[256];
-  __shared__ uint32_t sk[kPerBlock];
-  __shared__ uint32_t sv[kPerBlock];
+  __shared__ uint32_t sk[kRPerBlock];
+  __shared__ uint32_t sv[kRPerBlock];
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
   const uint32_t mask = (1u << bits) - 1u;
@@ -102,11 +107,11 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   gbase[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t block0 = (int64_t)blockIdx.x * kPerBlock;
-  const int64_t base = block0 + (int64_t)w * (kPerBlock / 4);
-  uint32_t key[kItems], val[kItems], loc[kItems];
+  const int64_t block0 = (int64_t)blockIdx.x * kRPerBlock;
+  const int64_t base = block0 + (int64_t)w * (kRPerBlock / 4);
+  uint32_t key[kRItems], val[kRItems], loc[kRItems];
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kRItems; ++r) {
     const int64_t j = base + (int64_t)r * 64 + lane;
     const bool ok = j < n;
     key[r] = ok ? keys[j] : 0u;
@@ -137,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   dofs[tid] = dstart;
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
+  for (int r = 0; r < kRItems; ++r) {
     const int64_t j = base + (int64_t)r * 64 + lane;
     if (j < n) {
       const uint32_t d = (key[r] >> shift) & mask;
@@ -147,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     }
   }
   __syncthreads();
-  const int in_block = (int)min((int64_t)kPerBlock, n - block0);
+  const int in_block = (int)min((int64_t)kRPerBlock, n - block0);
   for (int i = tid; i < in_block; i += kBlock) {
     const uint32_t k = sk[i];
     const uint32_t d = (k >> shift) & mask;
@@ -270,7 +275,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 Ws carve(void* base, int64_t n_entries, int64_t pair_cap) {
   const int64_t big = n_entries > pair_cap ? n_entries : pair_cap;
-  const int64_t nb = (big + kPerBlock - 1) / kPerBlock;
+  const int64_t nb = (big + kRPerBlock - 1) / kRPerBlock;
   Ws w;
   char* p = (char*)base;
   size_t off = 0;
@@ -301,7 +306,7 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
   const int width = (nbits + passes - 1) / passes;
   uint32_t* final_keys = ((passes - 1) % 2 == 0) ? kb : ka;
   if (n <= 0) return final_keys;
-  const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
+  const int64_t nb = (n + kRPerBlock - 1) / kRPerBlock;
   for (int p = 0; p < passes; ++p) {
     const int shift = width * p;
     const int bits = (nbits - shift) < width ? (nbits - shift) : width;

@@ -750,7 +750,7 @@ int env_pix(const char* name, int dflt) {
 
 void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, float* image, float* t_final,
                        uint32_t* n_contrib, hipStream_t st) {
-  static const int pix = env_pix("SSS_PIX_FWD", 2);
+  static const int pix = env_pix("SSS_PIX_FWD", 1);
   const dim3 grid((unsigned)cb.total_tiles);
   const Rec* sr = (const Rec*)b.sorted_records;
 #define SSS_FWD(P)                                                                                          \
@@ -766,7 +766,7 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                        const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
                        float* loss_out, float* g2, int64_t total_pixels, const DetArgs* det, int64_t n,
                        hipStream_t st) {
-  static const int pix = env_pix("SSS_PIX_BWD", 4);
+  static const int pix = env_pix("SSS_PIX_BWD", 2);
   const float inv_count = 1.0f / (3.0f * (float)total_pixels);
   const dim3 grid((unsigned)cb.total_tiles);
   const Rec* sr = (const Rec*)b.sorted_records;
