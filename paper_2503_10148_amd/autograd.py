@@ -6,7 +6,8 @@ forward: sss_project -> sss_bin_sort -> sss_render_fwd; backward:
 sss_render_bwd with the incoming dL/dimage.  mode "stored" keeps the
 forward image and per-pixel list positions for the backward; "recompute"
 keeps nothing per pixel and re-walks each tile's list in the backward, so
-memory stays flat in the image size.  The inputs are the activated
+memory stays flat in the image size.  deterministic=True makes the backward
+atomic-free: the gradients are bit-identical from run to run.  The inputs are the activated
 parameters (opacity already in [-1, 1], scales positive); activations and
 losses are ordinary torch operations around this function.
 
@@ -33,12 +34,14 @@ def _degree(sh: torch.Tensor) -> int:
 class _Ctx:
     """Buffers reused across calls (pair list, workspaces)."""
 
-    def __init__(self):
-        self.binner = sss.BinSorter(0)
+    def __init__(self, deterministic: bool = False):
+        self.binner = sss.BinSorter(0, keep_offsets=deterministic)
+        self.deterministic = deterministic
         self.bwd_ws = None
 
 
 _DEFAULT = _Ctx()
+_DEFAULT_DET = _Ctx(deterministic=True)
 
 
 class RenderFunction(torch.autograd.Function):
@@ -62,22 +65,29 @@ class RenderFunction(torch.autograd.Function):
     def backward(ctx, dl_dimage):
         st = ctx.state
         n = ctx.scene["means"].shape[0]
-        need = int(sss.lib().sss_render_bwd_workspace(n * len(ctx.cams)))
+        if st.deterministic:
+            need = int(sss.lib().sss_render_bwd_workspace_det(n * len(ctx.cams), ctx.bins.n_pairs,
+                                                              sss.total_tiles(ctx.cams)))
+        else:
+            need = int(sss.lib().sss_render_bwd_workspace(n * len(ctx.cams)))
         if st.bwd_ws is None or st.bwd_ws.numel() * 4 < need:
             st.bwd_ws = torch.empty(need // 4, dtype=torch.float32, device=dl_dimage.device)
         mode = sss.BWD_STORED if ctx.mode == "stored" else sss.BWD_RECOMPUTE
         grads = sss.render_bwd(ctx.scene, ctx.proj, ctx.bins, ctx.cams, dl_dimage.contiguous().float(), ctx.opts,
                                mode=mode, loss=sss.LOSS_GRAD, image=ctx.image, n_contrib=ctx.n_contrib,
-                               ws=st.bwd_ws)
+                               ws=st.bwd_ws, deterministic=st.deterministic)
         ctx.scene = ctx.proj = ctx.bins = ctx.image = ctx.n_contrib = None
         return tuple(grads[k] for k in _PARAMS) + (None, None, None, None)
 
 
-def render(means, scales, quats, nu, opacity, sh, cams, opts=None, mode: str = "stored", state: _Ctx | None = None):
+def render(means, scales, quats, nu, opacity, sh, cams, opts=None, mode: str = "stored", state: _Ctx | None = None,
+           deterministic: bool = False):
     """Differentiable render of all `cams` (list of camera dicts)."""
     if mode not in ("stored", "recompute"):
         raise ValueError(mode)
-    return RenderFunction.apply(means, scales, quats, nu, opacity, sh, list(cams), opts, mode, state or _DEFAULT)
+    if state is None:
+        state = _DEFAULT_DET if deterministic else _DEFAULT
+    return RenderFunction.apply(means, scales, quats, nu, opacity, sh, list(cams), opts, mode, state)
 
 
 def split_views(image: torch.Tensor, cams):

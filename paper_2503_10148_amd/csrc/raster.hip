@@ -38,7 +38,8 @@ struct __align__(16) LRec {
   float mx, my, qa, qb;      // mean relative to the tile origin; conic a, b
   float qc, hs, o, inv_nu;   // conic c; truncation test level; opacity; 1/nu
   float nb, cr, cg, cb;      // -(nu+2)/2; colour
-  float pad0, ey;            // -; half extent in y of the pre-test ellipse
+  uint32_t smask;            // bit s: the pre-test ellipse reaches tile rows 4s..4s+3
+  float ey;                  // half extent in y of the pre-test ellipse
   uint32_t entry;
   uint32_t slot;             // deterministic backward: the pair's emission position
 };
@@ -56,9 +57,16 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   l.inv_nu = r.inv_nu;
   l.nb = r.nb;
   l.cr = r.cr; l.cg = r.cg; l.cb = r.cb;
-  l.pad0 = 0.0f;
   // sqrt(1.0001) covers the widened pre-test level, the rest FP32 rounding
   l.ey = r.ey * 1.0001f + 1e-3f;
+  // strips of 4 pixel rows (centres 4s + 1/2 .. 4s + 7/2) the ellipse can reach
+  uint32_t m = 0;
+#pragma unroll
+  for (int st = 0; st < kTile / 4; ++st) {
+    const float y0 = (float)(4 * st) + 0.5f;
+    if (l.my + l.ey >= y0 && l.my - l.ey <= y0 + 3.0f) m |= 1u << st;
+  }
+  l.smask = m;
   l.entry = r.entry;
   l.slot = 0u;
   *dst = l;
@@ -220,13 +228,27 @@ __device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint3
   return t;
 }
 
-// Whether the ellipse of a staged record can reach the 16x4 pixel strip that
-// this wave covers in its k-th pixel group (rows 4w + k*rowstep .. +3).
+// The 16x4 pixel strips a wave covers: its k-th pixel group is rows
+// 4w + k*rowstep .. +3, i.e. strip w + k*rowstep/4.  Returns the strip bits
+// of all groups (wave-uniform) and each group's bit.
 template <int PIX>
-__device__ __forceinline__ bool strip_hit(const LRec& L, int k) {
+struct WaveStrips {
+  uint32_t all;
+  uint32_t bit[PIX];
+};
+
+template <int PIX>
+__device__ __forceinline__ WaveStrips<PIX> wave_strips() {
   constexpr int kRowStep = kBlock / PIX / kTile;
-  const float y0 = (float)((threadIdx.x >> 6) * 4 + k * kRowStep) + 0.5f;
-  return L.my + L.ey >= y0 && L.my - L.ey <= y0 + 3.0f;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  WaveStrips<PIX> ws;
+  ws.all = 0;
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    ws.bit[k] = 1u << (w + k * (kRowStep / 4));
+    ws.all |= ws.bit[k];
+  }
+  return ws;
 }
 
 // A batch is one staged record per thread.
@@ -276,6 +298,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
     last[k] = 0;
   }
   constexpr uint32_t kBatch = kBlock / PIX;
+  const WaveStrips<PIX> ws = wave_strips<PIX>();
   for (uint32_t base = t.start; base < t.end; base += kBatch) {
     bool alive = false;
 #pragma unroll
@@ -285,12 +308,15 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
     __syncthreads();
     const int cnt = (int)min(kBatch, t.end - base);
     for (int j = 0; j < cnt && alive; ++j) {
+      // records that miss every strip of this wave are skipped on a scalar branch
+      const uint32_t sm = __builtin_amdgcn_readfirstlane(lds[j].smask);
+      if (!(sm & ws.all)) continue;
       const LRec L = lds[j];
       alive = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
         if (done[k]) continue;
-        if (!strip_hit<PIX>(L, k)) {
+        if (!(sm & ws.bit[k])) {
           alive |= true;
           continue;
         }
@@ -437,6 +463,7 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   if (kDet && threadIdx.x == 0) det.lastp1[blockIdx.x] = stop > t.start ? pair_rank[stop - 1] + 1u : 0u;
 
   // ---- front-to-back gradient walk ----
+  const WaveStrips<PIX> ws = wave_strips<PIX>();
   float T[PIX], gA[PIX];
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
@@ -451,6 +478,16 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
     const int cnt = (int)min(kBatch, stop - base);
     for (int j = 0; j < cnt; ++j) {
       const uint32_t pos = base - t.start + (uint32_t)j;
+      const uint32_t sm = __builtin_amdgcn_readfirstlane(lds[j].smask);
+      if (!(sm & ws.all)) {
+        // no pixel of this wave can be hit; the deterministic mode still
+        // writes the pair's slot
+        if (kDet && lane < 16 && tr_index(lane) >= 0) {
+          const uint32_t slot = lds[j].slot;
+          if (slot < det.n_pairs) det.part[(size_t)slot * kG2 + tr_index(lane)] = 0.0f;
+        }
+        continue;
+      }
       const LRec L = lds[j];
       float v[10];
 #pragma unroll
@@ -458,7 +495,7 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
       bool hit = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
-        if (pos >= bound[k] || !strip_hit<PIX>(L, k)) continue;
+        if (pos >= bound[k] || !(sm & ws.bit[k])) continue;
         Eval E;
         evaluate(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
         if (!E.hit) continue;

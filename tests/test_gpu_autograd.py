@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from paper_2503_10148_amd import scenes
-from tests._util import PARAMS
+from tests._util import PARAMS, grad_close
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -110,6 +110,9 @@ def test_autograd_matches_finite_differences_on_training_workload(mods):
 
 
 def test_autograd_stored_and_recompute_agree(mods):
+    """The two backward modes make the same decisions: with the deterministic
+    backward their gradients are bit-identical; with float atomics (summation
+    order varies) they agree to the parity bar."""
     sss, ag = mods
     s = scenes.make_scene(20000, 3, seed=21, neg_frac=0.3)
     cams = [scenes.ring_camera(320, 240, angle=0.4), scenes.ring_camera(200, 150, angle=2.0)]
@@ -117,16 +120,21 @@ def test_autograd_stored_and_recompute_agree(mods):
     P = sum(c["width"] * c["height"] for c in cams)
     wt = torch.as_tensor(rng.standard_normal((P, 3)), dtype=torch.float32, device="cuda")
     out = {}
-    for mode in ("stored", "recompute"):
-        p = _leaf(s)
-        img = ag.render(p["means"], p["scales"], p["quats"], p["nu"], p["opacity"], p["sh"], cams, mode=mode)
-        (img * wt).sum().backward()
-        out[mode] = (img.detach().cpu().numpy(), {k: p[k].grad.cpu().numpy() for k in PARAMS})
-    assert np.array_equal(out["stored"][0], out["recompute"][0])
+    for det in (True, False):
+        for mode in ("stored", "recompute"):
+            p = _leaf(s)
+            img = ag.render(p["means"], p["scales"], p["quats"], p["nu"], p["opacity"], p["sh"], cams, mode=mode,
+                            deterministic=det)
+            (img * wt).sum().backward()
+            out[det, mode] = (img.detach().cpu().numpy(), {k: p[k].grad.cpu().numpy() for k in PARAMS})
+    assert np.array_equal(out[True, "stored"][0], out[True, "recompute"][0])
+    assert np.array_equal(out[False, "stored"][0], out[True, "stored"][0])
     for k in PARAMS:
-        a, b = out["stored"][1][k], out["recompute"][1][k]
-        scale = np.sqrt(np.mean(a ** 2))
-        assert np.all(np.abs(a - b) <= 1e-4 * np.maximum(np.abs(a), scale)), k
+        a, b = out[True, "stored"][1][k], out[True, "recompute"][1][k]
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), k
+        for mode in ("stored", "recompute"):
+            ok, worst = grad_close(out[False, mode][1][k], a)
+            assert ok, (k, mode, worst)
 
 
 def test_autograd_l1_through_torch_matches_oracle(mods):
