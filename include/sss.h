@@ -253,7 +253,8 @@ int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views
  *                           over all 3P values; loss_out (device float,
  *                           nullable) receives += L
  * grads: += or = (see sss_grads_t).  Workspace: ws_bytes >=
- * sss_render_bwd_workspace(n_views*n) (per-entry screen-space gradients).
+ * sss_render_bwd_workspace(n_views*n) (per-entry screen-space gradients,
+ * 12 FP64 each).
  * Errors: INVALID for NULL pointers, a short workspace, unknown mode/loss. */
 enum { SSS_BWD_STORED = 0, SSS_BWD_RECOMPUTE = 1, SSS_BWD_DETERMINISTIC = 4 };
 enum { SSS_LOSS_GRAD = 0, SSS_LOSS_L1 = 1 };

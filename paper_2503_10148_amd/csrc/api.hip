@@ -146,7 +146,7 @@ size_t sss_bin_sort_workspace(int64_t n_entries, int64_t pair_capacity) {
 
 size_t sss_render_bwd_workspace(int64_t n_entries) {
   if (n_entries < 0) return 0;
-  return (size_t)n_entries * kG2 * sizeof(float);
+  return (size_t)n_entries * kG2 * sizeof(double);
 }
 
 int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts,
@@ -236,7 +236,7 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
   }
   hipStream_t st = (hipStream_t)stream;
   const OptsDev op = make_opts(opts);
-  float* g2 = (float*)ws;
+  double* g2 = (double*)ws;
   DetArgs da{};
   if (det) {
     da = carve_det(ws, n_entries, bins->n_pairs, cb.total_tiles, &g2);
@@ -246,7 +246,7 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
     da.ell = (const Ellipse*)proj->ellipse;
     da.n_pairs = (uint32_t)bins->n_pairs;
   }
-  launch_zero(g2, n_entries * kG2, st);
+  launch_zero((float*)g2, n_entries * kG2 * 2, st);
   launch_render_bwd(cb, op, *bins, mode, loss, dl_or_target, image, n_contrib, image_out, loss_out, g2,
                     total_pixels(cb), det ? &da : nullptr, scene->n, st);
   launch_project_bwd(cb, op, *scene, proj->tiles_touched, g2, *grads, st);

@@ -50,8 +50,11 @@ struct __align__(16) Rec {
 };
 static_assert(sizeof(Rec) == SSS_RECORD_BYTES, "record size");
 
-// Number of float slots per entry in the screen-space gradient buffer:
-// d/d(mx, my), d/d(qa, qb, qc), d/d(cr, cg, cb), d/do, d/dnu (+2 pad).
+// Number of slots per entry in the screen-space gradient buffer:
+// d/d(mx, my), d/d(qa, qb, qc), d/d(cr, cg, cb), d/do, d/dnu (+2 pad).  The
+// per-entry buffer holds FP64 (it sums the partial sums of every tile the
+// entry is listed in, often with cancellation); the deterministic mode's
+// per-pair slots hold FP32.
 constexpr int kG2 = 12;
 
 // Brackets one kernel launch with HIP events when timing is enabled.
@@ -82,7 +85,7 @@ OptsDev make_opts(const sss_render_opts_t* o);
 void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
                     const sss_proj_t& out, hipStream_t st);
 void launch_project_bwd(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
-                        const uint32_t* touched, const float* g2, const sss_grads_t& g,
+                        const uint32_t* touched, const double* g2, const sss_grads_t& g,
                         hipStream_t st);
 int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins_t* bins,
                  void* ws, size_t ws_bytes, hipStream_t st);
@@ -108,10 +111,10 @@ struct DetArgs {
   uint32_t n_pairs;           // bound of the slots (part has n_pairs rows)
 };
 size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_tiles);
-DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, float** g2);
+DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, double** g2);
 void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, int mode,
                        int loss, const float* dl_or_target, const float* image,
-                       const uint32_t* n_contrib, float* image_out, float* loss_out, float* g2,
+                       const uint32_t* n_contrib, float* image_out, float* loss_out, double* g2,
                        int64_t total_pixels, const DetArgs* det, int64_t n, hipStream_t st);
 void launch_zero(float* p, int64_t count, hipStream_t st);
 size_t relocate_workspace(int64_t n, double max_fraction);

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
 __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     CamBatch cb, OptsDev op, int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
     const float* __restrict__ quats, const float* __restrict__ nu, const uint32_t* __restrict__ touched,
-    const float* __restrict__ g2, float* __restrict__ d_means, float* __restrict__ d_scales,
+    const double* __restrict__ g2, float* __restrict__ d_means, float* __restrict__ d_scales,
     float* __restrict__ d_quats, float* __restrict__ d_nu, float* __restrict__ d_opac, int overwrite) {
   using F = float;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -322,12 +322,11 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     if (touched[e] == 0) continue;
     any = true;
     const CamDev& c = cb.v[v];
-    const float4 ga4 = *reinterpret_cast<const float4*>(g2 + e * kG2);
-    const float4 gb4 = *reinterpret_cast<const float4*>(g2 + e * kG2 + 4);
-    const float2 gc2 = *reinterpret_cast<const float2*>(g2 + e * kG2 + 8);
-    const F gmx = ga4.x, gmy = ga4.y, gqa = ga4.z, gqb = ga4.w, gqc = gb4.x;
-    gop += gc2.x;
-    gnu += gc2.y;
+    const double2* gp = reinterpret_cast<const double2*>(g2 + e * kG2);
+    const double2 g01 = gp[0], g23 = gp[1], g45 = gp[2], g89 = gp[4];
+    const F gmx = (F)g01.x, gmy = (F)g01.y, gqa = (F)g23.x, gqb = (F)g23.y, gqc = (F)g45.x;
+    gop += (F)g89.x;
+    gnu += (F)g89.y;
 
     Geo<F> g;
     geometry<F>(c, op, mu, s, quats + 4 * i, g);
@@ -436,7 +435,7 @@ template <int DEG>
 __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, const float* __restrict__ means,
                                                         const float* __restrict__ sh,
                                                         const uint32_t* __restrict__ touched,
-                                                        const float* __restrict__ g2, float* __restrict__ d_means,
+                                                        const double* __restrict__ g2, float* __restrict__ d_means,
                                                         float* __restrict__ d_sh, int overwrite) {
   using F = float;
   constexpr int K = (DEG + 1) * (DEG + 1), KC = 3 * K, STR = KC + 1;
@@ -455,8 +454,8 @@ __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, 
       const int64_t e = (int64_t)v * n + i;
       if (touched[e] == 0) continue;
       const CamDev& c = cb.v[v];
-      const float4 gb4 = *reinterpret_cast<const float4*>(g2 + e * kG2 + 4);
-      const F gcol[3] = {gb4.y, gb4.z, gb4.w};
+      const double* gq = g2 + e * kG2;
+      const F gcol[3] = {(F)gq[5], (F)gq[6], (F)gq[7]};
       F dir[3], vn;
       view_dir<F>(c, mu, dir, &vn);
       F Yb[K];
@@ -494,8 +493,8 @@ __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, 
       const int64_t e = (int64_t)v * n + i;
       if (touched[e] == 0) continue;
       const CamDev& c = cb.v[v];
-      const float4 gb4 = *reinterpret_cast<const float4*>(g2 + e * kG2 + 4);
-      const F gcol[3] = {gb4.y, gb4.z, gb4.w};
+      const double* gq = g2 + e * kG2;
+      const F gcol[3] = {(F)gq[5], (F)gq[6], (F)gq[7]};
       F dir[3], vn;
       view_dir<F>(c, mu, dir, &vn);
       F Yb[K];
@@ -537,7 +536,7 @@ void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
 }
 
 void launch_project_bwd(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s, const uint32_t* touched,
-                        const float* g2, const sss_grads_t& gr, hipStream_t st) {
+                        const double* g2, const sss_grads_t& gr, hipStream_t st) {
   dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock));
 #define SSS_SHB(D)                                                                                         \
   SSS_LAUNCH("sh_bwd", sh_bwd_kernel<D>, grid, dim3(kBlock), 0, st, cb, (int64_t)s.n, s.means, s.sh, touched, \

@@ -288,13 +288,18 @@ template <int PIX>
 __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDev& op, const Rec* __restrict__ srec,
                                              const uint32_t* __restrict__ pair_rank, LRec* lds, float (*C)[3],
                                              float* Tout, uint32_t* last_out) {
+  // The colour sums are kept in FP64: the backward pass subtracts the colour
+  // accumulated up to a component from the output, and for components deep
+  // in a list (small T) an FP32 running sum's accumulated rounding would be
+  // a large part of that difference.  FP64 FMA issues at the FP32 rate here.
   bool done[PIX];
-  float T[PIX], c0[PIX], c1[PIX], c2[PIX];
+  float T[PIX];
+  double c0[PIX], c1[PIX], c2[PIX];
   uint32_t last[PIX];
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     done[k] = !t.inside[k];
-    T[k] = 1.0f; c0[k] = 0.0f; c1[k] = 0.0f; c2[k] = 0.0f;
+    T[k] = 1.0f; c0[k] = 0.0; c1[k] = 0.0; c2[k] = 0.0;
     last[k] = 0;
   }
   constexpr uint32_t kBatch = kBlock / PIX;
@@ -328,9 +333,9 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
             done[k] = true;
           } else {
             const float wgt = E.alpha * T[k];
-            c0[k] = __fmaf_rn(L.cr, wgt, c0[k]);
-            c1[k] = __fmaf_rn(L.cg, wgt, c1[k]);
-            c2[k] = __fmaf_rn(L.cb, wgt, c2[k]);
+            c0[k] = __fma_rn((double)L.cr, (double)wgt, c0[k]);
+            c1[k] = __fma_rn((double)L.cg, (double)wgt, c1[k]);
+            c2[k] = __fma_rn((double)L.cb, (double)wgt, c2[k]);
             T[k] = Tn;
             last[k] = base - t.start + (uint32_t)j + 1u;
           }
@@ -341,9 +346,9 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
   }
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
-    C[k][0] = __fmaf_rn(T[k], op.bg[0], c0[k]);
-    C[k][1] = __fmaf_rn(T[k], op.bg[1], c1[k]);
-    C[k][2] = __fmaf_rn(T[k], op.bg[2], c2[k]);
+    C[k][0] = (float)__fma_rn((double)T[k], (double)op.bg[0], c0[k]);
+    C[k][1] = (float)__fma_rn((double)T[k], (double)op.bg[1], c1[k]);
+    C[k][2] = (float)__fma_rn((double)T[k], (double)op.bg[2], c2[k]);
     Tout[k] = T[k];
     last_out[k] = last[k];
   }
@@ -379,7 +384,7 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
     CamBatch cb, OptsDev op, const Rec* __restrict__ srec, const uint32_t* __restrict__ tile_start,
     const uint32_t* __restrict__ pair_rank, const float* __restrict__ dl_or_target, const float* __restrict__ image,
     const uint32_t* __restrict__ n_contrib, float* __restrict__ image_out, float* __restrict__ loss_out,
-    float inv_count, float* __restrict__ g2, DetArgs det) {
+    float inv_count, double* __restrict__ g2, DetArgs det) {
   static_assert(!kDet || PIX == 4, "the deterministic variant runs one wave per tile");
   constexpr int kWaves = kBlock / PIX / 64;
   constexpr uint32_t kBatch = kBlock / PIX;
@@ -419,7 +424,8 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
       bound[k] = n_contrib[t.pix[k]];
     }
   }
-  float g[PIX][3], gout[PIX];
+  float g[PIX][3];
+  double gout[PIX];
   float l1 = 0.0f;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
@@ -437,7 +443,8 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
         g[k][2] = dl_or_target[3 * t.pix[k] + 2];
       }
     }
-    gout[k] = g[k][0] * out[k][0] + g[k][1] * out[k][1] + g[k][2] * out[k][2];
+    gout[k] = __fma_rn((double)g[k][2], (double)out[k][2],
+                       __fma_rn((double)g[k][1], (double)out[k][1], (double)g[k][0] * (double)out[k][0]));
   }
   if (kLoss == SSS_LOSS_L1 && loss_out) {
     // |out - target| summed over the workgroup, one atomic per tile
@@ -464,11 +471,15 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
 
   // ---- front-to-back gradient walk ----
   const WaveStrips<PIX> ws = wave_strips<PIX>();
-  float T[PIX], gA[PIX];
+  // gA: g . (colour accumulated so far), in FP64 like the forward's sums, so
+  // that gout - gA (the part of the output behind a component) keeps its
+  // precision deep in a list
+  float T[PIX];
+  double gA[PIX];
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     T[k] = 1.0f;
-    gA[k] = 0.0f;
+    gA[k] = 0.0;
   }
   for (uint32_t base = t.start; base < stop; base += kBatch) {
     __syncthreads();
@@ -504,8 +515,8 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
         const float Tk = T[k];
         const float w = a * Tk;
         const float gc = __fmaf_rn(g[k][2], L.cb, __fmaf_rn(g[k][1], L.cg, g[k][0] * L.cr));
-        gA[k] = __fmaf_rn(w, gc, gA[k]);
-        const float gR = gout[k] - gA[k];
+        gA[k] = __fma_rn((double)w, (double)gc, gA[k]);
+        const float gR = (float)(gout[k] - gA[k]);
         const float da = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), Tk * gc);
         v[5] = __fmaf_rn(g[k][0], w, v[5]);
         v[6] = __fmaf_rn(g[k][1], w, v[6]);
@@ -549,7 +560,7 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
         if (lane < 16 && idx >= 0 && L.slot < det.n_pairs) det.part[(size_t)L.slot * kG2 + idx] = g2_scale(idx) * x;
       } else if (__any(hit)) {
         const float x = wave_sum10_transposed(v);
-        if (lane < 16 && idx >= 0) atomicAdd(g2 + (size_t)L.entry * kG2 + idx, g2_scale(idx) * x);
+        if (lane < 16 && idx >= 0) atomicAdd(g2 + (size_t)L.entry * kG2 + idx, (double)(g2_scale(idx) * x));
       }
     }
   }
@@ -582,11 +593,11 @@ __device__ __forceinline__ void seg_step(int key, float (&v)[10]) {
 // depends only on the data, never on scheduling.
 __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t n, int64_t n_vis, uint32_t m,
                                                             const Rec* __restrict__ srec, DetArgs det,
-                                                            float* __restrict__ g2) {
+                                                            double* __restrict__ g2) {
   struct WaveMeta {
     uint32_t off[65];
     int base[64], h[64], total[64], y0[64], toff[64], tiles_x[64], fits[64];
-    float acc[64][10];
+    double acc[64][10];
   };
   __shared__ RowTable s_rows[kBlock / 64];
   __shared__ WaveMeta s_meta[kBlock / 64];
@@ -624,7 +635,7 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
   M.tiles_x[lane] = my_tx;
   M.fits[lane] = valid && wr.fits;
 #pragma unroll
-  for (int f = 0; f < 10; ++f) M.acc[lane][f] = 0.0f;
+  for (int f = 0; f < 10; ++f) M.acc[lane][f] = 0.0;
   __syncthreads();
   if (r0 >= n_vis) return;   // uniform per wave; no barrier follows
   const uint32_t s0 = M.off[0], s1 = M.off[64];
@@ -673,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
     const int next = __shfl_down(key, 1, 64);
     if (in && (lane == 63 || next != key)) {
 #pragma unroll
-      for (int f = 0; f < 10; ++f) M.acc[rho][f] += v[f];
+      for (int f = 0; f < 10; ++f) M.acc[rho][f] += (double)v[f];
     }
   }
   // ranks whose rows did not fit the table
@@ -703,14 +714,14 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
     for (int f = 0; f < 10; ++f) a[f] = wave_sum63(a[f]);
     if (lane == 63) {
 #pragma unroll
-      for (int f = 0; f < 10; ++f) M.acc[j][f] = a[f];
+      for (int f = 0; f < 10; ++f) M.acc[j][f] = (double)a[f];
     }
   }
   if (valid) {
-    float4* g = reinterpret_cast<float4*>(g2 + (size_t)my_e * kG2);
-    g[0] = make_float4(M.acc[lane][0], M.acc[lane][1], M.acc[lane][2], M.acc[lane][3]);
-    g[1] = make_float4(M.acc[lane][4], M.acc[lane][5], M.acc[lane][6], M.acc[lane][7]);
-    g[2] = make_float4(M.acc[lane][8], M.acc[lane][9], 0.0f, 0.0f);
+    double2* g = reinterpret_cast<double2*>(g2 + (size_t)my_e * kG2);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) g[f] = make_double2(M.acc[lane][2 * f], M.acc[lane][2 * f + 1]);
+    g[5] = make_double2(0.0, 0.0);
   }
 }
 
@@ -748,7 +759,7 @@ void launch_zero(float* p, int64_t count, hipStream_t st) {
 // sums [M][kG2], per-tile visit bounds [T] and loss values [T], each
 // 256-byte aligned.
 static size_t det_parts(int64_t n_entries, int64_t n_pairs, int64_t n_tiles, size_t part[4]) {
-  part[0] = sizeof(float) * kG2 * (size_t)n_entries;
+  part[0] = sizeof(double) * kG2 * (size_t)n_entries;
   part[1] = sizeof(float) * kG2 * (size_t)(n_pairs > 0 ? n_pairs : 1);
   part[2] = sizeof(uint32_t) * (size_t)n_tiles;
   part[3] = sizeof(float) * (size_t)n_tiles;
@@ -762,7 +773,7 @@ size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_ti
   return det_parts(n_entries, n_pairs, n_tiles, part);
 }
 
-DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, float** g2) {
+DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, double** g2) {
   size_t part[4];
   det_parts(n_entries, n_pairs, n_tiles, part);
   char* q[4];
@@ -772,7 +783,7 @@ DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles,
     p += (part[k] + 255) & ~(size_t)255;
   }
   DetArgs d{};
-  *g2 = (float*)q[0];
+  *g2 = (double*)q[0];
   d.part = (float*)q[1];
   d.lastp1 = (uint32_t*)q[2];
   d.loss_part = (float*)q[3];
@@ -801,7 +812,7 @@ void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
 
 void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, int mode, int loss,
                        const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
-                       float* loss_out, float* g2, int64_t total_pixels, const DetArgs* det, int64_t n,
+                       float* loss_out, double* g2, int64_t total_pixels, const DetArgs* det, int64_t n,
                        hipStream_t st) {
   static const int pix = env_pix("SSS_PIX_BWD", 2);
   const float inv_count = 1.0f / (3.0f * (float)total_pixels);

@@ -1,0 +1,129 @@
+"""Parity at the full workload sizes, in the configuration the benchmark
+times (default pixels per lane, one launch over all views): the GPU image
+and gradients are compared with the FP64 oracle on sampled 32x32 windows.
+
+The oracle renders each window with the window's own camera (principal
+point shifted, frustum clamp of the full image), which gives exactly the
+full image's pixels there (pinned by test_window_render_equals_crop_of_full_render).
+The loss weight is random inside the windows and zero elsewhere, so the
+oracle's window gradients add up to the gradient of the GPU's whole-image
+backward pass.  Explained pixels (a decision within its margin) get weight
+zero and are not compared; components the oracle flags are not compared.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_10148_amd import scenes
+from tests._util import PARAMS, grad_close, to_device
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+WIN = 32
+
+
+@pytest.fixture(scope="module")
+def sss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_10148_amd import sss as binding
+    binding.lib()
+    return binding
+
+
+def _windows(cams, count, rng):
+    """Disjoint windows (view, x0, y0), not aligned to tiles."""
+    out = []
+    while len(out) < count:
+        v = int(rng.integers(0, len(cams)))
+        c = cams[v]
+        x0 = int(rng.integers(0, c["width"] - WIN))
+        y0 = int(rng.integers(0, c["height"] - WIN))
+        if all(w[0] != v or abs(w[1] - x0) >= WIN or abs(w[2] - y0) >= WIN for w in out):
+            out.append((v, x0, y0))
+    return out
+
+
+@pytest.mark.parametrize("name,mode,count", [("m1", "stored", 6), ("large", "recompute", 4),
+                                             ("multiview", "stored", 4)])
+def test_full_size_windows_match_oracle(sss, name, mode, count):
+    scene, cams = scenes.workload(name)
+    n = scene["means"].shape[0]
+    s64 = {k: np.asarray(scene[k], np.float64) for k in PARAMS}
+    s64["sh_degree"] = scene["sh_degree"]
+    dev = to_device(scene)
+    del scene
+    proj = sss.project(dev, cams)
+    bins = sss.BinSorter(0)(proj, cams, n)
+    img, _, ncon = sss.render_fwd(bins, cams)
+    torch.cuda.synchronize()
+    offs = np.cumsum([0] + [c["width"] * c["height"] for c in cams])
+    img_np = img.cpu().numpy()
+    dl = np.zeros_like(img_np)
+    rng = np.random.default_rng(scenes.SEED_FD + 7)
+    gref = {k: np.zeros_like(s64[k]) for k in PARAMS}
+    flagged = np.zeros(n, bool)
+    bad_total, explained_total = 0, 0
+    for v, x0, y0 in _windows(cams, count, rng):
+        cam = cams[v]
+        wc = oracle.window_camera(cam, x0, y0, WIN, WIN)
+        ref = oracle.render(s64, wc)
+        W = cam["width"]
+        rows = offs[v] + (y0 + np.arange(WIN))[:, None] * W + (x0 + np.arange(WIN))[None, :]
+        got = img_np[rows.reshape(-1)].reshape(WIN, WIN, 3)
+        explained = ref["xflags"] != 0
+        bad = (np.abs(got - ref["image"]).max(axis=2) > 1e-4) & ~explained
+        bad_total += int(bad.sum())
+        explained_total += int(explained.sum())
+        w = rng.standard_normal((WIN, WIN, 3)).astype(np.float32)
+        w[explained] = 0.0
+        dl[rows.reshape(-1)] = w.reshape(-1, 3)
+        g = oracle.render_backward(s64, wc, w.astype(np.float64), fwd=ref)
+        for k in PARAMS:
+            gref[k] += g[k]
+        flagged |= ref["proj"]["pflags"] != 0
+    assert bad_total == 0, bad_total
+    assert explained_total < 0.02 * count * WIN * WIN
+    m = sss.BWD_STORED if mode == "stored" else sss.BWD_RECOMPUTE
+    g = sss.render_bwd(dev, proj, bins, cams, torch.as_tensor(dl, device="cuda"), mode=m,
+                       image=img if mode == "stored" else None, n_contrib=ncon if mode == "stored" else None)
+    torch.cuda.synchronize()
+    touched = np.abs(gref["opacity"]) > 0
+    assert touched.sum() > 100
+    fails = []
+    for k in PARAMS:
+        got = g[k].cpu().numpy()
+        ok, worst = grad_close(got, gref[k], mask=~flagged)
+        if not ok:
+            a = got.reshape(n, -1).astype(np.float64)
+            b = gref[k].reshape(n, -1)
+            rms = np.sqrt(np.mean(b ** 2))
+            ratio = np.where(flagged[:, None], 0.0, np.abs(a - b) / (1e-3 * np.maximum(np.abs(b), rms)))
+            i, j = np.unravel_index(np.argmax(ratio), ratio.shape)
+            detail = dict(i=int(i), j=int(j), got=float(a[i, j]), ref=float(b[i, j]), rms=float(rms),
+                          nu=float(s64["nu"][i]), o=float(s64["opacity"][i]), n_over=int((ratio > 1).sum()))
+            fails.append(f"{k}: worst {worst:.3f} {detail}")
+    if fails:
+        raise AssertionError(f"{name}: " + "; ".join(fails))
+
+
+def test_sghmc_step_on_five_million_components(sss):
+    """The sampler step over all 5M means of the multi-view workload's size
+    (counters beyond 2^22 exercise the high words of the Philox counter's
+    index), element by element against the oracle."""
+    n = 5_000_000
+    rng = np.random.default_rng(scenes.SEED_SGHMC)
+    f = lambda a: a.astype(np.float32)
+    mu, r, g = f(rng.standard_normal((n, 3))), f(rng.standard_normal((n, 3))), f(rng.standard_normal((n, 3)))
+    o = f(rng.uniform(-1, 1, n))
+    o[::7] = f(rng.uniform(-0.004, 0.004, o[::7].size))          # switch on
+    sc, q = f(np.exp(rng.uniform(-4, -2, (n, 3)))), f(rng.standard_normal((n, 4)))
+    ref_mu, ref_r = oracle.sghmc_step(mu, r, g, o, sc, q, 0.01, 0.1, 100.0, 0.995, False, True, seed=9, step=3)
+    T = lambda a: torch.as_tensor(a, device="cuda")
+    dmu, dr = T(mu.copy()), T(r.copy())
+    sss.sghmc_step(dmu, dr, T(g), T(o), 0.01, 0.1, 100.0, 0.995, False, True, seed=9, step=3, scales=T(sc),
+                   quats=T(q))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(dmu.cpu().numpy(), ref_mu, rtol=1e-5, atol=2e-6)
+    np.testing.assert_allclose(dr.cpu().numpy(), ref_r, rtol=1e-5, atol=2e-6)
