@@ -37,12 +37,15 @@ SLOTS_FWD, SLOTS_BWD = 28, 70
 # (no packed FP32), and 8 TB/s HBM3E.
 PEAK_VALU = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
+PARAMS = ("means", "scales", "quats", "nu", "opacity", "sh")
 
 WORKLOADS = {
     "m1": "1M components, SH degree 3, one 1920x1080 camera, fwd+bwd+SGHMC",
     "train": "300k components, SH degree 3, one 1297x840 camera, fwd+bwd+SGHMC",
     "small": "10k components, SH degree 0, one 256x256 camera, fwd+bwd+SGHMC",
     "large": "3M clustered components, nu 1..150, 30% negative, one 1920x1080 camera, fwd+bwd+SGHMC",
+    "multiview": "5M clustered components, SH degree 3, 8 cameras of 1600x1064 in one launch per kernel, "
+                 "fwd+bwd+SGHMC",
 }
 
 
@@ -53,7 +56,8 @@ def log(*a):
 def make_inputs(workload):
     from paper_2503_10148_amd import scenes
     scene, cams = scenes.workload(workload)
-    target = scenes.smooth_target(cams[0]["width"], cams[0]["height"])
+    target = np.concatenate([scenes.smooth_target(c["width"], c["height"], seed=scenes.SEED_TARGET + v).reshape(-1, 3)
+                             for v, c in enumerate(cams)])
     return scene, cams, target
 
 
@@ -157,40 +161,14 @@ def copy_probe():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--copy-probe", action="store_true", help="only run the counter calibration copy")
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="m1", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="stored", choices=["stored", "recompute"])
-    ap.add_argument("--deterministic", action="store_true",
-                    help="backward without float atomics (bit-identical gradients run to run)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=int, default=768 * 768)
-    ap.add_argument("--serve-seconds", type=float, default=6.0,
-                    help="arrival window of each serving run (0 disables the serving measurement)")
-    ap.add_argument("--serve-rates", default="200,1000",
-                    help="Poisson request rates (req/s) for the serving comparison")
-    args = ap.parse_args()
-    if args.copy_probe:
-        copy_probe()
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (one GPU per box in this build)",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2503_10148_amd import sss
-    PARAMS = ("means", "scales", "quats", "nu", "opacity", "sh")
-
-    torch.cuda.set_device(0)
-    scene_np, cams, target_np = make_inputs(args.workload)
+def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instrument=True):
+    """Run warmup + timed (uninstrumented) training steps of a workload; with
+    `instrument`, a few more steps with per-kernel HIP-event timing and the
+    algorithmic work of the last step."""
+    scene_np, cams, target_np = make_inputs(workload)
     n = scene_np["means"].shape[0]
     P = sss.total_pixels(cams)
-    log(f"workload {args.workload}: n={n} pixels={P}")
+    log(f"workload {workload}: n={n} pixels={P}")
     scene = sss.scene_to_device(scene_np)
     target = torch.as_tensor(target_np.reshape(-1, 3), device="cuda")
     mom = torch.zeros_like(scene["means"])
@@ -199,13 +177,13 @@ def main():
     bounds = dict(scales=(1e-4, 3.0e38), quats=(-3.0e38, 3.0e38), nu=(1.0, 1e4), opacity=(-1.0, 1.0),
                   sh=(-3.0e38, 3.0e38))
     lrs = dict(scales=1e-4, quats=1e-3, nu=1e-2, opacity=1e-3, sh=2.5e-4)
-    binner = sss.BinSorter(0, keep_offsets=args.deterministic)
+    binner = sss.BinSorter(0, keep_offsets=deterministic)
     image = torch.empty((P, 3), device="cuda")
     t_final = torch.empty(P, device="cuda")
     n_contrib = torch.empty(P, dtype=torch.int32, device="cuda")
     loss = torch.zeros(1, device="cuda")
     bwd_ws = torch.empty(int(sss.lib().sss_render_bwd_workspace(n * len(cams))) // 4, device="cuda")
-    mode = sss.BWD_STORED if args.mode == "stored" else sss.BWD_RECOMPUTE
+    mode = sss.BWD_STORED if mode_name == "stored" else sss.BWD_RECOMPUTE
     state = {"proj": None, "bins": None}
     T = sss.total_tiles(cams)
 
@@ -215,7 +193,7 @@ def main():
         state["proj"] = proj
         bins = binner(proj, cams, n, out=state["bins"])
         state["bins"] = bins
-        if args.deterministic:
+        if deterministic:
             need = int(sss.lib().sss_render_bwd_workspace_det(n * len(cams), bins.n_pairs, T))
             if bwd_ws.numel() * 4 < need:
                 bwd_ws = torch.empty(int(need * 1.1) // 4 + 64, device="cuda")
@@ -223,17 +201,17 @@ def main():
             sss.render_fwd(bins, cams, image=image, t_final=t_final, n_contrib=n_contrib)
             sss.render_bwd(scene, proj, bins, cams, target, mode=mode, loss=sss.LOSS_L1, image=image,
                            n_contrib=n_contrib, loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True,
-                           deterministic=args.deterministic)
+                           deterministic=deterministic)
         else:
             sss.render_bwd(scene, proj, bins, cams, target, mode=mode, loss=sss.LOSS_L1, image_out=image,
-                           loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True, deterministic=args.deterministic)
+                           loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True, deterministic=deterministic)
         adam = dict(beta1=0.9, beta2=0.999, eps=1e-15, t=it + 1,
                     arrays=[dict(param=scene[k], grad=grads[k], m=adam_state[k][0], v=adam_state[k][1], lr=lrs[k],
                                  lo=bounds[k][0], hi=bounds[k][1]) for k in adam_state])
         sss.sghmc_step(scene["means"], mom, grads["means"], scene["opacity"], lr=1e-3, friction=0.1, seed=4,
                        step=it, scales=scene["scales"], quats=scene["quats"], adam=adam)
 
-    for it in range(args.warmup):
+    for it in range(warmup):
         step(it)
     torch.cuda.synchronize()
     log(f"warmup done: pairs={state['bins'].n_pairs} visible={state['bins'].n_visible}")
@@ -242,19 +220,22 @@ def main():
     # a few further steps with HIP events around every launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for it in range(args.warmup, args.warmup + args.steps):
+    for it in range(warmup, warmup + steps):
         step(it)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = P * args.steps / (t1 - t0) / 1e6
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.1f} Mpix/s")
-    n_inst = max(1, min(args.steps, 5))
+    ms_step = (t1 - t0) * 1e3 / steps
+    value = P * steps / (t1 - t0) / 1e6
+    log(f"timed {steps} steps: {ms_step:.3f} ms/step, {value:.1f} Mpix/s")
+    n_inst = max(1, min(steps, 5))
+    if not instrument:
+        torch.cuda.synchronize()
+        return dict(ms_step=ms_step, value=value, P=P, n=n, views=len(cams), bins=state["bins"])
     sss.timing_enable(True)
     sss.timing_reset()
     torch.cuda.synchronize()
     ti0 = time.perf_counter()
-    for it in range(args.warmup + args.steps, args.warmup + args.steps + n_inst):
+    for it in range(warmup + steps, warmup + steps + n_inst):
         step(it)
     torch.cuda.synchronize()
     ti1 = time.perf_counter()
@@ -276,13 +257,13 @@ def main():
     par_b = 4 * (3 + 3 + 4 + 1 + 1 + 3 * K)
     V = len(cams)
     bytes_ = {
-        # params in, 64 B record + key + rect + touched out, per entry
-        "project": n * V * (par_b + 64 + 16),
-        # means, scales, quats, nu + per view touched and 40 B of screen gradients in;
+        # params in; 64 B record, key, rect, count and 32 B FP64 ellipse out, per entry
+        "project": n * V * (par_b + 64 + 16 + 32),
+        # means, scales, quats, nu + per view touched and 80 B of FP64 screen gradients in;
         # means (read-modify-write), scales, quats, opacity, nu out
-        "project_bwd": n * (4 * (3 + 3 + 4 + 1) + V * 44 + 4 * (3 + 3 + 3 + 4 + 1 + 1)),
-        # means, SH, per view touched and 12 B colour gradient in; d_sh and d_means out
-        "sh_bwd": n * (4 * (3 + 3 * K) + V * 16 + 4 * (3 * K + 3)),
+        "project_bwd": n * (4 * (3 + 3 + 4 + 1) + V * 84 + 4 * (3 + 3 + 3 + 4 + 1 + 1)),
+        # means, SH, per view touched and 24 B FP64 colour gradient in; d_sh and d_means out
+        "sh_bwd": n * (4 * (3 + 3 * K) + V * 28 + 4 * (3 * K + 3)),
         "sghmc": n * 64,
         "adam": n * (3 + 4 + 1 + 1 + 3 * K) * 28 / 5,           # per launch, 5 arrays
     }
@@ -296,6 +277,61 @@ def main():
         stages["render_fwd"]["valu_frac"] = round(SLOTS_FWD * evals / (avg["render_fwd"] * 1e-3) / PEAK_VALU, 4)
     step_bytes = (bytes_["project"] + bytes_["project_bwd"] + bytes_["sh_bwd"] + bytes_["sghmc"] + 5 * bytes_["adam"]
                   + 16 * n + 136 * bins.n_visible + 8 * bins.n_pairs + P * (12 + 12 + 4 + 12))
+
+    return dict(ms_step=ms_step, value=value, evals=evals, bins=bins, stages=stages, kt=kt, P=P, n=n,
+                bwd_ms=bwd_ms, achieved=achieved, step_bytes=step_bytes, ti0=ti0, ti1=ti1, n_inst=n_inst, loss=loss,
+                views=len(cams), scene_np=scene_np, cams=cams)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--copy-probe", action="store_true", help="only run the counter calibration copy")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="m1", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="stored", choices=["stored", "recompute"])
+    ap.add_argument("--other-workloads", default="large:recompute,multiview:stored",
+                    help="further workloads (name:mode, comma separated) timed for 5 steps each; '' to skip")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="backward without float atomics (bit-identical gradients run to run)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-window", type=int, default=768 * 768)
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="arrival window of each serving run (0 disables the serving measurement)")
+    ap.add_argument("--serve-rates", default="200,1000",
+                    help="Poisson request rates (req/s) for the serving comparison")
+    args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (one GPU per box in this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_10148_amd import sss
+
+    torch.cuda.set_device(0)
+    r = measure(sss, torch, args.workload, args.mode, args.deterministic, args.steps, args.warmup)
+    ms_step, value, evals, bins, stages, kt = r["ms_step"], r["value"], r["evals"], r["bins"], r["stages"], r["kt"]
+    P, n, bwd_ms, achieved, step_bytes = r["P"], r["n"], r["bwd_ms"], r["achieved"], r["step_bytes"]
+    ti0, ti1, n_inst, loss = r["ti0"], r["ti1"], r["n_inst"], r["loss"]
+    scene_np, cams = r["scene_np"], r["cams"]
+    del r
+    others = {}
+    for spec in [x for x in args.other_workloads.split(",") if x]:
+        name, mode = spec.split(":")
+        if name == args.workload:
+            continue
+        torch.cuda.empty_cache()
+        o = measure(sss, torch, name, mode, False, 5, 1, instrument=False)
+        others[name] = {"bwd_mode": mode, "ms_per_step": round(o["ms_step"], 3), "mpix_s": round(o["value"], 1),
+                        "pixels_per_step": o["P"], "components": o["n"], "views": o["views"], "pairs": o["bins"].n_pairs,
+                        "workload": WORKLOADS[name]}
+        del o
+        torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
@@ -321,6 +357,7 @@ def main():
                      "avg_ms": round(bwd_ms, 4), "units": evals, "ops_per_unit": SLOTS_BWD},
         "stages": stages,
         "instrumented_ms_per_step": round((ti1 - ti0) * 1e3 / n_inst, 4),
+        "other_workloads": others,
         "loss": float(loss.item()) / (args.warmup + args.steps + n_inst),
     }
     if args.serve_seconds > 0:
