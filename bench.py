@@ -182,7 +182,8 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
     t_final = torch.empty(P, device="cuda")
     n_contrib = torch.empty(P, dtype=torch.int32, device="cuda")
     loss = torch.zeros(1, device="cuda")
-    bwd_ws = torch.empty(int(sss.lib().sss_render_bwd_workspace(n * len(cams))) // 4, device="cuda")
+    bwd_ws = torch.empty(int(sss.lib().sss_render_bwd_workspace(n * len(cams), sss.total_tiles(cams))) // 4,
+                         device="cuda")
     mode = sss.BWD_STORED if mode_name == "stored" else sss.BWD_RECOMPUTE
     state = {"proj": None, "bins": None}
     T = sss.total_tiles(cams)

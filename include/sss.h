@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define SSS_VERSION 101
+#define SSS_VERSION 102
 #define SSS_TILE 16           /* tile edge in pixels                            */
 #define SSS_MAX_VIEWS 16      /* views per call                                 */
 #define SSS_RECORD_BYTES 64   /* size of one projected record                  */
@@ -253,13 +253,15 @@ int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views
  *                           over all 3P values; loss_out (device float,
  *                           nullable) receives += L
  * grads: += or = (see sss_grads_t).  Workspace: ws_bytes >=
- * sss_render_bwd_workspace(n_views*n) (per-entry screen-space gradients,
- * 12 FP64 each).
+ * sss_render_bwd_workspace(n_views*n, n_tiles) (per-entry screen-space
+ * gradients, 12 FP64 each, and one loss value per tile; the L1 loss is
+ * summed over tiles in a fixed order, so loss_out gets the same value on
+ * every run).
  * Errors: INVALID for NULL pointers, a short workspace, unknown mode/loss. */
 enum { SSS_BWD_STORED = 0, SSS_BWD_RECOMPUTE = 1, SSS_BWD_DETERMINISTIC = 4 };
 enum { SSS_LOSS_GRAD = 0, SSS_LOSS_L1 = 1 };
 
-size_t sss_render_bwd_workspace(int64_t n_entries);
+size_t sss_render_bwd_workspace(int64_t n_entries, int64_t n_tiles);
 size_t sss_render_bwd_workspace_det(int64_t n_entries, int64_t n_pairs, int64_t n_tiles);
 
 int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,

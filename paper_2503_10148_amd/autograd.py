@@ -69,7 +69,7 @@ class RenderFunction(torch.autograd.Function):
             need = int(sss.lib().sss_render_bwd_workspace_det(n * len(ctx.cams), ctx.bins.n_pairs,
                                                               sss.total_tiles(ctx.cams)))
         else:
-            need = int(sss.lib().sss_render_bwd_workspace(n * len(ctx.cams)))
+            need = int(sss.lib().sss_render_bwd_workspace(n * len(ctx.cams), sss.total_tiles(ctx.cams)))
         if st.bwd_ws is None or st.bwd_ws.numel() * 4 < need:
             st.bwd_ws = torch.empty(need // 4, dtype=torch.float32, device=dl_dimage.device)
         mode = sss.BWD_STORED if ctx.mode == "stored" else sss.BWD_RECOMPUTE

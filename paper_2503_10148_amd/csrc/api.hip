@@ -144,9 +144,9 @@ size_t sss_bin_sort_workspace(int64_t n_entries, int64_t pair_capacity) {
   return bin_sort_workspace(n_entries, pair_capacity);
 }
 
-size_t sss_render_bwd_workspace(int64_t n_entries) {
-  if (n_entries < 0) return 0;
-  return (size_t)n_entries * kG2 * sizeof(double);
+size_t sss_render_bwd_workspace(int64_t n_entries, int64_t n_tiles) {
+  if (n_entries < 0 || n_tiles < 0) return 0;
+  return render_bwd_workspace(n_entries, n_tiles);
 }
 
 int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts,
@@ -229,7 +229,7 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
     return SSS_ERR_INVALID;
   }
   const size_t need = det ? render_bwd_det_workspace(n_entries, bins->n_pairs, cb.total_tiles)
-                          : sss_render_bwd_workspace(n_entries);
+                          : render_bwd_workspace(n_entries, cb.total_tiles);
   if (ws_bytes < need) {
     set_error("sss_render_bwd: workspace of %zu bytes, %zu needed", ws_bytes, need);
     return SSS_ERR_INVALID;
@@ -238,6 +238,7 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
   const OptsDev op = make_opts(opts);
   double* g2 = (double*)ws;
   DetArgs da{};
+  if (!det) da = carve_bwd(ws, n_entries, cb.total_tiles, &g2);
   if (det) {
     da = carve_det(ws, n_entries, bins->n_pairs, cb.total_tiles, &g2);
     da.order = bins->order;
@@ -248,7 +249,7 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
   }
   launch_zero((float*)g2, n_entries * kG2 * 2, st);
   launch_render_bwd(cb, op, *bins, mode, loss, dl_or_target, image, n_contrib, image_out, loss_out, g2,
-                    total_pixels(cb), det ? &da : nullptr, scene->n, st);
+                    total_pixels(cb), det, da, scene->n, st);
   launch_project_bwd(cb, op, *scene, proj->tiles_touched, g2, *grads, st);
   return hip_ok(hipGetLastError(), "sss_render_bwd launch") ? SSS_OK : SSS_ERR_HIP;
 }

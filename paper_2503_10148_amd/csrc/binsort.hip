@@ -1,19 +1,22 @@
 // Tile binning and depth ordering.
 //
-//  1. visible entries (tiles_touched > 0) are compacted in entry order and
-//     the total pair count is reduced; both counts are read back once;
-//  2. a stable LSD radix sort by the 32-bit depth key gives each visible
-//     entry its rank (ties keep entry order, i.e. component index);
-//  3. every (tile, rank) pair of a visible entry's rectangle is written in
+//  1. every entry gets its depth key (culled ones 2^32 - 1) and per-block
+//     counts of visible entries, pairs and the visible key range are reduced;
+//     the counts are read back once;
+//  2. a stable LSD radix sort by the depth key, relative to the smallest
+//     visible key and over only the bits that vary, gives each visible entry
+//     its rank (ties keep entry order, i.e. component index); culled entries
+//     sort last;
+//  3. every (tile, rank) pair of a visible entry's listed tiles is written in
 //     rank order (exclusive scan of tiles_touched over ranks), the projected
 //     records are gathered into rank order alongside;
 //  4. a stable radix sort of the pairs by global tile id leaves each tile's
 //     ranks ascending, i.e. in (depth key, component index) order;
 //  5. tile_start[] marks where each tile's run begins.
 //
-// All passes stream through HBM with coalesced 16-byte accesses where the
-// data allows; the radix scatter ranks keys inside a wave with ballots
-// (64-wide match) so the sort is stable without per-thread digit counters.
+// All passes stream through HBM with coalesced accesses where the data
+// allows; the radix scatter ranks keys inside a wave with ballots (64-wide
+// match) so the sort is stable without per-thread digit counters.
 #include "common.hpp"
 #include "tiles.hpp"
 #include "scan.hpp"
@@ -23,44 +26,84 @@ namespace {
 
 
 // ---------------------------------------------------------------------------
-// 1. visibility
+// 1. sort input and counts
 // ---------------------------------------------------------------------------
-// The pair total is accumulated into kPairCounters separate counters (block b
-// adds to counter b mod kPairCounters), so the atomics of thousands of blocks
-// do not queue on one address; the host adds them up.
-constexpr int kPairCounters = 32;
+// Every entry goes into the depth sort; a culled one gets the key 2^32 - 1,
+// which the depth passes map above every visible key, so the n_visible
+// visible entries come first in depth order.  Each block writes its count of
+// visible entries, its pair total and the range of its visible keys to its
+// own slot (no atomics), and one workgroup reduces the slots.
+struct BlockStat {
+  unsigned long long pairs;
+  uint32_t visible, kmin, kmax, pad;
+};
 
-__global__ __launch_bounds__(kBlock) void visible_kernel(const uint32_t* __restrict__ touched, int64_t n,
-                                                         uint32_t* __restrict__ flags,
-                                                         unsigned long long* __restrict__ counters) {
-  __shared__ unsigned long long red[kBlock / 64];
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint32_t t = j < n ? touched[j] : 0u;
-  if (j < n) flags[j] = t > 0 ? 1u : 0u;
-  unsigned long long v = t;
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned long long b = red[0] + red[1] + red[2] + red[3];
-    if (b) atomicAdd(counters + 1 + blockIdx.x % kPairCounters, b);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* __restrict__ flags,
-                                                         const uint32_t* __restrict__ pos,
+__global__ __launch_bounds__(kBlock) void prepare_kernel(const uint32_t* __restrict__ touched,
                                                          const uint32_t* __restrict__ keys, int64_t n,
                                                          uint32_t* __restrict__ out_keys,
                                                          uint32_t* __restrict__ out_vals,
-                                                         unsigned long long* __restrict__ counters) {
+                                                         BlockStat* __restrict__ stats) {
+  __shared__ BlockStat red[kBlock / 64];
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n) return;
-  const uint32_t p = pos[j];
-  if (flags[j]) {
-    out_keys[p] = keys[j];
-    out_vals[p] = (uint32_t)j;
+  const uint32_t t = j < n ? touched[j] : 0u;
+  const uint32_t k = j < n ? keys[j] : 0u;
+  if (j < n) {
+    out_keys[j] = t > 0 ? k : 0xFFFFFFFFu;
+    out_vals[j] = (uint32_t)j;
   }
-  if (j == n - 1) counters[0] = (unsigned long long)p + flags[j];
+  unsigned long long pairs = t;
+  uint32_t vis = t > 0 ? 1u : 0u, lo = t > 0 ? k : 0xFFFFFFFFu, hi = t > 0 ? k : 0u;
+  for (int d = 32; d > 0; d >>= 1) {
+    pairs += __shfl_xor(pairs, d, 64);
+    vis += __shfl_xor(vis, d, 64);
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, d, 64));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = BlockStat{pairs, vis, lo, hi, 0u};
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    BlockStat b = red[0];
+    for (int w = 1; w < kBlock / 64; ++w) {
+      b.pairs += red[w].pairs;
+      b.visible += red[w].visible;
+      b.kmin = min(b.kmin, red[w].kmin);
+      b.kmax = max(b.kmax, red[w].kmax);
+    }
+    stats[blockIdx.x] = b;
+  }
+}
+
+// counters: visible entries, pairs, smallest and largest visible key.
+__global__ __launch_bounds__(kBlock) void stat_reduce_kernel(const BlockStat* __restrict__ stats, int64_t nb,
+                                                             unsigned long long* __restrict__ counters) {
+  __shared__ BlockStat red[kBlock];
+  BlockStat b{0ull, 0u, 0xFFFFFFFFu, 0u, 0u};
+  for (int64_t i = threadIdx.x; i < nb; i += kBlock) {
+    const BlockStat s = stats[i];
+    b.pairs += s.pairs;
+    b.visible += s.visible;
+    b.kmin = min(b.kmin, s.kmin);
+    b.kmax = max(b.kmax, s.kmax);
+  }
+  red[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      BlockStat& a = red[threadIdx.x];
+      const BlockStat& c = red[threadIdx.x + h];
+      a.pairs += c.pairs;
+      a.visible += c.visible;
+      a.kmin = min(a.kmin, c.kmin);
+      a.kmax = max(a.kmax, c.kmax);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    counters[0] = red[0].visible;
+    counters[1] = red[0].pairs;
+    counters[2] = red[0].kmin;
+    counters[3] = red[0].kmax;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -71,8 +114,16 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(const uint32_t* __restr
 #endif
 constexpr int kRItems = SSS_RADIX_ITEMS;           // items per thread of a radix pass
 constexpr int kRPerBlock = kBlock * kRItems;      // items per workgroup
+// Keys enter the passes as min(key - base, cap) (unsigned): the depth sort
+// subtracts the smallest visible key and maps culled entries to cap, so only
+// the bits that vary are sorted; the pair sort uses base 0, cap 2^32 - 1.
+__device__ __forceinline__ uint32_t radix_digit(uint32_t key, uint32_t base, uint32_t cap, int shift, uint32_t mask) {
+  return (min(key - base, cap) >> shift) & mask;
+}
+
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
-                                                            int shift, uint32_t mask, int64_t nblocks,
+                                                            uint32_t base_key, uint32_t cap, int shift,
+                                                            uint32_t mask, int64_t nblocks,
                                                             uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -80,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
   const int64_t base = (int64_t)blockIdx.x * kRPerBlock;
   for (int k = 0; k < kRItems; ++k) {
     const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-    if (j < n) atomicAdd(&h[(keys[j] >> shift) & mask], 1u);
+    if (j < n) atomicAdd(&h[radix_digit(keys[j], base_key, cap, shift, mask)], 1u);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
@@ -92,8 +143,8 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
 // reordered by digit in LDS and written out digit run by digit run, so
 // consecutive threads store to consecutive addresses.
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift, int bits,
-    int64_t nblocks, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ okeys,
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, uint32_t base_key, uint32_t cap,
+    int shift, int bits, int64_t nblocks, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ okeys,
     uint32_t* __restrict__ ovals) {
   __shared__ uint32_t cnt[4][256];
   __shared__ uint32_t gbase[256];
@@ -116,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     const bool ok = j < n;
     key[r] = ok ? keys[j] : 0u;
     val[r] = ok ? vals[j] : 0u;
-    const uint32_t d = (key[r] >> shift) & mask;
+    const uint32_t d = radix_digit(key[r], base_key, cap, shift, mask);
     uint64_t peers = __ballot(ok);
     for (int b = 0; b < bits; ++b) {
       const bool bit = (d >> b) & 1u;
@@ -145,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   for (int r = 0; r < kRItems; ++r) {
     const int64_t j = base + (int64_t)r * 64 + lane;
     if (j < n) {
-      const uint32_t d = (key[r] >> shift) & mask;
+      const uint32_t d = radix_digit(key[r], base_key, cap, shift, mask);
       const uint32_t bp = cnt[w][d] + loc[r];
       sk[bp] = key[r];
       sv[bp] = val[r];
@@ -155,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   const int in_block = (int)min((int64_t)kRPerBlock, n - block0);
   for (int i = tid; i < in_block; i += kBlock) {
     const uint32_t k = sk[i];
-    const uint32_t d = (k >> shift) & mask;
+    const uint32_t d = radix_digit(k, base_key, cap, shift, mask);
     const uint32_t p = gbase[d] + ((uint32_t)i - dofs[d]);
     okeys[p] = k;
     ovals[p] = sv[i];
@@ -268,6 +319,7 @@ __global__ __launch_bounds__(kBlock) void tile_start_kernel(const uint32_t* __re
 struct Ws {
   uint32_t *flags, *pos, *ka, *va, *kb, *vb, *hist, *scan;
   unsigned long long* counters;
+  BlockStat* stats;
   size_t bytes;
 };
 
@@ -280,7 +332,8 @@ Ws carve(void* base, int64_t n_entries, int64_t pair_cap) {
   char* p = (char*)base;
   size_t off = 0;
   auto take = [&](size_t bytes) { char* q = p ? p + off : nullptr; off += align256(bytes); return q; };
-  w.counters = (unsigned long long*)take((1 + kPairCounters) * sizeof(unsigned long long));
+  w.counters = (unsigned long long*)take(4 * sizeof(unsigned long long));
+  w.stats = (BlockStat*)take(sizeof(BlockStat) * (size_t)((n_entries + kBlock - 1) / kBlock + 1));
   w.flags = (uint32_t*)take(sizeof(uint32_t) * (size_t)n_entries);
   w.pos = (uint32_t*)take(sizeof(uint32_t) * (size_t)n_entries);
   w.ka = (uint32_t*)take(sizeof(uint32_t) * (size_t)big);
@@ -298,7 +351,7 @@ Ws carve(void* base, int64_t n_entries, int64_t pair_cap) {
 // the last pass writes the values to out_v.  Returns the buffer holding the
 // sorted keys (never the last pass's input).
 uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int nbits,
-                     uint32_t* out_v, Ws& w, hipStream_t st) {
+                     uint32_t* out_v, Ws& w, hipStream_t st, uint32_t base_key = 0u, uint32_t cap = 0xFFFFFFFFu) {
   // as few passes of at most 8 bits as possible, with the bits spread evenly
   // (e.g. 13 bits as 7 + 6): wider runs per digit and block make the
   // scatter's stores longer
@@ -314,11 +367,11 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
     uint32_t* iv = (p % 2 == 0) ? va : vb;
     uint32_t* okk = (p % 2 == 0) ? kb : ka;
     uint32_t* ovv = (p == passes - 1) ? out_v : ((p % 2 == 0) ? vb : va);
-    SSS_LAUNCH("radix_hist", radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, n, shift,
+    SSS_LAUNCH("radix_hist", radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, n, base_key, cap, shift,
                        (uint32_t)((1u << bits) - 1u), nb, w.hist);
     scan_excl(w.hist, w.hist, 256 * nb, w.scan, st);
-    SSS_LAUNCH("radix_scatter", radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, iv, n, shift, bits,
-                       nb, (const uint32_t*)w.hist, okk, ovv);
+    SSS_LAUNCH("radix_scatter", radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, iv, n, base_key,
+                       cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv);
   }
   return final_keys;
 }
@@ -344,20 +397,15 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
     return SSS_ERR_INVALID;
   }
   const unsigned g1 = (unsigned)((n_entries + kBlock - 1) / kBlock);
-  if (!hip_ok(hipMemsetAsync(w.counters, 0, (1 + kPairCounters) * sizeof(unsigned long long), st), "memset"))
-    return SSS_ERR_HIP;
-  SSS_LAUNCH("visible", visible_kernel, dim3(g1), dim3(kBlock), 0, st, proj.tiles_touched, n_entries, w.flags,
-                     w.counters);
-  scan_excl(w.flags, w.pos, n_entries, w.scan, st);
-  SSS_LAUNCH("compact", compact_kernel, dim3(g1), dim3(kBlock), 0, st, w.flags, w.pos, proj.depth_key, n_entries,
-                     w.ka, w.va, w.counters);
-  unsigned long long counts[1 + kPairCounters];
+  SSS_LAUNCH("prepare", prepare_kernel, dim3(g1), dim3(kBlock), 0, st, proj.tiles_touched, proj.depth_key, n_entries,
+             w.ka, w.va, w.stats);
+  SSS_LAUNCH("stat_reduce", stat_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const BlockStat*)w.stats, (int64_t)g1,
+             w.counters);
+  unsigned long long counts[4];
   if (!hip_ok(hipMemcpyAsync(counts, w.counters, sizeof(counts), hipMemcpyDeviceToHost, st), "count readback"))
     return SSS_ERR_HIP;
   if (!hip_ok(hipStreamSynchronize(st), "count sync")) return SSS_ERR_HIP;
-  int64_t m = 0;
-  for (int k = 0; k < kPairCounters; ++k) m += (int64_t)counts[1 + k];
-  const int64_t n_vis = (int64_t)counts[0];
+  const int64_t n_vis = (int64_t)counts[0], m = (int64_t)counts[1];
   bins->n_visible = n_vis;
   bins->n_pairs = m;
   if (m > bins->pair_capacity) {
@@ -368,8 +416,13 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
     set_error("sss_bin_sort: %lld pairs exceed 2^32", (long long)m);
     return SSS_ERR_UNSUPPORTED;
   }
-  // 2. depth order of the visible entries
-  radix_sort(w.ka, w.va, w.kb, w.vb, n_vis, 32, bins->order, w, st);
+  // 2. depth order: keys relative to the smallest visible key, culled entries
+  //    at range + 1 (after every visible one); only the varying bits are sorted
+  if (n_vis > 0) {
+    const uint32_t kmin = (uint32_t)counts[2], range = (uint32_t)counts[3] - kmin;
+    const uint32_t cap = range == 0xFFFFFFFFu ? range : range + 1u;
+    radix_sort(w.ka, w.va, w.kb, w.vb, n_entries, bits_for((int64_t)cap + 1), bins->order, w, st, kmin, cap);
+  }
   // 3. pair offsets in rank order, emission, record gather
   if (n_vis > 0) {
     const unsigned gv = (unsigned)((n_vis + kBlock - 1) / kBlock);

@@ -107,15 +107,17 @@ struct DetArgs {
   const Ellipse* ell;         // per-entry ellipses
   float* part;                // [n_pairs][kG2] per-pair sums
   uint32_t* lastp1;           // [n_tiles] last visited rank + 1
-  float* loss_part;           // [n_tiles] per-tile loss
+  float* loss_part;           // [n_tiles] per-tile loss (both modes)
   uint32_t n_pairs;           // bound of the slots (part has n_pairs rows)
 };
 size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_tiles);
+size_t render_bwd_workspace(int64_t n_entries, int64_t n_tiles);
+DetArgs carve_bwd(void* ws, int64_t n_entries, int64_t n_tiles, double** g2);
 DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, double** g2);
 void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, int mode,
                        int loss, const float* dl_or_target, const float* image,
                        const uint32_t* n_contrib, float* image_out, float* loss_out, double* g2,
-                       int64_t total_pixels, const DetArgs* det, int64_t n, hipStream_t st);
+                       int64_t total_pixels, bool det_mode, const DetArgs& dargs, int64_t n, hipStream_t st);
 void launch_zero(float* p, int64_t count, hipStream_t st);
 size_t relocate_workspace(int64_t n, double max_fraction);
 size_t loss_workspace(int64_t total_pixels);

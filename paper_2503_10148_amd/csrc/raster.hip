@@ -463,8 +463,7 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   if (kLoss == SSS_LOSS_L1 && loss_out && threadIdx.x == 0) {
     float l = 0.0f;
     for (int w = 0; w < kWaves; ++w) l += s_loss[w];
-    if (kDet) det.loss_part[blockIdx.x] = l * inv_count;
-    else atomicAdd(loss_out, l * inv_count);
+    det.loss_part[blockIdx.x] = l * inv_count;
   }
   // pairs of this tile up to rank lastp1 - 1 are visited (lists ascend in rank)
   if (kDet && threadIdx.x == 0) det.lastp1[blockIdx.x] = stop > t.start ? pair_rank[stop - 1] + 1u : 0u;
@@ -725,8 +724,10 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
   }
 }
 
-// Fixed-order sum of the per-tile loss values (one workgroup).
-__global__ __launch_bounds__(kBlock) void det_loss_kernel(const float* __restrict__ part, int64_t n,
+// Fixed-order sum of the per-tile loss values (one workgroup): one add to
+// loss_out instead of one atomic per tile on a single address, and the same
+// value on every run.
+__global__ __launch_bounds__(kBlock) void loss_reduce_kernel(const float* __restrict__ part, int64_t n,
                                                           float* __restrict__ loss_out) {
   __shared__ float red[kBlock];
   float s = 0.0f;
@@ -773,6 +774,19 @@ size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_ti
   return det_parts(n_entries, n_pairs, n_tiles, part);
 }
 
+// Workspace of the atomic mode: screen-space gradients [E][kG2] FP64 and the
+// per-tile loss values [T].
+size_t render_bwd_workspace(int64_t n_entries, int64_t n_tiles) {
+  return ((sizeof(double) * kG2 * (size_t)n_entries + 255) & ~(size_t)255) + sizeof(float) * (size_t)n_tiles;
+}
+
+DetArgs carve_bwd(void* ws, int64_t n_entries, int64_t n_tiles, double** g2) {
+  DetArgs d{};
+  *g2 = (double*)ws;
+  d.loss_part = (float*)((char*)ws + ((sizeof(double) * kG2 * (size_t)n_entries + 255) & ~(size_t)255));
+  return d;
+}
+
 DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, double** g2) {
   size_t part[4];
   det_parts(n_entries, n_pairs, n_tiles, part);
@@ -812,8 +826,10 @@ void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
 
 void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, int mode, int loss,
                        const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
-                       float* loss_out, double* g2, int64_t total_pixels, const DetArgs* det, int64_t n,
-                       hipStream_t st) {
+                       float* loss_out, double* g2, int64_t total_pixels, bool det_mode, const DetArgs& dargs,
+                       int64_t n, hipStream_t st) {
+  const DetArgs* det = det_mode ? &dargs : nullptr;
+  const DetArgs* pdargs = &dargs;
   static const int pix = env_pix("SSS_PIX_BWD", 2);
   const float inv_count = 1.0f / (3.0f * (float)total_pixels);
   const dim3 grid((unsigned)cb.total_tiles);
@@ -836,14 +852,13 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                  (uint32_t)b.n_pairs, sr, *det, g2);
     }
     if (loss == SSS_LOSS_L1 && loss_out)
-      SSS_LAUNCH("det_loss", det_loss_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)det->loss_part,
+      SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)det->loss_part,
                  (int64_t)cb.total_tiles, loss_out);
     return;
   }
-  const DetArgs nodet{};
 #define SSS_BWD(P, M, L)                                                                                    \
   SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L, false>), grid, dim3(kBlock / P), 0, st, cb, op, sr, ts, pr, \
-             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, nodet)
+             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, *pdargs)
 #define SSS_BWD_P(M, L)              \
   if (pix == 1) SSS_BWD(1, M, L);    \
   else if (pix == 2) SSS_BWD(2, M, L); \
@@ -854,6 +869,9 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
   else { SSS_BWD_P(SSS_BWD_RECOMPUTE, SSS_LOSS_L1); }
 #undef SSS_BWD_P
 #undef SSS_BWD
+  if (loss == SSS_LOSS_L1 && loss_out)
+    SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)dargs.loss_part,
+               (int64_t)cb.total_tiles, loss_out);
 }
 
 }  // namespace sss

@@ -114,7 +114,7 @@ def lib():
         L.sss_bin_sort_workspace.restype = ctypes.c_size_t
         L.sss_bin_sort_workspace.argtypes = [i64, i64]
         L.sss_render_bwd_workspace.restype = ctypes.c_size_t
-        L.sss_render_bwd_workspace.argtypes = [i64]
+        L.sss_render_bwd_workspace.argtypes = [i64, i64]
         L.sss_render_bwd_workspace_det.restype = ctypes.c_size_t
         L.sss_render_bwd_workspace_det.argtypes = [i64, i64, i64]
         L.sss_total_tiles.restype = i64
@@ -355,7 +355,7 @@ def render_bwd(scene, proj: Projected, bins: Binned, cams, dl_or_target, opts=No
         mode |= BWD_DETERMINISTIC
         need = int(lib().sss_render_bwd_workspace_det(E, bins.n_pairs, total_tiles(cams)))
     else:
-        need = int(lib().sss_render_bwd_workspace(E))
+        need = int(lib().sss_render_bwd_workspace(E, total_tiles(cams)))
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need // 4, dtype=torch.float32, device=scene["means"].device)
     s = scene_struct(scene)

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(sss):
     lib = ctypes.CDLL(sss.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert sss.lib().sss_version() == 101
+    assert sss.lib().sss_version() == 102
 
 
 def test_default_options(sss):
@@ -58,7 +58,8 @@ def test_workspace_sizes_grow(sss):
     a = L.sss_bin_sort_workspace(1000, 1000)
     b = L.sss_bin_sort_workspace(1000, 10 ** 6)
     assert 0 < a < b
-    assert L.sss_render_bwd_workspace(1000) == 1000 * 12 * 8          # FP64 per-entry sums
+    assert L.sss_render_bwd_workspace(1000, 0) == 1000 * 12 * 8       # FP64 per-entry sums
+    assert L.sss_render_bwd_workspace(1000, 100) >= 1000 * 12 * 8 + 400
 
 
 def _scene_struct(sss, n=10, deg=0, null=None):
