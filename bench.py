@@ -266,7 +266,7 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
         # means, SH, per view touched and 24 B FP64 colour gradient in; d_sh and d_means out
         "sh_bwd": n * (4 * (3 + 3 * K) + V * 28 + 4 * (3 * K + 3)),
         "sghmc": n * 64,
-        "adam": n * (3 + 4 + 1 + 1 + 3 * K) * 28 / 5,           # per launch, 5 arrays
+        "adam": n * (3 + 4 + 1 + 1 + 3 * K) * 28,               # one launch over the 5 arrays
     }
     stages = {k: {"ms_per_step": round(per_step[k], 4), "launches_per_step": kt[k][0] / n_inst}
               for k in sorted(kt)}
@@ -276,7 +276,7 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
             stages[k]["hbm_frac"] = round(b / (avg[k] * 1e-3) / PEAK_HBM, 4)
     if "render_fwd" in avg:
         stages["render_fwd"]["valu_frac"] = round(SLOTS_FWD * evals / (avg["render_fwd"] * 1e-3) / PEAK_VALU, 4)
-    step_bytes = (bytes_["project"] + bytes_["project_bwd"] + bytes_["sh_bwd"] + bytes_["sghmc"] + 5 * bytes_["adam"]
+    step_bytes = (bytes_["project"] + bytes_["project_bwd"] + bytes_["sh_bwd"] + bytes_["sghmc"] + bytes_["adam"]
                   + 16 * n + 136 * bins.n_visible + 8 * bins.n_pairs + P * (12 + 12 + 4 + 12))
 
     return dict(ms_step=ms_step, value=value, evals=evals, bins=bins, stages=stages, kt=kt, P=P, n=n,

@@ -281,7 +281,8 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
  * counter (i lo, step lo, step hi, i hi); uniforms ((x >> 9) + 1/2) 2^-23;
  * Box-Muller on words (0, 1) for x, y and (2, 3) for z.  noise = 0 turns it off.
  * adam (nullable): Adam (beta1, beta2, eps, step t >= 1) on up to 6 further
- * arrays (the paper's non-mean parameters), each clamped to [lo, hi].
+ * arrays (the paper's non-mean parameters), each clamped to [lo, hi]; one
+ * launch for all arrays (an array of count 0 is skipped).
  * Arrays: device FP32; means, momentum, grad_means [n][3]; opacity [n];
  * scales [n][3] and quats [n][4] (read only for burn_in).
  * Errors: INVALID for n <= 0, NULL arrays, lr < 0, adam->t < 1. */

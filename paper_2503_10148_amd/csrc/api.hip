@@ -274,17 +274,15 @@ int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const
     }
     for (int k = 0; k < adam->n_arrays; ++k) {
       const sss_adam_array_t& a = adam->arrays[k];
-      if (!a.param || !a.grad || !a.m || !a.v || a.count < 0) {
-        set_error("sss_sghmc_step: adam array %d has a null pointer or negative count", k);
+      if (a.count < 0 || (a.count > 0 && (!a.param || !a.grad || !a.m || !a.v))) {
+        set_error("sss_sghmc_step: adam array %d has a null pointer or a negative count", k);
         return SSS_ERR_INVALID;
       }
     }
   }
   hipStream_t st = (hipStream_t)stream;
   launch_sghmc(means, momentum, grad_means, opacity, scales, quats, n, *opts, st);
-  if (adam)
-    for (int k = 0; k < adam->n_arrays; ++k)
-      if (adam->arrays[k].count > 0) launch_adam(adam->arrays[k], adam->beta1, adam->beta2, adam->eps, adam->t, st);
+  if (adam) launch_adam(*adam, st);
   return hip_ok(hipGetLastError(), "sss_sghmc_step launch") ? SSS_OK : SSS_ERR_HIP;
 }
 

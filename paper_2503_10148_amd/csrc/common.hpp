@@ -127,7 +127,7 @@ int run_relocate(const sss_scene_t& s, float* const* state, const int32_t* width
                  const sss_relocate_opts_t& o, void* ws, size_t ws_bytes, int64_t* n_moved, hipStream_t st);
 void launch_sghmc(float* means, float* mom, const float* g, const float* opac, const float* scales,
                   const float* quats, int64_t n, const sss_sghmc_opts_t& o, hipStream_t st);
-void launch_adam(const sss_adam_array_t& a, float b1, float b2, float eps, int64_t t, hipStream_t st);
+void launch_adam(const sss_adam_t& ad, hipStream_t st);
 void launch_regularise(const float* opac, const float* scales, int64_t n, float eps_o, float eps_s, float* d_opac,
                        float* d_scales, float* loss_out, hipStream_t st);
 

@@ -75,19 +75,44 @@ __global__ __launch_bounds__(kBlock) void sghmc_kernel(float* __restrict__ means
   }
 }
 
-__global__ __launch_bounds__(kBlock) void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
-                                                      float* __restrict__ m, float* __restrict__ v, int64_t n,
-                                                      float lr, float b1, float b2, float omb1, float omb2, float eps,
-                                                      float c1, float c2, float lo, float hi) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + omb1 * gi;
-  const float vi = b2 * v[i] + omb2 * gi * gi;
+// Adam on up to six arrays in one launch: array a owns the workgroups
+// [first_block[a], first_block[a+1]), so the array (and its pointers) is
+// uniform over a workgroup and is picked on scalar registers.
+struct AdamBatch {
+  float* p[6];
+  const float* g[6];
+  float* m[6];
+  float* v[6];
+  int64_t count[6];
+  uint32_t first_block[7];
+  float lr[6], lo[6], hi[6];
+  int32_t n;
+};
+
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float lo, float hi, float b1,
+                                         float b2, float omb1, float omb2, float eps, float c1, float c2) {
+  m = b1 * m + omb1 * g;
+  v = b2 * v + omb2 * g * g;
+  const float upd = lr * (m / c1) / (sqrtf(v / c2) + eps);
+  p = fminf(fmaxf(p - upd, lo), hi);
+}
+
+__global__ __launch_bounds__(kBlock) void adam_kernel(AdamBatch ab, float b1, float b2, float omb1, float omb2,
+                                                      float eps, float c1, float c2) {
+  int a = 0;
+  for (int k = 1; k < ab.n; ++k)
+    if (blockIdx.x >= ab.first_block[k]) a = k;
+  a = __builtin_amdgcn_readfirstlane(a);
+  const int64_t i = (int64_t)(blockIdx.x - ab.first_block[a]) * kBlock + threadIdx.x;
+  if (i >= ab.count[a]) return;
+  float* __restrict__ p = ab.p[a];
+  float* __restrict__ m = ab.m[a];
+  float* __restrict__ v = ab.v[a];
+  float pi = p[i], mi = m[i], vi = v[i];
+  adam_one(pi, ab.g[a][i], mi, vi, ab.lr[a], ab.lo[a], ab.hi[a], b1, b2, omb1, omb2, eps, c1, c2);
+  p[i] = pi;
   m[i] = mi;
   v[i] = vi;
-  const float upd = lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  p[i] = fminf(fmaxf(p[i] - upd, lo), hi);
 }
 
 // Regularisers of the Sec. 3.4 loss: eps_o sum_i |o_i| + eps_s sum_ij sqrt(lambda_ij)
@@ -134,13 +159,28 @@ void launch_sghmc(float* means, float* mom, const float* g, const float* opac, c
                      opac, scales, quats, n, o.lr, o.friction, o.k, o.t, (int)o.burn_in, (int)o.noise, o.seed, o.step);
 }
 
-void launch_adam(const sss_adam_array_t& a, float b1, float b2, float eps, int64_t t, hipStream_t st) {
+void launch_adam(const sss_adam_t& ad, hipStream_t st) {
   // 1 - beta and the bias corrections on the host, in FP64
-  const float c1 = (float)(1.0 - pow((double)b1, (double)t));
-  const float c2 = (float)(1.0 - pow((double)b2, (double)t));
-  const float omb1 = (float)(1.0 - (double)b1), omb2 = (float)(1.0 - (double)b2);
-  SSS_LAUNCH("adam", adam_kernel, dim3((unsigned)((a.count + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a.param,
-                     a.grad, a.m, a.v, a.count, a.lr, b1, b2, omb1, omb2, eps, c1, c2, a.lo, a.hi);
+  const float c1 = (float)(1.0 - pow((double)ad.beta1, (double)ad.t));
+  const float c2 = (float)(1.0 - pow((double)ad.beta2, (double)ad.t));
+  const float omb1 = (float)(1.0 - (double)ad.beta1), omb2 = (float)(1.0 - (double)ad.beta2);
+  AdamBatch ab{};
+  ab.first_block[0] = 0;
+  int k = 0;
+  for (int a = 0; a < ad.n_arrays; ++a) {
+    const sss_adam_array_t& x = ad.arrays[a];
+    if (x.count <= 0) continue;
+    ab.p[k] = x.param; ab.g[k] = x.grad; ab.m[k] = x.m; ab.v[k] = x.v;
+    ab.lr[k] = x.lr; ab.lo[k] = x.lo; ab.hi[k] = x.hi;
+    ab.count[k] = x.count;
+    ab.first_block[k + 1] = ab.first_block[k] + (uint32_t)((x.count + kBlock - 1) / kBlock);
+    ++k;
+  }
+  ab.n = k;
+  const uint32_t blocks = ab.first_block[k];
+  if (blocks == 0) return;
+  SSS_LAUNCH("adam", adam_kernel, dim3(blocks), dim3(kBlock), 0, st, ab,
+             ad.beta1, ad.beta2, omb1, omb2, ad.eps, c1, c2);
 }
 
 }  // namespace sss

@@ -421,6 +421,34 @@ def test_adam_matches_oracle(sss):
     np.testing.assert_allclose(dv.cpu().numpy(), ref[2], rtol=1e-5, atol=1e-8)
 
 
+def test_adam_on_six_arrays_in_one_launch(sss):
+    """Arrays of different lengths (one empty), learning rates and bounds in
+    one call: each element is updated with its own array's settings."""
+    rng = np.random.default_rng(4)
+    f32 = lambda x: float(np.float32(x))
+    sizes = [3001, 0, 1, 4096, 777, 12345]
+    specs = [(0.01, -1.0, 1.0), (0.5, -2.0, 2.0), (0.02, 0.0, 0.5), (1e-3, -3e38, 3e38), (0.1, -0.2, 0.3),
+             (2.5e-4, -3e38, 3e38)]
+    T = lambda a: torch.as_tensor(a.copy(), device="cuda")
+    host, arrays = [], []
+    for nsz, (lr, lo, hi) in zip(sizes, specs):
+        p, g = rng.standard_normal(nsz).astype(np.float32), rng.standard_normal(nsz).astype(np.float32)
+        m, v = (rng.standard_normal(nsz) * 0.1).astype(np.float32), rng.uniform(0, 0.1, nsz).astype(np.float32)
+        host.append(oracle.adam_step(p, g, m, v, lr=f32(lr), b1=f32(0.9), b2=f32(0.999), eps=f32(1e-15), t=3,
+                                     lo=f32(lo), hi=f32(hi)) if nsz else None)
+        arrays.append(dict(param=T(p), grad=T(g), m=T(m), v=T(v), lr=lr, lo=lo, hi=hi))
+    z = torch.zeros((1, 3), device="cuda")
+    sss.sghmc_step(z.clone(), z.clone(), z.clone(), torch.ones(1, device="cuda"), 0.0, noise=False,
+                   adam=dict(beta1=0.9, beta2=0.999, eps=1e-15, t=3, arrays=arrays))
+    torch.cuda.synchronize()
+    for a, ref in zip(arrays, host):
+        if ref is None:
+            continue
+        np.testing.assert_allclose(a["param"].cpu().numpy(), ref[0], rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(a["m"].cpu().numpy(), ref[1], rtol=1e-5, atol=1e-7)
+        np.testing.assert_allclose(a["v"].cpu().numpy(), ref[2], rtol=1e-5, atol=1e-8)
+
+
 @pytest.mark.parametrize("name", ["sh3_ragged", "bigcomp"])
 def test_gaussian_family_matches_oracle(sss, name):
     scene, cams = _case(name)
