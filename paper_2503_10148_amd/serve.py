@@ -45,19 +45,42 @@ class _Req:
         self.t_done = None
 
 
+class _Slot:
+    """Per-stream scratch buffers that only grow (projection outputs, bins,
+    the pair list and sort workspace, per-pixel side outputs), reused by every
+    batch launched on the stream; images handed to callers are allocated per
+    batch."""
+
+    def __init__(self):
+        self.binner = sss.BinSorter(0)
+        self.buf = {}
+
+    def take(self, name, shape, dtype, device):
+        numel = int(math.prod(shape))
+        b = self.buf.get(name)
+        if b is None or b.numel() < numel:
+            b = torch.empty(max(numel, 1), dtype=dtype, device=device)
+            self.buf[name] = b
+        return b[:numel].view(shape)
+
+
 class RenderServer:
     def __init__(self, scene: dict, opts=None, max_batch: int = 16, mem_budget: int = 6 << 30,
-                 n_streams: int = 2, pairs_per_pixel: float = 20.0, device: int = 0):
-        """scene: dict of device tensors (see sss.scene_struct)."""
+                 n_streams: int = 2, pairs_per_pixel: float = 20.0, device: int = 0, max_inflight: int | None = None):
+        """scene: dict of device tensors (see sss.scene_struct).  At most
+        `max_inflight` batches (default: n_streams) are on the device at once;
+        requests arriving meanwhile wait and join the next batch."""
         if not 1 <= max_batch <= sss.MAX_VIEWS:
             raise ValueError(f"max_batch must be in 1..{sss.MAX_VIEWS}")
         self.scene = scene
         self.n = scene["means"].shape[0]
         self.opts = opts
         self.max_batch = max_batch
+        self.max_inflight = n_streams if max_inflight is None else max(1, int(max_inflight))
         self.mem_budget = int(mem_budget)
         self.device = device
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self._slots = [_Slot() for _ in range(n_streams)]
         self.pairs_per_pixel = float(pairs_per_pixel)   # running estimate, refined from every batch
         self._q = collections.deque()
         self._cv = threading.Condition()
@@ -113,6 +136,9 @@ class RenderServer:
                     self._cv.wait()
                 if not self._running and not self._q:
                     return
+                if len(self._inflight) + self._launching >= self.max_inflight:
+                    self._cv.wait(timeout=0.05)              # let requests gather for the next batch
+                    continue
                 batch = []
                 while self._q and len(batch) < self.max_batch:
                     cand = batch + [self._q[0]]
@@ -127,9 +153,10 @@ class RenderServer:
                 self._mem_used += need
                 self._launching += 1
             stream = self.streams[k % len(self.streams)]
+            slot = self._slots[k % len(self.streams)]
             k += 1
             try:
-                keep, ev = self._launch(batch, stream)
+                keep, ev = self._launch(batch, stream, slot)
             except Exception as exc:                            # pragma: no cover - surfaced to callers
                 for r in batch:
                     r.future.set_exception(exc)
@@ -145,19 +172,31 @@ class RenderServer:
                 self.batch_sizes.append(len(batch))
                 self._cv.notify_all()
 
-    def _launch(self, batch, stream):
+    def _launch(self, batch, stream, slot):
         cams = [r.cam for r in batch]
+        dev = self.scene["means"].device
+        E = len(cams) * self.n
+        P = sum(r.pixels for r in batch)
+        T = sss.total_tiles(cams)
         with torch.cuda.stream(stream):
-            proj = sss.project(self.scene, cams, self.opts, stream=stream)
-            P = sum(r.pixels for r in batch)
-            binner = sss.BinSorter(int(P * self.pairs_per_pixel * 1.25) + 1024)
-            bins = binner(proj, cams, self.n, stream=stream)
-            image, _, _ = sss.render_fwd(bins, cams, self.opts, stream=stream)
+            proj = sss.Projected(slot.take("records", (E, sss.RECORD_BYTES), torch.uint8, dev),
+                                 slot.take("key", (E,), torch.int32, dev),
+                                 slot.take("rect", (E, 4), torch.int16, dev),
+                                 slot.take("touched", (E,), torch.int32, dev),
+                                 slot.take("ellipse", (E, 4), torch.float64, dev))
+            sss.project(self.scene, cams, self.opts, stream=stream, out=proj)
+            out = sss.Binned(slot.take("order", (E,), torch.int32, dev),
+                             slot.take("sorted", (E, sss.RECORD_BYTES), torch.uint8, dev),
+                             slot.take("tile_start", (T + 1,), torch.int32, dev), None)
+            bins = slot.binner(proj, cams, self.n, stream=stream, out=out)
+            image, _, _ = sss.render_fwd(bins, cams, self.opts, stream=stream,
+                                         t_final=slot.take("t_final", (P,), torch.float32, dev),
+                                         n_contrib=slot.take("n_contrib", (P,), torch.int32, dev))
             ev = torch.cuda.Event()
             ev.record(stream)
         if P > 0:
             self.pairs_per_pixel = 0.8 * self.pairs_per_pixel + 0.2 * bins.n_pairs / P
-        return (proj, bins, binner, image), ev
+        return (proj, bins, image), ev
 
     def _complete(self):
         torch.cuda.set_device(self.device)
@@ -170,7 +209,7 @@ class RenderServer:
                 ev, batch, need, keep = self._inflight[0]
             ev.synchronize()
             t = time.perf_counter()
-            image = keep[3]
+            image = keep[2]
             off = 0
             for r in batch:
                 H, W = int(r.cam["height"]), int(r.cam["width"])
