@@ -300,7 +300,7 @@ def main():
     ap.add_argument("--cpu-window", type=int, default=768 * 768)
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="arrival window of each serving run (0 disables the serving measurement)")
-    ap.add_argument("--serve-rates", default="200,1000",
+    ap.add_argument("--serve-rates", default="200,500,1000",
                     help="Poisson request rates (req/s) for the serving comparison")
     args = ap.parse_args()
     if args.copy_probe:
