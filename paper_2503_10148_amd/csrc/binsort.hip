@@ -129,9 +129,18 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRPerBlock;
+  // all loads first, so their latencies overlap (LDS atomics in between
+  // would keep the compiler from hoisting them)
+  uint32_t kk[kRItems];
+#pragma unroll
   for (int k = 0; k < kRItems; ++k) {
     const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-    if (j < n) atomicAdd(&h[radix_digit(keys[j], base_key, cap, shift, mask)], 1u);
+    kk[k] = j < n ? keys[j] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < kRItems; ++k) {
+    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
+    if (j < n) atomicAdd(&h[radix_digit(kk[k], base_key, cap, shift, mask)], 1u);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
@@ -161,12 +170,18 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   const int64_t block0 = (int64_t)blockIdx.x * kRPerBlock;
   const int64_t base = block0 + (int64_t)w * (kRPerBlock / 4);
   uint32_t key[kRItems], val[kRItems], loc[kRItems];
+  // all loads first: the ranking below writes LDS between rounds, which
+  // would otherwise serialise one memory latency per round
+#pragma unroll
+  for (int r = 0; r < kRItems; ++r) {
+    const int64_t j = base + (int64_t)r * 64 + lane;
+    key[r] = j < n ? keys[j] : 0u;
+    val[r] = j < n ? vals[j] : 0u;
+  }
 #pragma unroll
   for (int r = 0; r < kRItems; ++r) {
     const int64_t j = base + (int64_t)r * 64 + lane;
     const bool ok = j < n;
-    key[r] = ok ? keys[j] : 0u;
-    val[r] = ok ? vals[j] : 0u;
     const uint32_t d = radix_digit(key[r], base_key, cap, shift, mask);
     uint64_t peers = __ballot(ok);
     for (int b = 0; b < bits; ++b) {
