@@ -187,18 +187,43 @@ template <int DEG>
 __device__ __forceinline__ void stage_sh(const float* __restrict__ sh, int64_t i0, int cnt, float* lds) {
   constexpr int KC = 3 * (DEG + 1) * (DEG + 1), STR = KC + 1;
   const float* src = sh + (size_t)i0 * KC;
-  if (KC % 4 == 0) {
+  // every load of the thread is issued before the first LDS store, so the
+  // memory latencies overlap instead of adding up
+  if constexpr (KC % 4 == 0) {
+    constexpr int PER = KC / 4;                 // float4 loads per thread for a full block
     const float4* s4 = reinterpret_cast<const float4*>(src);
-    for (int g = threadIdx.x; g < cnt * KC / 4; g += kBlock) {
-      const float4 q = s4[g];
-      const int f = 4 * g, c = f / KC, j = f - c * KC;
-      float* d = lds + c * STR + j;
-      d[0] = q.x; d[1] = q.y; d[2] = q.z; d[3] = q.w;
+    const int total = cnt * KC / 4;
+    float4 q[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int g = threadIdx.x + it * kBlock;
+      q[it] = g < total ? s4[g] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int g = threadIdx.x + it * kBlock;
+      if (g < total) {
+        const int f = 4 * g, c = f / KC, j = f - c * KC;
+        float* d = lds + c * STR + j;
+        d[0] = q[it].x; d[1] = q[it].y; d[2] = q[it].z; d[3] = q[it].w;
+      }
     }
   } else {
-    for (int g = threadIdx.x; g < cnt * KC; g += kBlock) {
-      const int c = g / KC, j = g - c * KC;
-      lds[c * STR + j] = src[g];
+    constexpr int PER = KC;                     // loads per thread for a full block
+    const int total = cnt * KC;
+    float q[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int g = threadIdx.x + it * kBlock;
+      q[it] = g < total ? src[g] : 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int g = threadIdx.x + it * kBlock;
+      if (g < total) {
+        const int c = g / KC, j = g - c * KC;
+        lds[c * STR + j] = q[it];
+      }
     }
   }
 }
