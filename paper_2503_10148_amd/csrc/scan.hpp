@@ -47,24 +47,49 @@ __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const T* __restrict
   if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
 }
 
-// Exclusive scan of one 4096-item block plus the block's prefix (in may alias out).
+// Exclusive scan of one 4096-item block plus the block's prefix (in may alias
+// out).  Loads and stores are coalesced (item k*256 + t by thread t) and
+// staged in LDS with one pad word per 16, so that thread t can scan its 16
+// consecutive items without bank conflicts.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const T* in, int64_t n, const T* __restrict__ prefix,
                                                             T* out) {
+  constexpr int kPad = kItems + 1;
   __shared__ T lds[kBlock];
-  const int64_t base = (int64_t)blockIdx.x * kPerBlock + (int64_t)threadIdx.x * kItems;
+  __shared__ T tile[kBlock * kPad];
+  const int64_t base = (int64_t)blockIdx.x * kPerBlock;
+  const int t = threadIdx.x;
+  T ld[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t j = base + (int64_t)k * kBlock + t;
+    ld[k] = j < n ? in[j] : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int i = k * kBlock + t;                // item index inside the block
+    tile[(i / kItems) * kPad + i % kItems] = ld[k];
+  }
+  __syncthreads();
   T v[kItems];
   T s = 0;
+#pragma unroll
   for (int k = 0; k < kItems; ++k) {
-    const int64_t j = base + k;
-    v[k] = j < n ? in[j] : T(0);
+    v[k] = tile[t * kPad + k];
     s += v[k];
   }
   T run = block_excl_scan<T>(s, lds, nullptr) + (prefix ? prefix[blockIdx.x] : T(0));
+#pragma unroll
   for (int k = 0; k < kItems; ++k) {
-    const int64_t j = base + k;
-    if (j < n) out[j] = run;
+    tile[t * kPad + k] = run;
     run += v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int i = k * kBlock + t;
+    const int64_t j = base + i;
+    if (j < n) out[j] = tile[(i / kItems) * kPad + i % kItems];
   }
 }
 
