@@ -574,3 +574,47 @@ def test_deterministic_backward_multiview_l1_loss(sss):
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), k
         ok, worst = grad_close(a, gref[k], mask=~skip)
         assert ok, (k, worst)
+
+
+# ---------------------------------------------------------------------------
+# components spanning many tile rows: the per-wave row tables overflow and
+# the emission / deterministic reduction take their wave-wide fallback
+# ---------------------------------------------------------------------------
+def test_huge_components_overflow_the_row_tables(sss):
+    s = scenes.make_scene(300, 1, seed=19, neg_frac=0.3, scale_range=(0.4, 1.2))
+    cams = [scenes.ring_camera(640, 360, angle=0.7)]
+    cam = cams[0]
+    n = s["means"].shape[0]
+    o = oracle.project(s, cam)
+    vis = o["touched"] > 0
+    rows = (o["rect"][:, 3] - o["rect"][:, 1] + 1)[vis]
+    assert vis.sum() >= 128 and rows.mean() > 12          # > 640 table rows per wave of 64 entries
+    tx, ty = oracle.tiles(cam)
+    ost, olst = oracle.bin_tiles(o["touched"], o["rect"], o["key"], tx, ty, proj=o)
+    dev = to_device(s)
+    proj = sss.project(dev, cams)
+    bins = sss.BinSorter(1024, keep_offsets=True)(proj, cams, n)
+    torch.cuda.synchronize()
+    order = bins.order.cpu().numpy().view(np.uint32).astype(np.int64)
+    start = bins.tile_start.cpu().numpy().astype(np.int64)
+    pr = bins.pair_rank.cpu().numpy()[: bins.n_pairs].astype(np.int64)
+    flagged = set(np.nonzero(o["pflags"] & oracle.PF_RECT_EDGE)[0].tolist())
+    for t in range(tx * ty):
+        g = [int(i) for i in order[pr[start[t]:start[t + 1]]] if int(i) not in flagged]
+        r = [int(i) for i in olst[ost[t]:ost[t + 1]] if int(i) not in flagged]
+        assert g == r, t
+    ref = oracle.render(s, cam)
+    img, _, ncon = sss.render_fwd(bins, cams)
+    bad, _, _ = _image_check(img.cpu().numpy(), ref, ref["xflags"])
+    assert not bad.any()
+    w = np.random.default_rng(20).standard_normal(ref["image"].shape)
+    w[ref["xflags"] != 0] = 0.0
+    gref = oracle.render_backward(s, cam, w, fwd=ref)
+    dl = torch.as_tensor(w.reshape(-1, 3), dtype=torch.float32, device="cuda")
+    keep = ref["proj"]["pflags"] == 0
+    for det in (False, True):
+        g = sss.render_bwd(dev, proj, bins, cams, dl, image=img, n_contrib=ncon, deterministic=det)
+        torch.cuda.synchronize()
+        for k in PARAMS:
+            ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=keep)
+            assert ok, (det, k, worst)
