@@ -289,6 +289,43 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
   for (int j = 0; j < 64; ++j) {
     const int cntj = bcast_i(my_cnt, j);
     if (cntj == 0) continue;
+    // two small entries at once: lanes 0..31 take entry j, lanes 32..63 entry
+    // j + 1 (both in the table, at most 32 pairs each; halves the sequential
+    // steps for the common case)
+    if (j + 1 < 64) {
+      const int cnt1 = bcast_i(my_cnt, j + 1);
+      if (cntj <= 32 && cnt1 <= 32 && __builtin_amdgcn_readlane((int)wr.fits, j) &&
+          __builtin_amdgcn_readlane((int)wr.fits, j + 1)) {
+        const bool hi = lane >= 32;
+        const int kk = lane & 31;
+        const int cnt = hi ? cnt1 : cntj;
+        const int tot = hi ? bcast_i(wr.total, j + 1) : bcast_i(wr.total, j);
+        const uint32_t offk = (uint32_t)(hi ? bcast_i(my_off, j + 1) : bcast_i(my_off, j));
+        const uint32_t rank = (uint32_t)(r0 + j + (hi ? 1 : 0));
+        if (kk < cnt) {
+          uint32_t key = (uint32_t)cb.total_tiles;   // sentinel for slots beyond the listed tiles
+          if (kk < tot) {
+            const int base = hi ? bcast_i(wr.base, j + 1) : bcast_i(wr.base, j);
+            const int h = hi ? bcast_i(wr.h, j + 1) : bcast_i(wr.h, j);
+            int lo = 0, hq = h - 1;
+            while (lo < hq) {
+              const int mid = (lo + hq + 1) >> 1;
+              if ((int)table->cum[base + mid] <= kk) lo = mid;
+              else hq = mid - 1;
+            }
+            const int x = (int)table->t0[base + lo] + (kk - (int)table->cum[base + lo]);
+            const int y = (hi ? bcast_i(my_y0, j + 1) : bcast_i(my_y0, j)) + lo;
+            const int toff = hi ? bcast_i(my_toff, j + 1) : bcast_i(my_toff, j);
+            const int tx = hi ? bcast_i(my_tx, j + 1) : bcast_i(my_tx, j);
+            key = (uint32_t)(toff + y * tx + x);
+          }
+          tkeys[offk + kk] = key;
+          tvals[offk + kk] = rank;
+        }
+        ++j;
+        continue;
+      }
+    }
     const uint32_t offj = (uint32_t)bcast_i(my_off, j);
     const uint32_t rank = (uint32_t)(r0 + j);
     const int toff = bcast_i(my_toff, j), tx = bcast_i(my_tx, j);
