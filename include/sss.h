@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define SSS_VERSION 102
+#define SSS_VERSION 103
 #define SSS_TILE 16           /* tile edge in pixels                            */
 #define SSS_MAX_VIEWS 16      /* views per call                                 */
 #define SSS_RECORD_BYTES 64   /* size of one projected record                  */
@@ -192,6 +192,20 @@ int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
  *                  order: rank r emitted its rectangle's tiles row-major at
  *                  positions rank_offset[r] + k, k < tiles_touched.  Needed
  *                  by the deterministic backward pass.
+ *   tile_order     [n_tiles] (nullable) a permutation of the global tiles,
+ *                  longest list first (coarse buckets of the list length;
+ *                  order within a bucket unspecified).  sss_render_fwd and
+ *                  the recompute backward launch tile tile_order[b] as
+ *                  workgroup b, so the tiles with the most work start
+ *                  first; NULL launches them in row-major order.  Only the
+ *                  schedule changes: every tile's result is the same.
+ *   tile_work      [n_tiles] (nullable) not written here: sss_render_fwd
+ *                  stores each tile's largest n_contrib (the list prefix
+ *                  the backward pass walks), and the stored-mode backward
+ *                  orders its tiles by it.
+ * A non-NULL tile_order must hold what sss_bin_sort wrote (tiles outside
+ * the grid are skipped, so another permutation only reorders work and
+ * anything else leaves tiles unrendered).
  * Host outputs: n_visible, n_pairs (always written when the call returns
  * SSS_OK or SSS_ERR_CAPACITY).
  * Workspace: ws of ws_bytes >= sss_bin_sort_workspace(n_entries, pair_capacity).
@@ -204,6 +218,8 @@ typedef struct {
   uint32_t* tile_start;
   uint32_t* pair_rank;
   uint32_t* rank_offset;
+  uint32_t* tile_order;
+  uint32_t* tile_work;
   int64_t pair_capacity;
   int64_t n_visible;   /* out */
   int64_t n_pairs;     /* out */
@@ -225,6 +241,8 @@ int sss_bin_sort(const sss_proj_t* proj, const sss_camera_t* cams, int n_views, 
  *   image     [P][3]  C + T bg
  *   t_final   [P]     final transmittance T
  *   n_contrib [P]     list position after the last added component
+ *   bins->tile_work   (if not NULL) per tile, the largest n_contrib of its pixels
+ * Tiles are launched in bins->tile_order when it is not NULL.
  * Errors: INVALID for NULL pointers / bad views. */
 int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views,
                    const sss_render_opts_t* opts, float* image, float* t_final,
@@ -254,9 +272,12 @@ int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views
  *                           nullable) receives += L
  * grads: += or = (see sss_grads_t).  Workspace: ws_bytes >=
  * sss_render_bwd_workspace(n_views*n, n_tiles) (per-entry screen-space
- * gradients, 12 FP64 each, and one loss value per tile; the L1 loss is
- * summed over tiles in a fixed order, so loss_out gets the same value on
- * every run).
+ * gradients, 12 FP64 each, one loss value per tile and the tiles' launch
+ * order; the L1 loss is summed over tiles in a fixed order, so loss_out
+ * gets the same value on every run).  Tile schedule: in stored mode with
+ * bins->tile_work set (by sss_render_fwd), the tiles with the longest
+ * walks start first; otherwise bins->tile_order (or row-major) as in the
+ * forward pass.  The schedule never changes a tile's own sums.
  * Errors: INVALID for NULL pointers, a short workspace, unknown mode/loss. */
 enum { SSS_BWD_STORED = 0, SSS_BWD_RECOMPUTE = 1, SSS_BWD_DETERMINISTIC = 4 };
 enum { SSS_LOSS_GRAD = 0, SSS_LOSS_L1 = 1 };

@@ -186,6 +186,8 @@ __device__ __forceinline__ float g2_scale(int idx) { return idx < 2 ? -2.0f : (i
 // t/16 + k*(256/PIX)/16, k < PIX.
 template <int PIX>
 struct TileCtx {
+  int g;       // global tile id
+  bool skip;   // g is outside the grid (an order entry that is not a tile)
   int view, tx, ty;
   uint32_t start, end;
   double ox, oy;
@@ -196,11 +198,18 @@ struct TileCtx {
 };
 
 template <int PIX>
-__device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint32_t* __restrict__ tile_start) {
+__device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint32_t* __restrict__ tile_start,
+                                                 const uint32_t* __restrict__ tile_order) {
   constexpr int kThreads = kBlock / PIX;
   constexpr int kRowStep = kThreads / kTile;
   TileCtx<PIX> t;
-  const int g = blockIdx.x;
+  // workgroup b renders tile tile_order[b]: the tiles with the most work are
+  // launched first, so they do not run alone at the end of the grid
+  const uint32_t gu = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
+  t.g = (int)gu;
+  t.skip = gu >= (uint32_t)cb.total_tiles;
+  if (t.skip) return t;
+  const int g = t.g;
   int v = 0;
   for (int k = 1; k < cb.n_views; ++k)
     if (g >= cb.v[k].tile_offset) v = k;
@@ -361,12 +370,19 @@ __global__ __launch_bounds__(kBlock / PIX) void render_fwd_kernel(CamBatch cb, O
                                                                   const uint32_t* __restrict__ pair_rank,
                                                                   float* __restrict__ image,
                                                                   float* __restrict__ t_final,
-                                                                  uint32_t* __restrict__ n_contrib) {
+                                                                  uint32_t* __restrict__ n_contrib,
+                                                                  const uint32_t* __restrict__ tile_order,
+                                                                  uint32_t* __restrict__ tile_work) {
   __shared__ LRec lds[kBlock / PIX];
-  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start);
+  __shared__ uint32_t s_work;
+  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, tile_order);
+  if (t.skip) return;
+  if (threadIdx.x == 0) s_work = 0;
+  __syncthreads();
   float C[PIX][3], T[PIX];
   uint32_t last[PIX];
   forward_walk<PIX>(t, op, srec, pair_rank, lds, C, T, last);
+  uint32_t work = 0;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     if (!t.inside[k]) continue;
@@ -376,6 +392,12 @@ __global__ __launch_bounds__(kBlock / PIX) void render_fwd_kernel(CamBatch cb, O
     image[3 * p + 2] = C[k][2];
     if (t_final) t_final[p] = T[k];
     if (n_contrib) n_contrib[p] = last[k];
+    work = max(work, last[k]);
+  }
+  if (tile_work) {
+    atomicMax(&s_work, work);
+    __syncthreads();
+    if (threadIdx.x == 0) tile_work[t.g] = s_work;
   }
 }
 
@@ -391,7 +413,8 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   __shared__ LRec lds[kBatch];
   __shared__ uint32_t s_max;
   __shared__ float s_loss[kWaves];
-  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start);
+  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, det.tile_order);
+  if (t.skip) return;
   const int lane = threadIdx.x & 63;
 
   // ---- per-pixel forward output and loss gradient ----
@@ -463,10 +486,10 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   if (kLoss == SSS_LOSS_L1 && loss_out && threadIdx.x == 0) {
     float l = 0.0f;
     for (int w = 0; w < kWaves; ++w) l += s_loss[w];
-    det.loss_part[blockIdx.x] = l * inv_count;
+    det.loss_part[t.g] = l * inv_count;
   }
   // pairs of this tile up to rank lastp1 - 1 are visited (lists ascend in rank)
-  if (kDet && threadIdx.x == 0) det.lastp1[blockIdx.x] = stop > t.start ? pair_rank[stop - 1] + 1u : 0u;
+  if (kDet && threadIdx.x == 0) det.lastp1[t.g] = stop > t.start ? pair_rank[stop - 1] + 1u : 0u;
 
   // ---- front-to-back gradient walk ----
   const WaveStrips<PIX> ws = wave_strips<PIX>();
@@ -741,12 +764,64 @@ __global__ __launch_bounds__(kBlock) void loss_reduce_kernel(const float* __rest
   if (threadIdx.x == 0) atomicAdd(loss_out, red[0]);
 }
 
+// Launch order of the tiles: a counting sort by a logarithmic bucket of the
+// cost (12 buckets per doubling), most expensive bucket first.  One
+// workgroup; the order inside a bucket follows the LDS atomics.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 256;
+
+__device__ __forceinline__ int order_bucket(uint32_t c) {
+  const int b = (int)(12.0f * __log2f(1.0f + (float)c));
+  return kOrderBuckets - 1 - min(b, kOrderBuckets - 1);
+}
+
+__global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_t* __restrict__ cost,
+                                                                   const uint32_t* __restrict__ tile_start,
+                                                                   int64_t n_tiles, uint32_t* __restrict__ order) {
+  __shared__ uint32_t hist[kOrderBuckets];
+  for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) hist[i] = 0;
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < n_tiles; t += kOrderThreads) {
+    const uint32_t c = cost ? cost[t] : tile_start[t + 1] - tile_start[t];
+    atomicAdd(&hist[order_bucket(c)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    // exclusive scan of the 256 counts by one wave, 4 per lane
+    uint32_t c[4], s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c[k] = hist[4 * threadIdx.x + k];
+      s += c[k];
+    }
+    const uint32_t incl = (uint32_t)wave_incl_scan((int)s);
+    uint32_t run = incl - s;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      hist[4 * threadIdx.x + k] = run;
+      run += c[k];
+    }
+  }
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < n_tiles; t += kOrderThreads) {
+    const uint32_t c = cost ? cost[t] : tile_start[t + 1] - tile_start[t];
+    order[atomicAdd(&hist[order_bucket(c)], 1u)] = (uint32_t)t;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void zero_kernel(float4* __restrict__ p, int64_t n4) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n4) p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 }  // namespace
+
+void launch_tile_order(const uint32_t* cost, const uint32_t* tile_start, int64_t n_tiles, uint32_t* order,
+                       hipStream_t st) {
+  if (n_tiles <= 0) return;
+  SSS_LAUNCH("tile_order", tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, st, cost, tile_start, n_tiles,
+             order);
+}
 
 void launch_zero(float* p, int64_t count, hipStream_t st) {
   // count is a multiple of 4 for every caller (kG2 = 12 floats per entry)
@@ -756,51 +831,60 @@ void launch_zero(float* p, int64_t count, hipStream_t st) {
                      (float4*)p, n4);
 }
 
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 // Deterministic-mode workspace: screen-space gradients [E][kG2], per-pair
-// sums [M][kG2], per-tile visit bounds [T] and loss values [T], each
-// 256-byte aligned.
-static size_t det_parts(int64_t n_entries, int64_t n_pairs, int64_t n_tiles, size_t part[4]) {
+// sums [M][kG2], per-tile visit bounds [T], loss values [T] and tile order
+// [T], each 256-byte aligned.
+static size_t det_parts(int64_t n_entries, int64_t n_pairs, int64_t n_tiles, size_t part[5]) {
   part[0] = sizeof(double) * kG2 * (size_t)n_entries;
   part[1] = sizeof(float) * kG2 * (size_t)(n_pairs > 0 ? n_pairs : 1);
   part[2] = sizeof(uint32_t) * (size_t)n_tiles;
   part[3] = sizeof(float) * (size_t)n_tiles;
+  part[4] = sizeof(uint32_t) * (size_t)n_tiles;
   size_t total = 0;
-  for (int k = 0; k < 4; ++k) total += (part[k] + 255) & ~(size_t)255;
+  for (int k = 0; k < 5; ++k) total += align256(part[k]);
   return total;
 }
 
 size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_tiles) {
-  size_t part[4];
+  size_t part[5];
   return det_parts(n_entries, n_pairs, n_tiles, part);
 }
 
-// Workspace of the atomic mode: screen-space gradients [E][kG2] FP64 and the
-// per-tile loss values [T].
+// Workspace of the atomic mode: screen-space gradients [E][kG2] FP64, the
+// per-tile loss values [T] and the tile order [T].
 size_t render_bwd_workspace(int64_t n_entries, int64_t n_tiles) {
-  return ((sizeof(double) * kG2 * (size_t)n_entries + 255) & ~(size_t)255) + sizeof(float) * (size_t)n_tiles;
+  return align256(sizeof(double) * kG2 * (size_t)n_entries) + align256(sizeof(float) * (size_t)n_tiles) +
+         sizeof(uint32_t) * (size_t)n_tiles;
 }
 
 DetArgs carve_bwd(void* ws, int64_t n_entries, int64_t n_tiles, double** g2) {
   DetArgs d{};
-  *g2 = (double*)ws;
-  d.loss_part = (float*)((char*)ws + ((sizeof(double) * kG2 * (size_t)n_entries + 255) & ~(size_t)255));
+  char* p = (char*)ws;
+  *g2 = (double*)p;
+  p += align256(sizeof(double) * kG2 * (size_t)n_entries);
+  d.loss_part = (float*)p;
+  p += align256(sizeof(float) * (size_t)n_tiles);
+  d.order_ws = (uint32_t*)p;
   return d;
 }
 
 DetArgs carve_det(void* ws, int64_t n_entries, int64_t n_pairs, int64_t n_tiles, double** g2) {
-  size_t part[4];
+  size_t part[5];
   det_parts(n_entries, n_pairs, n_tiles, part);
-  char* q[4];
+  char* q[5];
   char* p = (char*)ws;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
     q[k] = p;
-    p += (part[k] + 255) & ~(size_t)255;
+    p += align256(part[k]);
   }
   DetArgs d{};
   *g2 = (double*)q[0];
   d.part = (float*)q[1];
   d.lastp1 = (uint32_t*)q[2];
   d.loss_part = (float*)q[3];
+  d.order_ws = (uint32_t*)q[4];
   return d;
 }
 
@@ -817,7 +901,8 @@ void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
   const Rec* sr = (const Rec*)b.sorted_records;
 #define SSS_FWD(P)                                                                                          \
   SSS_LAUNCH("render_fwd", render_fwd_kernel<P>, grid, dim3(kBlock / P), 0, st, cb, op, sr,                \
-             (const uint32_t*)b.tile_start, (const uint32_t*)b.pair_rank, image, t_final, n_contrib)
+             (const uint32_t*)b.tile_start, (const uint32_t*)b.pair_rank, image, t_final, n_contrib,           \
+             (const uint32_t*)b.tile_order, b.tile_work)
   if (pix == 1) SSS_FWD(1);
   else if (pix == 2) SSS_FWD(2);
   else SSS_FWD(4);
@@ -828,8 +913,16 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                        const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
                        float* loss_out, double* g2, int64_t total_pixels, bool det_mode, const DetArgs& dargs,
                        int64_t n, hipStream_t st) {
-  const DetArgs* det = det_mode ? &dargs : nullptr;
-  const DetArgs* pdargs = &dargs;
+  // tile schedule: by the forward's walk lengths when the backward walks
+  // the stored prefixes, else the binning's list-length order
+  DetArgs da = dargs;
+  da.tile_order = b.tile_order;
+  if (mode == SSS_BWD_STORED && b.tile_work && da.order_ws) {
+    launch_tile_order(b.tile_work, nullptr, cb.total_tiles, da.order_ws, st);
+    da.tile_order = da.order_ws;
+  }
+  const DetArgs* det = det_mode ? &da : nullptr;
+  const DetArgs* pdargs = &da;
   static const int pix = env_pix("SSS_PIX_BWD", 2);
   const float inv_count = 1.0f / (3.0f * (float)total_pixels);
   const dim3 grid((unsigned)cb.total_tiles);
@@ -870,7 +963,7 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
 #undef SSS_BWD_P
 #undef SSS_BWD
   if (loss == SSS_LOSS_L1 && loss_out)
-    SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)dargs.loss_part,
+    SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)da.loss_part,
                (int64_t)cb.total_tiles, loss_out);
 }
 

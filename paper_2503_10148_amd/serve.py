@@ -187,7 +187,8 @@ class RenderServer:
             sss.project(self.scene, cams, self.opts, stream=stream, out=proj)
             out = sss.Binned(slot.take("order", (E,), torch.int32, dev),
                              slot.take("sorted", (E, sss.RECORD_BYTES), torch.uint8, dev),
-                             slot.take("tile_start", (T + 1,), torch.int32, dev), None)
+                             slot.take("tile_start", (T + 1,), torch.int32, dev), None,
+                             tile_order=slot.take("tile_order", (T,), torch.int32, dev))
             bins = slot.binner(proj, cams, self.n, stream=stream, out=out)
             image, _, _ = sss.render_fwd(bins, cams, self.opts, stream=stream,
                                          t_final=slot.take("t_final", (P,), torch.float32, dev),

@@ -59,7 +59,8 @@ class Proj(ctypes.Structure):
 
 class Bins(ctypes.Structure):
     _fields_ = [("order", ctypes.c_void_p), ("sorted_records", ctypes.c_void_p), ("tile_start", ctypes.c_void_p),
-                ("pair_rank", ctypes.c_void_p), ("rank_offset", ctypes.c_void_p), ("pair_capacity", ctypes.c_int64),
+                ("pair_rank", ctypes.c_void_p), ("rank_offset", ctypes.c_void_p), ("tile_order", ctypes.c_void_p),
+                ("tile_work", ctypes.c_void_p), ("pair_capacity", ctypes.c_int64),
                 ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64)]
 
 
@@ -274,22 +275,28 @@ class Binned:
     n_visible: int = 0
     n_pairs: int = 0
     rank_offset: torch.Tensor | None = None   # int32 [E], kept for the deterministic backward
+    tile_order: torch.Tensor | None = None    # int32 [tiles], launch order (longest list first)
+    tile_work: torch.Tensor | None = None     # int32 [tiles], per tile the largest n_contrib (from render_fwd)
 
     def struct(self):
         return Bins(self.order.data_ptr(), self.sorted_records.data_ptr(), self.tile_start.data_ptr(),
-                    self.pair_rank.data_ptr(), _addr(self.rank_offset), self.pair_rank.numel(), self.n_visible,
-                    self.n_pairs)
+                    self.pair_rank.data_ptr(), _addr(self.rank_offset), _addr(self.tile_order),
+                    _addr(self.tile_work), self.pair_rank.numel(), self.n_visible, self.n_pairs)
 
 
 class BinSorter:
     """Holds the pair and workspace buffers of sss_bin_sort and grows them
-    (with 25% headroom) when a call reports SSS_ERR_CAPACITY."""
+    (with 25% headroom) when a call reports SSS_ERR_CAPACITY.  With
+    `schedule` (default), the Binned it creates carries the tile launch
+    order and per-tile work arrays, so the raster kernels start the most
+    expensive tiles first."""
 
-    def __init__(self, pair_capacity: int = 0, keep_offsets: bool = False):
+    def __init__(self, pair_capacity: int = 0, keep_offsets: bool = False, schedule: bool = True):
         self.cap = int(pair_capacity)
         self.ws = None
         self.pair_rank = None
         self.keep_offsets = keep_offsets
+        self.schedule = schedule
 
     def __call__(self, proj: Projected, cams, n: int, stream=None, out: Binned | None = None) -> Binned:
         E = n * len(cams)
@@ -299,6 +306,9 @@ class BinSorter:
             out = Binned(torch.empty(E, dtype=torch.int32, device=dev),
                          torch.empty((E, RECORD_BYTES), dtype=torch.uint8, device=dev),
                          torch.empty(T + 1, dtype=torch.int32, device=dev), None)
+            if self.schedule:
+                out.tile_order = torch.empty(T, dtype=torch.int32, device=dev)
+                out.tile_work = torch.empty(T, dtype=torch.int32, device=dev)
         if self.keep_offsets and (out.rank_offset is None or out.rank_offset.numel() < E):
             out.rank_offset = torch.empty(E, dtype=torch.int32, device=dev)
         camarr = camera_array(cams)

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(sss):
     lib = ctypes.CDLL(sss.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert sss.lib().sss_version() == 102
+    assert sss.lib().sss_version() == 103
 
 
 def test_default_options(sss):
@@ -59,7 +59,7 @@ def test_workspace_sizes_grow(sss):
     b = L.sss_bin_sort_workspace(1000, 10 ** 6)
     assert 0 < a < b
     assert L.sss_render_bwd_workspace(1000, 0) == 1000 * 12 * 8       # FP64 per-entry sums
-    assert L.sss_render_bwd_workspace(1000, 100) >= 1000 * 12 * 8 + 400
+    assert L.sss_render_bwd_workspace(1000, 100) >= 1000 * 12 * 8 + 800    # + loss and order per tile
 
 
 def _scene_struct(sss, n=10, deg=0, null=None):
@@ -109,9 +109,9 @@ def test_bin_sort_rejects_short_workspace_and_nulls(sss):
     L = sss.lib()
     cams = sss.camera_array([scenes.ring_camera(64, 48)])
     p = _proj_struct(sss)
-    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, None, 100, 0, 0)
+    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, None, None, None, 100, 0, 0)
     assert L.sss_bin_sort(ctypes.byref(p), cams, 1, 10, ctypes.byref(b), None, 0, None) == sss.ERR_INVALID
-    b0 = sss.Bins(0, 0x2000, 0x3000, 0x4000, None, 100, 0, 0)
+    b0 = sss.Bins(0, 0x2000, 0x3000, 0x4000, None, None, None, 100, 0, 0)
     assert L.sss_bin_sort(ctypes.byref(p), cams, 1, 10, ctypes.byref(b0), ctypes.c_void_p(0x9000), 10 ** 9,
                           None) == sss.ERR_INVALID
 
@@ -122,7 +122,7 @@ def test_render_bwd_rejects_unknown_mode_and_short_workspace(sss):
     opts = sss.render_opts()
     scene = _scene_struct(sss)
     p = _proj_struct(sss)
-    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, None, 100, 0, 0)
+    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, None, None, None, 100, 0, 0)
     g = sss.Grads(0, 0, 0, 0, 0, 0, 0, 0)
     args = lambda mode, loss, wsb: (ctypes.byref(scene), ctypes.byref(p), ctypes.byref(b), cams, 1,
                                     ctypes.byref(opts), mode, loss, ctypes.c_void_p(0x6000), ctypes.c_void_p(0x7000),

@@ -618,3 +618,65 @@ def test_huge_components_overflow_the_row_tables(sss):
         for k in PARAMS:
             ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=keep)
             assert ok, (det, k, worst)
+
+
+# ---------------------------------------------------------------------------
+# tile schedule: launch order of the raster workgroups
+# ---------------------------------------------------------------------------
+def _tile_of_pixel(cams):
+    out, off = [], 0
+    for c in cams:
+        W, H = c["width"], c["height"]
+        tx = (W + 15) // 16
+        y, x = np.mgrid[0:H, 0:W]
+        out.append((off + (y // 16) * tx + x // 16).reshape(-1))
+        off += tx * ((H + 15) // 16)
+    return np.concatenate(out), off
+
+
+def test_tile_schedule_changes_no_result(sss):
+    """Launching the tiles longest-list first (and, in the stored backward,
+    longest walk first) reorders workgroups only: images, n_contrib and the
+    deterministic gradients and loss are bit-identical to row-major launch;
+    tile_order is a permutation in non-increasing list length (up to its
+    buckets) and tile_work is each tile's largest n_contrib."""
+    s = scenes.make_scene(5000, 3, seed=21, layout="clusters", neg_frac=0.3, nu_mode="loguniform")
+    cams = [scenes.ring_camera(203, 141, angle=0.7), scenes.ring_camera(64, 80, angle=2.5),
+            scenes.ring_camera(130, 33, angle=4.1)]
+    n = s["means"].shape[0]
+    dev = to_device(s)
+    proj = sss.project(dev, cams)
+    tgt = torch.as_tensor(np.concatenate([scenes.smooth_target(c["width"], c["height"], seed=i).reshape(-1, 3)
+                                          for i, c in enumerate(cams)]), device="cuda")
+    res = {}
+    for sched in (False, True):
+        bins = sss.BinSorter(1024, keep_offsets=True, schedule=sched)(proj, cams, n)
+        img, tfin, ncon = sss.render_fwd(bins, cams)
+        out = dict(img=img.clone(), tfin=tfin.clone(), ncon=ncon.clone(), bins=bins)
+        for mode in (sss.BWD_STORED, sss.BWD_RECOMPUTE):
+            loss = torch.zeros(1, device="cuda")
+            out[mode] = (sss.render_bwd(dev, proj, bins, cams, tgt, mode=mode, loss=sss.LOSS_L1, image=img,
+                                        n_contrib=ncon, loss_out=loss, deterministic=True), loss)
+        res[sched] = out
+    torch.cuda.synchronize()
+    a, b = res[False], res[True]
+    assert a["bins"].tile_order is None and b["bins"].tile_order is not None
+    for k in ("img", "tfin", "ncon"):
+        assert np.array_equal(a[k].cpu().numpy().view(np.uint32), b[k].cpu().numpy().view(np.uint32)), k
+    for mode in (sss.BWD_STORED, sss.BWD_RECOMPUTE):
+        assert a[mode][1].item() == b[mode][1].item()
+        for k in PARAMS:
+            ga, gb = a[mode][0][k].cpu().numpy(), b[mode][0][k].cpu().numpy()
+            assert np.array_equal(ga.view(np.uint32), gb.view(np.uint32)), (mode, k)
+    tile, T = _tile_of_pixel(cams)
+    bins = b["bins"]
+    order = bins.tile_order.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(T))
+    start = bins.tile_start.cpu().numpy().astype(np.int64)
+    length = (start[1:] - start[:-1])[order].astype(np.float64)
+    suffix_max = np.maximum.accumulate(length[::-1])[::-1]
+    assert np.all(suffix_max[1:] <= 1.1 * length[:-1] + 1.0)
+    ncon = b["ncon"].cpu().numpy().astype(np.int64)
+    work = np.zeros(T, np.int64)
+    np.maximum.at(work, tile, ncon)
+    assert np.array_equal(bins.tile_work.cpu().numpy().astype(np.int64), work)
