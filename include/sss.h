@@ -194,15 +194,18 @@ int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
  *                  by the deterministic backward pass.
  *   tile_order     [n_tiles] (nullable) a permutation of the global tiles,
  *                  longest list first (coarse buckets of the list length;
- *                  order within a bucket unspecified).  sss_render_fwd and
- *                  the recompute backward launch tile tile_order[b] as
- *                  workgroup b, so the tiles with the most work start
- *                  first; NULL launches them in row-major order.  Only the
- *                  schedule changes: every tile's result is the same.
- *   tile_work      [n_tiles] (nullable) not written here: sss_render_fwd
- *                  stores each tile's largest n_contrib (the list prefix
- *                  the backward pass walks), and the stored-mode backward
- *                  orders its tiles by it.
+ *                  order within a bucket unspecified).  The raster kernels
+ *                  render a tile as 1, 2 or 4 workgroups (units of 16, 8 or
+ *                  4 pixel rows) and launch the units of tile tile_order[b]
+ *                  after those of tile_order[b - 1], so the tiles with the
+ *                  most work start first; NULL launches them in row-major
+ *                  order.  Only the schedule changes: every pixel's and
+ *                  every pair's result is the same.
+ *   tile_work      [n_tiles][4] (nullable) not written here: sss_render_fwd
+ *                  stores, per 16x4 pixel strip s (tile rows 4s..4s+3), the
+ *                  largest n_contrib of its pixels (the list prefix the
+ *                  backward pass walks), and the stored-mode backward
+ *                  launches its units in decreasing order of it.
  * A non-NULL tile_order must hold what sss_bin_sort wrote (tiles outside
  * the grid are skipped, so another permutation only reorders work and
  * anything else leaves tiles unrendered).
@@ -241,7 +244,7 @@ int sss_bin_sort(const sss_proj_t* proj, const sss_camera_t* cams, int n_views, 
  *   image     [P][3]  C + T bg
  *   t_final   [P]     final transmittance T
  *   n_contrib [P]     list position after the last added component
- *   bins->tile_work   (if not NULL) per tile, the largest n_contrib of its pixels
+ *   bins->tile_work   (if not NULL) per 16x4 strip, the largest n_contrib of its pixels
  * Tiles are launched in bins->tile_order when it is not NULL.
  * Errors: INVALID for NULL pointers / bad views. */
 int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views,
@@ -274,10 +277,10 @@ int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views
  * sss_render_bwd_workspace(n_views*n, n_tiles) (per-entry screen-space
  * gradients, 12 FP64 each, one loss value per tile and the tiles' launch
  * order; the L1 loss is summed over tiles in a fixed order, so loss_out
- * gets the same value on every run).  Tile schedule: in stored mode with
- * bins->tile_work set (by sss_render_fwd), the tiles with the longest
- * walks start first; otherwise bins->tile_order (or row-major) as in the
- * forward pass.  The schedule never changes a tile's own sums.
+ * gets the same value on every run).  Schedule: in stored mode with
+ * bins->tile_work set (by sss_render_fwd), the units with the longest walks
+ * start first; otherwise bins->tile_order (or row-major) as in the forward
+ * pass.  The schedule never changes a unit's own sums.
  * Errors: INVALID for NULL pointers, a short workspace, unknown mode/loss. */
 enum { SSS_BWD_STORED = 0, SSS_BWD_RECOMPUTE = 1, SSS_BWD_DETERMINISTIC = 4 };
 enum { SSS_LOSS_GRAD = 0, SSS_LOSS_L1 = 1 };

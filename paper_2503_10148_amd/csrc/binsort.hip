@@ -495,7 +495,7 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
   SSS_LAUNCH("tile_start", tile_start_kernel, dim3(gt), dim3(kBlock), 0, st, tkeys, m,
                      (int64_t)cb.total_tiles, bins->tile_start);
   // 6. launch order of the tiles for the raster kernels, longest list first
-  if (bins->tile_order) launch_tile_order(nullptr, bins->tile_start, cb.total_tiles, bins->tile_order, st);
+  if (bins->tile_order) launch_tile_order(nullptr, 0, bins->tile_start, cb.total_tiles, bins->tile_order, st);
   if (!hip_ok(hipGetLastError(), "bin_sort launch")) return SSS_ERR_HIP;
   return SSS_OK;
 }

@@ -108,14 +108,17 @@ struct DetArgs {
   float* part;                // [n_pairs][kG2] per-pair sums
   uint32_t* lastp1;           // [n_tiles] last visited rank + 1
   float* loss_part;           // [n_tiles] per-tile loss (both modes)
-  uint32_t* order_ws;         // [n_tiles] the backward's own tile order (both modes)
-  const uint32_t* tile_order; // launch order of the tiles (nullable: row-major)
+  uint32_t* order_ws;         // [4 n_tiles] the backward's own unit order (both modes)
+  const uint32_t* tile_order; // launch order (nullable: row-major) of tiles, or of units if unit_order
+  int32_t unit_order;
   uint32_t n_pairs;           // bound of the slots (part has n_pairs rows)
 };
-// Tiles sorted by a coarse bucket of their cost, most expensive first; cost
-// is cost[t] or, when cost is NULL, the list length from tile_start.
-void launch_tile_order(const uint32_t* cost, const uint32_t* tile_start, int64_t n_tiles, uint32_t* order,
-                       hipStream_t st);
+// Items (tiles or units) sorted by a coarse bucket of their cost, most
+// expensive first.  The cost of item t is the largest of
+// strip_cost[k*t .. k*t + k) (k = strips_per_item) or, when strip_cost is
+// NULL, the list length of tile t from tile_start.
+void launch_tile_order(const uint32_t* strip_cost, int strips_per_item, const uint32_t* tile_start, int64_t n_items,
+                       uint32_t* order, hipStream_t st);
 size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_tiles);
 size_t render_bwd_workspace(int64_t n_entries, int64_t n_tiles);
 DetArgs carve_bwd(void* ws, int64_t n_entries, int64_t n_tiles, double** g2);

@@ -2,10 +2,11 @@
 // components (Sec. 3.4 eq. SSS_color) and its closed-form backward pass
 // (SM "Backward Pass").
 //
-// One workgroup of 256 threads per 16x16 tile, one pixel per thread (wave w
-// covers tile rows 4w..4w+3).  The tile's depth-ordered list is consumed in
-// batches of 256 records staged in LDS; every thread reads each staged record
-// as a broadcast.  The 2D mean is re-based on the tile origin in FP64 while
+// Work unit: one wave of 64 threads, each thread PIX pixels, renders 4*PIX
+// consecutive rows of a 16x16 tile (4/PIX units per tile), as a workgroup
+// of its own, so the hardware schedules units rather than whole tiles.  The
+// tile's depth-ordered list is consumed in batches of 64 records staged in
+// LDS; every thread reads each staged record as a broadcast.  The 2D mean is re-based on the tile origin in FP64 while
 // staging, so pixel offsets keep full FP32 relative precision.
 //
 // The backward pass walks the list front to back, like the forward pass: with
@@ -44,8 +45,9 @@ struct __align__(16) LRec {
   uint32_t slot;             // deterministic backward: the pair's emission position
 };
 
+// Stages one record in LDS; returns its strip mask and the entry.
 __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, double ox, double oy,
-                                          LRec* dst) {
+                                          LRec* dst, uint32_t* entry) {
   const Rec r = srec[rank];
   LRec l;
   l.mx = (float)(r.mx - ox);
@@ -70,7 +72,8 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   l.entry = r.entry;
   l.slot = 0u;
   *dst = l;
-  return r.entry;
+  *entry = r.entry;
+  return m;
 }
 
 // Evaluation of one record at one pixel, shared bit-for-bit by the forward
@@ -181,12 +184,18 @@ __device__ __forceinline__ int tr_index(int lane) {
 // d = pixel - mean.
 __device__ __forceinline__ float g2_scale(int idx) { return idx < 2 ? -2.0f : (idx == 3 ? 2.0f : 1.0f); }
 
-// Pixels of one tile owned by a thread: with PIX pixels per thread the
-// workgroup has 256/PIX threads; thread t owns column t % 16 and the rows
-// t/16 + k*(256/PIX)/16, k < PIX.
+// Pixels of a unit owned by a thread: unit `sub` of a tile covers rows
+// r0 = 4*PIX*sub .. r0 + 4*PIX - 1; thread t (of 64) owns column t % 16 and
+// rows r0 + t/16 + 4k, k < PIX, so its k-th pixel lies in the tile's 16x4
+// strip PIX*sub + k.
+constexpr int kUnitThreads = 64;
+template <int PIX>
+constexpr int kUnits = 4 / PIX;   // units per tile
+
 template <int PIX>
 struct TileCtx {
   int g;       // global tile id
+  int sub;     // unit within the tile
   bool skip;   // g is outside the grid (an order entry that is not a tile)
   int view, tx, ty;
   uint32_t start, end;
@@ -199,14 +208,24 @@ struct TileCtx {
 
 template <int PIX>
 __device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint32_t* __restrict__ tile_start,
-                                                 const uint32_t* __restrict__ tile_order) {
-  constexpr int kThreads = kBlock / PIX;
-  constexpr int kRowStep = kThreads / kTile;
+                                                 const uint32_t* __restrict__ order, bool unit_order) {
   TileCtx<PIX> t;
-  // workgroup b renders tile tile_order[b]: the tiles with the most work are
-  // launched first, so they do not run alone at the end of the grid
-  const uint32_t gu = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
+  // The units with the most work are launched first, so that they do not
+  // run alone at the end of the grid: with a unit order, workgroup b renders
+  // unit order[b]; with a tile order, the units of tile order[b / units]
+  // follow each other.
+  uint32_t gu, sub;
+  if (unit_order) {
+    const uint32_t u = order[blockIdx.x];
+    gu = u / kUnits<PIX>;
+    sub = u % kUnits<PIX>;
+  } else {
+    const uint32_t b = blockIdx.x / kUnits<PIX>;
+    sub = blockIdx.x % kUnits<PIX>;
+    gu = order ? order[b] : b;
+  }
   t.g = (int)gu;
+  t.sub = (int)sub;
   t.skip = gu >= (uint32_t)cb.total_tiles;
   if (t.skip) return t;
   const int g = t.g;
@@ -219,12 +238,12 @@ __device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint3
   t.view = v;
   t.tx = tx;
   t.ty = ty;
-  const int lx = threadIdx.x & (kTile - 1), ly0 = threadIdx.x / kTile;
+  const int lx = threadIdx.x & (kTile - 1), ly0 = (int)threadIdx.x / kTile + 4 * PIX * t.sub;
   const int x = tx * kTile + lx;
   t.px = (float)lx + 0.5f;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
-    const int ly = ly0 + k * kRowStep;
+    const int ly = ly0 + 4 * k;
     const int y = ty * kTile + ly;
     t.py[k] = (float)ly + 0.5f;
     t.inside[k] = x < c.W && y < c.H;
@@ -237,9 +256,9 @@ __device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint3
   return t;
 }
 
-// The 16x4 pixel strips a wave covers: its k-th pixel group is rows
-// 4w + k*rowstep .. +3, i.e. strip w + k*rowstep/4.  Returns the strip bits
-// of all groups (wave-uniform) and each group's bit.
+// The 16x4 pixel strips a unit covers: its k-th pixel group is strip
+// PIX*sub + k.  Returns the strip bits of all groups (wave-uniform) and each
+// group's bit.
 template <int PIX>
 struct WaveStrips {
   uint32_t all;
@@ -247,48 +266,66 @@ struct WaveStrips {
 };
 
 template <int PIX>
-__device__ __forceinline__ WaveStrips<PIX> wave_strips() {
-  constexpr int kRowStep = kBlock / PIX / kTile;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__device__ __forceinline__ WaveStrips<PIX> wave_strips(int sub) {
   WaveStrips<PIX> ws;
   ws.all = 0;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
-    ws.bit[k] = 1u << (w + k * (kRowStep / 4));
+    ws.bit[k] = 1u << (PIX * sub + k);
     ws.all |= ws.bit[k];
   }
   return ws;
 }
 
-// A batch is one staged record per thread.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, 64));
+  return v;
+}
+
+// A batch is one staged record per thread.  Returns the wave's set of
+// staged records whose strip mask meets `strips` (bit j: record j), so the
+// walk visits those records only.
 template <int PIX>
-__device__ __forceinline__ void stage_batch(const TileCtx<PIX>& t, const Rec* __restrict__ srec,
-                                            const uint32_t* __restrict__ pair_rank, uint32_t base, uint32_t stop,
-                                            LRec* lds) {
+__device__ __forceinline__ uint64_t stage_batch(const TileCtx<PIX>& t, const Rec* __restrict__ srec,
+                                                const uint32_t* __restrict__ pair_rank, uint32_t base, uint32_t stop,
+                                                LRec* lds, uint32_t strips) {
   const uint32_t k = base + threadIdx.x;
-  if (k < stop) stage(srec, pair_rank[k], t.ox, t.oy, lds + threadIdx.x);
+  uint32_t m = 0, e;
+  if (k < stop) m = stage(srec, pair_rank[k], t.ox, t.oy, lds + threadIdx.x, &e);
+  return __ballot((m & strips) != 0u);
 }
 
 // The same, also recording each pair's emission position: the rank's offset
 // plus the number of the entry's listed tiles before this one (rows above,
 // then columns to the left in this row), from the same row_run as the
 // emission.
+// Every visited pair's slot is written: a record that meets none of the
+// strips gets zeros here, from the thread that staged it.
 template <int PIX>
-__device__ __forceinline__ void stage_batch_slot(const TileCtx<PIX>& t, const Rec* __restrict__ srec,
-                                                 const uint32_t* __restrict__ pair_rank, const DetArgs& det,
-                                                 uint32_t base, uint32_t stop, LRec* lds) {
+__device__ __forceinline__ uint64_t stage_batch_slot(const TileCtx<PIX>& t, const Rec* __restrict__ srec,
+                                                     const uint32_t* __restrict__ pair_rank, const DetArgs& det,
+                                                     uint32_t base, uint32_t stop, LRec* lds, uint32_t strips) {
   const uint32_t k = base + threadIdx.x;
+  uint32_t m = 0;
   if (k < stop) {
     const uint32_t rank = pair_rank[k];
-    const uint32_t e = stage(srec, rank, t.ox, t.oy, lds + threadIdx.x);
+    uint32_t e;
+    m = stage(srec, rank, t.ox, t.oy, lds + threadIdx.x, &e);
     const ushort4 rc = det.rects[e];
     const RowGeo g = make_row_geo(srec[rank].mx, srec[rank].my, det.ell[e]);
     uint32_t pos = det.rank_off[rank];
     int t0;
     for (int ty = rc.y; ty < t.ty; ++ty) pos += (uint32_t)row_run(g, ty, rc.x, rc.z, &t0);
     row_run(g, t.ty, rc.x, rc.z, &t0);
-    lds[threadIdx.x].slot = pos + (uint32_t)(t.tx - t0);
+    const uint32_t slot = pos + (uint32_t)(t.tx - t0);
+    lds[threadIdx.x].slot = slot;
+    if (!(m & strips) && slot < det.n_pairs) {
+#pragma unroll
+      for (int f = 0; f < 10; ++f) det.part[(size_t)slot * kG2 + f] = 0.0f;
+    }
   }
+  return __ballot((m & strips) != 0u);
 }
 
 // Forward traversal of the tile list; identical in render_fwd and in the
@@ -311,21 +348,21 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
     T[k] = 1.0f; c0[k] = 0.0; c1[k] = 0.0; c2[k] = 0.0;
     last[k] = 0;
   }
-  constexpr uint32_t kBatch = kBlock / PIX;
-  const WaveStrips<PIX> ws = wave_strips<PIX>();
+  constexpr uint32_t kBatch = kUnitThreads;
+  const WaveStrips<PIX> ws = wave_strips<PIX>(t.sub);
   for (uint32_t base = t.start; base < t.end; base += kBatch) {
     bool alive = false;
 #pragma unroll
     for (int k = 0; k < PIX; ++k) alive |= !done[k];
     if (__syncthreads_count(alive) == 0) break;
-    stage_batch<PIX>(t, srec, pair_rank, base, t.end, lds);
+    // records that miss every strip of this unit are never visited
+    uint64_t hits = stage_batch<PIX>(t, srec, pair_rank, base, t.end, lds, ws.all);
     __syncthreads();
-    const int cnt = (int)min(kBatch, t.end - base);
-    for (int j = 0; j < cnt && alive; ++j) {
-      // records that miss every strip of this wave are skipped on a scalar branch
-      const uint32_t sm = __builtin_amdgcn_readfirstlane(lds[j].smask);
-      if (!(sm & ws.all)) continue;
+    while (hits && alive) {
+      const int j = (int)__builtin_ctzll(hits);
+      hits &= hits - 1;
       const LRec L = lds[j];
+      const uint32_t sm = PIX > 1 ? __builtin_amdgcn_readfirstlane(L.smask) : ws.all;
       alive = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
@@ -364,7 +401,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
 }
 
 template <int PIX>
-__global__ __launch_bounds__(kBlock / PIX) void render_fwd_kernel(CamBatch cb, OptsDev op,
+__global__ __launch_bounds__(kUnitThreads) void render_fwd_kernel(CamBatch cb, OptsDev op,
                                                                   const Rec* __restrict__ srec,
                                                                   const uint32_t* __restrict__ tile_start,
                                                                   const uint32_t* __restrict__ pair_rank,
@@ -373,16 +410,12 @@ __global__ __launch_bounds__(kBlock / PIX) void render_fwd_kernel(CamBatch cb, O
                                                                   uint32_t* __restrict__ n_contrib,
                                                                   const uint32_t* __restrict__ tile_order,
                                                                   uint32_t* __restrict__ tile_work) {
-  __shared__ LRec lds[kBlock / PIX];
-  __shared__ uint32_t s_work;
-  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, tile_order);
+  __shared__ LRec lds[kUnitThreads];
+  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, tile_order, false);
   if (t.skip) return;
-  if (threadIdx.x == 0) s_work = 0;
-  __syncthreads();
   float C[PIX][3], T[PIX];
   uint32_t last[PIX];
   forward_walk<PIX>(t, op, srec, pair_rank, lds, C, T, last);
-  uint32_t work = 0;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     if (!t.inside[k]) continue;
@@ -392,28 +425,28 @@ __global__ __launch_bounds__(kBlock / PIX) void render_fwd_kernel(CamBatch cb, O
     image[3 * p + 2] = C[k][2];
     if (t_final) t_final[p] = T[k];
     if (n_contrib) n_contrib[p] = last[k];
-    work = max(work, last[k]);
   }
   if (tile_work) {
-    atomicMax(&s_work, work);
-    __syncthreads();
-    if (threadIdx.x == 0) tile_work[t.g] = s_work;
+    // per 16x4 strip, the longest prefix any of its pixels used (outside
+    // pixels have last = 0)
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) {
+      const uint32_t w = wave_max_u32(last[k]);
+      if (threadIdx.x == 0) tile_work[4 * (int64_t)t.g + PIX * t.sub + k] = w;
+    }
   }
 }
 
 template <int PIX, int kMode, int kLoss, bool kDet>
-__global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
+__global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
     CamBatch cb, OptsDev op, const Rec* __restrict__ srec, const uint32_t* __restrict__ tile_start,
     const uint32_t* __restrict__ pair_rank, const float* __restrict__ dl_or_target, const float* __restrict__ image,
     const uint32_t* __restrict__ n_contrib, float* __restrict__ image_out, float* __restrict__ loss_out,
     float inv_count, double* __restrict__ g2, DetArgs det) {
-  static_assert(!kDet || PIX == 4, "the deterministic variant runs one wave per tile");
-  constexpr int kWaves = kBlock / PIX / 64;
-  constexpr uint32_t kBatch = kBlock / PIX;
+  static_assert(!kDet || PIX == 4, "the deterministic variant runs one unit per tile");
+  constexpr uint32_t kBatch = kUnitThreads;
   __shared__ LRec lds[kBatch];
-  __shared__ uint32_t s_max;
-  __shared__ float s_loss[kWaves];
-  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, det.tile_order);
+  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, det.tile_order, det.unit_order != 0);
   if (t.skip) return;
   const int lane = threadIdx.x & 63;
 
@@ -470,29 +503,21 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
                        __fma_rn((double)g[k][1], (double)out[k][1], (double)g[k][0] * (double)out[k][0]));
   }
   if (kLoss == SSS_LOSS_L1 && loss_out) {
-    // |out - target| summed over the workgroup, one atomic per tile
+    // |out - target| summed over the unit; the units' values are added in a
+    // fixed order afterwards
     l1 = wave_sum63(l1);
-    if (lane == 63) s_loss[threadIdx.x >> 6] = l1;
+    if (lane == 63) det.loss_part[(int64_t)t.g * kUnits<PIX> + t.sub] = l1 * inv_count;
   }
 
   uint32_t mb = 0;
 #pragma unroll
   for (int k = 0; k < PIX; ++k) mb = max(mb, bound[k]);
-  if (threadIdx.x == 0) s_max = 0;
-  __syncthreads();
-  atomicMax(&s_max, mb);
-  __syncthreads();
-  const uint32_t stop = min(t.start + s_max, t.end);
-  if (kLoss == SSS_LOSS_L1 && loss_out && threadIdx.x == 0) {
-    float l = 0.0f;
-    for (int w = 0; w < kWaves; ++w) l += s_loss[w];
-    det.loss_part[t.g] = l * inv_count;
-  }
+  const uint32_t stop = min(t.start + wave_max_u32(mb), t.end);
   // pairs of this tile up to rank lastp1 - 1 are visited (lists ascend in rank)
   if (kDet && threadIdx.x == 0) det.lastp1[t.g] = stop > t.start ? pair_rank[stop - 1] + 1u : 0u;
 
   // ---- front-to-back gradient walk ----
-  const WaveStrips<PIX> ws = wave_strips<PIX>();
+  const WaveStrips<PIX> ws = wave_strips<PIX>(t.sub);
   // gA: g . (colour accumulated so far), in FP64 like the forward's sums, so
   // that gout - gA (the part of the output behind a component) keeps its
   // precision deep in a list
@@ -505,23 +530,15 @@ __global__ __launch_bounds__(kBlock / PIX) void render_bwd_kernel(
   }
   for (uint32_t base = t.start; base < stop; base += kBatch) {
     __syncthreads();
-    if (kDet) stage_batch_slot<PIX>(t, srec, pair_rank, det, base, stop, lds);
-    else stage_batch<PIX>(t, srec, pair_rank, base, stop, lds);
+    uint64_t hits = kDet ? stage_batch_slot<PIX>(t, srec, pair_rank, det, base, stop, lds, ws.all)
+                         : stage_batch<PIX>(t, srec, pair_rank, base, stop, lds, ws.all);
     __syncthreads();
-    const int cnt = (int)min(kBatch, stop - base);
-    for (int j = 0; j < cnt; ++j) {
+    while (hits) {
+      const int j = (int)__builtin_ctzll(hits);
+      hits &= hits - 1;
       const uint32_t pos = base - t.start + (uint32_t)j;
-      const uint32_t sm = __builtin_amdgcn_readfirstlane(lds[j].smask);
-      if (!(sm & ws.all)) {
-        // no pixel of this wave can be hit; the deterministic mode still
-        // writes the pair's slot
-        if (kDet && lane < 16 && tr_index(lane) >= 0) {
-          const uint32_t slot = lds[j].slot;
-          if (slot < det.n_pairs) det.part[(size_t)slot * kG2 + tr_index(lane)] = 0.0f;
-        }
-        continue;
-      }
       const LRec L = lds[j];
+      const uint32_t sm = PIX > 1 ? __builtin_amdgcn_readfirstlane(L.smask) : ws.all;
       float v[10];
 #pragma unroll
       for (int f = 0; f < 10; ++f) v[f] = 0.0f;
@@ -775,16 +792,24 @@ __device__ __forceinline__ int order_bucket(uint32_t c) {
   return kOrderBuckets - 1 - min(b, kOrderBuckets - 1);
 }
 
-__global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_t* __restrict__ cost,
+// Cost of item t: the largest of strip_cost[spi*t .. spi*t + spi) when
+// strip_cost is given, else the list length of tile t.
+__device__ __forceinline__ uint32_t item_cost(const uint32_t* __restrict__ strip_cost, int spi,
+                                              const uint32_t* __restrict__ tile_start, int64_t t) {
+  if (!strip_cost) return tile_start[t + 1] - tile_start[t];
+  uint32_t c = 0;
+  for (int j = 0; j < spi; ++j) c = max(c, strip_cost[spi * t + j]);
+  return c;
+}
+
+__global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_t* __restrict__ strip_cost, int spi,
                                                                    const uint32_t* __restrict__ tile_start,
-                                                                   int64_t n_tiles, uint32_t* __restrict__ order) {
+                                                                   int64_t n_items, uint32_t* __restrict__ order) {
   __shared__ uint32_t hist[kOrderBuckets];
   for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) hist[i] = 0;
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < n_tiles; t += kOrderThreads) {
-    const uint32_t c = cost ? cost[t] : tile_start[t + 1] - tile_start[t];
-    atomicAdd(&hist[order_bucket(c)], 1u);
-  }
+  for (int64_t t = threadIdx.x; t < n_items; t += kOrderThreads)
+    atomicAdd(&hist[order_bucket(item_cost(strip_cost, spi, tile_start, t))], 1u);
   __syncthreads();
   if (threadIdx.x < 64) {
     // exclusive scan of the 256 counts by one wave, 4 per lane
@@ -803,10 +828,8 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_
     }
   }
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < n_tiles; t += kOrderThreads) {
-    const uint32_t c = cost ? cost[t] : tile_start[t + 1] - tile_start[t];
-    order[atomicAdd(&hist[order_bucket(c)], 1u)] = (uint32_t)t;
-  }
+  for (int64_t t = threadIdx.x; t < n_items; t += kOrderThreads)
+    order[atomicAdd(&hist[order_bucket(item_cost(strip_cost, spi, tile_start, t))], 1u)] = (uint32_t)t;
 }
 
 __global__ __launch_bounds__(kBlock) void zero_kernel(float4* __restrict__ p, int64_t n4) {
@@ -816,11 +839,11 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(float4* __restrict__ p, in
 
 }  // namespace
 
-void launch_tile_order(const uint32_t* cost, const uint32_t* tile_start, int64_t n_tiles, uint32_t* order,
-                       hipStream_t st) {
-  if (n_tiles <= 0) return;
-  SSS_LAUNCH("tile_order", tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, st, cost, tile_start, n_tiles,
-             order);
+void launch_tile_order(const uint32_t* strip_cost, int strips_per_item, const uint32_t* tile_start, int64_t n_items,
+                       uint32_t* order, hipStream_t st) {
+  if (n_items <= 0) return;
+  SSS_LAUNCH("tile_order", tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, st, strip_cost, strips_per_item,
+             tile_start, n_items, order);
 }
 
 void launch_zero(float* p, int64_t count, hipStream_t st) {
@@ -834,14 +857,14 @@ void launch_zero(float* p, int64_t count, hipStream_t st) {
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Deterministic-mode workspace: screen-space gradients [E][kG2], per-pair
-// sums [M][kG2], per-tile visit bounds [T], loss values [T] and tile order
-// [T], each 256-byte aligned.
+// sums [M][kG2], per-tile visit bounds [T], loss values [4T] and unit order
+// [4T] (up to 4 units per tile), each 256-byte aligned.
 static size_t det_parts(int64_t n_entries, int64_t n_pairs, int64_t n_tiles, size_t part[5]) {
   part[0] = sizeof(double) * kG2 * (size_t)n_entries;
   part[1] = sizeof(float) * kG2 * (size_t)(n_pairs > 0 ? n_pairs : 1);
   part[2] = sizeof(uint32_t) * (size_t)n_tiles;
-  part[3] = sizeof(float) * (size_t)n_tiles;
-  part[4] = sizeof(uint32_t) * (size_t)n_tiles;
+  part[3] = sizeof(float) * 4 * (size_t)n_tiles;
+  part[4] = sizeof(uint32_t) * 4 * (size_t)n_tiles;
   size_t total = 0;
   for (int k = 0; k < 5; ++k) total += align256(part[k]);
   return total;
@@ -853,10 +876,10 @@ size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_ti
 }
 
 // Workspace of the atomic mode: screen-space gradients [E][kG2] FP64, the
-// per-tile loss values [T] and the tile order [T].
+// per-unit loss values [4T] and the unit order [4T].
 size_t render_bwd_workspace(int64_t n_entries, int64_t n_tiles) {
-  return align256(sizeof(double) * kG2 * (size_t)n_entries) + align256(sizeof(float) * (size_t)n_tiles) +
-         sizeof(uint32_t) * (size_t)n_tiles;
+  return align256(sizeof(double) * kG2 * (size_t)n_entries) + align256(sizeof(float) * 4 * (size_t)n_tiles) +
+         sizeof(uint32_t) * 4 * (size_t)n_tiles;
 }
 
 DetArgs carve_bwd(void* ws, int64_t n_entries, int64_t n_tiles, double** g2) {
@@ -865,7 +888,7 @@ DetArgs carve_bwd(void* ws, int64_t n_entries, int64_t n_tiles, double** g2) {
   *g2 = (double*)p;
   p += align256(sizeof(double) * kG2 * (size_t)n_entries);
   d.loss_part = (float*)p;
-  p += align256(sizeof(float) * (size_t)n_tiles);
+  p += align256(sizeof(float) * 4 * (size_t)n_tiles);
   d.order_ws = (uint32_t*)p;
   return d;
 }
@@ -897,10 +920,10 @@ int env_pix(const char* name, int dflt) {
 void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, float* image, float* t_final,
                        uint32_t* n_contrib, hipStream_t st) {
   static const int pix = env_pix("SSS_PIX_FWD", 1);
-  const dim3 grid((unsigned)cb.total_tiles);
+  const dim3 grid((unsigned)(cb.total_tiles * (4 / pix)));
   const Rec* sr = (const Rec*)b.sorted_records;
 #define SSS_FWD(P)                                                                                          \
-  SSS_LAUNCH("render_fwd", render_fwd_kernel<P>, grid, dim3(kBlock / P), 0, st, cb, op, sr,                \
+  SSS_LAUNCH("render_fwd", render_fwd_kernel<P>, grid, dim3(kUnitThreads), 0, st, cb, op, sr,              \
              (const uint32_t*)b.tile_start, (const uint32_t*)b.pair_rank, image, t_final, n_contrib,           \
              (const uint32_t*)b.tile_order, b.tile_work)
   if (pix == 1) SSS_FWD(1);
@@ -913,58 +936,59 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                        const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
                        float* loss_out, double* g2, int64_t total_pixels, bool det_mode, const DetArgs& dargs,
                        int64_t n, hipStream_t st) {
-  // tile schedule: by the forward's walk lengths when the backward walks
-  // the stored prefixes, else the binning's list-length order
+  // the deterministic variant runs one unit (one wave of 4 pixels per
+  // thread) per tile, so each pair's sums come from one wave
+  static const int env_bwd = env_pix("SSS_PIX_BWD", 2);
+  const int pix = det_mode ? 4 : env_bwd;
+  const int64_t units = cb.total_tiles * (4 / pix);
+  // schedule: units ordered by the forward's per-strip walk lengths when
+  // the backward walks the stored prefixes, else the binning's tile order
   DetArgs da = dargs;
   da.tile_order = b.tile_order;
+  da.unit_order = 0;
   if (mode == SSS_BWD_STORED && b.tile_work && da.order_ws) {
-    launch_tile_order(b.tile_work, nullptr, cb.total_tiles, da.order_ws, st);
+    launch_tile_order(b.tile_work, pix, nullptr, units, da.order_ws, st);
     da.tile_order = da.order_ws;
+    da.unit_order = 1;
   }
-  const DetArgs* det = det_mode ? &da : nullptr;
-  const DetArgs* pdargs = &da;
-  static const int pix = env_pix("SSS_PIX_BWD", 2);
   const float inv_count = 1.0f / (3.0f * (float)total_pixels);
-  const dim3 grid((unsigned)cb.total_tiles);
+  const dim3 grid((unsigned)units);
   const Rec* sr = (const Rec*)b.sorted_records;
   const uint32_t* ts = b.tile_start;
   const uint32_t* pr = b.pair_rank;
-  if (det) {
-    // one wave per tile; then the fixed-order sums
-#define SSS_BWD_DET(M, L)                                                                                       \
-  SSS_LAUNCH("render_bwd", (render_bwd_kernel<4, M, L, true>), grid, dim3(kBlock / 4), 0, st, cb, op, sr, ts, pr, \
-             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, *det)
+  if (det_mode) {
+#define SSS_BWD_DET(M, L)                                                                                         \
+  SSS_LAUNCH("render_bwd", (render_bwd_kernel<4, M, L, true>), grid, dim3(kUnitThreads), 0, st, cb, op, sr, ts, pr, \
+             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da)
     if (mode == SSS_BWD_STORED && loss == SSS_LOSS_GRAD) { SSS_BWD_DET(SSS_BWD_STORED, SSS_LOSS_GRAD); }
     else if (mode == SSS_BWD_STORED) { SSS_BWD_DET(SSS_BWD_STORED, SSS_LOSS_L1); }
     else if (loss == SSS_LOSS_GRAD) { SSS_BWD_DET(SSS_BWD_RECOMPUTE, SSS_LOSS_GRAD); }
     else { SSS_BWD_DET(SSS_BWD_RECOMPUTE, SSS_LOSS_L1); }
 #undef SSS_BWD_DET
+    // then the fixed-order sums
     if (b.n_visible > 0) {
       const unsigned gr = (unsigned)((b.n_visible + kBlock - 1) / kBlock);
       SSS_LAUNCH("det_reduce", det_reduce_kernel, dim3(gr), dim3(kBlock), 0, st, cb, n, b.n_visible,
-                 (uint32_t)b.n_pairs, sr, *det, g2);
+                 (uint32_t)b.n_pairs, sr, da, g2);
     }
-    if (loss == SSS_LOSS_L1 && loss_out)
-      SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)det->loss_part,
-                 (int64_t)cb.total_tiles, loss_out);
-    return;
-  }
-#define SSS_BWD(P, M, L)                                                                                    \
-  SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L, false>), grid, dim3(kBlock / P), 0, st, cb, op, sr, ts, pr, \
-             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, *pdargs)
-#define SSS_BWD_P(M, L)              \
-  if (pix == 1) SSS_BWD(1, M, L);    \
+  } else {
+#define SSS_BWD(P, M, L)                                                                                      \
+  SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L, false>), grid, dim3(kUnitThreads), 0, st, cb, op, sr, ts, pr, \
+             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da)
+#define SSS_BWD_P(M, L)                \
+  if (pix == 1) SSS_BWD(1, M, L);      \
   else if (pix == 2) SSS_BWD(2, M, L); \
   else SSS_BWD(4, M, L)
-  if (mode == SSS_BWD_STORED && loss == SSS_LOSS_GRAD) { SSS_BWD_P(SSS_BWD_STORED, SSS_LOSS_GRAD); }
-  else if (mode == SSS_BWD_STORED) { SSS_BWD_P(SSS_BWD_STORED, SSS_LOSS_L1); }
-  else if (loss == SSS_LOSS_GRAD) { SSS_BWD_P(SSS_BWD_RECOMPUTE, SSS_LOSS_GRAD); }
-  else { SSS_BWD_P(SSS_BWD_RECOMPUTE, SSS_LOSS_L1); }
+    if (mode == SSS_BWD_STORED && loss == SSS_LOSS_GRAD) { SSS_BWD_P(SSS_BWD_STORED, SSS_LOSS_GRAD); }
+    else if (mode == SSS_BWD_STORED) { SSS_BWD_P(SSS_BWD_STORED, SSS_LOSS_L1); }
+    else if (loss == SSS_LOSS_GRAD) { SSS_BWD_P(SSS_BWD_RECOMPUTE, SSS_LOSS_GRAD); }
+    else { SSS_BWD_P(SSS_BWD_RECOMPUTE, SSS_LOSS_L1); }
 #undef SSS_BWD_P
 #undef SSS_BWD
+  }
   if (loss == SSS_LOSS_L1 && loss_out)
-    SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)da.loss_part,
-               (int64_t)cb.total_tiles, loss_out);
+    SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)da.loss_part, units,
+               loss_out);
 }
 
 }  // namespace sss

@@ -276,7 +276,7 @@ class Binned:
     n_pairs: int = 0
     rank_offset: torch.Tensor | None = None   # int32 [E], kept for the deterministic backward
     tile_order: torch.Tensor | None = None    # int32 [tiles], launch order (longest list first)
-    tile_work: torch.Tensor | None = None     # int32 [tiles], per tile the largest n_contrib (from render_fwd)
+    tile_work: torch.Tensor | None = None     # int32 [tiles, 4], per 16x4 strip the largest n_contrib (render_fwd)
 
     def struct(self):
         return Bins(self.order.data_ptr(), self.sorted_records.data_ptr(), self.tile_start.data_ptr(),
@@ -308,7 +308,7 @@ class BinSorter:
                          torch.empty(T + 1, dtype=torch.int32, device=dev), None)
             if self.schedule:
                 out.tile_order = torch.empty(T, dtype=torch.int32, device=dev)
-                out.tile_work = torch.empty(T, dtype=torch.int32, device=dev)
+                out.tile_work = torch.empty((T, 4), dtype=torch.int32, device=dev)
         if self.keep_offsets and (out.rank_offset is None or out.rank_offset.numel() < E):
             out.rank_offset = torch.empty(E, dtype=torch.int32, device=dev)
         camarr = camera_array(cams)

@@ -623,13 +623,15 @@ def test_huge_components_overflow_the_row_tables(sss):
 # ---------------------------------------------------------------------------
 # tile schedule: launch order of the raster workgroups
 # ---------------------------------------------------------------------------
-def _tile_of_pixel(cams):
+def _strip_of_pixel(cams):
+    """Global index 4 * tile + strip (16x4 pixel strip of the tile) of every
+    pixel of the concatenated views, and the total tile count."""
     out, off = [], 0
     for c in cams:
         W, H = c["width"], c["height"]
         tx = (W + 15) // 16
         y, x = np.mgrid[0:H, 0:W]
-        out.append((off + (y // 16) * tx + x // 16).reshape(-1))
+        out.append((4 * (off + (y // 16) * tx + x // 16) + (y % 16) // 4).reshape(-1))
         off += tx * ((H + 15) // 16)
     return np.concatenate(out), off
 
@@ -639,7 +641,7 @@ def test_tile_schedule_changes_no_result(sss):
     longest walk first) reorders workgroups only: images, n_contrib and the
     deterministic gradients and loss are bit-identical to row-major launch;
     tile_order is a permutation in non-increasing list length (up to its
-    buckets) and tile_work is each tile's largest n_contrib."""
+    buckets) and tile_work is each 16x4 strip's largest n_contrib."""
     s = scenes.make_scene(5000, 3, seed=21, layout="clusters", neg_frac=0.3, nu_mode="loguniform")
     cams = [scenes.ring_camera(203, 141, angle=0.7), scenes.ring_camera(64, 80, angle=2.5),
             scenes.ring_camera(130, 33, angle=4.1)]
@@ -668,7 +670,7 @@ def test_tile_schedule_changes_no_result(sss):
         for k in PARAMS:
             ga, gb = a[mode][0][k].cpu().numpy(), b[mode][0][k].cpu().numpy()
             assert np.array_equal(ga.view(np.uint32), gb.view(np.uint32)), (mode, k)
-    tile, T = _tile_of_pixel(cams)
+    strip, T = _strip_of_pixel(cams)
     bins = b["bins"]
     order = bins.tile_order.cpu().numpy().astype(np.int64)
     assert np.array_equal(np.sort(order), np.arange(T))
@@ -677,6 +679,6 @@ def test_tile_schedule_changes_no_result(sss):
     suffix_max = np.maximum.accumulate(length[::-1])[::-1]
     assert np.all(suffix_max[1:] <= 1.1 * length[:-1] + 1.0)
     ncon = b["ncon"].cpu().numpy().astype(np.int64)
-    work = np.zeros(T, np.int64)
-    np.maximum.at(work, tile, ncon)
-    assert np.array_equal(bins.tile_work.cpu().numpy().astype(np.int64), work)
+    work = np.zeros(4 * T, np.int64)
+    np.maximum.at(work, strip, ncon)
+    assert np.array_equal(bins.tile_work.cpu().numpy().astype(np.int64).reshape(-1), work)
