@@ -24,6 +24,9 @@
  *    a message for the calling thread.
  *  - All arithmetic of the raster kernels is FP32; the per-component
  *    projection (forward and backward) computes in FP64 and stores FP32.
+ *  - Workspaces (`ws`) are device buffers of at least the size the matching
+ *    *_workspace() call returns, 256-byte aligned (hipMalloc and torch
+ *    allocations are); a misaligned ws is rejected with SSS_ERR_INVALID.
  *  - Cameras of one call may have different sizes.  Images of all views are
  *    concatenated: view v occupies pixels [P_v, P_v + W_v H_v) with
  *    P_v = sum_{u<v} W_u H_u, row-major, 3 channels (HWC) where noted.

@@ -165,6 +165,13 @@ int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
   return hip_ok(hipGetLastError(), "sss_project launch") ? SSS_OK : SSS_ERR_HIP;
 }
 
+// Workspaces are carved into 256-byte aligned parts, read with 16-byte loads.
+static bool ws_aligned(const void* ws, const char* fn) {
+  if (((uintptr_t)ws & 255) == 0) return true;
+  set_error("%s: workspace must be 256-byte aligned", fn);
+  return false;
+}
+
 int sss_bin_sort(const sss_proj_t* proj, const sss_camera_t* cams, int n_views, int64_t n, sss_bins_t* bins,
                  void* ws, size_t ws_bytes, void* stream) {
   CamBatch cb;
@@ -176,6 +183,7 @@ int sss_bin_sort(const sss_proj_t* proj, const sss_camera_t* cams, int n_views, 
     set_error("sss_bin_sort: null pointer, n <= 0 or negative pair capacity");
     return SSS_ERR_INVALID;
   }
+  if (!ws_aligned(ws, "sss_bin_sort")) return SSS_ERR_INVALID;
   return run_bin_sort(cb, *proj, n, bins, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -234,6 +242,7 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
     set_error("sss_render_bwd: workspace of %zu bytes, %zu needed", ws_bytes, need);
     return SSS_ERR_INVALID;
   }
+  if (!ws_aligned(ws, "sss_render_bwd")) return SSS_ERR_INVALID;
   hipStream_t st = (hipStream_t)stream;
   const OptsDev op = make_opts(opts);
   double* g2 = (double*)ws;
@@ -305,6 +314,7 @@ int sss_loss(const float* image, const float* target, const sss_camera_t* cams, 
     set_error("sss_loss: workspace of %zu bytes, %zu needed", ws_bytes, loss_workspace(P));
     return SSS_ERR_INVALID;
   }
+  if (!ws_aligned(ws, "sss_loss")) return SSS_ERR_INVALID;
   launch_loss(cb, image, target, lambda_dssim, dl_dimage, loss_out, (float*)ws, P, (hipStream_t)stream);
   return hip_ok(hipGetLastError(), "sss_loss launch") ? SSS_OK : SSS_ERR_HIP;
 }
@@ -334,6 +344,7 @@ int sss_relocate(const sss_scene_t* scene, const sss_state_t* state, int n_state
     set_error("sss_relocate: options, workspace or state list invalid (max_fraction in [0,1], <= 8 states)");
     return SSS_ERR_INVALID;
   }
+  if (!ws_aligned(ws, "sss_relocate")) return SSS_ERR_INVALID;
   float* ptrs[8];
   int32_t widths[8];
   for (int k = 0; k < n_state; ++k) {

@@ -354,15 +354,37 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
 // ---------------------------------------------------------------------------
 // 5. tile ranges
 // ---------------------------------------------------------------------------
+// Tile ranges from the sorted tile keys: position i starts every tile in
+// (key[i-1], key[i]] (key[-1] = -1, key[m] = n_tiles).  Each thread takes four
+// consecutive positions with one 16-byte load (keys is 16-byte aligned).
+__device__ __forceinline__ void mark_starts(int64_t prev, int64_t cur, int64_t n_tiles, uint32_t i,
+                                            uint32_t* __restrict__ start) {
+  if (prev > n_tiles) prev = n_tiles;
+  if (cur > n_tiles) cur = n_tiles;
+  for (int64_t t = prev + 1; t <= cur; ++t) start[t] = i;
+}
+
 __global__ __launch_bounds__(kBlock) void tile_start_kernel(const uint32_t* __restrict__ tkeys, int64_t m,
                                                             int64_t n_tiles, uint32_t* __restrict__ start) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i > m) return;
-  int64_t prev = i == 0 ? -1 : (int64_t)tkeys[i - 1];
-  if (prev > n_tiles) prev = n_tiles;
-  int64_t cur = i == m ? n_tiles : (int64_t)tkeys[i];
-  if (cur > n_tiles) cur = n_tiles;
-  for (int64_t t = prev + 1; t <= cur; ++t) start[t] = (uint32_t)i;
+  const int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+  if (i0 > m) return;
+  int64_t prev = i0 == 0 ? -1 : (int64_t)tkeys[i0 - 1];
+  if (i0 + 4 <= m) {
+    const uint4 k = *(const uint4*)(tkeys + i0);
+    const uint32_t kk[4] = {k.x, k.y, k.z, k.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if ((int64_t)kk[j] != prev) mark_starts(prev, kk[j], n_tiles, (uint32_t)(i0 + j), start);
+      prev = kk[j];
+    }
+  } else {
+    // the last positions, up to and including m
+    for (int64_t i = i0; i <= m; ++i) {
+      const int64_t cur = i == m ? n_tiles : (int64_t)tkeys[i];
+      if (cur != prev) mark_starts(prev, cur, n_tiles, (uint32_t)i, start);
+      prev = cur;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -491,7 +513,7 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
   // 4. stable sort of the pairs by tile
   const uint32_t* tkeys = radix_sort(w.ka, w.va, w.kb, w.vb, m, bits_for((int64_t)cb.total_tiles + 1), bins->pair_rank, w, st);
   // 5. tile ranges
-  const unsigned gt = (unsigned)((m + 1 + kBlock - 1) / kBlock);
+  const unsigned gt = (unsigned)(((m + 4) / 4 + kBlock - 1) / kBlock);
   SSS_LAUNCH("tile_start", tile_start_kernel, dim3(gt), dim3(kBlock), 0, st, tkeys, m,
                      (int64_t)cb.total_tiles, bins->tile_start);
   // 6. launch order of the tiles for the raster kernels, longest list first

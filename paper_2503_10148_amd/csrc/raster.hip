@@ -767,14 +767,23 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
 // Fixed-order sum of the per-tile loss values (one workgroup): one add to
 // loss_out instead of one atomic per tile on a single address, and the same
 // value on every run.
-__global__ __launch_bounds__(kBlock) void loss_reduce_kernel(const float* __restrict__ part, int64_t n,
-                                                          float* __restrict__ loss_out) {
-  __shared__ float red[kBlock];
+// Sum of the per-unit loss values in a fixed order (each thread a fixed
+// strided subset, then a fixed tree), added to *loss_out.
+constexpr int kLossThreads = 1024;
+__global__ __launch_bounds__(kLossThreads) void loss_reduce_kernel(const float* __restrict__ part, int64_t n,
+                                                                 float* __restrict__ loss_out) {
+  __shared__ float red[kLossThreads];
   float s = 0.0f;
-  for (int64_t i = threadIdx.x; i < n; i += kBlock) s += part[i];
+  const int64_t n4 = n / 4;
+  const float4* __restrict__ p4 = (const float4*)part;
+  for (int64_t i = threadIdx.x; i < n4; i += kLossThreads) {
+    const float4 v = p4[i];
+    s += (v.x + v.y) + (v.z + v.w);
+  }
+  for (int64_t i = 4 * n4 + threadIdx.x; i < n; i += kLossThreads) s += part[i];
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int h = kBlock / 2; h > 0; h >>= 1) {
+  for (int h = kLossThreads / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
@@ -987,7 +996,7 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
 #undef SSS_BWD
   }
   if (loss == SSS_LOSS_L1 && loss_out)
-    SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const float*)da.loss_part, units,
+    SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kLossThreads), 0, st, (const float*)da.loss_part, units,
                loss_out);
 }
 

@@ -178,3 +178,22 @@ def test_records_layout_matches_decoder():
     from tests._util import REC_DTYPE
     assert REC_DTYPE.itemsize == 64
     assert REC_DTYPE.names[-2:] == ("entry", "ey")
+
+
+def test_misaligned_workspaces_are_rejected(sss):
+    """Workspaces are carved into 256-byte aligned parts: a misaligned ws is
+    an argument error, found before anything is launched."""
+    L = sss.lib()
+    cams = sss.camera_array([scenes.ring_camera(64, 48)])
+    p = _proj_struct(sss)
+    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, None, None, None, 100, 0, 0)
+    assert L.sss_bin_sort(ctypes.byref(p), cams, 1, 10, ctypes.byref(b), ctypes.c_void_p(0x9010), 10 ** 9,
+                          None) == sss.ERR_INVALID
+    assert b"aligned" in L.sss_last_error()
+    opts = sss.render_opts()
+    scene = _scene_struct(sss)
+    g = sss.Grads(0, 0, 0, 0, 0, 0, 0, 0)
+    assert L.sss_render_bwd(ctypes.byref(scene), ctypes.byref(p), ctypes.byref(b), cams, 1, ctypes.byref(opts), 0, 0,
+                            ctypes.c_void_p(0x6000), ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000), None, None,
+                            ctypes.byref(g), ctypes.c_void_p(0x9080), 10 ** 9, None) == sss.ERR_INVALID
+    assert b"aligned" in L.sss_last_error()
