@@ -89,30 +89,26 @@ __device__ __forceinline__ void evaluate(float px, float py, const LRec& L, floa
   E.ax = __fmaf_rn(L.qb, E.dy, L.qa * E.dx);
   E.ay = __fmaf_rn(L.qb, E.dx, L.qc * E.dy);
   E.h = __fmaf_rn(E.dx, E.ax, E.dy * E.ay);
-  E.hit = false;
-  E.clamped = false;
-  if (!(E.h <= L.hs)) return;
+  // Branch-free: once a record passes the strip test nearly every wave has
+  // a lane inside the ellipse, so the whole chain runs anyway; selects keep
+  // the exec mask untouched.
   // T2D = (1 + h/nu)^(-(nu+2)/2) = 2^(nb log2(1 + y)), y = h/nu.  log2(1 + y) is
-  // corrected by the rounding error of u = 1 + y while u < 2.
-  if (L.inv_nu != 0.0f) {
-    E.y = E.h * L.inv_nu;
-    E.u = 1.0f + E.y;
-    const float z = E.u - 1.0f;
-    const float corr = E.u < 2.0f ? (E.y - z) : 0.0f;
-    E.l2 = __fmaf_rn(corr, kLog2e, __builtin_amdgcn_logf(E.u));
-  } else {
-    // Gaussian family: T2D = exp(-h/2) = 2^(nb h), nb = -log2(e)/2
-    E.y = 0.0f;
-    E.u = 1.0f;
-    E.l2 = E.h;
-  }
+  // corrected by the rounding error of u = 1 + y while u < 2.  Gaussian
+  // family (inv_nu = 0): T2D = exp(-h/2) = 2^(nb h), nb = -log2(e)/2.
+  const bool student = L.inv_nu != 0.0f;
+  const float y = E.h * L.inv_nu;
+  const float u = 1.0f + y;
+  const float z = u - 1.0f;
+  const float corr = u < 2.0f ? (y - z) : 0.0f;
+  const float l2 = __fmaf_rn(corr, kLog2e, __builtin_amdgcn_logf(u));
+  E.y = student ? y : 0.0f;
+  E.u = student ? u : 1.0f;
+  E.l2 = student ? l2 : E.h;
   E.t2 = __builtin_amdgcn_exp2f(L.nb * E.l2);
-  float a = L.o * E.t2;
-  if (fabsf(a) < amin) return;
+  const float a = L.o * E.t2;
+  E.hit = E.h <= L.hs && !(fabsf(a) < amin);
   E.clamped = fabsf(a) > amax;
-  a = fminf(fmaxf(a, -amax), amax);
-  E.alpha = a;
-  E.hit = true;
+  E.alpha = __builtin_amdgcn_fmed3f(a, -amax, amax);
 }
 
 template <int kCtrl, int kRowMask>
@@ -509,10 +505,15 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
     if (lane == 63) det.loss_part[(int64_t)t.g * kUnits<PIX> + t.sub] = l1 * inv_count;
   }
 
-  uint32_t mb = 0;
+  // per pixel group, the walk bound of its longest pixel (wave-uniform): a
+  // group is skipped on a scalar branch once the walk passes it
+  uint32_t gmax[PIX], mb = 0;
 #pragma unroll
-  for (int k = 0; k < PIX; ++k) mb = max(mb, bound[k]);
-  const uint32_t stop = min(t.start + wave_max_u32(mb), t.end);
+  for (int k = 0; k < PIX; ++k) {
+    gmax[k] = __builtin_amdgcn_readfirstlane(wave_max_u32(bound[k]));
+    mb = max(mb, gmax[k]);
+  }
+  const uint32_t stop = min(t.start + mb, t.end);
   // pairs of this tile up to rank lastp1 - 1 are visited (lists ascend in rank)
   if (kDet && threadIdx.x == 0) det.lastp1[t.g] = stop > t.start ? pair_rank[stop - 1] + 1u : 0u;
 
@@ -545,23 +546,27 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
       bool hit = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
-        if (pos >= bound[k] || !(sm & ws.bit[k])) continue;
+        if (!(sm & ws.bit[k]) || pos >= gmax[k]) continue;
+        // Predicated rather than branched (see evaluate): lanes past their
+        // walk bound or outside the ellipse add zeros and keep T.
         Eval E;
         evaluate(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
-        if (!E.hit) continue;
+        const bool hk = pos < bound[k] && E.hit;
+        if (!__any(hk)) continue;
         hit = true;
         const float a = E.alpha;
         const float Tk = T[k];
-        const float w = a * Tk;
+        const float w = hk ? a * Tk : 0.0f;
         const float gc = __fmaf_rn(g[k][2], L.cb, __fmaf_rn(g[k][1], L.cg, g[k][0] * L.cr));
         gA[k] = __fma_rn((double)w, (double)gc, gA[k]);
         const float gR = (float)(gout[k] - gA[k]);
-        const float da = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), Tk * gc);
+        // a clamped alpha passes no gradient to T2D
+        const float da0 = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), Tk * gc);
+        const float da = hk && !E.clamped ? da0 : 0.0f;
         v[5] = __fmaf_rn(g[k][0], w, v[5]);
         v[6] = __fmaf_rn(g[k][1], w, v[6]);
         v[7] = __fmaf_rn(g[k][2], w, v[7]);
-        T[k] = Tk * (1.0f - a);
-        if (E.clamped) continue;
+        T[k] = hk ? Tk * (1.0f - a) : Tk;
         v[8] = __fmaf_rn(da, E.t2, v[8]);
         const float dt2 = da * L.o;
         const float ru = __builtin_amdgcn_rcpf(E.u);
@@ -574,19 +579,15 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
         v[2] = __fmaf_rn(tq, E.dx, v[2]);
         v[3] = __fmaf_rn(tq, E.dy, v[3]);
         v[4] = __fmaf_rn(dh * E.dy, E.dy, v[4]);
-        // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]
+        // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]; the first
+        // two terms by their series below y = 0.1 (they cancel)
         const float y = E.y;
-        float q;
-        if (y < 0.1f) {
-          float s = __fmaf_rn(y, 6.0f / 7.0f, -5.0f / 6.0f);
-          s = __fmaf_rn(y, s, 4.0f / 5.0f);
-          s = __fmaf_rn(y, s, -3.0f / 4.0f);
-          s = __fmaf_rn(y, s, 2.0f / 3.0f);
-          s = __fmaf_rn(y, s, -0.5f);
-          q = y * y * s;
-        } else {
-          q = __fmaf_rn(y, ru, -E.l2 * kLn2);
-        }
+        float s = __fmaf_rn(y, 6.0f / 7.0f, -5.0f / 6.0f);
+        s = __fmaf_rn(y, s, 4.0f / 5.0f);
+        s = __fmaf_rn(y, s, -3.0f / 4.0f);
+        s = __fmaf_rn(y, s, 2.0f / 3.0f);
+        s = __fmaf_rn(y, s, -0.5f);
+        const float q = y < 0.1f ? y * y * s : __fmaf_rn(y, ru, -E.l2 * kLn2);
         const float dtn = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
         v[9] = __fmaf_rn(dt2, dtn, v[9]);
       }
