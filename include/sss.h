@@ -67,7 +67,9 @@ enum {
  *   sh      [n][(d+1)^2][3]  real SH coefficients, degree d in 0..3, basis
  *                    ordered k = l*l + l + m with the Condon-Shortley phase;
  *                    colour = max(0, sum_k Y_k(dir) sh[k] + 1/2) with dir the
- *                    unit vector from the camera centre to the mean. */
+ *                    unit vector from the camera centre to the mean.
+ * quats and sh must be 16-byte aligned (any device allocation is);
+ * otherwise calls taking a scene return SSS_ERR_INVALID. */
 typedef struct {
   int64_t n;
   int32_t sh_degree;
@@ -311,7 +313,7 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
  * arrays (the paper's non-mean parameters), each clamped to [lo, hi]; one
  * launch for all arrays (an array of count 0 is skipped).
  * Arrays: device FP32; means, momentum, grad_means [n][3]; opacity [n];
- * scales [n][3] and quats [n][4] (read only for burn_in).
+ * scales [n][3] and quats [n][4] (read only for burn_in; quats 16-byte aligned).
  * Errors: INVALID for n <= 0, NULL arrays, lr < 0, adam->t < 1. */
 typedef struct {
   float lr, friction, k, t;

@@ -82,6 +82,11 @@ static int check_scene(const sss_scene_t* s, const char* fn) {
               (long long)(0xFFFFFFFFll / SSS_MAX_VIEWS));
     return SSS_ERR_INVALID;
   }
+  // quaternions and SH rows are read with 16-byte loads
+  if (((uintptr_t)s->quats | (uintptr_t)s->sh) & 15) {
+    set_error("%s: scene quats and sh must be 16-byte aligned", fn);
+    return SSS_ERR_INVALID;
+  }
   return SSS_OK;
 }
 
@@ -274,6 +279,10 @@ int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const
   if (!means || !momentum || !grad_means || !opacity || !opts || n <= 0 || !(opts->lr >= 0.0f) ||
       (opts->burn_in && (!scales || !quats))) {
     set_error("sss_sghmc_step: null array, n <= 0 or lr < 0 (burn-in needs scales and quats)");
+    return SSS_ERR_INVALID;
+  }
+  if (opts->burn_in && ((uintptr_t)quats & 15)) {
+    set_error("sss_sghmc_step: quats must be 16-byte aligned");
     return SSS_ERR_INVALID;
   }
   if (adam) {

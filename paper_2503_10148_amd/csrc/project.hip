@@ -234,13 +234,9 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     const float* __restrict__ quats, const float* __restrict__ nu, const float* __restrict__ opac,
     const float* __restrict__ sh, Rec* __restrict__ rec, uint32_t* __restrict__ keys, ushort4* __restrict__ rects,
     uint32_t* __restrict__ touched, Ellipse* __restrict__ ell) {
-  constexpr int K = (DEG + 1) * (DEG + 1), STR = 3 * K + 1;
-  __shared__ float shs[kBlock * STR];
+  constexpr int K = (DEG + 1) * (DEG + 1);
   const int v = blockIdx.y;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
-  stage_sh<DEG>(sh, i0, (int)min((int64_t)kBlock, n - i0), shs);
-  __syncthreads();
-  const int64_t i = i0 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const CamDev& c = cb.v[v];
   const int64_t e = (int64_t)v * n + i;
@@ -294,7 +290,21 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   view_dir<double>(c, mu, dir, &vn);
   double Y[16];
   sh_basis<double>(DEG, dir[0], dir[1], dir[2], Y);
-  const float* shi = shs + threadIdx.x * STR;
+  // Each thread reads its own coefficients (16-byte loads when the row is a
+  // multiple of 4 floats): without a staging array in LDS the kernel keeps 4
+  // waves per SIMD instead of 3, and only entries that reach a tile read them.
+  float shi[3 * K];
+  if constexpr ((3 * K) % 4 == 0) {
+    const float4* s4 = reinterpret_cast<const float4*>(sh + (size_t)i * 3 * K);
+#pragma unroll
+    for (int q = 0; q < 3 * K / 4; ++q) {
+      const float4 t = s4[q];
+      shi[4 * q] = t.x; shi[4 * q + 1] = t.y; shi[4 * q + 2] = t.z; shi[4 * q + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 3 * K; ++q) shi[q] = sh[(size_t)i * 3 * K + q];
+  }
   double col[3] = {0.5, 0.5, 0.5};
 #pragma unroll
   for (int k = 0; k < K; ++k) {

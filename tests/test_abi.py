@@ -197,3 +197,19 @@ def test_misaligned_workspaces_are_rejected(sss):
                             ctypes.c_void_p(0x6000), ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000), None, None,
                             ctypes.byref(g), ctypes.c_void_p(0x9080), 10 ** 9, None) == sss.ERR_INVALID
     assert b"aligned" in L.sss_last_error()
+
+
+def test_misaligned_scene_arrays_are_rejected(sss):
+    """quats and SH rows are read with 16-byte loads: a scene whose quats or
+    sh pointer is not 16-byte aligned is an argument error."""
+    L = sss.lib()
+    cams = sss.camera_array([scenes.ring_camera(64, 48)])
+    opts = sss.render_opts()
+    for idx in (2, 5):                                   # quats, sh
+        scene = _scene_struct(sss)
+        ptrs = [scene.means, scene.scales, scene.quats, scene.nu, scene.opacity, scene.sh]
+        ptrs[idx] = ptrs[idx] + 4
+        scene = sss.Scene(10, 0, 0, *[ctypes.c_void_p(q) for q in ptrs])
+        p = _proj_struct(sss)
+        assert L.sss_project(ctypes.byref(scene), cams, 1, ctypes.byref(opts), ctypes.byref(p), None) == sss.ERR_INVALID
+        assert b"16-byte" in L.sss_last_error()
