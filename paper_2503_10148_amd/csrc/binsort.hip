@@ -308,12 +308,7 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
           if (kk < tot) {
             const int base = hi ? bcast_i(wr.base, j + 1) : bcast_i(wr.base, j);
             const int h = hi ? bcast_i(wr.h, j + 1) : bcast_i(wr.h, j);
-            int lo = 0, hq = h - 1;
-            while (lo < hq) {
-              const int mid = (lo + hq + 1) >> 1;
-              if ((int)table->cum[base + mid] <= kk) lo = mid;
-              else hq = mid - 1;
-            }
+            const int lo = find_row(table, base, h, kk);
             const int x = (int)table->t0[base + lo] + (kk - (int)table->cum[base + lo]);
             const int y = (hi ? bcast_i(my_y0, j + 1) : bcast_i(my_y0, j)) + lo;
             const int toff = hi ? bcast_i(my_toff, j + 1) : bcast_i(my_toff, j);

@@ -697,12 +697,7 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
       const int k = (int)(s - M.off[rho]);
       if (k < M.total[rho]) {
         const int b = M.base[rho];
-        int qlo = 0, qhi = M.h[rho] - 1;
-        while (qlo < qhi) {
-          const int mid = (qlo + qhi + 1) >> 1;
-          if ((int)table->cum[b + mid] <= k) qlo = mid;
-          else qhi = mid - 1;
-        }
+        const int qlo = find_row(table, b, M.h[rho], k);
         const int x = (int)table->t0[b + qlo] + (k - (int)table->cum[b + qlo]);
         const int y = M.y0[rho] + qlo;
         if ((uint32_t)(r0 + rho) < det.lastp1[M.toff[rho] + y * M.tiles_x[rho] + x]) {

@@ -110,17 +110,26 @@ __device__ __forceinline__ WaveRows wave_row_table(bool valid, double mx, double
 // table, in emission order: the lanes take positions k = lane, lane + 64,
 // ... and find their row as the last one whose cum is <= k (binary search),
 // then call f(k, tile_x, tile_y).
+// Row of the k-th listed tile of an entry whose h rows start at table
+// slot `base`: cum is the exclusive prefix of the row lengths, so the row is
+// the last one with cum <= k (binary search; entries span a few rows, and a
+// counted scan of 16 predicated reads measured slower).
+__device__ __forceinline__ int find_row(const RowTable* table, int base, int h, int k) {
+  int lo = 0, hi = h - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int)table->cum[base + mid] <= k) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 template <typename F>
 __device__ __forceinline__ void for_each_tile_in_table(const RowTable* table, int base, int h, int total, int y0,
                                                        F&& f) {
   const int lane = threadIdx.x & 63;
   for (int k = lane; k < total; k += 64) {
-    int lo = 0, hi = h - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if ((int)table->cum[base + mid] <= k) lo = mid;
-      else hi = mid - 1;
-    }
+    const int lo = find_row(table, base, h, k);
     f(k, (int)table->t0[base + lo] + (k - (int)table->cum[base + lo]), y0 + lo);
   }
 }
