@@ -244,15 +244,43 @@ __device__ __forceinline__ uint32_t off_next(const uint32_t* __restrict__ off, i
   return (r + 1 < n_vis ? off[r + 1] : total) - off[r];
 }
 
+// Inclusive max-scan over the wave of non-negative values (DPP row shifts,
+// then row broadcasts; lanes outside a row or in masked rows read 0).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_max(int v) {
+  return max(v, __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xf, true));
+}
+
+__device__ __forceinline__ int wave_incl_max(int v) {
+  v = dpp_max<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_max<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_max<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_max<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_max<0x142, 0xa>(v);  // row_bcast:15
+  v = dpp_max<0x143, 0xc>(v);  // row_bcast:31
+  return v;
+}
+
+// Per-wave metadata of the emission: the 64 ranks' first slots and row
+// table coordinates, read by the lanes that write those ranks' pairs.
+struct EmitMeta {
+  uint32_t off[64];
+  int base[64], h[64], total[64], y0[64], toff[64], tx[64], fits[64];
+  int mark[64];
+};
+
 // One lane per rank gathers that rank's record and evaluates the rows of its
-// rectangle into the wave's row table (wave_row_table); the pairs are then
-// written wave-cooperatively: for each of the wave's 64 ranks in turn, the
-// lanes store its listed tiles in emission order, so the stores of one rank
-// are contiguous.  Exactly tiles_touched pairs are written per rank (the scan
-// reserved that many, and the projection counted them with the same row_run
-// on the same values); slots left over if the two ever disagreed get the
-// sentinel key n_tiles, which sorts after every real tile, and no store
-// leaves the rank's range.
+// rectangle into the wave's row table (wave_row_table).  The 64 ranks' pairs
+// are one contiguous slot range, which the wave then writes 64 slots at a
+// time: a rank that starts inside the window marks its start, an inclusive
+// max-scan of the marks gives every slot its rank, and the slot's tile comes
+// from that rank's rows (find_row).  Stores are coalesced and each step does
+// the same work whatever the ranks' sizes.  Exactly tiles_touched pairs are
+// written per rank (the scan reserved that many, and the projection counted
+// them with the same row_run on the same values); slots left over if the two
+// ever disagreed get the sentinel key n_tiles, which sorts after every real
+// tile, and no store leaves the rank's range.  Ranks whose rows do not fit
+// the table are written afterwards with for_each_listed_tile.
 __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, const uint32_t* __restrict__ order,
                                                       const ushort4* __restrict__ rects,
                                                       const Ellipse* __restrict__ ell,
@@ -260,9 +288,11 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
                                                       const uint4* __restrict__ rec_in, uint4* __restrict__ rec_out,
                                                       uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
   __shared__ RowTable s_rows[kBlock / 64];
+  __shared__ EmitMeta s_meta[kBlock / 64];
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
   RowTable* table = &s_rows[threadIdx.x >> 6];
+  EmitMeta& M = s_meta[threadIdx.x >> 6];
   int my_off = 0, my_cnt = 0, my_x0 = 0, my_y0 = 0, my_x1 = 0, my_y1 = 0, my_toff = 0, my_tx = 1;
   double my_mx = 0.0, my_my = 0.0;
   Ellipse my_el{1.0, 0.0, 1.0, 0.0};
@@ -285,43 +315,49 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
     my_x0 = rc.x; my_y0 = rc.y; my_x1 = rc.z; my_y1 = rc.w;
   }
   const WaveRows wr = wave_row_table(valid, my_mx, my_my, my_el, my_x0, my_y0, my_x1, my_y1, table);
+  M.off[lane] = (uint32_t)my_off;
+  M.base[lane] = wr.base;
+  M.h[lane] = wr.h;
+  M.total[lane] = wr.total;
+  M.y0[lane] = my_y0;
+  M.toff[lane] = my_toff;
+  M.tx[lane] = my_tx;
+  M.fits[lane] = valid && wr.fits;
   __syncthreads();
   const int64_t r0 = r - lane;
-  for (int j = 0; j < 64; ++j) {
-    const int cntj = bcast_i(my_cnt, j);
-    if (cntj == 0) continue;
-    // two small entries at once: lanes 0..31 take entry j, lanes 32..63 entry
-    // j + 1 (both in the table, at most 32 pairs each; halves the sequential
-    // steps for the common case)
-    if (j + 1 < 64) {
-      const int cnt1 = bcast_i(my_cnt, j + 1);
-      if (cntj <= 32 && cnt1 <= 32 && __builtin_amdgcn_readlane((int)wr.fits, j) &&
-          __builtin_amdgcn_readlane((int)wr.fits, j + 1)) {
-        const bool hi = lane >= 32;
-        const int kk = lane & 31;
-        const int cnt = hi ? cnt1 : cntj;
-        const int tot = hi ? bcast_i(wr.total, j + 1) : bcast_i(wr.total, j);
-        const uint32_t offk = (uint32_t)(hi ? bcast_i(my_off, j + 1) : bcast_i(my_off, j));
-        const uint32_t rank = (uint32_t)(r0 + j + (hi ? 1 : 0));
-        if (kk < cnt) {
-          uint32_t key = (uint32_t)cb.total_tiles;   // sentinel for slots beyond the listed tiles
-          if (kk < tot) {
-            const int base = hi ? bcast_i(wr.base, j + 1) : bcast_i(wr.base, j);
-            const int h = hi ? bcast_i(wr.h, j + 1) : bcast_i(wr.h, j);
-            const int lo = find_row(table, base, h, kk);
-            const int x = (int)table->t0[base + lo] + (kk - (int)table->cum[base + lo]);
-            const int y = (hi ? bcast_i(my_y0, j + 1) : bcast_i(my_y0, j)) + lo;
-            const int toff = hi ? bcast_i(my_toff, j + 1) : bcast_i(my_toff, j);
-            const int tx = hi ? bcast_i(my_tx, j + 1) : bcast_i(my_tx, j);
-            key = (uint32_t)(toff + y * tx + x);
-          }
-          tkeys[offk + kk] = key;
-          tvals[offk + kk] = rank;
-        }
-        ++j;
-        continue;
+  if (r0 >= n_vis) return;   // uniform per wave; no barrier follows
+  const int last = (int)min((int64_t)63, n_vis - 1 - r0);
+  const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane(my_off);
+  const uint32_t s1 = (uint32_t)__builtin_amdgcn_readlane(my_off + my_cnt, last);
+  int carry = 0;
+  for (uint32_t c0 = s0; c0 < s1; c0 += 64) {
+    M.mark[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && my_cnt > 0 && (uint32_t)my_off >= c0 && (uint32_t)my_off < c0 + 64u) M.mark[my_off - c0] = lane + 1;
+    __builtin_amdgcn_wave_barrier();
+    const int m = wave_incl_max(M.mark[lane]);
+    const int rk = m > 0 ? m - 1 : carry;
+    carry = __builtin_amdgcn_readlane(rk, 63);
+    const uint32_t sl = c0 + (uint32_t)lane;
+    if (sl < s1 && M.fits[rk]) {
+      const int k = (int)(sl - M.off[rk]);
+      uint32_t key = (uint32_t)cb.total_tiles;
+      if (k < M.total[rk]) {
+        const int b = M.base[rk];
+        const int row = find_row(table, b, M.h[rk], k);
+        const int x = (int)table->t0[b + row] + (k - (int)table->cum[b + row]);
+        key = (uint32_t)(M.toff[rk] + (M.y0[rk] + row) * M.tx[rk] + x);
       }
+      tkeys[sl] = key;
+      tvals[sl] = (uint32_t)(r0 + rk);
     }
+  }
+  // ranks whose rows did not fit the table, one at a time
+  uint64_t rest = __ballot(valid && my_cnt > 0 && !wr.fits);
+  while (rest) {
+    const int j = (int)__builtin_ctzll(rest);
+    rest &= rest - 1;
+    const int cntj = bcast_i(my_cnt, j);
     const uint32_t offj = (uint32_t)bcast_i(my_off, j);
     const uint32_t rank = (uint32_t)(r0 + j);
     const int toff = bcast_i(my_toff, j), tx = bcast_i(my_tx, j);
@@ -331,15 +367,9 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
         tvals[offj + k] = rank;
       }
     };
-    int written;
-    if (__builtin_amdgcn_readlane((int)wr.fits, j)) {
-      written = bcast_i(wr.total, j);
-      for_each_tile_in_table(table, bcast_i(wr.base, j), bcast_i(wr.h, j), written, bcast_i(my_y0, j), put);
-    } else {
-      const Ellipse el{bcast_d(my_el.A, j), bcast_d(my_el.B, j), bcast_d(my_el.D, j), bcast_d(my_el.hr, j)};
-      written = for_each_listed_tile(bcast_d(my_mx, j), bcast_d(my_my, j), el, bcast_i(my_x0, j), bcast_i(my_y0, j),
-                                     bcast_i(my_x1, j), bcast_i(my_y1, j), put);
-    }
+    const Ellipse el{bcast_d(my_el.A, j), bcast_d(my_el.B, j), bcast_d(my_el.D, j), bcast_d(my_el.hr, j)};
+    const int written = for_each_listed_tile(bcast_d(my_mx, j), bcast_d(my_my, j), el, bcast_i(my_x0, j),
+                                             bcast_i(my_y0, j), bcast_i(my_x1, j), bcast_i(my_y1, j), put);
     for (int k = written + lane; k < cntj; k += 64) {
       tkeys[offj + k] = (uint32_t)cb.total_tiles;
       tvals[offj + k] = rank;
