@@ -244,23 +244,6 @@ __device__ __forceinline__ uint32_t off_next(const uint32_t* __restrict__ off, i
   return (r + 1 < n_vis ? off[r + 1] : total) - off[r];
 }
 
-// Inclusive max-scan over the wave of non-negative values (DPP row shifts,
-// then row broadcasts; lanes outside a row or in masked rows read 0).
-template <int kCtrl, int kRowMask>
-__device__ __forceinline__ int dpp_max(int v) {
-  return max(v, __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xf, true));
-}
-
-__device__ __forceinline__ int wave_incl_max(int v) {
-  v = dpp_max<0x111, 0xf>(v);  // row_shr:1
-  v = dpp_max<0x112, 0xf>(v);  // row_shr:2
-  v = dpp_max<0x114, 0xf>(v);  // row_shr:4
-  v = dpp_max<0x118, 0xf>(v);  // row_shr:8
-  v = dpp_max<0x142, 0xa>(v);  // row_bcast:15
-  v = dpp_max<0x143, 0xc>(v);  // row_bcast:31
-  return v;
-}
-
 // Per-wave metadata of the emission: the 64 ranks' first slots and row
 // table coordinates, read by the lanes that write those ranks' pairs.
 struct EmitMeta {

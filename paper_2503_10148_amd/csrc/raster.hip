@@ -638,6 +638,7 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
     uint32_t off[65];
     int base[64], h[64], total[64], y0[64], toff[64], tiles_x[64], fits[64];
     double acc[64][10];
+    int mark[64];
   };
   __shared__ RowTable s_rows[kBlock / 64];
   __shared__ WaveMeta s_meta[kBlock / 64];
@@ -679,17 +680,21 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
   __syncthreads();
   if (r0 >= n_vis) return;   // uniform per wave; no barrier follows
   const uint32_t s0 = M.off[0], s1 = M.off[64];
+  const int my_cnt = valid ? (int)(M.off[lane + 1] - my_off) : 0;
+  int carry = 0;
   for (uint32_t c0 = s0; c0 < s1; c0 += 64) {
     const uint32_t s = c0 + (uint32_t)lane;
     const bool in = s < s1;
-    // rank of the slot: last rho with off[rho] <= s
-    int lo = 0, hi = 63;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (M.off[mid] <= s) lo = mid;
-      else hi = mid - 1;
-    }
-    const int rho = lo;
+    // rank of the slot: a rank starting inside the window marks its start;
+    // the inclusive max-scan of the marks (or the rank running into the
+    // window) is the last rank with off <= s
+    M.mark[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    if (my_cnt > 0 && my_off >= c0 && my_off < c0 + 64u) M.mark[my_off - c0] = lane + 1;
+    __builtin_amdgcn_wave_barrier();
+    const int mk = wave_incl_max(M.mark[lane]);
+    const int rho = mk > 0 ? mk - 1 : carry;
+    carry = __builtin_amdgcn_readlane(rho, 63);
     float v[10];
 #pragma unroll
     for (int f = 0; f < 10; ++f) v[f] = 0.0f;

@@ -110,6 +110,23 @@ __device__ __forceinline__ WaveRows wave_row_table(bool valid, double mx, double
 // table, in emission order: the lanes take positions k = lane, lane + 64,
 // ... and find their row as the last one whose cum is <= k (binary search),
 // then call f(k, tile_x, tile_y).
+// Inclusive max-scan over the wave of non-negative values (DPP row shifts,
+// then row broadcasts; lanes outside a row or in masked rows read 0).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_max(int v) {
+  return max(v, __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xf, true));
+}
+
+__device__ __forceinline__ int wave_incl_max(int v) {
+  v = dpp_max<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_max<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_max<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_max<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_max<0x142, 0xa>(v);  // row_bcast:15
+  v = dpp_max<0x143, 0xc>(v);  // row_bcast:31
+  return v;
+}
+
 // Row of the k-th listed tile of an entry whose h rows start at table
 // slot `base`: cum is the exclusive prefix of the row lengths, so the row is
 // the last one with cum <= k (binary search; entries span a few rows, and a
