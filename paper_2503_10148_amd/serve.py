@@ -108,6 +108,15 @@ class RenderServer:
             self._cv.notify_all()
         return r.future
 
+    def warmup(self, cams):
+        """Render the batch `cams` once on every stream before requests arrive,
+        so each stream's scratch buffers and pair capacity are sized for it;
+        later batches up to that size allocate nothing."""
+        cams = list(cams)
+        for stream, slot in zip(self.streams, self._slots):
+            _, ev = self._launch([_Req(c) for c in cams], stream, slot)
+            ev.synchronize()
+
     def close(self):
         with self._cv:
             self._running = False
@@ -232,6 +241,12 @@ class PlainRenderer:
         self.opts = opts
         self.binner = sss.BinSorter(0)
 
+    def warmup(self, cams):
+        """Render each camera once (sizes the pair capacity and the allocator's
+        cache before requests arrive)."""
+        for c in cams:
+            self.render(c)
+
     def render(self, cam):
         cams = [cam]
         proj = sss.project(self.scene, cams, self.opts)
@@ -260,16 +275,20 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, **server_kw):
+def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, warm=None, **server_kw):
     """Replay `arrivals` (seconds from start) with the request cameras `cams`
     against the batched server or the plain renderer.  Latency is measured
     from the scheduled arrival to the moment the image is ready on the
-    device.  Returns (latencies in s, wall time in s, server stats)."""
+    device.  `warm` (cameras, optional) is rendered before the clock starts:
+    by the batched server as one batch per stream, by the plain renderer one
+    by one.  Returns (latencies in s, wall time in s, server stats)."""
     lat = []
-    t0 = time.perf_counter()
     stats = {}
     if server_kind == "batched":
         srv = RenderServer(scene, opts, **server_kw)
+        if warm:
+            srv.warmup(warm)
+        t0 = time.perf_counter()
         futs = []
         for a, cam in zip(arrivals, cams):
             now = time.perf_counter() - t0
@@ -284,6 +303,9 @@ def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, **server_
         stats = dict(batches=srv.batches, mean_batch=sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)))
     elif server_kind == "plain":
         pr = PlainRenderer(scene, opts)
+        if warm:
+            pr.warmup(warm)
+        t0 = time.perf_counter()
         for a, cam in zip(arrivals, cams):
             now = time.perf_counter() - t0
             if a > now:

@@ -42,6 +42,23 @@ def test_each_result_is_the_same_alone_and_in_the_mix(env):
         assert np.array_equal(a, b)
 
 
+def test_warmed_server_allocates_nothing_for_smaller_batches(env):
+    """After warmup with a large batch, serving smaller batches grows no
+    stream buffer and gives the same images as the plain renderer."""
+    serve, sss, _, scene = env
+    big = _cams(3, seed=5)
+    srv = serve.RenderServer(scene, max_batch=3, mem_budget=2 << 30)
+    srv.warmup(big)
+    sizes = [{k: v.data_ptr() for k, v in slot.buf.items()} for slot in srv._slots]
+    cams = _cams(6, seed=6)
+    got = [f.result(timeout=60).cpu().numpy() for f in [srv.submit(c) for c in cams]]
+    srv.close()
+    assert [{k: v.data_ptr() for k, v in slot.buf.items()} for slot in srv._slots] == sizes
+    plain = serve.PlainRenderer(scene)
+    for c, g in zip(cams, got):
+        assert np.array_equal(plain.render(c).cpu().numpy(), g)
+
+
 def test_requests_arriving_while_others_run_are_admitted(env):
     serve, sss, _, scene = env
     cams = _cams(40, seed=1)
