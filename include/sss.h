@@ -119,7 +119,10 @@ typedef struct {
  *   family    SSS_FAMILY_STUDENT_T; SSS_FAMILY_GAUSSIAN renders every component
  *                    with the Gaussian kernel exp(-h/2) (the nu -> infinity limit,
  *                    Sec. 3.2; the paper's SGHMC-with-Gaussians ablation), nu
- *                    is ignored and gets no gradient
+ *                    is ignored and gets no gradient.  The projected records
+ *                    carry the family, and the raster calls are compiled per
+ *                    family: sss_render_fwd / sss_render_bwd must get the
+ *                    family the entries were projected with
  *   trunc_mode SSS_TRUNC_ALPHA: a component's tile rectangle bounds its alpha
  *                    level set h <= h* (lossless: outside it every pixel
  *                    fails the alpha test).  SSS_TRUNC_COVERAGE: the paper's

@@ -83,6 +83,10 @@ struct Eval {
   bool hit, clamped;
 };
 
+// kGauss: the Gaussian family (every record has inv_nu = 0 and
+// nb = -log2(e)/2); the kernels are instantiated per family, which the
+// caller's options select for the whole call.
+template <bool kGauss>
 __device__ __forceinline__ void evaluate(float px, float py, const LRec& L, float amin, float amax, Eval& E) {
   E.dx = px - L.mx;
   E.dy = py - L.my;
@@ -92,18 +96,20 @@ __device__ __forceinline__ void evaluate(float px, float py, const LRec& L, floa
   // Branch-free: once a record passes the strip test nearly every wave has
   // a lane inside the ellipse, so the whole chain runs anyway; selects keep
   // the exec mask untouched.
-  // T2D = (1 + h/nu)^(-(nu+2)/2) = 2^(nb log2(1 + y)), y = h/nu.  log2(1 + y) is
-  // corrected by the rounding error of u = 1 + y while u < 2.  Gaussian
-  // family (inv_nu = 0): T2D = exp(-h/2) = 2^(nb h), nb = -log2(e)/2.
-  const bool student = L.inv_nu != 0.0f;
-  const float y = E.h * L.inv_nu;
-  const float u = 1.0f + y;
-  const float z = u - 1.0f;
-  const float corr = u < 2.0f ? (y - z) : 0.0f;
-  const float l2 = __fmaf_rn(corr, kLog2e, __builtin_amdgcn_logf(u));
-  E.y = student ? y : 0.0f;
-  E.u = student ? u : 1.0f;
-  E.l2 = student ? l2 : E.h;
+  if constexpr (kGauss) {
+    // T2D = exp(-h/2) = 2^(nb h)
+    E.y = 0.0f;
+    E.u = 1.0f;
+    E.l2 = E.h;
+  } else {
+    // T2D = (1 + h/nu)^(-(nu+2)/2) = 2^(nb log2(1 + y)), y = h/nu.  log2(1 + y)
+    // is corrected by the rounding error of u = 1 + y while u < 2.
+    E.y = E.h * L.inv_nu;
+    E.u = 1.0f + E.y;
+    const float z = E.u - 1.0f;
+    const float corr = E.u < 2.0f ? (E.y - z) : 0.0f;
+    E.l2 = __fmaf_rn(corr, kLog2e, __builtin_amdgcn_logf(E.u));
+  }
   E.t2 = __builtin_amdgcn_exp2f(L.nb * E.l2);
   const float a = L.o * E.t2;
   E.hit = E.h <= L.hs && !(fabsf(a) < amin);
@@ -326,7 +332,7 @@ __device__ __forceinline__ uint64_t stage_batch_slot(const TileCtx<PIX>& t, cons
 
 // Forward traversal of the tile list; identical in render_fwd and in the
 // recompute phase of render_bwd.
-template <int PIX>
+template <int PIX, bool kGauss>
 __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDev& op, const Rec* __restrict__ srec,
                                              const uint32_t* __restrict__ pair_rank, LRec* lds, float (*C)[3],
                                              float* Tout, uint32_t* last_out) {
@@ -368,7 +374,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
           continue;
         }
         Eval E;
-        evaluate(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
+        evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
         if (E.hit) {
           const float Tn = T[k] * (1.0f - E.alpha);
           if (Tn < op.t_min) {
@@ -396,7 +402,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
   }
 }
 
-template <int PIX>
+template <int PIX, bool kGauss>
 __global__ __launch_bounds__(kUnitThreads) void render_fwd_kernel(CamBatch cb, OptsDev op,
                                                                   const Rec* __restrict__ srec,
                                                                   const uint32_t* __restrict__ tile_start,
@@ -411,7 +417,7 @@ __global__ __launch_bounds__(kUnitThreads) void render_fwd_kernel(CamBatch cb, O
   if (t.skip) return;
   float C[PIX][3], T[PIX];
   uint32_t last[PIX];
-  forward_walk<PIX>(t, op, srec, pair_rank, lds, C, T, last);
+  forward_walk<PIX, kGauss>(t, op, srec, pair_rank, lds, C, T, last);
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     if (!t.inside[k]) continue;
@@ -433,7 +439,7 @@ __global__ __launch_bounds__(kUnitThreads) void render_fwd_kernel(CamBatch cb, O
   }
 }
 
-template <int PIX, int kMode, int kLoss, bool kDet>
+template <int PIX, int kMode, int kLoss, bool kDet, bool kGauss>
 __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
     CamBatch cb, OptsDev op, const Rec* __restrict__ srec, const uint32_t* __restrict__ tile_start,
     const uint32_t* __restrict__ pair_rank, const float* __restrict__ dl_or_target, const float* __restrict__ image,
@@ -451,7 +457,7 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
   uint32_t bound[PIX];
   if (kMode == SSS_BWD_RECOMPUTE) {
     float T[PIX];
-    forward_walk<PIX>(t, op, srec, pair_rank, lds, out, T, bound);
+    forward_walk<PIX, kGauss>(t, op, srec, pair_rank, lds, out, T, bound);
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
       if (!t.inside[k]) {
@@ -550,7 +556,7 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
         // Predicated rather than branched (see evaluate): lanes past their
         // walk bound or outside the ellipse add zeros and keep T.
         Eval E;
-        evaluate(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
+        evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
         const bool hk = pos < bound[k] && E.hit;
         if (!__any(hk)) continue;
         hit = true;
@@ -569,9 +575,9 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
         T[k] = hk ? Tk * (1.0f - a) : Tk;
         v[8] = __fmaf_rn(da, E.t2, v[8]);
         const float dt2 = da * L.o;
-        const float ru = __builtin_amdgcn_rcpf(E.u);
+        const float ru = kGauss ? 1.0f : __builtin_amdgcn_rcpf(E.u);
         // d log2 T / dh = nb / (nu (1 + y)); nb ln 2 for the Gaussian family
-        const float kh = L.inv_nu != 0.0f ? L.inv_nu * ru : kLn2;
+        const float kh = kGauss ? kLn2 : L.inv_nu * ru;
         const float dh = dt2 * E.t2 * L.nb * kh;
         v[0] = __fmaf_rn(dh, E.ax, v[0]);
         v[1] = __fmaf_rn(dh, E.ay, v[1]);
@@ -579,17 +585,20 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
         v[2] = __fmaf_rn(tq, E.dx, v[2]);
         v[3] = __fmaf_rn(tq, E.dy, v[3]);
         v[4] = __fmaf_rn(dh * E.dy, E.dy, v[4]);
-        // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]; the first
-        // two terms by their series below y = 0.1 (they cancel)
-        const float y = E.y;
-        float s = __fmaf_rn(y, 6.0f / 7.0f, -5.0f / 6.0f);
-        s = __fmaf_rn(y, s, 4.0f / 5.0f);
-        s = __fmaf_rn(y, s, -3.0f / 4.0f);
-        s = __fmaf_rn(y, s, 2.0f / 3.0f);
-        s = __fmaf_rn(y, s, -0.5f);
-        const float q = y < 0.1f ? y * y * s : __fmaf_rn(y, ru, -E.l2 * kLn2);
-        const float dtn = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
-        v[9] = __fmaf_rn(dt2, dtn, v[9]);
+        if constexpr (!kGauss) {
+          // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]; the first
+          // two terms by their series below y = 0.1 (they cancel).  The
+          // Gaussian family has no nu.
+          const float y = E.y;
+          float s = __fmaf_rn(y, 6.0f / 7.0f, -5.0f / 6.0f);
+          s = __fmaf_rn(y, s, 4.0f / 5.0f);
+          s = __fmaf_rn(y, s, -3.0f / 4.0f);
+          s = __fmaf_rn(y, s, 2.0f / 3.0f);
+          s = __fmaf_rn(y, s, -0.5f);
+          const float q = y < 0.1f ? y * y * s : __fmaf_rn(y, ru, -E.l2 * kLn2);
+          const float dtn = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
+          v[9] = __fmaf_rn(dt2, dtn, v[9]);
+        }
       }
       // sums over the wave, transposed: lane tr_index(l) of the first row
       // holds component tr_index(l) of the entry's screen-space gradient
@@ -932,13 +941,18 @@ void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
   static const int pix = env_pix("SSS_PIX_FWD", 1);
   const dim3 grid((unsigned)(cb.total_tiles * (4 / pix)));
   const Rec* sr = (const Rec*)b.sorted_records;
-#define SSS_FWD(P)                                                                                          \
-  SSS_LAUNCH("render_fwd", render_fwd_kernel<P>, grid, dim3(kUnitThreads), 0, st, cb, op, sr,              \
+  const bool gauss = op.family == SSS_FAMILY_GAUSSIAN;
+#define SSS_FWD(P, G)                                                                                       \
+  SSS_LAUNCH("render_fwd", (render_fwd_kernel<P, G>), grid, dim3(kUnitThreads), 0, st, cb, op, sr,         \
              (const uint32_t*)b.tile_start, (const uint32_t*)b.pair_rank, image, t_final, n_contrib,           \
              (const uint32_t*)b.tile_order, b.tile_work)
-  if (pix == 1) SSS_FWD(1);
-  else if (pix == 2) SSS_FWD(2);
-  else SSS_FWD(4);
+#define SSS_FWD_G(P)                \
+  if (gauss) SSS_FWD(P, true);      \
+  else SSS_FWD(P, false)
+  if (pix == 1) { SSS_FWD_G(1); }
+  else if (pix == 2) { SSS_FWD_G(2); }
+  else { SSS_FWD_G(4); }
+#undef SSS_FWD_G
 #undef SSS_FWD
 }
 
@@ -966,15 +980,20 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
   const Rec* sr = (const Rec*)b.sorted_records;
   const uint32_t* ts = b.tile_start;
   const uint32_t* pr = b.pair_rank;
+  const bool gauss = op.family == SSS_FAMILY_GAUSSIAN;
   if (det_mode) {
-#define SSS_BWD_DET(M, L)                                                                                         \
-  SSS_LAUNCH("render_bwd", (render_bwd_kernel<4, M, L, true>), grid, dim3(kUnitThreads), 0, st, cb, op, sr, ts, pr, \
-             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da)
+#define SSS_BWD_DET1(M, L, G)                                                                                       \
+  SSS_LAUNCH("render_bwd", (render_bwd_kernel<4, M, L, true, G>), grid, dim3(kUnitThreads), 0, st, cb, op, sr, ts, \
+             pr, dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da)
+#define SSS_BWD_DET(M, L)            \
+  if (gauss) SSS_BWD_DET1(M, L, true); \
+  else SSS_BWD_DET1(M, L, false)
     if (mode == SSS_BWD_STORED && loss == SSS_LOSS_GRAD) { SSS_BWD_DET(SSS_BWD_STORED, SSS_LOSS_GRAD); }
     else if (mode == SSS_BWD_STORED) { SSS_BWD_DET(SSS_BWD_STORED, SSS_LOSS_L1); }
     else if (loss == SSS_LOSS_GRAD) { SSS_BWD_DET(SSS_BWD_RECOMPUTE, SSS_LOSS_GRAD); }
     else { SSS_BWD_DET(SSS_BWD_RECOMPUTE, SSS_LOSS_L1); }
 #undef SSS_BWD_DET
+#undef SSS_BWD_DET1
     // then the fixed-order sums
     if (b.n_visible > 0) {
       const unsigned gr = (unsigned)((b.n_visible + kBlock - 1) / kBlock);
@@ -982,9 +1001,14 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                  (uint32_t)b.n_pairs, sr, da, g2);
     }
   } else {
-#define SSS_BWD(P, M, L)                                                                                      \
-  SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L, false>), grid, dim3(kUnitThreads), 0, st, cb, op, sr, ts, pr, \
-             dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da)
+#define SSS_BWD1(P, M, L, G)                                                                                   \
+  SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L, false, G>), grid, dim3(kUnitThreads), 0, st, cb, op, sr, ts, \
+             pr, dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da)
+#define SSS_BWD(P, M, L)                 \
+  do {                                   \
+    if (gauss) SSS_BWD1(P, M, L, true);  \
+    else SSS_BWD1(P, M, L, false);       \
+  } while (0)
 #define SSS_BWD_P(M, L)                \
   if (pix == 1) SSS_BWD(1, M, L);      \
   else if (pix == 2) SSS_BWD(2, M, L); \
@@ -995,6 +1019,7 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
     else { SSS_BWD_P(SSS_BWD_RECOMPUTE, SSS_LOSS_L1); }
 #undef SSS_BWD_P
 #undef SSS_BWD
+#undef SSS_BWD1
   }
   if (loss == SSS_LOSS_L1 && loss_out)
     SSS_LAUNCH("loss_reduce", loss_reduce_kernel, dim3(1), dim3(kLossThreads), 0, st, (const float*)da.loss_part, units,
