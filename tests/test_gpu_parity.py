@@ -451,24 +451,33 @@ def test_adam_on_six_arrays_in_one_launch(sss):
 
 @pytest.mark.parametrize("name", ["sh3_ragged", "bigcomp"])
 def test_gaussian_family_matches_oracle(sss, name):
+    """The Gaussian-family kernels: image, and gradients in every backward
+    variant (stored / recompute, atomic / deterministic)."""
     scene, cams = _case(name)
     cam = cams[0]
+    n = scene["means"].shape[0]
     opts = dict(family="gaussian")
     ref = oracle.render(scene, cam, opts)
-    dev, proj, bins, img, _, ncon = gpu_forward(sss, scene, cams, opts)
+    dev = to_device(scene)
+    proj = sss.project(dev, cams, opts)
+    bins = sss.BinSorter(1024, keep_offsets=True)(proj, cams, n)
+    img, _, ncon = sss.render_fwd(bins, cams, opts)
     bad, _, _ = _image_check(img.cpu().numpy(), ref, ref["xflags"])
     assert not bad.any()
     w = np.random.default_rng(8).standard_normal(ref["image"].shape)
     w[ref["xflags"] != 0] = 0.0
     gref = oracle.render_backward(scene, cam, w, opts, fwd=ref)
-    g = sss.render_bwd(dev, proj, bins, cams, torch.as_tensor(w.reshape(-1, 3), dtype=torch.float32, device="cuda"),
-                       opts, image=img, n_contrib=ncon)
-    torch.cuda.synchronize()
+    dl = torch.as_tensor(w.reshape(-1, 3), dtype=torch.float32, device="cuda")
     keep = ref["proj"]["pflags"] == 0
-    assert not np.any(g["nu"].cpu().numpy())
-    for k in PARAMS:
-        ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=keep)
-        assert ok, (k, worst)
+    for mode in (sss.BWD_STORED, sss.BWD_RECOMPUTE):
+        for det in (False, True):
+            g = sss.render_bwd(dev, proj, bins, cams, dl, opts, mode=mode, image=img, n_contrib=ncon,
+                               deterministic=det)
+            torch.cuda.synchronize()
+            assert not np.any(g["nu"].cpu().numpy())
+            for k in PARAMS:
+                ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=keep)
+                assert ok, (mode, det, k, worst)
 
 
 @pytest.mark.parametrize("family", ["student_t", "gaussian"])
