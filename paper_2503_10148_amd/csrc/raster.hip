@@ -360,19 +360,18 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
     // records that miss every strip of this unit are never visited
     uint64_t hits = stage_batch<PIX>(t, srec, pair_rank, base, t.end, lds, ws.all);
     __syncthreads();
-    while (hits && alive) {
+    // Finished pixels are masked off; whether the whole wave is finished is
+    // asked every 8 visited records only (a per-record test cost more than
+    // the few records a finished wave may still walk).
+    int since = 0;
+    while (hits) {
       const int j = (int)__builtin_ctzll(hits);
       hits &= hits - 1;
       const LRec L = lds[j];
       const uint32_t sm = PIX > 1 ? __builtin_amdgcn_readfirstlane(L.smask) : ws.all;
-      alive = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
-        if (done[k]) continue;
-        if (!(sm & ws.bit[k])) {
-          alive |= true;
-          continue;
-        }
+        if (done[k] || !(sm & ws.bit[k])) continue;
         Eval E;
         evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
         if (E.hit) {
@@ -388,7 +387,13 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
             last[k] = base - t.start + (uint32_t)j + 1u;
           }
         }
-        alive |= !done[k];
+      }
+      if (++since == 8) {
+        since = 0;
+        bool left = false;
+#pragma unroll
+        for (int k = 0; k < PIX; ++k) left |= !done[k];
+        if (!__any(left)) break;
       }
     }
   }
