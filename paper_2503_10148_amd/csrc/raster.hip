@@ -340,14 +340,16 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
   // accumulated up to a component from the output, and for components deep
   // in a list (small T) an FP32 running sum's accumulated rounding would be
   // a large part of that difference.  FP64 FMA issues at the FP32 rate here.
-  bool done[PIX];
+  // A pixel is finished when its T is negative: T stays positive while it
+  // composites (1 - alpha lies in [0.01, 1.99]), and termination negates it,
+  // so the final transmittance is |T| and the per-record test is one compare.
   float T[PIX];
   double c0[PIX], c1[PIX], c2[PIX];
   uint32_t last[PIX];
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
-    done[k] = !t.inside[k];
-    T[k] = 1.0f; c0[k] = 0.0; c1[k] = 0.0; c2[k] = 0.0;
+    T[k] = t.inside[k] ? 1.0f : -1.0f;
+    c0[k] = 0.0; c1[k] = 0.0; c2[k] = 0.0;
     last[k] = 0;
   }
   constexpr uint32_t kBatch = kUnitThreads;
@@ -355,7 +357,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
   for (uint32_t base = t.start; base < t.end; base += kBatch) {
     bool alive = false;
 #pragma unroll
-    for (int k = 0; k < PIX; ++k) alive |= !done[k];
+    for (int k = 0; k < PIX; ++k) alive |= T[k] > 0.0f;
     if (__syncthreads_count(alive) == 0) break;
     // records that miss every strip of this unit are never visited
     uint64_t hits = stage_batch<PIX>(t, srec, pair_rank, base, t.end, lds, ws.all);
@@ -371,13 +373,13 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
       const uint32_t sm = PIX > 1 ? __builtin_amdgcn_readfirstlane(L.smask) : ws.all;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
-        if (done[k] || !(sm & ws.bit[k])) continue;
+        if (!(T[k] > 0.0f) || !(sm & ws.bit[k])) continue;
         Eval E;
         evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
         if (E.hit) {
           const float Tn = T[k] * (1.0f - E.alpha);
           if (Tn < op.t_min) {
-            done[k] = true;
+            T[k] = -T[k];
           } else {
             const float wgt = E.alpha * T[k];
             c0[k] = __fma_rn((double)L.cr, (double)wgt, c0[k]);
@@ -392,17 +394,18 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
         since = 0;
         bool left = false;
 #pragma unroll
-        for (int k = 0; k < PIX; ++k) left |= !done[k];
+        for (int k = 0; k < PIX; ++k) left |= T[k] > 0.0f;
         if (!__any(left)) break;
       }
     }
   }
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
-    C[k][0] = (float)__fma_rn((double)T[k], (double)op.bg[0], c0[k]);
-    C[k][1] = (float)__fma_rn((double)T[k], (double)op.bg[1], c1[k]);
-    C[k][2] = (float)__fma_rn((double)T[k], (double)op.bg[2], c2[k]);
-    Tout[k] = T[k];
+    const float Tf = fabsf(T[k]);
+    C[k][0] = (float)__fma_rn((double)Tf, (double)op.bg[0], c0[k]);
+    C[k][1] = (float)__fma_rn((double)Tf, (double)op.bg[1], c1[k]);
+    C[k][2] = (float)__fma_rn((double)Tf, (double)op.bg[2], c2[k]);
+    Tout[k] = Tf;
     last_out[k] = last[k];
   }
 }
