@@ -554,9 +554,10 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
       const uint32_t pos = base - t.start + (uint32_t)j;
       const LRec L = lds[j];
       const uint32_t sm = PIX > 1 ? __builtin_amdgcn_readfirstlane(L.smask) : ws.all;
+      // v: the record's ten gradient sums over this lane's pixels.  The first
+      // pixel group to run assigns them, later ones accumulate (zeroing ten
+      // registers per record cost more than the uniform branch).
       float v[10];
-#pragma unroll
-      for (int f = 0; f < 10; ++f) v[f] = 0.0f;
       bool hit = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
@@ -566,8 +567,7 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
         Eval E;
         evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
         const bool hk = pos < bound[k] && E.hit;
-        if (!__any(hk)) continue;
-        hit = true;
+        if (__builtin_amdgcn_ballot_w64(hk) == 0) continue;
         const float a = E.alpha;
         const float Tk = T[k];
         const float w = hk ? a * Tk : 0.0f;
@@ -577,22 +577,17 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
         // a clamped alpha passes no gradient to T2D
         const float da0 = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), Tk * gc);
         const float da = hk && !E.clamped ? da0 : 0.0f;
-        v[5] = __fmaf_rn(g[k][0], w, v[5]);
-        v[6] = __fmaf_rn(g[k][1], w, v[6]);
-        v[7] = __fmaf_rn(g[k][2], w, v[7]);
         T[k] = hk ? Tk * (1.0f - a) : Tk;
-        v[8] = __fmaf_rn(da, E.t2, v[8]);
         const float dt2 = da * L.o;
         const float ru = kGauss ? 1.0f : __builtin_amdgcn_rcpf(E.u);
         // d log2 T / dh = nb / (nu (1 + y)); nb ln 2 for the Gaussian family
         const float kh = kGauss ? kLn2 : L.inv_nu * ru;
         const float dh = dt2 * E.t2 * L.nb * kh;
-        v[0] = __fmaf_rn(dh, E.ax, v[0]);
-        v[1] = __fmaf_rn(dh, E.ay, v[1]);
         const float tq = dh * E.dx;
-        v[2] = __fmaf_rn(tq, E.dx, v[2]);
-        v[3] = __fmaf_rn(tq, E.dy, v[3]);
-        v[4] = __fmaf_rn(dh * E.dy, E.dy, v[4]);
+        // the ten terms as products A[f] * B[f]: d mean (2), d conic (3),
+        // d colour (3), d opacity, d nu
+        float A[10] = {dh, dh, tq, tq, dh * E.dy, g[k][0], g[k][1], g[k][2], da, dt2};
+        float B[10] = {E.ax, E.ay, E.dx, E.dy, E.dy, w, w, w, E.t2, 0.0f};
         if constexpr (!kGauss) {
           // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]; the first
           // two terms by their series below y = 0.1 (they cancel).  The
@@ -604,18 +599,25 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
           s = __fmaf_rn(y, s, 2.0f / 3.0f);
           s = __fmaf_rn(y, s, -0.5f);
           const float q = y < 0.1f ? y * y * s : __fmaf_rn(y, ru, -E.l2 * kLn2);
-          const float dtn = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
-          v[9] = __fmaf_rn(dt2, dtn, v[9]);
+          B[9] = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
         }
+        if (!hit) {
+#pragma unroll
+          for (int f = 0; f < 10; ++f) v[f] = A[f] * B[f];
+        } else {
+#pragma unroll
+          for (int f = 0; f < 10; ++f) v[f] = __fmaf_rn(A[f], B[f], v[f]);
+        }
+        hit = true;
       }
       // sums over the wave, transposed: lane tr_index(l) of the first row
       // holds component tr_index(l) of the entry's screen-space gradient
       const int idx = tr_index(lane);
       if (kDet) {
         // every visited pair's slot is written, zeros when no pixel was hit
-        const float x = __any(hit) ? wave_sum10_transposed(v) : 0.0f;
+        const float x = hit ? wave_sum10_transposed(v) : 0.0f;
         if (lane < 16 && idx >= 0 && L.slot < det.n_pairs) det.part[(size_t)L.slot * kG2 + idx] = g2_scale(idx) * x;
-      } else if (__any(hit)) {
+      } else if (hit) {   // wave-uniform
         const float x = wave_sum10_transposed(v);
         if (lane < 16 && idx >= 0) atomicAdd(g2 + (size_t)L.entry * kG2 + idx, (double)(g2_scale(idx) * x));
       }
