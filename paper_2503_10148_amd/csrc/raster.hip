@@ -567,7 +567,12 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
         Eval E;
         evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
         const bool hk = pos < bound[k] && E.hit;
-        if (__builtin_amdgcn_ballot_w64(hk) == 0) continue;
+        // ballot(hk) as the AND of the ballots of its three compares: the lane
+        // masks combine on the scalar unit (one ballot of the combined bool
+        // went through two vector instructions)
+        if ((__builtin_amdgcn_ballot_w64(pos < bound[k]) & __builtin_amdgcn_ballot_w64(E.h <= L.hs) &
+             __builtin_amdgcn_ballot_w64(!(fabsf(E.alpha) < op.alpha_min))) == 0)
+          continue;
         const float a = E.alpha;
         const float Tk = T[k];
         const float w = hk ? a * Tk : 0.0f;
