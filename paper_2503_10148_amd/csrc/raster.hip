@@ -554,25 +554,35 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
       const uint32_t pos = base - t.start + (uint32_t)j;
       const LRec L = lds[j];
       const uint32_t sm = PIX > 1 ? __builtin_amdgcn_readfirstlane(L.smask) : ws.all;
-      // v: the record's ten gradient sums over this lane's pixels.  The first
-      // pixel group to run assigns them, later ones accumulate (zeroing ten
-      // registers per record cost more than the uniform branch).
+      // v: the record's ten gradient sums over this lane's pixels.  Pixel
+      // group 0 assigns them (zeros when it does not run) and later groups
+      // accumulate, a choice made at compile time: zeroing ten registers on
+      // every record, or choosing at run time, cost more.
       float v[10];
       bool hit = false;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
-        if (!(sm & ws.bit[k]) || pos >= gmax[k]) continue;
+        bool run = (sm & ws.bit[k]) && pos < gmax[k];
         // Predicated rather than branched (see evaluate): lanes past their
         // walk bound or outside the ellipse add zeros and keep T.
         Eval E;
-        evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
-        const bool hk = pos < bound[k] && E.hit;
-        // ballot(hk) as the AND of the ballots of its three compares: the lane
-        // masks combine on the scalar unit (one ballot of the combined bool
-        // went through two vector instructions)
-        if ((__builtin_amdgcn_ballot_w64(pos < bound[k]) & __builtin_amdgcn_ballot_w64(E.h <= L.hs) &
-             __builtin_amdgcn_ballot_w64(!(fabsf(E.alpha) < op.alpha_min))) == 0)
+        bool hk = false;
+        if (run) {
+          evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
+          hk = pos < bound[k] && E.hit;
+          // ballot(hk) as the AND of the ballots of its three compares: the
+          // lane masks combine on the scalar unit (one ballot of the
+          // combined bool went through two vector instructions)
+          run = (__builtin_amdgcn_ballot_w64(pos < bound[k]) & __builtin_amdgcn_ballot_w64(E.h <= L.hs) &
+                 __builtin_amdgcn_ballot_w64(!(fabsf(E.alpha) < op.alpha_min))) != 0;
+        }
+        if (!run) {
+          if (k == 0) {
+#pragma unroll
+            for (int f = 0; f < 10; ++f) v[f] = 0.0f;
+          }
           continue;
+        }
         const float a = E.alpha;
         const float Tk = T[k];
         const float w = hk ? a * Tk : 0.0f;
@@ -606,7 +616,7 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
           const float q = y < 0.1f ? y * y * s : __fmaf_rn(y, ru, -E.l2 * kLn2);
           B[9] = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
         }
-        if (!hit) {
+        if (k == 0) {
 #pragma unroll
           for (int f = 0; f < 10; ++f) v[f] = A[f] * B[f];
         } else {
