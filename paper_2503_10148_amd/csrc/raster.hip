@@ -4,25 +4,28 @@
 //
 // Work unit: one wave of 64 threads, each thread PIX pixels, renders 4*PIX
 // consecutive rows of a 16x16 tile (4/PIX units per tile), as a workgroup
-// of its own, so the hardware schedules units rather than whole tiles.  The
-// tile's depth-ordered list is consumed in batches of 64 records staged in
-// LDS; every thread reads each staged record as a broadcast.  The 2D mean is re-based on the tile origin in FP64 while
-// staging, so pixel offsets keep full FP32 relative precision.
+// of its own, so the hardware schedules units rather than whole tiles; the
+// units are launched most expensive first.  The tile's depth-ordered list is
+// consumed in batches of 64 records staged in LDS, and the walk visits only
+// the staged records whose strip mask meets the unit (a ballot); every lane
+// reads a visited record as a broadcast.  The 2D mean is re-based on the
+// tile origin in FP64 while staging, so pixel offsets keep full FP32
+// relative precision.
 //
 // The backward pass walks the list front to back, like the forward pass: with
 // out = sum_j c_j a_j T_j + T_final bg and A_i = sum_{j<=i} c_j a_j T_j,
 //   d out / d a_i = c_i T_i - (out - A_i) / (1 - a_i),
 // so it needs only the forward output per pixel, never a division to recover
-// T.  The per-pixel gradients of each record are summed over the wave with
-// DPP row shifts / broadcasts, and lane 63 adds them to the entry's
-// screen-space gradient slot with hardware float atomics.
+// T.  The ten per-pixel gradient sums of a record are reduced over the wave
+// in transposed form (wave_sum10_transposed), and ten lanes add them to the
+// entry's screen-space gradient slot with one FP64 atomic instruction.
 //
-// Deterministic variant: instead of the atomics, lane 63 stores the sums of
-// each (tile, component) pair in the pair's own slot, addressed by the pair's
-// position in emission order (the component's rank offset plus the tile's
-// row-major index in its rectangle).  A second kernel then adds, for every
-// component, its slots in emission order with a fixed reduction tree, so the
-// result does not depend on scheduling.
+// Deterministic variant: instead of the atomics, those lanes store the sums
+// of each (tile, component) pair in the pair's own slot, addressed by the
+// pair's position in emission order (the component's rank offset plus the
+// tile's row-major index in its rectangle).  A second kernel then adds, for
+// every component, its slots in emission order with a fixed reduction tree,
+// so the result does not depend on scheduling.
 #include <stdlib.h>
 
 #include "common.hpp"
