@@ -8,11 +8,14 @@
 //     its rank (ties keep entry order, i.e. component index); culled entries
 //     sort last;
 //  3. every (tile, rank) pair of a visible entry's listed tiles is written in
-//     rank order (exclusive scan of tiles_touched over ranks), the projected
-//     records are gathered into rank order alongside;
+//     rank order (exclusive scan of tiles_touched over ranks; each wave
+//     streams its ranks' contiguous slot range), the projected records are
+//     gathered into rank order alongside;
 //  4. a stable radix sort of the pairs by global tile id leaves each tile's
 //     ranks ascending, i.e. in (depth key, component index) order;
-//  5. tile_start[] marks where each tile's run begins.
+//  5. tile_start[] marks where each tile's run begins;
+//  6. if the caller asks for it, the tiles' launch order for the raster
+//     kernels, longest list first.
 //
 // All passes stream through HBM with coalesced accesses where the data
 // allows; the radix scatter ranks keys inside a wave with ballots (64-wide

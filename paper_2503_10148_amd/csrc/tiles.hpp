@@ -106,10 +106,6 @@ __device__ __forceinline__ WaveRows wave_row_table(bool valid, double mx, double
   return w;
 }
 
-// Wave-cooperative walk over the `total` listed tiles of one entry of the
-// table, in emission order: the lanes take positions k = lane, lane + 64,
-// ... and find their row as the last one whose cum is <= k (binary search),
-// then call f(k, tile_x, tile_y).
 // Inclusive max-scan over the wave of non-negative values (DPP row shifts,
 // then row broadcasts; lanes outside a row or in masked rows read 0).
 template <int kCtrl, int kRowMask>
@@ -141,6 +137,10 @@ __device__ __forceinline__ int find_row(const RowTable* table, int base, int h, 
   return lo;
 }
 
+// Wave-cooperative walk over the `total` listed tiles of one entry of the
+// table, in emission order: the lanes take positions k = lane, lane + 64,
+// ... and find their row as the last one whose cum is <= k (binary search),
+// then call f(k, tile_x, tile_y).
 template <typename F>
 __device__ __forceinline__ void for_each_tile_in_table(const RowTable* table, int base, int h, int total, int y0,
                                                        F&& f) {
