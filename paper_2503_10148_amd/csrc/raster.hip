@@ -988,10 +988,13 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                        const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
                        float* loss_out, double* g2, int64_t total_pixels, bool det_mode, const DetArgs& dargs,
                        int64_t n, hipStream_t st) {
-  // the deterministic variant runs one unit (one wave of 4 pixels per
-  // thread) per tile, so each pair's sums come from one wave
-  static const int env_bwd = env_pix("SSS_PIX_BWD", 2);
-  const int pix = det_mode ? 4 : env_bwd;
+  // Pixels per lane: the deterministic variant runs one unit (one wave of 4
+  // pixels per thread) per tile, so each pair's sums come from one wave;
+  // otherwise 2 when the walk bounds are stored, 1 when the unit first
+  // recomputes the forward walk (which is fastest at 1: measured 15% on
+  // the 3M-component workload), unless SSS_PIX_BWD says otherwise.
+  static const int env_bwd = env_pix("SSS_PIX_BWD", 0);
+  const int pix = det_mode ? 4 : env_bwd ? env_bwd : (mode == SSS_BWD_RECOMPUTE ? 1 : 2);
   const int64_t units = cb.total_tiles * (4 / pix);
   // schedule: units ordered by the forward's per-strip walk lengths when
   // the backward walks the stored prefixes, else the binning's tile order
