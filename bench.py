@@ -114,8 +114,9 @@ def serving(scene_np, rates, seconds):
         cams = [scenes.sphere_camera(rng, *sizes[int(rng.integers(0, 3))]) for _ in arr]
         px = sum(c["width"] * c["height"] for c in cams)
         row = {"rate_req_s": rate, "requests": len(arr)}
-        # both start warm: buffers sized for two of the largest requests
-        big = [scenes.sphere_camera(rng, *sizes[-1]) for _ in range(2)]
+        # both start warm: buffers sized for a burst of four of the largest
+        # requests
+        big = [scenes.sphere_camera(rng, *sizes[-1]) for _ in range(4)]
         for kind in ("plain", "batched"):
             lat, wall, stats = serve.run_load(kind, scene, cams, arr, warm=big)
             row[kind] = {"p50_ms": round(serve.percentile(lat, 50) * 1e3, 3),

@@ -59,7 +59,10 @@ class _Slot:
         numel = int(math.prod(shape))
         b = self.buf.get(name)
         if b is None or b.numel() < numel:
-            b = torch.empty(max(numel, 1), dtype=dtype, device=device)
+            # grow with headroom, so a run of slightly larger batches does
+            # not allocate every time
+            grown = numel if b is None else max(numel, b.numel() + b.numel() // 4)
+            b = torch.empty(max(grown, 1), dtype=dtype, device=device)
             self.buf[name] = b
         return b[:numel].view(shape)
 
