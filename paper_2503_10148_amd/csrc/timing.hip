@@ -66,14 +66,22 @@ KernelTimer::KernelTimer(const char* name, hipStream_t st) : name_(name), st_(st
   if (!g_on) return;
   a_ = take_event();
   b_ = take_event();
-  if (a_ && b_) hipEventRecord(a_, st_);
+  if (a_ && b_ && hipEventRecord(a_, st_) == hipSuccess) return;
+  // no timing for this launch: hand the events back
+  if (a_) g_pool.push_back(a_);
+  if (b_) g_pool.push_back(b_);
+  a_ = b_ = nullptr;
 }
 
 KernelTimer::~KernelTimer() {
   if (!a_ || !b_) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  hipEventRecord(b_, st_);
-  g_pending.push_back(Pending{name_, a_, b_});
+  if (hipEventRecord(b_, st_) == hipSuccess) {
+    g_pending.push_back(Pending{name_, a_, b_});
+  } else {
+    g_pool.push_back(a_);
+    g_pool.push_back(b_);
+  }
 }
 
 }  // namespace sss
