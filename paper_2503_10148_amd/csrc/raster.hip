@@ -855,6 +855,7 @@ __global__ __launch_bounds__(kLossThreads) void loss_reduce_kernel(const float* 
 // workgroup; the order inside a bucket follows the LDS atomics.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 256;
+constexpr int kOrderBatch = 8;
 
 __device__ __forceinline__ int order_bucket(uint32_t c) {
   const int b = (int)(12.0f * __log2f(1.0f + (float)c));
@@ -862,23 +863,46 @@ __device__ __forceinline__ int order_bucket(uint32_t c) {
 }
 
 // Cost of item t: the largest of strip_cost[spi*t .. spi*t + spi) when
-// strip_cost is given, else the list length of tile t.
+// strip_cost is given (kSpi > 0: spi = kSpi; kSpi < 0: spi at run time),
+// else (kSpi = 0) the list length of tile t.  Straight-line loads, so the
+// costs of a round of items are all in flight together.
+template <int kSpi>
 __device__ __forceinline__ uint32_t item_cost(const uint32_t* __restrict__ strip_cost, int spi,
                                               const uint32_t* __restrict__ tile_start, int64_t t) {
-  if (!strip_cost) return tile_start[t + 1] - tile_start[t];
-  uint32_t c = 0;
-  for (int j = 0; j < spi; ++j) c = max(c, strip_cost[spi * t + j]);
-  return c;
+  if constexpr (kSpi == 0) {
+    return tile_start[t + 1] - tile_start[t];
+  } else if constexpr (kSpi > 0) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < kSpi; ++j) c = max(c, strip_cost[kSpi * t + j]);
+    return c;
+  } else {
+    uint32_t c = 0;
+    for (int j = 0; j < spi; ++j) c = max(c, strip_cost[spi * t + j]);
+    return c;
+  }
 }
 
+template <int kSpi>
 __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_t* __restrict__ strip_cost, int spi,
                                                                    const uint32_t* __restrict__ tile_start,
                                                                    int64_t n_items, uint32_t* __restrict__ order) {
   __shared__ uint32_t hist[kOrderBuckets];
   for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) hist[i] = 0;
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < n_items; t += kOrderThreads)
-    atomicAdd(&hist[order_bucket(item_cost(strip_cost, spi, tile_start, t))], 1u);
+  // kOrderBatch items per thread and round, their costs loaded before any is
+  // used (indices clamped into range, so the loads need no branch): a round
+  // waits for one memory latency rather than one per item
+  constexpr int64_t kStride = (int64_t)kOrderBatch * kOrderThreads;
+  for (int64_t t0 = threadIdx.x; t0 < n_items; t0 += kStride) {
+    uint32_t c[kOrderBatch];
+#pragma unroll
+    for (int j = 0; j < kOrderBatch; ++j)
+      c[j] = item_cost<kSpi>(strip_cost, spi, tile_start, min(t0 + (int64_t)j * kOrderThreads, n_items - 1));
+#pragma unroll
+    for (int j = 0; j < kOrderBatch; ++j)
+      if (t0 + (int64_t)j * kOrderThreads < n_items) atomicAdd(&hist[order_bucket(c[j])], 1u);
+  }
   __syncthreads();
   if (threadIdx.x < 64) {
     // exclusive scan of the 256 counts by one wave, 4 per lane
@@ -897,8 +921,17 @@ __global__ __launch_bounds__(kOrderThreads) void tile_order_kernel(const uint32_
     }
   }
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < n_items; t += kOrderThreads)
-    order[atomicAdd(&hist[order_bucket(item_cost(strip_cost, spi, tile_start, t))], 1u)] = (uint32_t)t;
+  for (int64_t t0 = threadIdx.x; t0 < n_items; t0 += kStride) {
+    uint32_t c[kOrderBatch];
+#pragma unroll
+    for (int j = 0; j < kOrderBatch; ++j)
+      c[j] = item_cost<kSpi>(strip_cost, spi, tile_start, min(t0 + (int64_t)j * kOrderThreads, n_items - 1));
+#pragma unroll
+    for (int j = 0; j < kOrderBatch; ++j) {
+      const int64_t t = t0 + (int64_t)j * kOrderThreads;
+      if (t < n_items) order[atomicAdd(&hist[order_bucket(c[j])], 1u)] = (uint32_t)t;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void zero_kernel(float4* __restrict__ p, int64_t n4) {
@@ -911,8 +944,15 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(float4* __restrict__ p, in
 void launch_tile_order(const uint32_t* strip_cost, int strips_per_item, const uint32_t* tile_start, int64_t n_items,
                        uint32_t* order, hipStream_t st) {
   if (n_items <= 0) return;
-  SSS_LAUNCH("tile_order", tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, st, strip_cost, strips_per_item,
-             tile_start, n_items, order);
+#define SSS_ORDER(K)                                                                                          \
+  SSS_LAUNCH("tile_order", tile_order_kernel<K>, dim3(1), dim3(kOrderThreads), 0, st, strip_cost, strips_per_item, \
+             tile_start, n_items, order)
+  if (!strip_cost) SSS_ORDER(0);
+  else if (strips_per_item == 1) SSS_ORDER(1);
+  else if (strips_per_item == 2) SSS_ORDER(2);
+  else if (strips_per_item == 4) SSS_ORDER(4);
+  else SSS_ORDER(-1);
+#undef SSS_ORDER
 }
 
 void launch_zero(float* p, int64_t count, hipStream_t st) {
