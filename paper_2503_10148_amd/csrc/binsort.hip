@@ -146,7 +146,9 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
     if (j < n) atomicAdd(&h[radix_digit(kk[k], base_key, cap, shift, mask)], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  // digit-major rows; only the mask + 1 digits of this pass (the scan
+  // covers just those rows)
+  if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
 // Block b owns items [b*4096, (b+1)*4096); wave w owns the w-th quarter and
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   const int w = tid >> 6, lane = tid & 63;
   const uint32_t mask = (1u << bits) - 1u;
   for (int k = 0; k < 4; ++k) cnt[k][tid] = 0;
-  gbase[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+  gbase[tid] = (uint32_t)tid <= mask ? offsets[(int64_t)tid * nblocks + blockIdx.x] : 0u;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t block0 = (int64_t)blockIdx.x * kRPerBlock;
@@ -455,7 +457,7 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
     uint32_t* ovv = (p == passes - 1) ? out_v : ((p % 2 == 0) ? vb : va);
     SSS_LAUNCH("radix_hist", radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, n, base_key, cap, shift,
                        (uint32_t)((1u << bits) - 1u), nb, w.hist);
-    scan_excl(w.hist, w.hist, 256 * nb, w.scan, st);
+    scan_excl(w.hist, w.hist, ((int64_t)1 << bits) * nb, w.scan, st);
     SSS_LAUNCH("radix_scatter", radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, iv, n, base_key,
                        cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv);
   }
