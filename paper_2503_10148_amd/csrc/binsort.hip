@@ -151,6 +151,16 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
   if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// Workgroups are dispatched to the chip's 8 XCDs in turn, each XCD with an
+// L2 of its own.  Logical block numbers that give every XCD one contiguous
+// range put neighbouring blocks, whose digit runs meet in the output, on the
+// same L2, where the cache lines they share are completed before write-back.
+// The grid is 8 * ceil(nblocks / 8) workgroups; numbers >= nblocks exit.
+__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
+  const int64_t per = (nblocks + 7) / 8;
+  return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
 // Block b owns items [b*4096, (b+1)*4096); wave w owns the w-th quarter and
 // walks it in 16 rounds of 64 consecutive items, so (wave, round, lane) is
 // item order and ranks computed in that order are stable.  The block is then
@@ -165,14 +175,16 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   __shared__ uint32_t dofs[256];
   __shared__ uint32_t sk[kRPerBlock];
   __shared__ uint32_t sv[kRPerBlock];
+  const int64_t blk = xcd_block(nblocks);
+  if (blk >= nblocks) return;   // uniform per workgroup, before any barrier
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
   const uint32_t mask = (1u << bits) - 1u;
   for (int k = 0; k < 4; ++k) cnt[k][tid] = 0;
-  gbase[tid] = (uint32_t)tid <= mask ? offsets[(int64_t)tid * nblocks + blockIdx.x] : 0u;
+  gbase[tid] = (uint32_t)tid <= mask ? offsets[(int64_t)tid * nblocks + blk] : 0u;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t block0 = (int64_t)blockIdx.x * kRPerBlock;
+  const int64_t block0 = blk * kRPerBlock;
   const int64_t base = block0 + (int64_t)w * (kRPerBlock / 4);
   uint32_t key[kRItems], val[kRItems], loc[kRItems];
   // all loads first: the ranking below writes LDS between rounds, which
@@ -458,7 +470,7 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
     SSS_LAUNCH("radix_hist", radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, n, base_key, cap, shift,
                        (uint32_t)((1u << bits) - 1u), nb, w.hist);
     scan_excl(w.hist, w.hist, ((int64_t)1 << bits) * nb, w.scan, st);
-    SSS_LAUNCH("radix_scatter", radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, iv, n, base_key,
+    SSS_LAUNCH("radix_scatter", radix_scatter_kernel, dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(kBlock), 0, st, ik, iv, n, base_key,
                        cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv);
   }
   return final_keys;
