@@ -124,14 +124,27 @@ __device__ __forceinline__ uint32_t radix_digit(uint32_t key, uint32_t base, uin
   return (min(key - base, cap) >> shift) & mask;
 }
 
+// Workgroups are dispatched to the chip's 8 XCDs in turn, each XCD with an
+// L2 of its own.  Logical block numbers that give every XCD one contiguous
+// range put neighbouring blocks on the same L2, so the cache lines they
+// share (adjacent words of a histogram row; the ends of digit runs that
+// meet in the scatter's output) are completed there before write-back.
+// The grid is 8 * ceil(nblocks / 8) workgroups; numbers >= nblocks exit.
+__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
+  const int64_t per = (nblocks + 7) / 8;
+  return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
                                                             uint32_t base_key, uint32_t cap, int shift,
                                                             uint32_t mask, int64_t nblocks,
                                                             uint32_t* __restrict__ hist) {
+  const int64_t blk = xcd_block(nblocks);
+  if (blk >= nblocks) return;   // uniform per workgroup, before any barrier
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kRPerBlock;
+  const int64_t base = blk * kRPerBlock;
   // all loads first, so their latencies overlap (LDS atomics in between
   // would keep the compiler from hoisting them)
   uint32_t kk[kRItems];
@@ -148,17 +161,7 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
   __syncthreads();
   // digit-major rows; only the mask + 1 digits of this pass (the scan
   // covers just those rows)
-  if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
-}
-
-// Workgroups are dispatched to the chip's 8 XCDs in turn, each XCD with an
-// L2 of its own.  Logical block numbers that give every XCD one contiguous
-// range put neighbouring blocks, whose digit runs meet in the output, on the
-// same L2, where the cache lines they share are completed before write-back.
-// The grid is 8 * ceil(nblocks / 8) workgroups; numbers >= nblocks exit.
-__device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
-  const int64_t per = (nblocks + 7) / 8;
-  return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * nblocks + blk] = h[threadIdx.x];
 }
 
 // Block b owns items [b*4096, (b+1)*4096); wave w owns the w-th quarter and
@@ -467,7 +470,7 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
     uint32_t* iv = (p % 2 == 0) ? va : vb;
     uint32_t* okk = (p % 2 == 0) ? kb : ka;
     uint32_t* ovv = (p == passes - 1) ? out_v : ((p % 2 == 0) ? vb : va);
-    SSS_LAUNCH("radix_hist", radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, ik, n, base_key, cap, shift,
+    SSS_LAUNCH("radix_hist", radix_hist_kernel, dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(kBlock), 0, st, ik, n, base_key, cap, shift,
                        (uint32_t)((1u << bits) - 1u), nb, w.hist);
     scan_excl(w.hist, w.hist, ((int64_t)1 << bits) * nb, w.scan, st);
     SSS_LAUNCH("radix_scatter", radix_scatter_kernel, dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(kBlock), 0, st, ik, iv, n, base_key,
