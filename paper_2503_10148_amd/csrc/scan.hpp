@@ -11,40 +11,64 @@ namespace {
 constexpr int kItems = 16;                 // items per thread in scans / radix passes
 constexpr int kPerBlock = kBlock * kItems; // 4096
 
+constexpr int kScanWaves = kBlock / 64;
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Exclusive prefix of v over the 256 threads of the block (in thread order):
+// a scan inside each wave, then the totals of the waves before.  lds holds
+// at least kScanWaves values; it may be reused once this returns.
 template <typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T* lds, T* total) {
-  // Hillis-Steele over 256 values in LDS; returns the exclusive prefix.
-  const int t = threadIdx.x;
-  lds[t] = v;
+  const int w = threadIdx.x >> 6;
+  const T incl = wave_incl_sum(v);
+  if ((threadIdx.x & 63) == 63) lds[w] = incl;
   __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const T add = t >= off ? lds[t - off] : T(0);
-    __syncthreads();
-    lds[t] += add;
-    __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < kScanWaves; ++k) {
+    const T c = lds[k];
+    before += k < w ? c : T(0);
+    all += c;
   }
-  const T incl = lds[t];
-  if (total) *total = lds[kBlock - 1];
+  if (total) *total = all;
   __syncthreads();
-  return incl - v;
+  return before + incl - v;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const T* __restrict__ in, int64_t n, T* __restrict__ sums) {
-  __shared__ T red[kBlock];
+  __shared__ T red[kScanWaves];
   const int64_t base = (int64_t)blockIdx.x * kPerBlock;
-  T s = 0;
+  // all loads before the sum, so one memory latency is waited for, not 16
+  T v[kItems];
+#pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-    if (j < n) s += in[j];
+    v[k] = j < n ? in[j] : T(0);
   }
-  red[threadIdx.x] = s;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) s += v[k];
+  s = wave_incl_sum(s);   // lane 63 holds the wave's sum
+  if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    T t = 0;
+#pragma unroll
+    for (int k = 0; k < kScanWaves; ++k) t += red[k];
+    sums[blockIdx.x] = t;
   }
-  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
 }
 
 // Exclusive scan of one 4096-item block plus the block's prefix (in may alias
