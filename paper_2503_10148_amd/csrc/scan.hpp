@@ -72,12 +72,15 @@ __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const T* __restrict
 }
 
 // Exclusive scan of one 4096-item block plus the block's prefix (in may alias
-// out).  Loads and stores are coalesced (item k*256 + t by thread t) and
+// out).  The prefix is prefix[block] when prefix is given, else the sum of
+// block_sums[0 .. block) when that is given (each block adds the raw sums of
+// the blocks before it, which for up to kFusedBlocks blocks is cheaper than
+// a launch that scans them), else 0.  Loads and stores are coalesced (item k*256 + t by thread t) and
 // staged in LDS with one pad word per 16, so that thread t can scan its 16
 // consecutive items without bank conflicts.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const T* in, int64_t n, const T* __restrict__ prefix,
-                                                            T* out) {
+                                                            const T* __restrict__ block_sums, T* out) {
   constexpr int kPad = kItems + 1;
   __shared__ T lds[kBlock];
   __shared__ T tile[kBlock * kPad];
@@ -102,7 +105,13 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const T* in, int64_t
     v[k] = tile[t * kPad + k];
     s += v[k];
   }
-  T run = block_excl_scan<T>(s, lds, nullptr) + (prefix ? prefix[blockIdx.x] : T(0));
+  T pre = prefix ? prefix[blockIdx.x] : T(0);
+  if (!prefix && block_sums) {
+    T ps = 0;
+    for (int64_t i = t; i < (int64_t)blockIdx.x; i += kBlock) ps += block_sums[i];
+    block_excl_scan<T>(ps, lds, &pre);
+  }
+  T run = block_excl_scan<T>(s, lds, nullptr) + pre;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     tile[t * kPad + k] = run;
@@ -127,20 +136,28 @@ inline int64_t scan_ws_words(int64_t n) {
   return w + 16;
 }
 
+constexpr int64_t kFusedBlocks = 1024;
+
 template <typename T>
 void scan_excl(const T* in, T* out, int64_t n, T* ws, hipStream_t st) {
   if (n <= 0) return;
   const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
   if (nb == 1) {
-    SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3(1), dim3(kBlock), 0, st, in, n, (const T*)nullptr, out);
+    SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3(1), dim3(kBlock), 0, st, in, n, (const T*)nullptr,
+               (const T*)nullptr, out);
     return;
   }
   T* sums = ws;
   T* sums_scan = ws + nb;
   SSS_LAUNCH("scan_reduce", scan_reduce_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, sums);
+  if (nb <= kFusedBlocks) {
+    SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, (const T*)nullptr,
+               (const T*)sums, out);
+    return;
+  }
   scan_excl<T>(sums, sums_scan, nb, ws + 2 * nb, st);
   SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, (const T*)sums_scan,
-             out);
+             (const T*)nullptr, out);
 }
 
 }  // namespace
