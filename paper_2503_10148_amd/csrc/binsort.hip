@@ -112,11 +112,13 @@ __global__ __launch_bounds__(kBlock) void stat_reduce_kernel(const BlockStat* __
 // ---------------------------------------------------------------------------
 // 2./4. stable LSD radix sort, digits of up to 8 bits
 // ---------------------------------------------------------------------------
-#ifndef SSS_RADIX_ITEMS
-#define SSS_RADIX_ITEMS 16
-#endif
-constexpr int kRItems = SSS_RADIX_ITEMS;           // items per thread of a radix pass
-constexpr int kRPerBlock = kBlock * kRItems;      // items per workgroup
+// Items per thread of a radix pass: 16 for 8-bit digits, 8 (blocks of 2048,
+// half the LDS, so twice the workgroups per CU) for digits of up to 7 bits,
+// where a block's runs per digit stay as long (A/B on the 1M workload: the
+// pair scatter 0.217 -> 0.197 ms; 8-bit passes measured slower with 8).
+constexpr int kRItemsWide = 16;
+constexpr int kRItemsNarrow = 8;
+constexpr int radix_items(int width) { return width <= 7 ? kRItemsNarrow : kRItemsWide; }
 // Keys enter the passes as min(key - base, cap) (unsigned): the depth sort
 // subtracts the smallest visible key and maps culled entries to cap, so only
 // the bits that vary are sorted; the pair sort uses base 0, cap 2^32 - 1.
@@ -135,6 +137,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t nblocks) {
   return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
+template <int kRItems>
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
                                                             uint32_t base_key, uint32_t cap, int shift,
                                                             uint32_t mask, int64_t nblocks,
@@ -144,6 +147,7 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
+  constexpr int kRPerBlock = kBlock * kRItems;
   const int64_t base = blk * kRPerBlock;
   // all loads first, so their latencies overlap (LDS atomics in between
   // would keep the compiler from hoisting them)
@@ -164,11 +168,12 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t* __re
   if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * nblocks + blk] = h[threadIdx.x];
 }
 
-// Block b owns items [b*4096, (b+1)*4096); wave w owns the w-th quarter and
-// walks it in 16 rounds of 64 consecutive items, so (wave, round, lane) is
-// item order and ranks computed in that order are stable.  The block is then
-// reordered by digit in LDS and written out digit run by digit run, so
-// consecutive threads store to consecutive addresses.
+// Block b owns items [b*B, (b+1)*B), B = 256 * kRItems; wave w owns the w-th
+// quarter and walks it in kRItems rounds of 64 consecutive items, so (wave,
+// round, lane) is item order and ranks computed in that order are stable.
+// The block is then reordered by digit in LDS and written out digit run by
+// digit run, so consecutive threads store to consecutive addresses.
+template <int kRItems>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, uint32_t base_key, uint32_t cap,
     int shift, int bits, int64_t nblocks, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ okeys,
@@ -176,6 +181,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
   __shared__ uint32_t cnt[4][256];
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t dofs[256];
+  constexpr int kRPerBlock = kBlock * kRItems;
   __shared__ uint32_t sk[kRPerBlock];
   __shared__ uint32_t sv[kRPerBlock];
   const int64_t blk = xcd_block(nblocks);
@@ -430,7 +436,8 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 Ws carve(void* base, int64_t n_entries, int64_t pair_cap) {
   const int64_t big = n_entries > pair_cap ? n_entries : pair_cap;
-  const int64_t nb = (big + kRPerBlock - 1) / kRPerBlock;
+  // blocks of the narrowest pass (the most blocks, so the largest histogram)
+  const int64_t nb = (big + kBlock * kRItemsNarrow - 1) / (kBlock * kRItemsNarrow);
   Ws w;
   char* p = (char*)base;
   size_t off = 0;
@@ -462,7 +469,9 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
   const int width = (nbits + passes - 1) / passes;
   uint32_t* final_keys = ((passes - 1) % 2 == 0) ? kb : ka;
   if (n <= 0) return final_keys;
-  const int64_t nb = (n + kRPerBlock - 1) / kRPerBlock;
+  const int items = radix_items(width);
+  const int64_t nb = (n + kBlock * items - 1) / (kBlock * items);
+  const dim3 grid((unsigned)(8 * ((nb + 7) / 8)));
   for (int p = 0; p < passes; ++p) {
     const int shift = width * p;
     const int bits = (nbits - shift) < width ? (nbits - shift) : width;
@@ -470,11 +479,20 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
     uint32_t* iv = (p % 2 == 0) ? va : vb;
     uint32_t* okk = (p % 2 == 0) ? kb : ka;
     uint32_t* ovv = (p == passes - 1) ? out_v : ((p % 2 == 0) ? vb : va);
-    SSS_LAUNCH("radix_hist", radix_hist_kernel, dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(kBlock), 0, st, ik, n, base_key, cap, shift,
-                       (uint32_t)((1u << bits) - 1u), nb, w.hist);
+    const uint32_t mask = (1u << bits) - 1u;
+    if (items == kRItemsNarrow)
+      SSS_LAUNCH("radix_hist", radix_hist_kernel<kRItemsNarrow>, grid, dim3(kBlock), 0, st, ik, n, base_key, cap, shift,
+                 mask, nb, w.hist);
+    else
+      SSS_LAUNCH("radix_hist", radix_hist_kernel<kRItemsWide>, grid, dim3(kBlock), 0, st, ik, n, base_key, cap, shift,
+                 mask, nb, w.hist);
     scan_excl(w.hist, w.hist, ((int64_t)1 << bits) * nb, w.scan, st);
-    SSS_LAUNCH("radix_scatter", radix_scatter_kernel, dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(kBlock), 0, st, ik, iv, n, base_key,
-                       cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv);
+    if (items == kRItemsNarrow)
+      SSS_LAUNCH("radix_scatter", radix_scatter_kernel<kRItemsNarrow>, grid, dim3(kBlock), 0, st, ik, iv, n, base_key,
+                 cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv);
+    else
+      SSS_LAUNCH("radix_scatter", radix_scatter_kernel<kRItemsWide>, grid, dim3(kBlock), 0, st, ik, iv, n, base_key,
+                 cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv);
   }
   return final_keys;
 }
