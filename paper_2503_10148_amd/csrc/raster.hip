@@ -48,6 +48,43 @@ struct __align__(16) LRec {
   uint32_t slot;             // deterministic backward: the pair's emission position
 };
 
+// Forward-only LDS record (64 bytes): the colour is converted to FP64 once
+// when staged rather than per pixel in the compositing loop.
+struct __align__(16) FRec {
+  float mx, my, qa, qb;
+  float qc, hs, o, inv_nu;
+  float nb;
+  uint32_t smask;
+  double cr, cg, cb;
+};
+
+// Stages one forward-only record in LDS; returns its strip mask (the same
+// fields and strip test as the general record below).
+__device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, double ox, double oy,
+                                          FRec* dst, uint32_t* entry) {
+  const Rec r = srec[rank];
+  FRec l;
+  l.mx = (float)(r.mx - ox);
+  l.my = (float)(r.my - oy);
+  l.qa = r.qa; l.qb = r.qb; l.qc = r.qc;
+  l.hs = r.hs * 1.0001f;
+  l.o = r.o;
+  l.inv_nu = r.inv_nu;
+  l.nb = r.nb;
+  l.cr = (double)r.cr; l.cg = (double)r.cg; l.cb = (double)r.cb;
+  const float ey = r.ey * 1.0001f + 1e-3f;
+  uint32_t m = 0;
+#pragma unroll
+  for (int st = 0; st < kTile / 4; ++st) {
+    const float y0 = (float)(4 * st) + 0.5f;
+    if (l.my + ey >= y0 && l.my - ey <= y0 + 3.0f) m |= 1u << st;
+  }
+  l.smask = m;
+  *dst = l;
+  *entry = r.entry;
+  return m;
+}
+
 // Stages one record in LDS; returns its strip mask and the entry.
 __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, double ox, double oy,
                                           LRec* dst, uint32_t* entry) {
@@ -89,8 +126,8 @@ struct Eval {
 // kGauss: the Gaussian family (every record has inv_nu = 0 and
 // nb = -log2(e)/2); the kernels are instantiated per family, which the
 // caller's options select for the whole call.
-template <bool kGauss>
-__device__ __forceinline__ void evaluate(float px, float py, const LRec& L, float amin, float amax, Eval& E) {
+template <bool kGauss, typename R>
+__device__ __forceinline__ void evaluate(float px, float py, const R& L, float amin, float amax, Eval& E) {
   E.dx = px - L.mx;
   E.dy = py - L.my;
   E.ax = __fmaf_rn(L.qb, E.dy, L.qa * E.dx);
@@ -291,10 +328,10 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // A batch is one staged record per thread.  Returns the wave's set of
 // staged records whose strip mask meets `strips` (bit j: record j), so the
 // walk visits those records only.
-template <int PIX>
+template <int PIX, typename R>
 __device__ __forceinline__ uint64_t stage_batch(const TileCtx<PIX>& t, const Rec* __restrict__ srec,
                                                 const uint32_t* __restrict__ pair_rank, uint32_t base, uint32_t stop,
-                                                LRec* lds, uint32_t strips) {
+                                                R* lds, uint32_t strips) {
   const uint32_t k = base + threadIdx.x;
   uint32_t m = 0, e;
   if (k < stop) m = stage(srec, pair_rank[k], t.ox, t.oy, lds + threadIdx.x, &e);
@@ -338,9 +375,9 @@ __device__ __forceinline__ uint64_t stage_batch_slot(const TileCtx<PIX>& t, cons
 // composited: straight-line code with selects (the forward kernel: 3% faster)
 // or branches on hit and termination (the recompute phase, where the selects
 // measured 1-2% slower next to the backward body's registers).
-template <int PIX, bool kGauss, bool kSelect>
+template <int PIX, bool kGauss, bool kSelect, typename R>
 __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDev& op, const Rec* __restrict__ srec,
-                                             const uint32_t* __restrict__ pair_rank, LRec* lds, float (*C)[3],
+                                             const uint32_t* __restrict__ pair_rank, R* lds, float (*C)[3],
                                              float* Tout, uint32_t* last_out) {
   // The colour sums are kept in FP64: the backward pass subtracts the colour
   // accumulated up to a component from the output, and for components deep
@@ -366,7 +403,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
     for (int k = 0; k < PIX; ++k) alive |= T[k] > 0.0f;
     if (__syncthreads_count(alive) == 0) break;
     // records that miss every strip of this unit are never visited
-    uint64_t hits = stage_batch<PIX>(t, srec, pair_rank, base, t.end, lds, ws.all);
+    uint64_t hits = stage_batch<PIX, R>(t, srec, pair_rank, base, t.end, lds, ws.all);
     __syncthreads();
     // Finished pixels are masked off; whether the whole wave is finished is
     // asked every 8 visited records only (a per-record test cost more than
@@ -375,7 +412,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
     while (hits) {
       const int j = (int)__builtin_ctzll(hits);
       hits &= hits - 1;
-      const LRec L = lds[j];
+      const R L = lds[j];
       const uint32_t sm = PIX > 1 ? __builtin_amdgcn_readfirstlane(L.smask) : ws.all;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
@@ -445,7 +482,7 @@ __global__ __launch_bounds__(kUnitThreads) void render_fwd_kernel(CamBatch cb, O
                                                                   uint32_t* __restrict__ n_contrib,
                                                                   const uint32_t* __restrict__ tile_order,
                                                                   uint32_t* __restrict__ tile_work) {
-  __shared__ LRec lds[kUnitThreads];
+  __shared__ FRec lds[kUnitThreads];
   const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, tile_order, false);
   if (t.skip) return;
   float C[PIX][3], T[PIX];
@@ -571,7 +608,7 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
   for (uint32_t base = t.start; base < stop; base += kBatch) {
     __syncthreads();
     uint64_t hits = kDet ? stage_batch_slot<PIX>(t, srec, pair_rank, det, base, stop, lds, ws.all)
-                         : stage_batch<PIX>(t, srec, pair_rank, base, stop, lds, ws.all);
+                         : stage_batch<PIX, LRec>(t, srec, pair_rank, base, stop, lds, ws.all);
     __syncthreads();
     while (hits) {
       const int j = (int)__builtin_ctzll(hits);
