@@ -177,7 +177,7 @@ template <int kRItems>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, uint32_t base_key, uint32_t cap,
     int shift, int bits, int64_t nblocks, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ okeys,
-    uint32_t* __restrict__ ovals) {
+    uint32_t* __restrict__ ovals, const uint32_t* __restrict__ gsrc, int64_t gn, uint32_t* __restrict__ gout) {
   __shared__ uint32_t cnt[4][256];
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t dofs[256];
@@ -252,18 +252,15 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     const uint32_t p = gbase[d] + ((uint32_t)i - dofs[d]);
     okeys[p] = k;
     ovals[p] = sv[i];
+    // optional gather by the output value for the first gn positions (the
+    // depth sort's last pass: the visible entries' tile counts in rank order)
+    if (gsrc && (int64_t)p < gn) gout[p] = gsrc[sv[i]];
   }
 }
 
 // ---------------------------------------------------------------------------
 // 3. emission
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void touched_by_rank_kernel(const uint32_t* __restrict__ order,
-                                                                 const uint32_t* __restrict__ touched,
-                                                                 int64_t n_vis, uint32_t* __restrict__ out) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (r < n_vis) out[r] = touched[order[r]];
-}
 
 __device__ __forceinline__ uint32_t off_next(const uint32_t* __restrict__ off, int64_t r, int64_t n_vis,
                                               uint32_t total) {
@@ -460,8 +457,10 @@ Ws carve(void* base, int64_t n_entries, int64_t pair_cap) {
 // (ka, va); keys ping-pong between ka and kb, values between va and vb, and
 // the last pass writes the values to out_v.  Returns the buffer holding the
 // sorted keys (never the last pass's input).
+// With gsrc, the last pass also writes gout[p] = gsrc[out_v[p]] for p < gn.
 uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int nbits,
-                     uint32_t* out_v, Ws& w, hipStream_t st, uint32_t base_key = 0u, uint32_t cap = 0xFFFFFFFFu) {
+                     uint32_t* out_v, Ws& w, hipStream_t st, uint32_t base_key = 0u, uint32_t cap = 0xFFFFFFFFu,
+                     const uint32_t* gsrc = nullptr, int64_t gn = 0, uint32_t* gout = nullptr) {
   // as few passes of at most 8 bits as possible, with the bits spread evenly
   // (e.g. 13 bits as 7 + 6): wider runs per digit and block make the
   // scatter's stores longer
@@ -479,6 +478,7 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
     uint32_t* iv = (p % 2 == 0) ? va : vb;
     uint32_t* okk = (p % 2 == 0) ? kb : ka;
     uint32_t* ovv = (p == passes - 1) ? out_v : ((p % 2 == 0) ? vb : va);
+    const uint32_t* gs = (p == passes - 1) ? gsrc : nullptr;
     const uint32_t mask = (1u << bits) - 1u;
     if (items == kRItemsNarrow)
       SSS_LAUNCH("radix_hist", radix_hist_kernel<kRItemsNarrow>, grid, dim3(kBlock), 0, st, ik, n, base_key, cap, shift,
@@ -489,10 +489,10 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
     scan_excl(w.hist, w.hist, ((int64_t)1 << bits) * nb, w.scan, st);
     if (items == kRItemsNarrow)
       SSS_LAUNCH("radix_scatter", radix_scatter_kernel<kRItemsNarrow>, grid, dim3(kBlock), 0, st, ik, iv, n, base_key,
-                 cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv);
+                 cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv, gs, gn, gout);
     else
       SSS_LAUNCH("radix_scatter", radix_scatter_kernel<kRItemsWide>, grid, dim3(kBlock), 0, st, ik, iv, n, base_key,
-                 cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv);
+                 cap, shift, bits, nb, (const uint32_t*)w.hist, okk, ovv, gs, gn, gout);
   }
   return final_keys;
 }
@@ -542,13 +542,13 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
   if (n_vis > 0) {
     const uint32_t kmin = (uint32_t)counts[2], range = (uint32_t)counts[3] - kmin;
     const uint32_t cap = range == 0xFFFFFFFFu ? range : range + 1u;
-    radix_sort(w.ka, w.va, w.kb, w.vb, n_entries, bits_for((int64_t)cap + 1), bins->order, w, st, kmin, cap);
+    // the last pass also gathers each visible rank's tile count
+    radix_sort(w.ka, w.va, w.kb, w.vb, n_entries, bits_for((int64_t)cap + 1), bins->order, w, st, kmin, cap,
+               proj.tiles_touched, n_vis, w.flags);
   }
   // 3. pair offsets in rank order, emission, record gather
   if (n_vis > 0) {
     const unsigned gv = (unsigned)((n_vis + kBlock - 1) / kBlock);
-    SSS_LAUNCH("touched_by_rank", touched_by_rank_kernel, dim3(gv), dim3(kBlock), 0, st, bins->order, proj.tiles_touched,
-                       n_vis, w.flags);
     // the caller may keep the offsets (deterministic backward pass)
     uint32_t* offs = bins->rank_offset ? bins->rank_offset : w.pos;
     scan_excl(w.flags, offs, n_vis, w.scan, st);
