@@ -691,3 +691,50 @@ def test_tile_schedule_changes_no_result(sss):
     work = np.zeros(4 * T, np.int64)
     np.maximum.at(work, strip, ncon)
     assert np.array_equal(bins.tile_work.cpu().numpy().astype(np.int64).reshape(-1), work)
+
+
+def test_bin_sort_large_pair_count(sss):
+    """About 7e7 pairs (3 views of 1920x1080, whole-view rectangles): the
+    pair sort's offset scans exceed one level of block sums and its passes
+    run ~18000 workgroups.  Every tile of a view must list exactly the ranks
+    of that view's visible entries, ascending; checked on the device."""
+    rng = np.random.default_rng(202)
+    cams = [scenes.ring_camera(1920, 1080, angle=a) for a in (0.0, 1.0, 2.0)]
+    n = 4000
+    V = len(cams)
+    E = n * V
+    tiles = [oracle.tiles(c) for c in cams]
+    vis = rng.uniform(size=E) >= 0.25
+    rect = np.zeros((E, 4), np.int16)
+    touched = np.zeros(E, np.int32)
+    for v, (tx, ty) in enumerate(tiles):
+        sl = slice(v * n, (v + 1) * n)
+        rect[sl] = (0, 0, tx - 1, ty - 1)
+        touched[sl] = np.where(vis[sl], tx * ty, 0)
+    keys = (0x3F800000 + rng.integers(0, 5000, E)).astype(np.uint32)
+    records = rng.integers(0, 256, (E, 64), dtype=np.uint8)
+    ell = np.tile(np.array([1.0, 0.0, 1.0, np.inf]), (E, 1))
+    proj = sss.Projected(torch.as_tensor(records, device="cuda"), torch.as_tensor(keys.view(np.int32), device="cuda"),
+                         torch.as_tensor(rect, device="cuda"), torch.as_tensor(touched, device="cuda"),
+                         torch.as_tensor(ell, device="cuda"))
+    bins = sss.BinSorter(int(touched.sum()))(proj, cams, n)
+    torch.cuda.synchronize()
+    vi = np.nonzero(vis)[0]
+    assert bins.n_visible == len(vi) and bins.n_pairs == int(touched.sum())
+    assert bins.n_pairs > 6.7e7
+    order = bins.order[: bins.n_visible].to(torch.int64)
+    want = vi[np.lexsort((vi, keys[vi]))]
+    assert np.array_equal(order.cpu().numpy(), want)
+    start = bins.tile_start.to(torch.int64)
+    pr = bins.pair_rank[: bins.n_pairs].to(torch.int64)
+    ranks = torch.arange(bins.n_visible, device="cuda")
+    toff = 0
+    for v, (tx, ty) in enumerate(tiles):
+        T = tx * ty
+        rv = ranks[(order // n) == v]                       # this view's ranks, ascending
+        s = start[toff:toff + T + 1]
+        assert torch.equal(s[1:] - s[:-1], torch.full((T,), rv.numel(), device="cuda", dtype=torch.int64))
+        seg = pr[int(s[0]):int(s[-1])].view(T, rv.numel())
+        assert torch.equal(seg, rv.unsqueeze(0).expand(T, -1)), v
+        toff += T
+    assert int(start[toff]) == bins.n_pairs
