@@ -89,6 +89,11 @@ struct AdamBatch {
   int32_t n;
 };
 
+// Elements per thread in the Adam kernel, 256 apart (each round of loads
+// coalesced), all loaded before any is updated: 2-3% faster than one per
+// thread; eight measured 13% slower.
+constexpr int kAdamIt = 4;
+
 __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float lo, float hi, float b1,
                                          float b2, float omb1, float omb2, float eps, float c1, float c2) {
   m = b1 * m + omb1 * g;
@@ -103,20 +108,33 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(AdamBatch ab, float b1, fl
   for (int k = 1; k < ab.n; ++k)
     if (blockIdx.x >= ab.first_block[k]) a = k;
   a = __builtin_amdgcn_readfirstlane(a);
-  const int64_t i = (int64_t)(blockIdx.x - ab.first_block[a]) * kBlock + threadIdx.x;
-  if (i >= ab.count[a]) return;
+  const int64_t i0 = (int64_t)(blockIdx.x - ab.first_block[a]) * (kBlock * kAdamIt) + threadIdx.x;
+  const int64_t cnt = ab.count[a];
   float* __restrict__ p = ab.p[a];
   float* __restrict__ m = ab.m[a];
   float* __restrict__ v = ab.v[a];
+  const float* __restrict__ g = ab.g[a];
   // every element is touched once per step: streaming (non-temporal) loads
   // and stores keep the caches out of the way (measured 6% faster)
-  float pi = __builtin_nontemporal_load(p + i), mi = __builtin_nontemporal_load(m + i);
-  float vi = __builtin_nontemporal_load(v + i);
-  adam_one(pi, __builtin_nontemporal_load(ab.g[a] + i), mi, vi, ab.lr[a], ab.lo[a], ab.hi[a], b1, b2, omb1, omb2, eps,
-           c1, c2);
-  __builtin_nontemporal_store(pi, p + i);
-  __builtin_nontemporal_store(mi, m + i);
-  __builtin_nontemporal_store(vi, v + i);
+  float pi[kAdamIt], mi[kAdamIt], vi[kAdamIt], gi[kAdamIt];
+#pragma unroll
+  for (int k = 0; k < kAdamIt; ++k) {
+    const int64_t i = i0 + (int64_t)k * kBlock;
+    if (i < cnt) {
+      pi[k] = __builtin_nontemporal_load(p + i); mi[k] = __builtin_nontemporal_load(m + i);
+      vi[k] = __builtin_nontemporal_load(v + i); gi[k] = __builtin_nontemporal_load(g + i);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kAdamIt; ++k) {
+    const int64_t i = i0 + (int64_t)k * kBlock;
+    if (i < cnt) {
+      adam_one(pi[k], gi[k], mi[k], vi[k], ab.lr[a], ab.lo[a], ab.hi[a], b1, b2, omb1, omb2, eps, c1, c2);
+      __builtin_nontemporal_store(pi[k], p + i);
+      __builtin_nontemporal_store(mi[k], m + i);
+      __builtin_nontemporal_store(vi[k], v + i);
+    }
+  }
 }
 
 // Regularisers of the Sec. 3.4 loss: eps_o sum_i |o_i| + eps_s sum_ij sqrt(lambda_ij)
@@ -177,7 +195,7 @@ void launch_adam(const sss_adam_t& ad, hipStream_t st) {
     ab.p[k] = x.param; ab.g[k] = x.grad; ab.m[k] = x.m; ab.v[k] = x.v;
     ab.lr[k] = x.lr; ab.lo[k] = x.lo; ab.hi[k] = x.hi;
     ab.count[k] = x.count;
-    ab.first_block[k + 1] = ab.first_block[k] + (uint32_t)((x.count + kBlock - 1) / kBlock);
+    ab.first_block[k + 1] = ab.first_block[k] + (uint32_t)((x.count + kBlock * kAdamIt - 1) / (kBlock * kAdamIt));
     ++k;
   }
   ab.n = k;
