@@ -81,12 +81,23 @@ __global__ __launch_bounds__(kBlock) void stat_reduce_kernel(const BlockStat* __
                                                              unsigned long long* __restrict__ counters) {
   __shared__ BlockStat red[kBlock];
   BlockStat b{0ull, 0u, 0xFFFFFFFFu, 0u, 0u};
-  for (int64_t i = threadIdx.x; i < nb; i += kBlock) {
-    const BlockStat s = stats[i];
-    b.pairs += s.pairs;
-    b.visible += s.visible;
-    b.kmin = min(b.kmin, s.kmin);
-    b.kmax = max(b.kmax, s.kmax);
+  // rounds of 8 statistics per thread, loaded before any is combined, so a
+  // round waits for one memory latency (the host waits on this kernel)
+  constexpr int kRound = 8;
+  for (int64_t i0 = threadIdx.x; i0 < nb; i0 += (int64_t)kRound * kBlock) {
+    BlockStat s[kRound];
+#pragma unroll
+    for (int j = 0; j < kRound; ++j) {
+      const int64_t i = i0 + (int64_t)j * kBlock;
+      s[j] = i < nb ? stats[i] : BlockStat{0ull, 0u, 0xFFFFFFFFu, 0u, 0u};
+    }
+#pragma unroll
+    for (int j = 0; j < kRound; ++j) {
+      b.pairs += s[j].pairs;
+      b.visible += s[j].visible;
+      b.kmin = min(b.kmin, s[j].kmin);
+      b.kmax = max(b.kmax, s[j].kmax);
+    }
   }
   red[threadIdx.x] = b;
   __syncthreads();
