@@ -41,21 +41,40 @@ struct BlockStat {
   uint32_t visible, kmin, kmax, pad;
 };
 
+constexpr int kPrepItems = 4;
+
 __global__ __launch_bounds__(kBlock) void prepare_kernel(const uint32_t* __restrict__ touched,
                                                          const uint32_t* __restrict__ keys, int64_t n,
                                                          uint32_t* __restrict__ out_keys,
                                                          uint32_t* __restrict__ out_vals,
                                                          BlockStat* __restrict__ stats) {
   __shared__ BlockStat red[kBlock / 64];
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint32_t t = j < n ? touched[j] : 0u;
-  const uint32_t k = j < n ? keys[j] : 0u;
-  if (j < n) {
-    out_keys[j] = t > 0 ? k : 0xFFFFFFFFu;
-    out_vals[j] = (uint32_t)j;
+  // kPrepItems entries per thread, kBlock apart, loaded before use; one
+  // statistics record per block of kPrepItems * kBlock entries
+  const int64_t j0 = (int64_t)blockIdx.x * (kBlock * kPrepItems) + threadIdx.x;
+  uint32_t t[kPrepItems], k[kPrepItems];
+#pragma unroll
+  for (int q = 0; q < kPrepItems; ++q) {
+    const int64_t j = j0 + (int64_t)q * kBlock;
+    t[q] = j < n ? touched[j] : 0u;
+    k[q] = j < n ? keys[j] : 0u;
   }
-  unsigned long long pairs = t;
-  uint32_t vis = t > 0 ? 1u : 0u, lo = t > 0 ? k : 0xFFFFFFFFu, hi = t > 0 ? k : 0u;
+  unsigned long long pairs = 0;
+  uint32_t vis = 0, lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+  for (int q = 0; q < kPrepItems; ++q) {
+    const int64_t j = j0 + (int64_t)q * kBlock;
+    if (j < n) {
+      out_keys[j] = t[q] > 0 ? k[q] : 0xFFFFFFFFu;
+      out_vals[j] = (uint32_t)j;
+    }
+    pairs += t[q];
+    if (t[q] > 0) {
+      vis += 1u;
+      lo = min(lo, k[q]);
+      hi = max(hi, k[q]);
+    }
+  }
   for (int d = 32; d > 0; d >>= 1) {
     pairs += __shfl_xor(pairs, d, 64);
     vis += __shfl_xor(vis, d, 64);
@@ -528,7 +547,7 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
     set_error("sss_bin_sort: workspace of %zu bytes, %zu needed", ws_bytes, w.bytes);
     return SSS_ERR_INVALID;
   }
-  const unsigned g1 = (unsigned)((n_entries + kBlock - 1) / kBlock);
+  const unsigned g1 = (unsigned)((n_entries + kBlock * kPrepItems - 1) / (kBlock * kPrepItems));
   SSS_LAUNCH("prepare", prepare_kernel, dim3(g1), dim3(kBlock), 0, st, proj.tiles_touched, proj.depth_key, n_entries,
              w.ka, w.va, w.stats);
   SSS_LAUNCH("stat_reduce", stat_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const BlockStat*)w.stats, (int64_t)g1,
