@@ -185,8 +185,9 @@ def project(scene, cam, opts=None):
 
 def bin_tiles(touched, rect, key, tiles_x, tiles_y, proj=None):
     """Per-tile component lists in ascending (depth key, index) order.  With
-    `proj` (a projection result) every rectangle row is cut to the ellipse;
-    without it whole rectangles are listed."""
+    `proj` (a projection result) a tile of a component's rectangle is listed
+    when its box of pixel centres meets the component's ellipse; without it
+    whole rectangles are listed."""
     lib = _load()
     touched = np.ascontiguousarray(touched, dtype=np.int32)
     rect = np.ascontiguousarray(rect, dtype=np.int32)
@@ -196,7 +197,7 @@ def bin_tiles(touched, rect, key, tiles_x, tiles_y, proj=None):
     start = np.zeros(tiles_x * tiles_y + 1, np.int32)
     lst = np.zeros(max(m, 1), np.int32)
     geo = (None, None, None) if proj is None else tuple(
-        np.ascontiguousarray(proj[k], dtype=np.float64) for k in ("mean2d", "cov2d", "hrect"))
+        np.ascontiguousarray(proj[k], dtype=np.float64) for k in ("mean2d", "conic", "hrect"))
     got = lib.orc_bin(ctypes.c_int(n), _p(touched), _p(rect), _p(key), *(None if g is None else _p(g) for g in geo),
                       ctypes.c_int(tiles_x), ctypes.c_int(tiles_y), _p(start), _p(lst), ctypes.c_int64(max(m, 1)))
     assert got == m, (got, m)

@@ -224,50 +224,44 @@ static uint32_t depth_key32(const double* cam, const double* mu, float* zf_out) 
   return bits;
 }
 
-/* Tile columns of tile row ty met by the ellipse {d : d^T Sigma2D^-1 d <= hr}
- * around (mx, my), Sigma2D = [[A, B], [B, D]], sampled at pixel centres: the
- * ellipse's x-extent over the band of pixel-centre rows
- * [16 ty + 1/2, 16 ty + 31/2] (a convex set, so an interval), mapped to the
- * tiles whose pixel-centre columns [16 tx + 1/2, 16 tx + 31/2] it reaches and
- * clipped to [x0, x1].  On the chord at height dy the ellipse spans
- * dx = (B/D) dy +- sqrt((A - B^2/D)(hr - dy^2/D)) (Schur complement), whose
- * right end is largest at dy = B sqrt(hr/A) (the ellipse's rightmost point)
- * and left end smallest at the opposite point; over a band the extremes are
- * these points clamped into it.  The per-component constants are formed once
- * (1/D as a reciprocal); the kernels use the same operations in the same
- * order, so both sides list the same tiles.  Returns the number of tiles;
- * sets *edge when a tile decision lies within 1e-9 of its threshold. */
-typedef struct { double mx, my, k, S, ds, ey, iD, hr; int inf; } row_geo;
-
-static row_geo make_row_geo(double mx, double my, double A, double B, double D, double hr) {
-  row_geo g;
-  g.mx = mx; g.my = my; g.hr = hr;
-  g.inf = isinf(hr) ? 1 : 0;
-  g.iD = 1.0 / D;
-  g.k = B * g.iD;
-  g.S = A - B * g.k;
-  g.ds = B * sqrt(hr / A);
-  g.ey = sqrt(hr * D);
-  return g;
+/* Tile membership, by definition: a component is listed in tile (tx, ty)
+ * when some point of the tile's box of pixel centres
+ * [16 tx + 1/2, 16 tx + 31/2] x [16 ty + 1/2, 16 ty + 31/2] lies in its
+ * ellipse {p : (p - m)^T Q (p - m) <= hr}, Q the conic (inverse 2D
+ * covariance), i.e. when the minimum of the quadratic form over the box is
+ * at most hr.  The minimum is 0 when the mean lies in the box; otherwise it
+ * sits on the boundary, and along each edge the form is a one-dimensional
+ * quadratic whose minimum is its vertex clamped to the edge.  hr = infinity
+ * (no cut-off) lists every tile. */
+static double box_min_h(const double* Q, double mx, double my, double bx0, double bx1, double by0, double by1) {
+  const double a = Q[0], b = Q[1], c = Q[2];
+  if (mx >= bx0 && mx <= bx1 && my >= by0 && my <= by1) return 0.0;
+  double best = INFINITY;
+  const double xs[2] = {bx0, bx1}, ys[2] = {by0, by1};
+  for (int e = 0; e < 2; ++e) {
+    /* vertical edge x = xs[e]: minimise over dy */
+    const double dx = xs[e] - mx;
+    const double dy = fmin(fmax(-b * dx / c, by0 - my), by1 - my);
+    best = fmin(best, a * dx * dx + 2.0 * b * dx * dy + c * dy * dy);
+  }
+  for (int e = 0; e < 2; ++e) {
+    /* horizontal edge y = ys[e]: minimise over dx */
+    const double dy = ys[e] - my;
+    const double dx = fmin(fmax(-b * dy / a, bx0 - mx), bx1 - mx);
+    best = fmin(best, a * dx * dx + 2.0 * b * dx * dy + c * dy * dy);
+  }
+  return best;
 }
 
-static int row_run(const row_geo* g, int ty, int x0, int x1, int* t0, int* t1, int* edge) {
-  *t0 = x0; *t1 = x0 - 1;
-  if (g->inf) { *t1 = x1; return x1 - x0 + 1; }
-  const double y0 = 16.0 * ty + 0.5 - g->my, y1 = 16.0 * ty + 15.5 - g->my;
-  const double lo = fmax(y0, -g->ey), hi = fmin(y1, g->ey);
-  if (fabs(lo - hi) <= 1e-9 * fmax(1.0, fabs(lo))) *edge = 1;
-  if (lo > hi) return 0;
-  const double dr = fmin(fmax(g->ds, lo), hi), dl = fmin(fmax(-g->ds, lo), hi);
-  const double wr = g->S * (g->hr - dr * dr * g->iD), wl = g->S * (g->hr - dl * dl * g->iD);
-  const double xr = g->mx + (g->k * dr + (wr > 0.0 ? sqrt(wr) : 0.0));
-  const double xl = g->mx + (g->k * dl - (wl > 0.0 ? sqrt(wl) : 0.0));
-  const double ul = (xl - 15.5) * 0.0625, ur = (xr - 0.5) * 0.0625;
-  if (near_integer(ul) || near_integer(ur)) *edge = 1;
-  const int a = (int)fmin(fmax(ceil(ul), (double)x0), (double)x1 + 1.0);
-  const int b = (int)fmax(fmin(floor(ur), (double)x1), (double)x0 - 1.0);
-  *t0 = a; *t1 = b;
-  return b >= a ? b - a + 1 : 0;
+/* Whether tile (tx, ty) is listed; sets *edge when the box minimum lies
+ * within 1e-9 (relative) of hr, where the FP32/FP64 rounding of another
+ * formulation of the same test could decide the other way. */
+static int tile_listed(const double* Q, double mx, double my, double hr, int tx, int ty, int* edge) {
+  if (isinf(hr)) return 1;
+  const double hmin = box_min_h(Q, mx, my, ORC_TILE * tx + 0.5, ORC_TILE * tx + 15.5, ORC_TILE * ty + 0.5,
+                                ORC_TILE * ty + 15.5);
+  if (fabs(hmin - hr) <= 1e-9 * hr) *edge = 1;
+  return hmin <= hr;
 }
 
 int orc_tiles_x(const double* cam) { return ((int)cam[16] + ORC_TILE - 1) / ORC_TILE; }
@@ -386,13 +380,11 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
       hs = hr = INFINITY;
       x0 = 0; x1 = tx_n - 1; y0 = 0; y1 = ty_n - 1;
     }
-    /* tiles: the rows of the rectangle, each cut to the ellipse's extent */
+    /* tiles: those of the rectangle whose pixel-centre box meets the ellipse */
     int count = 0, edge = 0;
-    const row_geo rg = make_row_geo(mx, my, A, B, D, hr);
-    for (int ty = y0; ty <= y1; ++ty) {
-      int a, b;
-      count += row_run(&rg, ty, x0, x1, &a, &b, &edge);
-    }
+    const double Qc[3] = {D / det, -B / det, A / det};
+    for (int ty = y0; ty <= y1; ++ty)
+      for (int tx = x0; tx <= x1; ++tx) count += tile_listed(Qc, mx, my, hr, tx, ty, &edge);
     if (edge) pflags[i] |= PF_RECT_EDGE;
     if (count == 0) continue;
 
@@ -413,7 +405,7 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
     valid[i] = 1;
     mean2d[2 * i] = mx; mean2d[2 * i + 1] = my;
     cov2d[3 * i] = A; cov2d[3 * i + 1] = B; cov2d[3 * i + 2] = D;
-    conic[3 * i] = D / det; conic[3 * i + 1] = -B / det; conic[3 * i + 2] = A / det;
+    conic[3 * i] = Qc[0]; conic[3 * i + 1] = Qc[1]; conic[3 * i + 2] = Qc[2];
     nu_c[i] = nuc;
     hstar[i] = hs;
     hrect[i] = hr;
@@ -437,12 +429,13 @@ static int pair_cmp(const void* pa, const void* pb) {
 }
 
 /* rect[4*i] = x0,y0,x1,y1 (inclusive tile range); touched[i] == 0 means not
- * listed.  With geometry (mean2d, cov2d, hrect non-NULL) each row of the
- * rectangle is cut to the ellipse (row_run), else the whole rectangle is
- * listed.  Writes tile_start[n_tiles+1] and tile_list[] (component indices).
- * Returns the number of pairs, or -(needed) when it exceeds list_cap. */
+ * listed.  With geometry (mean2d, conic, hrect non-NULL) a tile of the
+ * rectangle is listed when its pixel-centre box meets the ellipse
+ * (tile_listed), else the whole rectangle is listed.  Writes
+ * tile_start[n_tiles+1] and tile_list[] (component indices).  Returns the
+ * number of pairs, or -(needed) when it exceeds list_cap. */
 int64_t orc_bin(int n, const int32_t* touched, const int32_t* rect, const uint32_t* key,
-                const double* mean2d, const double* cov2d, const double* hrect,
+                const double* mean2d, const double* conic, const double* hrect,
                 int tiles_x, int tiles_y, int32_t* tile_start, int32_t* tile_list, int64_t list_cap) {
   int64_t m = 0;
   for (int i = 0; i < n; ++i) m += touched[i] > 0 ? touched[i] : 0;
@@ -452,14 +445,10 @@ int64_t orc_bin(int n, const int32_t* touched, const int32_t* rect, const uint32
   for (int i = 0; i < n; ++i) {
     if (touched[i] <= 0) continue;
     for (int ty = rect[4 * i + 1]; ty <= rect[4 * i + 3]; ++ty) {
-      int a = rect[4 * i], b = rect[4 * i + 2], edge = 0;
-      if (mean2d) {
-        const row_geo rg = make_row_geo(mean2d[2 * i], mean2d[2 * i + 1], cov2d[3 * i], cov2d[3 * i + 1],
-                                        cov2d[3 * i + 2], hrect[i]);
-        row_run(&rg, ty, rect[4 * i], rect[4 * i + 2], &a, &b, &edge);
-      }
-      for (int tx = a; tx <= b; ++tx) {
-        if (p == m) { free(pairs); return -(m + 1); }   /* touched does not match the rows */
+      for (int tx = rect[4 * i]; tx <= rect[4 * i + 2]; ++tx) {
+        int edge = 0;
+        if (mean2d && !tile_listed(conic + 3 * i, mean2d[2 * i], mean2d[2 * i + 1], hrect[i], tx, ty, &edge)) continue;
+        if (p == m) { free(pairs); return -(m + 1); }   /* touched does not match the tiles */
         pairs[p].tile = (int64_t)ty * tiles_x + tx;
         pairs[p].key = key[i];
         pairs[p].idx = i;

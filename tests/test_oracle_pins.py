@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 from scipy.spatial.transform import Rotation
 from scipy import stats
+from scipy.optimize import lsq_linear
 
 from paper_2503_10148_amd import scenes
 
@@ -282,28 +283,25 @@ def test_brute_force_equals_tiled(oracle_lib, seed, n, W, H, deg):
 
 
 def _box_min_h(conic, m, bx0, bx1, by0, by1):
-    """Minimum of d^T Q d over the box [bx0, bx1] x [by0, by1] (d = p - m): the
-    centre if inside, else the smallest of the four edge minima (on an edge the
-    form is a 1D quadratic, minimised at its vertex clamped to the edge)."""
+    """Minimum of d^T Q d over the box [bx0, bx1] x [by0, by1] (d = p - m), by
+    a bounded linear least-squares solve: with Q = L^T L (Cholesky),
+    d^T Q d = |L p - L m|^2, minimised over p in the box by scipy's
+    bounded-variable least squares (an active-set method, exact for two
+    variables up to rounding)."""
     a, b, c = conic
-    if bx0 <= m[0] <= bx1 and by0 <= m[1] <= by1:
-        return 0.0
-    best = np.inf
-    for x in (bx0, bx1):                       # vertical edges: minimise over y
-        dx = x - m[0]
-        dy = np.clip(-b * dx / c, by0 - m[1], by1 - m[1])
-        best = min(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
-    for y in (by0, by1):                       # horizontal edges: minimise over x
-        dy = y - m[1]
-        dx = np.clip(-b * dy / a, bx0 - m[0], bx1 - m[0])
-        best = min(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
-    return best
+    Lt = np.linalg.cholesky(np.array([[a, b], [b, c]]))       # Q = Lt Lt^T
+    L = Lt.T
+    res = lsq_linear(L, L @ np.asarray(m, np.float64), bounds=([bx0, by0], [bx1, by1]), method="bvls",
+                     tol=1e-14)
+    r = L @ res.x - L @ np.asarray(m, np.float64)
+    return float(r @ r)
 
 
 def test_tile_lists_are_ellipse_membership_in_depth_order(oracle_lib):
     """A component is listed in exactly the tiles of its rectangle whose box of
-    pixel centres meets its ellipse h <= h_rect (minimum of the quadratic form
-    over the box, computed edge by edge), in (depth key, index) order."""
+    pixel centres meets its ellipse h <= h_rect (the minimum of the quadratic
+    form over the box, found by a bounded least-squares solver), in
+    (depth key, index) order."""
     s = scenes.make_scene(800, 0, seed=41, neg_frac=0.2)
     s["scales"] *= np.float32(2.0)
     cam = scenes.ring_camera(200, 130, angle=1.0)
@@ -333,6 +331,46 @@ def test_tile_lists_are_ellipse_membership_in_depth_order(oracle_lib):
         got = lst[start[t]:start[t + 1]]
         assert np.array_equal([g for g in got if g not in unsure], [w for w in want if w not in unsure]), t
     assert int(p["touched"].sum()) == len(lst)
+    assert len(unsure) <= 2
+
+
+def test_tile_membership_by_dense_sampling(oracle_lib):
+    """Brute force on a fine grid: a tile whose pixel-centre box holds a
+    sampled point inside the ellipse is listed, and a listed tile has a
+    sampled point within a small margin of the ellipse (the grid spacing
+    bounds how far the true closest point can be)."""
+    s = scenes.make_scene(300, 0, seed=43, neg_frac=0.3)
+    s["scales"] *= np.float32(3.0)
+    cam = scenes.ring_camera(120, 90, angle=2.2)
+    p = oracle_lib.project(s, cam)
+    tx, ty = oracle_lib.tiles(cam)
+    start, lst = oracle_lib.bin_tiles(p["touched"], p["rect"], p["key"], tx, ty, proj=p)
+    listed = set()
+    for t in range(tx * ty):
+        for i in lst[start[t]:start[t + 1]]:
+            listed.add((int(i), t))
+    g = np.linspace(0.5, 15.5, 61)                          # 0.25 px spacing over the box
+    gx, gy = np.meshgrid(g, g)
+    checked = 0
+    for i in np.nonzero(p["touched"] > 0)[0]:
+        a, b, c = p["conic"][i]
+        hr = p["hrect"][i]
+        x0, y0, x1, y1 = p["rect"][i]
+        for y in range(y0, y1 + 1):
+            for x in range(x0, x1 + 1):
+                dx = 16 * x + gx - p["mean2d"][i, 0]
+                dy = 16 * y + gy - p["mean2d"][i, 1]
+                h = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+                # the form grows by at most |grad| * (spacing / sqrt 2) between samples
+                grad = 2 * np.sqrt((a * dx + b * dy) ** 2 + (b * dx + c * dy) ** 2)
+                slack = (grad * 0.25 / math.sqrt(2) + (abs(a) + abs(c) + 2 * abs(b)) * 0.0625).min()
+                is_listed = (int(i), y * tx + x) in listed
+                if h.min() <= hr:
+                    assert is_listed, (i, x, y)
+                elif is_listed:
+                    assert h.min() <= hr + slack + 1e-9 * hr, (i, x, y)
+                checked += 1
+    assert checked > 500
 
 
 def test_truncation_is_lossless(oracle_lib):
@@ -434,6 +472,157 @@ def test_backward_fd_low_nu_and_lowpass(oracle_lib):
     cams = [scenes.ring_camera(40, 36, angle=2.5)]
     checked = _fd_check(oracle_lib, s, cams, dict(lowpass=0.3), 10, 54, 1e-5)
     assert checked >= 40
+
+
+# ---------------------------------------------------------------------------
+# the alpha clamp and the nu clamp (readings: |alpha| clamped to 0.99 with no
+# gradient through a clamped alpha; nu clamped to [1, 1e4], gradient only
+# inside the closed interval)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("o", [0.999, -0.999])
+@pytest.mark.parametrize("nu", [1.0, 5.0, 1e4])
+def test_alpha_clamp_closed_form(oracle_lib, o, nu):
+    """A single on-axis isotropic component with |o| = 0.999: near its centre
+    |o T2D| > 0.99 and the image is the closed form with alpha clipped to
+    +-0.99 (T = 1 - alpha may reach 1.99 for the negative one)."""
+    cam = axis_camera(64, 64)
+    sc = 20.0 * 4.0 / cam["fx"]                      # sigma = 20 px
+    s = one_component(scale=(sc, sc, sc), nu=nu, opacity=o, colour=(0.8, 0.5, 0.3))
+    bg = (0.2, 0.1, 0.4)
+    f = oracle_lib.render(s, cam, dict(bg=bg))
+    sigma = cam["fx"] * np.float64(np.float32(sc)) / 4.0
+    of, nuf = np.float64(np.float32(o)), np.float64(np.float32(nu))
+    colour = np.float64(s["sh"][0, 0]) / (2 * math.sqrt(math.pi)) + 0.5
+    ref = _student_t_image(64, 64, cam["cx"], cam["cy"], sigma, nuf, of, colour,
+                           np.float64(np.asarray(bg, np.float32)), alpha_min=np.float32(1 / 255),
+                           alpha_max=np.float64(np.float32(0.99)))
+    np.testing.assert_allclose(f["image"], ref, rtol=0, atol=1e-12)
+    ys, xs = np.mgrid[0:64, 0:64]
+    h = ((xs + 0.5 - cam["cx"]) ** 2 + (ys + 0.5 - cam["cy"]) ** 2) / sigma ** 2
+    a = of * (1 + h / nuf) ** (-(nuf + 2) / 2)
+    assert (np.abs(a) > 0.99).sum() >= 4 and (np.abs(a) < 0.99).sum() > 1000     # both sides occur
+    unclamped = np.abs(a) < 0.99
+    assert np.allclose(f["tfinal"][~unclamped], 1 - np.sign(of) * np.float64(np.float32(0.99)), atol=1e-15)
+
+
+def _clamp_scene():
+    """Three on-axis components: two with |o| = 0.999 (one positive, one
+    negative, clamped near their centres), one ordinary in front."""
+    cam = axis_camera(48, 48)
+    sc = 12.0 * 4.0 / cam["fx"]
+    a = one_component(mu=(0.05, 0.02, 0.3), scale=(sc, sc * 0.8, sc), nu=4.0, opacity=0.999,
+                      colour=(0.9, 0.3, 0.6), quat=(0.9, 0.2, -0.1, 0.3))
+    b = one_component(mu=(-0.04, 0.03, -0.2), scale=(sc * 0.9, sc, sc), nu=30.0, opacity=-0.999,
+                      colour=(0.2, 0.7, 0.4), quat=(0.7, -0.3, 0.4, 0.1))
+    c = one_component(mu=(0.1, -0.1, 0.8), scale=(sc * 0.5, sc * 0.4, sc * 0.6), nu=2.0, opacity=0.4,
+                      colour=(0.5, 0.5, 0.1), quat=(0.5, 0.5, 0.5, 0.5))
+    s = {k: (np.concatenate([a[k], b[k], c[k]]) if k != "sh_degree" else 0) for k in a}
+    return s, cam
+
+
+def _clamped_pixels(oracle_lib, s, cam):
+    """Pixels where some composited alpha is clamped, and a margin-free mask
+    of pixels whose every |alpha| is far from 0.99."""
+    f = oracle_lib.render(s, cam, dict(alpha_min=0.0))
+    p = f["proj"]
+    H, W = cam["height"], cam["width"]
+    ys, xs = np.mgrid[0:H, 0:W]
+    clamped = np.zeros((H, W), bool)
+    near = np.zeros((H, W), bool)
+    for i in range(3):
+        a_, b_, c_ = p["conic"][i]
+        dx, dy = xs + 0.5 - p["mean2d"][i, 0], ys + 0.5 - p["mean2d"][i, 1]
+        hh = a_ * dx * dx + 2 * b_ * dx * dy + c_ * dy * dy
+        al = np.abs(p["opacity"][i] * (1 + hh / p["nu_c"][i]) ** (-(p["nu_c"][i] + 2) / 2))
+        clamped |= al > 0.99
+        near |= np.abs(al - 0.99) < 2e-3
+    return f, clamped, near
+
+
+def test_clamped_alpha_passes_no_gradient(oracle_lib):
+    """Loss weights only on pixels where an alpha is clamped: every
+    gradient but the colour's is zero analytically, and central finite
+    differences of the whole pipeline agree (a clamped alpha does not move
+    with o, the mean, the covariance or nu)."""
+    s, cam = _clamp_scene()
+    opts = dict(alpha_min=0.0)
+    f, clamped, near = _clamped_pixels(oracle_lib, s, cam)
+    assert clamped.sum() >= 8
+    w = np.zeros((cam["height"], cam["width"], 3))
+    w[clamped & ~near] = 1.0
+    g = oracle_lib.render_backward(s, cam, w, opts, fwd=f)
+    # at a weighted pixel one of the two |o| = 0.999 components is clamped
+    # and the others are not: analytic and FD gradients must agree there
+    s64 = {k: (np.asarray(v, np.float64).copy() if k != "sh_degree" else v) for k, v in s.items()}
+    moved = 0
+    for name in ("means", "scales", "quats", "nu", "opacity"):
+        flat = s64[name].reshape(-1)                         # a view: 3 components, `width` values each
+        gflat = g[name].reshape(-1)
+        width = flat.size // 3
+        for i in (0, 1):
+            for j in range(i * width, (i + 1) * width):
+                old = flat[j]
+                step = 1e-6 * max(1.0, abs(old))
+                flat[j] = old + step
+                lp = float((oracle_lib.render(s64, cam, opts)["image"] * w).sum())
+                flat[j] = old - step
+                lm = float((oracle_lib.render(s64, cam, opts)["image"] * w).sum())
+                flat[j] = old
+                fd = (lp - lm) / (2 * step)
+                assert gflat[j] == pytest.approx(fd, rel=1e-5, abs=1e-9), (name, i, j)
+                moved += fd != 0.0
+    # only the pixels where a component is not clamped move the loss
+    assert moved > 0
+    # the clamped components' colours still receive alpha T per pixel
+    assert np.abs(g["sh"][0]).max() > 1e-3 and np.abs(g["sh"][1]).max() > 1e-3
+
+
+def test_backward_fd_with_clamped_alphas(oracle_lib):
+    """Random loss weights over the whole image of a scene with clamped
+    alphas: analytic gradients match central finite differences."""
+    s, cam = _clamp_scene()
+    checked = _fd_check(oracle_lib, s, [cam], dict(bg=(0.1, 0.3, 0.2)), 30, 55, 1e-5)
+    assert checked >= 40                             # of the 45 parameters
+
+
+@pytest.mark.parametrize("raw_nu,clamped_to", [(0.5, 1.0), (0.7, 1.0), (2e4, 1e4), (1e6, 1e4)])
+def test_nu_outside_the_clamp_gets_no_gradient(oracle_lib, raw_nu, clamped_to):
+    """Raw nu outside [1, 1e4] renders as the clamp bound, and its gradient is
+    zero; finite differences of the pipeline agree (the image does not move
+    with nu there).  Inside the interval the gradient is the FD one."""
+    cam = axis_camera(40, 40)
+    sc = 6.0 * 4.0 / cam["fx"]
+    base = one_component(scale=(sc, sc * 1.3, sc), nu=raw_nu, opacity=0.6, colour=(0.7, 0.2, 0.5),
+                         quat=(0.8, 0.1, 0.3, -0.2))
+    at_bound = dict(base)
+    at_bound["nu"] = np.array([clamped_to], np.float32)
+    w = np.random.default_rng(7).standard_normal((40, 40, 3))
+    f = oracle_lib.render(base, cam)
+    assert np.array_equal(f["image"], oracle_lib.render(at_bound, cam)["image"])
+    g = oracle_lib.render_backward(base, cam, w, fwd=f)
+    assert g["nu"][0] == 0.0
+    assert g["g_nu"][0] != 0.0                       # the screen-space gradient exists; the gate stops it
+    s64 = {k: (np.asarray(v, np.float64).copy() if k != "sh_degree" else v) for k, v in base.items()}
+    nu0 = s64["nu"][0]
+    for step in (1e-3 * nu0, 1e-6 * nu0):
+        s64["nu"][0] = nu0 + step
+        lp = float((oracle_lib.render(s64, cam)["image"] * w).sum())
+        s64["nu"][0] = nu0 - step
+        lm = float((oracle_lib.render(s64, cam)["image"] * w).sum())
+        assert lp == lm
+    s64["nu"][0] = nu0
+    # inside the interval the gate is open: the analytic gradient is the FD one
+    inside = dict(base)
+    inside["nu"] = np.array([3.0 if clamped_to == 1.0 else 5e3], np.float32)
+    gi = oracle_lib.render_backward(inside, cam, w)
+    s64["nu"][0] = np.float64(inside["nu"][0])
+    step = 1e-6 * s64["nu"][0]
+    s64["nu"][0] += step
+    lp = float((oracle_lib.render(s64, cam)["image"] * w).sum())
+    s64["nu"][0] -= 2 * step
+    lm = float((oracle_lib.render(s64, cam)["image"] * w).sum())
+    assert gi["nu"][0] == pytest.approx((lp - lm) / (2 * step), rel=1e-5, abs=1e-12)
+    assert gi["nu"][0] != 0.0
 
 
 def test_printed_dnu_lacks_exponent_term():
