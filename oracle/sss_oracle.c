@@ -60,7 +60,8 @@ enum {
   PF_DET = 2,        /* projected covariance nearly singular                  */
   PF_RGB_CLAMP = 4,  /* an SH colour channel within 1e-9 of the clamp at 0    */
   PF_TX_CLAMP = 8,   /* x/z or y/z within 1e-9 of the EWA frustum clamp       */
-  PF_NU_CLAMP = 16,  /* nu within 1e-9 of a clamp bound                        */
+  PF_NU_CLAMP = 16,  /* unused: the clamp and its gradient gate compare the    */
+                     /* FP32 input itself, identically on both sides           */
 };
 enum {
   XF_ALPHA_MIN = 1,  /* some |alpha| within 1e-5 (relative) of alpha_min      */
@@ -351,7 +352,6 @@ void orc_project(int n, int sh_degree, const double* means, const double* scales
 
     const double mx = fx * xz + cx, my = fy * yz + cy;
     const double nuc = fmin(fmax(nu[i], nu_min), nu_max);
-    if (fabs(nu[i] - nu_min) <= 1e-9 * nu_min || fabs(nu[i] - nu_max) <= 1e-9 * nu_max) pflags[i] |= PF_NU_CLAMP;
 
     /* truncation: the alpha level set |o| T2D(h) = alpha_min, i.e.
        h* = nu ((|o|/alpha_min)^(2/(nu+2)) - 1); outside it |alpha| < alpha_min */

@@ -32,10 +32,13 @@ def _degree(sh: torch.Tensor) -> int:
 
 
 class _Ctx:
-    """Buffers reused across calls (pair list, workspaces)."""
+    """Workspaces reused across calls.  Each forward keeps a pair list of its
+    own (several renders may be alive before their backward passes run);
+    the sort and backward workspaces are shared, since every call uses them
+    only while it runs on the stream."""
 
     def __init__(self, deterministic: bool = False):
-        self.binner = sss.BinSorter(0, keep_offsets=deterministic)
+        self.binner = sss.BinSorter(0, keep_offsets=deterministic, own_pairs=True)
         self.deterministic = deterministic
         self.bwd_ws = None
 
@@ -55,10 +58,11 @@ class RenderFunction(torch.autograd.Function):
         image, _, n_contrib = sss.render_fwd(bins, cams, opts)
         ctx.scene = scene
         ctx.proj, ctx.bins, ctx.cams, ctx.opts, ctx.mode, ctx.state = proj, bins, cams, opts, mode, state
+        # stored mode reads the forward image and list positions back: saved
+        # through autograd, so an in-place change of the returned image is
+        # reported instead of silently corrupting the gradients
         if mode == "stored":
-            ctx.image, ctx.n_contrib = image, n_contrib
-        else:
-            ctx.image = ctx.n_contrib = None
+            ctx.save_for_backward(image, n_contrib)
         return image
 
     @staticmethod
@@ -73,10 +77,13 @@ class RenderFunction(torch.autograd.Function):
         if st.bwd_ws is None or st.bwd_ws.numel() * 4 < need:
             st.bwd_ws = torch.empty(need // 4, dtype=torch.float32, device=dl_dimage.device)
         mode = sss.BWD_STORED if ctx.mode == "stored" else sss.BWD_RECOMPUTE
+        image = n_contrib = None
+        if ctx.mode == "stored":
+            image, n_contrib = ctx.saved_tensors
         grads = sss.render_bwd(ctx.scene, ctx.proj, ctx.bins, ctx.cams, dl_dimage.contiguous().float(), ctx.opts,
-                               mode=mode, loss=sss.LOSS_GRAD, image=ctx.image, n_contrib=ctx.n_contrib,
+                               mode=mode, loss=sss.LOSS_GRAD, image=image, n_contrib=n_contrib,
                                ws=st.bwd_ws, deterministic=st.deterministic)
-        ctx.scene = ctx.proj = ctx.bins = ctx.image = ctx.n_contrib = None
+        ctx.scene = ctx.proj = ctx.bins = None
         return tuple(grads[k] for k in _PARAMS) + (None, None, None, None)
 
 

@@ -15,6 +15,14 @@ Each view is rendered independently inside a batch (its own tiles, ranks
 ordered by depth within the view), so a request's image is bit-identical
 alone and in any mix.
 
+Streams: a request's image is complete when its future resolves.  It may be
+read on the server's consumer stream (by default the stream that was
+current when the server was created, normally the default stream) with no
+further synchronisation: the server records that stream on the image's
+memory, so the memory is not reused by a later batch before the consumer
+stream's work queued up to the image's release has run.  To read an image
+on any other stream, call `image.record_stream(that_stream)` first.
+
 `PlainRenderer` is the baseline: one request per launch sequence, FIFO, one
 stream, same kernels.
 """
@@ -69,10 +77,13 @@ class _Slot:
 
 class RenderServer:
     def __init__(self, scene: dict, opts=None, max_batch: int = 16, mem_budget: int = 6 << 30,
-                 n_streams: int = 2, pairs_per_pixel: float = 20.0, device: int = 0, max_inflight: int | None = None):
+                 n_streams: int = 2, pairs_per_pixel: float = 20.0, device: int = 0, max_inflight: int | None = None,
+                 consumer_stream=None):
         """scene: dict of device tensors (see sss.scene_struct).  At most
         `max_inflight` batches (default: n_streams) are on the device at once;
-        requests arriving meanwhile wait and join the next batch."""
+        requests arriving meanwhile wait and join the next batch.
+        consumer_stream: the stream results are read on (default: the
+        current stream of `device` at construction)."""
         if not 1 <= max_batch <= sss.MAX_VIEWS:
             raise ValueError(f"max_batch must be in 1..{sss.MAX_VIEWS}")
         self.scene = scene
@@ -82,6 +93,7 @@ class RenderServer:
         self.max_inflight = n_streams if max_inflight is None else max(1, int(max_inflight))
         self.mem_budget = int(mem_budget)
         self.device = device
+        self.consumer = consumer_stream if consumer_stream is not None else torch.cuda.current_stream(device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         self._slots = [_Slot() for _ in range(n_streams)]
         self.pairs_per_pixel = float(pairs_per_pixel)   # running estimate, refined from every batch
@@ -223,6 +235,9 @@ class RenderServer:
             ev.synchronize()
             t = time.perf_counter()
             image = keep[2]
+            # the image was allocated on the batch's stream: tie its release
+            # to the consumer stream too (see the module notes on streams)
+            image.record_stream(self.consumer)
             off = 0
             for r in batch:
                 H, W = int(r.cam["height"]), int(r.cam["width"])

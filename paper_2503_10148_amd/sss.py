@@ -289,14 +289,22 @@ class BinSorter:
     (with 25% headroom) when a call reports SSS_ERR_CAPACITY.  With
     `schedule` (default), the Binned it creates carries the tile launch
     order and per-tile work arrays, so the raster kernels start the most
-    expensive tiles first."""
+    expensive tiles first.
 
-    def __init__(self, pair_capacity: int = 0, keep_offsets: bool = False, schedule: bool = True):
+    By default every Binned the sorter returns shares the sorter's one pair
+    list (the next call overwrites it), which suits a loop that consumes
+    each binning before the next.  With `own_pairs`, each call gets a pair
+    list of its own, so several binnings can be alive at once (renders
+    whose backward passes run later)."""
+
+    def __init__(self, pair_capacity: int = 0, keep_offsets: bool = False, schedule: bool = True,
+                 own_pairs: bool = False):
         self.cap = int(pair_capacity)
         self.ws = None
         self.pair_rank = None
         self.keep_offsets = keep_offsets
         self.schedule = schedule
+        self.own_pairs = own_pairs
 
     def __call__(self, proj: Projected, cams, n: int, stream=None, out: Binned | None = None) -> Binned:
         E = n * len(cams)
@@ -313,13 +321,19 @@ class BinSorter:
             out.rank_offset = torch.empty(E, dtype=torch.int32, device=dev)
         camarr = camera_array(cams)
         p = proj.struct()
+        pairs = None
         for _ in range(3):
-            if self.pair_rank is None or self.pair_rank.numel() < max(self.cap, 1):
-                self.pair_rank = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
-            need = int(lib().sss_bin_sort_workspace(E, self.pair_rank.numel()))
+            if self.own_pairs:
+                if pairs is None or pairs.numel() < max(self.cap, 1):
+                    pairs = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
+            else:
+                if self.pair_rank is None or self.pair_rank.numel() < max(self.cap, 1):
+                    self.pair_rank = torch.empty(max(self.cap, 1), dtype=torch.int32, device=dev)
+                pairs = self.pair_rank
+            need = int(lib().sss_bin_sort_workspace(E, pairs.numel()))
             if self.ws is None or self.ws.numel() < need:
                 self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
-            out.pair_rank = self.pair_rank
+            out.pair_rank = pairs
             b = out.struct()
             rc = lib().sss_bin_sort(ctypes.byref(p), camarr, len(cams), n, ctypes.byref(b), _ptr(self.ws),
                                     self.ws.numel(), _stream(stream))

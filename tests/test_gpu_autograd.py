@@ -164,3 +164,50 @@ def test_autograd_l1_through_torch_matches_oracle(mods):
         want = gref[k].reshape(skip.size, -1)[~skip]
         scale = np.sqrt(np.mean(gref[k] ** 2))
         assert np.all(np.abs(got - want) <= 1e-3 * np.maximum(np.abs(want), scale)), k
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_two_renders_before_one_backward(mods, mode):
+    """Two renders (the second with more tile pairs) and a no-grad render in
+    between, then one backward through a loss built from both: each render
+    keeps its own pair list, so the gradients equal the sum of the two
+    renders' separate backward passes (bit for bit with the deterministic
+    backward)."""
+    sss, ag = mods
+    s = scenes.make_scene(15000, 3, seed=23, neg_frac=0.3)
+    cams_a = [scenes.ring_camera(160, 120, angle=0.9)]
+    cams_b = [scenes.ring_camera(320, 240, angle=2.4), scenes.ring_camera(200, 150, angle=4.0)]
+    rng = np.random.default_rng(5)
+    wa = torch.as_tensor(rng.standard_normal((160 * 120, 3)), dtype=torch.float32, device="cuda")
+    wb = torch.as_tensor(rng.standard_normal((320 * 240 + 200 * 150, 3)), dtype=torch.float32, device="cuda")
+    args = lambda p: (p["means"], p["scales"], p["quats"], p["nu"], p["opacity"], p["sh"])
+
+    sep = {}
+    for name, cams, w in (("a", cams_a, wa), ("b", cams_b, wb)):
+        p = _leaf(s)
+        img = ag.render(*args(p), cams, mode=mode, deterministic=True)
+        (img * w).sum().backward()
+        sep[name] = {k: p[k].grad.detach().clone() for k in PARAMS}
+
+    p = _leaf(s)
+    img_a = ag.render(*args(p), cams_a, mode=mode, deterministic=True)
+    img_b = ag.render(*args(p), cams_b, mode=mode, deterministic=True)
+    with torch.no_grad():
+        ag.render(*args(p), [scenes.ring_camera(400, 300, angle=5.5)], mode=mode, deterministic=True)
+    ((img_a * wa).sum() + (img_b * wb).sum()).backward()
+    for k in PARAMS:
+        both = p[k].grad
+        assert torch.equal(both, sep["a"][k] + sep["b"][k]), k
+
+
+def test_in_place_change_of_the_image_is_reported(mods):
+    """The stored backward reads the forward image: changing it in place
+    before backward() raises instead of giving wrong gradients."""
+    sss, ag = mods
+    s = scenes.make_scene(2000, 0, seed=24)
+    cams = [scenes.ring_camera(64, 48, angle=0.2)]
+    p = _leaf(s)
+    img = ag.render(p["means"], p["scales"], p["quats"], p["nu"], p["opacity"], p["sh"], cams, mode="stored")
+    img.mul_(2.0)
+    with pytest.raises(RuntimeError):
+        img.sum().backward()

@@ -127,3 +127,27 @@ def test_served_image_matches_oracle(env):
         ref = oracle.render(scene_np, c)
         diff = np.abs(img - ref["image"]).max(axis=2)
         assert not ((diff > 1e-4) & (ref["xflags"] == 0)).any()
+
+
+def test_results_read_asynchronously_on_the_consumer_stream(env):
+    """Results are read on the consumer stream without a host wait and then
+    dropped while later batches run: every copy equals the plain render
+    (the server ties each image's release to the consumer stream)."""
+    serve, sss, _, scene = env
+    cams = _cams(24, seed=3)
+    plain = serve.PlainRenderer(scene)
+    alone = [plain.render(c).cpu().numpy() for c in cams]
+    srv = serve.RenderServer(scene, max_batch=4, mem_budget=2 << 30)
+    copies = []
+    futs = [srv.submit(c) for c in cams[:4]]
+    for k in range(len(cams)):
+        img = futs[k].result(timeout=60)
+        copies.append(img.mul(1.0))                      # queued on the consumer stream, no wait
+        del img
+        futs[k] = None
+        if k + 4 < len(cams):
+            futs.append(srv.submit(cams[k + 4]))
+    srv.close()
+    torch.cuda.synchronize()
+    for a, c in zip(alone, copies):
+        assert np.array_equal(a, c.cpu().numpy())
