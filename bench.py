@@ -61,14 +61,24 @@ def make_inputs(workload):
     return scene, cams, target
 
 
-def cpu_baseline(scene, cam, budget_px=128 * 128):
-    """The FP64 oracle on a bounded sample: full projection (+ its backward)
-    of every component and the raster fwd+bwd of a central window; the raster
-    time is scaled to the full frame."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_frame(scene, cam, side):
+    """Seconds of the FP64 oracle for one full-frame fwd+bwd, from the
+    projection (+ its backward) of every component and the raster fwd+bwd of
+    a central side x side window, scaled by pixel count."""
     import oracle
     from paper_2503_10148_amd import scenes
     W, H = cam["width"], cam["height"]
-    side = int(math.sqrt(budget_px))
     x0, y0 = (W - side) // 2 // 16 * 16, (H - side) // 2 // 16 * 16
     win = oracle.window_camera(cam, x0, y0, side, side)
     target = scenes.smooth_target(W, H)[y0:y0 + side, x0:x0 + side]
@@ -84,12 +94,31 @@ def cpu_baseline(scene, cam, budget_px=128 * 128):
     # count it with the projection, estimated as the forward projection time
     t_proj = (t1 - t0) * 2.0
     t_raster = (t2 - t1) + (t3 - t2) - (t1 - t0)
-    t_frame = t_proj + max(t_raster, 0.0) * (W * H) / float(side * side)
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    return {"value": round(W * H / t_frame / 1e6, 6), "unit": "Mpix/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"FP64 oracle: projection of all {scene['means'].shape[0]} components, raster fwd+bwd of a "
-                       f"{side}x{side} window at ({x0},{y0}) scaled to {W}x{H}; measured {t3 - t0:.1f} s, "
-                       f"projection/compositing loops on {threads} OpenMP threads, raster backward single-threaded")}
+    return t_proj + max(t_raster, 0.0) * (W * H) / float(side * side), t3 - t0, (x0, y0)
+
+
+def cpu_baseline(scene, cam, side_all=768, side_one=192):
+    """The FP64 oracle on bounded samples, on all host threads and on one:
+    projection (+ its backward) of every component and the raster fwd+bwd of
+    a central window, the raster time scaled to the full frame."""
+    import oracle
+    W, H = cam["width"], cam["height"]
+    threads = oracle.max_threads()
+    t_all, wall_all, org_all = _oracle_frame(scene, cam, side_all)
+    oracle.set_threads(1)
+    try:
+        t_one, wall_one, org_one = _oracle_frame(scene, cam, side_one)
+    finally:
+        oracle.set_threads(threads)
+    n = scene["means"].shape[0]
+    return {"value": round(W * H / t_all / 1e6, 6), "unit": "Mpix/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 oracle, {threads} OpenMP threads: projection and its backward of all {n} components, "
+                       f"raster fwd+bwd of a {side_all}x{side_all} window at {org_all}, scaled to {W}x{H}; "
+                       f"measured {wall_all:.1f} s"),
+            "single_thread": {"value": round(W * H / t_one / 1e6, 6), "unit": "Mpix/s", "cores": 1,
+                              "sample": (f"same, one thread, window {side_one}x{side_one} at {org_one}; "
+                                         f"measured {wall_one:.1f} s")},
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def serving(scene_np, rates, seconds):
@@ -300,7 +329,7 @@ def main():
     ap.add_argument("--deterministic", action="store_true",
                     help="backward without float atomics (bit-identical gradients run to run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=int, default=768 * 768)
+    ap.add_argument("--cpu-window", type=int, default=768, help="side of the all-thread oracle window")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="arrival window of each serving run (0 disables the serving measurement)")
     ap.add_argument("--serve-rates", default="200,500,1000",

@@ -60,6 +60,16 @@ def _load():
     return _lib
 
 
+def set_threads(k: int) -> None:
+    """Thread count of the oracle's OpenMP loops (projection, compositing,
+    raster backward)."""
+    _load().orc_set_threads(ctypes.c_int(int(k)))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 

@@ -49,6 +49,7 @@
  *              as the Gaussian 3-sigma ellipse)
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -590,52 +591,79 @@ void orc_render_backward(int n, const double* mean2d, const double* conic, const
                          const double* opts, const double* dl_dimg, double* g_mean2d,
                          double* g_conic, double* g_rgb, double* g_opac, double* g_nu) {
   const int tx_n = (W + ORC_TILE - 1) / ORC_TILE;
-  int cap = 1024;
-  orc_hit* hits = (orc_hit*)malloc(sizeof(orc_hit) * cap);
-  (void)n;
-  for (int y = 0; y < H; ++y)
-    for (int x = 0; x < W; ++x) {
-      const int64_t t = (int64_t)(y / ORC_TILE) * tx_n + x / ORC_TILE;
-      const int64_t p = (int64_t)y * W + x;
-      const int64_t len = tile_start[t + 1] - tile_start[t];
-      if (len > cap) { cap = (int)len; hits = (orc_hit*)realloc(hits, sizeof(orc_hit) * cap); }
-      double out[3], tf;
-      int32_t nc, xf;
-      const int nh = composite_pixel(x + 0.5, y + 0.5, tile_list + tile_start[t], len, mean2d, conic,
-                                     rgb, opac, nu_c, pflags, opts, out, &tf, &nc, &xf, hits, cap);
-      const double* g = dl_dimg + 3 * p;
-      double S[3] = {opts[7], opts[8], opts[9]};
-      for (int j = nh - 1; j >= 0; --j) {
-        const orc_hit* e = &hits[j];
-        const int32_t i = e->idx;
-        const double* c = rgb + 3 * i;
-        double dalpha = 0.0;
-        for (int ch = 0; ch < 3; ++ch) {
-          dalpha += g[ch] * e->T * (c[ch] - S[ch]);
-          g_rgb[3 * i + ch] += g[ch] * e->alpha * e->T;
+  /* Pixel rows are shared among the threads; each thread adds its pixels'
+   * terms into its own ten sums per component (mean2d 2, conic 3, rgb 3,
+   * opacity, nu), and the partial sums are added into the outputs in thread
+   * order afterwards. */
+  const int nt = omp_get_max_threads();
+  double* part = (double*)calloc((size_t)nt * (size_t)n * 10, sizeof(double));
+#pragma omp parallel num_threads(nt)
+  {
+    double* acc = part + (size_t)omp_get_thread_num() * (size_t)n * 10;
+    int cap = 1024;
+    orc_hit* hits = (orc_hit*)malloc(sizeof(orc_hit) * cap);
+#pragma omp for schedule(dynamic, 1)
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        const int64_t t = (int64_t)(y / ORC_TILE) * tx_n + x / ORC_TILE;
+        const int64_t p = (int64_t)y * W + x;
+        const int64_t len = tile_start[t + 1] - tile_start[t];
+        if (len > cap) { cap = (int)len; hits = (orc_hit*)realloc(hits, sizeof(orc_hit) * cap); }
+        double out[3], tf;
+        int32_t nc, xf;
+        const int nh = composite_pixel(x + 0.5, y + 0.5, tile_list + tile_start[t], len, mean2d, conic,
+                                       rgb, opac, nu_c, pflags, opts, out, &tf, &nc, &xf, hits, cap);
+        const double* g = dl_dimg + 3 * p;
+        double S[3] = {opts[7], opts[8], opts[9]};
+        for (int j = nh - 1; j >= 0; --j) {
+          const orc_hit* e = &hits[j];
+          const int32_t i = e->idx;
+          const double* c = rgb + 3 * i;
+          double* a10 = acc + (size_t)i * 10;
+          double dalpha = 0.0;
+          for (int ch = 0; ch < 3; ++ch) {
+            dalpha += g[ch] * e->T * (c[ch] - S[ch]);
+            a10[5 + ch] += g[ch] * e->alpha * e->T;
+          }
+          for (int ch = 0; ch < 3; ++ch) S[ch] = c[ch] * e->alpha + (1.0 - e->alpha) * S[ch];
+          if (e->clamped) continue;
+          a10[8] += dalpha * e->t2;
+          const double dt2 = dalpha * opac[i];
+          const double nu = nu_c[i], h = e->h;
+          /* dT2D/dh = -(nu+2)/(2 nu) (1 + h/nu)^(-(nu+4)/2); Gaussian: -T/2 */
+          const double dt_dh = opts[10] == 1.0 ? -0.5 * e->t2 : -e->t2 * (nu + 2.0) / (2.0 * (nu + h));
+          /* dT2D/dnu, both the base and the exponent depend on nu; Gaussian: 0 */
+          const double dt_dnu = opts[10] == 1.0 ? 0.0
+                                                : e->t2 * 0.5 * ((nu + 2.0) * h / (nu * (nu + h)) - log1p(h / nu));
+          const double dh = dt2 * dt_dh;
+          const double a = conic[3 * i], b = conic[3 * i + 1], cc = conic[3 * i + 2];
+          a10[0] += dh * (-2.0) * (a * e->dx + b * e->dy);
+          a10[1] += dh * (-2.0) * (b * e->dx + cc * e->dy);
+          a10[2] += dh * e->dx * e->dx;
+          a10[3] += dh * 2.0 * e->dx * e->dy;
+          a10[4] += dh * e->dy * e->dy;
+          a10[9] += dt2 * dt_dnu;
         }
-        for (int ch = 0; ch < 3; ++ch) S[ch] = c[ch] * e->alpha + (1.0 - e->alpha) * S[ch];
-        if (e->clamped) continue;
-        g_opac[i] += dalpha * e->t2;
-        const double dt2 = dalpha * opac[i];
-        const double nu = nu_c[i], h = e->h;
-        /* dT2D/dh = -(nu+2)/(2 nu) (1 + h/nu)^(-(nu+4)/2); Gaussian: -T/2 */
-        const double dt_dh = opts[10] == 1.0 ? -0.5 * e->t2 : -e->t2 * (nu + 2.0) / (2.0 * (nu + h));
-        /* dT2D/dnu, both the base and the exponent depend on nu; Gaussian: 0 */
-        const double dt_dnu = opts[10] == 1.0 ? 0.0
-                                              : e->t2 * 0.5 * ((nu + 2.0) * h / (nu * (nu + h)) - log1p(h / nu));
-        const double dh = dt2 * dt_dh;
-        const double a = conic[3 * i], b = conic[3 * i + 1], cc = conic[3 * i + 2];
-        g_mean2d[2 * i] += dh * (-2.0) * (a * e->dx + b * e->dy);
-        g_mean2d[2 * i + 1] += dh * (-2.0) * (b * e->dx + cc * e->dy);
-        g_conic[3 * i] += dh * e->dx * e->dx;
-        g_conic[3 * i + 1] += dh * 2.0 * e->dx * e->dy;
-        g_conic[3 * i + 2] += dh * e->dy * e->dy;
-        g_nu[i] += dt2 * dt_dnu;
       }
+    free(hits);
+  }
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i)
+    for (int th = 0; th < nt; ++th) {
+      const double* a10 = part + ((size_t)th * (size_t)n + (size_t)i) * 10;
+      g_mean2d[2 * i] += a10[0];
+      g_mean2d[2 * i + 1] += a10[1];
+      for (int k = 0; k < 3; ++k) g_conic[3 * i + k] += a10[2 + k];
+      for (int k = 0; k < 3; ++k) g_rgb[3 * i + k] += a10[5 + k];
+      g_opac[i] += a10[8];
+      g_nu[i] += a10[9];
     }
-  free(hits);
+  free(part);
 }
+
+/* Thread count of the OpenMP loops (the CPU baseline times 1 and all). */
+void orc_set_threads(int k) { omp_set_num_threads(k > 0 ? k : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Backward through the projection (per component)                           */
