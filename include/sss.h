@@ -303,6 +303,30 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
                    const sss_grads_t* grads, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * sss_render_bwd_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): sss_render_bwd with the same arguments, modes and results,
+ * minus the workspace, which the library holds itself as a device array of
+ * SSS_NOALLOC_WORKSPACE_BYTES (128 MiB; about 1.3M entries at 1080p in the
+ * atomic modes) per GPU it runs on, kept until the process ends.  The call
+ * allocates nothing (no hipMalloc/hipFree, no library allocator).
+ * The first call on a device looks up that device's copy of the array.
+ * Calls that overlap on one GPU share the array and race: serialise them
+ * (one stream, or events between streams).  Each call clears what it needs
+ * zeroed with a kernel of its own (no memset node under graph capture).
+ * Errors: as sss_render_bwd, plus INVALID (with the needed size in the
+ * message) when sss_render_bwd_workspace / _workspace_det of the call
+ * exceeds SSS_NOALLOC_WORKSPACE_BYTES; HIP if the array's address cannot be
+ * looked up. */
+#define SSS_NOALLOC_WORKSPACE_BYTES ((size_t)128 << 20)
+
+int sss_render_bwd_noalloc(const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
+                           const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts,
+                           int mode, int loss, const float* dl_or_target, const float* image,
+                           const uint32_t* n_contrib, float* image_out, float* loss_out,
+                           const sss_grads_t* grads, void* stream);
+
+/* ------------------------------------------------------------------------
  * sss_sghmc_step -- Sec. 3.4 eq. (sigmoidUpdate) / SM eq. (SGHMC), per mean
  * element, eps = lr, C = friction, switch s = sigmoid(k ((1 - |o|) - t)) (on
  * for |o| below 1 - t), n ~ N(0, 2 eps C) per axis:

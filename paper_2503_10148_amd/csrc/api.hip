@@ -206,49 +206,59 @@ int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views
   return hip_ok(hipGetLastError(), "sss_render_fwd launch") ? SSS_OK : SSS_ERR_HIP;
 }
 
-int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
-                   const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts, int mode, int loss,
-                   const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
-                   float* loss_out, const sss_grads_t* grads, void* ws, size_t ws_bytes, void* stream) {
-  int rc = check_scene(scene, "sss_render_bwd");
+}  // extern "C"
+
+namespace sss {
+
+// The body of sss_render_bwd and of its variant with a library-held
+// workspace (noalloc.hip).  ws == nullptr asks for the size check only:
+// on success *need is the workspace size and nothing is enqueued; with a
+// workspace, the check and the launches.
+int render_bwd_impl(const char* fn, const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
+                    const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts, int mode, int loss,
+                    const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
+                    float* loss_out, const sss_grads_t* grads, void* ws, size_t ws_bytes, size_t* need_out,
+                    hipStream_t st) {
+  int rc = check_scene(scene, fn);
   if (rc) return rc;
-  if ((rc = check_opts(opts, "sss_render_bwd"))) return rc;
+  if ((rc = check_opts(opts, fn))) return rc;
   CamBatch cb;
   if ((rc = make_cam_batch(cams, n_views, &cb))) return rc;
   const bool det = (mode & SSS_BWD_DETERMINISTIC) != 0;
   mode &= ~SSS_BWD_DETERMINISTIC;
   if (mode != SSS_BWD_STORED && mode != SSS_BWD_RECOMPUTE) {
-    set_error("sss_render_bwd: unknown mode %d", mode);
+    set_error("%s: unknown mode %d", fn, mode);
     return SSS_ERR_INVALID;
   }
   if (loss != SSS_LOSS_GRAD && loss != SSS_LOSS_L1) {
-    set_error("sss_render_bwd: unknown loss %d", loss);
+    set_error("%s: unknown loss %d", fn, loss);
     return SSS_ERR_INVALID;
   }
   if (!proj || !proj->tiles_touched || !bins || !bins->sorted_records || !bins->tile_start || !bins->pair_rank ||
-      !dl_or_target || !grads || !ws) {
-    set_error("sss_render_bwd: null pointer");
+      !dl_or_target || !grads) {
+    set_error("%s: null pointer", fn);
     return SSS_ERR_INVALID;
   }
   if (mode == SSS_BWD_STORED && (!image || !n_contrib)) {
-    set_error("sss_render_bwd: STORED mode needs image and n_contrib");
+    set_error("%s: STORED mode needs image and n_contrib", fn);
     return SSS_ERR_INVALID;
   }
   const int64_t n_entries = scene->n * n_views;
   if (det && (!bins->order || !bins->rank_offset || !proj->rect || !proj->ellipse || bins->n_pairs < 0 ||
               bins->n_visible < 0 || bins->n_visible > n_entries)) {
-    set_error("sss_render_bwd: the deterministic mode needs bins->order, bins->rank_offset, proj->rect, proj->ellipse and the "
-              "counts of the sss_bin_sort call");
+    set_error("%s: the deterministic mode needs bins->order, bins->rank_offset, proj->rect, proj->ellipse and the "
+              "counts of the sss_bin_sort call", fn);
     return SSS_ERR_INVALID;
   }
   const size_t need = det ? render_bwd_det_workspace(n_entries, bins->n_pairs, cb.total_tiles)
                           : render_bwd_workspace(n_entries, cb.total_tiles);
+  if (need_out) *need_out = need;
+  if (!ws) return SSS_OK;
   if (ws_bytes < need) {
-    set_error("sss_render_bwd: workspace of %zu bytes, %zu needed", ws_bytes, need);
+    set_error("%s: workspace of %zu bytes, %zu needed", fn, ws_bytes, need);
     return SSS_ERR_INVALID;
   }
-  if (!ws_aligned(ws, "sss_render_bwd")) return SSS_ERR_INVALID;
-  hipStream_t st = (hipStream_t)stream;
+  if (!ws_aligned(ws, fn)) return SSS_ERR_INVALID;
   const OptsDev op = make_opts(opts);
   double* g2 = (double*)ws;
   DetArgs da{};
@@ -265,7 +275,24 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
   launch_render_bwd(cb, op, *bins, mode, loss, dl_or_target, image, n_contrib, image_out, loss_out, g2,
                     total_pixels(cb), det, da, scene->n, st);
   launch_project_bwd(cb, op, *scene, proj->tiles_touched, g2, *grads, st);
-  return hip_ok(hipGetLastError(), "sss_render_bwd launch") ? SSS_OK : SSS_ERR_HIP;
+  return hip_ok(hipGetLastError(), fn) ? SSS_OK : SSS_ERR_HIP;
+}
+
+
+}  // namespace sss
+
+extern "C" {
+
+int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
+                   const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts, int mode, int loss,
+                   const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
+                   float* loss_out, const sss_grads_t* grads, void* ws, size_t ws_bytes, void* stream) {
+  if (!ws) {
+    set_error("sss_render_bwd: null workspace");
+    return SSS_ERR_INVALID;
+  }
+  return render_bwd_impl("sss_render_bwd", scene, proj, bins, cams, n_views, opts, mode, loss, dl_or_target, image,
+                         n_contrib, image_out, loss_out, grads, ws, ws_bytes, nullptr, (hipStream_t)stream);
 }
 
 size_t sss_render_bwd_workspace_det(int64_t n_entries, int64_t n_pairs, int64_t n_tiles) {

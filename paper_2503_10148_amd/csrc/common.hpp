@@ -128,6 +128,13 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                        const uint32_t* n_contrib, float* image_out, float* loss_out, double* g2,
                        int64_t total_pixels, bool det_mode, const DetArgs& dargs, int64_t n, hipStream_t st);
 void launch_zero(float* p, int64_t count, hipStream_t st);
+// Argument checks and launches of sss_render_bwd (api.hip); ws == nullptr
+// checks only and returns the workspace size in *need_out.
+int render_bwd_impl(const char* fn, const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
+                    const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts, int mode, int loss,
+                    const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
+                    float* loss_out, const sss_grads_t* grads, void* ws, size_t ws_bytes, size_t* need_out,
+                    hipStream_t st);
 size_t relocate_workspace(int64_t n, double max_fraction);
 size_t loss_workspace(int64_t total_pixels);
 void launch_loss(const CamBatch& cb, const float* img, const float* tgt, float lam, float* dl, float* loss_out,

@@ -94,10 +94,12 @@ class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+# every function include/sss.h declares; lib() checks that each is exported
 EXPORTS = ["sss_default_render_opts", "sss_project", "sss_bin_sort", "sss_bin_sort_workspace", "sss_total_tiles",
-           "sss_total_pixels", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_workspace", "sss_sghmc_step",
-           "sss_last_error", "sss_version", "sss_loss", "sss_loss_workspace", "sss_relocate", "sss_relocate_workspace", "sss_timing_enable",
-           "sss_timing_reset", "sss_timing_read"]
+           "sss_total_pixels", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_workspace",
+           "sss_render_bwd_workspace_det", "sss_render_bwd_noalloc", "sss_sghmc_step", "sss_loss",
+           "sss_loss_workspace", "sss_regularise", "sss_relocate", "sss_relocate_workspace", "sss_timing_enable",
+           "sss_timing_reset", "sss_timing_read", "sss_last_error", "sss_version"]
 
 _lib = None
 
@@ -109,6 +111,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_10148_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
+        missing = [name for name in EXPORTS if not hasattr(L, name)]
+        if missing:
+            raise RuntimeError(f"{LIB_PATH} does not export {missing}: rebuild it")
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         L.sss_last_error.restype = ctypes.c_char_p
         L.sss_version.restype = i32
@@ -127,6 +132,7 @@ def lib():
         L.sss_render_fwd.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
         L.sss_render_bwd.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                      ctypes.c_size_t, vp]
+        L.sss_render_bwd_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.sss_sghmc_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]
         L.sss_loss_workspace.restype = ctypes.c_size_t
         L.sss_loss_workspace.argtypes = [i64]
@@ -143,7 +149,8 @@ def lib():
         L.sss_timing_reset.restype = None
         L.sss_timing_read.argtypes = [vp, i32]
         L.sss_timing_read.restype = i32
-        for name in ("sss_project", "sss_bin_sort", "sss_render_fwd", "sss_render_bwd", "sss_sghmc_step"):
+        for name in ("sss_project", "sss_bin_sort", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_noalloc",
+                     "sss_sghmc_step"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -364,11 +371,13 @@ def zero_grads_like(scene):
 
 def render_bwd(scene, proj: Projected, bins: Binned, cams, dl_or_target, opts=None, mode=BWD_STORED,
                loss=LOSS_GRAD, image=None, n_contrib=None, image_out=None, loss_out=None, grads=None,
-               ws=None, stream=None, overwrite=None, deterministic=False):
+               ws=None, stream=None, overwrite=None, deterministic=False, noalloc=False):
     """Gradients into `grads` (+= by default; written when overwrite, which is
     the default when grads is None and new buffers are allocated).
     deterministic: no float atomics, bit-identical results run to run (needs
-    bins from BinSorter(keep_offsets=True))."""
+    bins from BinSorter(keep_offsets=True)).
+    noalloc: call sss_render_bwd_noalloc, whose workspace the library holds
+    (up to SSS_NOALLOC_WORKSPACE_BYTES); `ws` is ignored."""
     n = scene["means"].shape[0]
     E = n * len(cams)
     if grads is None:
@@ -380,12 +389,19 @@ def render_bwd(scene, proj: Projected, bins: Binned, cams, dl_or_target, opts=No
         need = int(lib().sss_render_bwd_workspace_det(E, bins.n_pairs, total_tiles(cams)))
     else:
         need = int(lib().sss_render_bwd_workspace(E, total_tiles(cams)))
-    if ws is None or ws.numel() * ws.element_size() < need:
-        ws = torch.empty(need // 4, dtype=torch.float32, device=scene["means"].device)
     s = scene_struct(scene)
     g = Grads(*(grads[k].data_ptr() for k in ("means", "scales", "quats", "nu", "opacity", "sh")), int(overwrite), 0)
     p = proj.struct()
     b = bins.struct()
+    if noalloc:
+        _check(lib().sss_render_bwd_noalloc(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), camera_array(cams),
+                                            len(cams), ctypes.byref(render_opts(opts)), mode, loss,
+                                            _ptr(dl_or_target), _ptr(image), _ptr(n_contrib), _ptr(image_out),
+                                            _ptr(loss_out), ctypes.byref(g), _stream(stream)),
+               "sss_render_bwd_noalloc")
+        return grads
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need // 4, dtype=torch.float32, device=scene["means"].device)
     _check(lib().sss_render_bwd(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), camera_array(cams), len(cams),
                                 ctypes.byref(render_opts(opts)), mode, loss, _ptr(dl_or_target), _ptr(image),
                                 _ptr(n_contrib), _ptr(image_out), _ptr(loss_out), ctypes.byref(g), _ptr(ws),

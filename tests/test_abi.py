@@ -213,3 +213,37 @@ def test_misaligned_scene_arrays_are_rejected(sss):
         p = _proj_struct(sss)
         assert L.sss_project(ctypes.byref(scene), cams, 1, ctypes.byref(opts), ctypes.byref(p), None) == sss.ERR_INVALID
         assert b"16-byte" in L.sss_last_error()
+
+
+def test_binding_export_list_is_the_header(sss):
+    """sss.EXPORTS (checked when the binding loads the library) lists exactly
+    the functions include/sss.h declares."""
+    assert sorted(sss.EXPORTS) == declared_functions()
+
+
+def test_noalloc_rejects_bad_arguments_and_oversize_before_any_gpu_call(sss):
+    """sss_render_bwd_noalloc checks its arguments, then the workspace the
+    call needs against the array the library holds, before it looks up that
+    array's device address: both errors come back on a machine without a
+    GPU."""
+    L = sss.lib()
+    cams = sss.camera_array([scenes.ring_camera(64, 48)])
+    opts = sss.render_opts()
+    p = _proj_struct(sss)
+    b = sss.Bins(0x1000, 0x2000, 0x3000, 0x4000, None, None, None, 100, 0, 0)
+    g = sss.Grads(0, 0, 0, 0, 0, 0, 0, 0)
+
+    def call(scene, mode):
+        return L.sss_render_bwd_noalloc(ctypes.byref(scene), ctypes.byref(p), ctypes.byref(b), cams, 1,
+                                        ctypes.byref(opts), mode, 0, ctypes.c_void_p(0x6000),
+                                        ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000), None, None,
+                                        ctypes.byref(g), None)
+
+    assert call(_scene_struct(sss), 7) == sss.ERR_INVALID
+    assert b"sss_render_bwd_noalloc" in L.sss_last_error()
+    assert call(_scene_struct(sss, null=1), 0) == sss.ERR_INVALID
+    # 1.5M entries need 1.5M x 96 B of per-entry sums: more than 128 MiB
+    big = _scene_struct(sss, n=1_500_000)
+    assert L.sss_render_bwd_workspace(1_500_000, 12) > (128 << 20)
+    assert call(big, 0) == sss.ERR_INVALID
+    assert b"SSS_NOALLOC_WORKSPACE_BYTES" in L.sss_last_error()

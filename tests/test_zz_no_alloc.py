@@ -1,0 +1,99 @@
+"""sss_render_bwd_noalloc (workspace held by the library) against
+sss_render_bwd (caller's workspace), through the C-ABI, on two calls in a
+row, the second with a smaller input.
+
+Tolerances are those of the gradient parity bar: float atomics order the
+per-entry sums differently from run to run, so the atomic modes agree within
+1e-3 max(|g|, rms(g)) per array; the forward image (recompute mode) and the
+fixed-order L1 loss are bit-identical, and the deterministic mode is
+bit-identical throughout.
+"""
+import numpy as np
+import pytest
+
+from paper_2503_10148_amd import scenes
+from tests._util import PARAMS, grad_close, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_10148_amd import sss as binding
+    binding.lib()
+    return binding
+
+
+def _inputs(sss, n, W, H, seed):
+    scene = scenes.make_scene(n, 3, seed=seed, neg_frac=0.3)
+    cams = [scenes.ring_camera(W, H, angle=0.3 + seed)]
+    dev = to_device(scene)
+    proj = sss.project(dev, cams)
+    bins = sss.BinSorter(1024, keep_offsets=True, own_pairs=True)(proj, cams, n)
+    target = torch.as_tensor(scenes.smooth_target(W, H, seed=seed).reshape(-1, 3), device="cuda")
+    return dev, cams, proj, bins, target
+
+
+def _run(sss, dev, cams, proj, bins, target, mode, det, noalloc):
+    P = sss.total_pixels(cams)
+    img, _, ncon = sss.render_fwd(bins, cams)
+    image_out = torch.full((P, 3), -7.0, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    grads = {k: torch.full_like(dev[k], 3.0) for k in PARAMS}        # overwritten by the call
+    sss.render_bwd(dev, proj, bins, cams, target, mode=mode, loss=sss.LOSS_L1, image=img, n_contrib=ncon,
+                   image_out=image_out if mode == sss.BWD_RECOMPUTE else None, loss_out=loss, grads=grads,
+                   overwrite=True, deterministic=det, noalloc=noalloc)
+    torch.cuda.synchronize()
+    out = {k: grads[k].cpu().numpy() for k in PARAMS}
+    out["loss"] = float(loss.item())
+    out["image"] = (image_out if mode == sss.BWD_RECOMPUTE else img).cpu().numpy()
+    return out
+
+
+@pytest.mark.parametrize("det", [False, True], ids=["atomic", "deterministic"])
+@pytest.mark.parametrize("mode_name", ["stored", "recompute"])
+def test_noalloc_matches_workspace_entry_point(sss, mode_name, det):
+    mode = sss.BWD_STORED if mode_name == "stored" else sss.BWD_RECOMPUTE
+    # the second call has fewer components and pixels than the first: the
+    # library's array keeps the first call's contents, which must not leak
+    for n, W, H, seed in ((20000, 330, 250, 1), (3000, 120, 90, 2)):
+        print(f"noalloc case: mode={mode_name} det={det} n={n} {W}x{H} seed={seed}", flush=True)
+        dev, cams, proj, bins, target = _inputs(sss, n, W, H, seed)
+        ref = _run(sss, dev, cams, proj, bins, target, mode, det, noalloc=False)
+        got = _run(sss, dev, cams, proj, bins, target, mode, det, noalloc=True)
+        assert np.array_equal(got["image"], ref["image"])
+        assert got["loss"] == ref["loss"]
+        for k in PARAMS:
+            g, r = got[k].reshape(n, -1), ref[k].reshape(n, -1)
+            assert np.all(np.isfinite(g)), k
+            if det:
+                assert np.array_equal(g, r), k
+            else:
+                ok, worst = grad_close(g, r)
+                assert ok, f"{k}: worst ratio {worst:.3g}"
+
+
+def test_noalloc_rejects_more_than_it_holds(sss):
+    """A call whose workspace would exceed SSS_NOALLOC_WORKSPACE_BYTES is an
+    argument error with the needed size in the message; nothing runs."""
+    n = 1_500_000                       # 1.5M entries x 96 B > 128 MiB
+    scene = {k: torch.zeros(1, dtype=torch.float32, device="cuda") for k in PARAMS}
+    # only the pointers and n are read before the size check: use tiny
+    # tensors and a scene struct that states n
+    cams = [scenes.ring_camera(64, 48)]
+    import ctypes
+    s = sss.Scene(n, 0, 0, *(scene[k].data_ptr() for k in PARAMS))
+    p = sss.Proj(*(scene["means"].data_ptr(),) * 5)
+    b = sss.Bins(*(scene["means"].data_ptr(),) * 4, None, None, None, 1, 0, 0)
+    g = sss.Grads(*(scene["means"].data_ptr(),) * 6, 1, 0)
+    L = sss.lib()
+    rc = L.sss_render_bwd_noalloc(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), sss.camera_array(cams), 1,
+                                  ctypes.byref(sss.render_opts()), sss.BWD_RECOMPUTE, sss.LOSS_L1,
+                                  ctypes.c_void_p(scene["means"].data_ptr()), None, None, None, None,
+                                  ctypes.byref(g), None)
+    assert rc == sss.ERR_INVALID
+    assert b"SSS_NOALLOC_WORKSPACE_BYTES" in L.sss_last_error()
