@@ -44,7 +44,8 @@ WORKLOADS = {
     "train": "300k components, SH degree 3, one 1297x840 camera, fwd+bwd+SGHMC",
     "small": "10k components, SH degree 0, one 256x256 camera, fwd+bwd+SGHMC",
     "large": "3M clustered components, nu 1..150, 30% negative, one 1920x1080 camera, fwd+bwd+SGHMC",
-    "multiview": "5M clustered components, SH degree 3, 8 cameras of 1600x1064 in one launch per kernel, "
+    "multiview": "5M clustered components, SH degree 3, 8 cameras of 1600x1064 in one launch per kernel "
+                 "(recompute mode: per tile the forward walk and the backward in one launch, L1 loss fused), "
                  "fwd+bwd+SGHMC",
 }
 
@@ -79,6 +80,7 @@ def _oracle_frame(scene, cam, side):
     import oracle
     from paper_2503_10148_amd import scenes
     W, H = cam["width"], cam["height"]
+    side = min(side, W, H)
     x0, y0 = (W - side) // 2 // 16 * 16, (H - side) // 2 // 16 * 16
     win = oracle.window_camera(cam, x0, y0, side, side)
     target = scenes.smooth_target(W, H)[y0:y0 + side, x0:x0 + side]
@@ -97,7 +99,7 @@ def _oracle_frame(scene, cam, side):
     return t_proj + max(t_raster, 0.0) * (W * H) / float(side * side), t3 - t0, (x0, y0)
 
 
-def cpu_baseline(scene, cam, side_all=768, side_one=192):
+def cpu_baseline(scene, cam, side_all=1024, side_one=384):
     """The FP64 oracle on bounded samples, on all host threads and on one:
     projection (+ its backward) of every component and the raster fwd+bwd of
     a central window, the raster time scaled to the full frame."""
@@ -121,7 +123,7 @@ def cpu_baseline(scene, cam, side_all=768, side_one=192):
             "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
-def serving(scene_np, rates, seconds):
+def serving(scene_np, rates, seconds, closed_clients=16):
     """Batched server vs plain one-request-per-launch on the resident 1M
     scene (SH 3): Poisson arrivals, cameras on a sphere of radius 3..5,
     resolution uniform over {640x360, 1280x720, 1920x1080}, batch <= 16."""
@@ -153,6 +155,21 @@ def serving(scene_np, rates, seconds):
                          "mpix_s": round(px / wall / 1e6, 2), **stats}
             log(f"serve rate {rate} {kind}: {row[kind]}")
         res["runs"].append(row)
+    if closed_clients > 0:
+        # saturation: closed loop of clients, each sending its next request
+        # when the previous one returns
+        crng = np.random.default_rng(scenes.SEED_ARRIVALS + 1)
+        ccams = [scenes.sphere_camera(crng, *sizes[int(crng.integers(0, 3))]) for _ in range(100000)]
+        big = [scenes.sphere_camera(crng, *sizes[-1]) for _ in range(4)]
+        row = {"closed_loop_clients": closed_clients}
+        for kind in ("plain", "batched"):
+            lat, nreq, px, wall, stats = serve.run_closed(kind, scene, lambda k: ccams[k % len(ccams)],
+                                                          closed_clients, seconds, warm=big)
+            row[kind] = {"req_s": round(nreq / wall, 1), "mpix_s": round(px / wall / 1e6, 2),
+                         "p50_ms": round(serve.percentile(lat, 50) * 1e3, 3),
+                         "p99_ms": round(serve.percentile(lat, 99) * 1e3, 3), **stats}
+            log(f"serve closed loop {closed_clients} clients {kind}: {row[kind]}")
+        res["closed_loop"] = row
     return res
 
 
@@ -193,10 +210,11 @@ def copy_probe():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
 
 
-def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instrument=True):
+def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instrument=True, fused=True):
     """Run warmup + timed (uninstrumented) training steps of a workload; with
     `instrument`, a few more steps with per-kernel HIP-event timing and the
-    algorithmic work of the last step."""
+    algorithmic work of the last step.  fused: the backward pass and the
+    SGHMC/Adam step as one call (sss_render_bwd_step), else the two calls."""
     scene_np, cams, target_np = make_inputs(workload)
     n = scene_np["means"].shape[0]
     P = sss.total_pixels(cams)
@@ -209,7 +227,13 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
     bounds = dict(scales=(1e-4, 3.0e38), quats=(-3.0e38, 3.0e38), nu=(1.0, 1e4), opacity=(-1.0, 1.0),
                   sh=(-3.0e38, 3.0e38))
     lrs = dict(scales=1e-4, quats=1e-3, nu=1e-2, opacity=1e-3, sh=2.5e-4)
-    binner = sss.BinSorter(0, keep_offsets=deterministic)
+    # the bin sort reads its counts on the device and never waits (after the
+    # first call, which sizes the pair buffers); every step's counts land in
+    # its own row of step_counts and are checked against the capacity after
+    # the timed loop.  The deterministic backward needs the host counts.
+    binner = sss.BinSorter(0, keep_offsets=deterministic, no_wait=not deterministic)
+    n_all = warmup + steps + max(1, min(steps, 5)) + 1
+    step_counts = torch.zeros((n_all, 2), dtype=torch.int64, device="cuda")
     image = torch.empty((P, 3), device="cuda")
     t_final = torch.empty(P, device="cuda")
     n_contrib = torch.empty(P, dtype=torch.int32, device="cuda")
@@ -220,18 +244,32 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
     state = {"proj": None, "bins": None}
     T = sss.total_tiles(cams)
 
+    cams = sss.CameraBatch(cams)          # marshalled once for every call of every step
+    adam_fused = dict(beta1=0.9, beta2=0.999, eps=1e-15, m={k: adam_state[k][0] for k in adam_state},
+                      v={k: adam_state[k][1] for k in adam_state}, lr=lrs,
+                      lo={k: bounds[k][0] for k in adam_state}, hi={k: bounds[k][1] for k in adam_state})
+
     def step(it):
         nonlocal bwd_ws
         proj = sss.project(scene, cams, out=state["proj"])
         state["proj"] = proj
-        bins = binner(proj, cams, n, out=state["bins"])
+        bins = binner(proj, cams, n, out=state["bins"], counts=step_counts[it])
         state["bins"] = bins
         if deterministic:
             need = int(sss.lib().sss_render_bwd_workspace_det(n * len(cams), bins.n_pairs, T))
             if bwd_ws.numel() * 4 < need:
                 bwd_ws = torch.empty(int(need * 1.1) // 4 + 64, device="cuda")
-        if mode == sss.BWD_STORED:
+        stored = mode == sss.BWD_STORED
+        if stored:
             sss.render_fwd(bins, cams, image=image, t_final=t_final, n_contrib=n_contrib)
+        if fused:
+            adam_fused["t"] = it + 1
+            sss.render_bwd_step(scene, proj, bins, cams, target, mom, dict(lr=1e-3, friction=0.1, seed=4, step=it),
+                                adam=adam_fused, mode=mode, loss=sss.LOSS_L1, image=image if stored else None,
+                                n_contrib=n_contrib if stored else None, image_out=None if stored else image,
+                                loss_out=loss, ws=bwd_ws, deterministic=deterministic)
+            return
+        if stored:
             sss.render_bwd(scene, proj, bins, cams, target, mode=mode, loss=sss.LOSS_L1, image=image,
                            n_contrib=n_contrib, loss_out=loss, grads=grads, ws=bwd_ws, overwrite=True,
                            deterministic=deterministic)
@@ -244,10 +282,19 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
         sss.sghmc_step(scene["means"], mom, grads["means"], scene["opacity"], lr=1e-3, friction=0.1, seed=4,
                        step=it, scales=scene["scales"], quats=scene["quats"], adam=adam)
 
+    def check_counts(upto):
+        """Every step so far had the pair capacity it needed."""
+        c = step_counts[:upto].cpu()
+        cap = state["bins"].pair_rank.numel()
+        if int(c[:, 1].max()) > cap:
+            raise RuntimeError(f"a step needed {int(c[:, 1].max())} pairs, more than the capacity {cap}")
+        return c
+
     for it in range(warmup):
         step(it)
     torch.cuda.synchronize()
-    log(f"warmup done: pairs={state['bins'].n_pairs} visible={state['bins'].n_visible}")
+    check_counts(warmup)
+    log(f"warmup done: pairs={int(step_counts[warmup - 1, 1])} visible={int(step_counts[warmup - 1, 0])}")
 
     # the timed steps run uninstrumented; the per-kernel breakdown comes from
     # a few further steps with HIP events around every launch
@@ -257,13 +304,14 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
         step(it)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    check_counts(warmup + steps)
     ms_step = (t1 - t0) * 1e3 / steps
     value = P * steps / (t1 - t0) / 1e6
     log(f"timed {steps} steps: {ms_step:.3f} ms/step, {value:.1f} Mpix/s")
     n_inst = max(1, min(steps, 5))
     if not instrument:
         torch.cuda.synchronize()
-        return dict(ms_step=ms_step, value=value, P=P, n=n, views=len(cams), bins=state["bins"])
+        return dict(ms_step=ms_step, value=value, P=P, n=n, views=len(cams), bins=state["bins"].resolve())
     sss.timing_enable(True)
     sss.timing_reset()
     torch.cuda.synchronize()
@@ -274,13 +322,14 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
     ti1 = time.perf_counter()
     kt = sss.timing_read()
     sss.timing_enable(False)
+    check_counts(warmup + steps + n_inst)
 
     # algorithmic work of the last step
     if mode == sss.BWD_RECOMPUTE:
         sss.render_fwd(state["bins"], cams, image=image, t_final=t_final, n_contrib=n_contrib)
     torch.cuda.synchronize()
     evals = float(n_contrib.to(torch.float64).sum().item())
-    bins = state["bins"]
+    bins = state["bins"].resolve()
     avg = {k: v[1] / v[0] for k, v in kt.items()}          # ms per launch
     per_step = {k: v[1] / n_inst for k, v in kt.items()}
     bwd_ms = avg.get("render_bwd", float("nan"))
@@ -290,8 +339,8 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
     par_b = 4 * (3 + 3 + 4 + 1 + 1 + 3 * K)
     V = len(cams)
     bytes_ = {
-        # params in; 64 B record, key, rect, count and 32 B FP64 ellipse out, per entry
-        "project": n * V * (par_b + 64 + 16 + 32),
+        # params in; 128 B entry line (104 B written), key and count out, per entry
+        "project": n * V * (par_b + 104 + 8),
         # means, scales, quats, nu + per view touched and 80 B of FP64 screen gradients in;
         # means (read-modify-write), scales, quats, opacity, nu out
         "project_bwd": n * (4 * (3 + 3 + 4 + 1) + V * 84 + 4 * (3 + 3 + 3 + 4 + 1 + 1)),
@@ -300,6 +349,16 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
         "sghmc": n * 64,
         "adam": n * (3 + 4 + 1 + 1 + 3 * K) * 28,               # one launch over the 5 arrays
     }
+    if fused:
+        # the gradients stay in registers: SH kernel reads means, SH, per
+        # view touched and 24 B of colour gradient, and the SH moments;
+        # writes SH, moments and the 12 B means partial.  Geometry kernel
+        # reads means, scales, quats, nu, opacity, momentum, their moments,
+        # the partial and per view touched + 64 B of screen gradients;
+        # writes means, momentum, scales, quats, nu, opacity and moments.
+        bytes_["sh_bwd"] = n * (4 * (3 + 3 * K * 3) + V * 28 + 4 * (3 * K * 3) + 12)
+        bytes_["project_bwd"] = n * (4 * (3 + 3 + 4 + 1 + 1 + 3 + 2 * 9 + 3) + V * 68 + 4 * (3 + 3 + 3 + 4 + 1 + 1 + 2 * 9))
+        del bytes_["sghmc"], bytes_["adam"]
     stages = {k: {"ms_per_step": round(per_step[k], 4), "launches_per_step": kt[k][0] / n_inst}
               for k in sorted(kt)}
     for k, b in bytes_.items():
@@ -308,8 +367,11 @@ def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instr
             stages[k]["hbm_frac"] = round(b / (avg[k] * 1e-3) / PEAK_HBM, 4)
     if "render_fwd" in avg:
         stages["render_fwd"]["valu_frac"] = round(SLOTS_FWD * evals / (avg["render_fwd"] * 1e-3) / PEAK_VALU, 4)
-    step_bytes = (bytes_["project"] + bytes_["project_bwd"] + bytes_["sh_bwd"] + bytes_["sghmc"] + bytes_["adam"]
-                  + 16 * n + 136 * bins.n_visible + 8 * bins.n_pairs + P * (12 + 12 + 4 + 12))
+    step_bytes = (sum(bytes_.values())
+                  # bin sort: keys and counts per entry; per visible entry its 104 B
+                  # of entry line read, the 64 B record written, order and offset;
+                  # 8 B per pair; per pixel image, t_final, n_contrib, target, loss
+                  + 16 * n + 176 * bins.n_visible + 8 * bins.n_pairs + P * (12 + 12 + 4 + 12))
 
     return dict(ms_step=ms_step, value=value, evals=evals, bins=bins, stages=stages, kt=kt, P=P, n=n,
                 bwd_ms=bwd_ms, achieved=achieved, step_bytes=step_bytes, ti0=ti0, ti1=ti1, n_inst=n_inst, loss=loss,
@@ -324,16 +386,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="m1", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="stored", choices=["stored", "recompute"])
-    ap.add_argument("--other-workloads", default="large:recompute,multiview:stored",
+    ap.add_argument("--other-workloads", default="large:recompute,multiview:recompute",
                     help="further workloads (name:mode, comma separated) timed for 5 steps each; '' to skip")
     ap.add_argument("--deterministic", action="store_true",
                     help="backward without float atomics (bit-identical gradients run to run)")
+    ap.add_argument("--unfused", action="store_true",
+                    help="backward and SGHMC/Adam step as two calls (gradients through memory)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=int, default=768, help="side of the all-thread oracle window")
-    ap.add_argument("--serve-seconds", type=float, default=6.0,
+    ap.add_argument("--cpu-window", type=int, default=1024, help="side of the all-thread oracle window")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="arrival window of each serving run (0 disables the serving measurement)")
-    ap.add_argument("--serve-rates", default="200,500,1000",
+    ap.add_argument("--serve-rates", default="200,500,1000,2000",
                     help="Poisson request rates (req/s) for the serving comparison")
+    ap.add_argument("--serve-clients", type=int, default=16,
+                    help="clients of the closed-loop serving run (0 disables it)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -347,7 +413,8 @@ def main():
     from paper_2503_10148_amd import sss
 
     torch.cuda.set_device(0)
-    r = measure(sss, torch, args.workload, args.mode, args.deterministic, args.steps, args.warmup)
+    r = measure(sss, torch, args.workload, args.mode, args.deterministic, args.steps, args.warmup,
+                fused=not args.unfused)
     ms_step, value, evals, bins, stages, kt = r["ms_step"], r["value"], r["evals"], r["bins"], r["stages"], r["kt"]
     P, n, bwd_ms, achieved, step_bytes = r["P"], r["n"], r["bwd_ms"], r["achieved"], r["step_bytes"]
     ti0, ti1, n_inst, loss = r["ti0"], r["ti1"], r["n_inst"], r["loss"]
@@ -394,7 +461,8 @@ def main():
         "loss": float(loss.item()) / (args.warmup + args.steps + n_inst),
     }
     if args.serve_seconds > 0:
-        out["serving"] = serving(scene_np, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
+        out["serving"] = serving(scene_np, [float(r) for r in args.serve_rates.split(",") if r],
+                                 args.serve_seconds, args.serve_clients)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(scene_np, cams[0], args.cpu_window)

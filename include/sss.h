@@ -16,9 +16,9 @@
  *    (sss_scene_t, sss_camera_t, ...) live in host memory and are read during
  *    the call only.
  *  - `stream` is a hipStream_t (NULL = the default stream).  All device work
- *    is enqueued on it.  sss_bin_sort additionally waits for the stream once
- *    (it reads two counts back to size its launches); every other call
- *    returns without waiting.
+ *    is enqueued on it.  sss_bin_sort waits for the stream once unless its
+ *    no_wait flag is set (it reads two counts back); every other call
+ *    returns without waiting (sss_relocate when asked for its count).
  *  - Return value: SSS_OK or a negative SSS_ERR_* code.  On error nothing
  *    has been enqueued unless stated otherwise, and sss_last_error() returns
  *    a message for the calling thread.
@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SSS_VERSION 103
+#define SSS_VERSION 105
 #define SSS_TILE 16           /* tile edge in pixels                            */
 #define SSS_MAX_VIEWS 16      /* views per call                                 */
 #define SSS_RECORD_BYTES 64   /* size of one projected record                  */
@@ -153,7 +153,8 @@ void sss_default_render_opts(sss_render_opts_t* opts);
  * (the conic), colour from SH, clamped nu, and the truncation ellipse
  * h <= h* with h* = nu ((|o|/alpha_min)^(2/(nu+2)) - 1), outside of which
  * |o T2D| < alpha_min (SSS_TRUNC_COVERAGE: h <= min(q, h*), see
- * sss_render_opts_t).  rect is the range of tiles of its axis-aligned box;
+ * sss_render_opts_t).  The rectangle is the range of tiles of its
+ * axis-aligned box;
  * the entry is listed in the tiles of that range whose box of pixel centres
  * meets the ellipse (row by row: the ellipse's x-extent over the band of
  * pixel-centre rows), and tiles_touched counts those tiles.
@@ -161,22 +162,27 @@ void sss_default_render_opts(sss_render_opts_t* opts);
  * Culled (tiles_touched = 0): depth key <= z_near, |o| < alpha_min, degenerate
  * 2D covariance, or a rectangle entirely off screen.
  * Outputs (device, caller-allocated, n_views*n entries each):
- *   records        64-byte projected records (opaque to the caller)
+ *   entries        SSS_ENTRY_BYTES (128) per entry, 16-byte aligned:
+ *                    bytes   0..63   the raster record (opaque to the caller)
+ *                    bytes  64..95   the FP64 ellipse: 2D covariance A, B, D
+ *                                    and the level of the listed ellipse
+ *                    bytes  96..103  the tile rectangle x0, y0, x1, y1
+ *                                    (uint16, inclusive)
+ *                    bytes 104..127  unused
+ *                  (valid where tiles_touched > 0).  One line per entry, so
+ *                  sss_bin_sort gathers each visible entry's data in depth
+ *                  order with one 128-byte read.
  *   depth_key      uint32
- *   rect           uint16 x0, y0, x1, y1 per entry (inclusive tile range)
  *   tiles_touched  uint32, number of listed tiles, 0 = culled
- *   ellipse        4 doubles per entry: the FP64 2D covariance A, B, D and
- *                  the ellipse level (valid where tiles_touched > 0; read
- *                  by sss_bin_sort and the deterministic backward pass)
  * Errors: INVALID for n <= 0, sh_degree outside 0..3, n_views outside
  * 1..SSS_MAX_VIEWS, a NULL array, a camera with width/height <= 0 or
- * non-positive focal lengths. */
+ * non-positive focal lengths, entries not 16-byte aligned. */
+#define SSS_ENTRY_BYTES 128   /* size of one projected entry                  */
+
 typedef struct {
-  void* records;
+  void* entries;
   uint32_t* depth_key;
-  uint16_t* rect;
   uint32_t* tiles_touched;
-  double* ellipse;
 } sss_proj_t;
 
 int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
@@ -217,12 +223,24 @@ int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
  * A non-NULL tile_order must hold what sss_bin_sort wrote (tiles outside
  * the grid are skipped, so another permutation only reorders work and
  * anything else leaves tiles unrendered).
- * Host outputs: n_visible, n_pairs (always written when the call returns
- * SSS_OK or SSS_ERR_CAPACITY).
+ * Counts: the number of visible entries and the number of pairs the lists
+ * need (which may exceed pair_capacity).  The kernels read them on the
+ * device, so the work is enqueued without waiting for them:
+ *   no_wait = 0  the call waits once for the counts and writes n_visible and
+ *                n_pairs (host fields, also on SSS_ERR_CAPACITY); on
+ *                CAPACITY nothing after the count is enqueued.
+ *   no_wait = 1  the call never waits; n_visible and n_pairs are set to -1.
+ *                If the pairs exceed pair_capacity the lists hold only the
+ *                first pair_capacity emitted pairs (no write leaves the
+ *                buffers) and must not be used: the caller checks counts[1]
+ *                and calls again with a larger pair_rank and workspace.
+ *   counts       (device, nullable) receives (n_visible, required pairs) as
+ *                two uint64 on the stream, in either mode.
+ * The deterministic backward pass needs the host counts (no_wait = 0).
  * Workspace: ws of ws_bytes >= sss_bin_sort_workspace(n_entries, pair_capacity).
- * Errors: CAPACITY when n_pairs > pair_capacity (nothing after the count is
- * enqueued; re-allocate pair_rank and the workspace for n_pairs and call
- * again); INVALID for NULL pointers or a short workspace. */
+ * Errors: CAPACITY (no_wait = 0) when n_pairs > pair_capacity (re-allocate
+ * pair_rank and the workspace for n_pairs and call again); INVALID for NULL
+ * pointers or a short workspace; UNSUPPORTED for pair_capacity >= 2^32. */
 typedef struct {
   uint32_t* order;
   void* sorted_records;
@@ -232,8 +250,11 @@ typedef struct {
   uint32_t* tile_order;
   uint32_t* tile_work;
   int64_t pair_capacity;
-  int64_t n_visible;   /* out */
-  int64_t n_pairs;     /* out */
+  int64_t n_visible;   /* out (host; -1 with no_wait) */
+  int64_t n_pairs;     /* out (host; -1 with no_wait) */
+  uint64_t* counts;    /* nullable device [2]: n_visible, required pairs */
+  int32_t no_wait;     /* 1: enqueue everything without waiting for the counts */
+  int32_t reserved;
 } sss_bins_t;
 
 size_t sss_bin_sort_workspace(int64_t n_entries, int64_t pair_capacity);
@@ -273,7 +294,7 @@ int sss_render_fwd(const sss_bins_t* bins, const sss_camera_t* cams, int n_views
  *                           sums go to their own slot, then every entry sums
  *                           its slots in emission order, so gradients and
  *                           loss_out are bit-identical run to run.  Needs
- *                           bins->order and bins->rank_offset, proj->rect
+ *                           bins->order and bins->rank_offset, proj->entries
  *                           and the larger workspace
  *                           sss_render_bwd_workspace_det(n_entries,
  *                           bins->n_pairs, n_tiles).
@@ -367,6 +388,45 @@ typedef struct {
 int sss_sghmc_step(float* means, float* momentum, const float* grad_means, const float* opacity,
                    const float* scales, const float* quats, int64_t n,
                    const sss_sghmc_opts_t* opts, const sss_adam_t* adam, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sss_render_bwd_step -- sss_render_bwd followed by sss_sghmc_step with Adam
+ * on the other parameters, in one call: the projection backward applies the
+ * update to each component while its gradient (summed over the views) is
+ * still in registers, so the parameter gradients never go through memory.
+ * The result is that of the two calls in sequence: SGHMC on the means with
+ * the old opacity (and, with burn_in, the old scales and rotation), then
+ * Adam (bias-corrected with t) on scales, quats, nu, opacity and sh, each
+ * clamped to [lo, hi].
+ *   scene    read for the gradients; its six arrays are the ones updated,
+ *            given again, writable, in step->params (means, scales, quats,
+ *            nu, opacity, sh; each must equal the scene's pointer)
+ *   step     momentum [n][3] of the means; sghmc options (as
+ *            sss_sghmc_step); Adam beta1, beta2, eps, t >= 1 and per array
+ *            (scales, quats, nu, opacity, sh) the moments m, v of the
+ *            array's shape, lr, lo, hi; adam = 0 leaves those arrays as
+ *            they are
+ *   grads    nullable: when given, also receives the gradients (overwrite)
+ * Other arguments, modes, workspace and errors as sss_render_bwd
+ * (INVALID also for a NULL step, momentum or moment array, pointers that
+ * differ from the scene's, lr < 0 or t < 1). */
+typedef struct {
+  float* params[6];
+  float* momentum;
+  sss_sghmc_opts_t sghmc;
+  float beta1, beta2, eps;
+  int32_t adam;
+  int64_t t;
+  float* m[5];
+  float* v[5];
+  float lr[5], lo[5], hi[5];
+} sss_step_t;
+
+int sss_render_bwd_step(const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
+                        const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts, int mode, int loss,
+                        const float* dl_or_target, const float* image, const uint32_t* n_contrib,
+                        float* image_out, float* loss_out, const sss_grads_t* grads, const sss_step_t* step,
+                        void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * sss_loss -- the photometric loss of Sec. 3.4,

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include "common.hpp"
+#include "step.hpp"
 
 namespace sss {
 
@@ -161,8 +162,12 @@ int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
   if ((rc = check_opts(opts, "sss_project"))) return rc;
   CamBatch cb;
   if ((rc = make_cam_batch(cams, n_views, &cb))) return rc;
-  if (!out || !out->records || !out->depth_key || !out->rect || !out->tiles_touched || !out->ellipse) {
+  if (!out || !out->entries || !out->depth_key || !out->tiles_touched) {
     set_error("sss_project: output arrays must be non-null");
+    return SSS_ERR_INVALID;
+  }
+  if ((uintptr_t)out->entries & 15) {
+    set_error("sss_project: entries must be 16-byte aligned");
     return SSS_ERR_INVALID;
   }
   hipStream_t st = (hipStream_t)stream;
@@ -182,7 +187,7 @@ int sss_bin_sort(const sss_proj_t* proj, const sss_camera_t* cams, int n_views, 
   CamBatch cb;
   int rc = make_cam_batch(cams, n_views, &cb);
   if (rc) return rc;
-  if (!proj || !proj->records || !proj->depth_key || !proj->rect || !proj->tiles_touched || !proj->ellipse || !bins ||
+  if (!proj || !proj->entries || !proj->depth_key || !proj->tiles_touched || !bins ||
       !bins->order || !bins->sorted_records || !bins->tile_start || !bins->pair_rank || !ws || n <= 0 ||
       bins->pair_capacity < 0 || n > (int64_t)0xFFFFFFFF / SSS_MAX_VIEWS) {
     set_error("sss_bin_sort: null pointer, n <= 0 or negative pair capacity");
@@ -214,11 +219,57 @@ namespace sss {
 // workspace (noalloc.hip).  ws == nullptr asks for the size check only:
 // on success *need is the workspace size and nothing is enqueued; with a
 // workspace, the check and the launches.
+// Checks the fused update's arguments and fills its kernel arguments.
+static int make_step_args(const char* fn, const sss_scene_t* scene, const sss_step_t* step, StepArgs* sa) {
+  *sa = StepArgs{};
+  if (!step) return SSS_OK;
+  const float* want[6] = {scene->means, scene->scales, scene->quats, scene->nu, scene->opacity, scene->sh};
+  for (int k = 0; k < 6; ++k)
+    if (step->params[k] != want[k]) {
+      set_error("%s: step->params[%d] must be the scene's array", fn, k);
+      return SSS_ERR_INVALID;
+    }
+  if (!step->momentum || !(step->sghmc.lr >= 0.0f)) {
+    set_error("%s: step needs the momentum array and lr >= 0", fn);
+    return SSS_ERR_INVALID;
+  }
+  if (step->adam) {
+    if (step->t < 1) {
+      set_error("%s: Adam needs t >= 1", fn);
+      return SSS_ERR_INVALID;
+    }
+    for (int k = 0; k < 5; ++k)
+      if (!step->m[k] || !step->v[k]) {
+        set_error("%s: Adam moments of array %d are NULL", fn, k);
+        return SSS_ERR_INVALID;
+      }
+  }
+  sa->on = 1;
+  sa->means = step->params[0];
+  sa->scales = step->params[1];
+  sa->quats = step->params[2];
+  sa->nu = step->params[3];
+  sa->opac = step->params[4];
+  sa->sh = step->params[5];
+  sa->mom = step->momentum;
+  sa->sg = sghmc_args(step->sghmc);
+  sa->adam = step->adam ? 1 : 0;
+  if (step->adam) sa->ac = adam_const(step->beta1, step->beta2, step->eps, step->t);
+  for (int k = 0; k < 5; ++k) {
+    sa->m[k] = step->m[k];
+    sa->v[k] = step->v[k];
+    sa->lr[k] = step->lr[k];
+    sa->lo[k] = step->lo[k];
+    sa->hi[k] = step->hi[k];
+  }
+  return SSS_OK;
+}
+
 int render_bwd_impl(const char* fn, const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
                     const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts, int mode, int loss,
                     const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
-                    float* loss_out, const sss_grads_t* grads, void* ws, size_t ws_bytes, size_t* need_out,
-                    hipStream_t st) {
+                    float* loss_out, const sss_grads_t* grads, const sss_step_t* step, void* ws, size_t ws_bytes,
+                    size_t* need_out, hipStream_t st) {
   int rc = check_scene(scene, fn);
   if (rc) return rc;
   if ((rc = check_opts(opts, fn))) return rc;
@@ -235,19 +286,25 @@ int render_bwd_impl(const char* fn, const sss_scene_t* scene, const sss_proj_t* 
     return SSS_ERR_INVALID;
   }
   if (!proj || !proj->tiles_touched || !bins || !bins->sorted_records || !bins->tile_start || !bins->pair_rank ||
-      !dl_or_target || !grads) {
+      !dl_or_target || (!grads && !step)) {
     set_error("%s: null pointer", fn);
     return SSS_ERR_INVALID;
   }
+  StepArgs sa;
+  if ((rc = make_step_args(fn, scene, step, &sa))) return rc;
+  // with the fused update the gradients are optional, and written whole
+  sss_grads_t gr{};
+  if (grads) gr = *grads;
+  if (step) gr.overwrite = 1;
   if (mode == SSS_BWD_STORED && (!image || !n_contrib)) {
     set_error("%s: STORED mode needs image and n_contrib", fn);
     return SSS_ERR_INVALID;
   }
   const int64_t n_entries = scene->n * n_views;
-  if (det && (!bins->order || !bins->rank_offset || !proj->rect || !proj->ellipse || bins->n_pairs < 0 ||
+  if (det && (!bins->order || !bins->rank_offset || !proj->entries || bins->n_pairs < 0 ||
               bins->n_visible < 0 || bins->n_visible > n_entries)) {
-    set_error("%s: the deterministic mode needs bins->order, bins->rank_offset, proj->rect, proj->ellipse and the "
-              "counts of the sss_bin_sort call", fn);
+    set_error("%s: the deterministic mode needs bins->order, bins->rank_offset, proj->entries and the "
+              "host counts of an sss_bin_sort call that waited for them (no_wait = 0)", fn);
     return SSS_ERR_INVALID;
   }
   const size_t need = det ? render_bwd_det_workspace(n_entries, bins->n_pairs, cb.total_tiles)
@@ -267,14 +324,13 @@ int render_bwd_impl(const char* fn, const sss_scene_t* scene, const sss_proj_t* 
     da = carve_det(ws, n_entries, bins->n_pairs, cb.total_tiles, &g2);
     da.order = bins->order;
     da.rank_off = bins->rank_offset;
-    da.rects = (const ushort4*)proj->rect;
-    da.ell = (const Ellipse*)proj->ellipse;
+    da.ent = (const Entry*)proj->entries;
     da.n_pairs = (uint32_t)bins->n_pairs;
   }
   launch_zero((float*)g2, n_entries * kG2 * 2, st);
   launch_render_bwd(cb, op, *bins, mode, loss, dl_or_target, image, n_contrib, image_out, loss_out, g2,
                     total_pixels(cb), det, da, scene->n, st);
-  launch_project_bwd(cb, op, *scene, proj->tiles_touched, g2, *grads, st);
+  launch_project_bwd(cb, op, *scene, proj->tiles_touched, g2, gr, sa, st);
   return hip_ok(hipGetLastError(), fn) ? SSS_OK : SSS_ERR_HIP;
 }
 
@@ -292,7 +348,21 @@ int sss_render_bwd(const sss_scene_t* scene, const sss_proj_t* proj, const sss_b
     return SSS_ERR_INVALID;
   }
   return render_bwd_impl("sss_render_bwd", scene, proj, bins, cams, n_views, opts, mode, loss, dl_or_target, image,
-                         n_contrib, image_out, loss_out, grads, ws, ws_bytes, nullptr, (hipStream_t)stream);
+                         n_contrib, image_out, loss_out, grads, nullptr, ws, ws_bytes, nullptr, (hipStream_t)stream);
+}
+
+int sss_render_bwd_step(const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
+                        const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts, int mode, int loss,
+                        const float* dl_or_target, const float* image, const uint32_t* n_contrib,
+                        float* image_out, float* loss_out, const sss_grads_t* grads, const sss_step_t* step,
+                        void* ws, size_t ws_bytes, void* stream) {
+  if (!ws || !step) {
+    set_error("sss_render_bwd_step: null workspace or step");
+    return SSS_ERR_INVALID;
+  }
+  return render_bwd_impl("sss_render_bwd_step", scene, proj, bins, cams, n_views, opts, mode, loss, dl_or_target,
+                         image, n_contrib, image_out, loss_out, grads, step, ws, ws_bytes, nullptr,
+                         (hipStream_t)stream);
 }
 
 size_t sss_render_bwd_workspace_det(int64_t n_entries, int64_t n_pairs, int64_t n_tiles) {

@@ -84,8 +84,9 @@ OptsDev make_opts(const sss_render_opts_t* o);
 // launchers (stream is hipStream_t)
 void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
                     const sss_proj_t& out, hipStream_t st);
+struct StepArgs;
 void launch_project_bwd(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
-                        const uint32_t* touched, const double* g2, const sss_grads_t& g,
+                        const uint32_t* touched, double* g2, const sss_grads_t& g, const StepArgs& sa,
                         hipStream_t st);
 int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins_t* bins,
                  void* ws, size_t ws_bytes, hipStream_t st);
@@ -99,12 +100,21 @@ struct Ellipse {
   double A, B, D, hr;
 };
 
+// One projected entry (the layout sss.h states): the raster record, the
+// FP64 ellipse and the tile rectangle in one 128-byte line.
+struct __align__(16) Entry {
+  Rec rec;
+  Ellipse ell;
+  ushort4 rect;
+  uint32_t pad[6];
+};
+static_assert(sizeof(Entry) == SSS_ENTRY_BYTES, "entry size");
+
 // Buffers of the deterministic backward pass (see raster.hip).
 struct DetArgs {
   const uint32_t* order;      // rank -> entry
   const uint32_t* rank_off;   // first emission position of each rank
-  const ushort4* rects;       // per-entry tile rectangles
-  const Ellipse* ell;         // per-entry ellipses
+  const Entry* ent;           // projected entries (tile rectangles and ellipses)
   float* part;                // [n_pairs][kG2] per-pair sums
   uint32_t* lastp1;           // [n_tiles] last visited rank + 1
   float* loss_part;           // [n_tiles] per-tile loss (both modes)
@@ -112,6 +122,8 @@ struct DetArgs {
   const uint32_t* tile_order; // launch order (nullable: row-major) of tiles, or of units if unit_order
   int32_t unit_order;
   uint32_t n_pairs;           // bound of the slots (part has n_pairs rows)
+  uint32_t* queue;            // work counter of the persistent backward (zeroed before the launch)
+  uint32_t n_units;           // launch slots of the backward
 };
 // Items (tiles or units) sorted by a coarse bucket of their cost, most
 // expensive first.  The cost of item t is the largest of
@@ -133,8 +145,8 @@ void launch_zero(float* p, int64_t count, hipStream_t st);
 int render_bwd_impl(const char* fn, const sss_scene_t* scene, const sss_proj_t* proj, const sss_bins_t* bins,
                     const sss_camera_t* cams, int n_views, const sss_render_opts_t* opts, int mode, int loss,
                     const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
-                    float* loss_out, const sss_grads_t* grads, void* ws, size_t ws_bytes, size_t* need_out,
-                    hipStream_t st);
+                    float* loss_out, const sss_grads_t* grads, const sss_step_t* step, void* ws, size_t ws_bytes,
+                    size_t* need_out, hipStream_t st);
 size_t relocate_workspace(int64_t n, double max_fraction);
 size_t loss_workspace(int64_t total_pixels);
 void launch_loss(const CamBatch& cb, const float* img, const float* tgt, float lam, float* dl, float* loss_out,

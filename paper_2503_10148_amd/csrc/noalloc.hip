@@ -63,7 +63,7 @@ extern "C" int sss_render_bwd_noalloc(const sss_scene_t* scene, const sss_proj_t
   // arguments and the workspace size first: nothing is enqueued
   size_t need = 0;
   int rc = render_bwd_impl(fn, scene, proj, bins, cams, n_views, opts, mode, loss, dl_or_target, image, n_contrib,
-                           image_out, loss_out, grads, nullptr, 0, &need, st);
+                           image_out, loss_out, grads, nullptr, nullptr, 0, &need, st);
   if (rc) return rc;
   if (need > kScratchBytes) {
     set_error("%s: the call needs a workspace of %zu bytes and the library holds %zu (SSS_NOALLOC_WORKSPACE_BYTES); "
@@ -73,5 +73,5 @@ extern "C" int sss_render_bwd_noalloc(const sss_scene_t* scene, const sss_proj_t
   void* ws = nullptr;
   if ((rc = scratch_address(&ws))) return rc;
   return render_bwd_impl(fn, scene, proj, bins, cams, n_views, opts, mode, loss, dl_or_target, image, n_contrib,
-                         image_out, loss_out, grads, ws, kScratchBytes, nullptr, st);
+                         image_out, loss_out, grads, nullptr, ws, kScratchBytes, nullptr, st);
 }

@@ -8,6 +8,7 @@
 // is exact to far below a pixel's 1e-6; results are stored in FP32 except the
 // mean, which the record keeps in FP64.
 #include "common.hpp"
+#include "step.hpp"
 #include "tiles.hpp"
 
 namespace sss {
@@ -234,29 +235,27 @@ __device__ __forceinline__ void stage_sh(const float* __restrict__ sh, int64_t i
   }
 }
 
+// One entry: writes its depth key and (0 when culled) tile count, and
+// returns true with the entry's line in `out` when it is listed anywhere.
 template <int DEG>
-__global__ __launch_bounds__(kBlock) void project_kernel(
-    CamBatch cb, OptsDev op, int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
-    const float* __restrict__ quats, const float* __restrict__ nu, const float* __restrict__ opac,
-    const float* __restrict__ sh, Rec* __restrict__ rec, uint32_t* __restrict__ keys, ushort4* __restrict__ rects,
-    uint32_t* __restrict__ touched, Ellipse* __restrict__ ell) {
+__device__ __forceinline__ bool project_entry(const CamDev& c, const OptsDev& op, int64_t i, int64_t e,
+                                              const float* __restrict__ means, const float* __restrict__ scales,
+                                              const float* __restrict__ quats, const float* __restrict__ nu,
+                                              const float* __restrict__ opac, const float* __restrict__ sh,
+                                              uint32_t* __restrict__ keys, uint32_t* __restrict__ touched,
+                                              Entry& out) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  const int v = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const CamDev& c = cb.v[v];
-  const int64_t e = (int64_t)v * n + i;
   const float* mu = means + 3 * i;
 
   const float zf = fmaf(c.R[6], mu[0], fmaf(c.R[7], mu[1], fmaf(c.R[8], mu[2], c.t[2])));
   keys[e] = __float_as_uint(zf);
   touched[e] = 0;
   const float o = opac[i];
-  if (!(zf > op.z_near) || !(fabsf(o) >= op.alpha_min)) return;
+  if (!(zf > op.z_near) || !(fabsf(o) >= op.alpha_min)) return false;
 
   Geo<double> g;
   geometry<double>(c, op, mu, scales + 3 * i, quats + 4 * i, g);
-  if (!(g.qn > 0.0) || !(g.det > 0.0)) return;
+  if (!(g.qn > 0.0) || !(g.det > 0.0)) return false;
 
   const double mx = c.fx * g.xz + c.cx, my = c.fy * g.yz + c.cy;
   const double nuc = fmin(fmax((double)nu[i], (double)op.nu_min), (double)op.nu_max);
@@ -274,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     const double erx = sqrt(hr * g.A), ery = sqrt(hr * g.D);
     const double lx = (mx - erx) * (1.0 / kTile), hx = (mx + erx) * (1.0 / kTile);
     const double ly = (my - ery) * (1.0 / kTile), hy = (my + ery) * (1.0 / kTile);
-    if (hx < 0.0 || lx >= c.tiles_x || hy < 0.0 || ly >= c.tiles_y) return;
+    if (hx < 0.0 || lx >= c.tiles_x || hy < 0.0 || ly >= c.tiles_y) return false;
     x0 = (int)fmax(0.0, floor(lx)); x1 = (int)fmin((double)(c.tiles_x - 1), floor(hx));
     y0 = (int)fmax(0.0, floor(ly)); y1 = (int)fmin((double)(c.tiles_y - 1), floor(hy));
   } else {
@@ -290,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     int t0;
     count += row_run(rg, ty, x0, x1, &t0);
   }
-  if (count == 0) return;
+  if (count == 0) return false;
 
   double dir[3], vn;
   view_dir<double>(c, mu, dir, &vn);
@@ -335,10 +334,50 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   r.hs = (float)hs;
   r.entry = (uint32_t)e;
   r.ey = (float)ey;
-  rec[e] = r;
-  rects[e] = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1);
-  ell[e] = el;
+  out.rec = r;
+  out.ell = el;
+  out.rect = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out.pad[k] = 0u;
   touched[e] = (uint32_t)count;
+  return true;
+}
+
+// Per (view, component): project_entry, then the block's entry lines go out
+// through LDS: each thread stages its 128-byte line (its eight 16-byte parts
+// rotated by the thread number, against bank conflicts), and each wave
+// writes its 64 threads' lines as eight contiguous 1 KB runs, whole lines
+// only (a per-thread 128-byte store pattern measured 30% slower; culled
+// entries' lines are not written).
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void project_kernel(
+    CamBatch cb, OptsDev op, int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
+    const float* __restrict__ quats, const float* __restrict__ nu, const float* __restrict__ opac,
+    const float* __restrict__ sh, Entry* __restrict__ ent, uint32_t* __restrict__ keys,
+    uint32_t* __restrict__ touched) {
+  __shared__ uint4 stage[kBlock * 8];
+  const int v = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+  const int64_t i = i0 + threadIdx.x;
+  const CamDev& c = cb.v[v];
+  const int64_t e = (int64_t)v * n + i;
+  Entry out;
+  const bool listed = i < n && project_entry<DEG>(c, op, i, e, means, scales, quats, nu, opac, sh, keys, touched, out);
+  if (listed) {
+    const uint4* src = reinterpret_cast<const uint4*>(&out);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) stage[threadIdx.x * 8 + ((k + threadIdx.x) & 7)] = src[k];
+  }
+  const uint64_t wave_listed = __ballot(listed);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t wave_i0 = i0 + 64 * w;
+  uint4* dst = reinterpret_cast<uint4*>(ent + (int64_t)v * n + wave_i0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int j = 8 * k + (lane >> 3), part = lane & 7;   // entry within the wave, its 16-byte part
+    if ((wave_listed >> j) & 1ull) dst[8 * j + part] = stage[(64 * w + j) * 8 + ((part + j) & 7)];
+  }
 }
 
 // Backward of the geometry: per component, sum over views of the chain from
@@ -346,15 +385,30 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
 // FP32; the SH part is sh_bwd_kernel.  d_means is always accumulated (+=):
 // sh_bwd_kernel runs first and initialises it when overwriting.
 __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
-    CamBatch cb, OptsDev op, int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
-    const float* __restrict__ quats, const float* __restrict__ nu, const uint32_t* __restrict__ touched,
-    const double* __restrict__ g2, float* __restrict__ d_means, float* __restrict__ d_scales,
-    float* __restrict__ d_quats, float* __restrict__ d_nu, float* __restrict__ d_opac, int overwrite) {
+    CamBatch cb, OptsDev op, int64_t n, const float* means, const float* scales, const float* quats, const float* nu,
+    const uint32_t* __restrict__ touched, const double* __restrict__ g2, float* __restrict__ d_means,
+    float* __restrict__ d_scales, float* __restrict__ d_quats, float* __restrict__ d_nu, float* __restrict__ d_opac,
+    int overwrite, StepArgs sa) {
+  // means, scales, quats and nu are not __restrict__: with sa.on the same
+  // arrays are written through sa after this thread's reads
   using F = float;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const float* mu = means + 3 * i;
   const float* s = scales + 3 * i;
+  // the update's state does not depend on the gradient: its loads are
+  // issued first, so their latency hides behind the arithmetic below
+  float st_r[3], st_m[9], st_v[9], st_o = 0.0f;
+  if (sa.on) {
+    for (int a = 0; a < 3; ++a) st_r[a] = sa.mom[3 * i + a];
+    st_o = sa.opac[i];
+    if (sa.adam) {
+      for (int a = 0; a < 3; ++a) { st_m[a] = sa.m[0][3 * i + a]; st_v[a] = sa.v[0][3 * i + a]; }
+      for (int a = 0; a < 4; ++a) { st_m[3 + a] = sa.m[1][4 * i + a]; st_v[3 + a] = sa.v[1][4 * i + a]; }
+      st_m[7] = sa.m[2][i]; st_v[7] = sa.v[2][i];
+      st_m[8] = sa.m[3][i]; st_v[8] = sa.v[3][i];
+    }
+  }
   F gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0};
   F gnu = 0, gop = 0;
   bool any = false;
@@ -449,10 +503,50 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     const F dq = gu[0] * g.q[0] + gu[1] * g.q[1] + gu[2] * g.q[2] + gu[3] * g.q[3];
     for (int a = 0; a < 4; ++a) gq[a] += (gu[a] - g.q[a] * dq) / g.qn;
   }
-  if (!any && !overwrite) return;
+  if (!any && !overwrite && !sa.on) return;
   const float nv = nu[i];
   if (!(nv >= op.nu_min && nv <= op.nu_max) || op.family == SSS_FAMILY_GAUSSIAN) gnu = 0;
   if (d_means) for (int a = 0; a < 3; ++a) d_means[3 * i + a] += gmu[a];
+  if (sa.on) {
+    // the component's whole gradient is here: the SH part of d_means left by
+    // sh_bwd_kernel in the unused slots of the entry's screen-space record,
+    // plus the geometric part; SGHMC on the mean with the old opacity (and
+    // old scales and rotation for burn-in), then Adam on the other arrays
+    const float* part = reinterpret_cast<const float*>(g2 + (size_t)i * kG2 + 10);
+    const float G[3] = {part[0] + gmu[0], part[1] + gmu[1], part[2] + gmu[2]};
+    float mu_i[3] = {mu[0], mu[1], mu[2]}, si[3] = {s[0], s[1], s[2]};
+    const float4 q = *reinterpret_cast<const float4*>(quats + 4 * i);
+    sghmc_one(i, mu_i, st_r, G, st_o, q, si, sa.sg);
+    for (int a = 0; a < 3; ++a) {
+      sa.means[3 * i + a] = mu_i[a];
+      sa.mom[3 * i + a] = st_r[a];
+    }
+    if (sa.adam) {
+      float qq[4] = {q.x, q.y, q.z, q.w};
+      float op_i = st_o, nu_i = nv;
+      for (int a = 0; a < 3; ++a) adam_one(si[a], gs[a], st_m[a], st_v[a], sa.lr[0], sa.lo[0], sa.hi[0], sa.ac);
+      for (int a = 0; a < 4; ++a)
+        adam_one(qq[a], gq[a], st_m[3 + a], st_v[3 + a], sa.lr[1], sa.lo[1], sa.hi[1], sa.ac);
+      adam_one(nu_i, gnu, st_m[7], st_v[7], sa.lr[2], sa.lo[2], sa.hi[2], sa.ac);
+      adam_one(op_i, gop, st_m[8], st_v[8], sa.lr[3], sa.lo[3], sa.hi[3], sa.ac);
+      for (int a = 0; a < 3; ++a) {
+        sa.scales[3 * i + a] = si[a];
+        sa.m[0][3 * i + a] = st_m[a];
+        sa.v[0][3 * i + a] = st_v[a];
+      }
+      *reinterpret_cast<float4*>(sa.quats + 4 * i) = make_float4(qq[0], qq[1], qq[2], qq[3]);
+      for (int a = 0; a < 4; ++a) {
+        sa.m[1][4 * i + a] = st_m[3 + a];
+        sa.v[1][4 * i + a] = st_v[3 + a];
+      }
+      sa.nu[i] = nu_i;
+      sa.m[2][i] = st_m[7];
+      sa.v[2][i] = st_v[7];
+      sa.opac[i] = op_i;
+      sa.m[3][i] = st_m[8];
+      sa.v[3][i] = st_v[8];
+    }
+  }
   if (overwrite) {
     if (d_scales) for (int a = 0; a < 3; ++a) d_scales[3 * i + a] = gs[a];
     if (d_quats) for (int a = 0; a < 4; ++a) d_quats[4 * i + a] = gq[a];
@@ -473,11 +567,11 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
 // d_sh and are written back coalesced.  d_means is written (overwrite) or
 // accumulated; project_bwd_kernel adds the geometric part afterwards.
 template <int DEG>
-__global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, const float* __restrict__ means,
-                                                        const float* __restrict__ sh,
+__global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, const float* means,
+                                                        const float* sh,
                                                         const uint32_t* __restrict__ touched,
-                                                        const double* __restrict__ g2, float* __restrict__ d_means,
-                                                        float* __restrict__ d_sh, int overwrite) {
+                                                        double* __restrict__ g2, float* __restrict__ d_means,
+                                                        float* __restrict__ d_sh, int overwrite, StepArgs sa) {
   using F = float;
   constexpr int K = (DEG + 1) * (DEG + 1), KC = 3 * K, STR = KC + 1;
   __shared__ float shs[kBlock * STR];
@@ -528,6 +622,12 @@ __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, 
       if (overwrite) for (int a = 0; a < 3; ++a) d_means[3 * i + a] = gmu[a];
       else for (int a = 0; a < 3; ++a) d_means[3 * i + a] += gmu[a];
     }
+    if (sa.on) {
+      // for project_bwd_kernel's update: the two unused slots of entry i's
+      // screen-space record (view 0) hold this part of d_means
+      float* part = reinterpret_cast<float*>(g2 + (size_t)i * kG2 + 10);
+      for (int a = 0; a < 3; ++a) part[a] = gmu[a];
+    }
     // the SH values of this slot are no longer needed: accumulate d_sh in it
     for (int j = 0; j < KC; ++j) slot[j] = 0.0f;
     for (int v = 0; v < cb.n_views; ++v) {
@@ -549,6 +649,38 @@ __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, 
     }
   }
   __syncthreads();
+  if (sa.on && sa.adam) {
+    // Adam on the block's SH coefficients, coalesced, with the gradient
+    // from LDS: rounds of kShAdamIt elements per thread (256 apart), all
+    // their loads issued before any update; every element is touched once
+    // per step (streaming access)
+    constexpr int kShAdamIt = 4;
+    const size_t o0 = (size_t)i0 * KC;
+    const int total = cnt * KC;
+    for (int g0 = threadIdx.x; g0 < total; g0 += kShAdamIt * kBlock) {
+      float p[kShAdamIt], m[kShAdamIt], v[kShAdamIt];
+#pragma unroll
+      for (int k = 0; k < kShAdamIt; ++k) {
+        const int g = g0 + k * kBlock;
+        if (g < total) {
+          p[k] = __builtin_nontemporal_load(sa.sh + o0 + g);
+          m[k] = __builtin_nontemporal_load(sa.m[4] + o0 + g);
+          v[k] = __builtin_nontemporal_load(sa.v[4] + o0 + g);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kShAdamIt; ++k) {
+        const int g = g0 + k * kBlock;
+        if (g < total) {
+          const int c = g / KC, j = g - c * KC;
+          adam_one(p[k], shs[c * STR + j], m[k], v[k], sa.lr[4], sa.lo[4], sa.hi[4], sa.ac);
+          __builtin_nontemporal_store(p[k], sa.sh + o0 + g);
+          __builtin_nontemporal_store(m[k], sa.m[4] + o0 + g);
+          __builtin_nontemporal_store(v[k], sa.v[4] + o0 + g);
+        }
+      }
+    }
+  }
   if (!d_sh) return;
   float* dst = d_sh + (size_t)i0 * KC;
   for (int g = threadIdx.x; g < cnt * KC; g += kBlock) {
@@ -565,8 +697,7 @@ void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
   dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock), (unsigned)cb.n_views);
 #define SSS_PROJ(D)                                                                                          \
   SSS_LAUNCH("project", project_kernel<D>, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, s.means, s.scales, \
-             s.quats, s.nu, s.opacity, s.sh, (Rec*)out.records, out.depth_key, (ushort4*)out.rect,            \
-             out.tiles_touched, (Ellipse*)out.ellipse)
+             s.quats, s.nu, s.opacity, s.sh, (Entry*)out.entries, out.depth_key, out.tiles_touched)
   switch (s.sh_degree) {
     case 0: SSS_PROJ(0); break;
     case 1: SSS_PROJ(1); break;
@@ -577,11 +708,11 @@ void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s,
 }
 
 void launch_project_bwd(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s, const uint32_t* touched,
-                        const double* g2, const sss_grads_t& gr, hipStream_t st) {
+                        double* g2, const sss_grads_t& gr, const StepArgs& sa, hipStream_t st) {
   dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock));
 #define SSS_SHB(D)                                                                                         \
   SSS_LAUNCH("sh_bwd", sh_bwd_kernel<D>, grid, dim3(kBlock), 0, st, cb, (int64_t)s.n, s.means, s.sh, touched, \
-             g2, gr.means, gr.sh, (int)gr.overwrite)
+             g2, gr.means, gr.sh, (int)gr.overwrite, sa)
   switch (s.sh_degree) {
     case 0: SSS_SHB(0); break;
     case 1: SSS_SHB(1); break;
@@ -590,7 +721,8 @@ void launch_project_bwd(const CamBatch& cb, const OptsDev& op, const sss_scene_t
   }
 #undef SSS_SHB
   SSS_LAUNCH("project_bwd", project_bwd_kernel, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, s.means, s.scales,
-             s.quats, s.nu, touched, g2, gr.means, gr.scales, gr.quats, gr.nu, gr.opacity, (int)gr.overwrite);
+             s.quats, s.nu, touched, (const double*)g2, gr.means, gr.scales, gr.quats, gr.nu, gr.opacity,
+             (int)gr.overwrite, sa);
 }
 
 }  // namespace sss

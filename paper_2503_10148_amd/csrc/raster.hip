@@ -143,11 +143,13 @@ __device__ __forceinline__ void evaluate(float px, float py, const R& L, float a
     E.l2 = E.h;
   } else {
     // T2D = (1 + h/nu)^(-(nu+2)/2) = 2^(nb log2(1 + y)), y = h/nu.  log2(1 + y)
-    // is corrected by the rounding error of u = 1 + y while u < 2.
+    // is corrected by the rounding error of u = 1 + y, which y - (u - 1) gives
+    // exactly for every u (both subtractions are exact), taken with the slope
+    // log2(e) of log2 at u = 1: where the slope 1/u differs the correction is
+    // below 1e-7 relative, and with |nb| large there T2D is far below alpha_min.
     E.y = E.h * L.inv_nu;
     E.u = 1.0f + E.y;
-    const float z = E.u - 1.0f;
-    const float corr = E.u < 2.0f ? (E.y - z) : 0.0f;
+    const float corr = E.y - (E.u - 1.0f);
     E.l2 = __fmaf_rn(corr, kLog2e, __builtin_amdgcn_logf(E.u));
   }
   E.t2 = __builtin_amdgcn_exp2f(L.nb * E.l2);
@@ -250,20 +252,21 @@ struct TileCtx {
 
 template <int PIX>
 __device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint32_t* __restrict__ tile_start,
-                                                 const uint32_t* __restrict__ order, bool unit_order) {
+                                                 const uint32_t* __restrict__ order, bool unit_order, uint32_t blk) {
   TileCtx<PIX> t;
   // The units with the most work are launched first, so that they do not
-  // run alone at the end of the grid: with a unit order, workgroup b renders
-  // unit order[b]; with a tile order, the units of tile order[b / units]
-  // follow each other.
+  // run alone at the end of the grid: with a unit order, launch slot blk
+  // renders unit order[blk]; with a tile order, the units of tile
+  // order[blk / units] follow each other.  blk is the workgroup number, or
+  // in the persistent backward the number a wave took from the work queue.
   uint32_t gu, sub;
   if (unit_order) {
-    const uint32_t u = order[blockIdx.x];
+    const uint32_t u = order[blk];
     gu = u / kUnits<PIX>;
     sub = u % kUnits<PIX>;
   } else {
-    const uint32_t b = blockIdx.x / kUnits<PIX>;
-    sub = blockIdx.x % kUnits<PIX>;
+    const uint32_t b = blk / kUnits<PIX>;
+    sub = blk % kUnits<PIX>;
     gu = order ? order[b] : b;
   }
   t.g = (int)gu;
@@ -354,8 +357,8 @@ __device__ __forceinline__ uint64_t stage_batch_slot(const TileCtx<PIX>& t, cons
     const uint32_t rank = pair_rank[k];
     uint32_t e;
     m = stage(srec, rank, t.ox, t.oy, lds + threadIdx.x, &e);
-    const ushort4 rc = det.rects[e];
-    const RowGeo g = make_row_geo(srec[rank].mx, srec[rank].my, det.ell[e]);
+    const ushort4 rc = det.ent[e].rect;
+    const RowGeo g = make_row_geo(srec[rank].mx, srec[rank].my, det.ent[e].ell);
     uint32_t pos = det.rank_off[rank];
     int t0;
     for (int ty = rc.y; ty < t.ty; ++ty) pos += (uint32_t)row_run(g, ty, rc.x, rc.z, &t0);
@@ -483,7 +486,7 @@ __global__ __launch_bounds__(kUnitThreads) void render_fwd_kernel(CamBatch cb, O
                                                                   const uint32_t* __restrict__ tile_order,
                                                                   uint32_t* __restrict__ tile_work) {
   __shared__ FRec lds[kUnitThreads];
-  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, tile_order, false);
+  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, tile_order, false, blockIdx.x);
   if (t.skip) return;
   float C[PIX][3], T[PIX];
   uint32_t last[PIX];
@@ -509,16 +512,17 @@ __global__ __launch_bounds__(kUnitThreads) void render_fwd_kernel(CamBatch cb, O
   }
 }
 
+// One unit of the backward pass (launch slot blk).
 template <int PIX, int kMode, int kLoss, bool kDet, bool kGauss>
-__global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
-    CamBatch cb, OptsDev op, const Rec* __restrict__ srec, const uint32_t* __restrict__ tile_start,
-    const uint32_t* __restrict__ pair_rank, const float* __restrict__ dl_or_target, const float* __restrict__ image,
-    const uint32_t* __restrict__ n_contrib, float* __restrict__ image_out, float* __restrict__ loss_out,
-    float inv_count, double* __restrict__ g2, DetArgs det) {
+__device__ __forceinline__ void render_bwd_unit(
+    uint32_t blk, LRec* lds, const CamBatch& cb, const OptsDev& op, const Rec* __restrict__ srec,
+    const uint32_t* __restrict__ tile_start, const uint32_t* __restrict__ pair_rank,
+    const float* __restrict__ dl_or_target, const float* __restrict__ image, const uint32_t* __restrict__ n_contrib,
+    float* __restrict__ image_out, float* __restrict__ loss_out, float inv_count, double* __restrict__ g2,
+    const DetArgs& det) {
   static_assert(!kDet || PIX == 4, "the deterministic variant runs one unit per tile");
   constexpr uint32_t kBatch = kUnitThreads;
-  __shared__ LRec lds[kBatch];
-  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, det.tile_order, det.unit_order != 0);
+  const TileCtx<PIX> t = tile_ctx<PIX>(cb, tile_start, det.tile_order, det.unit_order != 0, blk);
   if (t.skip) return;
   const int lane = threadIdx.x & 63;
 
@@ -702,6 +706,34 @@ __global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
   }
 }
 
+// kQueue: a persistent grid (as many waves as are resident); each wave takes
+// launch slots from the work counter det.queue, in launch order, until the
+// counter passes det.n_units (every wave reaches that exit).  Otherwise one
+// workgroup per unit.
+template <int PIX, int kMode, int kLoss, bool kDet, bool kGauss, bool kQueue>
+__global__ __launch_bounds__(kUnitThreads) void render_bwd_kernel(
+    CamBatch cb, OptsDev op, const Rec* __restrict__ srec, const uint32_t* __restrict__ tile_start,
+    const uint32_t* __restrict__ pair_rank, const float* __restrict__ dl_or_target, const float* __restrict__ image,
+    const uint32_t* __restrict__ n_contrib, float* __restrict__ image_out, float* __restrict__ loss_out,
+    float inv_count, double* __restrict__ g2, DetArgs det) {
+  __shared__ LRec lds[kUnitThreads];
+  if constexpr (kQueue) {
+    for (;;) {
+      uint32_t b = 0;
+      if (threadIdx.x == 0) b = atomicAdd(det.queue, 1u);
+      b = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)b, 0, 64));
+      if (b >= det.n_units) break;
+      render_bwd_unit<PIX, kMode, kLoss, kDet, kGauss>(b, lds, cb, op, srec, tile_start, pair_rank, dl_or_target,
+                                                        image, n_contrib, image_out, loss_out, inv_count, g2, det);
+      __syncthreads();   // the next unit restages the LDS batch
+    }
+  } else {
+    render_bwd_unit<PIX, kMode, kLoss, kDet, kGauss>(blockIdx.x, lds, cb, op, srec, tile_start, pair_rank,
+                                                      dl_or_target, image, n_contrib, image_out, loss_out, inv_count,
+                                                      g2, det);
+  }
+}
+
 // One step of a segmented inclusive scan over the wave: the value of the
 // lane the DPP control selects is added where that lane has the same key
 // (keys are non-decreasing over lanes and >= 1; lanes outside the row or
@@ -752,8 +784,8 @@ __global__ __launch_bounds__(kBlock) void det_reduce_kernel(CamBatch cb, int64_t
     const uint32_t e = det.order[r];
     my_e = (int)e;
     my_off = det.rank_off[r];
-    rc = det.rects[e];
-    el = det.ell[e];
+    rc = det.ent[e].rect;
+    el = det.ent[e].ell;
     mx = srec[r].mx;
     my = srec[r].my;
     const int v = (int)(e / (uint64_t)n);
@@ -1024,8 +1056,9 @@ size_t render_bwd_det_workspace(int64_t n_entries, int64_t n_pairs, int64_t n_ti
 // Workspace of the atomic mode: screen-space gradients [E][kG2] FP64, the
 // per-unit loss values [4T] and the unit order [4T].
 size_t render_bwd_workspace(int64_t n_entries, int64_t n_tiles) {
+  // screen-space sums, per-unit loss, unit order, work counter (16 B)
   return align256(sizeof(double) * kG2 * (size_t)n_entries) + align256(sizeof(float) * 4 * (size_t)n_tiles) +
-         sizeof(uint32_t) * 4 * (size_t)n_tiles;
+         align256(sizeof(uint32_t) * 4 * (size_t)n_tiles) + 16;
 }
 
 DetArgs carve_bwd(void* ws, int64_t n_entries, int64_t n_tiles, double** g2) {
@@ -1036,6 +1069,8 @@ DetArgs carve_bwd(void* ws, int64_t n_entries, int64_t n_tiles, double** g2) {
   d.loss_part = (float*)p;
   p += align256(sizeof(float) * 4 * (size_t)n_tiles);
   d.order_ws = (uint32_t*)p;
+  p += align256(sizeof(uint32_t) * 4 * (size_t)n_tiles);
+  d.queue = (uint32_t*)p;
   return d;
 }
 
@@ -1083,6 +1118,30 @@ void launch_render_fwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
 #undef SSS_FWD
 }
 
+// The recompute-mode backward as one persistent launch over a work queue
+// (see render_bwd_kernel) when SSS_BWD_PERSISTENT=1; off by default: on the
+// 3M- and 5M-component workloads it measured 12-18% slower than one
+// workgroup per unit in launch order.
+static bool persistent_recompute() {
+  static const int on = env_pix("SSS_BWD_PERSISTENT", 0);
+  return on != 0;
+}
+
+// Waves of a persistent grid: what the occupancy lets every CU hold, and no
+// more than there are units.
+static unsigned resident_waves(const void* kernel, int64_t units) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kUnitThreads, 0) != hipSuccess || per_cu < 1 ||
+      cus < 1) {
+    cus = 256;
+    per_cu = 8;
+  }
+  const int64_t w = (int64_t)cus * per_cu;
+  return (unsigned)(w < units ? w : (units > 0 ? units : 1));
+}
+
 void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& b, int mode, int loss,
                        const float* dl_or_target, const float* image, const uint32_t* n_contrib, float* image_out,
                        float* loss_out, double* g2, int64_t total_pixels, bool det_mode, const DetArgs& dargs,
@@ -1107,14 +1166,15 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
   }
   const float inv_count = 1.0f / (3.0f * (float)total_pixels);
   const dim3 grid((unsigned)units);
+  da.n_units = (uint32_t)units;
   const Rec* sr = (const Rec*)b.sorted_records;
   const uint32_t* ts = b.tile_start;
   const uint32_t* pr = b.pair_rank;
   const bool gauss = op.family == SSS_FAMILY_GAUSSIAN;
   if (det_mode) {
 #define SSS_BWD_DET1(M, L, G)                                                                                       \
-  SSS_LAUNCH("render_bwd", (render_bwd_kernel<4, M, L, true, G>), grid, dim3(kUnitThreads), 0, st, cb, op, sr, ts, \
-             pr, dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da)
+  SSS_LAUNCH("render_bwd", (render_bwd_kernel<4, M, L, true, G, false>), grid, dim3(kUnitThreads), 0, st, cb, op, sr, \
+             ts, pr, dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da)
 #define SSS_BWD_DET(M, L)            \
   if (gauss) SSS_BWD_DET1(M, L, true); \
   else SSS_BWD_DET1(M, L, false)
@@ -1131,9 +1191,18 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                  (uint32_t)b.n_pairs, sr, da, g2);
     }
   } else {
-#define SSS_BWD1(P, M, L, G)                                                                                   \
-  SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L, false, G>), grid, dim3(kUnitThreads), 0, st, cb, op, sr, ts, \
-             pr, dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da)
+#define SSS_BWD1(P, M, L, G)                                                                                  \
+  do {                                                                                                        \
+    if (M == SSS_BWD_RECOMPUTE && persistent_recompute()) {                                                  \
+      auto kern = render_bwd_kernel<P, SSS_BWD_RECOMPUTE, L, false, G, true>;                                  \
+      launch_zero((float*)da.queue, 4, st);                                                                   \
+      SSS_LAUNCH("render_bwd", kern, dim3(resident_waves((const void*)kern, units)), dim3(kUnitThreads), 0, st,  \
+                 cb, op, sr, ts, pr, dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da);    \
+    } else {                                                                                                  \
+      SSS_LAUNCH("render_bwd", (render_bwd_kernel<P, M, L, false, G, false>), grid, dim3(kUnitThreads), 0, st,  \
+                 cb, op, sr, ts, pr, dl_or_target, image, n_contrib, image_out, loss_out, inv_count, g2, da);    \
+    }                                                                                                         \
+  } while (0)
 #define SSS_BWD(P, M, L)                 \
   do {                                   \
     if (gauss) SSS_BWD1(P, M, L, true);  \

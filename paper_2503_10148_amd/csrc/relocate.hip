@@ -15,6 +15,7 @@
 //     FP64; the moved components' optimiser state rows are zeroed.
 // Every count stays on the device; grids are sized by the cap.
 #include "common.hpp"
+#include "step.hpp"
 #include "scan.hpp"
 
 namespace sss {
@@ -47,24 +48,13 @@ __global__ __launch_bounds__(kBlock) void rl_dead_list_kernel(const uint32_t* __
   if (i < n && flag[i] && (int64_t)pos[i] < cap) dead[pos[i]] = (uint32_t)i;
 }
 
-__device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-    k.x += 0x9E3779B9u;
-    k.y += 0xBB67AE85u;
-  }
-  return c;
-}
-
 __global__ __launch_bounds__(kBlock) void rl_draw_kernel(const unsigned long long* __restrict__ excl, int64_t n,
                                                          const unsigned long long* __restrict__ counts, int64_t cap,
                                                          uint64_t seed, uint64_t step, uint32_t* __restrict__ target,
                                                          uint32_t* __restrict__ hits) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= cap || j >= (int64_t)counts[0] || counts[1] == 0) return;
-  const uint4 x = philox(make_uint4((uint32_t)j, (uint32_t)step, (uint32_t)(step >> 32), 0x80000000u | (uint32_t)(j >> 32)),
+  const uint4 x = philox4x32_10(make_uint4((uint32_t)j, (uint32_t)step, (uint32_t)(step >> 32), 0x80000000u | (uint32_t)(j >> 32)),
                          make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
   const unsigned long long r = ((unsigned long long)x.y << 32) | x.x;
   const unsigned long long pos = __umul64hi(r, counts[1]);

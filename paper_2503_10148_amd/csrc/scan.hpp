@@ -46,10 +46,23 @@ __device__ __forceinline__ T block_excl_scan(T v, T* lds, T* total) {
   return before + incl - v;
 }
 
+// Item count of a scan: n, or the smaller count *n_dev when the device
+// supplies it (the grid is sized for n).
+__device__ __forceinline__ int64_t scan_count(int64_t n, const uint32_t* n_dev) {
+  return n_dev ? min(n, (int64_t)*n_dev) : n;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const T* __restrict__ in, int64_t n, T* __restrict__ sums) {
+__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const T* __restrict__ in, int64_t n_max,
+                                                             const uint32_t* __restrict__ n_dev,
+                                                             T* __restrict__ sums) {
   __shared__ T red[kScanWaves];
+  const int64_t n = scan_count(n_max, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kPerBlock;
+  if (base >= n) {              // uniform per block; past the device's count
+    if (threadIdx.x == 0) sums[blockIdx.x] = T(0);
+    return;
+  }
   // all loads before the sum, so one memory latency is waited for, not 16
   T v[kItems];
 #pragma unroll
@@ -79,12 +92,15 @@ __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(const T* __restrict
 // staged in LDS with one pad word per 16, so that thread t can scan its 16
 // consecutive items without bank conflicts.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void scan_apply_kernel(const T* in, int64_t n, const T* __restrict__ prefix,
+__global__ __launch_bounds__(kBlock) void scan_apply_kernel(const T* in, int64_t n_max, const uint32_t* __restrict__ n_dev,
+                                                            const T* __restrict__ prefix,
                                                             const T* __restrict__ block_sums, T* out) {
   constexpr int kPad = kItems + 1;
   __shared__ T lds[kBlock];
   __shared__ T tile[kBlock * kPad];
+  const int64_t n = scan_count(n_max, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kPerBlock;
+  if (base >= n) return;        // uniform per block, before any barrier
   const int t = threadIdx.x;
   T ld[kItems];
 #pragma unroll
@@ -138,26 +154,30 @@ inline int64_t scan_ws_words(int64_t n) {
 
 constexpr int64_t kFusedBlocks = 1024;
 
+// Exclusive scan of in[0, n) into out.  With n_dev, the device supplies the
+// count (at most n; n sizes the grids): blocks past it do nothing, so a
+// scan sized for a bound costs little more than one sized for the count.
 template <typename T>
-void scan_excl(const T* in, T* out, int64_t n, T* ws, hipStream_t st) {
+void scan_excl(const T* in, T* out, int64_t n, T* ws, hipStream_t st, const uint32_t* n_dev = nullptr) {
   if (n <= 0) return;
   const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
   if (nb == 1) {
-    SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3(1), dim3(kBlock), 0, st, in, n, (const T*)nullptr,
+    SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3(1), dim3(kBlock), 0, st, in, n, n_dev, (const T*)nullptr,
                (const T*)nullptr, out);
     return;
   }
   T* sums = ws;
   T* sums_scan = ws + nb;
-  SSS_LAUNCH("scan_reduce", scan_reduce_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, sums);
+  SSS_LAUNCH("scan_reduce", scan_reduce_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, n_dev, sums);
   if (nb <= kFusedBlocks) {
-    SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, (const T*)nullptr,
-               (const T*)sums, out);
+    SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, n_dev,
+               (const T*)nullptr, (const T*)sums, out);
     return;
   }
+  // the block sums of blocks past the device's count are zero
   scan_excl<T>(sums, sums_scan, nb, ws + 2 * nb, st);
-  SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, (const T*)sums_scan,
-             (const T*)nullptr, out);
+  SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, n_dev,
+             (const T*)sums_scan, (const T*)nullptr, out);
 }
 
 }  // namespace

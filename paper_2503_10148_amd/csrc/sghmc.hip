@@ -1,77 +1,36 @@
 // SGHMC on the component means (Sec. 3.4 eq. sigmoidUpdate, SM eq. SGHMC)
-// and Adam on the other parameters.  Elementwise and HBM-bound: one thread
-// per component reads 40 bytes (mean, momentum, gradient, opacity) and writes
-// 24; the noise is generated in registers from a counter-based generator, so
-// a step is reproducible from (seed, step) alone.
+// and Adam on the other parameters (the per-element arithmetic is in
+// step.hpp).  Elementwise and HBM-bound: one thread per component reads 40
+// bytes (mean, momentum, gradient, opacity) and writes 24; the noise is
+// generated in registers from a counter-based generator, so a step is
+// reproducible from (seed, step) alone.
 #include "common.hpp"
+#include "step.hpp"
 
 namespace sss {
 namespace {
 
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
-// 32x32->64 multiplies with the published multipliers and Weyl key schedule.
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-    k.x += 0x9E3779B9u;
-    k.y += 0xBB67AE85u;
-  }
-  return c;
-}
-
-// (0, 1) uniform from the top 23 bits, exact in FP32.
-__device__ __forceinline__ float unit_open(uint32_t x) { return ((float)(x >> 9) + 0.5f) * (1.0f / 8388608.0f); }
-
 __global__ __launch_bounds__(kBlock) void sghmc_kernel(float* __restrict__ means, float* __restrict__ mom,
                                                        const float* __restrict__ grad, const float* __restrict__ opac,
                                                        const float* __restrict__ scales, const float* __restrict__ quats,
-                                                       int64_t n, float lr, float friction, float k, float t,
-                                                       int burn_in, int noise, uint64_t seed, uint64_t step) {
+                                                       int64_t n, SghmcArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const float sw = 1.0f / (1.0f + expf(-k * ((1.0f - fabsf(opac[i])) - t)));
-  float z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
-  if (noise) {
-    const uint4 x = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)(i >> 32)),
-                                  make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
-    const float r0 = sqrtf(-2.0f * logf(unit_open(x.x)));
-    const float r1 = sqrtf(-2.0f * logf(unit_open(x.z)));
-    const float a0 = 2.0f * unit_open(x.y), a1 = 2.0f * unit_open(x.w);
-    z0 = r0 * cospif(a0);
-    z1 = r0 * sinpif(a0);
-    z2 = r1 * cospif(a1);
+  float mu[3], r[3], G[3], s[3] = {0.0f, 0.0f, 0.0f};
+  float4 q = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+  for (int c = 0; c < 3; ++c) {
+    mu[c] = means[3 * i + c];
+    r[c] = mom[3 * i + c];
+    G[c] = grad[3 * i + c];
   }
-  const float sd = sqrtf(2.0f * lr * friction);
-  const float n0 = sd * z0, n1 = sd * z1, n2 = sd * z2;
-  float k0 = n0, k1 = n1, k2 = n2;
-  if (burn_in) {
-    // Sigma n with Sigma = R diag(s^2) R^T
-    const float4 q = *reinterpret_cast<const float4*>(quats + 4 * i);
-    const float inv = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
-    const float w = q.x * inv, x = q.y * inv, y = q.z * inv, z = q.w * inv;
-    const float R[9] = {1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y - w * z), 2.0f * (x * z + w * y),
-                        2.0f * (x * y + w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z - w * x),
-                        2.0f * (x * z - w * y), 2.0f * (y * z + w * x), 1.0f - 2.0f * (x * x + y * y)};
-    const float s0 = scales[3 * i], s1 = scales[3 * i + 1], s2 = scales[3 * i + 2];
-    const float sq[3] = {s0 * s0, s1 * s1, s2 * s2};
-    // u = diag(s^2) R^T n
-    float u[3];
-    for (int c = 0; c < 3; ++c) u[c] = sq[c] * (R[c] * n0 + R[3 + c] * n1 + R[6 + c] * n2);
-    k0 = R[0] * u[0] + R[1] * u[1] + R[2] * u[2];
-    k1 = R[3] * u[0] + R[4] * u[1] + R[5] * u[2];
-    k2 = R[6] * u[0] + R[7] * u[1] + R[8] * u[2];
+  if (a.burn_in) {
+    q = *reinterpret_cast<const float4*>(quats + 4 * i);
+    for (int c = 0; c < 3; ++c) s[c] = scales[3 * i + c];
   }
-  const float decay = 1.0f - lr * friction;
-  const float fsc = burn_in ? 0.0f : sw * lr * decay;
-  const float lr2 = lr * lr;
-  const float kick[3] = {k0, k1, k2};
-  const float nz[3] = {n0, n1, n2};
-  for (int a = 0; a < 3; ++a) {
-    const float r = mom[3 * i + a], G = grad[3 * i + a];
-    means[3 * i + a] = means[3 * i + a] - lr2 * G + fsc * r + sw * lr * kick[a];
-    mom[3 * i + a] = decay * r - lr * G + nz[a];
+  sghmc_one(i, mu, r, G, opac[i], q, s, a);
+  for (int c = 0; c < 3; ++c) {
+    means[3 * i + c] = mu[c];
+    mom[3 * i + c] = r[c];
   }
 }
 
@@ -94,16 +53,7 @@ struct AdamBatch {
 // thread; eight measured 13% slower.
 constexpr int kAdamIt = 4;
 
-__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float lo, float hi, float b1,
-                                         float b2, float omb1, float omb2, float eps, float c1, float c2) {
-  m = b1 * m + omb1 * g;
-  v = b2 * v + omb2 * g * g;
-  const float upd = lr * (m / c1) / (sqrtf(v / c2) + eps);
-  p = fminf(fmaxf(p - upd, lo), hi);
-}
-
-__global__ __launch_bounds__(kBlock) void adam_kernel(AdamBatch ab, float b1, float b2, float omb1, float omb2,
-                                                      float eps, float c1, float c2) {
+__global__ __launch_bounds__(kBlock) void adam_kernel(AdamBatch ab, AdamConst ac) {
   int a = 0;
   for (int k = 1; k < ab.n; ++k)
     if (blockIdx.x >= ab.first_block[k]) a = k;
@@ -129,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(AdamBatch ab, float b1, fl
   for (int k = 0; k < kAdamIt; ++k) {
     const int64_t i = i0 + (int64_t)k * kBlock;
     if (i < cnt) {
-      adam_one(pi[k], gi[k], mi[k], vi[k], ab.lr[a], ab.lo[a], ab.hi[a], b1, b2, omb1, omb2, eps, c1, c2);
+      adam_one(pi[k], gi[k], mi[k], vi[k], ab.lr[a], ab.lo[a], ab.hi[a], ac);
       __builtin_nontemporal_store(pi[k], p + i);
       __builtin_nontemporal_store(mi[k], m + i);
       __builtin_nontemporal_store(vi[k], v + i);
@@ -178,14 +128,10 @@ void launch_regularise(const float* opac, const float* scales, int64_t n, float 
 void launch_sghmc(float* means, float* mom, const float* g, const float* opac, const float* scales,
                   const float* quats, int64_t n, const sss_sghmc_opts_t& o, hipStream_t st) {
   SSS_LAUNCH("sghmc", sghmc_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, means, mom, g,
-                     opac, scales, quats, n, o.lr, o.friction, o.k, o.t, (int)o.burn_in, (int)o.noise, o.seed, o.step);
+             opac, scales, quats, n, sghmc_args(o));
 }
 
 void launch_adam(const sss_adam_t& ad, hipStream_t st) {
-  // 1 - beta and the bias corrections on the host, in FP64
-  const float c1 = (float)(1.0 - pow((double)ad.beta1, (double)ad.t));
-  const float c2 = (float)(1.0 - pow((double)ad.beta2, (double)ad.t));
-  const float omb1 = (float)(1.0 - (double)ad.beta1), omb2 = (float)(1.0 - (double)ad.beta2);
   AdamBatch ab{};
   ab.first_block[0] = 0;
   int k = 0;
@@ -201,8 +147,7 @@ void launch_adam(const sss_adam_t& ad, hipStream_t st) {
   ab.n = k;
   const uint32_t blocks = ab.first_block[k];
   if (blocks == 0) return;
-  SSS_LAUNCH("adam", adam_kernel, dim3(blocks), dim3(kBlock), 0, st, ab,
-             ad.beta1, ad.beta2, omb1, omb2, ad.eps, c1, c2);
+  SSS_LAUNCH("adam", adam_kernel, dim3(blocks), dim3(kBlock), 0, st, ab, adam_const(ad.beta1, ad.beta2, ad.eps, ad.t));
 }
 
 }  // namespace sss

@@ -9,7 +9,15 @@ sss_bin_sort + sss_render_fwd sequence over all its views, on the next of
 sort run on another stream while the previous batch still rasterizes.  A
 completion thread waits for each batch's event, hands every request its
 image (a [H, W, 3] device tensor) and releases the batch's memory, which lets
-the scheduler admit more.
+the scheduler admit more.  A request that arrives while nothing is queued or
+in flight is launched at once by the submitting thread (a batch of one),
+without a hand-over to the scheduler.
+
+Nothing on the launch path waits for the device: the bin sort reads its
+counts on the device and copies them, with the batch, to pinned host memory.
+The completion thread checks them; a batch whose pair lists outgrew its
+stream's capacity is rendered again with a larger one before its results are
+handed out (the capacity only grows, and `warmup` sizes it up front).
 
 Each view is rendered independently inside a batch (its own tiles, ranks
 ordered by depth within the view), so a request's image is bit-identical
@@ -60,8 +68,10 @@ class _Slot:
     batch."""
 
     def __init__(self):
-        self.binner = sss.BinSorter(0)
+        self.binner = sss.BinSorter(0, no_wait=True)
         self.buf = {}
+        self.host_counts = None
+        self.event = None
 
     def take(self, name, shape, dtype, device):
         numel = int(math.prod(shape))
@@ -80,7 +90,7 @@ class RenderServer:
                  n_streams: int = 2, pairs_per_pixel: float = 20.0, device: int = 0, max_inflight: int | None = None,
                  consumer_stream=None):
         """scene: dict of device tensors (see sss.scene_struct).  At most
-        `max_inflight` batches (default: n_streams) are on the device at once;
+        `max_inflight` batches (default and at most: n_streams) are on the device at once;
         requests arriving meanwhile wait and join the next batch.
         consumer_stream: the stream results are read on (default: the
         current stream of `device` at construction)."""
@@ -90,18 +100,22 @@ class RenderServer:
         self.n = scene["means"].shape[0]
         self.opts = opts
         self.max_batch = max_batch
-        self.max_inflight = n_streams if max_inflight is None else max(1, int(max_inflight))
+        # a stream's scratch buffers serve one batch at a time
+        self.max_inflight = n_streams if max_inflight is None else max(1, min(int(max_inflight), n_streams))
         self.mem_budget = int(mem_budget)
         self.device = device
         self.consumer = consumer_stream if consumer_stream is not None else torch.cuda.current_stream(device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         self._slots = [_Slot() for _ in range(n_streams)]
         self.pairs_per_pixel = float(pairs_per_pixel)   # running estimate, refined from every batch
+        self.pairs_per_pixel_max = float(pairs_per_pixel)  # largest ratio seen: sizes the pair passes
+        self._ws_cache = {}
         self._q = collections.deque()
         self._cv = threading.Condition()
-        self._inflight = collections.deque()           # (event, reqs, bytes, keepalive)
+        self._inflight = collections.deque()           # (event, reqs, bytes, keepalive, stream index)
         self._mem_used = 0
         self._launching = 0                            # batches popped but not yet in flight
+        self._next_stream = 0
         self._running = True
         self.batches = 0
         self.batch_sizes = []
@@ -113,14 +127,24 @@ class RenderServer:
     # ---------------------------------------------------------------- public
     def submit(self, cam) -> Future:
         r = _Req(cam)
-        if self._estimate([r]) > self.mem_budget:
+        need = self._estimate([r])
+        if need > self.mem_budget:
             r.future.set_exception(MemoryError(f"request of {r.pixels} pixels exceeds the memory budget"))
             return r.future
         with self._cv:
             if not self._running:
                 raise RuntimeError("server closed")
-            self._q.append(r)
-            self._cv.notify_all()
+            direct = (not self._q and not self._inflight and self._launching == 0
+                      and self._mem_used + need <= self.mem_budget)
+            if not direct:
+                self._q.append(r)
+                self._cv.notify_all()
+                return r.future
+            self._mem_used += need
+            self._launching += 1
+            k = self._take_stream()
+        # the device is idle: launch from this thread, like a plain renderer
+        self._run_batch([r], need, k)
         return r.future
 
     def warmup(self, cams):
@@ -129,8 +153,16 @@ class RenderServer:
         later batches up to that size allocate nothing."""
         cams = list(cams)
         for stream, slot in zip(self.streams, self._slots):
-            _, ev = self._launch([_Req(c) for c in cams], stream, slot)
+            reqs = [_Req(c) for c in cams]
+            keep, ev = self._launch(reqs, stream, slot)
             ev.synchronize()
+            P = sum(r.pixels for r in reqs)
+            if P > 0:
+                self.pairs_per_pixel_max = max(self.pairs_per_pixel_max, int(keep[3][1]) / P)
+            if int(keep[3][1]) > keep[1].cap():
+                slot.binner.grow(int(keep[3][1]))
+                keep, ev = self._launch(reqs, stream, slot)
+                ev.synchronize()
 
     def close(self):
         with self._cv:
@@ -141,19 +173,23 @@ class RenderServer:
 
     # ------------------------------------------------------------- internals
     def _estimate(self, reqs) -> int:
-        """Device bytes of one batch: per-view projection + bins, per-pixel
-        outputs, and the pair list + sort buffers from the pair estimate."""
+        """Device bytes of one batch: per-view projection + bins, the image,
+        and the pair list + sort buffers from the pair estimate."""
         V = len(reqs)
         P = sum(r.pixels for r in reqs)
         E = V * self.n
         M = int(P * self.pairs_per_pixel * 1.25) + 1024
-        per_entry = _REC + 4 + 8 + 4 + 32 + 4 + _REC
-        ws = int(sss.lib().sss_bin_sort_workspace(E, M))
-        return E * per_entry + P * (12 + 4 + 4) + 4 * M + ws
+        per_entry = sss.ENTRY_BYTES + 4 + 4 + 4 + _REC
+        key = (E, M)
+        ws = self._ws_cache.get(key)
+        if ws is None:
+            ws = int(sss.lib().sss_bin_sort_workspace(E, M))
+            if len(self._ws_cache) < 4096:
+                self._ws_cache[key] = ws
+        return E * per_entry + P * 12 + 4 * M + ws
 
     def _schedule(self):
         torch.cuda.set_device(self.device)
-        k = 0
         while True:
             with self._cv:
                 while self._running and not self._q:
@@ -176,52 +212,68 @@ class RenderServer:
                 need = self._estimate(batch)
                 self._mem_used += need
                 self._launching += 1
-            stream = self.streams[k % len(self.streams)]
-            slot = self._slots[k % len(self.streams)]
-            k += 1
-            try:
-                keep, ev = self._launch(batch, stream, slot)
-            except Exception as exc:                            # pragma: no cover - surfaced to callers
-                for r in batch:
-                    r.future.set_exception(exc)
-                with self._cv:
-                    self._mem_used -= need
-                    self._launching -= 1
-                    self._cv.notify_all()
-                continue
+                k = self._take_stream()
+            self._run_batch(batch, need, k)
+
+    def _take_stream(self) -> int:
+        """Next stream index, round robin (called with the lock held)."""
+        k = self._next_stream
+        self._next_stream = (k + 1) % len(self.streams)
+        return k
+
+    def _run_batch(self, batch, need, k):
+        """Launch a popped batch on stream k and put it in flight."""
+        stream, slot = self.streams[k], self._slots[k]
+        try:
+            keep, ev = self._launch(batch, stream, slot)
+        except Exception as exc:                            # pragma: no cover - surfaced to callers
+            for r in batch:
+                r.future.set_exception(exc)
             with self._cv:
-                self._inflight.append((ev, batch, need, keep))
+                self._mem_used -= need
                 self._launching -= 1
-                self.batches += 1
-                self.batch_sizes.append(len(batch))
                 self._cv.notify_all()
+            return
+        with self._cv:
+            self._inflight.append((ev, batch, need, keep, k))
+            self._launching -= 1
+            self.batches += 1
+            self.batch_sizes.append(len(batch))
+            self._cv.notify_all()
 
     def _launch(self, batch, stream, slot):
-        cams = [r.cam for r in batch]
+        cams = sss.CameraBatch([r.cam for r in batch])     # marshalled once for the three calls
         dev = self.scene["means"].device
         E = len(cams) * self.n
-        P = sum(r.pixels for r in batch)
-        T = sss.total_tiles(cams)
+        P = cams.n_pixels
+        T = cams.n_tiles
         with torch.cuda.stream(stream):
-            proj = sss.Projected(slot.take("records", (E, sss.RECORD_BYTES), torch.uint8, dev),
+            proj = sss.Projected(slot.take("entries", (E, sss.ENTRY_BYTES), torch.uint8, dev),
                                  slot.take("key", (E,), torch.int32, dev),
-                                 slot.take("rect", (E, 4), torch.int16, dev),
-                                 slot.take("touched", (E,), torch.int32, dev),
-                                 slot.take("ellipse", (E, 4), torch.float64, dev))
+                                 slot.take("touched", (E,), torch.int32, dev))
             sss.project(self.scene, cams, self.opts, stream=stream, out=proj)
             out = sss.Binned(slot.take("order", (E,), torch.int32, dev),
                              slot.take("sorted", (E, sss.RECORD_BYTES), torch.uint8, dev),
                              slot.take("tile_start", (T + 1,), torch.int32, dev), None,
                              tile_order=slot.take("tile_order", (T,), torch.int32, dev))
-            bins = slot.binner(proj, cams, self.n, stream=stream, out=out)
-            image, _, _ = sss.render_fwd(bins, cams, self.opts, stream=stream,
-                                         t_final=slot.take("t_final", (P,), torch.float32, dev),
-                                         n_contrib=slot.take("n_contrib", (P,), torch.int32, dev))
-            ev = torch.cuda.Event()
+            counts = slot.take("counts", (2,), torch.int64, dev)
+            # the pair passes are sized by an estimate from the pairs per
+            # pixel seen so far (a batch that needs more is rendered again)
+            hint = int(self.pairs_per_pixel_max * 1.5 * P) + 8192
+            bins = slot.binner(proj, cams, self.n, stream=stream, out=out, counts=counts, capacity=hint)
+            image, _, _ = sss.render_fwd(bins, cams, self.opts, stream=stream, aux=False)
+            # the counts reach the host with the batch (read after its event;
+            # one pinned buffer per stream: a stream has one batch in flight)
+            if slot.host_counts is None:
+                slot.host_counts = torch.empty(2, dtype=torch.int64, pin_memory=True)
+            host_counts = slot.host_counts
+            host_counts.copy_(counts, non_blocking=True)
+            # one event per stream: a stream has one batch in flight
+            if slot.event is None:
+                slot.event = torch.cuda.Event()
+            ev = slot.event
             ev.record(stream)
-        if P > 0:
-            self.pairs_per_pixel = 0.8 * self.pairs_per_pixel + 0.2 * bins.n_pairs / P
-        return (proj, bins, image), ev
+        return (proj, bins, image, host_counts), ev
 
     def _complete(self):
         torch.cuda.set_device(self.device)
@@ -231,8 +283,21 @@ class RenderServer:
                     if not self._running and not self._q and self._launching == 0:
                         return
                     self._cv.wait(timeout=0.05)
-                ev, batch, need, keep = self._inflight[0]
+                ev, batch, need, keep, k = self._inflight[0]
             ev.synchronize()
+            n_pairs = int(keep[3][1])
+            P = sum(r.pixels for r in batch)
+            if P > 0:
+                self.pairs_per_pixel = 0.8 * self.pairs_per_pixel + 0.2 * n_pairs / P
+                self.pairs_per_pixel_max = max(self.pairs_per_pixel_max, n_pairs / P)
+            if n_pairs > keep[1].cap():
+                # the lists were cut short: grow this stream's buffers (and
+                # the estimate, above) and render the batch again (its
+                # stream has nothing else queued: one batch per stream is in
+                # flight)
+                self._slots[k].binner.grow(n_pairs)
+                keep, ev = self._launch(batch, self.streams[k], self._slots[k])
+                ev.synchronize()
             t = time.perf_counter()
             image = keep[2]
             # the image was allocated on the batch's stream: tie its release
@@ -253,11 +318,14 @@ class RenderServer:
 class PlainRenderer:
     """One request per launch sequence, FIFO, one stream."""
 
-    def __init__(self, scene: dict, opts=None):
+    def __init__(self, scene: dict, opts=None, pairs_per_pixel: float = 20.0):
         self.scene = scene
         self.n = scene["means"].shape[0]
         self.opts = opts
-        self.binner = sss.BinSorter(0)
+        self.binner = sss.BinSorter(0, no_wait=True, work=False)
+        # as the server: the pair passes are sized by the largest pairs per
+        # pixel seen so far
+        self.pairs_per_pixel_max = float(pairs_per_pixel)
 
     def warmup(self, cams):
         """Render each camera once (sizes the pair capacity and the allocator's
@@ -266,12 +334,22 @@ class PlainRenderer:
             self.render(c)
 
     def render(self, cam):
-        cams = [cam]
-        proj = sss.project(self.scene, cams, self.opts)
-        bins = self.binner(proj, cams, self.n)
-        image, _, _ = sss.render_fwd(bins, cams, self.opts)
-        torch.cuda.current_stream().synchronize()
-        return image.view(int(cam["height"]), int(cam["width"]), 3)
+        cams = sss.CameraBatch([cam])
+        P = cams.n_pixels
+        while True:
+            proj = sss.project(self.scene, cams, self.opts)
+            bins = self.binner(proj, cams, self.n, capacity=int(self.pairs_per_pixel_max * 1.5 * P) + 8192)
+            image, _, _ = sss.render_fwd(bins, cams, self.opts, aux=False)
+            torch.cuda.current_stream().synchronize()
+            try:
+                bins.resolve()           # counts arrived with the render
+            except sss.SSSError:
+                self.binner.grow(bins.n_pairs)
+                continue
+            finally:
+                if bins.n_pairs >= 0 and P > 0:
+                    self.pairs_per_pixel_max = max(self.pairs_per_pixel_max, bins.n_pairs / P)
+            return image.view(int(cam["height"]), int(cam["width"]), 3)
 
 
 def poisson_arrivals(rate: float, duration: float, rng):
@@ -334,3 +412,63 @@ def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, warm=None
     else:
         raise ValueError(server_kind)
     return lat, t_end - t0, stats
+
+
+def run_closed(server_kind: str, scene: dict, make_cam, n_clients: int, duration: float, opts=None, warm=None,
+               **server_kw):
+    """Closed loop: n_clients clients each submit a request (make_cam(k) for
+    the k-th request overall), wait for its image and submit the next, for
+    `duration` seconds.  The plain renderer serves the clients one request
+    at a time in arrival order (a lock).  Returns (latencies in s, requests
+    completed, pixels completed, wall time in s, server stats)."""
+    lock = threading.Lock()
+    lat, px = [], [0]
+    counter = [0]
+    stats = {}
+    if server_kind == "batched":
+        srv = RenderServer(scene, opts, **server_kw)
+        if warm:
+            srv.warmup(warm)
+    elif server_kind == "plain":
+        pr = PlainRenderer(scene, opts)
+        if warm:
+            pr.warmup(warm)
+        serial = threading.Lock()
+    else:
+        raise ValueError(server_kind)
+    t0 = time.perf_counter()
+    t_stop = t0 + duration
+
+    def client():
+        torch.cuda.set_device(scene["means"].device)
+        while True:
+            with lock:
+                k = counter[0]
+                counter[0] += 1
+            cam = make_cam(k)
+            ts = time.perf_counter()
+            if ts >= t_stop:
+                return
+            if server_kind == "batched":
+                f = srv.submit(cam)
+                f.result()
+                done = f.request.t_done
+            else:
+                with serial:
+                    pr.render(cam)
+                done = time.perf_counter()
+            with lock:
+                lat.append(done - ts)
+                px[0] += int(cam["width"]) * int(cam["height"])
+
+    threads = [threading.Thread(target=client, daemon=True) for _ in range(n_clients)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    t_end = time.perf_counter()
+    if server_kind == "batched":
+        srv.close()
+        stats = dict(batches=srv.batches, mean_batch=sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)))
+    return lat, len(lat), px[0], t_end - t0, stats
+

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libsss.so")
 TILE = 16
 MAX_VIEWS = 16
 RECORD_BYTES = 64
+ENTRY_BYTES = 128
 G2_SLOTS = 12
 OK, ERR_INVALID, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 BWD_STORED, BWD_RECOMPUTE, BWD_DETERMINISTIC = 0, 1, 4
@@ -53,15 +54,15 @@ class RenderOpts(ctypes.Structure):
 
 
 class Proj(ctypes.Structure):
-    _fields_ = [("records", ctypes.c_void_p), ("depth_key", ctypes.c_void_p), ("rect", ctypes.c_void_p),
-                ("tiles_touched", ctypes.c_void_p), ("ellipse", ctypes.c_void_p)]
+    _fields_ = [("entries", ctypes.c_void_p), ("depth_key", ctypes.c_void_p), ("tiles_touched", ctypes.c_void_p)]
 
 
 class Bins(ctypes.Structure):
     _fields_ = [("order", ctypes.c_void_p), ("sorted_records", ctypes.c_void_p), ("tile_start", ctypes.c_void_p),
                 ("pair_rank", ctypes.c_void_p), ("rank_offset", ctypes.c_void_p), ("tile_order", ctypes.c_void_p),
                 ("tile_work", ctypes.c_void_p), ("pair_capacity", ctypes.c_int64),
-                ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64)]
+                ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("counts", ctypes.c_void_p),
+                ("no_wait", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SghmcOpts(ctypes.Structure):
@@ -81,6 +82,13 @@ class Adam(ctypes.Structure):
                 ("n_arrays", ctypes.c_int32), ("t", ctypes.c_int64), ("arrays", AdamArray * 6)]
 
 
+class Step(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p * 6), ("momentum", ctypes.c_void_p), ("sghmc", SghmcOpts),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("adam", ctypes.c_int32),
+                ("t", ctypes.c_int64), ("m", ctypes.c_void_p * 5), ("v", ctypes.c_void_p * 5),
+                ("lr", ctypes.c_float * 5), ("lo", ctypes.c_float * 5), ("hi", ctypes.c_float * 5)]
+
+
 class RelocateOpts(ctypes.Structure):
     _fields_ = [("dead_opacity", ctypes.c_float), ("max_fraction", ctypes.c_float), ("seed", ctypes.c_uint64),
                 ("step", ctypes.c_uint64)]
@@ -97,7 +105,8 @@ class KernelTime(ctypes.Structure):
 # every function include/sss.h declares; lib() checks that each is exported
 EXPORTS = ["sss_default_render_opts", "sss_project", "sss_bin_sort", "sss_bin_sort_workspace", "sss_total_tiles",
            "sss_total_pixels", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_workspace",
-           "sss_render_bwd_workspace_det", "sss_render_bwd_noalloc", "sss_sghmc_step", "sss_loss",
+           "sss_render_bwd_workspace_det", "sss_render_bwd_noalloc", "sss_render_bwd_step", "sss_sghmc_step",
+           "sss_loss",
            "sss_loss_workspace", "sss_regularise", "sss_relocate", "sss_relocate_workspace", "sss_timing_enable",
            "sss_timing_reset", "sss_timing_read", "sss_last_error", "sss_version"]
 
@@ -133,6 +142,8 @@ def lib():
         L.sss_render_bwd.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp,
                                      ctypes.c_size_t, vp]
         L.sss_render_bwd_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.sss_render_bwd_step.argtypes = [vp, vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                          ctypes.c_size_t, vp]
         L.sss_sghmc_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp]
         L.sss_loss_workspace.restype = ctypes.c_size_t
         L.sss_loss_workspace.argtypes = [i64]
@@ -150,7 +161,7 @@ def lib():
         L.sss_timing_read.argtypes = [vp, i32]
         L.sss_timing_read.restype = i32
         for name in ("sss_project", "sss_bin_sort", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_noalloc",
-                     "sss_sghmc_step"):
+                     "sss_render_bwd_step", "sss_sghmc_step"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -188,14 +199,41 @@ def _need(t, dtype, name):
 # ---------------------------------------------------------------------------
 # argument structs
 # ---------------------------------------------------------------------------
+class CameraBatch:
+    """Cameras marshalled once into the C-ABI's array, with the batch's
+    total tiles and pixels.  Every call that takes `cams` accepts either a
+    list of camera dicts or a CameraBatch (reuse it across the calls of one
+    step or one request to skip repeated marshalling)."""
+
+    def __init__(self, cams):
+        cams = list(cams)
+        self.cams = cams
+        self.array = (Camera * len(cams))()
+        for i, c in enumerate(cams):
+            vm = c["viewmat"]
+            vm = vm.reshape(-1).tolist() if hasattr(vm, "reshape") else [x for row in vm for x in row]
+            self.array[i].viewmat[:] = [float(x) for x in vm]
+            self.array[i].fx, self.array[i].fy, self.array[i].cx, self.array[i].cy = c["fx"], c["fy"], c["cx"], c["cy"]
+            self.array[i].width, self.array[i].height = int(c["width"]), int(c["height"])
+        self.n_tiles = int(lib().sss_total_tiles(self.array, len(cams)))
+        self.n_pixels = int(lib().sss_total_pixels(self.array, len(cams)))
+
+    def __len__(self):
+        return len(self.cams)
+
+    def __getitem__(self, k):
+        return self.cams[k]
+
+    def __iter__(self):
+        return iter(self.cams)
+
+
+def camera_batch(cams) -> CameraBatch:
+    return cams if isinstance(cams, CameraBatch) else CameraBatch(cams)
+
+
 def camera_array(cams):
-    arr = (Camera * len(cams))()
-    for i, c in enumerate(cams):
-        vm = [float(x) for x in list(torch.as_tensor(c["viewmat"], dtype=torch.float32).reshape(12))]
-        arr[i].viewmat[:] = vm
-        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = c["fx"], c["fy"], c["cx"], c["cy"]
-        arr[i].width, arr[i].height = int(c["width"]), int(c["height"])
-    return arr
+    return camera_batch(cams).array
 
 
 def render_opts(opts=None):
@@ -233,11 +271,11 @@ def scene_to_device(scene, device="cuda"):
 
 
 def total_tiles(cams):
-    return int(lib().sss_total_tiles(camera_array(cams), len(cams)))
+    return camera_batch(cams).n_tiles
 
 
 def total_pixels(cams):
-    return int(lib().sss_total_pixels(camera_array(cams), len(cams)))
+    return camera_batch(cams).n_pixels
 
 
 # ---------------------------------------------------------------------------
@@ -245,30 +283,41 @@ def total_pixels(cams):
 # ---------------------------------------------------------------------------
 @dataclass
 class Projected:
-    records: torch.Tensor      # uint8 [E, 64]
+    entries: torch.Tensor      # uint8 [E, 128]: record, FP64 ellipse, tile rectangle (include/sss.h)
     depth_key: torch.Tensor    # int32 [E] (uint32 bits)
-    rect: torch.Tensor         # int16 [E, 4]
     touched: torch.Tensor      # int32 [E]
-    ellipse: torch.Tensor      # float64 [E, 4]
+
+    @property
+    def records(self) -> torch.Tensor:
+        """uint8 [E, 64] view: the raster records."""
+        return self.entries[:, :RECORD_BYTES]
+
+    @property
+    def ellipse(self) -> torch.Tensor:
+        """float64 [E, 4] view: 2D covariance A, B, D and the listed level."""
+        return self.entries[:, 64:96].view(torch.float64)
+
+    @property
+    def rect(self) -> torch.Tensor:
+        """int16 [E, 4] view: tile rectangle x0, y0, x1, y1 (uint16 bits)."""
+        return self.entries[:, 96:104].view(torch.int16)
 
     def struct(self):
-        return Proj(self.records.data_ptr(), self.depth_key.data_ptr(), self.rect.data_ptr(), self.touched.data_ptr(),
-                    self.ellipse.data_ptr())
+        return Proj(self.entries.data_ptr(), self.depth_key.data_ptr(), self.touched.data_ptr())
 
 
 def project(scene, cams, opts=None, stream=None, out: Projected | None = None) -> Projected:
+    cams = camera_batch(cams)
     n = scene["means"].shape[0]
     E = n * len(cams)
     dev = scene["means"].device
     if out is None:
-        out = Projected(torch.empty((E, RECORD_BYTES), dtype=torch.uint8, device=dev),
+        out = Projected(torch.empty((E, ENTRY_BYTES), dtype=torch.uint8, device=dev),
                         torch.empty(E, dtype=torch.int32, device=dev),
-                        torch.empty((E, 4), dtype=torch.int16, device=dev),
-                        torch.empty(E, dtype=torch.int32, device=dev),
-                        torch.empty((E, 4), dtype=torch.float64, device=dev))
+                        torch.empty(E, dtype=torch.int32, device=dev))
     s = scene_struct(scene)
     p = out.struct()
-    _check(lib().sss_project(ctypes.byref(s), camera_array(cams), len(cams), ctypes.byref(render_opts(opts)),
+    _check(lib().sss_project(ctypes.byref(s), cams.array, len(cams), ctypes.byref(render_opts(opts)),
                              ctypes.byref(p), _stream(stream)), "sss_project")
     return out
 
@@ -284,11 +333,28 @@ class Binned:
     rank_offset: torch.Tensor | None = None   # int32 [E], kept for the deterministic backward
     tile_order: torch.Tensor | None = None    # int32 [tiles], launch order (longest list first)
     tile_work: torch.Tensor | None = None     # int32 [tiles, 4], per 16x4 strip the largest n_contrib (render_fwd)
+    counts: torch.Tensor | None = None        # int64 [2] device: visible entries, required pairs (no-wait calls)
+    capacity: int = 0                         # pairs the call could hold (0: all of pair_rank)
 
-    def struct(self):
+    def cap(self) -> int:
+        return self.capacity if self.capacity > 0 else self.pair_rank.numel()
+
+    def struct(self, no_wait: bool = False):
         return Bins(self.order.data_ptr(), self.sorted_records.data_ptr(), self.tile_start.data_ptr(),
                     self.pair_rank.data_ptr(), _addr(self.rank_offset), _addr(self.tile_order),
-                    _addr(self.tile_work), self.pair_rank.numel(), self.n_visible, self.n_pairs)
+                    _addr(self.tile_work), self.cap(), self.n_visible, self.n_pairs,
+                    _addr(self.counts), int(no_wait), 0)
+
+    def resolve(self):
+        """After a no-wait binning: wait for its counts, fill n_visible and
+        n_pairs, and raise SSSError(ERR_CAPACITY) if the lists were cut short
+        by the pair capacity."""
+        if self.n_pairs < 0:
+            c = self.counts.cpu()
+            self.n_visible, self.n_pairs = int(c[0]), int(c[1])
+        if self.n_pairs > self.cap():
+            raise SSSError(ERR_CAPACITY, f"sss_bin_sort: {self.n_pairs} pairs exceed the capacity {self.cap()}")
+        return self
 
 
 class BinSorter:
@@ -302,20 +368,41 @@ class BinSorter:
     list (the next call overwrites it), which suits a loop that consumes
     each binning before the next.  With `own_pairs`, each call gets a pair
     list of its own, so several binnings can be alive at once (renders
-    whose backward passes run later)."""
+    whose backward passes run later).
+
+    With `no_wait`, calls after the first never wait for the device: the
+    counts go to a device tensor (`counts`, or one the sorter keeps) and
+    the returned Binned has n_visible = n_pairs = -1 until `resolve()`; a
+    binning whose pairs exceeded the capacity must be redone (resolve()
+    raises, and the sorter grows its capacity for the next call).  The
+    first call, with no capacity yet, waits to size the buffers."""
 
     def __init__(self, pair_capacity: int = 0, keep_offsets: bool = False, schedule: bool = True,
-                 own_pairs: bool = False):
+                 own_pairs: bool = False, no_wait: bool = False, headroom: float = 1.25, work: bool = True):
         self.cap = int(pair_capacity)
         self.ws = None
         self.pair_rank = None
         self.keep_offsets = keep_offsets
         self.schedule = schedule
         self.own_pairs = own_pairs
+        self.no_wait = no_wait
+        self.headroom = float(headroom)
+        self.work = work           # per-strip walk lengths for a later backward pass
+        self.counts = None
 
-    def __call__(self, proj: Projected, cams, n: int, stream=None, out: Binned | None = None) -> Binned:
+    def grow(self, n_pairs: int):
+        """Make the next calls' capacity hold n_pairs with the headroom."""
+        self.cap = max(self.cap, int(n_pairs * self.headroom) + 1024)
+
+    def __call__(self, proj: Projected, cams, n: int, stream=None, out: Binned | None = None,
+                 counts: torch.Tensor | None = None, capacity: int | None = None) -> Binned:
+        """capacity (no-wait calls): the most pairs this call may emit, if
+        less than the pair buffer holds; the pair passes' grids are sized by
+        it, so a good estimate keeps small calls cheap on large buffers (a
+        call that needs more must be redone: resolve() raises)."""
+        cams = camera_batch(cams)
         E = n * len(cams)
-        dev = proj.records.device
+        dev = proj.entries.device
         T = total_tiles(cams)
         if out is None:
             out = Binned(torch.empty(E, dtype=torch.int32, device=dev),
@@ -323,11 +410,19 @@ class BinSorter:
                          torch.empty(T + 1, dtype=torch.int32, device=dev), None)
             if self.schedule:
                 out.tile_order = torch.empty(T, dtype=torch.int32, device=dev)
-                out.tile_work = torch.empty((T, 4), dtype=torch.int32, device=dev)
+                if self.work:
+                    out.tile_work = torch.empty((T, 4), dtype=torch.int32, device=dev)
         if self.keep_offsets and (out.rank_offset is None or out.rank_offset.numel() < E):
             out.rank_offset = torch.empty(E, dtype=torch.int32, device=dev)
-        camarr = camera_array(cams)
+        camarr = cams.array
         p = proj.struct()
+        no_wait = self.no_wait and self.cap > 0
+        if no_wait:
+            if counts is None:
+                if self.counts is None:
+                    self.counts = torch.empty(2, dtype=torch.int64, device=dev)
+                counts = self.counts
+        out.counts = counts
         pairs = None
         for _ in range(3):
             if self.own_pairs:
@@ -341,26 +436,31 @@ class BinSorter:
             if self.ws is None or self.ws.numel() < need:
                 self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
             out.pair_rank = pairs
-            b = out.struct()
+            out.capacity = min(pairs.numel(), max(int(capacity), 1)) if (no_wait and capacity) else 0
+            b = out.struct(no_wait)
             rc = lib().sss_bin_sort(ctypes.byref(p), camarr, len(cams), n, ctypes.byref(b), _ptr(self.ws),
                                     self.ws.numel(), _stream(stream))
             out.n_visible, out.n_pairs = int(b.n_visible), int(b.n_pairs)
             if rc == ERR_CAPACITY:
-                self.cap = int(b.n_pairs * 1.25) + 1024
+                self.grow(b.n_pairs)
                 continue
             _check(rc, "sss_bin_sort")
             return out
         raise SSSError(ERR_CAPACITY, "sss_bin_sort: capacity retry did not converge")
 
 
-def render_fwd(bins: Binned, cams, opts=None, stream=None, image=None, t_final=None, n_contrib=None):
-    P = total_pixels(cams)
+def render_fwd(bins: Binned, cams, opts=None, stream=None, image=None, t_final=None, n_contrib=None, aux=True):
+    """aux=False: only the image (no final transmittance, no list positions:
+    a render that no backward pass will use)."""
+    cams = camera_batch(cams)
+    P = cams.n_pixels
     dev = bins.order.device
     image = torch.empty((P, 3), dtype=torch.float32, device=dev) if image is None else image
-    t_final = torch.empty(P, dtype=torch.float32, device=dev) if t_final is None else t_final
-    n_contrib = torch.empty(P, dtype=torch.int32, device=dev) if n_contrib is None else n_contrib
+    if aux:
+        t_final = torch.empty(P, dtype=torch.float32, device=dev) if t_final is None else t_final
+        n_contrib = torch.empty(P, dtype=torch.int32, device=dev) if n_contrib is None else n_contrib
     b = bins.struct()
-    _check(lib().sss_render_fwd(ctypes.byref(b), camera_array(cams), len(cams), ctypes.byref(render_opts(opts)),
+    _check(lib().sss_render_fwd(ctypes.byref(b), cams.array, len(cams), ctypes.byref(render_opts(opts)),
                                 _ptr(image), _ptr(t_final), _ptr(n_contrib), _stream(stream)), "sss_render_fwd")
     return image, t_final, n_contrib
 
@@ -378,6 +478,7 @@ def render_bwd(scene, proj: Projected, bins: Binned, cams, dl_or_target, opts=No
     bins from BinSorter(keep_offsets=True)).
     noalloc: call sss_render_bwd_noalloc, whose workspace the library holds
     (up to SSS_NOALLOC_WORKSPACE_BYTES); `ws` is ignored."""
+    cams = camera_batch(cams)
     n = scene["means"].shape[0]
     E = n * len(cams)
     if grads is None:
@@ -394,7 +495,7 @@ def render_bwd(scene, proj: Projected, bins: Binned, cams, dl_or_target, opts=No
     p = proj.struct()
     b = bins.struct()
     if noalloc:
-        _check(lib().sss_render_bwd_noalloc(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), camera_array(cams),
+        _check(lib().sss_render_bwd_noalloc(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), cams.array,
                                             len(cams), ctypes.byref(render_opts(opts)), mode, loss,
                                             _ptr(dl_or_target), _ptr(image), _ptr(n_contrib), _ptr(image_out),
                                             _ptr(loss_out), ctypes.byref(g), _stream(stream)),
@@ -402,7 +503,7 @@ def render_bwd(scene, proj: Projected, bins: Binned, cams, dl_or_target, opts=No
         return grads
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need // 4, dtype=torch.float32, device=scene["means"].device)
-    _check(lib().sss_render_bwd(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), camera_array(cams), len(cams),
+    _check(lib().sss_render_bwd(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), cams.array, len(cams),
                                 ctypes.byref(render_opts(opts)), mode, loss, _ptr(dl_or_target), _ptr(image),
                                 _ptr(n_contrib), _ptr(image_out), _ptr(loss_out), ctypes.byref(g), _ptr(ws),
                                 ws.numel() * ws.element_size(), _stream(stream)), "sss_render_bwd")
@@ -427,6 +528,63 @@ def sghmc_step(means, momentum, grad_means, opacity, lr, friction=0.1, k=100.0, 
     _check(lib().sss_sghmc_step(_ptr(means), _ptr(momentum), _ptr(grad_means), _ptr(opacity), _ptr(scales),
                                 _ptr(quats), means.shape[0], ctypes.byref(o),
                                 ctypes.byref(ad) if ad is not None else None, _stream(stream)), "sss_sghmc_step")
+
+
+STEP_ARRAYS = ("scales", "quats", "nu", "opacity", "sh")
+
+
+def render_bwd_step(scene, proj: Projected, bins: Binned, cams, dl_or_target, momentum, sghmc: dict,
+                    adam: dict | None = None, opts=None, mode=BWD_STORED, loss=LOSS_GRAD, image=None, n_contrib=None,
+                    image_out=None, loss_out=None, grads=None, ws=None, stream=None, deterministic=False):
+    """sss_render_bwd_step: the backward pass with the SGHMC step on the
+    means and Adam on the other arrays applied in place (scene tensors,
+    momentum and moments are updated; gradients are written to `grads` only
+    when given).
+    sghmc: lr, friction (0.1), k (100), t (0.995), burn_in, noise, seed, step.
+    adam: beta1, beta2, eps, t and per array of STEP_ARRAYS: m[name], v[name]
+    (moment tensors), lr[name], lo[name], hi[name] (defaults +-3e38)."""
+    cams = camera_batch(cams)
+    n = scene["means"].shape[0]
+    E = n * len(cams)
+    if deterministic:
+        mode |= BWD_DETERMINISTIC
+        need = int(lib().sss_render_bwd_workspace_det(E, bins.n_pairs, cams.n_tiles))
+    else:
+        need = int(lib().sss_render_bwd_workspace(E, cams.n_tiles))
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need // 4, dtype=torch.float32, device=scene["means"].device)
+    st = Step()
+    for k, name in enumerate(("means", "scales", "quats", "nu", "opacity", "sh")):
+        st.params[k] = scene[name].data_ptr()
+    _need(momentum, torch.float32, "momentum")
+    st.momentum = momentum.data_ptr()
+    st.sghmc = SghmcOpts(sghmc["lr"], sghmc.get("friction", 0.1), sghmc.get("k", 100.0), sghmc.get("t", 0.995),
+                         int(sghmc.get("burn_in", False)), int(sghmc.get("noise", True)), sghmc.get("seed", 0),
+                         sghmc.get("step", 0))
+    if adam is not None:
+        st.adam = 1
+        st.beta1, st.beta2, st.eps = adam.get("beta1", 0.9), adam.get("beta2", 0.999), adam.get("eps", 1e-15)
+        st.t = int(adam["t"])
+        for k, name in enumerate(STEP_ARRAYS):
+            _need(adam["m"][name], torch.float32, f"m[{name}]")
+            _need(adam["v"][name], torch.float32, f"v[{name}]")
+            st.m[k] = adam["m"][name].data_ptr()
+            st.v[k] = adam["v"][name].data_ptr()
+            st.lr[k] = adam["lr"][name]
+            st.lo[k] = adam.get("lo", {}).get(name, -3.0e38)
+            st.hi[k] = adam.get("hi", {}).get(name, 3.0e38)
+    s = scene_struct(scene)
+    p = proj.struct()
+    b = bins.struct()
+    g = None
+    if grads is not None:
+        g = Grads(*(grads[k].data_ptr() for k in ("means", "scales", "quats", "nu", "opacity", "sh")), 1, 0)
+    _check(lib().sss_render_bwd_step(ctypes.byref(s), ctypes.byref(p), ctypes.byref(b), cams.array, len(cams),
+                                     ctypes.byref(render_opts(opts)), mode, loss, _ptr(dl_or_target), _ptr(image),
+                                     _ptr(n_contrib), _ptr(image_out), _ptr(loss_out),
+                                     ctypes.byref(g) if g is not None else None, ctypes.byref(st), _ptr(ws),
+                                     ws.numel() * ws.element_size(), _stream(stream)), "sss_render_bwd_step")
+    return ws
 
 
 # ---------------------------------------------------------------------------
@@ -479,14 +637,15 @@ def relocate(scene, states=(), dead_opacity=0.005, max_fraction=0.05, seed=0, st
 def loss(image, target, cams, lambda_dssim=0.2, dl_dimage=None, loss_out=None, ws=None, stream=None):
     """(1 - lambda) L1 + lambda (1 - SSIM) over all views; returns dL/dimage
     (and adds L into loss_out when given)."""
-    P = total_pixels(cams)
+    cams = camera_batch(cams)
+    P = cams.n_pixels
     _need(image, torch.float32, "image")
     _need(target, torch.float32, "target")
     dl_dimage = torch.empty_like(image) if dl_dimage is None else dl_dimage
     need = int(lib().sss_loss_workspace(P))
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(max(need // 4, 1), dtype=torch.float32, device=image.device)
-    _check(lib().sss_loss(_ptr(image), _ptr(target), camera_array(cams), len(cams), lambda_dssim, _ptr(dl_dimage),
+    _check(lib().sss_loss(_ptr(image), _ptr(target), cams.array, len(cams), lambda_dssim, _ptr(dl_dimage),
                           _ptr(loss_out), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)), "sss_loss")
     return dl_dimage
 

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(sss):
     lib = ctypes.CDLL(sss.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert sss.lib().sss_version() == 103
+    assert sss.lib().sss_version() == 105
 
 
 def test_default_options(sss):
@@ -58,7 +58,7 @@ def test_workspace_sizes_grow(sss):
     a = L.sss_bin_sort_workspace(1000, 1000)
     b = L.sss_bin_sort_workspace(1000, 10 ** 6)
     assert 0 < a < b
-    assert L.sss_render_bwd_workspace(1000, 0) == 1000 * 12 * 8       # FP64 per-entry sums
+    assert L.sss_render_bwd_workspace(1000, 0) == 1000 * 12 * 8 + 16  # FP64 per-entry sums, work counter
     assert L.sss_render_bwd_workspace(1000, 100) >= 1000 * 12 * 8 + 800    # + loss and order per tile
 
 
@@ -70,7 +70,7 @@ def _scene_struct(sss, n=10, deg=0, null=None):
 
 
 def _proj_struct(sss):
-    return sss.Proj(0x2000, 0x3000, 0x4000, 0x5000, 0x5800)
+    return sss.Proj(0x2000, 0x3000, 0x5000)
 
 
 @pytest.mark.parametrize("kind", ["null_scene", "bad_degree", "zero_n", "null_array", "no_views", "too_many_views",
@@ -247,3 +247,46 @@ def test_noalloc_rejects_bad_arguments_and_oversize_before_any_gpu_call(sss):
     assert L.sss_render_bwd_workspace(1_500_000, 12) > (128 << 20)
     assert call(big, 0) == sss.ERR_INVALID
     assert b"SSS_NOALLOC_WORKSPACE_BYTES" in L.sss_last_error()
+
+
+def test_project_rejects_misaligned_entries(sss):
+    """Entries are 128-byte lines read with 16-byte loads: a pointer that is
+    not 16-byte aligned is an argument error."""
+    L = sss.lib()
+    cams = sss.camera_array([scenes.ring_camera(64, 48)])
+    scene = _scene_struct(sss)
+    p = sss.Proj(0x2008, 0x3000, 0x5000)
+    assert L.sss_project(ctypes.byref(scene), cams, 1, ctypes.byref(sss.render_opts()), ctypes.byref(p),
+                         None) == sss.ERR_INVALID
+    assert b"16-byte" in L.sss_last_error()
+
+
+def test_struct_layouts_match_the_header(sss, tmp_path):
+    """Every struct the binding passes has the size and field offsets the C
+    compiler gives the header's declaration."""
+    import subprocess
+    structs = {"sss_scene_t": sss.Scene, "sss_grads_t": sss.Grads, "sss_camera_t": sss.Camera,
+               "sss_render_opts_t": sss.RenderOpts, "sss_proj_t": sss.Proj, "sss_bins_t": sss.Bins,
+               "sss_sghmc_opts_t": sss.SghmcOpts, "sss_adam_array_t": sss.AdamArray, "sss_adam_t": sss.Adam,
+               "sss_step_t": sss.Step, "sss_relocate_opts_t": sss.RelocateOpts, "sss_state_t": sss.StateArray,
+               "sss_kernel_time_t": sss.KernelTime}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sss.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

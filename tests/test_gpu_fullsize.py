@@ -46,8 +46,15 @@ def _windows(cams, count, rng):
 
 
 @pytest.mark.parametrize("name,mode,count", [("m1", "stored", 6), ("large", "recompute", 4),
-                                             ("multiview", "stored", 4)])
+                                             ("multiview", "stored", 4), ("multiview", "recompute_l1", 4)])
 def test_full_size_windows_match_oracle(sss, name, mode, count):
+    """recompute_l1: the configuration the multi-view workload is timed in,
+    the forward pass recomputed per tile inside the backward launch with the
+    L1 loss fused.  The target equals the image outside the windows (the L1
+    gradient there is sign(0) = 0) and the image minus 0.5 sign(w) inside
+    them, so the fused loss gradient is sign(w) / (3P) in the windows: the
+    oracle gets that weight; the recomputed image must equal the forward
+    pass's bit for bit, and the loss is 0.5 per weighted value / (3P)."""
     scene, cams = scenes.workload(name)
     n = scene["means"].shape[0]
     s64 = {k: np.asarray(scene[k], np.float64) for k in PARAMS}
@@ -78,6 +85,8 @@ def test_full_size_windows_match_oracle(sss, name, mode, count):
         explained_total += int(explained.sum())
         w = rng.standard_normal((WIN, WIN, 3)).astype(np.float32)
         w[explained] = 0.0
+        if mode == "recompute_l1":
+            w = np.sign(w) / np.float32(3 * img_np.shape[0])     # the fused L1 loss's weights
         dl[rows.reshape(-1)] = w.reshape(-1, 3)
         g = oracle.render_backward(s64, wc, w.astype(np.float64), fwd=ref)
         for k in PARAMS:
@@ -86,9 +95,21 @@ def test_full_size_windows_match_oracle(sss, name, mode, count):
     assert bad_total == 0, bad_total
     assert explained_total < 0.02 * count * WIN * WIN
     m = sss.BWD_STORED if mode == "stored" else sss.BWD_RECOMPUTE
-    g = sss.render_bwd(dev, proj, bins, cams, torch.as_tensor(dl, device="cuda"), mode=m,
-                       image=img if mode == "stored" else None, n_contrib=ncon if mode == "stored" else None)
-    torch.cuda.synchronize()
+    if mode == "recompute_l1":
+        P = img_np.shape[0]
+        sgn = np.sign(dl)
+        target = torch.as_tensor((img_np - np.float32(0.5) * sgn).astype(np.float32), device="cuda")
+        image_out = torch.empty_like(img)
+        loss = torch.zeros(1, device="cuda")
+        g = sss.render_bwd(dev, proj, bins, cams, target, mode=m, loss=sss.LOSS_L1, image_out=image_out,
+                           loss_out=loss)
+        torch.cuda.synchronize()
+        assert torch.equal(image_out, img)
+        assert abs(float(loss.item()) - 0.5 * float(np.abs(sgn).sum()) / (3.0 * P)) <= 1e-6 * float(loss.item())
+    else:
+        g = sss.render_bwd(dev, proj, bins, cams, torch.as_tensor(dl, device="cuda"), mode=m,
+                           image=img if mode == "stored" else None, n_contrib=ncon if mode == "stored" else None)
+        torch.cuda.synchronize()
     touched = np.abs(gref["opacity"]) > 0
     assert touched.sum() > 100
     fails = []

@@ -18,7 +18,7 @@ import pytest
 
 import oracle
 from paper_2503_10148_amd import scenes
-from tests._util import PARAMS, decode_records, grad_close, to_device
+from tests._util import PARAMS, decode_records, grad_close, make_projected, pure_rel_fraction, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -106,11 +106,11 @@ def test_project_matches_oracle(sss, name):
 # ---------------------------------------------------------------------------
 # binning / sorting
 # ---------------------------------------------------------------------------
-def test_bin_sort_bit_exact_on_synthetic_inputs(sss):
-    """Given identical rectangles and keys (many ties), the GPU lists equal the
-    oracle's (tile, key, index) order exactly; records are gathered verbatim.
-    The ellipses have an infinite level, so whole rectangles are listed."""
-    rng = np.random.default_rng(101)
+def _synthetic_bins_input(sss, span, seed=101):
+    """Three views of 4000 entries with random rectangles (25% culled) and
+    depth keys from [1.0 as FP32 bits, + span): the number of key bits the
+    depth passes sort follows the span (1 to 30 bits)."""
+    rng = np.random.default_rng(seed)
     cams = [scenes.ring_camera(100, 90, angle=0.0), scenes.ring_camera(61, 37, angle=1.0),
             scenes.ring_camera(300, 20, angle=2.0)]
     n = 4000
@@ -118,7 +118,7 @@ def test_bin_sort_bit_exact_on_synthetic_inputs(sss):
     E = n * V
     touched = np.zeros(E, np.int32)
     rect = np.zeros((E, 4), np.int16)
-    keys = (0x3F800000 + rng.integers(0, 40, E)).astype(np.uint32)   # many equal depths
+    keys = (0x3F800000 + rng.integers(0, span, E)).astype(np.uint32)   # span 40: many equal depths
     for v, c in enumerate(cams):
         tx, ty = oracle.tiles(c)
         for i in range(n):
@@ -133,10 +133,27 @@ def test_bin_sort_bit_exact_on_synthetic_inputs(sss):
             touched[e] = (x1 - x0 + 1) * (y1 - y0 + 1)
     records = rng.integers(0, 256, (E, 64), dtype=np.uint8)
     ell = np.tile(np.array([1.0, 0.0, 1.0, np.inf]), (E, 1))
-    proj = sss.Projected(torch.as_tensor(records, device="cuda"), torch.as_tensor(keys.view(np.int32), device="cuda"),
-                         torch.as_tensor(rect, device="cuda"), torch.as_tensor(touched, device="cuda"),
-                         torch.as_tensor(ell, device="cuda"))
-    bins = sss.BinSorter(16)(proj, cams, n)
+    proj = make_projected(sss, records, keys, rect, touched, ell)
+    return cams, n, touched, rect, keys, records, proj
+
+
+@pytest.mark.parametrize("no_wait", [False, True], ids=["wait", "no_wait"])
+@pytest.mark.parametrize("span", [1, 40, 256, 257, 65537, (1 << 24) + 3, (1 << 30) + 12345])
+def test_bin_sort_bit_exact_on_synthetic_inputs(sss, span, no_wait):
+    """Given identical rectangles and keys (many ties), the GPU lists equal the
+    oracle's (tile, key, index) order exactly; records are gathered verbatim.
+    The ellipses have an infinite level, so whole rectangles are listed.  The
+    key spans put the last depth pass that runs at each of the four passes
+    (and at the boundaries of a digit); with no_wait the call enqueues
+    everything without reading the counts back, and they arrive on the
+    device."""
+    cams, n, touched, rect, keys, records, proj = _synthetic_bins_input(sss, span)
+    if no_wait:
+        bins = sss.BinSorter(int(touched.sum()) + 100, no_wait=True)(proj, cams, n)
+        assert bins.n_pairs == -1 and bins.n_visible == -1
+        bins.resolve()
+    else:
+        bins = sss.BinSorter(16)(proj, cams, n)
     torch.cuda.synchronize()
     vis = np.nonzero(touched > 0)[0]
     assert bins.n_visible == len(vis) and bins.n_pairs == int(touched.sum())
@@ -157,6 +174,64 @@ def test_bin_sort_bit_exact_on_synthetic_inputs(sss):
             assert np.array_equal(g, olst[ost[t]:ost[t + 1]]), (v, t)
         toff += tx * ty
     assert start[toff] == bins.n_pairs
+
+
+def test_bin_sort_no_wait_overflow_stays_in_bounds_and_is_reported(sss):
+    """A no-wait call whose pairs exceed the capacity writes nothing past the
+    pair list it was given or past its workspace, and reports the required
+    count on the device; a call with enough capacity then gives the lists of
+    a waiting call."""
+    import ctypes
+    cams, n, touched, rect, keys, records, proj = _synthetic_bins_input(sss, 1 << 20, seed=5)
+    total = int(touched.sum())
+    E = n * len(cams)
+    T = sss.total_tiles(cams)
+    cap = total // 3
+    guard = 4096
+    pairs = torch.full((cap + guard,), -7, dtype=torch.int32, device="cuda")
+    ws_bytes = int(sss.lib().sss_bin_sort_workspace(E, cap))
+    ws = torch.full((ws_bytes + guard,), 0x5A, dtype=torch.uint8, device="cuda")
+    counts = torch.full((2,), -1, dtype=torch.int64, device="cuda")
+    out = sss.Binned(torch.empty(E, dtype=torch.int32, device="cuda"),
+                     torch.empty((E, sss.RECORD_BYTES), dtype=torch.uint8, device="cuda"),
+                     torch.empty(T + 1, dtype=torch.int32, device="cuda"), pairs,
+                     tile_order=torch.empty(T, dtype=torch.int32, device="cuda"), counts=counts)
+    b = sss.Bins(out.order.data_ptr(), out.sorted_records.data_ptr(), out.tile_start.data_ptr(), pairs.data_ptr(),
+                 None, out.tile_order.data_ptr(), None, cap, 0, 0, counts.data_ptr(), 1, 0)
+    p = proj.struct()
+    rc = sss.lib().sss_bin_sort(ctypes.byref(p), sss.camera_array(cams), len(cams), n, ctypes.byref(b),
+                                ctypes.c_void_p(ws.data_ptr()), ws_bytes, None)
+    assert rc == sss.OK and b.n_pairs == -1
+    torch.cuda.synchronize()
+    c = counts.cpu().numpy()
+    assert c[0] == int((touched > 0).sum()) and c[1] == total
+    assert bool((pairs[cap:] == -7).all())
+    assert bool((ws[ws_bytes:] == 0x5A).all())
+    # the listed ranks are valid even though the lists are incomplete
+    pr = pairs[:cap].cpu().numpy()
+    assert pr.min() >= 0 and pr.max() < c[0]
+    # with the capacity the counts asked for, the lists are the waiting call's
+    binner = sss.BinSorter(cap, no_wait=True)
+    first = binner(proj, cams, n)
+    with pytest.raises(sss.SSSError):
+        first.resolve()
+    binner.grow(first.n_pairs)
+    again = binner(proj, cams, n).resolve()
+    ref = sss.BinSorter(16)(proj, cams, n)
+    torch.cuda.synchronize()
+    assert again.n_pairs == ref.n_pairs == total
+    assert torch.equal(again.order[:ref.n_visible], ref.order[:ref.n_visible])
+    assert torch.equal(again.tile_start, ref.tile_start)
+    assert torch.equal(again.pair_rank[:total], ref.pair_rank[:total])
+
+
+def test_bin_sort_no_wait_with_nothing_visible(sss):
+    """All entries culled: no pairs, every tile empty, counts (0, 0)."""
+    cams, n, touched, rect, keys, records, proj = _synthetic_bins_input(sss, 40, seed=6)
+    proj.touched.zero_()
+    bins = sss.BinSorter(64, no_wait=True)(proj, cams, n).resolve()
+    assert bins.n_visible == 0 and bins.n_pairs == 0
+    assert int(bins.tile_start.abs().max()) == 0
 
 
 def test_bin_sort_reports_capacity_and_recovers(sss):
@@ -308,7 +383,12 @@ def test_render_bwd_matches_oracle(sss, name, mode):
     keep = ref["proj"]["pflags"] == 0
     for k in PARAMS:
         ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=keep)
+        frac = pure_rel_fraction(g[k].cpu().numpy(), gref[k], mask=keep)
+        print(f"gradient {name} {mode} {k}: worst {worst:.3g} of the bar, {100 * frac:.2f}% within 1e-3 relative")
         assert ok, (k, worst)
+        # beside the bar (relative, with the array's rms as the floor): the
+        # plain 1e-3 relative criterion holds for at least 99% of the elements
+        assert frac >= 0.99, (k, frac)
 
 
 def test_render_bwd_l1_fused_matches_oracle(sss):
@@ -693,11 +773,14 @@ def test_tile_schedule_changes_no_result(sss):
     assert np.array_equal(bins.tile_work.cpu().numpy().astype(np.int64).reshape(-1), work)
 
 
-def test_bin_sort_large_pair_count(sss):
+@pytest.mark.parametrize("no_wait", [False, True], ids=["wait", "no_wait"])
+def test_bin_sort_large_pair_count(sss, no_wait):
     """About 7e7 pairs (3 views of 1920x1080, whole-view rectangles): the
     pair sort's offset scans exceed one level of block sums and its passes
     run ~18000 workgroups.  Every tile of a view must list exactly the ranks
-    of that view's visible entries, ascending; checked on the device."""
+    of that view's visible entries, ascending; checked on the device.  With
+    no_wait the pair passes' grids cover a capacity 10% above the pairs and
+    the device's count bounds the work."""
     rng = np.random.default_rng(202)
     cams = [scenes.ring_camera(1920, 1080, angle=a) for a in (0.0, 1.0, 2.0)]
     n = 4000
@@ -714,10 +797,11 @@ def test_bin_sort_large_pair_count(sss):
     keys = (0x3F800000 + rng.integers(0, 5000, E)).astype(np.uint32)
     records = rng.integers(0, 256, (E, 64), dtype=np.uint8)
     ell = np.tile(np.array([1.0, 0.0, 1.0, np.inf]), (E, 1))
-    proj = sss.Projected(torch.as_tensor(records, device="cuda"), torch.as_tensor(keys.view(np.int32), device="cuda"),
-                         torch.as_tensor(rect, device="cuda"), torch.as_tensor(touched, device="cuda"),
-                         torch.as_tensor(ell, device="cuda"))
-    bins = sss.BinSorter(int(touched.sum()))(proj, cams, n)
+    proj = make_projected(sss, records, keys, rect, touched, ell)
+    if no_wait:
+        bins = sss.BinSorter(int(touched.sum() * 1.1), no_wait=True)(proj, cams, n).resolve()
+    else:
+        bins = sss.BinSorter(int(touched.sum()))(proj, cams, n)
     torch.cuda.synchronize()
     vi = np.nonzero(vis)[0]
     assert bins.n_visible == len(vi) and bins.n_pairs == int(touched.sum())
@@ -738,3 +822,110 @@ def test_bin_sort_large_pair_count(sss):
         assert torch.equal(seg, rv.unsqueeze(0).expand(T, -1)), v
         toff += T
     assert int(start[toff]) == bins.n_pairs
+
+
+# ---------------------------------------------------------------------------
+# fused backward + SGHMC/Adam step
+# ---------------------------------------------------------------------------
+def _step_state(dev, seed):
+    rng = np.random.default_rng(seed)
+    mom = torch.as_tensor(rng.normal(0, 1e-3, tuple(dev["means"].shape)).astype(np.float32), device="cuda")
+    m = {k: torch.as_tensor(rng.normal(0, 1e-4, tuple(dev[k].shape)).astype(np.float32), device="cuda")
+         for k in sss_step_arrays()}
+    v = {k: torch.as_tensor(rng.uniform(0, 1e-6, tuple(dev[k].shape)).astype(np.float32), device="cuda")
+         for k in sss_step_arrays()}
+    return mom, m, v
+
+
+def sss_step_arrays():
+    return ("scales", "quats", "nu", "opacity", "sh")
+
+
+def _clone_scene(dev):
+    out = {k: dev[k].clone() for k in PARAMS}
+    out["sh_degree"] = dev["sh_degree"]
+    return out
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+@pytest.mark.parametrize("burn_in", [False, True])
+def test_fused_step_equals_backward_then_step(sss, mode, burn_in):
+    """sss_render_bwd_step gives bit for bit what sss_render_bwd followed by
+    sss_sghmc_step (SGHMC on the means, Adam on the other five arrays) gives,
+    in the deterministic mode where the gradients themselves repeat bitwise:
+    parameters, momentum, Adam moments and the gradients it reports."""
+    scene, cams = _case("sh3_ragged")
+    n = scene["means"].shape[0]
+    md = sss.BWD_STORED if mode == "stored" else sss.BWD_RECOMPUTE
+    base = to_device(scene)
+    proj = sss.project(base, cams)
+    bins = sss.BinSorter(1024, keep_offsets=True)(proj, cams, n)
+    img, _, ncon = sss.render_fwd(bins, cams)
+    W, H = cams[0]["width"], cams[0]["height"]
+    target = torch.as_tensor(scenes.smooth_target(W, H, seed=3).reshape(-1, 3), device="cuda")
+    mom0, m0, v0 = _step_state(base, 11)
+    sg = dict(lr=2e-3, friction=0.1, burn_in=burn_in, noise=True, seed=9, step=4)
+    lrs = dict(scales=1e-3, quats=1e-3, nu=1e-2, opacity=1e-3, sh=2.5e-3)
+    lo = dict(scales=1e-4, nu=1.0, opacity=-1.0)
+    hi = dict(nu=1e4, opacity=1.0)
+
+    # separate calls
+    a = _clone_scene(base)
+    ga = sss.render_bwd(a, proj, bins, cams, target, mode=md, loss=sss.LOSS_L1, image=img, n_contrib=ncon,
+                        deterministic=True)
+    mom_a = mom0.clone()
+    ma = {k: m0[k].clone() for k in m0}
+    va = {k: v0[k].clone() for k in v0}
+    adam = dict(beta1=0.9, beta2=0.999, eps=1e-15, t=3,
+                arrays=[dict(param=a[k], grad=ga[k], m=ma[k], v=va[k], lr=lrs[k], lo=lo.get(k, -3.0e38),
+                             hi=hi.get(k, 3.0e38)) for k in sss_step_arrays()])
+    sss.sghmc_step(a["means"], mom_a, ga["means"], a["opacity"], friction=sg["friction"], lr=sg["lr"],
+                   burn_in=burn_in, seed=sg["seed"], step=sg["step"], scales=a["scales"], quats=a["quats"], adam=adam)
+
+    # fused
+    b = _clone_scene(base)
+    gb = {k: torch.empty_like(base[k]) for k in PARAMS}
+    mom_b = mom0.clone()
+    mb = {k: m0[k].clone() for k in m0}
+    vb = {k: v0[k].clone() for k in v0}
+    sss.render_bwd_step(b, proj, bins, cams, target, mom_b, sg,
+                        adam=dict(beta1=0.9, beta2=0.999, eps=1e-15, t=3, m=mb, v=vb, lr=lrs, lo=lo, hi=hi),
+                        mode=md, loss=sss.LOSS_L1, image=img, n_contrib=ncon, grads=gb, deterministic=True)
+    torch.cuda.synchronize()
+    for k in PARAMS:
+        assert torch.equal(gb[k], ga[k]), f"gradient {k}"
+        assert torch.equal(b[k], a[k]), f"parameter {k}"
+    assert torch.equal(mom_b, mom_a)
+    for k in sss_step_arrays():
+        assert torch.equal(mb[k], ma[k]) and torch.equal(vb[k], va[k]), f"moments {k}"
+    # the step moved something
+    assert not torch.equal(b["means"], base["means"]) and not torch.equal(b["sh"], base["sh"])
+
+
+def test_fused_step_without_gradient_output_matches(sss):
+    """With no gradient arrays the fused call updates the same way (the
+    atomic mode: gradients agree within the bar, the SGHMC means within what
+    those differences move them)."""
+    scene, cams = _case("clusters")
+    n = scene["means"].shape[0]
+    base = to_device(scene)
+    proj = sss.project(base, cams)
+    bins = sss.BinSorter(1024)(proj, cams, n)
+    img, _, ncon = sss.render_fwd(bins, cams)
+    W, H = cams[0]["width"], cams[0]["height"]
+    target = torch.as_tensor(scenes.smooth_target(W, H, seed=4).reshape(-1, 3), device="cuda")
+    sg = dict(lr=1e-2, friction=0.1, noise=False, seed=1, step=1)
+    a = _clone_scene(base)
+    ga = sss.render_bwd(a, proj, bins, cams, target, loss=sss.LOSS_L1, image=img, n_contrib=ncon)
+    mom_a = torch.zeros_like(base["means"])
+    sss.sghmc_step(a["means"], mom_a, ga["means"], a["opacity"], lr=sg["lr"], noise=False, seed=1, step=1)
+    b = _clone_scene(base)
+    mom_b = torch.zeros_like(base["means"])
+    sss.render_bwd_step(b, proj, bins, cams, target, mom_b, sg, loss=sss.LOSS_L1, image=img, n_contrib=ncon)
+    torch.cuda.synchronize()
+    # momentum after one step from zero is -lr G: compare G through it
+    ok, worst = grad_close(mom_b.cpu().numpy() / -sg["lr"], mom_a.cpu().numpy() / -sg["lr"])
+    assert ok, worst
+    np.testing.assert_allclose(b["means"].cpu().numpy(), a["means"].cpu().numpy(), rtol=0, atol=1e-6)
+    for k in ("scales", "quats", "nu", "opacity", "sh"):
+        assert torch.equal(b[k], base[k]), f"{k} changed without Adam"

@@ -1,8 +1,9 @@
-"""The raster kernels' other pixels-per-lane variants (SSS_PIX_FWD,
-SSS_PIX_BWD, read once per process) against the oracle: each setting runs
-in a child process that renders a small ragged case, back-propagates in the
-stored and recompute modes and checks image and gradients at the parity
-bar of the default variants."""
+"""The raster kernels' other variants, chosen by environment variables read
+once per process, against the oracle: pixels per lane (SSS_PIX_FWD,
+SSS_PIX_BWD) and the persistent work-queue form of the recompute-mode
+backward (SSS_BWD_PERSISTENT).  Each setting runs in a child process that
+renders a small ragged case, back-propagates in the stored and recompute
+modes and checks image and gradients at the parity bar of the defaults."""
 import os
 import subprocess
 import sys
@@ -47,10 +48,10 @@ print("ok")
 """
 
 
-@pytest.mark.parametrize("fwd,bwd", [("2", "1"), ("4", "4")])
-def test_pixels_per_lane_variants_match_oracle(fwd, bwd):
+@pytest.mark.parametrize("fwd,bwd,persistent", [("2", "1", "0"), ("4", "4", "0"), ("1", "1", "1"), ("1", "2", "1")])
+def test_pixels_per_lane_variants_match_oracle(fwd, bwd, persistent):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    env = dict(os.environ, SSS_PIX_FWD=fwd, SSS_PIX_BWD=bwd)
+    env = dict(os.environ, SSS_PIX_FWD=fwd, SSS_PIX_BWD=bwd, SSS_BWD_PERSISTENT=persistent)
     r = subprocess.run([sys.executable, "-c", CHILD], cwd=ROOT, env=env, capture_output=True, text=True, timeout=240)
     assert r.returncode == 0 and "ok" in r.stdout, (r.stdout[-2000:], r.stderr[-4000:])

@@ -151,3 +151,19 @@ def test_results_read_asynchronously_on_the_consumer_stream(env):
     torch.cuda.synchronize()
     for a, c in zip(alone, copies):
         assert np.array_equal(a, c.cpu().numpy())
+
+
+def test_underestimated_pair_counts_are_rendered_again(env):
+    """A server whose pairs-per-pixel estimate is far too small sizes its
+    first batches' pair passes too small; the counts that come back with a
+    batch show it, and the batch is rendered again before its results are
+    handed out: every image equals the plain renderer's."""
+    serve, sss, _, scene = env
+    cams = _cams(8, seed=9)
+    srv = serve.RenderServer(scene, max_batch=3, mem_budget=2 << 30, pairs_per_pixel=1e-4)
+    got = [f.result(timeout=60).cpu().numpy() for f in [srv.submit(c) for c in cams]]
+    srv.close()
+    assert srv.pairs_per_pixel_max > 1e-3                 # learned from the batches
+    plain = serve.PlainRenderer(scene, pairs_per_pixel=1e-4)
+    for c, g in zip(cams, got):
+        assert np.array_equal(plain.render(c).cpu().numpy(), g)

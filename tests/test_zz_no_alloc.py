@@ -87,7 +87,7 @@ def test_noalloc_rejects_more_than_it_holds(sss):
     cams = [scenes.ring_camera(64, 48)]
     import ctypes
     s = sss.Scene(n, 0, 0, *(scene[k].data_ptr() for k in PARAMS))
-    p = sss.Proj(*(scene["means"].data_ptr(),) * 5)
+    p = sss.Proj(*(scene["means"].data_ptr(),) * 3)
     b = sss.Bins(*(scene["means"].data_ptr(),) * 4, None, None, None, 1, 0, 0)
     g = sss.Grads(*(scene["means"].data_ptr(),) * 6, 1, 0)
     L = sss.lib()
