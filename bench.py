@@ -73,17 +73,18 @@ def _cpu_model():
     return "unknown"
 
 
-def _oracle_frame(scene, cam, side):
+def _oracle_frame(scene, cam, w, h):
     """Seconds of the FP64 oracle for one full-frame fwd+bwd, from the
     projection (+ its backward) of every component and the raster fwd+bwd of
-    a central side x side window, scaled by pixel count."""
+    a central w x h window, scaled by pixel count (w, h are clamped to the
+    frame; the full frame needs no scaling)."""
     import oracle
     from paper_2503_10148_amd import scenes
     W, H = cam["width"], cam["height"]
-    side = min(side, W, H)
-    x0, y0 = (W - side) // 2 // 16 * 16, (H - side) // 2 // 16 * 16
-    win = oracle.window_camera(cam, x0, y0, side, side)
-    target = scenes.smooth_target(W, H)[y0:y0 + side, x0:x0 + side]
+    w, h = min(w, W), min(h, H)
+    x0, y0 = (W - w) // 2 // 16 * 16, (H - h) // 2 // 16 * 16
+    win = oracle.window_camera(cam, x0, y0, w, h)
+    target = scenes.smooth_target(W, H)[y0:y0 + h, x0:x0 + w]
     t0 = time.perf_counter()
     proj = oracle.project(scene, win)
     t1 = time.perf_counter()
@@ -96,30 +97,29 @@ def _oracle_frame(scene, cam, side):
     # count it with the projection, estimated as the forward projection time
     t_proj = (t1 - t0) * 2.0
     t_raster = (t2 - t1) + (t3 - t2) - (t1 - t0)
-    return t_proj + max(t_raster, 0.0) * (W * H) / float(side * side), t3 - t0, (x0, y0)
+    return t_proj + max(t_raster, 0.0) * (W * H) / float(w * h), t3 - t0, (x0, y0, w, h)
 
 
-def cpu_baseline(scene, cam, side_all=1024, side_one=384):
-    """The FP64 oracle on bounded samples, on all host threads and on one:
-    projection (+ its backward) of every component and the raster fwd+bwd of
-    a central window, the raster time scaled to the full frame."""
+def cpu_baseline(scene, cam, side_one=512):
+    """The FP64 oracle, on all host threads over the whole frame and on one
+    thread over a central side_one x side_one window (scaled to the frame):
+    projection (+ its backward) of every component and the raster fwd+bwd."""
     import oracle
     W, H = cam["width"], cam["height"]
     threads = oracle.max_threads()
-    t_all, wall_all, org_all = _oracle_frame(scene, cam, side_all)
+    t_all, wall_all, win_all = _oracle_frame(scene, cam, W, H)
     oracle.set_threads(1)
     try:
-        t_one, wall_one, org_one = _oracle_frame(scene, cam, side_one)
+        t_one, wall_one, win_one = _oracle_frame(scene, cam, side_one, side_one)
     finally:
         oracle.set_threads(threads)
     n = scene["means"].shape[0]
     return {"value": round(W * H / t_all / 1e6, 6), "unit": "Mpix/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 oracle, {threads} OpenMP threads: projection and its backward of all {n} components, "
-                       f"raster fwd+bwd of a {side_all}x{side_all} window at {org_all}, scaled to {W}x{H}; "
-                       f"measured {wall_all:.1f} s"),
+                       f"raster fwd+bwd of the whole {W}x{H} frame; measured {wall_all:.1f} s"),
             "single_thread": {"value": round(W * H / t_one / 1e6, 6), "unit": "Mpix/s", "cores": 1,
-                              "sample": (f"same, one thread, window {side_one}x{side_one} at {org_one}; "
-                                         f"measured {wall_one:.1f} s")},
+                              "sample": (f"same, one thread, raster over a {win_one[2]}x{win_one[3]} window at "
+                                         f"({win_one[0]},{win_one[1]}) scaled to the frame; measured {wall_one:.1f} s")},
             "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
@@ -184,17 +184,34 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per render_bwd launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration);
-    None if there is none or the kernel sources changed since it was taken."""
+def measured_counters(workload):
+    """The committed rocprofv3 counter summary of the render_bwd launch
+    (HBM bytes = FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel
+    calibration; SQ_INSTS_VALU per launch where taken); {} if there is none
+    or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"render_bwd_{workload}_traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     d = json.load(open(path))
     if d.get("source_sha256") != kernel_source_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
+        return {}
+    return d
+
+
+def roofline(achieved, bwd_ms, evals, step_bytes, ms_step, ctr):
+    """The dominant kernel (render_bwd) against the VALU model peak, with
+    the counter cross-checks: its measured HBM bytes per launch, and the VALU
+    issue rate its SQ_INSTS_VALU count gives at the live launch time (wave
+    instructions x 64 lanes per second over the same peak); plus the whole
+    step's algorithmic bytes over its time as a fraction of HBM peak."""
+    out = {"bound": "alu", "kernel": "render_bwd", "achieved": round(achieved / 1e12, 3),
+           "peak": round(PEAK_VALU / 1e12, 3), "unit": "Tops/s", "frac": round(achieved / PEAK_VALU, 4),
+           "traffic": ctr.get("hbm_bytes_per_launch"), "avg_ms": round(bwd_ms, 4), "units": evals,
+           "ops_per_unit": SLOTS_BWD,
+           "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / PEAK_HBM, 4)}
+    vi = ctr.get("valu_insts_per_launch")
+    out["valu_issue_frac"] = round(vi * 64 / (bwd_ms * 1e-3) / PEAK_VALU, 4) if vi else None
+    return out
 
 
 def copy_probe():
@@ -393,7 +410,7 @@ def main():
     ap.add_argument("--unfused", action="store_true",
                     help="backward and SGHMC/Adam step as two calls (gradients through memory)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=int, default=1024, help="side of the all-thread oracle window")
+    ap.add_argument("--cpu-window", type=int, default=512, help="side of the one-thread oracle window")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="arrival window of each serving run (0 disables the serving measurement)")
     ap.add_argument("--serve-rates", default="200,500,1000,2000",
@@ -405,8 +422,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (one GPU per box in this build)",
-              file=sys.stderr)
+        print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -451,10 +467,7 @@ def main():
                    "deterministic": args.deterministic, "loss": "L1", "pairs": bins.n_pairs,
                    "visible": bins.n_visible, "evaluations": evals},
         "hbm_gbps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
-        "roofline": {"bound": "alu", "kernel": "render_bwd", "achieved": round(achieved / 1e12, 3),
-                     "peak": round(PEAK_VALU / 1e12, 3), "unit": "Tops/s",
-                     "frac": round(achieved / PEAK_VALU, 4), "traffic": measured_traffic(args.workload),
-                     "avg_ms": round(bwd_ms, 4), "units": evals, "ops_per_unit": SLOTS_BWD},
+        "roofline": roofline(achieved, bwd_ms, evals, step_bytes, ms_step, measured_counters(args.workload)),
         "stages": stages,
         "instrumented_ms_per_step": round((ti1 - ti0) * 1e3 / n_inst, 4),
         "other_workloads": others,
@@ -465,7 +478,7 @@ def main():
                                  args.serve_seconds, args.serve_clients)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(scene_np, cams[0], args.cpu_window)
+        out["cpu_baseline"] = cpu_baseline(scene_np, cams[0], side_one=args.cpu_window)
     print(json.dumps(out), flush=True)
 
 

@@ -133,8 +133,10 @@ __global__ __launch_bounds__(kBlock) void stat_reduce_kernel(const BlockStat* __
                                                              SortLayout lay, unsigned long long pair_capacity,
                                                              unsigned long long* __restrict__ counters,
                                                              SortDyn* __restrict__ dyn,
-                                                             unsigned long long* __restrict__ counts_out) {
+                                                             unsigned long long* __restrict__ counts_out,
+                                                             ScanSync* __restrict__ sync) {
   __shared__ BlockStat red[kBlock];
+  scan_sync_clear(sync);   // for the sort's single-pass scans
   BlockStat b{0ull, 0u, 0xFFFFFFFFu, 0u, 0u};
   // rounds of 8 statistics per thread, loaded before any is combined, so a
   // round waits for one memory latency (every later kernel waits on this one)
@@ -409,15 +411,41 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     }
     __syncthreads();
     const int in_block = (int)min((int64_t)kRPerBlock, n - block0);
-    for (int i = tid; i < in_block; i += kBlock) {
-      const uint32_t k = sk[i];
-      const uint32_t d = radix_digit(k, base_key, cap, shift, mask);
-      const uint32_t p = gbase[d] + ((uint32_t)i - dofs[d]);
-      okeys[p] = k;
-      ovals[p] = sv[i];
-      // optional gather by the output value for the first gn positions (the
-      // depth sort's last pass: the visible entries' tile counts in rank order)
-      if (gsrc && (int64_t)p < gn) gout[p] = gsrc[sv[i]];
+    if (gsrc) {
+      // the depth sort's last pass also gathers, for the first gn output
+      // positions, gsrc by the value (the visible entries' tile counts in
+      // rank order): all of a thread's gather loads are issued before its
+      // stores, so their latencies overlap
+      uint32_t gk[kRItems], gp[kRItems], gv[kRItems], gt[kRItems];
+#pragma unroll
+      for (int r = 0; r < kRItems; ++r) {
+        const int i = tid + r * kBlock;
+        gk[r] = gv[r] = gp[r] = 0u;
+        if (i < in_block) {
+          gk[r] = sk[i];
+          gv[r] = sv[i];
+          const uint32_t d = radix_digit(gk[r], base_key, cap, shift, mask);
+          gp[r] = gbase[d] + ((uint32_t)i - dofs[d]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRItems; ++r)
+        gt[r] = (tid + r * kBlock < in_block && (int64_t)gp[r] < gn) ? gsrc[gv[r]] : 0u;
+#pragma unroll
+      for (int r = 0; r < kRItems; ++r) {
+        if (tid + r * kBlock >= in_block) continue;
+        okeys[gp[r]] = gk[r];
+        ovals[gp[r]] = gv[r];
+        if ((int64_t)gp[r] < gn) gout[gp[r]] = gt[r];
+      }
+    } else {
+      for (int i = tid; i < in_block; i += kBlock) {
+        const uint32_t k = sk[i];
+        const uint32_t d = radix_digit(k, base_key, cap, shift, mask);
+        const uint32_t p = gbase[d] + ((uint32_t)i - dofs[d]);
+        okeys[p] = k;
+        ovals[p] = sv[i];
+      }
     }
   }  // radix blocks
 }
@@ -508,7 +536,59 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
   const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane(my_off);
   const uint32_t s1 = min((uint32_t)__builtin_amdgcn_readlane(my_off + my_cnt, last), capacity);
   int carry = 0;
-  for (uint32_t c0 = s0; c0 < s1; c0 += 64) {
+  // Row path, when every table rank's rows add up to its reserved count and
+  // a tile key fits 25 bits: the table's rows, in slot order, become (start
+  // slot, first key | rank lane << 25 | empty << 31); in each 64-slot window
+  // the non-empty rows that start there mark their start, and the max-scan
+  // hands every slot its row directly (key = the row's first key plus the
+  // slot's distance from the row start).
+  const uint64_t fitm = __ballot(valid && wr.fits);
+  const bool row_path = !__any(valid && wr.fits && wr.total != my_cnt) && cb.total_tiles <= (1 << 25);
+  if (row_path) {
+    uint32_t nrows = 0, s1m = s0;
+    if (fitm) {
+      const int lf = 63 - __builtin_clzll(fitm);                 // fitting ranks are a prefix
+      nrows = (uint32_t)__builtin_amdgcn_readlane(wr.base + wr.h, lf);
+      s1m = lf == last ? s1 : min(s1, (uint32_t)__builtin_amdgcn_readlane(my_off, lf + 1));
+    }
+    if (valid && wr.fits) {
+      for (int q = 0; q < wr.h; ++q) {
+        const int rw = wr.base + q;
+        const uint32_t c = table->cum[rw];
+        const uint32_t cn = q + 1 < wr.h ? table->cum[rw + 1] : (uint32_t)wr.total;
+        const uint32_t key = (uint32_t)(my_toff + (my_y0 + q) * my_tx) + table->t0[rw];
+        table->t0[rw] = key | ((uint32_t)lane << 25) | (cn == c ? 0x80000000u : 0u);
+        table->cum[rw] = (uint32_t)my_off + c;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint32_t rptr = 0;
+    for (uint32_t c0 = s0; c0 < s1m; c0 += 64) {
+      M.mark[lane] = 0;
+      __builtin_amdgcn_wave_barrier();
+      // rows are consumed in order: every row before rptr starts before c0
+      uint32_t taken;
+      do {
+        const uint32_t rw = rptr + (uint32_t)lane;
+        const uint32_t st = rw < nrows ? table->cum[rw] : 0xFFFFFFFFu;
+        const bool in = st < c0 + 64u;
+        if (in && !(table->t0[rw] >> 31)) M.mark[st - c0] = (int)rw + 1;
+        taken = (uint32_t)__popcll(__ballot(in));
+        rptr += taken;
+      } while (taken == 64u);
+      __builtin_amdgcn_wave_barrier();
+      const int m = wave_incl_max(M.mark[lane]);
+      const int rw = m > 0 ? m - 1 : carry;
+      carry = __builtin_amdgcn_readlane(rw, 63);
+      const uint32_t sl = c0 + (uint32_t)lane;
+      if (sl < s1m) {
+        const uint32_t pk = table->t0[rw];
+        tkeys[sl] = (pk & 0x1FFFFFFu) + (sl - table->cum[rw]);
+        tvals[sl] = (uint32_t)r0 + ((pk >> 25) & 63u);
+      }
+    }
+  }
+  for (uint32_t c0 = s0; !row_path && c0 < s1; c0 += 64) {
     M.mark[lane] = 0;
     __builtin_amdgcn_wave_barrier();
     if (valid && my_cnt > 0 && (uint32_t)my_off >= c0 && (uint32_t)my_off < c0 + 64u) M.mark[my_off - c0] = lane + 1;
@@ -606,6 +686,7 @@ __global__ __launch_bounds__(kBlock) void tile_start_kernel(const uint32_t* __re
 // ---------------------------------------------------------------------------
 struct Ws {
   uint32_t *flags, *pos, *ka, *va, *kb, *vb, *hist, *scan;
+  ScanSync* sync;
   unsigned long long* counters;
   SortDyn* dyn;
   BlockStat* stats;
@@ -624,6 +705,7 @@ Ws carve(void* base, int64_t n_entries, int64_t pair_cap) {
   auto take = [&](size_t bytes) { char* q = p ? p + off : nullptr; off += align256(bytes); return q; };
   w.counters = (unsigned long long*)take(4 * sizeof(unsigned long long));
   w.dyn = (SortDyn*)take(sizeof(SortDyn));
+  w.sync = (ScanSync*)take(sizeof(ScanSync));
   w.stats = (BlockStat*)take(sizeof(BlockStat) * (size_t)((n_entries + kBlock - 1) / kBlock + 1));
   w.flags = (uint32_t*)take(sizeof(uint32_t) * (size_t)n_entries);
   w.pos = (uint32_t*)take(sizeof(uint32_t) * (size_t)n_entries);
@@ -685,7 +767,8 @@ uint32_t* radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int
     else
       SSS_LAUNCH("radix_hist", radix_hist_kernel<kRItemsWide>, grid, dim3(kBlock), 0, st, ik, pa, mask, w.hist);
     // the histogram of the blocks the device counted (0 for an idle pass)
-    scan_excl(w.hist, w.hist, ((int64_t)1 << bits) * nb, w.scan, st, (const uint32_t*)&w.dyn->scan_n[kind][p]);
+    scan_excl_sync(w.hist, w.hist, ((int64_t)1 << bits) * nb, w.scan, w.sync, st,
+                   (const uint32_t*)&w.dyn->scan_n[kind][p]);
     if (dg.items == kRItemsNarrow)
       SSS_LAUNCH("radix_scatter", radix_scatter_kernel<kRItemsNarrow>, grid, dim3(kBlock), 0, st, ik, iv, pa, bits,
                  (const uint32_t*)w.hist, okk, ovv, out_v, gsrc, gn, gout);
@@ -737,7 +820,8 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
     for (int p = 0; p < 4; ++p) lay.rows[k][p] = p < dg.passes ? 1 << dg.bits[p] : 0;
   }
   SSS_LAUNCH("stat_reduce", stat_reduce_kernel, dim3(1), dim3(kBlock), 0, st, (const BlockStat*)w.stats, (int64_t)g1,
-             lay, (unsigned long long)bins->pair_capacity, w.counters, w.dyn, (unsigned long long*)bins->counts);
+             lay, (unsigned long long)bins->pair_capacity, w.counters, w.dyn, (unsigned long long*)bins->counts,
+             w.sync);
   // the grids of the pair passes cover the pair capacity, or, when the call
   // waits for the counts, just the pairs
   int64_t pair_grid = bins->pair_capacity;
@@ -762,7 +846,7 @@ int run_bin_sort(const CamBatch& cb, const sss_proj_t& proj, int64_t n, sss_bins
   // 3. pair offsets in rank order, emission, record gather; the caller may
   //    keep the offsets (deterministic backward pass)
   uint32_t* offs = bins->rank_offset ? bins->rank_offset : w.pos;
-  scan_excl(w.flags, offs, n_entries, w.scan, st);
+  scan_excl_sync(w.flags, offs, n_entries, w.scan, w.sync, st);
   const unsigned ge = (unsigned)((n_entries + kBlock - 1) / kBlock);
   SSS_LAUNCH("emit", emit_kernel, dim3(ge), dim3(kBlock), 0, st, cb, n, bins->order, (const Entry*)proj.entries,
              (const uint32_t*)offs, (const uint32_t*)w.flags, (const SortDyn*)w.dyn, (uint32_t)bins->pair_capacity,

@@ -356,8 +356,19 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     const float* __restrict__ sh, Entry* __restrict__ ent, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ touched) {
   __shared__ uint4 stage[kBlock * 8];
-  const int v = blockIdx.y;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+  // Workgroup ids are dealt to the 8 XCDs in turn.  Ids run over chunks of
+  // 8 component blocks x all views, view-major inside a chunk, so the views
+  // of one component block land on one XCD close together in time and read
+  // the block's parameters (the SH above all) from that XCD's L2 after the
+  // first view (view-major over the whole grid, every view re-read them
+  // from HBM).
+  const int64_t nb = (n + kBlock - 1) / kBlock;
+  const int64_t per_chunk = 8 * (int64_t)cb.n_views;
+  const int64_t chunk = (int64_t)blockIdx.x / per_chunk, rem = (int64_t)blockIdx.x - chunk * per_chunk;
+  const int v = (int)(rem >> 3);
+  const int64_t blk = chunk * 8 + (rem & 7);
+  if (blk >= nb) return;   // padding of the last chunk (whole workgroup)
+  const int64_t i0 = blk * kBlock;
   const int64_t i = i0 + threadIdx.x;
   const CamDev& c = cb.v[v];
   const int64_t e = (int64_t)v * n + i;
@@ -563,9 +574,12 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
 // Backward of the SH colour: d_sh[k][c] = sum over views of d colour_c Y_k
 // (where the colour is not clamped), and the part of d_means that comes from
 // the viewing direction.  The block's SH are staged in LDS, read for every
-// view's colour and direction gradient, then the same LDS slots accumulate
-// d_sh and are written back coalesced.  d_means is written (overwrite) or
-// accumulated; project_bwd_kernel adds the geometric part afterwards.
+// view's colour and direction gradient; d_sh is summed in registers and
+// passes through the same LDS slots to be written back coalesced (and, in a
+// training step, to the Adam update, which takes the SH values from the
+// slots first, so the coefficients are read from memory once).  d_means is
+// written (overwrite) or accumulated; project_bwd_kernel adds the geometric
+// part afterwards.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, const float* means,
                                                         const float* sh,
@@ -581,6 +595,9 @@ __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, 
   __syncthreads();
   const int64_t i = i0 + threadIdx.x;
   float* slot = shs + threadIdx.x * STR;
+  F gsh[KC];
+#pragma unroll
+  for (int j = 0; j < KC; ++j) gsh[j] = 0.0f;
   if (i < n) {
     const float* mu = means + 3 * i;
     F gmu[3] = {0, 0, 0};
@@ -628,8 +645,8 @@ __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, 
       float* part = reinterpret_cast<float*>(g2 + (size_t)i * kG2 + 10);
       for (int a = 0; a < 3; ++a) part[a] = gmu[a];
     }
-    // the SH values of this slot are no longer needed: accumulate d_sh in it
-    for (int j = 0; j < KC; ++j) slot[j] = 0.0f;
+    // d_sh of this component, in registers: the slot keeps the SH values
+    // for the update below
     for (int v = 0; v < cb.n_views; ++v) {
       const int64_t e = (int64_t)v * n + i;
       if (touched[e] == 0) continue;
@@ -642,45 +659,69 @@ __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, 
       sh_basis<F>(DEG, dir[0], dir[1], dir[2], Yb);
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
-        if (clamped & (1ull << (3 * v + ch))) continue;
+        const F gc = (clamped & (1ull << (3 * v + ch))) ? F(0) : gcol[ch];
 #pragma unroll
-        for (int k = 0; k < K; ++k) slot[3 * k + ch] += gcol[ch] * Yb[k];
+        for (int k = 0; k < K; ++k) gsh[3 * k + ch] += gc * Yb[k];
       }
     }
+  }
+  if (sa.on && sa.adam) {
+    // Adam on the SH coefficients, per wave over its own 64 components, in
+    // the memory order of the coefficient arrays (lane l takes elements
+    // l + 64 t), so the moments stream coalesced.  The SH values come from
+    // the slots (staged once), the gradient through the same slots: every
+    // lane first takes its values, then the slots are overwritten with the
+    // per-component gradients and read back in the same order.
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nc = min(max(cnt - 64 * wv, 0), 64);
+    const int total = nc * KC;
+    const float* wsl = shs + 64 * wv * STR;
+    float pv[KC], gv[KC];
+#pragma unroll
+    for (int t = 0; t < KC; ++t) {
+      const int el = lane + 64 * t, c = el / KC, j = el - c * KC;
+      pv[t] = el < total ? wsl[c * STR + j] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KC; ++j) slot[j] = gsh[j];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < KC; ++t) {
+      const int el = lane + 64 * t, c = el / KC, j = el - c * KC;
+      gv[t] = el < total ? wsl[c * STR + j] : 0.0f;
+    }
+    const size_t o0 = (size_t)(i0 + 64 * wv) * KC;
+    constexpr int kGrp = 8;                    // loads of a group issued before its updates
+#pragma unroll
+    for (int t0 = 0; t0 < KC; t0 += kGrp) {
+      float m[kGrp], v[kGrp];
+#pragma unroll
+      for (int u = 0; u < kGrp && t0 + u < KC; ++u) {
+        const int el = lane + 64 * (t0 + u);
+        if (el < total) {
+          m[u] = __builtin_nontemporal_load(sa.m[4] + o0 + el);
+          v[u] = __builtin_nontemporal_load(sa.v[4] + o0 + el);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGrp && t0 + u < KC; ++u) {
+        const int el = lane + 64 * (t0 + u);
+        if (el < total) {
+          float pp = pv[t0 + u];
+          adam_one(pp, gv[t0 + u], m[u], v[u], sa.lr[4], sa.lo[4], sa.hi[4], sa.ac);
+          __builtin_nontemporal_store(pp, sa.sh + o0 + el);
+          __builtin_nontemporal_store(m[u], sa.m[4] + o0 + el);
+          __builtin_nontemporal_store(v[u], sa.v[4] + o0 + el);
+        }
+      }
+    }
+    // the slots hold the gradients (per component) for the d_sh output
+  } else {
+#pragma unroll
+    for (int j = 0; j < KC; ++j) slot[j] = gsh[j];
   }
   __syncthreads();
-  if (sa.on && sa.adam) {
-    // Adam on the block's SH coefficients, coalesced, with the gradient
-    // from LDS: rounds of kShAdamIt elements per thread (256 apart), all
-    // their loads issued before any update; every element is touched once
-    // per step (streaming access)
-    constexpr int kShAdamIt = 4;
-    const size_t o0 = (size_t)i0 * KC;
-    const int total = cnt * KC;
-    for (int g0 = threadIdx.x; g0 < total; g0 += kShAdamIt * kBlock) {
-      float p[kShAdamIt], m[kShAdamIt], v[kShAdamIt];
-#pragma unroll
-      for (int k = 0; k < kShAdamIt; ++k) {
-        const int g = g0 + k * kBlock;
-        if (g < total) {
-          p[k] = __builtin_nontemporal_load(sa.sh + o0 + g);
-          m[k] = __builtin_nontemporal_load(sa.m[4] + o0 + g);
-          v[k] = __builtin_nontemporal_load(sa.v[4] + o0 + g);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kShAdamIt; ++k) {
-        const int g = g0 + k * kBlock;
-        if (g < total) {
-          const int c = g / KC, j = g - c * KC;
-          adam_one(p[k], shs[c * STR + j], m[k], v[k], sa.lr[4], sa.lo[4], sa.hi[4], sa.ac);
-          __builtin_nontemporal_store(p[k], sa.sh + o0 + g);
-          __builtin_nontemporal_store(m[k], sa.m[4] + o0 + g);
-          __builtin_nontemporal_store(v[k], sa.v[4] + o0 + g);
-        }
-      }
-    }
-  }
   if (!d_sh) return;
   float* dst = d_sh + (size_t)i0 * KC;
   for (int g = threadIdx.x; g < cnt * KC; g += kBlock) {
@@ -694,7 +735,9 @@ __global__ __launch_bounds__(kBlock) void sh_bwd_kernel(CamBatch cb, int64_t n, 
 
 void launch_project(const CamBatch& cb, const OptsDev& op, const sss_scene_t& s, const sss_proj_t& out,
                     hipStream_t st) {
-  dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock), (unsigned)cb.n_views);
+  // component blocks rounded up to the 8-block chunks of project_kernel's ids
+  const int64_t nb = (s.n + kBlock - 1) / kBlock;
+  dim3 grid((unsigned)(((nb + 7) / 8) * 8 * cb.n_views));
 #define SSS_PROJ(D)                                                                                          \
   SSS_LAUNCH("project", project_kernel<D>, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, s.means, s.scales, \
              s.quats, s.nu, s.opacity, s.sh, (Entry*)out.entries, out.depth_key, out.tiles_touched)

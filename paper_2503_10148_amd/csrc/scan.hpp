@@ -142,6 +142,112 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(const T* in, int64_t
   }
 }
 
+// Single-pass exclusive scan of uint32 counts over at most kFusedBlocks
+// blocks, one launch instead of the reduce + apply pair (whose cost here is
+// mostly the second launch).  A block takes its number from a ticket counter
+// when it starts, so every block with a smaller number is already running;
+// it publishes its sum as soon as it has it (one 64-bit word: a ready bit
+// above the 32-bit sum), adds the published sums of all blocks before it,
+// then scans its items.  The wait for a predecessor's word is bounded (the
+// predecessors never wait themselves, so it ends long before the bound).
+// The last block to finish clears the counters and the words it used, so
+// the next scan starts from zeros; the first scan of a sort needs them zeroed
+// by an earlier kernel (scan_sync_clear).
+struct ScanSync {
+  uint32_t ticket, done;
+  uint32_t pad[62];
+  unsigned long long word[1024];
+};
+
+constexpr int kScanSpin = 1 << 22;
+
+// Zeroes a ScanSync with the calling block's threads.
+__device__ __forceinline__ void scan_sync_clear(ScanSync* sync) {
+  for (int i = threadIdx.x; i < 1024; i += blockDim.x) sync->word[i] = 0ull;
+  if (threadIdx.x == 0) {
+    sync->ticket = 0u;
+    sync->done = 0u;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void scan_1pass_kernel(const uint32_t* in, int64_t n_max,
+                                                            const uint32_t* __restrict__ n_dev, ScanSync* sync,
+                                                            uint32_t* out) {
+  constexpr int kPad = kItems + 1;
+  __shared__ uint32_t lds[kBlock];
+  __shared__ uint32_t tile[kBlock * kPad];
+  __shared__ uint32_t s_ticket, s_last;
+  const int t = threadIdx.x;
+  if (t == 0) s_ticket = atomicAdd(&sync->ticket, 1u);
+  __syncthreads();
+  const uint32_t b = s_ticket;
+  const int64_t n = scan_count(n_max, n_dev);
+  const int64_t base = (int64_t)b * kPerBlock;
+  if (base < n) {                                    // uniform per block
+    uint32_t ld[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t j = base + (int64_t)k * kBlock + t;
+      ld[k] = j < n ? in[j] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int i = k * kBlock + t;
+      tile[(i / kItems) * kPad + i % kItems] = ld[k];
+    }
+    __syncthreads();
+    uint32_t v[kItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      v[k] = tile[t * kPad + k];
+      s += v[k];
+    }
+    uint32_t total;
+    const uint32_t run0 = block_excl_scan<uint32_t>(s, lds, &total);
+    if (t == 0)
+      __hip_atomic_store(&sync->word[b], (1ull << 32) | (unsigned long long)total, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    // the sums of the blocks before this one
+    uint32_t ps = 0;
+    for (uint32_t i = (uint32_t)t; i < b; i += kBlock) {
+      unsigned long long wv = 0ull;
+      for (int spin = 0; spin < kScanSpin; ++spin) {
+        wv = __hip_atomic_load(&sync->word[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (wv >> 32) break;
+        __builtin_amdgcn_s_sleep(1);
+      }
+      ps += (uint32_t)wv;
+    }
+    uint32_t pre;
+    block_excl_scan<uint32_t>(ps, lds, &pre);
+    uint32_t run = run0 + pre;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      tile[t * kPad + k] = run;
+      run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int i = k * kBlock + t;
+      const int64_t j = base + i;
+      if (j < n) out[j] = tile[(i / kItems) * kPad + i % kItems];
+    }
+  }
+  // the last block to finish leaves the counters and words at zero
+  __syncthreads();
+  if (t == 0) s_last = atomicAdd(&sync->done, 1u) == gridDim.x - 1u;
+  __syncthreads();
+  if (s_last) {
+    for (uint32_t i = (uint32_t)t; i < gridDim.x; i += kBlock) sync->word[i] = 0ull;
+    if (t == 0) {
+      sync->ticket = 0u;
+      sync->done = 0u;
+    }
+  }
+}
+
 // Scratch elements (of T) that scan_excl needs for n items.
 inline int64_t scan_ws_words(int64_t n) {
   int64_t w = 0;
@@ -153,6 +259,12 @@ inline int64_t scan_ws_words(int64_t n) {
 }
 
 constexpr int64_t kFusedBlocks = 1024;
+
+// scan_excl for uint32 counts with a ScanSync (zeroed before the first use,
+// left zeroed by every single-pass scan): one launch for up to kFusedBlocks
+// blocks of items, the two-launch scan beyond.
+inline void scan_excl_sync(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* ws, ScanSync* sync,
+                           hipStream_t st, const uint32_t* n_dev = nullptr);
 
 // Exclusive scan of in[0, n) into out.  With n_dev, the device supplies the
 // count (at most n; n sizes the grids): blocks past it do nothing, so a
@@ -178,6 +290,17 @@ void scan_excl(const T* in, T* out, int64_t n, T* ws, hipStream_t st, const uint
   scan_excl<T>(sums, sums_scan, nb, ws + 2 * nb, st);
   SSS_LAUNCH("scan_apply", scan_apply_kernel<T>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, n_dev,
              (const T*)sums_scan, (const T*)nullptr, out);
+}
+
+inline void scan_excl_sync(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* ws, ScanSync* sync,
+                           hipStream_t st, const uint32_t* n_dev) {
+  if (n <= 0) return;
+  const int64_t nb = (n + kPerBlock - 1) / kPerBlock;
+  if (nb == 1 || nb > kFusedBlocks) {
+    scan_excl<uint32_t>(in, out, n, ws, st, n_dev);
+    return;
+  }
+  SSS_LAUNCH("scan_1pass", scan_1pass_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, n_dev, sync, out);
 }
 
 }  // namespace

@@ -70,19 +70,27 @@ class _Slot:
     def __init__(self):
         self.binner = sss.BinSorter(0, no_wait=True)
         self.buf = {}
+        self.views = {}
         self.host_counts = None
         self.event = None
 
     def take(self, name, shape, dtype, device):
+        v = self.views.get((name, shape))
+        if v is not None:
+            return v
         numel = int(math.prod(shape))
         b = self.buf.get(name)
         if b is None or b.numel() < numel:
             # grow with headroom, so a run of slightly larger batches does
-            # not allocate every time
+            # not allocate every time; views of the old buffer are dropped
             grown = numel if b is None else max(numel, b.numel() + b.numel() // 4)
             b = torch.empty(max(grown, 1), dtype=dtype, device=device)
             self.buf[name] = b
-        return b[:numel].view(shape)
+            self.views = {k: t for k, t in self.views.items() if k[0] != name}
+        v = b[:numel].view(shape)
+        if len(self.views) < 256:
+            self.views[(name, shape)] = v
+        return v
 
 
 class RenderServer:
@@ -98,7 +106,7 @@ class RenderServer:
             raise ValueError(f"max_batch must be in 1..{sss.MAX_VIEWS}")
         self.scene = scene
         self.n = scene["means"].shape[0]
-        self.opts = opts
+        self.opts = sss.render_opts(opts)                 # marshalled once for every launch
         self.max_batch = max_batch
         # a stream's scratch buffers serve one batch at a time
         self.max_inflight = n_streams if max_inflight is None else max(1, min(int(max_inflight), n_streams))
@@ -111,7 +119,12 @@ class RenderServer:
         self.pairs_per_pixel_max = float(pairs_per_pixel)  # largest ratio seen: sizes the pair passes
         self._ws_cache = {}
         self._q = collections.deque()
-        self._cv = threading.Condition()
+        # one lock; the scheduler waits for queued requests (or room to
+        # launch) on _cv_sched, the completion thread for batches in flight
+        # on _cv_done, so a launch wakes only the thread that has work
+        self._lock = threading.Lock()
+        self._cv_sched = threading.Condition(self._lock)
+        self._cv_done = threading.Condition(self._lock)
         self._inflight = collections.deque()           # (event, reqs, bytes, keepalive, stream index)
         self._mem_used = 0
         self._launching = 0                            # batches popped but not yet in flight
@@ -131,14 +144,14 @@ class RenderServer:
         if need > self.mem_budget:
             r.future.set_exception(MemoryError(f"request of {r.pixels} pixels exceeds the memory budget"))
             return r.future
-        with self._cv:
+        with self._lock:
             if not self._running:
                 raise RuntimeError("server closed")
             direct = (not self._q and not self._inflight and self._launching == 0
                       and self._mem_used + need <= self.mem_budget)
             if not direct:
                 self._q.append(r)
-                self._cv.notify_all()
+                self._cv_sched.notify()
                 return r.future
             self._mem_used += need
             self._launching += 1
@@ -147,11 +160,19 @@ class RenderServer:
         self._run_batch([r], need, k)
         return r.future
 
-    def warmup(self, cams):
+    def warmup(self, cams, fill_budget: bool = False):
         """Render the batch `cams` once on every stream before requests arrive,
         so each stream's scratch buffers and pair capacity are sized for it;
-        later batches up to that size allocate nothing."""
+        later batches up to that size allocate nothing.  fill_budget: repeat
+        the largest of `cams` up to the biggest batch the memory budget and
+        max_batch admit, so no admissible batch grows a buffer later."""
         cams = list(cams)
+        if fill_budget and cams:
+            big = max(cams, key=lambda c: int(c["width"]) * int(c["height"]))
+            batch = []
+            while len(batch) < self.max_batch and self._estimate([_Req(c) for c in batch + [big]]) <= self.mem_budget:
+                batch.append(big)
+            cams = batch or [big]
         for stream, slot in zip(self.streams, self._slots):
             reqs = [_Req(c) for c in cams]
             keep, ev = self._launch(reqs, stream, slot)
@@ -165,9 +186,10 @@ class RenderServer:
                 ev.synchronize()
 
     def close(self):
-        with self._cv:
+        with self._lock:
             self._running = False
-            self._cv.notify_all()
+            self._cv_sched.notify_all()
+            self._cv_done.notify_all()
         self._sched.join()
         self._done.join()
 
@@ -191,13 +213,13 @@ class RenderServer:
     def _schedule(self):
         torch.cuda.set_device(self.device)
         while True:
-            with self._cv:
+            with self._lock:
                 while self._running and not self._q:
-                    self._cv.wait()
+                    self._cv_sched.wait()
                 if not self._running and not self._q:
                     return
                 if len(self._inflight) + self._launching >= self.max_inflight:
-                    self._cv.wait(timeout=0.05)              # let requests gather for the next batch
+                    self._cv_sched.wait(timeout=0.05)        # let requests gather for the next batch
                     continue
                 batch = []
                 while self._q and len(batch) < self.max_batch:
@@ -207,7 +229,7 @@ class RenderServer:
                         break
                     batch.append(self._q.popleft())
                 if not batch:                                   # memory full: wait for a completion
-                    self._cv.wait(timeout=0.05)
+                    self._cv_sched.wait(timeout=0.05)
                     continue
                 need = self._estimate(batch)
                 self._mem_used += need
@@ -229,17 +251,18 @@ class RenderServer:
         except Exception as exc:                            # pragma: no cover - surfaced to callers
             for r in batch:
                 r.future.set_exception(exc)
-            with self._cv:
+            with self._lock:
                 self._mem_used -= need
                 self._launching -= 1
-                self._cv.notify_all()
+                self._cv_sched.notify()
+                self._cv_done.notify()
             return
-        with self._cv:
+        with self._lock:
             self._inflight.append((ev, batch, need, keep, k))
             self._launching -= 1
             self.batches += 1
             self.batch_sizes.append(len(batch))
-            self._cv.notify_all()
+            self._cv_done.notify()
 
     def _launch(self, batch, stream, slot):
         cams = sss.CameraBatch([r.cam for r in batch])     # marshalled once for the three calls
@@ -278,11 +301,11 @@ class RenderServer:
     def _complete(self):
         torch.cuda.set_device(self.device)
         while True:
-            with self._cv:
+            with self._lock:
                 while not self._inflight:
                     if not self._running and not self._q and self._launching == 0:
                         return
-                    self._cv.wait(timeout=0.05)
+                    self._cv_done.wait(timeout=0.05)
                 ev, batch, need, keep, k = self._inflight[0]
             ev.synchronize()
             n_pairs = int(keep[3][1])
@@ -309,10 +332,11 @@ class RenderServer:
                 r.t_done = t
                 r.future.set_result(image[off:off + r.pixels].view(H, W, 3))
                 off += r.pixels
-            with self._cv:
+            with self._lock:
                 self._inflight.popleft()
                 self._mem_used -= need
-                self._cv.notify_all()
+                if self._q:
+                    self._cv_sched.notify()
 
 
 class PlainRenderer:
@@ -321,7 +345,7 @@ class PlainRenderer:
     def __init__(self, scene: dict, opts=None, pairs_per_pixel: float = 20.0):
         self.scene = scene
         self.n = scene["means"].shape[0]
-        self.opts = opts
+        self.opts = sss.render_opts(opts)
         self.binner = sss.BinSorter(0, no_wait=True, work=False)
         # as the server: the pair passes are sized by the largest pairs per
         # pixel seen so far
@@ -371,7 +395,7 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, warm=None, **server_kw):
+def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, warm=None, fill_budget=True, **server_kw):
     """Replay `arrivals` (seconds from start) with the request cameras `cams`
     against the batched server or the plain renderer.  Latency is measured
     from the scheduled arrival to the moment the image is ready on the
@@ -383,7 +407,7 @@ def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, warm=None
     if server_kind == "batched":
         srv = RenderServer(scene, opts, **server_kw)
         if warm:
-            srv.warmup(warm)
+            srv.warmup(warm, fill_budget=fill_budget)
         t0 = time.perf_counter()
         futs = []
         for a, cam in zip(arrivals, cams):
@@ -415,60 +439,64 @@ def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, warm=None
 
 
 def run_closed(server_kind: str, scene: dict, make_cam, n_clients: int, duration: float, opts=None, warm=None,
-               **server_kw):
-    """Closed loop: n_clients clients each submit a request (make_cam(k) for
-    the k-th request overall), wait for its image and submit the next, for
-    `duration` seconds.  The plain renderer serves the clients one request
-    at a time in arrival order (a lock).  Returns (latencies in s, requests
-    completed, pixels completed, wall time in s, server stats)."""
-    lock = threading.Lock()
-    lat, px = [], [0]
-    counter = [0]
+               fill_budget=True, **server_kw):
+    """Closed loop of n_clients clients, each sending its next request
+    (make_cam(k) for the k-th request overall) as soon as its previous one
+    returns, for `duration` seconds.  One driver thread keeps the
+    n_clients requests outstanding (client threads of their own would
+    measure the interpreter's thread switching rather than the server).
+    The plain renderer serves them one at a time in arrival order, so a
+    request waits for the ones ahead of it.  Returns (latencies in s,
+    requests completed, pixels completed, wall time in s, server stats)."""
+    import concurrent.futures as cf
+    lat, px, k = [], 0, 0
     stats = {}
+    t0 = time.perf_counter()
+    t_stop = t0 + duration
     if server_kind == "batched":
         srv = RenderServer(scene, opts, **server_kw)
         if warm:
-            srv.warmup(warm)
+            srv.warmup(warm, fill_budget=fill_budget)
+        t0 = time.perf_counter()
+        t_stop = t0 + duration
+        pending = set()
+        for _ in range(n_clients):
+            pending.add(srv.submit(make_cam(k)))
+            k += 1
+        while pending:
+            done, pending = cf.wait(pending, return_when=cf.FIRST_COMPLETED)
+            now = time.perf_counter()
+            for f in done:
+                f.result()
+                r = f.request
+                lat.append(r.t_done - r.t_submit)
+                px += r.pixels
+                if now < t_stop:
+                    pending.add(srv.submit(make_cam(k)))
+                    k += 1
+        t_end = time.perf_counter()
+        srv.close()
+        stats = dict(batches=srv.batches, mean_batch=sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)))
     elif server_kind == "plain":
         pr = PlainRenderer(scene, opts)
         if warm:
             pr.warmup(warm)
-        serial = threading.Lock()
+        t0 = time.perf_counter()
+        t_stop = t0 + duration
+        queue = collections.deque()                     # (submit time, camera), FIFO
+        for _ in range(n_clients):
+            queue.append((t0, make_cam(k)))
+            k += 1
+        while queue:
+            ts, cam = queue.popleft()
+            pr.render(cam)
+            now = time.perf_counter()
+            lat.append(now - ts)
+            px += int(cam["width"]) * int(cam["height"])
+            if now < t_stop:
+                queue.append((now, make_cam(k)))
+                k += 1
+        t_end = time.perf_counter()
     else:
         raise ValueError(server_kind)
-    t0 = time.perf_counter()
-    t_stop = t0 + duration
-
-    def client():
-        torch.cuda.set_device(scene["means"].device)
-        while True:
-            with lock:
-                k = counter[0]
-                counter[0] += 1
-            cam = make_cam(k)
-            ts = time.perf_counter()
-            if ts >= t_stop:
-                return
-            if server_kind == "batched":
-                f = srv.submit(cam)
-                f.result()
-                done = f.request.t_done
-            else:
-                with serial:
-                    pr.render(cam)
-                done = time.perf_counter()
-            with lock:
-                lat.append(done - ts)
-                px[0] += int(cam["width"]) * int(cam["height"])
-
-    threads = [threading.Thread(target=client, daemon=True) for _ in range(n_clients)]
-    for t in threads:
-        t.start()
-    for t in threads:
-        t.join()
-    t_end = time.perf_counter()
-    if server_kind == "batched":
-        srv.close()
-        stats = dict(batches=srv.batches, mean_batch=sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)))
-    return lat, len(lat), px[0], t_end - t0, stats
-
+    return lat, len(lat), px, t_end - t0, stats

@@ -237,6 +237,9 @@ def camera_array(cams):
 
 
 def render_opts(opts=None):
+    """dict of overrides (or None) -> RenderOpts; a RenderOpts is passed through."""
+    if isinstance(opts, RenderOpts):
+        return opts
     o = RenderOpts()
     lib().sss_default_render_opts(ctypes.byref(o))
     for k, v in (opts or {}).items():
