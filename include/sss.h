@@ -234,8 +234,11 @@ int sss_project(const sss_scene_t* scene, const sss_camera_t* cams, int n_views,
  *                first pair_capacity emitted pairs (no write leaves the
  *                buffers) and must not be used: the caller checks counts[1]
  *                and calls again with a larger pair_rank and workspace.
- *   counts       (device, nullable) receives (n_visible, required pairs) as
- *                two uint64 on the stream, in either mode.
+ *   counts       (nullable) receives (n_visible, required pairs) as two
+ *                uint64, written by a kernel of the call, in either mode:
+ *                device memory, or pinned host memory the device can write
+ *                (hipHostMalloc), which the host may read once the call's
+ *                work has completed (no copy needed).
  * The deterministic backward pass needs the host counts (no_wait = 0).
  * Workspace: ws of ws_bytes >= sss_bin_sort_workspace(n_entries, pair_capacity).
  * Errors: CAPACITY (no_wait = 0) when n_pairs > pair_capacity (re-allocate
@@ -252,7 +255,7 @@ typedef struct {
   int64_t pair_capacity;
   int64_t n_visible;   /* out (host; -1 with no_wait) */
   int64_t n_pairs;     /* out (host; -1 with no_wait) */
-  uint64_t* counts;    /* nullable device [2]: n_visible, required pairs */
+  uint64_t* counts;    /* nullable [2], device or pinned host: n_visible, required pairs */
   int32_t no_wait;     /* 1: enqueue everything without waiting for the counts */
   int32_t reserved;
 } sss_bins_t;

@@ -520,15 +520,67 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
     my_off = (int)off[r];
     my_cnt = (int)cnt[r];
   }
-  const WaveRows wr = wave_row_table(valid, my_mx, my_my, my_el, my_x0, my_y0, my_x1, my_y1, table);
+  // The rows of the wave's entries, spread over the lanes: the entries'
+  // rows are numbered in rank order (entry j's h_j rows from base_j, an
+  // exclusive scan of the heights), and lane l evaluates rows l, l + 64, ...
+  // of those that fit the table (the entries that fit are a prefix).  A
+  // row's entry comes from a max-scan of marks at the entries' first rows,
+  // its constants from that entry's lane.  Each row is stored as (its start
+  // slot relative to the wave's first slot, first tile key | entry lane << 25
+  // | empty << 31); the start slots are a running sum of the row lengths,
+  // which equals the offsets scan whenever every entry's rows add up to its
+  // reserved count.
+  const int h = valid ? my_y1 - my_y0 + 1 : 0;
+  const int incl = wave_incl_scan(h);
+  const int base = incl - h;
+  const bool listed = valid && incl <= kRowSlots;
+  const uint64_t fitm = __ballot(listed);
+  const int nrows = fitm ? __builtin_amdgcn_readlane(incl, 63 - __builtin_clzll(fitm)) : 0;
+  const bool keys25 = cb.total_tiles < (1 << 25);
+  RowGeo geo{};
+  if (valid) geo = make_row_geo(my_mx, my_my, my_el);
+  uint32_t gsum = 0;                 // slots of the rows of earlier rounds
+  int own_carry = 0;
+  for (int q0 = 0; q0 < nrows; q0 += 64) {
+    M.mark[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    if (listed && h > 0 && base >= q0 && base < q0 + 64) M.mark[base - q0] = lane + 1;
+    __builtin_amdgcn_wave_barrier();
+    const int mk = wave_incl_max(M.mark[lane]);
+    const int own = mk > 0 ? mk - 1 : own_carry;
+    own_carry = __builtin_amdgcn_readlane(own, 63);
+    RowGeo og;
+    og.mx = __shfl(geo.mx, own, 64);
+    og.my = __shfl(geo.my, own, 64);
+    og.k = __shfl(geo.k, own, 64);
+    og.S = __shfl(geo.S, own, 64);
+    og.ds = __shfl(geo.ds, own, 64);
+    og.ey = __shfl(geo.ey, own, 64);
+    og.iD = __shfl(geo.iD, own, 64);
+    og.hr = __shfl(geo.hr, own, 64);
+    og.inf = __shfl((int)geo.inf, own, 64) != 0;
+    const int ob = __shfl(base, own, 64), oy0 = __shfl(my_y0, own, 64);
+    const int ox0 = __shfl(my_x0, own, 64), ox1 = __shfl(my_x1, own, 64);
+    const int otoff = __shfl(my_toff, own, 64), otx = __shfl(my_tx, own, 64);
+    const int rw = q0 + lane;
+    const int y = oy0 + (rw - ob);
+    int len = 0, t0 = ox0;
+    if (rw < nrows) len = row_run(og, y, ox0, ox1, &t0);
+    const int li = wave_incl_scan(len);
+    if (rw < nrows) {
+      const uint32_t key = (uint32_t)(otoff + y * otx + t0) & 0x1FFFFFFu;
+      table->t0[rw] = key | ((uint32_t)own << 25) | (len == 0 ? 0x80000000u : 0u);
+      table->cum[rw] = gsum + (uint32_t)(li - len);
+    }
+    gsum += (uint32_t)__builtin_amdgcn_readlane(li, 63);
+  }
+  __builtin_amdgcn_wave_barrier();
+  int total = 0;
+  if (listed && h > 0) total = (int)((base + h < nrows ? table->cum[base + h] : gsum) - table->cum[base]);
   M.off[lane] = (uint32_t)my_off;
-  M.base[lane] = wr.base;
-  M.h[lane] = wr.h;
-  M.total[lane] = wr.total;
   M.y0[lane] = my_y0;
   M.toff[lane] = my_toff;
   M.tx[lane] = my_tx;
-  M.fits[lane] = valid && wr.fits;
   __syncthreads();
   const int64_t r0 = r - lane;
   if (r0 >= n_vis) return;   // uniform per wave; no barrier follows
@@ -536,32 +588,18 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
   const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane(my_off);
   const uint32_t s1 = min((uint32_t)__builtin_amdgcn_readlane(my_off + my_cnt, last), capacity);
   int carry = 0;
-  // Row path, when every table rank's rows add up to its reserved count and
-  // a tile key fits 25 bits: the table's rows, in slot order, become (start
-  // slot, first key | rank lane << 25 | empty << 31); in each 64-slot window
-  // the non-empty rows that start there mark their start, and the max-scan
-  // hands every slot its row directly (key = the row's first key plus the
-  // slot's distance from the row start).
-  const uint64_t fitm = __ballot(valid && wr.fits);
-  const bool row_path = !__any(valid && wr.fits && wr.total != my_cnt) && cb.total_tiles <= (1 << 25);
+  // Row path, when every listed entry's rows add up to its reserved count
+  // and a tile key fits 25 bits: in each 64-slot window the non-empty rows
+  // that start there mark their start, and the max-scan hands every slot its
+  // row directly (key = the row's first key plus the slot's distance from the
+  // row start).
+  const bool row_path = !__any(listed && total != my_cnt) && keys25;
   if (row_path) {
-    uint32_t nrows = 0, s1m = s0;
+    uint32_t s1m = s0;
     if (fitm) {
-      const int lf = 63 - __builtin_clzll(fitm);                 // fitting ranks are a prefix
-      nrows = (uint32_t)__builtin_amdgcn_readlane(wr.base + wr.h, lf);
+      const int lf = 63 - __builtin_clzll(fitm);                 // listed ranks are a prefix
       s1m = lf == last ? s1 : min(s1, (uint32_t)__builtin_amdgcn_readlane(my_off, lf + 1));
     }
-    if (valid && wr.fits) {
-      for (int q = 0; q < wr.h; ++q) {
-        const int rw = wr.base + q;
-        const uint32_t c = table->cum[rw];
-        const uint32_t cn = q + 1 < wr.h ? table->cum[rw + 1] : (uint32_t)wr.total;
-        const uint32_t key = (uint32_t)(my_toff + (my_y0 + q) * my_tx) + table->t0[rw];
-        table->t0[rw] = key | ((uint32_t)lane << 25) | (cn == c ? 0x80000000u : 0u);
-        table->cum[rw] = (uint32_t)my_off + c;
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
     uint32_t rptr = 0;
     for (uint32_t c0 = s0; c0 < s1m; c0 += 64) {
       M.mark[lane] = 0;
@@ -570,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
       uint32_t taken;
       do {
         const uint32_t rw = rptr + (uint32_t)lane;
-        const uint32_t st = rw < nrows ? table->cum[rw] : 0xFFFFFFFFu;
+        const uint32_t st = rw < (uint32_t)nrows ? s0 + table->cum[rw] : 0xFFFFFFFFu;
         const bool in = st < c0 + 64u;
         if (in && !(table->t0[rw] >> 31)) M.mark[st - c0] = (int)rw + 1;
         taken = (uint32_t)__popcll(__ballot(in));
@@ -583,35 +621,45 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, co
       const uint32_t sl = c0 + (uint32_t)lane;
       if (sl < s1m) {
         const uint32_t pk = table->t0[rw];
-        tkeys[sl] = (pk & 0x1FFFFFFu) + (sl - table->cum[rw]);
+        tkeys[sl] = (pk & 0x1FFFFFFu) + (sl - s0 - table->cum[rw]);
         tvals[sl] = (uint32_t)r0 + ((pk >> 25) & 63u);
       }
     }
-  }
-  for (uint32_t c0 = s0; !row_path && c0 < s1; c0 += 64) {
-    M.mark[lane] = 0;
+  } else {
+    // the per-rank path: the table again in its plain form (first column and
+    // the tiles of the rows above, per entry), each slot's rank by the marks
+    // of the ranks' first slots and its row by binary search
+    const WaveRows wr = wave_row_table(valid, my_mx, my_my, my_el, my_x0, my_y0, my_x1, my_y1, table);
+    M.base[lane] = wr.base;
+    M.h[lane] = wr.h;
+    M.total[lane] = wr.total;
+    M.fits[lane] = valid && wr.fits;
     __builtin_amdgcn_wave_barrier();
-    if (valid && my_cnt > 0 && (uint32_t)my_off >= c0 && (uint32_t)my_off < c0 + 64u) M.mark[my_off - c0] = lane + 1;
-    __builtin_amdgcn_wave_barrier();
-    const int m = wave_incl_max(M.mark[lane]);
-    const int rk = m > 0 ? m - 1 : carry;
-    carry = __builtin_amdgcn_readlane(rk, 63);
-    const uint32_t sl = c0 + (uint32_t)lane;
-    if (sl < s1 && M.fits[rk]) {
-      const int k = (int)(sl - M.off[rk]);
-      uint32_t key = (uint32_t)cb.total_tiles;
-      if (k < M.total[rk]) {
-        const int b = M.base[rk];
-        const int row = find_row(table, b, M.h[rk], k);
-        const int x = (int)table->t0[b + row] + (k - (int)table->cum[b + row]);
-        key = (uint32_t)(M.toff[rk] + (M.y0[rk] + row) * M.tx[rk] + x);
+    for (uint32_t c0 = s0; c0 < s1; c0 += 64) {
+      M.mark[lane] = 0;
+      __builtin_amdgcn_wave_barrier();
+      if (valid && my_cnt > 0 && (uint32_t)my_off >= c0 && (uint32_t)my_off < c0 + 64u) M.mark[my_off - c0] = lane + 1;
+      __builtin_amdgcn_wave_barrier();
+      const int m = wave_incl_max(M.mark[lane]);
+      const int rk = m > 0 ? m - 1 : carry;
+      carry = __builtin_amdgcn_readlane(rk, 63);
+      const uint32_t sl = c0 + (uint32_t)lane;
+      if (sl < s1 && M.fits[rk]) {
+        const int k = (int)(sl - M.off[rk]);
+        uint32_t key = (uint32_t)cb.total_tiles;
+        if (k < M.total[rk]) {
+          const int b = M.base[rk];
+          const int row = find_row(table, b, M.h[rk], k);
+          const int x = (int)table->t0[b + row] + (k - (int)table->cum[b + row]);
+          key = (uint32_t)(M.toff[rk] + (M.y0[rk] + row) * M.tx[rk] + x);
+        }
+        tkeys[sl] = key;
+        tvals[sl] = (uint32_t)(r0 + rk);
       }
-      tkeys[sl] = key;
-      tvals[sl] = (uint32_t)(r0 + rk);
     }
   }
   // ranks whose rows did not fit the table, one at a time
-  uint64_t rest = __ballot(valid && my_cnt > 0 && !wr.fits);
+  uint64_t rest = __ballot(valid && my_cnt > 0 && !listed);
   while (rest) {
     const int j = (int)__builtin_ctzll(rest);
     rest &= rest - 1;

@@ -37,6 +37,7 @@ stream, same kernels.
 from __future__ import annotations
 
 import collections
+import functools
 import math
 import threading
 import time
@@ -72,6 +73,7 @@ class _Slot:
         self.buf = {}
         self.views = {}
         self.host_counts = None
+        self.host_np = None          # numpy view of host_counts
         self.event = None
 
     def take(self, name, shape, dtype, device):
@@ -140,10 +142,12 @@ class RenderServer:
     # ---------------------------------------------------------------- public
     def submit(self, cam) -> Future:
         r = _Req(cam)
+        fut = r.future            # r drops it on completion, which may come before this returns
         need = self._estimate([r])
         if need > self.mem_budget:
-            r.future.set_exception(MemoryError(f"request of {r.pixels} pixels exceeds the memory budget"))
-            return r.future
+            r.future = None
+            fut.set_exception(MemoryError(f"request of {r.pixels} pixels exceeds the memory budget"))
+            return fut
         with self._lock:
             if not self._running:
                 raise RuntimeError("server closed")
@@ -152,13 +156,13 @@ class RenderServer:
             if not direct:
                 self._q.append(r)
                 self._cv_sched.notify()
-                return r.future
+                return fut
             self._mem_used += need
             self._launching += 1
             k = self._take_stream()
         # the device is idle: launch from this thread, like a plain renderer
         self._run_batch([r], need, k)
-        return r.future
+        return fut
 
     def warmup(self, cams, fill_budget: bool = False):
         """Render the batch `cams` once on every stream before requests arrive,
@@ -201,6 +205,7 @@ class RenderServer:
         P = sum(r.pixels for r in reqs)
         E = V * self.n
         M = int(P * self.pairs_per_pixel * 1.25) + 1024
+        M = ((M + (1 << 20) - 1) >> 20) << 20       # whole Mi-pairs: the workspace size cache hits
         per_entry = sss.ENTRY_BYTES + 4 + 4 + 4 + _REC
         key = (E, M)
         ws = self._ws_cache.get(key)
@@ -250,7 +255,8 @@ class RenderServer:
             keep, ev = self._launch(batch, stream, slot)
         except Exception as exc:                            # pragma: no cover - surfaced to callers
             for r in batch:
-                r.future.set_exception(exc)
+                fut, r.future = r.future, None
+                fut.set_exception(exc)
             with self._lock:
                 self._mem_used -= need
                 self._launching -= 1
@@ -279,18 +285,18 @@ class RenderServer:
                              slot.take("sorted", (E, sss.RECORD_BYTES), torch.uint8, dev),
                              slot.take("tile_start", (T + 1,), torch.int32, dev), None,
                              tile_order=slot.take("tile_order", (T,), torch.int32, dev))
-            counts = slot.take("counts", (2,), torch.int64, dev)
+            # the counts go straight to pinned host memory, written by the
+            # sort's kernel and read after the batch's event (one buffer per
+            # stream: a stream has one batch in flight)
+            if slot.host_counts is None:
+                slot.host_counts = torch.empty(2, dtype=torch.int64, pin_memory=True)
+                slot.host_np = slot.host_counts.numpy()
+            host_counts = slot.host_counts
             # the pair passes are sized by an estimate from the pairs per
             # pixel seen so far (a batch that needs more is rendered again)
             hint = int(self.pairs_per_pixel_max * 1.5 * P) + 8192
-            bins = slot.binner(proj, cams, self.n, stream=stream, out=out, counts=counts, capacity=hint)
+            bins = slot.binner(proj, cams, self.n, stream=stream, out=out, counts=host_counts, capacity=hint)
             image, _, _ = sss.render_fwd(bins, cams, self.opts, stream=stream, aux=False)
-            # the counts reach the host with the batch (read after its event;
-            # one pinned buffer per stream: a stream has one batch in flight)
-            if slot.host_counts is None:
-                slot.host_counts = torch.empty(2, dtype=torch.int64, pin_memory=True)
-            host_counts = slot.host_counts
-            host_counts.copy_(counts, non_blocking=True)
             # one event per stream: a stream has one batch in flight
             if slot.event is None:
                 slot.event = torch.cuda.Event()
@@ -308,16 +314,13 @@ class RenderServer:
                     self._cv_done.wait(timeout=0.05)
                 ev, batch, need, keep, k = self._inflight[0]
             ev.synchronize()
-            n_pairs = int(keep[3][1])
+            n_pairs = int(self._slots[k].host_np[1])
             P = sum(r.pixels for r in batch)
-            if P > 0:
-                self.pairs_per_pixel = 0.8 * self.pairs_per_pixel + 0.2 * n_pairs / P
-                self.pairs_per_pixel_max = max(self.pairs_per_pixel_max, n_pairs / P)
             if n_pairs > keep[1].cap():
-                # the lists were cut short: grow this stream's buffers (and
-                # the estimate, above) and render the batch again (its
-                # stream has nothing else queued: one batch per stream is in
-                # flight)
+                # the lists were cut short: grow this stream's buffers and
+                # the estimate, and render the batch again (its stream has
+                # nothing else queued: one batch per stream is in flight)
+                self.pairs_per_pixel_max = max(self.pairs_per_pixel_max, n_pairs / max(P, 1))
                 self._slots[k].binner.grow(n_pairs)
                 keep, ev = self._launch(batch, self.streams[k], self._slots[k])
                 ev.synchronize()
@@ -330,8 +333,15 @@ class RenderServer:
             for r in batch:
                 H, W = int(r.cam["height"]), int(r.cam["width"])
                 r.t_done = t
-                r.future.set_result(image[off:off + r.pixels].view(H, W, 3))
+                # the request drops its future (future.request stays): no
+                # reference cycle keeps a served image alive after the
+                # caller lets go of the future
+                fut, r.future = r.future, None
+                fut.set_result(image[off:off + r.pixels].view(H, W, 3))
                 off += r.pixels
+            if P > 0:
+                self.pairs_per_pixel = 0.8 * self.pairs_per_pixel + 0.2 * n_pairs / P
+                self.pairs_per_pixel_max = max(self.pairs_per_pixel_max, n_pairs / P)
             with self._lock:
                 self._inflight.popleft()
                 self._mem_used -= need
@@ -408,18 +418,34 @@ def run_load(server_kind: str, scene: dict, cams, arrivals, opts=None, warm=None
         srv = RenderServer(scene, opts, **server_kw)
         if warm:
             srv.warmup(warm, fill_budget=fill_budget)
+        # latencies are taken as requests complete and the futures (and with
+        # them the images) are not kept: a long run at a high rate would
+        # otherwise hold every image it served
+        done_cv = threading.Condition()
+        left = [len(arrivals)]
+        errors = []
+
+        def finished(f, ta):
+            with done_cv:
+                if f.exception() is None:
+                    lat.append(f.request.t_done - ta)
+                else:
+                    errors.append(f.exception())
+                left[0] -= 1
+                done_cv.notify()
+
         t0 = time.perf_counter()
-        futs = []
         for a, cam in zip(arrivals, cams):
             now = time.perf_counter() - t0
             if a > now:
                 time.sleep(a - now)
-            futs.append((t0 + a, srv.submit(cam)))
-        for _, f in futs:
-            f.result()
+            srv.submit(cam).add_done_callback(functools.partial(finished, ta=t0 + a))
+        with done_cv:
+            done_cv.wait_for(lambda: left[0] == 0)
         t_end = time.perf_counter()
-        lat = [f.request.t_done - ta for ta, f in futs]
         srv.close()
+        if errors:
+            raise errors[0]
         stats = dict(batches=srv.batches, mean_batch=sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)))
     elif server_kind == "plain":
         pr = PlainRenderer(scene, opts)
