@@ -426,7 +426,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
           Eval E;
           evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
           const bool live = T[k] > 0.0f && E.hit;
-          const float Tn = T[k] * (1.0f - E.alpha);
+          const float Tn = __fmaf_rn(-T[k], E.alpha, T[k]);   // T (1 - alpha), one rounding
           const bool term = Tn < op.t_min;
           const bool comp = __builtin_unpredictable(live && !term);
           // the select on alpha, not on the product: one FP32 select
@@ -441,7 +441,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
           Eval E;
           evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
           if (E.hit) {
-            const float Tn = T[k] * (1.0f - E.alpha);
+            const float Tn = __fmaf_rn(-T[k], E.alpha, T[k]);
             if (Tn < op.t_min) {
               T[k] = -T[k];
             } else {
@@ -658,7 +658,7 @@ __device__ __forceinline__ void render_bwd_unit(
         // a clamped alpha passes no gradient to T2D
         const float da0 = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), Tk * gc);
         const float da = hk && !E.clamped ? da0 : 0.0f;
-        T[k] = hk ? Tk * (1.0f - a) : Tk;
+        T[k] = hk ? __fmaf_rn(-Tk, a, Tk) : Tk;   // as the forward walk
         const float dt2 = da * L.o;
         const float ru = kGauss ? 1.0f : __builtin_amdgcn_rcpf(E.u);
         // d log2 T / dh = nb / (nu (1 + y)); nb ln 2 for the Gaussian family

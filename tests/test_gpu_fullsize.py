@@ -148,3 +148,40 @@ def test_sghmc_step_on_five_million_components(sss):
     torch.cuda.synchronize()
     np.testing.assert_allclose(dmu.cpu().numpy(), ref_mu, rtol=1e-5, atol=2e-6)
     np.testing.assert_allclose(dr.cpu().numpy(), ref_r, rtol=1e-5, atol=2e-6)
+
+
+@pytest.mark.parametrize("name", ["m1", "large"])
+def test_full_size_tile_lists_match_oracle(sss, name):
+    """Every tile's list at the full workload size, in the binning the
+    benchmark runs (no host wait, a second call with the capacity the first
+    one sized), against the oracle's per-tile lists (box of pixel centres
+    meets the ellipse; depth key, then index): the same components in the
+    same order, except components whose rectangle decisions the oracle
+    flags as within its margin, which are dropped from both sides."""
+    scene, cams = scenes.workload(name)
+    cam = cams[0]
+    n = scene["means"].shape[0]
+    o = oracle.project(scene, cam)
+    tx, ty = oracle.tiles(cam)
+    ost, olst = oracle.bin_tiles(o["touched"], o["rect"], o["key"], tx, ty, proj=o)
+    dev = to_device(scene)
+    proj = sss.project(dev, cams)
+    binner = sss.BinSorter(0, no_wait=True)
+    binner(proj, cams, n).resolve()                       # sizes the capacity (this call waits)
+    counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+    bins = binner(proj, cams, n, counts=counts)           # the no-wait call
+    torch.cuda.synchronize()
+    bins.resolve()
+    assert bins.n_pairs == int(o["touched"].sum())
+    T = tx * ty
+    order = bins.order.cpu().numpy().view(np.uint32).astype(np.int64)
+    start = bins.tile_start.cpu().numpy().astype(np.int64)
+    assert start[0] == 0 and start[T] == bins.n_pairs
+    ids = order[bins.pair_rank.cpu().numpy()[: bins.n_pairs].astype(np.int64)]
+    tile = np.repeat(np.arange(T), np.diff(start[: T + 1]))
+    ref_tile = np.repeat(np.arange(T), np.diff(ost.astype(np.int64)))
+    flagged = (o["pflags"] & oracle.PF_RECT_EDGE) != 0
+    keep, ref_keep = ~flagged[ids], ~flagged[olst]
+    assert flagged.sum() < 0.001 * n
+    np.testing.assert_array_equal(tile[keep], ref_tile[ref_keep])
+    np.testing.assert_array_equal(ids[keep], olst[ref_keep].astype(np.int64))
