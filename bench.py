@@ -208,6 +208,9 @@ def roofline(achieved, bwd_ms, evals, step_bytes, ms_step, ctr):
            "peak": round(PEAK_VALU / 1e12, 3), "unit": "Tops/s", "frac": round(achieved / PEAK_VALU, 4),
            "traffic": ctr.get("hbm_bytes_per_launch"), "avg_ms": round(bwd_ms, 4), "units": evals,
            "ops_per_unit": SLOTS_BWD,
+           "basis": "frac: model estimate of 70 lane-ops per evaluation; valu_issue_frac: measured SQ_INSTS_VALU x 64 "
+                    "per launch (committed counters) over the live launch time; step_hbm_frac: the whole step's "
+                    "algorithmic bytes over its time",
            "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / PEAK_HBM, 4)}
     vi = ctr.get("valu_insts_per_launch")
     out["valu_issue_frac"] = round(vi * 64 / (bwd_ms * 1e-3) / PEAK_VALU, 4) if vi else None
