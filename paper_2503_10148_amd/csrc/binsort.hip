@@ -464,21 +464,26 @@ struct EmitMeta {
 };
 
 // One lane per rank reads that rank's entry line (record, ellipse,
-// rectangle: one 128-byte read) and evaluates the rows of its rectangle into
-// the wave's row table (wave_row_table).  The 64 ranks' pairs
-// are one contiguous slot range, which the wave then writes 64 slots at a
-// time: a rank that starts inside the window marks its start, an inclusive
-// max-scan of the marks gives every slot its rank, and the slot's tile comes
-// from that rank's rows (find_row).  Stores are coalesced and each step does
-// the same work whatever the ranks' sizes.  Exactly tiles_touched pairs are
-// written per rank (the scan reserved that many, and the projection counted
-// them with the same row_run on the same values); slots left over if the two
-// ever disagreed get the sentinel key n_tiles, which sorts after every real
-// tile, and no store leaves the rank's range.  Ranks whose rows do not fit
-// the table are written afterwards with for_each_listed_tile.  No slot at or
-// beyond the pair capacity is written (the caller learns from the required
-// count that the lists are incomplete).  The grid covers every entry; the
-// number of visible ranks comes from the device record.
+// rectangle: one 128-byte read) and copies the record to rank order.  The
+// rows of the wave's 64 rectangles are evaluated spread over the lanes into
+// the wave's row table (start slot, first tile key, rank lane).  The 64
+// ranks' pairs are one contiguous slot range, which the wave then writes 64
+// slots at a time: the non-empty rows that start inside the window mark
+// their start, an inclusive max-scan of the marks gives every slot its row,
+// and the slot's key is the row's first key plus the slot's distance from
+// the row start.  Stores are coalesced and each step does the same work
+// whatever the ranks' sizes.  Exactly tiles_touched pairs are written per
+// rank (the scan reserved that many, and the projection counted them with
+// the same row_run on the same values).  If the two ever disagreed, the wave
+// instead rebuilds the table per rank (wave_row_table) and writes by rank:
+// each slot's rank from marks at the ranks' first slots, its row by binary
+// search (find_row); slots a rank reserved beyond its rows get the sentinel
+// key n_tiles, which sorts after every real tile, and no store leaves the
+// rank's range.  Ranks whose rows do not fit the table are written
+// afterwards with for_each_listed_tile.  No slot at or beyond the pair
+// capacity is written (the caller learns from the required count that the
+// lists are incomplete).  The grid covers every entry; the number of
+// visible ranks comes from the device record.
 __global__ __launch_bounds__(kBlock) void emit_kernel(CamBatch cb, int64_t n, const uint32_t* __restrict__ order,
                                                       const Entry* __restrict__ ent,
                                                       const uint32_t* __restrict__ off,
