@@ -13,11 +13,15 @@ the scheduler admit more.  A request that arrives while nothing is queued or
 in flight is launched at once by the submitting thread (a batch of one),
 without a hand-over to the scheduler.
 
-Nothing on the launch path waits for the device: the bin sort reads its
-counts on the device and copies them, with the batch, to pinned host memory.
-The completion thread checks them; a batch whose pair lists outgrew its
-stream's capacity is rendered again with a larger one before its results are
-handed out (the capacity only grows, and `warmup` sizes it up front).
+Nothing on the launch path waits for the device: the bin sort's kernels
+read its counts on the device and write them straight into the stream's
+pinned host buffer.  The completion thread checks them after the batch's
+event; a batch whose pair lists outgrew its stream's capacity is rendered
+again with a larger one before its results are handed out (the capacity
+only grows, and `warmup` sizes it up front).  A resolved future keeps its
+request (`future.request`: submit and completion times, pixels), but the
+request no longer refers to the future, so an image is freed as soon as the
+caller drops the future.
 
 Each view is rendered independently inside a batch (its own tiles, ranks
 ordered by depth within the view), so a request's image is bit-identical
