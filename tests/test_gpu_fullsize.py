@@ -46,9 +46,12 @@ def _windows(cams, count, rng):
 
 
 @pytest.mark.parametrize("name,mode,count", [("m1", "stored", 6), ("large", "recompute", 4),
-                                             ("multiview", "stored", 4), ("multiview", "recompute_l1", 4)])
+                                             ("multiview", "stored", 4), ("multiview", "recompute_l1", 4),
+                                             ("m1", "stored_det", 4)])
 def test_full_size_windows_match_oracle(sss, name, mode, count):
-    """recompute_l1: the configuration the multi-view workload is timed in,
+    """stored_det: the deterministic backward (no float atomics), which must
+    also repeat bit for bit.
+    recompute_l1: the configuration the multi-view workload is timed in,
     the forward pass recomputed per tile inside the backward launch with the
     L1 loss fused.  The target equals the image outside the windows (the L1
     gradient there is sign(0) = 0) and the image minus 0.5 sign(w) inside
@@ -62,7 +65,8 @@ def test_full_size_windows_match_oracle(sss, name, mode, count):
     dev = to_device(scene)
     del scene
     proj = sss.project(dev, cams)
-    bins = sss.BinSorter(0)(proj, cams, n)
+    det = mode == "stored_det"
+    bins = sss.BinSorter(0, keep_offsets=det)(proj, cams, n)
     img, _, ncon = sss.render_fwd(bins, cams)
     torch.cuda.synchronize()
     offs = np.cumsum([0] + [c["width"] * c["height"] for c in cams])
@@ -94,7 +98,7 @@ def test_full_size_windows_match_oracle(sss, name, mode, count):
         flagged |= ref["proj"]["pflags"] != 0
     assert bad_total == 0, bad_total
     assert explained_total < 0.02 * count * WIN * WIN
-    m = sss.BWD_STORED if mode == "stored" else sss.BWD_RECOMPUTE
+    m = sss.BWD_RECOMPUTE if mode.startswith("recompute") else sss.BWD_STORED
     if mode == "recompute_l1":
         P = img_np.shape[0]
         sgn = np.sign(dl)
@@ -107,9 +111,16 @@ def test_full_size_windows_match_oracle(sss, name, mode, count):
         assert torch.equal(image_out, img)
         assert abs(float(loss.item()) - 0.5 * float(np.abs(sgn).sum()) / (3.0 * P)) <= 1e-6 * float(loss.item())
     else:
-        g = sss.render_bwd(dev, proj, bins, cams, torch.as_tensor(dl, device="cuda"), mode=m,
-                           image=img if mode == "stored" else None, n_contrib=ncon if mode == "stored" else None)
+        stored = m == sss.BWD_STORED
+        dl_dev = torch.as_tensor(dl, device="cuda")
+        g = sss.render_bwd(dev, proj, bins, cams, dl_dev, mode=m, image=img if stored else None,
+                           n_contrib=ncon if stored else None, deterministic=det)
         torch.cuda.synchronize()
+        if det:
+            again = sss.render_bwd(dev, proj, bins, cams, dl_dev, mode=m, image=img, n_contrib=ncon, deterministic=True)
+            torch.cuda.synchronize()
+            for k in PARAMS:
+                assert torch.equal(again[k], g[k]), k
     touched = np.abs(gref["opacity"]) > 0
     assert touched.sum() > 100
     fails = []
@@ -185,3 +196,44 @@ def test_full_size_tile_lists_match_oracle(sss, name):
     assert flagged.sum() < 0.001 * n
     np.testing.assert_array_equal(tile[keep], ref_tile[ref_keep])
     np.testing.assert_array_equal(ids[keep], olst[ref_keep].astype(np.int64))
+
+
+def test_multiview_tile_lists_in_windows_match_oracle(sss):
+    """The 8-view workload's tile lists (6e8 pairs, one binning over all
+    views), compared with the oracle on two tile-aligned windows of 4 x 4
+    tiles per view.  A window camera differs from its view only by a
+    principal point moved by whole pixels and keeps the view's frustum
+    clamp, so its tiles are the view's tiles and their lists the view's
+    lists; components the oracle flags near a rectangle decision are
+    dropped from both sides."""
+    scene, cams = scenes.workload("multiview")
+    n = scene["means"].shape[0]
+    dev = to_device(scene)
+    proj = sss.project(dev, cams)
+    bins = sss.BinSorter(0)(proj, cams, n)
+    torch.cuda.synchronize()
+    offs = np.cumsum([0] + [oracle.tiles(c)[0] * oracle.tiles(c)[1] for c in cams])
+    rng = np.random.default_rng(scenes.SEED_FD + 11)
+    compared = 0
+    for v, cam in enumerate(cams):
+        txs, tys = oracle.tiles(cam)
+        for _ in range(2):
+            tx0 = int(rng.integers(0, txs - 4)) if txs > 4 else 0
+            ty0 = int(rng.integers(0, tys - 4)) if tys > 4 else 0
+            wc = oracle.window_camera(cam, 16 * tx0, 16 * ty0, 64, 64)
+            o = oracle.project(scene, wc)
+            ost, olst = oracle.bin_tiles(o["touched"], o["rect"], o["key"], 4, 4, proj=o)
+            flagged = (o["pflags"] & oracle.PF_RECT_EDGE) != 0
+            for j in range(4):
+                for i in range(4):
+                    t = int(offs[v] + (ty0 + j) * txs + tx0 + i)
+                    s0, s1 = int(bins.tile_start[t].item()), int(bins.tile_start[t + 1].item())
+                    ranks = bins.pair_rank[s0:s1].long()
+                    ids = (bins.order[ranks].long() - v * n).cpu().numpy()
+                    ref = olst[ost[4 * j + i]:ost[4 * j + i + 1]].astype(np.int64)
+                    assert ((ids >= 0) & (ids < n)).all()
+                    got = ids[~flagged[ids]]
+                    want = ref[~flagged[ref]]
+                    np.testing.assert_array_equal(got, want, err_msg=f"view {v} tile ({tx0 + i}, {ty0 + j})")
+                    compared += len(want)
+    assert compared > 10000
