@@ -1148,11 +1148,18 @@ void launch_render_bwd(const CamBatch& cb, const OptsDev& op, const sss_bins_t& 
                        int64_t n, hipStream_t st) {
   // Pixels per lane: the deterministic variant runs one unit (one wave of 4
   // pixels per thread) per tile, so each pair's sums come from one wave;
-  // otherwise 2 when the walk bounds are stored, 1 when the unit first
-  // recomputes the forward walk (which is fastest at 1: measured 15% on
-  // the 3M-component workload), unless SSS_PIX_BWD says otherwise.
+  // otherwise 2 when the walk bounds are stored; when the unit first
+  // recomputes the forward walk, 1 for calls of up to kRecomputePix2Tiles
+  // tiles and 2 beyond (measured: one 1920x1080 view of 3M components,
+  // 8160 tiles, 2.00 ms at 1 against 2.43 at 2; eight 1600x1064 views of
+  // 5M, 53600 tiles, 11.7 ms at 1 against 10.1 at 2), unless SSS_PIX_BWD
+  // says otherwise.
+  constexpr int64_t kRecomputePix2Tiles = 16384;
   static const int env_bwd = env_pix("SSS_PIX_BWD", 0);
-  const int pix = det_mode ? 4 : env_bwd ? env_bwd : (mode == SSS_BWD_RECOMPUTE ? 1 : 2);
+  const int pix = det_mode ? 4
+                  : env_bwd ? env_bwd
+                  : mode == SSS_BWD_RECOMPUTE ? (cb.total_tiles > kRecomputePix2Tiles ? 2 : 1)
+                                               : 2;
   const int64_t units = cb.total_tiles * (4 / pix);
   // schedule: units ordered by the forward's per-strip walk lengths when
   // the backward walks the stored prefixes, else the binning's tile order
