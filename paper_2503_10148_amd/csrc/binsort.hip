@@ -411,41 +411,17 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
     }
     __syncthreads();
     const int in_block = (int)min((int64_t)kRPerBlock, n - block0);
-    if (gsrc) {
-      // the depth sort's last pass also gathers, for the first gn output
-      // positions, gsrc by the value (the visible entries' tile counts in
-      // rank order): all of a thread's gather loads are issued before its
-      // stores, so their latencies overlap
-      uint32_t gk[kRItems], gp[kRItems], gv[kRItems], gt[kRItems];
-#pragma unroll
-      for (int r = 0; r < kRItems; ++r) {
-        const int i = tid + r * kBlock;
-        gk[r] = gv[r] = gp[r] = 0u;
-        if (i < in_block) {
-          gk[r] = sk[i];
-          gv[r] = sv[i];
-          const uint32_t d = radix_digit(gk[r], base_key, cap, shift, mask);
-          gp[r] = gbase[d] + ((uint32_t)i - dofs[d]);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < kRItems; ++r)
-        gt[r] = (tid + r * kBlock < in_block && (int64_t)gp[r] < gn) ? gsrc[gv[r]] : 0u;
-#pragma unroll
-      for (int r = 0; r < kRItems; ++r) {
-        if (tid + r * kBlock >= in_block) continue;
-        okeys[gp[r]] = gk[r];
-        ovals[gp[r]] = gv[r];
-        if ((int64_t)gp[r] < gn) gout[gp[r]] = gt[r];
-      }
-    } else {
-      for (int i = tid; i < in_block; i += kBlock) {
-        const uint32_t k = sk[i];
-        const uint32_t d = radix_digit(k, base_key, cap, shift, mask);
-        const uint32_t p = gbase[d] + ((uint32_t)i - dofs[d]);
-        okeys[p] = k;
-        ovals[p] = sv[i];
-      }
+    for (int i = tid; i < in_block; i += kBlock) {
+      const uint32_t k = sk[i];
+      const uint32_t d = radix_digit(k, base_key, cap, shift, mask);
+      const uint32_t p = gbase[d] + ((uint32_t)i - dofs[d]);
+      okeys[p] = k;
+      ovals[p] = sv[i];
+      // optional gather by the output value for the first gn positions (the
+      // depth sort's last pass: the visible entries' tile counts in rank
+      // order; issuing these loads in batches measured no faster and, by the
+      // registers it took, slowed every other pass of this kernel)
+      if (gsrc && (int64_t)p < gn) gout[p] = gsrc[sv[i]];
     }
   }  // radix blocks
 }
