@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
 // sh_bwd_kernel runs first and initialises it when overwriting.
 __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     CamBatch cb, OptsDev op, int64_t n, const float* means, const float* scales, const float* quats, const float* nu,
-    const uint32_t* __restrict__ touched, const double* __restrict__ g2, float* __restrict__ d_means,
+    const float* opac, const uint32_t* __restrict__ touched, const double* __restrict__ g2, float* __restrict__ d_means,
     float* __restrict__ d_scales, float* __restrict__ d_quats, float* __restrict__ d_nu, float* __restrict__ d_opac,
     int overwrite, StepArgs sa) {
   // means, scales, quats and nu are not __restrict__: with sa.on the same
@@ -423,6 +423,19 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
   F gmu[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0};
   F gnu = 0, gop = 0;
   bool any = false;
+  // The raster's sums leave out the entry's own factors (the same float
+  // values its record holds): d mean2d and d conic carry o nb (1/nu, or
+  // ln 2 for the Gaussian family), d nu carries o / 2.
+  float cgeo, cnu;
+  {
+    const float o = opac[i];
+    const bool gauss = op.family == SSS_FAMILY_GAUSSIAN;
+    const double nuc = fmin(fmax((double)nu[i], (double)op.nu_min), (double)op.nu_max);
+    const float nb = gauss ? (float)(-0.5 * 1.4426950408889634) : (float)(-0.5 * (nuc + 2.0));
+    const float kh = gauss ? 0.6931471805599453f : (float)(1.0 / nuc);
+    cgeo = o * nb * kh;
+    cnu = 0.5f * o;
+  }
   for (int v = 0; v < cb.n_views; ++v) {
     const int64_t e = (int64_t)v * n + i;
     if (touched[e] == 0) continue;
@@ -430,9 +443,10 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     const CamDev& c = cb.v[v];
     const double2* gp = reinterpret_cast<const double2*>(g2 + e * kG2);
     const double2 g01 = gp[0], g23 = gp[1], g45 = gp[2], g89 = gp[4];
-    const F gmx = (F)g01.x, gmy = (F)g01.y, gqa = (F)g23.x, gqb = (F)g23.y, gqc = (F)g45.x;
+    const F gmx = (F)g01.x * cgeo, gmy = (F)g01.y * cgeo, gqa = (F)g23.x * cgeo, gqb = (F)g23.y * cgeo,
+            gqc = (F)g45.x * cgeo;
     gop += (F)g89.x;
-    gnu += (F)g89.y;
+    gnu += (F)g89.y * cnu;
 
     Geo<F> g;
     geometry<F>(c, op, mu, s, quats + 4 * i, g);
@@ -769,7 +783,7 @@ void launch_project_bwd(const CamBatch& cb, const OptsDev& op, const sss_scene_t
   }
 #undef SSS_SHB
   SSS_LAUNCH("project_bwd", project_bwd_kernel, grid, dim3(kBlock), 0, st, cb, op, (int64_t)s.n, s.means, s.scales,
-             s.quats, s.nu, touched, (const double*)g2, gr.means, gr.scales, gr.quats, gr.nu, gr.opacity,
+             s.quats, s.nu, s.opacity, touched, (const double*)g2, gr.means, gr.scales, gr.quats, gr.nu, gr.opacity,
              (int)gr.overwrite, sa);
 }
 

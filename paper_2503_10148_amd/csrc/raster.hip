@@ -659,15 +659,18 @@ __device__ __forceinline__ void render_bwd_unit(
         const float da0 = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), Tk * gc);
         const float da = hk && !E.clamped ? da0 : 0.0f;
         T[k] = hk ? __fmaf_rn(-Tk, a, Tk) : Tk;   // as the forward walk
-        const float dt2 = da * L.o;
         const float ru = kGauss ? 1.0f : __builtin_amdgcn_rcpf(E.u);
-        // d log2 T / dh = nb / (nu (1 + y)); nb ln 2 for the Gaussian family
-        const float kh = kGauss ? kLn2 : L.inv_nu * ru;
-        const float dh = dt2 * E.t2 * L.nb * kh;
+        // d T2D / dh = T2D nb kh with d log2 T / dh = nb / (nu (1 + y)), or nb
+        // ln 2 for the Gaussian family: kh = (1/nu or ln 2) ru.  The factors
+        // that are the entry's own (o from dt2 = da o, nb, 1/nu or ln 2, and
+        // the 1/2 of the nu term) are left out of the per-pixel terms and
+        // applied once per entry where the sums are read (entry_factors in
+        // the projection backward): dh here is dh / (o nb (1/nu or ln 2)).
+        const float dh = kGauss ? da * E.t2 : da * E.t2 * ru;
         const float tq = dh * E.dx;
         // the ten terms as products A[f] * B[f]: d mean (2), d conic (3),
-        // d colour (3), d opacity, d nu
-        float A[10] = {dh, dh, tq, tq, dh * E.dy, g[k][0], g[k][1], g[k][2], da, dt2};
+        // d colour (3), d opacity, d nu / (o/2)
+        float A[10] = {dh, dh, tq, tq, dh * E.dy, g[k][0], g[k][1], g[k][2], da, da};
         float B[10] = {E.ax, E.ay, E.dx, E.dy, E.dy, w, w, w, E.t2, 0.0f};
         if constexpr (!kGauss) {
           // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]; the first
@@ -680,7 +683,7 @@ __device__ __forceinline__ void render_bwd_unit(
           s = __fmaf_rn(y, s, 2.0f / 3.0f);
           s = __fmaf_rn(y, s, -0.5f);
           const float q = y < 0.1f ? y * y * s : __fmaf_rn(y, ru, -E.l2 * kLn2);
-          B[9] = 0.5f * E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
+          B[9] = E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
         }
         if (k == 0) {
 #pragma unroll
