@@ -425,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
   bool any = false;
   // The raster's sums leave out the entry's own factors (the same float
   // values its record holds): d mean2d and d conic carry o nb (1/nu, or
-  // ln 2 for the Gaussian family), d nu carries o / 2.
+  // ln 2 for the Gaussian family), d nu carries o ln(2) / 2.
   float cgeo, cnu;
   {
     const float o = opac[i];
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     const float nb = gauss ? (float)(-0.5 * 1.4426950408889634) : (float)(-0.5 * (nuc + 2.0));
     const float kh = gauss ? 0.6931471805599453f : (float)(1.0 / nuc);
     cgeo = o * nb * kh;
-    cnu = 0.5f * o;
+    cnu = 0.5f * o * 0.6931471805599453f;
   }
   for (int v = 0; v < cb.n_views; ++v) {
     const int64_t e = (int64_t)v * n + i;

@@ -35,7 +35,6 @@ namespace sss {
 namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.6931471805599453f;
 
 // LDS record (16 floats).
 struct __align__(16) LRec {
@@ -43,7 +42,7 @@ struct __align__(16) LRec {
   float qc, hs, o, inv_nu;   // conic c; truncation test level; opacity; 1/nu
   float nb, cr, cg, cb;      // -(nu+2)/2; colour
   uint32_t smask;            // bit s: the pre-test ellipse reaches tile rows 4s..4s+3
-  float ey;                  // half extent in y of the pre-test ellipse
+  float c2;                  // 2 log2(e) / nu (the backward's nu term; 0 for the Gaussian family)
   uint32_t entry;
   uint32_t slot;             // deterministic backward: the pair's emission position
 };
@@ -99,14 +98,15 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   l.inv_nu = r.inv_nu;
   l.nb = r.nb;
   l.cr = r.cr; l.cg = r.cg; l.cb = r.cb;
+  l.c2 = 2.0f * r.inv_nu * kLog2e;
   // sqrt(1.0001) covers the widened pre-test level, the rest FP32 rounding
-  l.ey = r.ey * 1.0001f + 1e-3f;
+  const float ey = r.ey * 1.0001f + 1e-3f;
   // strips of 4 pixel rows (centres 4s + 1/2 .. 4s + 7/2) the ellipse can reach
   uint32_t m = 0;
 #pragma unroll
   for (int st = 0; st < kTile / 4; ++st) {
     const float y0 = (float)(4 * st) + 0.5f;
-    if (l.my + l.ey >= y0 && l.my - l.ey <= y0 + 3.0f) m |= 1u << st;
+    if (l.my + ey >= y0 && l.my - ey <= y0 + 3.0f) m |= 1u << st;
   }
   l.smask = m;
   l.entry = r.entry;
@@ -120,7 +120,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
 // and backward kernels (explicit fma, compiled without contraction).
 struct Eval {
   float dx, dy, ax, ay, h, y, u, l2, t2, alpha;
-  bool hit, clamped;
+  bool aok, hit, clamped;   // aok: |o T2D| is not below alpha_min
 };
 
 // kGauss: the Gaussian family (every record has inv_nu = 0 and
@@ -154,7 +154,8 @@ __device__ __forceinline__ void evaluate(float px, float py, const R& L, float a
   }
   E.t2 = __builtin_amdgcn_exp2f(L.nb * E.l2);
   const float a = L.o * E.t2;
-  E.hit = E.h <= L.hs && !(fabsf(a) < amin);
+  E.aok = !(fabsf(a) < amin);
+  E.hit = E.h <= L.hs && E.aok;
   E.clamped = fabsf(a) > amax;
   E.alpha = __builtin_amdgcn_fmed3f(a, -amax, amax);
 }
@@ -640,7 +641,7 @@ __device__ __forceinline__ void render_bwd_unit(
           // lane masks combine on the scalar unit (one ballot of the
           // combined bool went through two vector instructions)
           run = (__builtin_amdgcn_ballot_w64(pos < bound[k]) & __builtin_amdgcn_ballot_w64(E.h <= L.hs) &
-                 __builtin_amdgcn_ballot_w64(!(fabsf(E.alpha) < op.alpha_min))) != 0;
+                 __builtin_amdgcn_ballot_w64(E.aok)) != 0;
         }
         if (!run) {
           if (k == 0) {
@@ -663,27 +664,33 @@ __device__ __forceinline__ void render_bwd_unit(
         // d T2D / dh = T2D nb kh with d log2 T / dh = nb / (nu (1 + y)), or nb
         // ln 2 for the Gaussian family: kh = (1/nu or ln 2) ru.  The factors
         // that are the entry's own (o from dt2 = da o, nb, 1/nu or ln 2, and
-        // the 1/2 of the nu term) are left out of the per-pixel terms and
-        // applied once per entry where the sums are read (entry_factors in
-        // the projection backward): dh here is dh / (o nb (1/nu or ln 2)).
-        const float dh = kGauss ? da * E.t2 : da * E.t2 * ru;
+        // ln(2)/2 of the nu term) are left out of the per-pixel terms and
+        // applied once per entry where the sums are read (the projection
+        // backward): dh here is dh / (o nb (1/nu or ln 2)).
+        const float dt = da * E.t2;
+        const float dh = kGauss ? dt : dt * ru;
         const float tq = dh * E.dx;
         // the ten terms as products A[f] * B[f]: d mean (2), d conic (3),
-        // d colour (3), d opacity, d nu / (o/2)
-        float A[10] = {dh, dh, tq, tq, dh * E.dy, g[k][0], g[k][1], g[k][2], da, da};
-        float B[10] = {E.ax, E.ay, E.dx, E.dy, E.dy, w, w, w, E.t2, 0.0f};
+        // d colour (3), d opacity, d nu / (o ln(2) / 2)
+        float A[10] = {dh, dh, tq, tq, dh * E.dy, g[k][0], g[k][1], g[k][2], dt, dt};
+        float B[10] = {E.ax, E.ay, E.dx, E.dy, E.dy, w, w, w, 1.0f, 0.0f};
         if constexpr (!kGauss) {
-          // dT2D/dnu = T2D/2 [y/(1+y) - log(1+y) + 2y/(nu (1+y))]; the first
-          // two terms by their series below y = 0.1 (they cancel).  The
-          // Gaussian family has no nu.
-          const float y = E.y;
-          float s = __fmaf_rn(y, 6.0f / 7.0f, -5.0f / 6.0f);
-          s = __fmaf_rn(y, s, 4.0f / 5.0f);
-          s = __fmaf_rn(y, s, -3.0f / 4.0f);
-          s = __fmaf_rn(y, s, 2.0f / 3.0f);
-          s = __fmaf_rn(y, s, -0.5f);
-          const float q = y < 0.1f ? y * y * s : __fmaf_rn(y, ru, -E.l2 * kLn2);
-          B[9] = E.t2 * __fmaf_rn(2.0f * y * L.inv_nu, ru, q);
+          // dT2D/dnu = T2D/2 [y/(1+y) - ln(1+y) + 2y/(nu (1+y))], here the
+          // bracket / ln 2.  The first two terms cancel for small y: below
+          // y = 0.1 they come from their series (coefficients times log2 e),
+          // evaluated only when a lane of the wave needs it.  The Gaussian
+          // family has no nu.
+          const float y = E.y, yr = y * ru;
+          float q = __fmaf_rn(yr, kLog2e, -E.l2);
+          if (__builtin_amdgcn_ballot_w64(y < 0.1f)) {   // wave-uniform
+            float s = __fmaf_rn(y, (float)(6.0 / 7.0 * 1.4426950408889634), (float)(-5.0 / 6.0 * 1.4426950408889634));
+            s = __fmaf_rn(y, s, (float)(4.0 / 5.0 * 1.4426950408889634));
+            s = __fmaf_rn(y, s, (float)(-3.0 / 4.0 * 1.4426950408889634));
+            s = __fmaf_rn(y, s, (float)(2.0 / 3.0 * 1.4426950408889634));
+            s = __fmaf_rn(y, s, (float)(-0.5 * 1.4426950408889634));
+            q = y < 0.1f ? y * y * s : q;
+          }
+          B[9] = __fmaf_rn(yr, L.c2, q);
         }
         if (k == 0) {
 #pragma unroll
