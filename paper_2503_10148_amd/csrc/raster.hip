@@ -204,11 +204,45 @@ __device__ __forceinline__ void halve(const float (&a)[N], float (&out)[(N + 1) 
 // span all 16 lanes, then two exchanges across rows.  About 40 instructions
 // instead of ten 6-step reductions, and the ten sums end in ten lanes of one
 // row, so one memory instruction can store or add them all.
+//
+// The first two steps pair lanes in different 4-lane banks (l^8: banks 0,1
+// with 2,3; l^7: banks 0,2 with 1,3), so the DPP bank mask can pick which
+// lanes an add writes: each pair costs two adds, one per half of the lanes,
+// instead of two selects and an add.  The compiler's DPP builtins cannot
+// express an add that leaves the other lanes' destination untouched, hence
+// the asm.  Its wait states: 5 before the first DPP read (a VALU or EXEC
+// write just before it), 2 between the steps and after the last write (a
+// DPP read of a VGPR written by the VALU), since the compiler's hazard
+// checks do not look inside it.  Same sums, same order as the halving
+// steps (keep + received, a commutative add).
 __device__ __forceinline__ float wave_sum10_transposed(const float (&v)[10]) {
   const int lane = threadIdx.x & 63;
-  float a[5], b[3], c[2], d[1];
-  halve<0x128, 10>(v, a, lane & 8);   // row_ror:8
-  halve<0x141, 5>(a, b, lane & 4);    // row_half_mirror
+  float a0, a1, a2, a3, a4, b[3], c[2], d[1];
+  asm("s_nop 4\n\t"
+      // l^8 (row_ror:8): lanes 0-7 of a row keep values 0-4, lanes 8-15 values 5-9
+      "v_add_f32_dpp %0, %13, %13 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+      "v_add_f32_dpp %1, %14, %14 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+      "v_add_f32_dpp %2, %15, %15 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+      "v_add_f32_dpp %3, %16, %16 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+      "v_add_f32_dpp %4, %17, %17 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+      "v_add_f32_dpp %0, %8, %8 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %1, %9, %9 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %2, %10, %10 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %3, %11, %11 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+      "v_add_f32_dpp %4, %12, %12 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+      "s_nop 1\n\t"
+      // l^7 (row_half_mirror): banks 0,2 keep (a0, a1, a2), banks 1,3 (a3, a4);
+      // b[2] of banks 1,3 (the zero padding) is left unwritten: the later
+      // steps carry it only into lanes tr_index marks empty
+      "v_add_f32_dpp %5, %3, %3 row_half_mirror row_mask:0xf bank_mask:0xa\n\t"
+      "v_add_f32_dpp %6, %4, %4 row_half_mirror row_mask:0xf bank_mask:0xa\n\t"
+      "v_add_f32_dpp %5, %0, %0 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+      "v_add_f32_dpp %6, %1, %1 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+      "v_add_f32_dpp %7, %2, %2 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+      "s_nop 1"
+      : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(a4), "=&v"(b[0]), "=&v"(b[1]), "=&v"(b[2])
+      : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]), "v"(v[8]),
+        "v"(v[9]));
   halve<0x1B, 3>(b, c, lane & 2);     // quad_perm [3,2,1,0]
   halve<0xB1, 2>(c, d, lane & 1);     // quad_perm [1,0,3,2]
   float x = d[0];
@@ -600,15 +634,15 @@ __device__ __forceinline__ void render_bwd_unit(
 
   // ---- front-to-back gradient walk ----
   const WaveStrips<PIX> ws = wave_strips<PIX>(t.sub);
-  // gA: g . (colour accumulated so far), in FP64 like the forward's sums, so
-  // that gout - gA (the part of the output behind a component) keeps its
-  // precision deep in a list
+  // gB: g . (the part of the output behind the current component), the
+  // output minus the colour accumulated so far, kept in FP64 like the
+  // forward's sums so that it keeps its precision deep in a list
   float T[PIX];
-  double gA[PIX];
+  double gB[PIX];
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     T[k] = 1.0f;
-    gA[k] = 0.0;
+    gB[k] = gout[k];
   }
   for (uint32_t base = t.start; base < stop; base += kBatch) {
     __syncthreads();
@@ -654,8 +688,8 @@ __device__ __forceinline__ void render_bwd_unit(
         const float Tk = T[k];
         const float w = hk ? a * Tk : 0.0f;
         const float gc = __fmaf_rn(g[k][2], L.cb, __fmaf_rn(g[k][1], L.cg, g[k][0] * L.cr));
-        gA[k] = __fma_rn((double)w, (double)gc, gA[k]);
-        const float gR = (float)(gout[k] - gA[k]);
+        gB[k] = __fma_rn(-(double)w, (double)gc, gB[k]);
+        const float gR = (float)gB[k];
         // a clamped alpha passes no gradient to T2D
         const float da0 = __fmaf_rn(-gR, __builtin_amdgcn_rcpf(1.0f - a), Tk * gc);
         const float da = hk && !E.clamped ? da0 : 0.0f;
