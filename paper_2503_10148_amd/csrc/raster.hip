@@ -41,7 +41,7 @@ struct __align__(16) LRec {
   float mx, my, qa, qb;      // mean relative to the tile origin; conic a, b
   float qc, hs, o, inv_nu;   // conic c; truncation test level; opacity; 1/nu
   float nb, cr, cg, cb;      // -(nu+2)/2; colour
-  uint32_t smask;            // bit s: the pre-test ellipse reaches tile rows 4s..4s+3
+  uint32_t smask;            // bit s: the ellipse reaches strip s (rows 4s..4s+3), of the unit's strips
   float c2;                  // 2 log2(e) / nu (the backward's nu term; 0 for the Gaussian family)
   uint32_t entry;
   uint32_t slot;             // deterministic backward: the pair's emission position
@@ -57,10 +57,71 @@ struct __align__(16) FRec {
   double cr, cg, cb;
 };
 
-// Stages one forward-only record in LDS; returns its strip mask (the same
-// fields and strip test as the general record below).
+// Strips of 4 pixel rows (bit st: pixel centres x in [1/2, 31/2], y in
+// [4 st + 1/2, 4 st + 7/2], tile coordinates) that the ellipse h <= h* of a
+// record reaches, for the strips in `want` (wave-uniform: the strips of the
+// caller's unit).  Exact rather than by the ellipse's row extent, which
+// visits 9% more strips on the 1M-component workload (tilted ellipses that
+// cross a tile's corner).
+//
+// The minimum of h over a box is 0 with the mean inside it, else it lies on
+// an edge.  On a row y = Y it is qa (x - x*)^2 + (Y - my)^2 / Sigma_yy, with
+// x* = mx - (qb/qa)(Y - my) the row's minimiser clamped to the box
+// (completing the square: two non-negative terms, so FP32 loses nothing to
+// cancellation, however elongated the ellipse); on a column x = X likewise
+// qc (y - y*)^2 + (X - mx)^2 / Sigma_xx.  The record gives 1/Sigma_yy =
+// h*/ey^2 and Sigma_xx / Sigma_yy = qc / qa.  A strip is kept when the
+// minimum is within 1% above the hit level h* x 1.0001 (rounding of these
+// few operations, and of h as the evaluation computes it, is far below
+// that).  Without a finite positive h* (alpha_min = 0) the row extent
+// decides, as it does for a zero-size ellipse.
+__device__ __forceinline__ uint32_t strip_mask(const Rec& r, float mx, float my, uint32_t want) {
+  uint32_t m = 0;
+  const float ey = r.ey;
+  if (!(r.hs > 0.0f && r.hs < __builtin_inff() && ey > 0.0f)) {
+    const float e = ey * 1.0001f + 1e-3f;
+#pragma unroll
+    for (int st = 0; st < kTile / 4; ++st) {
+      const float y0 = (float)(4 * st) + 0.5f;
+      if ((want >> st & 1u) && my + e >= y0 && my - e <= y0 + 3.0f) m |= 1u << st;
+    }
+    return m;
+  }
+  const float iyy = r.hs * __builtin_amdgcn_rcpf(ey * ey);
+  const float ixx = iyy * r.qa * __builtin_amdgcn_rcpf(r.qc);
+  const float kx = r.qb * __builtin_amdgcn_rcpf(r.qa), ky = r.qb * __builtin_amdgcn_rcpf(r.qc);
+  const float lvl = (r.hs * 1.0001f) * 1.01f;
+  constexpr float x0 = 0.5f, x1 = (float)kTile - 0.5f;
+#pragma unroll
+  for (int st = 0; st < kTile / 4; ++st) {
+    if (!(want >> st & 1u)) continue;   // wave-uniform
+    const float y0 = (float)(4 * st) + 0.5f, y1 = y0 + 3.0f;
+    bool keep = mx >= x0 && mx <= x1 && my >= y0 && my <= y1;
+    // rows y0, y1, then columns x0, x1 (each term computed where it is used,
+    // which keeps the staging's registers few)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const float dy = (e ? y1 : y0) - my;
+      const float xs = __fmaf_rn(-kx, dy, mx);
+      const float d = __builtin_amdgcn_fmed3f(xs, x0, x1) - xs;
+      keep |= __fmaf_rn(r.qa * d, d, dy * dy * iyy) <= lvl;
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const float dx = (e ? x1 : x0) - mx;
+      const float ys = __fmaf_rn(-ky, dx, my);
+      const float d = __builtin_amdgcn_fmed3f(ys, y0, y1) - ys;
+      keep |= __fmaf_rn(r.qc * d, d, dx * dx * ixx) <= lvl;
+    }
+    if (keep) m |= 1u << st;
+  }
+  return m;
+}
+
+// Stages one forward-only record in LDS; returns its strip mask over `want`
+// (the same fields and strip test as the general record below).
 __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, double ox, double oy,
-                                          FRec* dst, uint32_t* entry) {
+                                          uint32_t want, FRec* dst, uint32_t* entry) {
   const Rec r = srec[rank];
   FRec l;
   l.mx = (float)(r.mx - ox);
@@ -71,22 +132,16 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   l.inv_nu = r.inv_nu;
   l.nb = r.nb;
   l.cr = (double)r.cr; l.cg = (double)r.cg; l.cb = (double)r.cb;
-  const float ey = r.ey * 1.0001f + 1e-3f;
-  uint32_t m = 0;
-#pragma unroll
-  for (int st = 0; st < kTile / 4; ++st) {
-    const float y0 = (float)(4 * st) + 0.5f;
-    if (l.my + ey >= y0 && l.my - ey <= y0 + 3.0f) m |= 1u << st;
-  }
+  const uint32_t m = strip_mask(r, l.mx, l.my, want);
   l.smask = m;
   *dst = l;
   *entry = r.entry;
   return m;
 }
 
-// Stages one record in LDS; returns its strip mask and the entry.
+// Stages one record in LDS; returns its strip mask over `want` and the entry.
 __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, double ox, double oy,
-                                          LRec* dst, uint32_t* entry) {
+                                          uint32_t want, LRec* dst, uint32_t* entry) {
   const Rec r = srec[rank];
   LRec l;
   l.mx = (float)(r.mx - ox);
@@ -99,20 +154,15 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   l.nb = r.nb;
   l.cr = r.cr; l.cg = r.cg; l.cb = r.cb;
   l.c2 = 2.0f * r.inv_nu * kLog2e;
-  // sqrt(1.0001) covers the widened pre-test level, the rest FP32 rounding
-  const float ey = r.ey * 1.0001f + 1e-3f;
-  // strips of 4 pixel rows (centres 4s + 1/2 .. 4s + 7/2) the ellipse can reach
-  uint32_t m = 0;
-#pragma unroll
-  for (int st = 0; st < kTile / 4; ++st) {
-    const float y0 = (float)(4 * st) + 0.5f;
-    if (l.my + ey >= y0 && l.my - ey <= y0 + 3.0f) m |= 1u << st;
-  }
-  l.smask = m;
+  l.smask = 0u;
   l.entry = r.entry;
   l.slot = 0u;
-  *dst = l;
   *entry = r.entry;
+  // the record goes to LDS before the mask is computed, so that its
+  // registers are free by then (the backward's accumulators are live here)
+  *dst = l;
+  const uint32_t m = strip_mask(r, l.mx, l.my, want);
+  dst->smask = m;
   return m;
 }
 
@@ -372,7 +422,7 @@ __device__ __forceinline__ uint64_t stage_batch(const TileCtx<PIX>& t, const Rec
                                                 R* lds, uint32_t strips) {
   const uint32_t k = base + threadIdx.x;
   uint32_t m = 0, e;
-  if (k < stop) m = stage(srec, pair_rank[k], t.ox, t.oy, lds + threadIdx.x, &e);
+  if (k < stop) m = stage(srec, pair_rank[k], t.ox, t.oy, strips, lds + threadIdx.x, &e);
   return __ballot((m & strips) != 0u);
 }
 
@@ -391,7 +441,7 @@ __device__ __forceinline__ uint64_t stage_batch_slot(const TileCtx<PIX>& t, cons
   if (k < stop) {
     const uint32_t rank = pair_rank[k];
     uint32_t e;
-    m = stage(srec, rank, t.ox, t.oy, lds + threadIdx.x, &e);
+    m = stage(srec, rank, t.ox, t.oy, strips, lds + threadIdx.x, &e);
     const ushort4 rc = det.ent[e].rect;
     const RowGeo g = make_row_geo(srec[rank].mx, srec[rank].my, det.ent[e].ell);
     uint32_t pos = det.rank_off[rank];
