@@ -59,10 +59,10 @@ struct __align__(16) FRec {
 
 // Strips of 4 pixel rows (bit st: pixel centres x in [1/2, 31/2], y in
 // [4 st + 1/2, 4 st + 7/2], tile coordinates) that the ellipse h <= h* of a
-// record reaches, for the strips in `want` (wave-uniform: the strips of the
-// caller's unit).  Exact rather than by the ellipse's row extent, which
-// visits 9% more strips on the 1M-component workload (tilted ellipses that
-// cross a tile's corner).
+// record reaches, for the N strips first .. first + N - 1 (the caller's
+// unit; first is wave-uniform).  Exact rather than by the ellipse's row
+// extent, which visits 9% more strips on the 1M-component workload (tilted
+// ellipses that cross a tile's corner).
 //
 // The minimum of h over a box is 0 with the mean inside it, else it lies on
 // an edge.  On a row y = Y it is qa (x - x*)^2 + (Y - my)^2 / Sigma_yy, with
@@ -75,15 +75,16 @@ struct __align__(16) FRec {
 // few operations, and of h as the evaluation computes it, is far below
 // that).  Without a finite positive h* (alpha_min = 0) the row extent
 // decides, as it does for a zero-size ellipse.
-__device__ __forceinline__ uint32_t strip_mask(const Rec& r, float mx, float my, uint32_t want) {
+template <int N>
+__device__ __forceinline__ uint32_t strip_mask(const Rec& r, float mx, float my, int first) {
   uint32_t m = 0;
   const float ey = r.ey;
   if (!(r.hs > 0.0f && r.hs < __builtin_inff() && ey > 0.0f)) {
     const float e = ey * 1.0001f + 1e-3f;
 #pragma unroll
-    for (int st = 0; st < kTile / 4; ++st) {
-      const float y0 = (float)(4 * st) + 0.5f;
-      if ((want >> st & 1u) && my + e >= y0 && my - e <= y0 + 3.0f) m |= 1u << st;
+    for (int k = 0; k < N; ++k) {
+      const float y0 = (float)(4 * (first + k)) + 0.5f;
+      if (my + e >= y0 && my - e <= y0 + 3.0f) m |= 1u << (first + k);
     }
     return m;
   }
@@ -92,13 +93,12 @@ __device__ __forceinline__ uint32_t strip_mask(const Rec& r, float mx, float my,
   const float kx = r.qb * __builtin_amdgcn_rcpf(r.qa), ky = r.qb * __builtin_amdgcn_rcpf(r.qc);
   const float lvl = (r.hs * 1.0001f) * 1.01f;
   constexpr float x0 = 0.5f, x1 = (float)kTile - 0.5f;
+  const bool in_x = mx >= x0 && mx <= x1;
 #pragma unroll
-  for (int st = 0; st < kTile / 4; ++st) {
-    if (!(want >> st & 1u)) continue;   // wave-uniform
-    const float y0 = (float)(4 * st) + 0.5f, y1 = y0 + 3.0f;
-    bool keep = mx >= x0 && mx <= x1 && my >= y0 && my <= y1;
-    // rows y0, y1, then columns x0, x1 (each term computed where it is used,
-    // which keeps the staging's registers few)
+  for (int k = 0; k < N; ++k) {
+    const float y0 = (float)(4 * (first + k)) + 0.5f, y1 = y0 + 3.0f;
+    bool keep = in_x && my >= y0 && my <= y1;
+    // rows y0, y1, then columns x0, x1
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const float dy = (e ? y1 : y0) - my;
@@ -113,39 +113,53 @@ __device__ __forceinline__ uint32_t strip_mask(const Rec& r, float mx, float my,
       const float d = __builtin_amdgcn_fmed3f(ys, y0, y1) - ys;
       keep |= __fmaf_rn(r.qc * d, d, dx * dx * ixx) <= lvl;
     }
-    if (keep) m |= 1u << st;
+    if (keep) m |= 1u << (first + k);
   }
   return m;
 }
 
-// Stages one forward-only record in LDS; returns its strip mask over `want`
-// (the same fields and strip test as the general record below).
-__device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, double ox, double oy,
-                                          uint32_t want, FRec* dst, uint32_t* entry) {
+// The tile origin as FP64, converted where a batch is staged: the empty asm
+// makes the integer look redefined there, so the conversion is not hoisted
+// out of the walk and the origin stays in scalar registers (two FP64 values
+// held in vector registers across the walk cost the backward a wave per
+// SIMD).
+__device__ __forceinline__ double origin_f64(int o) {
+  asm volatile("" : "+s"(o));
+  return (double)o;
+}
+
+// Stages one forward-only record in LDS; returns its mask over the strips
+// first .. first + N - 1 (the same fields and strip test as the general
+// record below).
+template <int N>
+__device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, int ox, int oy,
+                                          int first, FRec* dst, uint32_t* entry) {
   const Rec r = srec[rank];
   FRec l;
-  l.mx = (float)(r.mx - ox);
-  l.my = (float)(r.my - oy);
+  l.mx = (float)(r.mx - origin_f64(ox));
+  l.my = (float)(r.my - origin_f64(oy));
   l.qa = r.qa; l.qb = r.qb; l.qc = r.qc;
   l.hs = r.hs * 1.0001f;
   l.o = r.o;
   l.inv_nu = r.inv_nu;
   l.nb = r.nb;
   l.cr = (double)r.cr; l.cg = (double)r.cg; l.cb = (double)r.cb;
-  const uint32_t m = strip_mask(r, l.mx, l.my, want);
+  const uint32_t m = strip_mask<N>(r, l.mx, l.my, first);
   l.smask = m;
   *dst = l;
   *entry = r.entry;
   return m;
 }
 
-// Stages one record in LDS; returns its strip mask over `want` and the entry.
-__device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, double ox, double oy,
-                                          uint32_t want, LRec* dst, uint32_t* entry) {
+// Stages one record in LDS; returns its mask over the strips first ..
+// first + N - 1, and the entry.
+template <int N>
+__device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t rank, int ox, int oy,
+                                          int first, LRec* dst, uint32_t* entry) {
   const Rec r = srec[rank];
   LRec l;
-  l.mx = (float)(r.mx - ox);
-  l.my = (float)(r.my - oy);
+  l.mx = (float)(r.mx - origin_f64(ox));
+  l.my = (float)(r.my - origin_f64(oy));
   l.qa = r.qa; l.qb = r.qb; l.qc = r.qc;
   // Conservative pre-test level; the alpha test itself decides.
   l.hs = r.hs * 1.0001f;
@@ -161,7 +175,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   // the record goes to LDS before the mask is computed, so that its
   // registers are free by then (the backward's accumulators are live here)
   *dst = l;
-  const uint32_t m = strip_mask(r, l.mx, l.my, want);
+  const uint32_t m = strip_mask<N>(r, l.mx, l.my, first);
   dst->smask = m;
   return m;
 }
@@ -328,7 +342,7 @@ struct TileCtx {
   bool skip;   // g is outside the grid (an order entry that is not a tile)
   int view, tx, ty;
   uint32_t start, end;
-  double ox, oy;
+  int ox, oy;   // tile origin (pixels)
   float px;
   float py[PIX];
   bool inside[PIX];
@@ -379,8 +393,8 @@ __device__ __forceinline__ TileCtx<PIX> tile_ctx(const CamBatch& cb, const uint3
     t.inside[k] = x < c.W && y < c.H;
     t.pix[k] = c.pix_offset + (int64_t)y * c.W + x;
   }
-  t.ox = (double)(tx * kTile);
-  t.oy = (double)(ty * kTile);
+  t.ox = tx * kTile;
+  t.oy = ty * kTile;
   t.start = tile_start[g];
   t.end = tile_start[g + 1];
   return t;
@@ -422,7 +436,7 @@ __device__ __forceinline__ uint64_t stage_batch(const TileCtx<PIX>& t, const Rec
                                                 R* lds, uint32_t strips) {
   const uint32_t k = base + threadIdx.x;
   uint32_t m = 0, e;
-  if (k < stop) m = stage(srec, pair_rank[k], t.ox, t.oy, strips, lds + threadIdx.x, &e);
+  if (k < stop) m = stage<PIX>(srec, pair_rank[k], t.ox, t.oy, PIX * t.sub, lds + threadIdx.x, &e);
   return __ballot((m & strips) != 0u);
 }
 
@@ -441,7 +455,7 @@ __device__ __forceinline__ uint64_t stage_batch_slot(const TileCtx<PIX>& t, cons
   if (k < stop) {
     const uint32_t rank = pair_rank[k];
     uint32_t e;
-    m = stage(srec, rank, t.ox, t.oy, strips, lds + threadIdx.x, &e);
+    m = stage<PIX>(srec, rank, t.ox, t.oy, PIX * t.sub, lds + threadIdx.x, &e);
     const ushort4 rc = det.ent[e].rect;
     const RowGeo g = make_row_geo(srec[rank].mx, srec[rank].my, det.ent[e].ell);
     uint32_t pos = det.rank_off[rank];
