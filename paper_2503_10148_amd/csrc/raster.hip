@@ -39,7 +39,7 @@ constexpr float kLog2e = 1.4426950408889634f;
 // LDS record (16 floats).
 struct __align__(16) LRec {
   float mx, my, qa, qb;      // mean relative to the tile origin; conic a, b
-  float qc, hs, o, inv_nu;   // conic c; truncation test level; opacity; 1/nu
+  float qc, pad, o, inv_nu;  // conic c; (unused); opacity; 1/nu
   float nb, cr, cg, cb;      // -(nu+2)/2; colour
   uint32_t smask;            // bit s: the ellipse reaches strip s (rows 4s..4s+3), of the unit's strips
   float c2;                  // 2 log2(e) / nu (the backward's nu term; 0 for the Gaussian family)
@@ -51,7 +51,7 @@ struct __align__(16) LRec {
 // when staged rather than per pixel in the compositing loop.
 struct __align__(16) FRec {
   float mx, my, qa, qb;
-  float qc, hs, o, inv_nu;
+  float qc, pad, o, inv_nu;
   float nb;
   uint32_t smask;
   double cr, cg, cb;
@@ -71,10 +71,13 @@ struct __align__(16) FRec {
 // cancellation, however elongated the ellipse); on a column x = X likewise
 // qc (y - y*)^2 + (X - mx)^2 / Sigma_xx.  The record gives 1/Sigma_yy =
 // h*/ey^2 and Sigma_xx / Sigma_yy = qc / qa.  A strip is kept when the
-// minimum is within 1% above the hit level h* x 1.0001 (rounding of these
-// few operations, and of h as the evaluation computes it, is far below
-// that).  Without a finite positive h* (alpha_min = 0) the row extent
-// decides, as it does for a zero-size ellipse.
+// minimum is within 1% above h* (the level set of the cut-off, |o| T2D(h*)
+// = alpha_min): the rounding of these few operations is far below that,
+// and so is the band of h in which a rounded alpha can still pass the
+// cut-off, except for an opacity within about 1e-4 of alpha_min, whose
+// alpha is at the cut-off to rounding everywhere.  Without a finite
+// positive h* (alpha_min = 0) the row extent decides, as it does for a
+// zero-size ellipse.
 template <int N>
 __device__ __forceinline__ uint32_t strip_mask(const Rec& r, float mx, float my, int first) {
   uint32_t m = 0;
@@ -139,7 +142,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   l.mx = (float)(r.mx - origin_f64(ox));
   l.my = (float)(r.my - origin_f64(oy));
   l.qa = r.qa; l.qb = r.qb; l.qc = r.qc;
-  l.hs = r.hs * 1.0001f;
+  l.pad = 0.0f;
   l.o = r.o;
   l.inv_nu = r.inv_nu;
   l.nb = r.nb;
@@ -162,7 +165,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   l.my = (float)(r.my - origin_f64(oy));
   l.qa = r.qa; l.qb = r.qb; l.qc = r.qc;
   // Conservative pre-test level; the alpha test itself decides.
-  l.hs = r.hs * 1.0001f;
+  l.pad = 0.0f;
   l.o = r.o;
   l.inv_nu = r.inv_nu;
   l.nb = r.nb;
@@ -184,7 +187,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
 // and backward kernels (explicit fma, compiled without contraction).
 struct Eval {
   float dx, dy, ax, ay, h, y, u, l2, t2, alpha;
-  bool aok, hit, clamped;   // aok: |o T2D| is not below alpha_min
+  bool hit, clamped;   // hit: |o T2D| >= alpha_min (false for NaN)
 };
 
 // kGauss: the Gaussian family (every record has inv_nu = 0 and
@@ -218,8 +221,10 @@ __device__ __forceinline__ void evaluate(float px, float py, const R& L, float a
   }
   E.t2 = __builtin_amdgcn_exp2f(L.nb * E.l2);
   const float a = L.o * E.t2;
-  E.aok = !(fabsf(a) < amin);
-  E.hit = E.h <= L.hs && E.aok;
+  // the cut-off alone decides a hit: h* is the level set |o| T2D(h*) =
+  // alpha_min, so a test of h against it could only differ from this one
+  // within rounding of the level
+  E.hit = fabsf(a) >= amin;
   E.clamped = fabsf(a) > amax;
   E.alpha = __builtin_amdgcn_fmed3f(a, -amax, amax);
 }
@@ -735,11 +740,10 @@ __device__ __forceinline__ void render_bwd_unit(
         if (run) {
           evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
           hk = pos < bound[k] && E.hit;
-          // ballot(hk) as the AND of the ballots of its three compares: the
+          // ballot(hk) as the AND of the ballots of its two compares: the
           // lane masks combine on the scalar unit (one ballot of the
           // combined bool went through two vector instructions)
-          run = (__builtin_amdgcn_ballot_w64(pos < bound[k]) & __builtin_amdgcn_ballot_w64(E.h <= L.hs) &
-                 __builtin_amdgcn_ballot_w64(E.aok)) != 0;
+          run = (__builtin_amdgcn_ballot_w64(pos < bound[k]) & __builtin_amdgcn_ballot_w64(E.hit)) != 0;
         }
         if (!run) {
           if (k == 0) {
