@@ -186,8 +186,8 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
 // Evaluation of one record at one pixel, shared bit-for-bit by the forward
 // and backward kernels (explicit fma, compiled without contraction).
 struct Eval {
-  float dx, dy, ax, ay, h, y, u, l2, t2, alpha;
-  bool hit, clamped;   // hit: |o T2D| >= alpha_min (false for NaN)
+  float dx, dy, ax, ay, h, y, u, l2, t2, a, alpha;   // a = o T2D, alpha = a clamped
+  bool hit, clamped;   // hit: |a| >= alpha_min (false for NaN)
 };
 
 // kGauss: the Gaussian family (every record has inv_nu = 0 and
@@ -221,6 +221,7 @@ __device__ __forceinline__ void evaluate(float px, float py, const R& L, float a
   }
   E.t2 = __builtin_amdgcn_exp2f(L.nb * E.l2);
   const float a = L.o * E.t2;
+  E.a = a;
   // the cut-off alone decides a hit: h* is the level set |o| T2D(h*) =
   // alpha_min, so a test of h against it could only differ from this one
   // within rounding of the level
@@ -741,9 +742,13 @@ __device__ __forceinline__ void render_bwd_unit(
           evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
           hk = pos < bound[k] && E.hit;
           // ballot(hk) as the AND of the ballots of its two compares: the
-          // lane masks combine on the scalar unit (one ballot of the
-          // combined bool went through two vector instructions)
-          run = (__builtin_amdgcn_ballot_w64(pos < bound[k]) & __builtin_amdgcn_ballot_w64(E.hit)) != 0;
+          // lane masks combine on the scalar unit.  The second ballot takes
+          // its own compare, the complement of |a| < alpha_min (the same
+          // lanes as E.hit, NaN aside, where it only adds a lane that
+          // contributes zeros): a ballot of E.hit itself, or of the combined
+          // bool, went through two more vector instructions.
+          run = (__builtin_amdgcn_ballot_w64(pos < bound[k]) &
+                 __builtin_amdgcn_ballot_w64(!(fabsf(E.a) < op.alpha_min))) != 0;
         }
         if (!run) {
           if (k == 0) {
