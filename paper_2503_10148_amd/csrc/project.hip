@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kShBlock) void sh_bwd_kernel(CamBatch cb, int64_t n
   if (sa.on && sa.adam) {
     // Adam on the SH coefficients, per wave over its own 64 components, in
     // the memory order of the coefficient arrays (lane l takes elements
-    // l + 64 t), so the moments stream coalesced.  The SH values come from
+    // l + 64 t, or 16-byte runs), so the moments stream coalesced.  The SH values come from
     // the slots (staged once), the gradient through the same slots: every
     // lane first takes its values, then the slots are overwritten with the
     // per-component gradients and read back in the same order.
@@ -694,43 +694,103 @@ __global__ __launch_bounds__(kShBlock) void sh_bwd_kernel(CamBatch cb, int64_t n
     const int nc = min(max(cnt - 64 * wv, 0), 64);
     const int total = nc * KC;
     const float* wsl = shs + 64 * wv * STR;
-    float pv[KC], gv[KC];
-#pragma unroll
-    for (int t = 0; t < KC; ++t) {
-      const int el = lane + 64 * t, c = el / KC, j = el - c * KC;
-      pv[t] = el < total ? wsl[c * STR + j] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < KC; ++j) slot[j] = gsh[j];
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < KC; ++t) {
-      const int el = lane + 64 * t, c = el / KC, j = el - c * KC;
-      gv[t] = el < total ? wsl[c * STR + j] : 0.0f;
-    }
     const size_t o0 = (size_t)(i0 + 64 * wv) * KC;
-    constexpr int kGrp = 8;                    // loads of a group issued before its updates
+    if constexpr (KC % 4 == 0) {
+      // 16-byte runs: lane l takes elements 4q .. 4q + 3, q = l + 64 t (a run
+      // lies in one component, KC being a multiple of 4), and each group
+      // keeps 4 runs of m and v in flight: twice the bytes per lane of
+      // scalar elements, where the kernel's 3 waves per SIMD (LDS and
+      // registers) leave the memory pipe short of requests
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      constexpr int Q = KC / 4;
+      f4 pv[Q], gv[Q];
 #pragma unroll
-    for (int t0 = 0; t0 < KC; t0 += kGrp) {
-      float m[kGrp], v[kGrp];
+      for (int t = 0; t < Q; ++t) {
+        const int el = 4 * (lane + 64 * t), c = el / KC, j = el - c * KC;
+        const float* w = wsl + c * STR + j;
+        pv[t] = el < total ? f4{w[0], w[1], w[2], w[3]} : f4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+      __syncthreads();
 #pragma unroll
-      for (int u = 0; u < kGrp && t0 + u < KC; ++u) {
-        const int el = lane + 64 * (t0 + u);
-        if (el < total) {
-          m[u] = __builtin_nontemporal_load(sa.m[4] + o0 + el);
-          v[u] = __builtin_nontemporal_load(sa.v[4] + o0 + el);
+      for (int j = 0; j < KC; ++j) slot[j] = gsh[j];
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < Q; ++t) {
+        const int el = 4 * (lane + 64 * t), c = el / KC, j = el - c * KC;
+        const float* w = wsl + c * STR + j;
+        gv[t] = el < total ? f4{w[0], w[1], w[2], w[3]} : f4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+      f4* const m4 = reinterpret_cast<f4*>(sa.m[4] + o0);
+      f4* const v4 = reinterpret_cast<f4*>(sa.v[4] + o0);
+      f4* const p4 = reinterpret_cast<f4*>(sa.sh + o0);
+      constexpr int kGrp = 4;
+#pragma unroll
+      for (int t0 = 0; t0 < Q; t0 += kGrp) {
+        f4 m[kGrp], v[kGrp];
+#pragma unroll
+        for (int u = 0; u < kGrp && t0 + u < Q; ++u) {
+          const int q = lane + 64 * (t0 + u);
+          if (4 * q < total) {
+            m[u] = __builtin_nontemporal_load(m4 + q);
+            v[u] = __builtin_nontemporal_load(v4 + q);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kGrp && t0 + u < Q; ++u) {
+          const int q = lane + 64 * (t0 + u);
+          if (4 * q < total) {
+            f4 pp = pv[t0 + u], mm = m[u], vv = v[u];
+            const f4 gg = gv[t0 + u];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              float pe = pp[e], me = mm[e], ve = vv[e];
+              adam_one(pe, gg[e], me, ve, sa.lr[4], sa.lo[4], sa.hi[4], sa.ac);
+              pp[e] = pe; mm[e] = me; vv[e] = ve;
+            }
+            __builtin_nontemporal_store(pp, p4 + q);
+            __builtin_nontemporal_store(mm, m4 + q);
+            __builtin_nontemporal_store(vv, v4 + q);
+          }
         }
       }
+    } else {
+      float pv[KC], gv[KC];
 #pragma unroll
-      for (int u = 0; u < kGrp && t0 + u < KC; ++u) {
-        const int el = lane + 64 * (t0 + u);
-        if (el < total) {
-          float pp = pv[t0 + u];
-          adam_one(pp, gv[t0 + u], m[u], v[u], sa.lr[4], sa.lo[4], sa.hi[4], sa.ac);
-          __builtin_nontemporal_store(pp, sa.sh + o0 + el);
-          __builtin_nontemporal_store(m[u], sa.m[4] + o0 + el);
-          __builtin_nontemporal_store(v[u], sa.v[4] + o0 + el);
+      for (int t = 0; t < KC; ++t) {
+        const int el = lane + 64 * t, c = el / KC, j = el - c * KC;
+        pv[t] = el < total ? wsl[c * STR + j] : 0.0f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < KC; ++j) slot[j] = gsh[j];
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < KC; ++t) {
+        const int el = lane + 64 * t, c = el / KC, j = el - c * KC;
+        gv[t] = el < total ? wsl[c * STR + j] : 0.0f;
+      }
+      constexpr int kGrp = 8;                  // loads of a group issued before its updates
+#pragma unroll
+      for (int t0 = 0; t0 < KC; t0 += kGrp) {
+        float m[kGrp], v[kGrp];
+#pragma unroll
+        for (int u = 0; u < kGrp && t0 + u < KC; ++u) {
+          const int el = lane + 64 * (t0 + u);
+          if (el < total) {
+            m[u] = __builtin_nontemporal_load(sa.m[4] + o0 + el);
+            v[u] = __builtin_nontemporal_load(sa.v[4] + o0 + el);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kGrp && t0 + u < KC; ++u) {
+          const int el = lane + 64 * (t0 + u);
+          if (el < total) {
+            float pp = pv[t0 + u];
+            adam_one(pp, gv[t0 + u], m[u], v[u], sa.lr[4], sa.lo[4], sa.hi[4], sa.ac);
+            __builtin_nontemporal_store(pp, sa.sh + o0 + el);
+            __builtin_nontemporal_store(m[u], sa.m[4] + o0 + el);
+            __builtin_nontemporal_store(v[u], sa.v[4] + o0 + el);
+          }
         }
       }
     }
