@@ -271,7 +271,7 @@ __device__ __forceinline__ void halve(const float (&a)[N], float (&out)[(N + 1) 
 // wave sum of value tr_index(l) (lanes where tr_index is -1 hold 0).  Four
 // halving steps inside each row of 16 lanes, with partners l^8 (row_ror:8),
 // l^7 (row_half_mirror), l^3 and l^1 (quad permutations), whose xor masks
-// span all 16 lanes, then two exchanges across rows.  About 40 instructions
+// span all 16 lanes, then two exchanges across rows.  About 30 instructions
 // instead of ten 6-step reductions, and the ten sums end in ten lanes of one
 // row, so one memory instruction can store or add them all.
 //
@@ -515,9 +515,18 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
     __syncthreads();
     // Finished pixels are masked off; whether the whole wave is finished is
     // asked every 8 visited records only (a per-record test cost more than
-    // the few records a finished wave may still walk).
+    // the few records a finished wave may still walk), at the top of the
+    // loop, so that T is not read between its update and the next record
+    // (a test after the update cost a register copy of T per record).
     int since = 0;
     while (hits) {
+      if (++since == 9) {
+        since = 1;
+        bool left = false;
+#pragma unroll
+        for (int k = 0; k < PIX; ++k) left |= T[k] > 0.0f;
+        if (!__any(left)) break;
+      }
       const int j = (int)__builtin_ctzll(hits);
       hits &= hits - 1;
       const R L = lds[j];
@@ -559,13 +568,6 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
             }
           }
         }
-      }
-      if (++since == 8) {
-        since = 0;
-        bool left = false;
-#pragma unroll
-        for (int k = 0; k < PIX; ++k) left |= T[k] > 0.0f;
-        if (!__any(left)) break;
       }
     }
   }
