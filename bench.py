@@ -219,15 +219,32 @@ def roofline(achieved, bwd_ms, evals, step_bytes, ms_step, ctr):
 
 def copy_probe():
     """A plain device copy of known size, for scaling the FETCH_SIZE /
-    WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    WRITE_SIZE counters (run under rocprofv3 --pmc), then the HBM rate of
+    the runtime's copy and of the library's streaming copy (the rate the
+    memory-bound stages are read against), each timed over 20 launches."""
     import torch
+    from paper_2503_10148_amd import sss
     n = 1 << 28                                            # 1 GiB of float32
     a = torch.ones(n, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+    out = {"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}
+    for name, fn in (("runtime_copy", lambda: b.copy_(a)), ("stream_copy", lambda: sss.stream_copy(a, b))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            fn()
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 20
+        out[name] = {"us_per_launch": round(us, 1), "tb_s_read_plus_write": round(8 * n / (us * 1e-6) / 1e12, 3)}
+    if not torch.equal(a, b):
+        raise RuntimeError("stream_copy did not copy")
+    print(json.dumps(out))
 
 
 def measure(sss, torch, workload, mode_name, deterministic, steps, warmup, instrument=True, fused=True):

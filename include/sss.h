@@ -498,6 +498,20 @@ int sss_relocate(const sss_scene_t* scene, const sss_state_t* state, int n_state
                  void* stream);
 
 /* ------------------------------------------------------------------------
+ * sss_stream_copy -- a measurement aid, not a step of the method.  Copies
+ * `bytes` from src to dst (device pointers, 16-byte aligned, not
+ * overlapping; bytes a multiple of 16) with the access pattern of the
+ * library's streaming kernels at their best: 16-byte non-temporal loads and
+ * stores, four in flight per thread, up to 32768 workgroups.  Its rate is
+ * the HBM rate such kernels reach on the device, against which the
+ * memory-bound stages are read (the runtime's own device copy moves less).
+ * Ownership stays with the caller; the call is asynchronous on `stream`.
+ * Errors: INVALID for a NULL or misaligned pointer or a size that is not a
+ * multiple of 16 (nothing launched); HIP for a launch error.  bytes = 0
+ * launches nothing. */
+int sss_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (tracing).  When enabled, every kernel the library launches
  * is bracketed by two HIP events on its own stream; sss_timing_read waits
  * for the recorded events and returns, per kernel name, the number of

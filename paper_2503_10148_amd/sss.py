@@ -108,7 +108,7 @@ EXPORTS = ["sss_default_render_opts", "sss_project", "sss_bin_sort", "sss_bin_so
            "sss_render_bwd_workspace_det", "sss_render_bwd_noalloc", "sss_render_bwd_step", "sss_sghmc_step",
            "sss_loss",
            "sss_loss_workspace", "sss_regularise", "sss_relocate", "sss_relocate_workspace", "sss_timing_enable",
-           "sss_timing_reset", "sss_timing_read", "sss_last_error", "sss_version"]
+           "sss_timing_reset", "sss_timing_read", "sss_stream_copy", "sss_last_error", "sss_version"]
 
 _lib = None
 
@@ -160,6 +160,8 @@ def lib():
         L.sss_timing_reset.restype = None
         L.sss_timing_read.argtypes = [vp, i32]
         L.sss_timing_read.restype = i32
+        L.sss_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.sss_stream_copy.restype = i32
         for name in ("sss_project", "sss_bin_sort", "sss_render_fwd", "sss_render_bwd", "sss_render_bwd_noalloc",
                      "sss_render_bwd_step", "sss_sghmc_step"):
             getattr(L, name).restype = i32
@@ -608,6 +610,20 @@ def timing_read() -> dict:
     if k < 0:
         _check(k, "sss_timing_read")
     return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(k)}
+
+
+# ---------------------------------------------------------------------------
+# streaming copy (a measurement aid)
+# ---------------------------------------------------------------------------
+def stream_copy(src, dst, stream=None):
+    """dst <- src with the library's streaming access pattern (same-size
+    contiguous CUDA tensors, 16-byte aligned, a multiple of 16 bytes)."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous CUDA tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    _check(lib().sss_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)), "sss_stream_copy")
 
 
 # ---------------------------------------------------------------------------

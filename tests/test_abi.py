@@ -150,6 +150,17 @@ def test_deterministic_workspace_covers_pairs_and_tiles(sss):
     assert L.sss_render_bwd_workspace_det(1000, 0, 10 ** 5) - base >= 2 * 4 * (10 ** 5 - 10) - 512
 
 
+def test_stream_copy_rejects_bad_arguments_before_any_gpu_call(sss):
+    L = sss.lib()
+    v = ctypes.c_void_p(0x1000)
+    assert L.sss_stream_copy(None, v, 64, None) == sss.ERR_INVALID
+    assert L.sss_stream_copy(v, None, 64, None) == sss.ERR_INVALID
+    assert L.sss_stream_copy(ctypes.c_void_p(0x1004), v, 64, None) == sss.ERR_INVALID
+    assert L.sss_stream_copy(v, ctypes.c_void_p(0x1008), 64, None) == sss.ERR_INVALID
+    assert L.sss_stream_copy(v, v, 40, None) == sss.ERR_INVALID
+    assert L.sss_stream_copy(v, ctypes.c_void_p(0x2000), 0, None) == sss.OK   # nothing to launch
+
+
 def test_sghmc_rejects_bad_arguments(sss):
     L = sss.lib()
     o = sss.SghmcOpts(0.01, 0.1, 100.0, 0.995, 0, 1, 0, 0)
