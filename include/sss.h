@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SSS_VERSION 105
+#define SSS_VERSION 106
 #define SSS_TILE 16           /* tile edge in pixels                            */
 #define SSS_MAX_VIEWS 16      /* views per call                                 */
 #define SSS_RECORD_BYTES 64   /* size of one projected record                  */

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(sss):
     lib = ctypes.CDLL(sss.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert sss.lib().sss_version() == 105
+    assert sss.lib().sss_version() == 106
 
 
 def test_default_options(sss):
