@@ -56,14 +56,23 @@ __device__ __forceinline__ int row_run(const RowGeo& g, int ty, int x0, int x1, 
 // Lane j's value of v, as a wave-uniform value.
 __device__ __forceinline__ int bcast_i(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
 
-// Inclusive prefix sum over the 64 lanes of a wave (all lanes active).
+
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active): DPP
+// row shifts by 1, 2, 4, 8 (a lane outside the row reads 0), then row 0's
+// last lane into row 1 and row 2's into row 3, then lane 31 into rows 2 and
+// 3.  Six VALU adds where shuffles took six LDS round trips.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_add_i(int v) {
+  return v + __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xf, true);
+}
+
 __device__ __forceinline__ int wave_incl_scan(int v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int u = __shfl_up(v, d, 64);
-    if (lane >= d) v += u;
-  }
+  v = dpp_add_i<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_add_i<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_add_i<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_add_i<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_add_i<0x142, 0xa>(v);  // row_bcast:15
+  v = dpp_add_i<0x143, 0xc>(v);  // row_bcast:31
   return v;
 }
 
