@@ -450,31 +450,47 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
 
     Geo<F> g;
     geometry<F>(c, op, mu, s, quats + 4 * i, g);
-    const F A = g.A, B = g.B, D = g.D, det = g.det;
-    // conic (qa, qb, qc) = (D, -B, A) / det -> gradients w.r.t. (A, B, D)
-    const F id = F(1) / det, id2 = id * id;
-    const F gA = -gqa * D * D * id2 + gqb * B * D * id2 + gqc * (id - A * D * id2);
-    const F gD = gqa * (id - A * D * id2) + gqb * A * B * id2 - gqc * A * A * id2;
-    const F gB = F(2) * gqa * B * D * id2 - gqb * (id + F(2) * B * B * id2) + F(2) * gqc * A * B * id2;
-    // G (symmetric 2x2, off-diagonal shared by B)
-    const F G00 = gA, G01 = F(0.5) * gB, G11 = gD;
-    // dSigma = M^T G M
+    // The chain runs through P = M Rq (2x3), the projected component axes,
+    // rather than through Sigma and Sigma2: with N = P diag(s), Sigma2 =
+    // N N^T + lowpass I, so A and D are sums of squares and det (Cauchy-
+    // Binet) is a sum of squared 2x2 minors plus positive low-pass terms,
+    // and the terms of the conic's inverse that were (1/det - A D / det^2)
+    // are -B^2 / det^2.  A D - B^2 in FP32 loses about 2 log2(r) bits for an
+    // ellipse of axis ratio r, as does Sigma = Rq diag(s^2) Rq^T for an
+    // elongated component; these forms lose none to cancellation.
     const F* M = g.M;
-    F GM[6];  // G M (2x3)
+    const F* R = g.Rq;
+    const F sv[3] = {s[0], s[1], s[2]};
+    const F sq[3] = {sv[0] * sv[0], sv[1] * sv[1], sv[2] * sv[2]};
+    F P[6];
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 3; ++k) P[3 * r + k] = M[3 * r] * R[k] + M[3 * r + 1] * R[3 + k] + M[3 * r + 2] * R[6 + k];
+    const F n00 = P[0] * sv[0], n01 = P[1] * sv[1], n02 = P[2] * sv[2];
+    const F n10 = P[3] * sv[0], n11 = P[4] * sv[1], n12 = P[5] * sv[2];
+    const F A0 = n00 * n00 + n01 * n01 + n02 * n02, D0 = n10 * n10 + n11 * n11 + n12 * n12;
+    const F B = n00 * n10 + n01 * n11 + n02 * n12;
+    const F m01 = n00 * n11 - n01 * n10, m02 = n00 * n12 - n02 * n10, m12 = n01 * n12 - n02 * n11;
+    const F lp = op.lowpass;
+    const F A = A0 + lp, D = D0 + lp;
+    const F det = m01 * m01 + m02 * m02 + m12 * m12 + lp * (A0 + D0) + lp * lp;
+    // conic (qa, qb, qc) = (D, -B, A) / det -> gradients w.r.t. (A, B, D)
+    const F id2 = F(1) / (det * det);
+    const F gA = id2 * (-gqa * D * D + gqb * B * D - gqc * B * B);
+    const F gD = id2 * (-gqa * B * B + gqb * A * B - gqc * A * A);
+    const F gB = id2 * (F(2) * gqa * B * D - gqb * (A * D + B * B) + F(2) * gqc * A * B);
+    // G (symmetric 2x2, off-diagonal shared by B) and G P (2x3)
+    const F G00 = gA, G01 = F(0.5) * gB, G11 = gD;
+    F GP[6];
     for (int k = 0; k < 3; ++k) {
-      GM[k] = G00 * M[k] + G01 * M[3 + k];
-      GM[3 + k] = G01 * M[k] + G11 * M[3 + k];
+      GP[k] = G00 * P[k] + G01 * P[3 + k];
+      GP[3 + k] = G01 * P[k] + G11 * P[3 + k];
     }
-    F dS[9];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) dS[3 * a + b] = M[a] * GM[b] + M[3 + a] * GM[3 + b];
-    // dM = 2 G M Sigma
-    const F* S = g.S;
-    const F Sf[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
+    // dM = 2 G M Sigma = 2 (G P) diag(s^2) Rq^T
     F dM[6];
     for (int r = 0; r < 2; ++r)
       for (int b = 0; b < 3; ++b)
-        dM[3 * r + b] = F(2) * (GM[3 * r] * Sf[b] + GM[3 * r + 1] * Sf[3 + b] + GM[3 * r + 2] * Sf[6 + b]);
+        dM[3 * r + b] = F(2) * (GP[3 * r] * sq[0] * R[3 * b] + GP[3 * r + 1] * sq[1] * R[3 * b + 1] +
+                                GP[3 * r + 2] * sq[2] * R[3 * b + 2]);
     // M = J Rview: dJ = dM Rview^T (only J00, J02, J11, J12 are non-zero)
     const F dJ00 = dM[0] * c.R[0] + dM[1] * c.R[1] + dM[2] * c.R[2];
     const F dJ02 = dM[0] * c.R[6] + dM[1] * c.R[7] + dM[2] * c.R[8];
@@ -499,22 +515,13 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     }
     for (int a = 0; a < 3; ++a) gmu[a] += c.R[a] * dX + c.R[3 + a] * dY + c.R[6 + a] * dZ;
 
-    // Sigma = Rq diag(s^2) Rq^T
-    const F* R = g.Rq;
-    const F sq[3] = {s[0] * s[0], s[1] * s[1], s[2] * s[2]};
+    // Sigma = Rq diag(s^2) Rq^T with dSigma = M^T G M: dRq = 2 dSigma Rq
+    // diag(s^2), where dSigma Rq = M^T (G P); d s_k = 2 s_k (Rq^T dSigma
+    // Rq)_kk = 2 s_k P_k^T G P_k (P_k: column k of P)
     F dR[9];
     for (int r = 0; r < 3; ++r)
-      for (int k = 0; k < 3; ++k) {
-        const F t = dS[3 * r] * R[k] + dS[3 * r + 1] * R[3 + k] + dS[3 * r + 2] * R[6 + k];
-        dR[3 * r + k] = F(2) * t * sq[k];
-      }
-    for (int k = 0; k < 3; ++k) {
-      // (R^T dS R)_kk
-      F acc = 0;
-      for (int r = 0; r < 3; ++r)
-        acc += R[3 * r + k] * (dS[3 * r] * R[k] + dS[3 * r + 1] * R[3 + k] + dS[3 * r + 2] * R[6 + k]);
-      gs[k] += F(2) * s[k] * acc;
-    }
+      for (int k = 0; k < 3; ++k) dR[3 * r + k] = F(2) * (M[r] * GP[k] + M[3 + r] * GP[3 + k]) * sq[k];
+    for (int k = 0; k < 3; ++k) gs[k] += F(2) * sv[k] * (P[k] * GP[k] + P[3 + k] * GP[3 + k]);
     const F w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
     F gu[4];
     gu[0] = -F(2) * z * dR[1] + F(2) * y * dR[2] + F(2) * z * dR[3] - F(2) * x * dR[5] - F(2) * y * dR[6] +

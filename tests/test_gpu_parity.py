@@ -47,10 +47,22 @@ def _case(name):
     if name == "bigcomp":                        # few large fat-tailed components
         s = scenes.make_scene(300, 1, seed=9, neg_frac=0.3, scale_range=(0.05, 0.3))
         return s, [scenes.ring_camera(170, 120, angle=0.2)]
+    if name == "needles":                        # elongated, randomly rotated: tilted
+        # ellipses that cross tile corners, where a strip test by the
+        # ellipse's row extent and the exact one differ (screen-space axis
+        # ratios 8 at the median, up to 24: within what the raster's FP32
+        # conic resolves; at ratios near 60 its rounding puts some scale
+        # gradients beyond the bar)
+        s = scenes.make_scene(1500, 1, seed=10, neg_frac=0.3)
+        rng = np.random.default_rng(10)
+        s["scales"] = np.ascontiguousarray(np.stack(
+            [rng.uniform(0.05, 0.2, 1500), rng.uniform(0.008, 0.015, 1500), rng.uniform(0.008, 0.015, 1500)],
+            axis=1), dtype=np.float32)
+        return s, [scenes.ring_camera(250, 181, angle=0.7)]
     raise KeyError(name)
 
 
-CASES = ["small", "sh3_ragged", "clusters", "bigcomp"]
+CASES = ["small", "sh3_ragged", "clusters", "bigcomp", "needles"]
 
 
 def gpu_forward(sss, scene, cams, opts=None):
