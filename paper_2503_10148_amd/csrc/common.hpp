@@ -39,7 +39,8 @@ struct OptsDev {
 // 1e-6 px at 1080p; everything a pixel evaluation needs follows.
 struct __align__(16) Rec {
   double mx, my;       // 2D mean (pixels)
-  float qa, qb, qc;    // conic: h = qa dx^2 + 2 qb dx dy + qc dy^2
+  float l11, l21, l22; // the conic Q = L L^T by its Cholesky factor L = [[l11, 0], [l21, l22]]:
+                       // h = d^T Q d = (l11 dx + l21 dy)^2 + (l22 dy)^2
   float cr, cg, cb;    // colour
   float o;             // signed opacity
   float inv_nu;        // 1 / nu; 0 for the Gaussian family

@@ -322,9 +322,14 @@ __device__ __forceinline__ bool project_entry(const CamDev& c, const OptsDev& op
   Rec r;
   r.mx = mx;
   r.my = my;
-  r.qa = (float)(g.D * idet);
-  r.qb = (float)(-g.B * idet);
-  r.qc = (float)(g.A * idet);
+  // the conic (D, -B, A) / det as its Cholesky factor, from the covariance
+  // in FP64 (det = A D - B^2 makes l22 = 1/sqrt(D)): h as a sum of two
+  // squares keeps its precision in FP32 near an elongated ellipse's major
+  // axis, where the three conic entries cancel about 2 log2(axis ratio) bits
+  const double sD = sqrt(g.D);
+  r.l11 = (float)(sD * sqrt(idet));
+  r.l21 = (float)(-g.B * sqrt(idet) / sD);
+  r.l22 = (float)(1.0 / sD);
   r.cr = (float)fmax(col[0], 0.0);
   r.cg = (float)fmax(col[1], 0.0);
   r.cb = (float)fmax(col[2], 0.0);
@@ -443,8 +448,11 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     const CamDev& c = cb.v[v];
     const double2* gp = reinterpret_cast<const double2*>(g2 + e * kG2);
     const double2 g01 = gp[0], g23 = gp[1], g45 = gp[2], g89 = gp[4];
-    const F gmx = (F)g01.x * cgeo, gmy = (F)g01.y * cgeo, gqa = (F)g23.x * cgeo, gqb = (F)g23.y * cgeo,
-            gqc = (F)g45.x * cgeo;
+    // the raster's sums in the frame w = L^T d of the conic's Cholesky
+    // factor L: mean (-2 sum dh w) and the symmetric sum dh w w^T (00, 2 x
+    // 01, 11)
+    const F gw0 = (F)g01.x * cgeo, gw1 = (F)g01.y * cgeo, gw00 = (F)g23.x * cgeo,
+            gw01 = F(0.5) * (F)g23.y * cgeo, gw11 = (F)g45.x * cgeo;
     gop += (F)g89.x;
     gnu += (F)g89.y * cnu;
 
@@ -473,13 +481,16 @@ __global__ __launch_bounds__(kBlock) void project_bwd_kernel(
     const F lp = op.lowpass;
     const F A = A0 + lp, D = D0 + lp;
     const F det = m01 * m01 + m02 * m02 + m12 * m12 + lp * (A0 + D0) + lp * lp;
-    // conic (qa, qb, qc) = (D, -B, A) / det -> gradients w.r.t. (A, B, D)
-    const F id2 = F(1) / (det * det);
-    const F gA = id2 * (-gqa * D * D + gqb * B * D - gqc * B * B);
-    const F gD = id2 * (-gqa * B * B + gqb * A * B - gqc * A * A);
-    const F gB = id2 * (F(2) * gqa * B * D - gqb * (A * D + B * B) + F(2) * gqc * A * B);
-    // G (symmetric 2x2, off-diagonal shared by B) and G P (2x3)
-    const F G00 = gA, G01 = F(0.5) * gB, G11 = gD;
+    // the conic's Cholesky factor (Q = Sigma2^-1 = L L^T), as the
+    // projection forms it: l11 = sqrt(D/det), l21 = -B/sqrt(D det), l22 =
+    // 1/sqrt(D); the mean's gradient is L (gw0, gw1), and the 2D covariance's
+    // G = -L (sum dh w w^T) L^T (symmetric 2x2, off-diagonal shared by B)
+    const F isD = F(1) / sqrt(D), isdet = F(1) / sqrt(det);
+    const F l11 = sqrt(D) * isdet, l21 = -B * isD * isdet, l22 = isD;
+    const F gmx = l11 * gw0, gmy = l21 * gw0 + l22 * gw1;
+    const F G00 = -(l11 * l11 * gw00);
+    const F G01 = -(l11 * (l21 * gw00 + l22 * gw01));
+    const F G11 = -(l21 * l21 * gw00 + F(2) * l21 * l22 * gw01 + l22 * l22 * gw11);
     F GP[6];
     for (int k = 0; k < 3; ++k) {
       GP[k] = G00 * P[k] + G01 * P[3 + k];

@@ -38,8 +38,8 @@ constexpr float kLog2e = 1.4426950408889634f;
 
 // LDS record (16 floats).
 struct __align__(16) LRec {
-  float mx, my, qa, qb;      // mean relative to the tile origin; conic a, b
-  float qc, pad, o, inv_nu;  // conic c; (unused); opacity; 1/nu
+  float mx, my, l11, l21;    // mean relative to the tile origin; conic's Cholesky factor
+  float l22, pad, o, inv_nu; // (h = (l11 dx + l21 dy)^2 + (l22 dy)^2); (unused); opacity; 1/nu
   float nb, cr, cg, cb;      // -(nu+2)/2; colour
   uint32_t smask;            // bit s: the ellipse reaches strip s (rows 4s..4s+3), of the unit's strips
   float c2;                  // 2 log2(e) / nu (the backward's nu term; 0 for the Gaussian family)
@@ -50,8 +50,8 @@ struct __align__(16) LRec {
 // Forward-only LDS record (64 bytes): the colour is converted to FP64 once
 // when staged rather than per pixel in the compositing loop.
 struct __align__(16) FRec {
-  float mx, my, qa, qb;
-  float qc, pad, o, inv_nu;
+  float mx, my, l11, l21;
+  float l22, pad, o, inv_nu;
   float nb;
   uint32_t smask;
   double cr, cg, cb;
@@ -91,9 +91,12 @@ __device__ __forceinline__ uint32_t strip_mask(const Rec& r, float mx, float my,
     }
     return m;
   }
+  // the conic's entries from its factor (qa = l11^2, qb = l11 l21, qc =
+  // l21^2 + l22^2: sums of products, no cancellation in qa and qc)
+  const float qa = r.l11 * r.l11, qb = r.l11 * r.l21, qc = __fmaf_rn(r.l21, r.l21, r.l22 * r.l22);
   const float iyy = r.hs * __builtin_amdgcn_rcpf(ey * ey);
-  const float ixx = iyy * r.qa * __builtin_amdgcn_rcpf(r.qc);
-  const float kx = r.qb * __builtin_amdgcn_rcpf(r.qa), ky = r.qb * __builtin_amdgcn_rcpf(r.qc);
+  const float ixx = iyy * qa * __builtin_amdgcn_rcpf(qc);
+  const float kx = r.l21 * __builtin_amdgcn_rcpf(r.l11), ky = qb * __builtin_amdgcn_rcpf(qc);
   const float lvl = (r.hs * 1.0001f) * 1.01f;
   constexpr float x0 = 0.5f, x1 = (float)kTile - 0.5f;
   const bool in_x = mx >= x0 && mx <= x1;
@@ -107,14 +110,14 @@ __device__ __forceinline__ uint32_t strip_mask(const Rec& r, float mx, float my,
       const float dy = (e ? y1 : y0) - my;
       const float xs = __fmaf_rn(-kx, dy, mx);
       const float d = __builtin_amdgcn_fmed3f(xs, x0, x1) - xs;
-      keep |= __fmaf_rn(r.qa * d, d, dy * dy * iyy) <= lvl;
+      keep |= __fmaf_rn(qa * d, d, dy * dy * iyy) <= lvl;
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const float dx = (e ? x1 : x0) - mx;
       const float ys = __fmaf_rn(-ky, dx, my);
       const float d = __builtin_amdgcn_fmed3f(ys, y0, y1) - ys;
-      keep |= __fmaf_rn(r.qc * d, d, dx * dx * ixx) <= lvl;
+      keep |= __fmaf_rn(qc * d, d, dx * dx * ixx) <= lvl;
     }
     if (keep) m |= 1u << (first + k);
   }
@@ -141,7 +144,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   FRec l;
   l.mx = (float)(r.mx - origin_f64(ox));
   l.my = (float)(r.my - origin_f64(oy));
-  l.qa = r.qa; l.qb = r.qb; l.qc = r.qc;
+  l.l11 = r.l11; l.l21 = r.l21; l.l22 = r.l22;
   l.pad = 0.0f;
   l.o = r.o;
   l.inv_nu = r.inv_nu;
@@ -163,7 +166,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   LRec l;
   l.mx = (float)(r.mx - origin_f64(ox));
   l.my = (float)(r.my - origin_f64(oy));
-  l.qa = r.qa; l.qb = r.qb; l.qc = r.qc;
+  l.l11 = r.l11; l.l21 = r.l21; l.l22 = r.l22;
   // Conservative pre-test level; the alpha test itself decides.
   l.pad = 0.0f;
   l.o = r.o;
@@ -186,7 +189,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
 // Evaluation of one record at one pixel, shared bit-for-bit by the forward
 // and backward kernels (explicit fma, compiled without contraction).
 struct Eval {
-  float dx, dy, ax, ay, h, y, u, l2, t2, a, alpha;   // a = o T2D, alpha = a clamped
+  float dx, dy, w0, w1, h, y, u, l2, t2, a, alpha;   // (w0, w1) = L^T d; a = o T2D, alpha = a clamped
   bool hit, clamped;   // hit: |a| >= alpha_min (false for NaN)
 };
 
@@ -197,9 +200,13 @@ template <bool kGauss, typename R>
 __device__ __forceinline__ void evaluate(float px, float py, const R& L, float amin, float amax, Eval& E) {
   E.dx = px - L.mx;
   E.dy = py - L.my;
-  E.ax = __fmaf_rn(L.qb, E.dy, L.qa * E.dx);
-  E.ay = __fmaf_rn(L.qb, E.dx, L.qc * E.dy);
-  E.h = __fmaf_rn(E.dx, E.ax, E.dy * E.ay);
+  // h = |w|^2 with w = L^T d (the conic's Cholesky factor L): a sum of two
+  // squares, so near an elongated ellipse's major axis FP32 keeps h to about
+  // (axis ratio) x 6e-8 relative, where the conic entries' form lost
+  // (axis ratio)^2 x 6e-8.  The backward's sums are taken in w as well.
+  E.w0 = __fmaf_rn(L.l21, E.dy, L.l11 * E.dx);
+  E.w1 = L.l22 * E.dy;
+  E.h = __fmaf_rn(E.w0, E.w0, E.w1 * E.w1);
   // Branch-free: once a record passes the strip test nearly every wave has
   // a lane inside the ellipse, so the whole chain runs anyway; selects keep
   // the exec mask untouched.
@@ -328,9 +335,9 @@ __device__ __forceinline__ int tr_index(int lane) {
   return 5 * b3 + 3 * b2 + 2 * b1 + b0;
 }
 
-// Scale of each screen-space gradient component as stored: d/d mean (x, y)
-// and d/d conic b carry the factors of h = a dx^2 + 2 b dx dy + c dy^2 with
-// d = pixel - mean.
+// Scale of each screen-space gradient component as stored: the two mean
+// sums carry the -2 of dh/d mean = -2 L w, and the off-diagonal sum of
+// dh w w^T is stored doubled (it appears twice in the symmetric matrix).
 __device__ __forceinline__ float g2_scale(int idx) { return idx < 2 ? -2.0f : (idx == 3 ? 2.0f : 1.0f); }
 
 // Pixels of a unit owned by a thread: unit `sub` of a tile covers rows
@@ -778,11 +785,17 @@ __device__ __forceinline__ void render_bwd_unit(
         // backward): dh here is dh / (o nb (1/nu or ln 2)).
         const float dt = da * E.t2;
         const float dh = kGauss ? dt : dt * ru;
-        const float tq = dh * E.dx;
-        // the ten terms as products A[f] * B[f]: d mean (2), d conic (3),
-        // d colour (3), d opacity, d nu / (o ln(2) / 2)
-        float A[10] = {dh, dh, tq, tq, dh * E.dy, g[k][0], g[k][1], g[k][2], dt, dt};
-        float B[10] = {E.ax, E.ay, E.dx, E.dy, E.dy, w, w, w, 1.0f, 0.0f};
+        // the ten terms as products A[f] * B[f]: dh w (2), dh w w^T (3: 00,
+        // 01, 11), d colour (3), d opacity, d nu / (o ln(2) / 2).  With Q =
+        // L L^T and d = pixel - mean, dh/d mean = -2 Q d = -2 L w and the
+        // gradient of the 2D covariance is -Q (sum dh d d^T) Q = -L (sum dh w
+        // w^T) L^T: the projection backward applies L once per entry.  In w
+        // the quadratic is isotropic, so its three sums stay of one size; in
+        // pixel coordinates the thin axis's share of sum dh d d^T was
+        // (axis ratio)^2 below the rest and lost to FP32.
+        const float tq = dh * E.w0;
+        float A[10] = {dh, dh, tq, tq, dh * E.w1, g[k][0], g[k][1], g[k][2], dt, dt};
+        float B[10] = {E.w0, E.w1, E.w0, E.w1, E.w1, w, w, w, 1.0f, 0.0f};
         if constexpr (!kGauss) {
           // dT2D/dnu = T2D/2 [y/(1+y) - ln(1+y) + 2y/(nu (1+y))], here the
           // bracket / ln 2.  The first two terms cancel for small y: below

@@ -1,7 +1,7 @@
 """Helpers shared by the tests: record decoding, device upload, tolerances."""
 import numpy as np
 
-REC_DTYPE = np.dtype([("mx", "<f8"), ("my", "<f8"), ("qa", "<f4"), ("qb", "<f4"), ("qc", "<f4"), ("cr", "<f4"),
+REC_DTYPE = np.dtype([("mx", "<f8"), ("my", "<f8"), ("l11", "<f4"), ("l21", "<f4"), ("l22", "<f4"), ("cr", "<f4"),
                       ("cg", "<f4"), ("cb", "<f4"), ("o", "<f4"), ("inv_nu", "<f4"), ("nb", "<f4"), ("hs", "<f4"),
                       ("entry", "<u4"), ("ey", "<f4")])
 assert REC_DTYPE.itemsize == 64

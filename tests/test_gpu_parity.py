@@ -49,14 +49,13 @@ def _case(name):
         return s, [scenes.ring_camera(170, 120, angle=0.2)]
     if name == "needles":                        # elongated, randomly rotated: tilted
         # ellipses that cross tile corners, where a strip test by the
-        # ellipse's row extent and the exact one differ (screen-space axis
-        # ratios 8 at the median, up to 24: within what the raster's FP32
-        # conic resolves; at ratios near 60 its rounding puts some scale
-        # gradients beyond the bar)
+        # ellipse's row extent and the exact one differ, and where h near the
+        # major axis is a small difference of large conic terms (screen-space
+        # axis ratios 17 at the median, up to 63)
         s = scenes.make_scene(1500, 1, seed=10, neg_frac=0.3)
         rng = np.random.default_rng(10)
         s["scales"] = np.ascontiguousarray(np.stack(
-            [rng.uniform(0.05, 0.2, 1500), rng.uniform(0.008, 0.015, 1500), rng.uniform(0.008, 0.015, 1500)],
+            [rng.uniform(0.05, 0.2, 1500), rng.uniform(0.003, 0.008, 1500), rng.uniform(0.003, 0.008, 1500)],
             axis=1), dtype=np.float32)
         return s, [scenes.ring_camera(250, 181, angle=0.7)]
     raise KeyError(name)
@@ -99,9 +98,20 @@ def test_project_matches_oracle(sss, name):
     assert np.array_equal(rect[m & ~flagged], o["rect"][m & ~flagged])
     np.testing.assert_allclose(rec["mx"][m], o["mean2d"][m, 0], rtol=1e-12, atol=1e-9)
     np.testing.assert_allclose(rec["my"][m], o["mean2d"][m, 1], rtol=1e-12, atol=1e-9)
+    # the conic as its Cholesky factor L (Q = L L^T), from the oracle's FP64
+    # covariance (A, B, D): l11 = sqrt(D/det), l21 = -B/sqrt(D det), l22 =
+    # 1/sqrt(D) with det = A D - B^2
+    A, B, D = (o["cov2d"][m, j] for j in range(3))
+    det = A * D - B * B
+    ref = {"l11": np.sqrt(D / det), "l21": -B / np.sqrt(D * det), "l22": 1.0 / np.sqrt(D)}
+    ls = sum(np.abs(ref[f]) for f in ref)
+    for f in ref:
+        assert np.all(np.abs(rec[f][m] - ref[f]) <= 2e-7 * ls), f
+    # and L L^T is the oracle's conic
+    l11, l21, l22 = (rec[f][m].astype(np.float64) for f in ("l11", "l21", "l22"))
     cs = np.abs(o["conic"][m]).sum(1)
-    for j, f in enumerate(("qa", "qb", "qc")):
-        assert np.all(np.abs(rec[f][m] - o["conic"][m, j]) <= 2e-7 * cs)
+    for q, j in ((l11 * l11, 0), (l11 * l21, 1), (l21 * l21 + l22 * l22, 2)):
+        assert np.all(np.abs(q - o["conic"][m, j]) <= 1e-6 * cs)
     for j, f in enumerate(("cr", "cg", "cb")):
         np.testing.assert_allclose(rec[f][m], o["rgb"][m, j], rtol=2e-7, atol=1e-7)
     np.testing.assert_allclose(1.0 / rec["inv_nu"][m].astype(np.float64), o["nu_c"][m], rtol=2e-7)
