@@ -108,9 +108,12 @@ typedef struct {
 
 /* Rendering conventions.  Defaults from sss_default_render_opts():
  *   alpha_min 1/255  a component is skipped at a pixel where |o T2D| < alpha_min
- *   alpha_max 0.99   |alpha| is clamped to alpha_max (no gradient when clamped)
+ *   alpha_max 0.99   |alpha| is clamped to alpha_max (no gradient when clamped);
+ *                    must lie in (0, 1)
  *   t_min     1e-4   a pixel stops before the component that would bring its
- *                    transmittance below t_min (that component is not added)
+ *                    transmittance below t_min (that component is not added);
+ *                    values below the smallest normal float (1.18e-38), 0
+ *                    included, act as that value
  *   z_near    0.2    components with depth <= z_near are culled
  *   nu_min, nu_max   1, 1e4 (SM "Implementation Details")
  *   lowpass   0      added to the diagonal of the 2D covariance (the paper's

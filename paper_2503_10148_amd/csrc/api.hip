@@ -68,7 +68,11 @@ OptsDev make_opts(const sss_render_opts_t* o) {
     o = &d;
   }
   OptsDev r;
-  r.alpha_min = o->alpha_min; r.alpha_max = o->alpha_max; r.t_min = o->t_min; r.z_near = o->z_near;
+  // a t_min below the smallest normal float acts as that value, so a
+  // compositing pixel's transmittance stays positive and a finished one's
+  // (negated) stays below it whatever it is multiplied by
+  r.alpha_min = o->alpha_min; r.alpha_max = o->alpha_max; r.t_min = fmaxf(o->t_min, 1.17549435e-38f);
+  r.z_near = o->z_near;
   r.nu_min = o->nu_min; r.nu_max = o->nu_max; r.lowpass = o->lowpass;
   r.bg[0] = o->bg[0]; r.bg[1] = o->bg[1]; r.bg[2] = o->bg[2];
   r.family = o->family;
@@ -93,11 +97,12 @@ static int check_scene(const sss_scene_t* s, const char* fn) {
 
 static int check_opts(const sss_render_opts_t* o, const char* fn) {
   if (!o) return SSS_OK;
-  if (!(o->alpha_min >= 0.0f) || !(o->alpha_max > 0.0f) || !(o->t_min >= 0.0f) || !(o->nu_min >= 1.0f) ||
+  if (!(o->alpha_min >= 0.0f) || !(o->alpha_max > 0.0f && o->alpha_max < 1.0f) || !(o->t_min >= 0.0f) ||
+      !(o->nu_min >= 1.0f) ||
       !(o->nu_max >= o->nu_min) || !(o->lowpass >= 0.0f) ||
       (o->family != SSS_FAMILY_STUDENT_T && o->family != SSS_FAMILY_GAUSSIAN) ||
       (o->trunc_mode != SSS_TRUNC_ALPHA && o->trunc_mode != SSS_TRUNC_COVERAGE)) {
-    set_error("%s: options out of range (alpha_min >= 0, alpha_max > 0, t_min >= 0, 1 <= nu_min <= nu_max, "
+    set_error("%s: options out of range (alpha_min >= 0, 0 < alpha_max < 1, t_min >= 0, 1 <= nu_min <= nu_max, "
               "lowpass >= 0, known family and truncation mode)", fn);
     return SSS_ERR_INVALID;
   }

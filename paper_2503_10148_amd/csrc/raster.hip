@@ -498,12 +498,18 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
   // accumulated up to a component from the output, and for components deep
   // in a list (small T) an FP32 running sum's accumulated rounding would be
   // a large part of that difference.  FP64 FMA issues at the FP32 rate here.
-  // A pixel is finished when its T is negative: T stays positive while it
-  // composites (1 - alpha lies in [0.01, 1.99]), and termination negates it,
-  // so the final transmittance is |T| and the per-record test is one compare.
+  // A pixel is finished when its T is negative: T stays at or above t_min
+  // (> 0) while it composites (1 - alpha lies in [1 - alpha_max, 1 +
+  // alpha_max], alpha_max < 1), and termination negates it, so the final
+  // transmittance is |T|.
   float T[PIX];
   double c0[PIX], c1[PIX], c2[PIX];
   uint32_t last[PIX];
+  // kSelect: the last compositing record of the current batch as its LDS
+  // byte offset (the address the record is read from), kNoRec if none;
+  // turned into a list position once per batch
+  constexpr uint32_t kNoRec = 0xFFFFFFFFu;
+  uint32_t lastj[PIX];
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     T[k] = t.inside[k] ? 1.0f : -1.0f;
@@ -526,6 +532,8 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
     // loop, so that T is not read between its update and the next record
     // (a test after the update cost a register copy of T per record).
     int since = 0;
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) lastj[k] = kNoRec;
     while (hits) {
       if (++since == 9) {
         since = 1;
@@ -542,21 +550,22 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
       for (int k = 0; k < PIX; ++k) {
         if constexpr (kSelect) {
           if (!(sm & ws.bit[k])) continue;  // wave-uniform
-          // A lane that is finished, misses the ellipse or terminates here
-          // adds a zero weight (x + 0 is x exactly) and keeps its T.
+          // A lane that misses the ellipse or terminates here adds a zero
+          // weight (x + 0 is x exactly) and keeps its T.  A finished lane
+          // needs no test of its own: its T (1 - alpha) is negative, below
+          // t_min, so it takes the termination branch and keeps -|T| = T.
           Eval E;
           evaluate<kGauss>(t.px, t.py[k], L, op.alpha_min, op.alpha_max, E);
-          const bool live = T[k] > 0.0f && E.hit;
           const float Tn = __fmaf_rn(-T[k], E.alpha, T[k]);   // T (1 - alpha), one rounding
           const bool term = Tn < op.t_min;
-          const bool comp = __builtin_unpredictable(live && !term);
+          const bool comp = __builtin_unpredictable(E.hit && !term);
           // the select on alpha, not on the product: one FP32 select
           const double wgt = (double)((comp ? E.alpha : 0.0f) * T[k]);
           c0[k] = __fma_rn((double)L.cr, wgt, c0[k]);
           c1[k] = __fma_rn((double)L.cg, wgt, c1[k]);
           c2[k] = __fma_rn((double)L.cb, wgt, c2[k]);
-          T[k] = __builtin_unpredictable(live) ? (term ? -T[k] : Tn) : T[k];
-          last[k] = comp ? base - t.start + (uint32_t)j + 1u : last[k];
+          T[k] = __builtin_unpredictable(E.hit) ? (term ? -fabsf(T[k]) : Tn) : T[k];
+          lastj[k] = comp ? (uint32_t)j * (uint32_t)sizeof(R) : lastj[k];
         } else {
           if (!(T[k] > 0.0f) || !(sm & ws.bit[k])) continue;
           Eval E;
@@ -576,6 +585,11 @@ __device__ __forceinline__ void forward_walk(const TileCtx<PIX>& t, const OptsDe
           }
         }
       }
+    }
+    if constexpr (kSelect) {
+#pragma unroll
+      for (int k = 0; k < PIX; ++k)
+        if (lastj[k] != kNoRec) last[k] = base - t.start + lastj[k] / (uint32_t)sizeof(R) + 1u;
     }
   }
 #pragma unroll

@@ -74,7 +74,7 @@ def _proj_struct(sss):
 
 
 @pytest.mark.parametrize("kind", ["null_scene", "bad_degree", "zero_n", "null_array", "no_views", "too_many_views",
-                                  "zero_width", "bad_focal", "bad_opts"])
+                                  "zero_width", "bad_focal", "bad_opts", "alpha_max_one"])
 def test_project_rejects_bad_arguments(sss, kind):
     L = sss.lib()
     cam = scenes.ring_camera(64, 48)
@@ -98,6 +98,8 @@ def test_project_rejects_bad_arguments(sss, kind):
         cams[0].fx = 0.0
     elif kind == "bad_opts":
         opts.nu_min = 0.5
+    elif kind == "alpha_max_one":
+        opts.alpha_max = 1.0      # 1 - alpha must stay positive
     p = _proj_struct(sss)
     sp = None if kind == "null_scene" else ctypes.byref(scene)
     rc = L.sss_project(sp, cams, nviews, ctypes.byref(opts), ctypes.byref(p), None)
