@@ -38,8 +38,8 @@ constexpr float kLog2e = 1.4426950408889634f;
 
 // LDS record (16 floats).
 struct __align__(16) LRec {
-  float mx, my, l11, l21;    // mean relative to the tile origin; conic's Cholesky factor
-  float l22, pad, o, inv_nu; // (h = (l11 dx + l21 dy)^2 + (l22 dy)^2); (unused); opacity; 1/nu
+  float q0, q1, l11, l21;    // L^T m (m: mean relative to the tile origin); conic's Cholesky factor
+  float l22, pad, o, inv_nu; // (L = [[l11, 0], [l21, l22]], h = |L^T p - L^T m|^2); (unused); opacity; 1/nu
   float nb, cr, cg, cb;      // -(nu+2)/2; colour
   uint32_t smask;            // bit s: the ellipse reaches strip s (rows 4s..4s+3), of the unit's strips
   float c2;                  // 2 log2(e) / nu (the backward's nu term; 0 for the Gaussian family)
@@ -50,7 +50,7 @@ struct __align__(16) LRec {
 // Forward-only LDS record (64 bytes): the colour is converted to FP64 once
 // when staged rather than per pixel in the compositing loop.
 struct __align__(16) FRec {
-  float mx, my, l11, l21;
+  float q0, q1, l11, l21;
   float l22, pad, o, inv_nu;
   float nb;
   uint32_t smask;
@@ -134,6 +134,18 @@ __device__ __forceinline__ double origin_f64(int o) {
   return (double)o;
 }
 
+// The record's mean relative to the tile origin (m, for the strip test) and
+// L^T m, both from the FP64 mean and rounded once: a pixel p of the tile then
+// has w = L^T (p - m) = L^T p - L^T m, two FMAs for w0 and one for w1.
+__device__ __forceinline__ void tile_frame(const Rec& r, int ox, int oy, float* q0, float* q1, float* mx,
+                                           float* my) {
+  const double dx = r.mx - origin_f64(ox), dy = r.my - origin_f64(oy);
+  *q0 = (float)__fma_rn((double)r.l21, dy, (double)r.l11 * dx);
+  *q1 = (float)((double)r.l22 * dy);
+  *mx = (float)dx;
+  *my = (float)dy;
+}
+
 // Stages one forward-only record in LDS; returns its mask over the strips
 // first .. first + N - 1 (the same fields and strip test as the general
 // record below).
@@ -142,15 +154,15 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
                                           int first, FRec* dst, uint32_t* entry) {
   const Rec r = srec[rank];
   FRec l;
-  l.mx = (float)(r.mx - origin_f64(ox));
-  l.my = (float)(r.my - origin_f64(oy));
+  float mx, my;
+  tile_frame(r, ox, oy, &l.q0, &l.q1, &mx, &my);
   l.l11 = r.l11; l.l21 = r.l21; l.l22 = r.l22;
   l.pad = 0.0f;
   l.o = r.o;
   l.inv_nu = r.inv_nu;
   l.nb = r.nb;
   l.cr = (double)r.cr; l.cg = (double)r.cg; l.cb = (double)r.cb;
-  const uint32_t m = strip_mask<N>(r, l.mx, l.my, first);
+  const uint32_t m = strip_mask<N>(r, mx, my, first);
   l.smask = m;
   *dst = l;
   *entry = r.entry;
@@ -164,8 +176,8 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
                                           int first, LRec* dst, uint32_t* entry) {
   const Rec r = srec[rank];
   LRec l;
-  l.mx = (float)(r.mx - origin_f64(ox));
-  l.my = (float)(r.my - origin_f64(oy));
+  float mx, my;
+  tile_frame(r, ox, oy, &l.q0, &l.q1, &mx, &my);
   l.l11 = r.l11; l.l21 = r.l21; l.l22 = r.l22;
   // Conservative pre-test level; the alpha test itself decides.
   l.pad = 0.0f;
@@ -181,7 +193,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
   // the record goes to LDS before the mask is computed, so that its
   // registers are free by then (the backward's accumulators are live here)
   *dst = l;
-  const uint32_t m = strip_mask<N>(r, l.mx, l.my, first);
+  const uint32_t m = strip_mask<N>(r, mx, my, first);
   dst->smask = m;
   return m;
 }
@@ -189,7 +201,7 @@ __device__ __forceinline__ uint32_t stage(const Rec* __restrict__ srec, uint32_t
 // Evaluation of one record at one pixel, shared bit-for-bit by the forward
 // and backward kernels (explicit fma, compiled without contraction).
 struct Eval {
-  float dx, dy, w0, w1, h, y, u, l2, t2, a, alpha;   // (w0, w1) = L^T d; a = o T2D, alpha = a clamped
+  float w0, w1, h, y, u, l2, t2, a, alpha;   // (w0, w1) = L^T (p - m); a = o T2D, alpha = a clamped
   bool hit, clamped;   // hit: |a| >= alpha_min (false for NaN)
 };
 
@@ -198,14 +210,14 @@ struct Eval {
 // caller's options select for the whole call.
 template <bool kGauss, typename R>
 __device__ __forceinline__ void evaluate(float px, float py, const R& L, float amin, float amax, Eval& E) {
-  E.dx = px - L.mx;
-  E.dy = py - L.my;
-  // h = |w|^2 with w = L^T d (the conic's Cholesky factor L): a sum of two
-  // squares, so near an elongated ellipse's major axis FP32 keeps h to about
-  // (axis ratio) x 6e-8 relative, where the conic entries' form lost
-  // (axis ratio)^2 x 6e-8.  The backward's sums are taken in w as well.
-  E.w0 = __fmaf_rn(L.l21, E.dy, L.l11 * E.dx);
-  E.w1 = L.l22 * E.dy;
+  // h = |w|^2 with w = L^T (p - m) (the conic's Cholesky factor L): a sum
+  // of two squares, so near an elongated ellipse's major axis FP32 keeps h
+  // to about (axis ratio) x 6e-8 relative, where the conic entries' form
+  // lost (axis ratio)^2 x 6e-8.  The backward's sums are taken in w as well.
+  // L^T m comes with the record, rounded once from FP64 (its error is that
+  // of rounding m itself, times L's entries).
+  E.w0 = __fmaf_rn(L.l11, px, __fmaf_rn(L.l21, py, -L.q0));
+  E.w1 = __fmaf_rn(L.l22, py, -L.q1);
   E.h = __fmaf_rn(E.w0, E.w0, E.w1 * E.w1);
   // Branch-free: once a record passes the strip test nearly every wave has
   // a lane inside the ellipse, so the whole chain runs anyway; selects keep
