@@ -253,3 +253,48 @@ def test_raw_nu_outside_the_clamp_renders_as_the_bound(sss, raw, bound):
     assert out[raw][1]["nu"][0] == 0.0 and out[bound][1]["nu"][0] != 0.0
     for k in ("means", "scales", "quats", "opacity", "sh"):
         assert np.array_equal(out[raw][1][k], out[bound][1][k]), k
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("opts", [dict(alpha_max=0.9999), dict(alpha_max=0.9999, t_min=0.0)],
+                         ids=["alpha_max_0.9999", "t_min_0"])
+def test_edges_extreme_compositing_options(sss, opts):
+    """alpha_max just below 1 (1 - alpha down to 1e-4) and t_min = 0: a
+    finished pixel keeps a negative transmittance that no later component
+    may flip or feed.  t_min = 0 acts as the smallest normal float in the
+    kernels, where the oracle never stops; what it adds beyond that point is
+    below 1e-38, so images and gradients match at the usual bars and the
+    contributor counts wherever the oracle's transmittance stays above
+    1e-30."""
+    s, cams = edges_case()
+    cam = cams[0]
+    n = s["means"].shape[0]
+    ref = oracle.render(s, cam, opts)
+    H, W = ref["xflags"].shape
+    explained = ref["xflags"] != 0
+    assert explained.mean() < 0.01
+    assert (ref["tfinal"] < 1e-3).sum() > 200           # deep, saturated pixels
+    dev = to_device(s)
+    proj = sss.project(dev, cams, opts)
+    bins = sss.BinSorter(1024)(proj, cams, n)
+    img, tfin, ncon = sss.render_fwd(bins, cams, opts)
+    torch.cuda.synchronize()
+    diff = np.abs(img.cpu().numpy().reshape(H, W, 3) - ref["image"]).max(axis=2)
+    assert not ((diff > 1e-4) & ~explained).any(), diff[~explained].max()
+    tf = tfin.cpu().numpy().reshape(H, W)
+    assert np.all(tf >= 0.0)
+    assert np.all(np.abs(tf - ref["tfinal"])[~explained] <= 1e-4 * np.maximum(1.0, ref["tfinal"][~explained]))
+    deep = ref["tfinal"] > 1e-30
+    nc = ncon.cpu().numpy().reshape(H, W)
+    assert np.array_equal(nc[~explained & deep], ref["ncontrib"][~explained & deep])
+    w = np.random.default_rng(80).standard_normal(ref["image"].shape)
+    w[explained] = 0.0
+    gref = oracle.render_backward(s, cam, w, opts, fwd=ref)
+    dl = torch.as_tensor(w.reshape(-1, 3), dtype=torch.float32, device="cuda")
+    keep = ref["proj"]["pflags"] == 0
+    for m in (sss.BWD_STORED, sss.BWD_RECOMPUTE):
+        g = sss.render_bwd(dev, proj, bins, cams, dl, opts, mode=m, image=img, n_contrib=ncon)
+        torch.cuda.synchronize()
+        for k in PARAMS:
+            ok, worst = grad_close(g[k].cpu().numpy(), gref[k], mask=keep)
+            assert ok, (k, m, worst)
