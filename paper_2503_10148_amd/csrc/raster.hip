@@ -9,8 +9,9 @@
 // consumed in batches of 64 records staged in LDS, and the walk visits only
 // the staged records whose strip mask meets the unit (a ballot); every lane
 // reads a visited record as a broadcast.  The 2D mean is re-based on the
-// tile origin in FP64 while staging, so pixel offsets keep full FP32
-// relative precision.
+// tile origin in FP64 while staging and the staged record carries L^T m
+// (L the conic's Cholesky factor, m that mean), so a pixel's w = L^T (p - m)
+// is three FMAs on tile coordinates.
 //
 // The backward pass walks the list front to back, like the forward pass: with
 // out = sum_j c_j a_j T_j + T_final bg and A_i = sum_{j<=i} c_j a_j T_j,
